@@ -1,0 +1,24 @@
+"""CPU oracle for the deform-and-match step of Preconditioned Deformation Grids.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, obviously-correct
+restatement of what the method computes, in float64 numpy, used to check the
+HIP path.  Only the tests, the smoke check and the benchmark's CPU-baseline
+leg may import it; the product path never does, and this package imports
+nothing from the product package.
+
+Modules (each function cites the passage of the paper it follows):
+
+* ``warp``      -- multi-resolution trilinear deformation (Sec. 3.1, Eq. 1),
+                   its grid adjoint and position Jacobian.
+* ``chamfer``   -- robust Chamfer distance (Sec. 3.4, Eq. 11-13): brute-force
+                   nearest neighbours, per-direction losses and gradients.
+* ``precond``   -- grid Sobolev preconditioner (I + lambda L)^-2 (Sec. 3.2,
+                   Eq. 3): dense Cholesky and the DCT-II closed form.
+* ``adam``      -- Adam with bias correction (Sec. 3.6).
+* ``sequence``  -- isometry loss (Eq. 18), confidence weights (Eq. 15-17),
+                   loss assembly (Eq. 9, 14) and one full optimisation step.
+
+Readings of the paper where it is silent or ambiguous are listed in the
+module docstrings where they are used.
+"""
+from . import warp, chamfer, precond, adam, sequence  # noqa: F401

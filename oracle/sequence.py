@@ -1,0 +1,223 @@
+"""Losses and one optimisation step of the method -- oracle.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows the paper's Sec. 3.3-3.6:
+* the template chain X_t = warp(G_t, X_{t-1}) (Eq. 8, translation form);
+* the point term P^_t = warp(G_t, P_{t-1}) (text after Eq. 14);
+* L_transform = 1/T sum_t [ w_conf(t) CD_R(X_t, P_t) + CD_R(P^_t, P_t) ] (Eq. 14);
+* w_conf(t) = prod_{tau <= t} (1 + max(0, CD_R(X_tau, P_tau) - cd_max))^{-delta}
+  with delta = 1 - sqrt(e / e_max) (Eq. 15-16) and
+  cd_max = max_t CD_R(sg(P^_t), P_t) (Eq. 17);
+* L_iso = 1/(T |E|) sum_t sum_(i,j) | |x_i,t - x_j,t| - |x_i,t-1 - x_j,t-1| | (Eq. 18);
+* L = L_transform + w_iso L_iso, w_iso = 250 (Eq. 9, without L_mesh: the
+  initial mesh is held fixed on this path);
+* gradients preconditioned per level by (I + lambda_l L_l)^{-2} (Eq. 3) and
+  applied by Adam with a per-level learning rate (Sec. 3.6).
+
+Readings:
+* Frame 0 is the keyframe; T = F - 1 transitions, grid G_t maps frame t-1 to t.
+* Eq. 14 is read as 1/T sum_t [w_conf(t) CD(X, P) + CD(P^, P)].
+* w_conf is a weight and is not differentiated (only cd_max is marked sg, the
+  bracket is ambiguous); tau runs from 1 to t inclusive; e is the 0-based
+  epoch and e_max the number of epochs.
+* cd_max is taken from the current iteration's forward pass.
+* Isometry: sign(0) = 0; a zero-length edge contributes no gradient; X_0 is
+  fixed.
+* "+10% / +50% per finer level" (Sec. 3.6) compounds:
+  eta_l = 5e-3 * 1.1^l, lambda_l = 0.25 * 1.5^l for the 0-based level l.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import adam as _adam
+from . import chamfer as _ch
+from . import precond as _pc
+from . import warp as _wp
+
+
+@dataclass
+class Hyper:
+    alpha: float = 5.56           # Eq. 13
+    w_iso: float = 250.0          # Eq. 9
+    eta0: float = 5e-3            # Sec. 3.6
+    eta_growth: float = 1.1
+    lam0: float = 0.25
+    lam_growth: float = 1.5
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    e_max: int = 50
+    level_scale: float | None = None     # 1/L (Eq. 1) when None
+
+    def schedule(self, levels: int):
+        etas = [self.eta0 * self.eta_growth ** l for l in range(levels)]
+        lams = [self.lam0 * self.lam_growth ** l for l in range(levels)]
+        return etas, lams
+
+    def scale(self, levels: int) -> float:
+        return 1.0 / levels if self.level_scale is None else float(self.level_scale)
+
+
+def isometry(xhat: np.ndarray, edges: np.ndarray, w_iso: float = 1.0):
+    """Eq. 18 and its gradient.  xhat (F, 3, V) with frame 0 the fixed X_0,
+    edges (2, E).  Returns (L_iso, grad (F, 3, V)) of w_iso * L_iso."""
+    x = np.asarray(xhat, np.float64)
+    f = x.shape[0]
+    t_count = f - 1
+    i, j = np.asarray(edges[0], np.int64), np.asarray(edges[1], np.int64)
+    e = i.shape[0]
+    d = x[:, :, i] - x[:, :, j]                   # (F, 3, E)
+    ln = np.sqrt(np.sum(d * d, axis=1))           # (F, E)
+    diff = ln[1:] - ln[:-1]                       # (T, E)
+    loss = float(np.sum(np.abs(diff)) / (t_count * e))
+    sig = np.sign(diff)                           # sign(0) = 0
+    coef = w_iso / (t_count * e)
+    # frame t gets +sig_t (as the later slice) and -sig_{t+1} (as the earlier)
+    s = np.zeros((f, e))
+    s[1:] += sig
+    s[:-1] -= sig
+    u = np.divide(d, ln[:, None, :], out=np.zeros_like(d), where=ln[:, None, :] > 0)
+    contrib = coef * s[:, None, :] * u            # (F, 3, E)
+    g = np.zeros_like(x)
+    for c in range(3):
+        for t in range(f):
+            np.add.at(g[t, c], i, contrib[t, c])
+            np.add.at(g[t, c], j, -contrib[t, c])
+    return w_iso * loss, g
+
+
+def confidence(cd_tm, cd_pt, epoch: int, e_max: int):
+    """Eq. 15-17.  Returns (w_conf (T,), cd_max, delta)."""
+    cd_tm = np.asarray(cd_tm, np.float64)
+    cd_max = float(np.max(cd_pt))
+    delta = 1.0 - np.sqrt(epoch / e_max)
+    factors = (1.0 / (1.0 + np.maximum(0.0, cd_tm - cd_max))) ** delta
+    return np.cumprod(factors), cd_max, float(delta)
+
+
+@dataclass
+class StepResult:
+    phat: np.ndarray                  # (T, 3, N) float64 warped input points
+    xhat: np.ndarray | None           # (F, 3, V) float64 template chain
+    nn: dict = field(default_factory=dict)       # 'pt_ab', 'pt_ba', 'tm_ab', 'tm_ba': (T, ...) int64
+    cd_pt: np.ndarray = None          # (T, 2) per direction
+    cd_tm: np.ndarray = None          # (T, 2)
+    cd_max: float = 0.0
+    w_conf: np.ndarray = None
+    l_iso: float = 0.0
+    loss: float = 0.0
+    grad: np.ndarray = None           # (T, P) raw packed grid gradient
+    pgrad: np.ndarray = None          # (T, P) preconditioned
+    theta: np.ndarray = None          # (T, P) after Adam
+    m: np.ndarray = None
+    v: np.ndarray = None
+    g_phat: np.ndarray = None         # (T, 3, N) dL/dP^_t
+    g_xhat: np.ndarray = None         # (T, 3, V) dL/dX_t (direct terms, frames 1..T)
+
+
+def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hyper(),
+         phat32=None, xhat32=None, workers: int = 1, precond_method: str = "dct",
+         grad_override=None, pgrad_override=None) -> StepResult:
+    """One iteration: warp, Chamfer + isometry losses, gradient, preconditioner, Adam.
+
+    points (F, 3, N) float32; template (3, V) float32 or None; edges (2, E);
+    theta, m, v (T, P) packed per-transition grid values.
+
+    ``phat32`` / ``xhat32`` give float32 warped positions on which to take the
+    nearest-neighbour decisions (so that another implementation's indices can
+    be compared on identical inputs); by default the oracle's own float64
+    positions are rounded to float32.  ``grad_override`` / ``pgrad_override``
+    replace the raw / preconditioned gradient fed to the following stage.
+    """
+    points = np.asarray(points)
+    f = points.shape[0]
+    t_count = f - 1
+    levels = len(res)
+    ls = hp.scale(levels)
+    etas, lams = hp.schedule(levels)
+    theta = np.asarray(theta, np.float64)
+    has_tm = template is not None and np.asarray(template).shape[1] > 0
+
+    phat = np.stack([_wp.warp(theta[t], res, points[t], ls) for t in range(t_count)])
+    xhat = None
+    if has_tm:
+        xs = [np.asarray(template, np.float64)]
+        for t in range(t_count):
+            src = xs[t] if xhat32 is None else np.asarray(xhat32[t], np.float64)
+            xs.append(_wp.warp(theta[t], res, src, ls))
+        xhat = np.stack(xs)
+    p_nn = phat.astype(np.float32) if phat32 is None else np.asarray(phat32, np.float32)
+    x_nn = None
+    if has_tm:
+        x_nn = xhat.astype(np.float32) if xhat32 is None else np.asarray(xhat32, np.float32)
+
+    r = StepResult(phat=phat, xhat=xhat)
+    cd_pt = np.zeros((t_count, 2))
+    cd_tm = np.zeros((t_count, 2))
+    nn = {k: [] for k in ("pt_ab", "pt_ba", "tm_ab", "tm_ba")}
+    for t in range(t_count):
+        tgt = points[t + 1]
+        a = p_nn[t]
+        na = _ch.nn_fp32(a, tgt, workers=workers)
+        nb = _ch.nn_fp32(tgt, a, workers=workers)
+        nn["pt_ab"].append(na)
+        nn["pt_ba"].append(nb)
+        cd_pt[t] = (_ch.direction_loss(a, tgt, na, hp.alpha),
+                    _ch.direction_loss(tgt, a, nb, hp.alpha))
+        if has_tm:
+            a = x_nn[t + 1]
+            na = _ch.nn_fp32(a, tgt, workers=workers)
+            nb = _ch.nn_fp32(tgt, a, workers=workers)
+            nn["tm_ab"].append(na)
+            nn["tm_ba"].append(nb)
+            cd_tm[t] = (_ch.direction_loss(a, tgt, na, hp.alpha),
+                        _ch.direction_loss(tgt, a, nb, hp.alpha))
+    r.nn = {k: np.stack(vv) for k, vv in nn.items() if vv}
+    r.cd_pt, r.cd_tm = cd_pt, cd_tm
+    pt = cd_pt.sum(axis=1)
+    tm = cd_tm.sum(axis=1)
+    if has_tm:
+        w_conf, cd_max, _ = confidence(tm, pt, epoch, hp.e_max)
+        l_iso, g_iso = isometry(x_nn, edges, hp.w_iso)
+    else:
+        w_conf, cd_max, l_iso, g_iso = np.ones(t_count), float(np.max(pt)), 0.0, None
+    r.w_conf, r.cd_max, r.l_iso = w_conf, cd_max, l_iso
+    r.loss = float(np.mean(w_conf * tm + pt) + l_iso) if has_tm else float(np.mean(pt))
+
+    # gradients of the loss with respect to the warped positions
+    g_phat = np.stack([_ch.gradient(p_nn[t], points[t + 1], r.nn["pt_ab"][t], r.nn["pt_ba"][t],
+                                    hp.alpha, 1.0 / t_count, 1.0 / t_count)
+                       for t in range(t_count)])
+    r.g_phat = g_phat
+    grad = np.stack([_wp.grid_adjoint(res, points[t], g_phat[t], ls) for t in range(t_count)])
+    if has_tm:
+        g_x = np.stack([_ch.gradient(x_nn[t + 1], points[t + 1], r.nn["tm_ab"][t], r.nn["tm_ba"][t],
+                                     hp.alpha, w_conf[t] / t_count, w_conf[t] / t_count)
+                        for t in range(t_count)]) + g_iso[1:]
+        r.g_xhat = g_x
+        chain_pos = x_nn
+        lam = g_x[t_count - 1]
+        for t in range(t_count - 1, -1, -1):
+            grad[t] += _wp.grid_adjoint(res, chain_pos[t], lam, ls)
+            if t > 0:
+                lam = g_x[t - 1] + _wp.position_adjoint(theta[t], res, chain_pos[t], lam, ls)
+    r.grad = grad
+    g_in = grad if grad_override is None else np.asarray(grad_override, np.float64)
+    pgrad = np.stack([_pc.apply_levels(g_in[t], res, lams, precond_method)
+                      for t in range(t_count)])
+    r.pgrad = pgrad
+    p_in = pgrad if pgrad_override is None else np.asarray(pgrad_override, np.float64)
+    th, mm, vv = np.empty_like(theta), np.empty_like(theta), np.empty_like(theta)
+    off = 0
+    for l, rr in enumerate(res):
+        sl = slice(off, off + 3 * rr ** 3)
+        th[:, sl], mm[:, sl], vv[:, sl] = _adam.update(
+            theta[:, sl], np.asarray(m)[:, sl], np.asarray(v)[:, sl], p_in[:, sl], etas[l],
+            epoch + 1, hp.beta1, hp.beta2, hp.eps)
+        off += 3 * rr ** 3
+    r.theta, r.m, r.v = th, mm, vv
+    return r

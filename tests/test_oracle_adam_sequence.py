@@ -1,0 +1,177 @@
+"""Pins for the oracle's Adam, isometry, confidence and full step."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import adam as A
+from oracle import chamfer as C
+from oracle import sequence as S
+from oracle import warp as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+
+
+def test_hyper_defaults_match_paper():
+    h = S.Hyper()
+    assert h.alpha == GOLD["alpha"]["value"] and h.w_iso == GOLD["w_iso"]["value"]
+    assert (h.beta1, h.beta2, h.eps) == (GOLD["adam"]["beta1"], GOLD["adam"]["beta2"], GOLD["adam"]["eps"])
+    etas, lams = h.schedule(5)
+    assert etas[0] == GOLD["eta_level1"]["value"] and lams[0] == GOLD["lambda_level1"]["value"]
+    np.testing.assert_allclose(etas[1] / etas[0], 1 + GOLD["eta_growth_per_level"]["value"])
+    np.testing.assert_allclose(lams[1] / lams[0], 1 + GOLD["lambda_growth_per_level"]["value"])
+    np.testing.assert_allclose(lams, [0.25, 0.375, 0.5625, 0.84375, 1.265625])
+
+
+def test_adam_first_step_closed_form():
+    # bias corrections cancel on the first step: update = -eta g / (|g| + eps)
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=100) * 10.0 ** rng.uniform(-9, 1, 100)
+    th, m, v = A.update(np.zeros(100), np.zeros(100), np.zeros(100), g, 0.01, 1)
+    np.testing.assert_allclose(th, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_adam_constant_gradient_and_zero_gradient():
+    g = np.array([2.0, -3.0, 0.0])
+    th, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for k in range(1, 6):
+        prev = th.copy()
+        th, m, v = A.update(th, m, v, g, 0.1, k)
+        # with a constant gradient m^ = g and v^ = g^2 at every step
+        np.testing.assert_allclose(th - prev, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    assert th[2] == 0.0
+
+
+def test_isometry_rigid_motion_zero():
+    v, f, e = synth.icosphere(2)
+    x0 = v.T
+    rng = np.random.default_rng(1)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    x1 = q @ x0 + np.array([[0.1], [0.2], [-0.3]])
+    x2 = x1 + 0.5
+    l_iso, g = S.isometry(np.stack([x0, x1, x2]), e)
+    assert l_iso < 1e-14
+
+
+def test_isometry_uniform_scale_closed_form():
+    v, f, e = synth.icosphere(1)
+    x0 = v.T
+    s = 1.07
+    l_iso, _ = S.isometry(np.stack([x0, s * x0]), e)
+    ln = np.linalg.norm(x0[:, e[0]] - x0[:, e[1]], axis=0)
+    assert abs(l_iso - abs(s - 1) * ln.mean()) < 1e-14
+
+
+def test_isometry_gradient_finite_difference():
+    v, f, e = synth.icosphere(1)
+    rng = np.random.default_rng(2)
+    x = np.stack([v.T + 0.05 * rng.normal(size=v.T.shape) for _ in range(4)])
+    l0, g = S.isometry(x, e, 3.0)
+    h = 1e-7
+    for t in (1, 2, 3):
+        for i in rng.choice(x.shape[2], 6, replace=False):
+            for c in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[t, c, i] += h
+                xm[t, c, i] -= h
+                fd = (S.isometry(xp, e, 3.0)[0] - S.isometry(xm, e, 3.0)[0]) / (2 * h)
+                assert abs(fd - g[t, c, i]) < 1e-6
+
+
+def test_confidence_cases():
+    # every template error below cd_max: all weights 1
+    w, cdm, d = S.confidence([0.1, 0.2], [0.3, 0.25], epoch=3, e_max=50)
+    assert cdm == 0.3 and np.all(w == 1.0)
+    # at e = e_max the exponent is 0 and every weight is 1
+    w, _, d = S.confidence([5.0, 7.0], [0.1, 0.1], epoch=50, e_max=50)
+    assert d == 0.0 and np.all(w == 1.0)
+    # hand-computed product at e = 0 (delta = 1): 1/(1+0.4) then 1/(1+0.4) * 1/(1+0.1)
+    w, _, _ = S.confidence([0.5, 0.2], [0.1, 0.05], epoch=0, e_max=50)
+    np.testing.assert_allclose(w, [1 / 1.4, 1 / 1.4 / 1.1], rtol=1e-15)
+
+
+def _tiny_sequence(frames=4, n=60, subdiv=1, seed=0):
+    return synth.deforming_sequence(seed=seed, frames=frames, n=n, subdiv=subdiv)
+
+
+def test_step_fixed_point_exact():
+    # zero grids, every frame identical and the template equal to the points:
+    # every Chamfer term and the isometry term vanish, so the gradient is 0 and
+    # Adam leaves the grids unchanged, exactly
+    rng = np.random.default_rng(3)
+    p = rng.uniform(-0.8, 0.8, (3, 50)).astype(np.float32)
+    pts = np.stack([p] * 3)
+    _, _, e = synth.icosphere(0)
+    tmpl = p[:, :12].copy()
+    res = (1, 2, 4)
+    tot = 3 * sum(r ** 3 for r in res)
+    z = np.zeros((2, tot))
+    # tmpl points are a subset of p, so their NN distance is zero both ways
+    # only when the template equals the cloud; use the cloud as template
+    r = S.step(pts, p, np.array([[0], [1]], np.int32), res, z, z, z, epoch=0)
+    assert r.loss == 0.0
+    assert np.all(r.grad == 0.0) and np.all(r.theta == 0.0)
+    assert tmpl.shape == (3, 12) and e.shape[0] == 2
+
+
+def _frozen_loss(seq, res, theta, ref, hp):
+    """Loss of the step as a function of the grid values with the neighbour
+    assignment and the confidence weights held at ``ref``'s values."""
+    pts = seq.points
+    t_count = pts.shape[0] - 1
+    ls = hp.scale(len(res))
+    tot = 0.0
+    xs = [seq.template.astype(np.float64)]
+    for t in range(t_count):
+        xs.append(W.warp(theta[t], res, xs[t], ls))
+    for t in range(t_count):
+        ph = W.warp(theta[t], res, pts[t], ls)
+        tgt = pts[t + 1]
+        cpt = C.direction_loss(ph, tgt, ref.nn["pt_ab"][t], hp.alpha) + \
+            C.direction_loss(tgt, ph, ref.nn["pt_ba"][t], hp.alpha)
+        ctm = C.direction_loss(xs[t + 1], tgt, ref.nn["tm_ab"][t], hp.alpha) + \
+            C.direction_loss(tgt, xs[t + 1], ref.nn["tm_ba"][t], hp.alpha)
+        tot += ref.w_conf[t] * ctm + cpt
+    return tot / t_count + S.isometry(np.stack(xs), seq.edges, hp.w_iso)[0]
+
+
+def test_step_gradient_finite_difference():
+    # the full reverse sweep (Chamfer adjoints, isometry, template chain and
+    # grid scatter) against central differences of the assembled loss
+    seq = _tiny_sequence(frames=4, n=40, subdiv=1, seed=5)
+    res = (1, 2, 4)
+    hp = S.Hyper(e_max=10)
+    rng = np.random.default_rng(6)
+    tot = 3 * sum(r ** 3 for r in res)
+    theta = rng.normal(0, 0.02, (3, tot))
+    z = np.zeros_like(theta)
+    ref = S.step(seq.points, seq.template, seq.edges, res, theta, z, z, epoch=2, hp=hp,
+                 phat32=None, xhat32=None)
+    # the oracle evaluates losses on float32-rounded positions; the frozen
+    # loss here is float64, so compare with a tolerance above that rounding
+    h = 1e-5
+    for t in range(3):
+        for k in rng.choice(tot, 5, replace=False):
+            tp, tm = theta.copy(), theta.copy()
+            tp[t, k] += h
+            tm[t, k] -= h
+            fd = (_frozen_loss(seq, res, tp, ref, hp) - _frozen_loss(seq, res, tm, ref, hp)) / (2 * h)
+            assert abs(fd - ref.grad[t, k]) <= 2e-4 * max(abs(fd), 1e-3), (t, k, fd, ref.grad[t, k])
+
+
+def test_step_loss_decreases_on_pair():
+    src, tgt = synth.pair_on_sphere(seed=0, n=512)
+    pts = np.stack([src, tgt])
+    res = (8, 16, 32)
+    tot = 3 * sum(r ** 3 for r in res)
+    th = np.zeros((1, tot))
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    losses = []
+    for e in range(6):
+        r = S.step(pts, None, None, res, th, m, v, epoch=e, hp=S.Hyper(e_max=6))
+        losses.append(r.loss)
+        th, m, v = r.theta, r.m, r.v
+    assert losses[-1] < 0.8 * losses[0]
