@@ -1,0 +1,252 @@
+/*
+ * pdg.h -- C ABI of the MI355X (gfx950) deform-and-match step of
+ * Preconditioned Deformation Grids (Kaltheuner et al., arXiv:2509.18097).
+ *
+ * Conventions for every call below
+ * --------------------------------
+ * - Pointers are DEVICE pointers unless marked [host].  The caller owns every
+ *   buffer; the library never frees caller memory.
+ * - Point sets are structure-of-arrays float32: a set of n points is three
+ *   consecutive rows of n floats (x row, y row, z row).  Rows of a set must be
+ *   4-byte aligned; 16-byte alignment of the set base is recommended.
+ * - A grid stack ("transition grid", paper Sec. 3.1) packs its levels one
+ *   after another; level l holds 3 channels of R_l^3 float32 values, each
+ *   channel a dense R x R x R block with x fastest:
+ *       value(c, z, y, x) at  level_offset(l) + ((c*R + z)*R + y)*R + x.
+ *   Values are cell-centred on the cube [-1,1]^3 (centre of cell i is
+ *   -1 + (2i+1)/R) and sampling clamps to the hull of the cell centres.
+ * - Every call validates its arguments on the host before enqueuing anything,
+ *   enqueues its work on `stream` and returns without waiting (asynchronous).
+ *   Argument errors return PDG_EINVAL and enqueue nothing.  A HIP launch error
+ *   returns PDG_EHIP.  A device fault shows up as PDG_EHIP on a later call or
+ *   synchronisation.  pdg_last_error() returns a thread-local message for the
+ *   most recent failing call.  No call allocates device memory except
+ *   pdg_problem_create (a few KB of tables) -- scratch space comes from the
+ *   caller through the `*_workspace` size queries.
+ * - Calls on one stream are ordered; calls sharing a workspace must not
+ *   overlap on different streams.
+ */
+#ifndef PDG_H
+#define PDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PDG_OK = 0,
+  PDG_EINVAL = 1,        /* invalid argument; nothing was enqueued            */
+  PDG_ENOMEM = 2,        /* workspace too small / host allocation failed     */
+  PDG_EHIP = 3,          /* HIP runtime error (launch failure, device fault) */
+  PDG_EUNSUPPORTED = 4   /* valid request that this build does not implement */
+} pdg_status;
+
+#define PDG_MAX_LEVELS 8
+
+/* [host] Thread-local message describing the last failing call ("" if none). */
+const char *pdg_last_error(void);
+/* [host] Library version, major*10000 + minor*100 + patch. */
+int32_t pdg_version(void);
+
+/* Multi-resolution grid stack (paper Sec. 3.1, Eq. 1).
+ *   levels      : L, 1..PDG_MAX_LEVELS.
+ *   res[l]      : cells per axis of level l (>= 1; R = 1 is a constant level).
+ *   channels    : must be 3 (translation per cell: the Cayley rotation of
+ *                 Eq. 4-7 with z = 0, where R(0) = I).
+ *   level_scale : factor applied to the sum over levels; 1/L reproduces the
+ *                 averaging of Eq. 1. */
+typedef struct {
+  int32_t levels;
+  int32_t res[PDG_MAX_LEVELS];
+  int32_t channels;
+  float level_scale;
+} pdg_grid_desc;
+
+/* [host] Number of float32 values in one grid stack (3 * sum_l R_l^3), or -1. */
+int64_t pdg_grid_size(const pdg_grid_desc *d);
+
+/* ---------------------------------------------------------------- deform --
+ * Warp (paper Eq. 1 with the translation form of Eq. 7):
+ *     out_i = x_i + level_scale * sum_l trilerp(G_l, x_i).
+ * grids: one packed stack; x, out: SoA [3][n]; n >= 0 (n = 0 is a no-op).
+ * out may alias x. */
+pdg_status pdg_deform(const pdg_grid_desc *d, const float *grids, const float *x,
+                      int64_t n, float *out, hipStream_t stream);
+
+/* [host] Workspace bytes needed by pdg_deform_backward for n samples. */
+pdg_status pdg_deform_backward_workspace(const pdg_grid_desc *d, int64_t n, size_t *bytes);
+
+/* Adjoint of pdg_deform for an upstream gradient gout (SoA [3][n]):
+ *   ggrids (nullable) <- level_scale * A^T gout   (OVERWRITES the whole stack;
+ *                        the sum at every node is taken in a fixed order, so
+ *                        the result is bitwise reproducible -- no atomics);
+ *   gx     (nullable) <- gout + J^T gout, with J the position Jacobian of the
+ *                        displacement (zero along clamped axes).
+ * ws: device workspace of at least pdg_deform_backward_workspace() bytes
+ * (needed only when ggrids != NULL). */
+pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const float *x,
+                               int64_t n, const float *gout, float *ggrids, float *gx,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* --------------------------------------------------------------- chamfer --
+ * Robust bidirectional Chamfer distance (paper Sec. 3.4, Eq. 11-13) between a
+ * moving set A (n points) and a fixed set B (m points):
+ *   nn_a[i] = argmin_j d2(a_i, b_j),  nn_b[j] = argmin_i d2(a_i, b_j),
+ *   loss[0] = 1/n sum_i exp(-alpha s_i) s_i,  s_i = |a_i - b_nn_a[i]|^2,
+ *   loss[1] = 1/m sum_j exp(-alpha s_j) s_j,  s_j = |a_nn_b[j] - b_j|^2.
+ * Neighbour contract: d2 is evaluated in float32 in difference form without
+ * fused multiply-add, dx = a_x - b_x, d2 = (dx*dx + dy*dy) + dz*dz, and ties
+ * go to the lowest index; both modes return exactly these indices.
+ * Losses are float64 sums of float64 distances (alpha is taken in float64
+ * there; the float32 gradient uses alpha rounded to float32).
+ *   mode PDG_CHAMFER_FP32       : exact float32 tiles.
+ *   mode PDG_CHAMFER_BF16_SCREEN: bf16 matrix-core screen of |x|^2+|y|^2-2x.y
+ *                                 with float32 accumulation, followed by an
+ *                                 exact float32 re-rank of every candidate the
+ *                                 screen cannot rule out.
+ * dir_weight (device double[2], nullable = {1,1}) scales the two directions
+ * for the gradient.  ga (nullable): OVERWRITTEN with
+ *   d/da [dir_weight[0]*loss[0] + dir_weight[1]*loss[1]]
+ * with the assignment held fixed and the Gaussian weight differentiated;
+ * B receives no gradient.  loss: device double[2].  nn_a: int32[n],
+ * nn_b: int32[m].  n, m >= 1 and < 2^31. */
+typedef enum { PDG_CHAMFER_FP32 = 0, PDG_CHAMFER_BF16_SCREEN = 1 } pdg_chamfer_mode;
+
+pdg_status pdg_chamfer_workspace(int64_t n, int64_t m, int32_t mode, size_t *bytes);
+pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, double alpha,
+                       int32_t mode, const double *dir_weight, double *loss,
+                       int32_t *nn_a, int32_t *nn_b, float *ga,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------- precondition --
+ * Grid Sobolev preconditioner (paper Sec. 3.2, Eq. 3), in place:
+ *   g_l <- (I + lambda[l] L_l)^{-2} g_l for every level l and channel of
+ *   `batch` consecutive packed stacks, L_l the 6-neighbour combinatorial
+ *   Laplacian of the R_l^3 cell box (free boundary).
+ * method PDG_PRECOND_CG : two matrix-free conjugate-gradient solves per
+ *   system with float32 vectors and float64 inner products; iters > 0 fixes
+ *   the iteration count, iters = 0 takes the a-priori count from
+ *   kappa <= 1 + 12 lambda for the A-norm tolerance `tol`.
+ * method PDG_PRECOND_DCT: exact separable DCT-II diagonalisation (dense box
+ *   grids); iters and tol are ignored.
+ * lambda: [host] float[levels], each >= 0. */
+typedef enum { PDG_PRECOND_CG = 0, PDG_PRECOND_DCT = 1 } pdg_precond_method;
+
+pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int32_t method,
+                                      size_t *bytes);
+pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *g,
+                            int32_t batch, int32_t method, int32_t iters, double tol,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------ adam --
+ * Adam with bias correction (paper Sec. 3.6) over `batch` packed stacks with
+ * a per-level learning rate: for every value of level l,
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+ *   theta <- theta - lr[l] * (m / (1-b1^k)) / (sqrt(v / (1-b2^k)) + eps),
+ * k = step (1-based).  lr: [host] float[levels]. */
+pdg_status pdg_adam(const pdg_grid_desc *d, int32_t batch, const float *lr, float beta1,
+                    float beta2, float eps, int32_t step, float *theta, float *m, float *v,
+                    const float *g, hipStream_t stream);
+
+/* ------------------------------------------------------------- problem ---
+ * One reconstruction request (paper Sec. 3, problem statement): a point-cloud
+ * sequence P_0..P_{F-1} (frame 0 is the keyframe), an initial mesh X_0 with
+ * edge list E, and one grid stack per transition t = 1..T = F-1 mapping frame
+ * t-1 to frame t.  One pdg_step performs one optimisation iteration:
+ *   1. P^_t = warp(G_t, P_{t-1}) for all t; X_t = warp(G_t, X_{t-1}), t = 1..T
+ *      (Eq. 1, Eq. 8);
+ *   2. CD_R(P^_t, P_t) and CD_R(X_t, P_t) (Eq. 11-13), cd_max (Eq. 17),
+ *      w_conf (Eq. 15-16, not differentiated), L_iso (Eq. 18) and
+ *      L = 1/T sum_t [w_conf(t) CD_R(X_t,P_t) + CD_R(P^_t,P_t)] + w_iso L_iso;
+ *   3. the gradient of L with respect to every grid value (reverse sweep of
+ *      the template chain; deterministic scatter into the grids);
+ *   4. (I + lambda_l L_l)^{-2} per level (Eq. 3), lambda_l = lambda0*growth^l;
+ *   5. Adam with lr_l = eta0 * eta_growth^l (Sec. 3.6).
+ * With verts = 0 the template terms are dropped (L = 1/T sum_t CD_R(P^_t,P_t)).
+ *
+ * All pointers in the descriptor are device pointers owned by the caller and
+ * must stay valid until pdg_problem_destroy.  params, adam_m, adam_v are
+ * [T][grid_size] float32 and are updated in place by pdg_step. */
+typedef struct {
+  double alpha;         /* Eq. 13, 5.56 (float64: it enters the float64 loss) */
+  float w_iso;          /* Eq. 9, 250                                         */
+  float eta0;           /* Sec. 3.6, 5e-3                                     */
+  float eta_growth;     /* 1.1 (+10% per finer level)                         */
+  float lambda0;        /* 0.25                                               */
+  float lambda_growth;  /* 1.5 (+50% per finer level)                         */
+  float beta1, beta2, eps;   /* 0.9, 0.999, 1e-8                              */
+  int32_t e_max;        /* total epochs for delta = 1 - sqrt(e/e_max) (Eq. 16) */
+} pdg_hyper;
+
+typedef struct {
+  int32_t frames;             /* F >= 2                                       */
+  int64_t n;                  /* points per frame, >= 1                       */
+  const float *points;        /* [F][3][n]                                    */
+  int32_t verts;              /* V >= 0 (0: no template terms)                */
+  const float *template_verts;/* [3][V] (X_0)                                 */
+  int32_t n_edges;            /* E >= 0 (edges only with V > 0)               */
+  const int32_t *edges;       /* [2][E], 0 <= i, j < V                        */
+  pdg_grid_desc grid;
+  pdg_hyper hp;
+  int32_t chamfer_mode;       /* pdg_chamfer_mode                             */
+  int32_t precond_method;     /* pdg_precond_method                           */
+  int32_t cg_iters;           /* 0: a-priori count per level for cg_tol       */
+  double cg_tol;              /* e.g. 1e-7                                    */
+  float *params;              /* [T][grid_size] theta                         */
+  float *adam_m;              /* [T][grid_size]                               */
+  float *adam_v;              /* [T][grid_size]                               */
+  void *workspace;            /* >= pdg_problem_workspace() bytes             */
+  size_t workspace_bytes;
+} pdg_problem_desc;
+
+typedef struct pdg_problem pdg_problem;
+
+/* [host] Workspace bytes for a problem (all intermediate buffers of a step). */
+pdg_status pdg_problem_workspace(const pdg_problem_desc *pd, size_t *bytes);
+/* Validates pd, lays out the workspace and enqueues the one-time set-up
+ * (static scatter tables of the input points, template edge incidence) on
+ * `stream`.  *out receives an opaque handle. */
+pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out);
+/* One iteration at 0-based epoch `epoch` (0 <= epoch <= e_max).  loss_terms
+ * (device double[8], nullable) receives {L, L_transform, L_iso, cd_max,
+ * sum_t CD_R(P^_t,P_t)/T, sum_t w_conf CD_R(X_t,P_t)/T, w_conf(T), epoch}.
+ * With use_graph != 0 the step is replayed from a HIP graph captured on the
+ * first call for this stream. */
+pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t use_graph,
+                    hipStream_t stream);
+/* Several problems' iterations in one call: each problem's step is enqueued
+ * on its own stream from `streams` (count entries, [host]); the caller joins
+ * them.  epochs: [host] int32[count]; loss_terms: [host] array of device
+ * pointers (entries nullable). */
+pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *epochs,
+                          double *const *loss_terms, int32_t use_graph,
+                          const hipStream_t *streams);
+pdg_status pdg_problem_destroy(pdg_problem *p);
+
+/* Intermediate buffers of the last step, for checking stage by stage.
+ *   PDG_BUF_PHAT   float [T][3][n]   warped input points
+ *   PDG_BUF_XHAT   float [F][3][V]   template chain (frame 0 = X_0)
+ *   PDG_BUF_NN     int32 [T][2n] (+ [T][V+n] with a template): per transition
+ *                  nn of P^ in P, nn of P in P^ (then nn of X in P, nn of P in X)
+ *   PDG_BUF_LOSSES double[T][4]      CD directions: P^->P, P->P^, X->P, P->X
+ *   PDG_BUF_WCONF  double[T]
+ *   PDG_BUF_GRAD   float [T][grid_size]  raw gradient dL/dG
+ *   PDG_BUF_PGRAD  float [T][grid_size]  preconditioned gradient
+ *   PDG_BUF_GPHAT  float [T][3][n]   dL/dP^_t
+ *   PDG_BUF_GXHAT  float [T][3][V]   direct dL/dX_t (Chamfer + isometry), frames 1..T
+ *   PDG_BUF_TERMS  double[8]         the loss terms of pdg_step */
+typedef enum {
+  PDG_BUF_PHAT = 0, PDG_BUF_XHAT = 1, PDG_BUF_NN = 2, PDG_BUF_LOSSES = 3,
+  PDG_BUF_WCONF = 4, PDG_BUF_GRAD = 5, PDG_BUF_PGRAD = 6, PDG_BUF_GPHAT = 7,
+  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9
+} pdg_buffer;
+pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDG_H */

@@ -1,0 +1,227 @@
+"""ctypes binding of libpdg.so (include/pdg.h): argument marshalling only.
+
+Every function takes and returns torch tensors on the current HIP device and
+enqueues on torch's current stream; all arithmetic runs in the library's HIP
+kernels.  If the library has not been built, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdg.so")
+MAX_LEVELS = 8
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1}
+PRECOND_METHODS = {"cg": 0, "dct": 1}
+BUFFERS = {"phat": 0, "xhat": 1, "nn": 2, "losses": 3, "wconf": 4, "grad": 5, "pgrad": 6,
+           "gphat": 7, "gxhat": 8, "terms": 9}
+
+
+class PdgError(RuntimeError):
+    def __init__(self, status: int, what: str, msg: str):
+        super().__init__(f"{what} failed with status {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("res", ctypes.c_int32 * MAX_LEVELS),
+                ("channels", ctypes.c_int32), ("level_scale", ctypes.c_float)]
+
+
+class Hyper(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("w_iso", ctypes.c_float), ("eta0", ctypes.c_float),
+                ("eta_growth", ctypes.c_float), ("lambda0", ctypes.c_float),
+                ("lambda_growth", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("e_max", ctypes.c_int32)]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_int32), ("n", ctypes.c_int64), ("points", ctypes.c_void_p),
+                ("verts", ctypes.c_int32), ("template_verts", ctypes.c_void_p),
+                ("n_edges", ctypes.c_int32), ("edges", ctypes.c_void_p),
+                ("grid", GridDesc), ("hp", Hyper), ("chamfer_mode", ctypes.c_int32),
+                ("precond_method", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double), ("params", ctypes.c_void_p),
+                ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_F = ctypes.c_float
+_D = ctypes.c_double
+_SIGS = {
+    "pdg_last_error": (ctypes.c_char_p, []),
+    "pdg_version": (_I32, []),
+    "pdg_grid_size": (_I64, [ctypes.POINTER(GridDesc)]),
+    "pdg_deform": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P]),
+    "pdg_deform_backward_workspace": (_I32, [ctypes.POINTER(GridDesc), _I64, ctypes.POINTER(_SZ)]),
+    "pdg_deform_backward": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "pdg_chamfer_workspace": (_I32, [_I64, _I64, _I32, ctypes.POINTER(_SZ)]),
+    "pdg_chamfer": (_I32, [_P, _I64, _P, _I64, _D, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pdg_precondition_workspace": (_I32, [ctypes.POINTER(GridDesc), _I32, _I32, ctypes.POINTER(_SZ)]),
+    "pdg_precondition": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_F), _P, _I32, _I32, _I32,
+                                _D, _P, _SZ, _P]),
+    "pdg_adam": (_I32, [ctypes.POINTER(GridDesc), _I32, ctypes.POINTER(_F), _F, _F, _F, _I32, _P,
+                        _P, _P, _P, _P]),
+    "pdg_problem_workspace": (_I32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(_SZ)]),
+    "pdg_problem_create": (_I32, [ctypes.POINTER(ProblemDesc), _P, ctypes.POINTER(_P)]),
+    "pdg_step": (_I32, [_P, _I32, _P, _I32, _P]),
+    "pdg_step_batch": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_I32), ctypes.POINTER(_P),
+                              _I32, ctypes.POINTER(_P)]),
+    "pdg_problem_destroy": (_I32, [_P]),
+    "pdg_problem_buffer": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libpdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2509_18097_amd._build` (there is no fallback)")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pdg_last_error().decode()
+
+
+def check(status: int, what: str):
+    if status != OK:
+        raise PdgError(status, what, last_error())
+
+
+def grid_desc(res, level_scale=None, channels=3) -> GridDesc:
+    res = tuple(int(r) for r in res)
+    if not 1 <= len(res) <= MAX_LEVELS:
+        raise ValueError(f"need 1..{MAX_LEVELS} levels, got {len(res)}")
+    d = GridDesc()
+    d.levels = len(res)
+    for i, r in enumerate(res):
+        d.res[i] = r
+    d.channels = channels
+    d.level_scale = 1.0 / len(res) if level_scale is None else float(level_scale)
+    return d
+
+
+def grid_size(res) -> int:
+    return 3 * sum(int(r) ** 3 for r in res)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def deform(grids: torch.Tensor, x: torch.Tensor, res, level_scale=None, out=None) -> torch.Tensor:
+    """x + level_scale * sum_l trilerp(G_l, x) (Eq. 1); x SoA (3, n) float32."""
+    d = grid_desc(res, level_scale)
+    _dev(grids, torch.float32, "grids")
+    _dev(x, torch.float32, "x")
+    if grids.numel() != grid_size(res) or x.dim() != 2 or x.shape[0] != 3:
+        raise ValueError("grids must hold one packed stack and x must be (3, n)")
+    out = torch.empty_like(x) if out is None else _dev(out, torch.float32, "out")
+    check(lib().pdg_deform(ctypes.byref(d), _ptr(grids), _ptr(x), x.shape[1], _ptr(out), _stream()),
+          "pdg_deform")
+    return out
+
+
+def deform_backward(grids, x, gout, res, level_scale=None, need_grids=True, need_x=True):
+    """(dL/dG, dL/dx) for an upstream dL/dout (Eq. 1 transposed)."""
+    d = grid_desc(res, level_scale)
+    _dev(grids, torch.float32, "grids")
+    _dev(x, torch.float32, "x")
+    _dev(gout, torch.float32, "gout")
+    n = x.shape[1]
+    gg = torch.empty_like(grids) if need_grids else None
+    gx = torch.empty_like(x) if need_x else None
+    nb = ctypes.c_size_t()
+    check(lib().pdg_deform_backward_workspace(ctypes.byref(d), n, ctypes.byref(nb)),
+          "pdg_deform_backward_workspace")
+    ws = _ws(nb.value, x.device) if need_grids else None
+    check(lib().pdg_deform_backward(ctypes.byref(d), _ptr(grids), _ptr(x), n, _ptr(gout), _ptr(gg),
+                                    _ptr(gx), _ptr(ws), nb.value if ws is not None else 0,
+                                    _stream()), "pdg_deform_backward")
+    return gg, gx
+
+
+def chamfer(a, b, alpha=5.56, mode="fp32", dir_weight=None, need_grad=False):
+    """Robust Chamfer (Eq. 11-13).  Returns (loss float64 (2,), nn_a, nn_b, ga or None)."""
+    _dev(a, torch.float32, "a")
+    _dev(b, torch.float32, "b")
+    n, m = a.shape[1], b.shape[1]
+    md = CHAMFER_MODES[mode]
+    nb = ctypes.c_size_t()
+    check(lib().pdg_chamfer_workspace(n, m, md, ctypes.byref(nb)), "pdg_chamfer_workspace")
+    ws = _ws(nb.value, a.device)
+    loss = torch.empty(2, dtype=torch.float64, device=a.device)
+    nn_a = torch.empty(n, dtype=torch.int32, device=a.device)
+    nn_b = torch.empty(m, dtype=torch.int32, device=a.device)
+    ga = torch.empty_like(a) if need_grad else None
+    if dir_weight is not None:
+        dir_weight = _dev(dir_weight, torch.float64, "dir_weight")
+    check(lib().pdg_chamfer(_ptr(a), n, _ptr(b), m, float(alpha), md, _ptr(dir_weight), _ptr(loss),
+                            _ptr(nn_a), _ptr(nn_b), _ptr(ga), _ptr(ws), nb.value, _stream()),
+          "pdg_chamfer")
+    return loss, nn_a, nn_b, ga
+
+
+def precondition(g, res, lambdas, batch=1, method="cg", iters=0, tol=1e-7):
+    """In place g <- (I + lambda_l L_l)^-2 g per level (Eq. 3)."""
+    d = grid_desc(res, 1.0)
+    _dev(g, torch.float32, "g")
+    if g.numel() != batch * grid_size(res):
+        raise ValueError("g must hold `batch` packed stacks")
+    md = PRECOND_METHODS[method]
+    lam = (ctypes.c_float * MAX_LEVELS)(*[float(v) for v in lambdas])
+    nb = ctypes.c_size_t()
+    check(lib().pdg_precondition_workspace(ctypes.byref(d), batch, md, ctypes.byref(nb)),
+          "pdg_precondition_workspace")
+    ws = _ws(nb.value, g.device)
+    check(lib().pdg_precondition(ctypes.byref(d), lam, _ptr(g), batch, md, iters, tol, _ptr(ws),
+                                 nb.value, _stream()), "pdg_precondition")
+    return g
+
+
+def adam(theta, m, v, g, res, lrs, step, batch=1, beta1=0.9, beta2=0.999, eps=1e-8):
+    d = grid_desc(res, 1.0)
+    for t, nm in ((theta, "theta"), (m, "m"), (v, "v"), (g, "g")):
+        _dev(t, torch.float32, nm)
+    lr = (ctypes.c_float * MAX_LEVELS)(*[float(x) for x in lrs])
+    check(lib().pdg_adam(ctypes.byref(d), batch, lr, beta1, beta2, eps, step, _ptr(theta), _ptr(m),
+                         _ptr(v), _ptr(g), _stream()), "pdg_adam")

@@ -1,0 +1,919 @@
+// C ABI of libpdg (declared in include/pdg.h): argument validation,
+// workspace layout and the orchestration of one optimisation step.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace pdg {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+pdg_status hip_fail(hipError_t e, const char *what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return PDG_EHIP;
+}
+
+pdg_status check_grid(const pdg_grid_desc *d) {
+  if (!d) {
+    set_error("grid descriptor is NULL");
+    return PDG_EINVAL;
+  }
+  if (d->levels < 1 || d->levels > PDG_MAX_LEVELS) {
+    set_error("levels = %d outside 1..%d", d->levels, PDG_MAX_LEVELS);
+    return PDG_EINVAL;
+  }
+  if (d->channels != 3) {
+    set_error("channels = %d: only the 3-channel translation grid is implemented",
+              d->channels);
+    return d->channels == 6 ? PDG_EUNSUPPORTED : PDG_EINVAL;
+  }
+  for (int l = 0; l < d->levels; ++l)
+    if (d->res[l] < 1 || d->res[l] > 1024) {
+      set_error("res[%d] = %d outside 1..1024", l, d->res[l]);
+      return PDG_EINVAL;
+    }
+  if (!(isfinite(d->level_scale))) {
+    set_error("level_scale is not finite");
+    return PDG_EINVAL;
+  }
+  return PDG_OK;
+}
+
+GridDev make_grid(const pdg_grid_desc &d) {
+  GridDev g;
+  memset(&g, 0, sizeof g);
+  g.levels = d.levels;
+  long long off = 0, noff = 0;
+  for (int l = 0; l < d.levels; ++l) {
+    const long long r3 = (long long)d.res[l] * d.res[l] * d.res[l];
+    g.res[l] = d.res[l];
+    g.off[l] = off;
+    g.noff[l] = noff;
+    off += 3 * r3;
+    noff += r3;
+  }
+  g.size = off;
+  g.nodes = noff;
+  g.scale = d.level_scale;
+  return g;
+}
+
+namespace {
+
+inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over a caller workspace; with base == nullptr it only sizes.
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base((char *)b) {}
+  template <class T>
+  T *take(long long count) {
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += a256((size_t)(count > 0 ? count : 0) * sizeof(T));
+    return p;
+  }
+};
+
+int bits_for(unsigned long long maxkey) {
+  int b = 1;
+  while (b < 32 && (1ull << b) <= maxkey) ++b;
+  return b;
+}
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
+
+pdg_status need(const void *p, const char *name) {
+  if (!p) {
+    set_error("%s is NULL", name);
+    return PDG_EINVAL;
+  }
+  if (!aligned4(p)) {
+    set_error("%s is not 4-byte aligned", name);
+    return PDG_EINVAL;
+  }
+  return PDG_OK;
+}
+
+// ------------------------------------------------------ deform backward --
+struct DeformBwdWs {
+  uint32_t *keys, *vals;
+  void *sort;
+};
+DeformBwdWs deform_bwd_layout(Carve &c, int levels, long long n) {
+  DeformBwdWs w;
+  const long long ne = (long long)levels * n;
+  w.keys = c.take<uint32_t>(ne);
+  w.vals = c.take<uint32_t>(ne);
+  w.sort = c.take<char>((long long)radix_sort_bytes(ne));
+  return w;
+}
+
+// Deterministic grid scatter of `segs` sample segments with S samples each.
+pdg_status grid_scatter(const GridDev &g, const float *x, long long xstride, long long ldx,
+                        long long S, int segs, const float *lam, long long lstride, long long ldl,
+                        float *grad, uint32_t *keys, uint32_t *vals, void *sort, bool keys_ready,
+                        hipStream_t st) {
+  const long long nent = (long long)segs * g.levels * S;
+  if (!keys_ready) {
+    PDG_TRY(launch_scatter_keys(g, x, xstride, ldx, S, segs, keys, vals, st));
+    PDG_TRY(radix_sort(keys, vals, nent, bits_for((unsigned long long)segs * g.nodes), sort, st));
+  }
+  for (int delta = 0; delta < 8; ++delta)
+    PDG_TRY(launch_scatter_pass(g, delta, keys, vals, nent, S, x, xstride, ldx, lam, lstride, ldl,
+                                grad, st));
+  return PDG_OK;
+}
+
+// --------------------------------------------------------------- chamfer --
+struct ChamferWs {
+  NNJob *jobs;
+  ChSeg *segs;
+  unsigned *b_base;
+  double *partials, *w_default;
+  uint32_t *keys, *vals;
+  void *sort;
+};
+ChamferWs chamfer_layout(Carve &c, long long n, long long m) {
+  ChamferWs w;
+  w.jobs = c.take<NNJob>(2);
+  w.segs = c.take<ChSeg>(1);
+  w.b_base = c.take<unsigned>(1);
+  w.partials = c.take<double>(2 * kLossBlocks);
+  w.w_default = c.take<double>(2);
+  w.keys = c.take<uint32_t>(m);
+  w.vals = c.take<uint32_t>(m);
+  w.sort = c.take<char>((long long)radix_sort_bytes(m));
+  return w;
+}
+
+// ---------------------------------------------------------- precondition --
+struct CGPlan {
+  std::vector<CGSys> sys;
+  int ntiles = 0;
+  int kmax = 0;
+};
+
+int cg_count(float lam, double tol) {
+  const double kappa = 1.0 + 12.0 * (double)lam;
+  const double sq = sqrt(kappa);
+  const double rho = (sq - 1.0) / (sq + 1.0);
+  if (rho <= 0.0) return 1;
+  const double k = ceil(log(2.0 / tol) / -log(rho));
+  return k < 1.0 ? 1 : (int)k;
+}
+
+CGPlan cg_plan(const GridDev &g, int batch, const float *lam, int iters, double tol) {
+  CGPlan p;
+  for (int b = 0; b < batch; ++b)
+    for (int l = 0; l < g.levels; ++l) {
+      const long long r3 = (long long)g.res[l] * g.res[l] * g.res[l];
+      // lam = 0: A = I, one CG iteration reproduces the input exactly
+      const int k = lam[l] == 0.0f ? 1 : (iters > 0 ? iters : cg_count(lam[l], tol));
+      for (int c = 0; c < 3; ++c) {
+        CGSys s;
+        s.base = (long long)b * g.size + g.off[l] + c * r3;
+        s.R = g.res[l];
+        s.iters = k;
+        s.lam = lam[l];
+        s.tile0 = p.ntiles;
+        p.ntiles += (int)((r3 + 1023) / 1024);
+        if (k > p.kmax) p.kmax = k;
+        p.sys.push_back(s);
+      }
+    }
+  return p;
+}
+
+pdg_status check_precond_args(const pdg_grid_desc *d, const float *lambda, int32_t batch,
+                              int32_t method, int32_t iters, double tol) {
+  PDG_TRY(check_grid(d));
+  if (!lambda) {
+    set_error("lambda is NULL");
+    return PDG_EINVAL;
+  }
+  for (int l = 0; l < d->levels; ++l)
+    if (!(lambda[l] >= 0.0f) || !isfinite(lambda[l])) {
+      set_error("lambda[%d] must be finite and >= 0", l);
+      return PDG_EINVAL;
+    }
+  if (batch < 0) {
+    set_error("batch < 0");
+    return PDG_EINVAL;
+  }
+  if (method != PDG_PRECOND_CG && method != PDG_PRECOND_DCT) {
+    set_error("unknown preconditioner method %d", method);
+    return PDG_EINVAL;
+  }
+  if (method == PDG_PRECOND_DCT) {
+    set_error("DCT preconditioner is not built into this library");
+    return PDG_EUNSUPPORTED;
+  }
+  if (iters < 0 || (iters == 0 && !(tol > 0.0 && tol < 1.0))) {
+    set_error("iters must be >= 0, and tol in (0,1) when iters == 0");
+    return PDG_EINVAL;
+  }
+  return PDG_OK;
+}
+
+size_t cg_ws_bytes(const CGPlan &p, long long floats) {
+  return a256(p.sys.size() * sizeof(CGSys)) + cg_bytes(floats, (int)p.sys.size(), p.ntiles);
+}
+
+}  // namespace
+}  // namespace pdg
+
+using namespace pdg;
+
+// ----------------------------------------------------------------- problem --
+struct pdg_problem {
+  pdg_problem_desc d;
+  GridDev g;
+  int T = 0, F = 0;
+  long long N = 0, V = 0, E = 0, P = 0;
+  bool has_tm = false;
+  // intermediate buffers (carved from the workspace)
+  float *phat = nullptr, *xhat = nullptr, *grad = nullptr, *pgrad = nullptr;
+  float *gphat = nullptr, *gxhat = nullptr, *lam = nullptr, *sig = nullptr, *u = nullptr;
+  int *nn = nullptr, *inc_off = nullptr, *epoch = nullptr;
+  double *losses = nullptr, *w = nullptr, *wconf = nullptr, *terms = nullptr;
+  double *partials = nullptr, *iso_partials = nullptr;
+  uint32_t *pkeys = nullptr, *pvals = nullptr, *tkeys = nullptr, *tvals = nullptr;
+  uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
+  void *sort = nullptr;
+  NNJob *jobs = nullptr;
+  ChSeg *segs = nullptr;
+  unsigned *b_base = nullptr;
+  CGSys *cgsys = nullptr;
+  void *cgws = nullptr;
+  int njobs = 0, nseg = 0, max_nq = 0, max_n = 0, max_m = 0;
+  long long nrev = 0;
+  CGPlan cg;
+  AdamLevels adam;
+  size_t ws_used = 0;
+  // graph replay
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace pdg {
+namespace {
+
+pdg_status check_problem(const pdg_problem_desc *pd) {
+  if (!pd) {
+    set_error("problem descriptor is NULL");
+    return PDG_EINVAL;
+  }
+  PDG_TRY(check_grid(&pd->grid));
+  if (pd->frames < 2) {
+    set_error("frames = %d: need at least 2", pd->frames);
+    return PDG_EINVAL;
+  }
+  if (pd->n < 1 || pd->n >= (1ll << 31)) {
+    set_error("n = %lld outside [1, 2^31)", (long long)pd->n);
+    return PDG_EINVAL;
+  }
+  if (pd->verts < 0 || pd->n_edges < 0 || (pd->verts == 0 && pd->n_edges > 0)) {
+    set_error("verts/n_edges invalid");
+    return PDG_EINVAL;
+  }
+  PDG_TRY(need(pd->points, "points"));
+  if (pd->verts > 0) PDG_TRY(need(pd->template_verts, "template_verts"));
+  if (pd->n_edges > 0) PDG_TRY(need(pd->edges, "edges"));
+  PDG_TRY(need(pd->params, "params"));
+  PDG_TRY(need(pd->adam_m, "adam_m"));
+  PDG_TRY(need(pd->adam_v, "adam_v"));
+  if (pd->chamfer_mode != PDG_CHAMFER_FP32 && pd->chamfer_mode != PDG_CHAMFER_BF16_SCREEN) {
+    set_error("unknown chamfer mode %d", pd->chamfer_mode);
+    return PDG_EINVAL;
+  }
+  if (pd->chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
+    set_error("BF16 screen is not built into this library");
+    return PDG_EUNSUPPORTED;
+  }
+  const pdg_hyper &h = pd->hp;
+  if (!(h.alpha >= 0.0) || !isfinite(h.alpha) || !(h.w_iso >= 0.f) || !(h.eta0 > 0.f) || !(h.eta_growth > 0.f) ||
+      !(h.lambda0 >= 0.f) || !(h.lambda_growth > 0.f) || !(h.beta1 >= 0.f && h.beta1 < 1.f) ||
+      !(h.beta2 >= 0.f && h.beta2 < 1.f) || !(h.eps > 0.f) || h.e_max < 1) {
+    set_error("hyperparameters out of range");
+    return PDG_EINVAL;
+  }
+  float lam[PDG_MAX_LEVELS];
+  for (int l = 0; l < pd->grid.levels; ++l) lam[l] = pd->hp.lambda0 * powf(pd->hp.lambda_growth, (float)l);
+  PDG_TRY(check_precond_args(&pd->grid, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
+  const GridDev g = make_grid(pd->grid);
+  const long long T = pd->frames - 1;
+  if ((unsigned long long)T * g.nodes >= (1ull << 32)) {
+    set_error("T * nodes = %lld does not fit the 32-bit scatter keys", T * g.nodes);
+    return PDG_EINVAL;
+  }
+  if ((unsigned long long)T * g.levels * (pd->n > pd->verts ? pd->n : pd->verts) >= (1ull << 31)) {
+    set_error("T * levels * samples exceeds 2^31 scatter entries");
+    return PDG_EINVAL;
+  }
+  if ((unsigned long long)T * (pd->n + pd->verts) >= (1ull << 31)) {
+    set_error("T * (n + V) exceeds 2^31");
+    return PDG_EINVAL;
+  }
+  return PDG_OK;
+}
+
+// Lays out (or sizes, with base == nullptr) every buffer of a problem.
+void layout(pdg_problem &p, Carve &c) {
+  const long long T = p.T, F = p.F, N = p.N, V = p.V, E = p.E, P = p.P, L = p.g.levels;
+  p.phat = c.take<float>(T * 3 * N);
+  p.xhat = c.take<float>(F * 3 * V);
+  p.nn = c.take<int>(T * (2 * N + V + N));
+  p.losses = c.take<double>(4 * T);
+  p.w = c.take<double>(4 * T);
+  p.wconf = c.take<double>(T);
+  p.terms = c.take<double>(8);
+  p.partials = c.take<double>(4 * T * kLossBlocks);
+  p.iso_partials = c.take<double>(kLossBlocks);
+  p.grad = c.take<float>(T * P);
+  p.pgrad = c.take<float>(T * P);
+  p.gphat = c.take<float>(T * 3 * N);
+  p.gxhat = c.take<float>(T * 3 * V);
+  p.lam = c.take<float>(T * 3 * V);
+  p.sig = c.take<float>(T * E);
+  p.u = c.take<float>(T * 3 * E);
+  p.inc_off = c.take<int>(V + 1);
+  p.epoch = c.take<int>(1);
+  p.pkeys = c.take<uint32_t>(T * L * N);
+  p.pvals = c.take<uint32_t>(T * L * N);
+  p.tkeys = c.take<uint32_t>(T * L * V);
+  p.tvals = c.take<uint32_t>(T * L * V);
+  p.nrev = T * N * (p.has_tm ? 2 : 1);
+  p.rkeys = c.take<uint32_t>(p.nrev);
+  p.rvals = c.take<uint32_t>(p.nrev);
+  p.ikeys = c.take<uint32_t>(2 * E);
+  p.ivals = c.take<uint32_t>(2 * E);
+  long long smax = T * L * N;
+  if (T * L * V > smax) smax = T * L * V;
+  if (p.nrev > smax) smax = p.nrev;
+  if (2 * E > smax) smax = 2 * E;
+  p.sort = c.take<char>((long long)radix_sort_bytes(smax));
+  p.nseg = (int)(p.has_tm ? 2 * T : T);
+  p.njobs = 2 * p.nseg;
+  p.jobs = c.take<NNJob>(p.njobs);
+  p.segs = c.take<ChSeg>(p.nseg);
+  p.b_base = c.take<unsigned>(p.nseg);
+  p.cgsys = c.take<CGSys>((long long)p.cg.sys.size());
+  p.cgws = c.take<char>((long long)cg_bytes(T * P, (int)p.cg.sys.size(), p.cg.ntiles));
+}
+
+void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
+  p.d = pd;
+  p.g = make_grid(pd.grid);
+  p.F = pd.frames;
+  p.T = pd.frames - 1;
+  p.N = pd.n;
+  p.V = pd.verts;
+  p.E = pd.verts > 0 ? pd.n_edges : 0;
+  p.P = p.g.size;
+  p.has_tm = p.V > 0;
+  float lam[PDG_MAX_LEVELS];
+  p.adam.levels = p.g.levels;
+  for (int l = 0; l < p.g.levels; ++l) {
+    lam[l] = pd.hp.lambda0 * powf(pd.hp.lambda_growth, (float)l);
+    p.adam.lr[l] = pd.hp.eta0 * powf(pd.hp.eta_growth, (float)l);
+    p.adam.off[l] = p.g.off[l];
+  }
+  p.adam.off[p.g.levels] = p.g.size;
+  p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol);
+}
+
+pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
+  const GridDev &g = p.g;
+  const long long T = p.T, N = p.N, V = p.V, P = p.P;
+  const pdg_hyper &h = p.d.hp;
+  // 1. warps (Eq. 1, Eq. 8)
+  PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T, st));
+  if (p.has_tm) {
+    PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
+    for (long long t = 0; t < T; ++t)
+      PDG_TRY(launch_warp(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0, V,
+                          p.xhat + (t + 1) * 3 * V, 0, V, V, 1, st));
+  }
+  // 2. nearest neighbours and Chamfer losses (Eq. 11-13)
+  PDG_TRY(launch_nn_exact(p.jobs, p.njobs, p.max_nq, st));
+  PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
+  IsoArgs ia;
+  ia.xhat = p.xhat;
+  ia.edges = p.d.edges;
+  ia.V = (int)V;
+  ia.E = (int)p.E;
+  ia.T = (int)T;
+  ia.sig = p.sig;
+  ia.u = p.u;
+  ia.partials = p.iso_partials;
+  ia.inc_off = p.inc_off;
+  ia.inc = p.ivals;
+  ia.gx = p.gxhat;
+  ia.coef = p.E > 0 ? (double)h.w_iso / ((double)T * (double)p.E) : 0.0;
+  // edge pass here (loss); the vertex pass adds its gradient after the
+  // Chamfer gradient has been written into gxhat
+  if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_edges(ia, st));
+  // 3. confidence weights and loss assembly (Eq. 9, 14-17)
+  AssembleArgs aa;
+  aa.losses = p.losses;
+  aa.iso_partials = p.iso_partials;
+  aa.T = (int)T;
+  aa.E = (int)p.E;
+  aa.has_tm = p.has_tm ? 1 : 0;
+  aa.epoch = p.epoch;
+  aa.e_max = h.e_max;
+  aa.w_iso = h.w_iso;
+  aa.w = p.w;
+  aa.wconf = p.wconf;
+  aa.terms = p.terms;
+  aa.user_terms = user_terms;
+  PDG_TRY(launch_assemble(aa, st));
+  // 4. gradient wrt warped positions: forward direction (overwrite), reverse
+  //    direction (sorted runs), isometry (vertex gather)
+  PDG_TRY(launch_chamfer_grad_fwd(p.segs, p.nseg, p.max_n, (float)h.alpha, p.w, st));
+  PDG_TRY(launch_chamfer_rev_keys(p.segs, p.nseg, p.max_m, p.b_base, p.rkeys, p.rvals, st));
+  PDG_TRY(radix_sort(p.rkeys, p.rvals, p.nrev,
+                     bits_for((unsigned long long)(T * N + T * V)), p.sort, st));
+  PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, nullptr, p.rkeys, p.rvals, p.nrev,
+                                     (float)h.alpha, p.w, st));
+  if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(ia, st));
+  // 5. reverse sweep of the template chain (adjoint of Eq. 8)
+  if (p.has_tm) {
+    PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
+    for (long long k = T - 1; k >= 1; --k)
+      PDG_TRY(launch_chain_adjoint(g, p.d.params + k * P, p.xhat + k * 3 * V, V,
+                                   p.lam + k * 3 * V, V, p.gxhat + (k - 1) * 3 * V, V,
+                                   p.lam + (k - 1) * 3 * V, V, V, st));
+  }
+  // 6. deterministic scatter into the grids (transpose of Eq. 1)
+  PDG_TRY(launch_fill(p.grad, T * P, 0.f, st));
+  PDG_TRY(grid_scatter(g, p.d.points, 3 * N, N, N, (int)T, p.gphat, 3 * N, N, p.grad, p.pkeys,
+                       p.pvals, p.sort, true, st));
+  if (p.has_tm)
+    PDG_TRY(grid_scatter(g, p.xhat, 3 * V, V, V, (int)T, p.lam, 3 * V, V, p.grad, p.tkeys,
+                         p.tvals, p.sort, false, st));
+  // 7. preconditioner (Eq. 3) and Adam (Sec. 3.6)
+  PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
+  PDG_TRY(run_cg(p.cgsys, (int)p.cg.sys.size(), p.cg.ntiles, p.cg.kmax, p.pgrad, T * P, p.cgws,
+                 st));
+  PDG_TRY(launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
+                      p.d.adam_m, p.d.adam_v, p.pgrad, st));
+  return PDG_OK;
+}
+
+}  // namespace
+}  // namespace pdg
+
+extern "C" {
+
+const char *pdg_last_error(void) { return g_err.c_str(); }
+
+int32_t pdg_version(void) { return 100; }
+
+int64_t pdg_grid_size(const pdg_grid_desc *d) {
+  if (check_grid(d) != PDG_OK) return -1;
+  return make_grid(*d).size;
+}
+
+pdg_status pdg_deform(const pdg_grid_desc *d, const float *grids, const float *x, int64_t n,
+                      float *out, hipStream_t stream) {
+  PDG_TRY(check_grid(d));
+  if (n < 0 || n >= (1ll << 40)) {
+    set_error("n = %lld invalid", (long long)n);
+    return PDG_EINVAL;
+  }
+  if (n == 0) return PDG_OK;
+  PDG_TRY(need(grids, "grids"));
+  PDG_TRY(need(x, "x"));
+  PDG_TRY(need(out, "out"));
+  const GridDev g = make_grid(*d);
+  return launch_warp(g, grids, 0, x, 0, n, out, 0, n, n, 1, stream);
+}
+
+pdg_status pdg_deform_backward_workspace(const pdg_grid_desc *d, int64_t n, size_t *bytes) {
+  PDG_TRY(check_grid(d));
+  if (!bytes || n < 0) {
+    set_error("bytes is NULL or n < 0");
+    return PDG_EINVAL;
+  }
+  Carve c(nullptr);
+  deform_bwd_layout(c, d->levels, n);
+  *bytes = c.off;
+  return PDG_OK;
+}
+
+pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const float *x,
+                               int64_t n, const float *gout, float *ggrids, float *gx, void *ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  PDG_TRY(check_grid(d));
+  if (n < 0) {
+    set_error("n < 0");
+    return PDG_EINVAL;
+  }
+  const GridDev g = make_grid(*d);
+  if ((long long)d->levels * n >= (1ll << 31) || (unsigned long long)g.nodes >= (1ull << 32)) {
+    set_error("problem too large for 32-bit scatter entries");
+    return PDG_EINVAL;
+  }
+  if (ggrids) PDG_TRY(need(ggrids, "ggrids"));
+  if (gx) PDG_TRY(need(grids, "grids"));
+  if (n > 0) {
+    PDG_TRY(need(x, "x"));
+    PDG_TRY(need(gout, "gout"));
+  }
+  if (ggrids) {
+    Carve probe(nullptr);
+    deform_bwd_layout(probe, d->levels, n);
+    if (!ws || ws_bytes < probe.off) {
+      set_error("workspace of %zu bytes < %zu needed", ws_bytes, probe.off);
+      return PDG_ENOMEM;
+    }
+    Carve c(ws);
+    DeformBwdWs w = deform_bwd_layout(c, d->levels, n);
+    PDG_TRY(launch_fill(ggrids, g.size, 0.f, stream));
+    if (n > 0)
+      PDG_TRY(grid_scatter(g, x, 0, n, n, 1, gout, 0, n, ggrids, w.keys, w.vals, w.sort, false,
+                           stream));
+  }
+  if (gx && n > 0)
+    PDG_TRY(launch_chain_adjoint(g, grids, x, n, gout, n, nullptr, 0, gx, n, n, stream));
+  return PDG_OK;
+}
+
+pdg_status pdg_chamfer_workspace(int64_t n, int64_t m, int32_t mode, size_t *bytes) {
+  if (!bytes || n < 1 || m < 1 || n >= (1ll << 31) || m >= (1ll << 31)) {
+    set_error("bytes NULL or n, m outside [1, 2^31)");
+    return PDG_EINVAL;
+  }
+  if (mode != PDG_CHAMFER_FP32 && mode != PDG_CHAMFER_BF16_SCREEN) {
+    set_error("unknown chamfer mode %d", mode);
+    return PDG_EINVAL;
+  }
+  Carve c(nullptr);
+  chamfer_layout(c, n, m);
+  *bytes = c.off;
+  return PDG_OK;
+}
+
+pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, double alpha,
+                       int32_t mode, const double *dir_weight, double *loss, int32_t *nn_a,
+                       int32_t *nn_b, float *ga, void *ws, size_t ws_bytes, hipStream_t stream) {
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_chamfer_workspace(n, m, mode, &need_bytes));
+  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+    set_error("BF16 screen is not built into this library");
+    return PDG_EUNSUPPORTED;
+  }
+  if (!(alpha >= 0.0) || !isfinite(alpha)) {
+    set_error("alpha must be finite and >= 0");
+    return PDG_EINVAL;
+  }
+  PDG_TRY(need(a, "a"));
+  PDG_TRY(need(b, "b"));
+  PDG_TRY(need(loss, "loss"));
+  PDG_TRY(need(nn_a, "nn_a"));
+  PDG_TRY(need(nn_b, "nn_b"));
+  if (ga) PDG_TRY(need(ga, "ga"));
+  if (!ws || ws_bytes < need_bytes) {
+    set_error("workspace of %zu bytes < %zu needed", ws_bytes, need_bytes);
+    return PDG_ENOMEM;
+  }
+  Carve c(ws);
+  ChamferWs w = chamfer_layout(c, n, m);
+  NNJob jobs[2];
+  memset(jobs, 0, sizeof jobs);
+  jobs[0].q = a;
+  jobs[0].c = b;
+  jobs[0].nq = (int)n;
+  jobs[0].nc = (int)m;
+  jobs[0].nn = nn_a;
+  jobs[1].q = b;
+  jobs[1].c = a;
+  jobs[1].nq = (int)m;
+  jobs[1].nc = (int)n;
+  jobs[1].nn = nn_b;
+  ChSeg seg;
+  memset(&seg, 0, sizeof seg);
+  seg.a = a;
+  seg.b = b;
+  seg.n = (int)n;
+  seg.m = (int)m;
+  seg.nn_a = nn_a;
+  seg.nn_b = nn_b;
+  seg.ga = ga;
+  seg.a_base = 0;
+  const unsigned bb = 0;
+  const double ones[2] = {1.0, 1.0};
+  PDG_TRY(upload_small(w.jobs, jobs, sizeof jobs, stream));
+  PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
+  PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
+  PDG_TRY(upload_small(w.w_default, ones, sizeof ones, stream));
+  PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
+  PDG_TRY(launch_chamfer_loss(w.segs, 1, alpha, w.partials, loss, stream));
+  if (ga) {
+    const double *dw = dir_weight ? dir_weight : w.w_default;
+    PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dw, stream));
+    PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
+    PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
+    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, nullptr, w.keys, w.vals, m,
+                                       (float)alpha, dw, stream));
+  }
+  return PDG_OK;
+}
+
+pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int32_t method,
+                                      size_t *bytes) {
+  PDG_TRY(check_grid(d));
+  if (!bytes || batch < 0) {
+    set_error("bytes NULL or batch < 0");
+    return PDG_EINVAL;
+  }
+  if (method != PDG_PRECOND_CG && method != PDG_PRECOND_DCT) {
+    set_error("unknown preconditioner method %d", method);
+    return PDG_EINVAL;
+  }
+  const GridDev g = make_grid(*d);
+  float lam[PDG_MAX_LEVELS];
+  for (int l = 0; l < d->levels; ++l) lam[l] = 1.0f;
+  CGPlan p = cg_plan(g, batch, lam, 1, 0.5);
+  *bytes = cg_ws_bytes(p, g.size * batch);
+  return PDG_OK;
+}
+
+pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *g, int32_t batch,
+                            int32_t method, int32_t iters, double tol, void *ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  PDG_TRY(check_precond_args(d, lambda, batch, method, iters, tol));
+  if (batch == 0) return PDG_OK;
+  PDG_TRY(need(g, "g"));
+  size_t nb = 0;
+  PDG_TRY(pdg_precondition_workspace(d, batch, method, &nb));
+  if (!ws || ws_bytes < nb) {
+    set_error("workspace of %zu bytes < %zu needed", ws_bytes, nb);
+    return PDG_ENOMEM;
+  }
+  const GridDev gd = make_grid(*d);
+  CGPlan p = cg_plan(gd, batch, lambda, iters, tol);
+  const size_t tbytes = p.sys.size() * sizeof(CGSys);
+  char *w = (char *)ws;
+  for (size_t off = 0; off < tbytes; off += 2048) {
+    const size_t chunk = tbytes - off < 2048 ? tbytes - off : 2048;
+    PDG_TRY(upload_small(w + off, (const char *)p.sys.data() + off, chunk, stream));
+  }
+  return run_cg((const CGSys *)w, (int)p.sys.size(), p.ntiles, p.kmax, g, gd.size * batch,
+                w + ((tbytes + 255) & ~(size_t)255), stream);
+}
+
+pdg_status pdg_adam(const pdg_grid_desc *d, int32_t batch, const float *lr, float beta1,
+                    float beta2, float eps, int32_t step, float *theta, float *m, float *v,
+                    const float *g, hipStream_t stream) {
+  PDG_TRY(check_grid(d));
+  if (!lr || batch < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f)) {
+    set_error("invalid Adam arguments");
+    return PDG_EINVAL;
+  }
+  if (batch == 0) return PDG_OK;
+  PDG_TRY(need(theta, "theta"));
+  PDG_TRY(need(m, "m"));
+  PDG_TRY(need(v, "v"));
+  PDG_TRY(need(g, "g"));
+  const GridDev gd = make_grid(*d);
+  AdamLevels lv;
+  lv.levels = gd.levels;
+  for (int l = 0; l < gd.levels; ++l) {
+    lv.off[l] = gd.off[l];
+    lv.lr[l] = lr[l];
+  }
+  lv.off[gd.levels] = gd.size;
+  return launch_adam(lv, gd.size, batch, beta1, beta2, eps, nullptr, step, theta, m, v, g, stream);
+}
+
+pdg_status pdg_problem_workspace(const pdg_problem_desc *pd, size_t *bytes) {
+  PDG_TRY(check_problem(pd));
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return PDG_EINVAL;
+  }
+  pdg_problem p;
+  init_problem(p, *pd);
+  Carve c(nullptr);
+  layout(p, c);
+  *bytes = c.off;
+  return PDG_OK;
+}
+
+pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out) {
+  PDG_TRY(check_problem(pd));
+  if (!out) {
+    set_error("out is NULL");
+    return PDG_EINVAL;
+  }
+  pdg_problem *p = new (std::nothrow) pdg_problem;
+  if (!p) {
+    set_error("host allocation failed");
+    return PDG_ENOMEM;
+  }
+  init_problem(*p, *pd);
+  Carve probe(nullptr);
+  layout(*p, probe);
+  if (!pd->workspace || pd->workspace_bytes < probe.off) {
+    set_error("workspace of %zu bytes < %zu needed", pd->workspace_bytes, probe.off);
+    delete p;
+    return PDG_ENOMEM;
+  }
+  Carve c(pd->workspace);
+  layout(*p, c);
+  p->ws_used = c.off;
+  const long long T = p->T, N = p->N, V = p->V;
+  // Chamfer pairs: point term P^_t <-> P_t, template term X_t <-> P_t
+  std::vector<ChSeg> segs(p->nseg);
+  std::vector<NNJob> jobs(p->njobs);
+  std::vector<unsigned> bb(p->nseg);
+  unsigned bsum = 0;
+  for (int s = 0; s < p->nseg; ++s) {
+    const bool tm = s >= T;
+    const long long t = tm ? s - T : s;
+    ChSeg &q = segs[s];
+    memset(&q, 0, sizeof q);
+    q.b = pd->points + (t + 1) * 3 * N;
+    q.m = (int)N;
+    if (!tm) {
+      q.a = p->phat + t * 3 * N;
+      q.n = (int)N;
+      q.nn_a = p->nn + t * 2 * N;
+      q.nn_b = q.nn_a + N;
+      q.ga = p->gphat + t * 3 * N;
+      q.a_base = (unsigned)(t * N);
+    } else {
+      q.a = p->xhat + (t + 1) * 3 * V;
+      q.n = (int)V;
+      q.nn_a = p->nn + T * 2 * N + t * (V + N);
+      q.nn_b = q.nn_a + V;
+      q.ga = p->gxhat + t * 3 * V;
+      q.a_base = (unsigned)(T * N + t * V);
+    }
+    bb[s] = bsum;
+    bsum += (unsigned)q.m;
+    NNJob &j0 = jobs[2 * s];
+    NNJob &j1 = jobs[2 * s + 1];
+    memset(&j0, 0, sizeof j0);
+    memset(&j1, 0, sizeof j1);
+    j0.q = q.a;
+    j0.c = q.b;
+    j0.nq = q.n;
+    j0.nc = q.m;
+    j0.nn = q.nn_a;
+    j1.q = q.b;
+    j1.c = q.a;
+    j1.nq = q.m;
+    j1.nc = q.n;
+    j1.nn = q.nn_b;
+    if (q.n > p->max_nq) p->max_nq = q.n;
+    if (q.m > p->max_nq) p->max_nq = q.m;
+    if (q.n > p->max_n) p->max_n = q.n;
+    if (q.m > p->max_m) p->max_m = q.m;
+  }
+  hipError_t e = hipSuccess;
+  if (p->E > 0) {
+    // edge indices index the template on the GPU: check their range once
+    std::vector<int32_t> eh(2 * p->E);
+    e = hipMemcpy(eh.data(), pd->edges, eh.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      pdg_status s = hip_fail(e, "pdg_problem_create edge check");
+      delete p;
+      return s;
+    }
+    for (size_t i = 0; i < eh.size(); ++i)
+      if (eh[i] < 0 || eh[i] >= V) {
+        set_error("edge index %d at position %zu outside [0, %lld)", eh[i], i, V);
+        delete p;
+        return PDG_EINVAL;
+      }
+  }
+  if (e == hipSuccess) e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(ChSeg), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->jobs, jobs.data(), jobs.size() * sizeof(NNJob), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->b_base, bb.data(), bb.size() * sizeof(unsigned), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !p->cg.sys.empty())
+    e = hipMemcpy(p->cgsys, p->cg.sys.data(), p->cg.sys.size() * sizeof(CGSys), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    pdg_status s = hip_fail(e, "pdg_problem_create table upload");
+    delete p;
+    return s;
+  }
+  // static scatter entries of the input points (fixed positions)
+  pdg_status s = launch_scatter_keys(p->g, pd->points, 3 * N, N, N, (int)T, p->pkeys, p->pvals, stream);
+  if (s == PDG_OK)
+    s = radix_sort(p->pkeys, p->pvals, T * p->g.levels * N,
+                   bits_for((unsigned long long)T * p->g.nodes), p->sort, stream);
+  if (s == PDG_OK && p->has_tm)
+    s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
+                         stream);
+  if (s == PDG_OK) s = launch_set_int(p->epoch, 0, stream);
+  if (s != PDG_OK) {
+    delete p;
+    return s;
+  }
+  *out = p;
+  return PDG_OK;
+}
+
+pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t use_graph,
+                    hipStream_t stream) {
+  if (!p) {
+    set_error("problem is NULL");
+    return PDG_EINVAL;
+  }
+  if (epoch < 0 || epoch > p->d.hp.e_max) {
+    set_error("epoch %d outside [0, e_max = %d]", epoch, p->d.hp.e_max);
+    return PDG_EINVAL;
+  }
+  PDG_TRY(launch_set_int(p->epoch, epoch, stream));
+  if (!use_graph) return enqueue_step(*p, stream, loss_terms);
+  if (loss_terms) {
+    set_error("loss_terms must be NULL with use_graph (read PDG_BUF terms instead)");
+    return PDG_EINVAL;
+  }
+  if (!p->exec) {
+    if (!p->cap) PDG_TRY_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    PDG_TRY_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    pdg_status s = enqueue_step(*p, p->cap, nullptr);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap, &graph);
+    if (s != PDG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    p->graph = graph;
+    PDG_TRY_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  }
+  PDG_TRY_HIP(hipGraphLaunch(p->exec, stream));
+  return PDG_OK;
+}
+
+pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *epochs,
+                          double *const *loss_terms, int32_t use_graph,
+                          const hipStream_t *streams) {
+  if (count < 0 || (count > 0 && (!ps || !epochs || !streams))) {
+    set_error("invalid batch arguments");
+    return PDG_EINVAL;
+  }
+  for (int i = 0; i < count; ++i)
+    PDG_TRY(pdg_step(ps[i], epochs[i], loss_terms ? loss_terms[i] : nullptr, use_graph,
+                     streams[i]));
+  return PDG_OK;
+}
+
+pdg_status pdg_problem_destroy(pdg_problem *p) {
+  if (!p) return PDG_OK;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+  return PDG_OK;
+}
+
+pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes) {
+  if (!p || !ptr || !bytes) {
+    set_error("NULL argument");
+    return PDG_EINVAL;
+  }
+  const long long T = p->T, N = p->N, V = p->V, P = p->P;
+  switch (which) {
+    case PDG_BUF_PHAT: *ptr = p->phat; *bytes = T * 3 * N * 4; break;
+    case PDG_BUF_XHAT: *ptr = p->xhat; *bytes = (T + 1) * 3 * V * 4; break;
+    case PDG_BUF_NN: *ptr = p->nn; *bytes = T * (2 * N + (p->has_tm ? V + N : 0)) * 4; break;
+    case PDG_BUF_LOSSES: *ptr = p->losses; *bytes = T * 4 * 8; break;
+    case PDG_BUF_WCONF: *ptr = p->wconf; *bytes = T * 8; break;
+    case PDG_BUF_GRAD: *ptr = p->grad; *bytes = T * P * 4; break;
+    case PDG_BUF_PGRAD: *ptr = p->pgrad; *bytes = T * P * 4; break;
+    case PDG_BUF_GPHAT: *ptr = p->gphat; *bytes = T * 3 * N * 4; break;
+    case PDG_BUF_GXHAT: *ptr = p->gxhat; *bytes = T * 3 * V * 4; break;
+    case PDG_BUF_TERMS: *ptr = p->terms; *bytes = 8 * 8; break;
+    default:
+      set_error("unknown buffer %d", which);
+      return PDG_EINVAL;
+  }
+  return PDG_OK;
+}
+
+}  // extern "C"

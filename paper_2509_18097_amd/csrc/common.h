@@ -1,0 +1,193 @@
+// Internal declarations shared by the HIP translation units of libpdg.
+// Not part of the public ABI (that is include/pdg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "pdg.h"
+
+namespace pdg {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const char *fmt, ...);
+pdg_status hip_fail(hipError_t e, const char *what);
+
+#define PDG_TRY_HIP(expr)                                                  \
+  do {                                                                     \
+    hipError_t _e = (expr);                                                \
+    if (_e != hipSuccess) return ::pdg::hip_fail(_e, #expr);               \
+  } while (0)
+
+#define PDG_TRY(expr)                                                      \
+  do {                                                                     \
+    pdg_status _s = (expr);                                                \
+    if (_s != PDG_OK) return _s;                                           \
+  } while (0)
+
+// Check the launch that was just enqueued.
+inline pdg_status launched(const char *what) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PDG_OK : hip_fail(e, what);
+}
+
+// ------------------------------------------------------------ grid layout --
+// Device-side copy of a grid stack description: per level the resolution,
+// the float offset of the level inside the packed stack and the node offset
+// (one channel) inside the stack's node numbering.
+struct GridDev {
+  int levels;
+  int res[PDG_MAX_LEVELS];
+  long long off[PDG_MAX_LEVELS];     // float offset of level l (3 channels)
+  long long noff[PDG_MAX_LEVELS];    // node offset of level l (per channel)
+  long long size;                    // floats per stack = 3 * nodes
+  long long nodes;                   // nodes per stack (per channel)
+  float scale;
+};
+
+GridDev make_grid(const pdg_grid_desc &d);
+pdg_status check_grid(const pdg_grid_desc *d);
+
+// Trilinear stencil of coordinate s on a level with R >= 2 cells per axis:
+// cell-centred values, border clamp to the hull of the centres.
+__device__ __forceinline__ void stencil1(int R, float s, int &i0, float &f, bool &inside) {
+  float u = (s + 1.0f) * (0.5f * (float)R) - 0.5f;
+  inside = (u >= 0.0f) && (u <= (float)(R - 1));
+  u = fminf(fmaxf(u, 0.0f), (float)(R - 1));
+  int i = (int)floorf(u);
+  i = i < R - 2 ? i : R - 2;
+  i0 = i;
+  f = u - (float)i;
+}
+
+inline unsigned div_up(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// ------------------------------------------------------------ radix sort --
+// Stable LSD radix sort of (key, value) pairs on uint32 keys, 8 bits a pass.
+// Scratch: two key/value buffers of n entries plus a histogram.
+size_t radix_sort_bytes(long long n);
+// Sorts keys/vals in place (the scratch is used as the alternate buffer).
+// bits: number of significant key bits (1..32).
+pdg_status radix_sort(uint32_t *keys, uint32_t *vals, long long n, int bits, void *scratch,
+                      hipStream_t stream);
+
+// ------------------------------------------------------------- launchers --
+// warp.hip
+pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, const float *x,
+                       long long xstride, long long ldx, float *out, long long ostride,
+                       long long ldo, long long n, int batch, hipStream_t st);
+// lam_out = gdir (nullable) + lam + J^T lam at positions x under `grids`.
+pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const float *x, long long ldx,
+                                const float *lam, long long ldl, const float *gdir, long long ldd,
+                                float *lam_out, long long ldo, long long n, hipStream_t st);
+// Entry keys for the deterministic grid scatter: for sample s of segment
+// seg and level l (entry e = (seg*L + l)*S + s) the key is the global node id
+// of its base cell, seg*nodes + noff[l] + cell.
+pdg_status launch_scatter_keys(const GridDev &g, const float *x, long long xstride, long long ldx,
+                               long long S, int segs, uint32_t *keys, uint32_t *vals,
+                               hipStream_t st);
+pdg_status launch_fill(float *p, long long count, float value, hipStream_t st);
+pdg_status launch_copy(float *dst, const float *src, long long count, hipStream_t st);
+// Upload up to 2 KB of host bytes to device memory in stream order (the bytes
+// travel as a kernel argument, so the call is safe under graph capture).
+pdg_status upload_small(void *dst, const void *src, size_t bytes, hipStream_t st);
+// One corner pass of the scatter over sorted entries: every run of equal
+// keys adds level_scale * sum_s w_delta(s) * lam(s) to node base + delta.
+pdg_status launch_scatter_pass(const GridDev &g, int delta, const uint32_t *keys,
+                               const uint32_t *vals, long long nent, long long S, const float *x,
+                               long long xstride, long long ldx, const float *lam,
+                               long long lstride, long long ldl, float *grad, hipStream_t st);
+
+// chamfer.hip
+struct ChSeg {               // one (moving A, fixed B) Chamfer pair
+  const float *a;            // SoA [3][n]
+  const float *b;            // SoA [3][m]
+  int n, m;
+  int *nn_a;                 // [n]
+  int *nn_b;                 // [m]
+  float *ga;                 // SoA [3][n] gradient wrt a (nullable)
+  unsigned a_base;           // global index of a_0 for the reverse scatter
+  int pad;
+};
+struct NNJob {               // one directed nearest-neighbour search
+  const float *q; const float *c;
+  int nq, nc;
+  int *nn;
+  int pad[2];
+};
+pdg_status launch_nn_exact(const NNJob *jobs, int njobs, int max_nq, hipStream_t st);
+constexpr int kLossBlocks = 32;  // fixed partial count per (segment, direction)
+// partials[(seg*2+dir)*kLossBlocks + blk]; then losses[seg*2+dir] = mean.
+pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double *partials,
+                               double *losses, hipStream_t st);
+// ga <- forward-direction gradient (overwrite), weights w[seg*2 + dir].
+pdg_status launch_chamfer_grad_fwd(const ChSeg *segs, int nseg, int max_n, float alpha,
+                                   const double *w, hipStream_t st);
+// Reverse-direction keys: for b_j of segment seg the key is a_base + nn_b[j],
+// value = global b index (seg base + j).  b_base[seg] = first global b index.
+pdg_status launch_chamfer_rev_keys(const ChSeg *segs, int nseg, int max_m,
+                                   const unsigned *b_base, uint32_t *keys, uint32_t *vals,
+                                   hipStream_t st);
+pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigned *b_base,
+                                      const unsigned *a_base_sorted, const uint32_t *keys,
+                                      const uint32_t *vals, long long nent, float alpha,
+                                      const double *w, hipStream_t st);
+
+// precond.hip
+struct CGSys {               // one (stack, level, channel) system
+  long long base;            // float offset of the system in the batch
+  int R;
+  int iters;
+  float lam;
+  int tile0;                 // first tile index of the system
+};
+size_t cg_bytes(long long floats, int nsys, int ntiles);
+pdg_status run_cg(const CGSys *sys_dev, int nsys, int ntiles, int kmax, float *g, long long floats,
+                  void *ws, hipStream_t st);
+
+// optim.hip
+struct AdamLevels {
+  int levels;
+  long long off[PDG_MAX_LEVELS + 1];
+  float lr[PDG_MAX_LEVELS];
+};
+pdg_status launch_adam(const AdamLevels &lv, long long stack, int batch, float b1, float b2,
+                       float eps, const int *step_dev, int step_host, float *theta, float *m,
+                       float *v, const float *g, hipStream_t st);
+pdg_status launch_set_int(int *p, int value, hipStream_t st);
+struct IsoArgs {
+  const float *xhat;   // [F][3][V]
+  const int *edges;    // [2][E]
+  int V, E, T;
+  float *sig;          // [T][E]   sign of the length change at frame t
+  float *u;            // [T][3][E] unit edge vector at frame t
+  double *partials;    // [kLossBlocks]
+  const int *inc_off;  // [V+1] incidence offsets
+  const uint32_t *inc; // [2E] sorted incidences: edge*2 + side
+  float *gx;           // [T][3][V] direct gradient (accumulated into)
+  double coef;         // w_iso / (T*E)
+};
+// Edge pass: signs, unit vectors and loss partials (before the assembly).
+pdg_status launch_iso_edges(const IsoArgs &a, hipStream_t st);
+// Vertex pass: adds the isometry gradient into gx (after the Chamfer gradient).
+pdg_status launch_iso_vertices(const IsoArgs &a, hipStream_t st);
+pdg_status launch_incidence(const int *edges, int E, int V, uint32_t *keys, uint32_t *vals,
+                            int *inc_off, void *sort_scratch, hipStream_t st);
+struct AssembleArgs {
+  const double *losses;      // [seg][2]: seg t = point term, seg T+t = template term
+  const double *iso_partials;
+  int T;
+  int E;
+  int has_tm;
+  const int *epoch;
+  int e_max;
+  float w_iso;
+  double *w;                 // out [seg][2] gradient weights
+  double *wconf;             // out [T]
+  double *terms;             // out [8]
+  double *user_terms;        // out [8] nullable
+};
+pdg_status launch_assemble(const AssembleArgs &a, hipStream_t st);
+
+}  // namespace pdg

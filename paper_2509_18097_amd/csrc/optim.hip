@@ -1,0 +1,226 @@
+// Adam (paper Sec. 3.6), the isometry loss (Eq. 18) with its adjoint, and
+// the loss assembly with confidence weights (Eq. 9, 14-17).
+#include "common.h"
+
+namespace pdg {
+namespace {
+
+__global__ __launch_bounds__(256) void adam_kernel(AdamLevels lv, long long stack, long long total,
+                                                   float b1, float b2, float eps,
+                                                   const int *__restrict__ step_dev, int step_host,
+                                                   float *__restrict__ th, float *__restrict__ m,
+                                                   float *__restrict__ v,
+                                                   const float *__restrict__ g) {
+  __shared__ float sbc[2];
+  if (threadIdx.x == 0) {
+    const int k = step_dev ? (*step_dev + 1) : step_host;
+    sbc[0] = (float)(1.0 - pow((double)b1, (double)k));
+    sbc[1] = (float)(1.0 - pow((double)b2, (double)k));
+  }
+  __syncthreads();
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long w = i % stack;
+  int l = 0;
+  while (l + 1 < lv.levels && w >= lv.off[l + 1]) ++l;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / sbc[0];
+  const float vh = vi / sbc[1];
+  th[i] = th[i] - lv.lr[l] * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void set_int_kernel(int *p, int v) { *p = v; }
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;
+}
+
+// Per (frame t = 1..T, edge e): sign of the length change and the unit edge
+// vector at t; float64 partial sums of |l_t - l_{t-1}|.
+__global__ __launch_bounds__(256) void iso_edge_kernel(IsoArgs a) {
+#pragma clang fp contract(off)
+  __shared__ double sh[4];
+  const long long total = (long long)a.T * a.E;
+  const long long V = a.V, E = a.E;
+  double acc = 0.0;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < total;
+       k += (long long)gridDim.x * 256) {
+    const int t = (int)(k / E) + 1;
+    const int e = (int)(k % E);
+    const int i = a.edges[e], j = a.edges[E + e];
+    const float *xc = a.xhat + (long long)t * 3 * V;
+    const float *xp = xc - 3 * V;
+    const double cx = (double)xc[i] - (double)xc[j];
+    const double cy = (double)xc[V + i] - (double)xc[V + j];
+    const double cz = (double)xc[2 * V + i] - (double)xc[2 * V + j];
+    const double px = (double)xp[i] - (double)xp[j];
+    const double py = (double)xp[V + i] - (double)xp[V + j];
+    const double pz = (double)xp[2 * V + i] - (double)xp[2 * V + j];
+    const double lc = sqrt((cx * cx + cy * cy) + cz * cz);
+    const double lp = sqrt((px * px + py * py) + pz * pz);
+    const double d = lc - lp;
+    acc += fabs(d);
+    const long long o = (long long)(t - 1) * E + e;
+    a.sig[o] = d > 0.0 ? 1.0f : (d < 0.0 ? -1.0f : 0.0f);
+    const double inv = lc > 0.0 ? 1.0 / lc : 0.0;
+    const long long ou = (long long)(t - 1) * 3 * E + e;
+    a.u[ou] = (float)(cx * inv);
+    a.u[ou + E] = (float)(cy * inv);
+    a.u[ou + 2 * E] = (float)(cz * inv);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) a.partials[blockIdx.x] = t;
+}
+
+// Per (frame t = 1..T, vertex v): gather over the incident edges (sorted by
+// edge id) coef * (sig_t - sig_{t+1}) * (+-u_t) and add to the direct
+// gradient of X_t.
+__global__ __launch_bounds__(256) void iso_vertex_kernel(IsoArgs a) {
+  const long long V = a.V, E = a.E;
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= (long long)a.T * V) return;
+  const int t = (int)(k / V) + 1;
+  const int v = (int)(k % V);
+  const float coef = (float)a.coef;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int q = a.inc_off[v]; q < a.inc_off[v + 1]; ++q) {
+    const uint32_t code = a.inc[q];
+    const int e = (int)(code >> 1);
+    const float side = (code & 1u) ? -1.0f : 1.0f;
+    float s = a.sig[(long long)(t - 1) * E + e];
+    if (t < a.T) s -= a.sig[(long long)t * E + e];
+    if (s == 0.0f) continue;
+    const long long ou = (long long)(t - 1) * 3 * E + e;
+    const float c = coef * s * side;
+    s0 += c * a.u[ou];
+    s1 += c * a.u[ou + E];
+    s2 += c * a.u[ou + 2 * E];
+  }
+  float *gx = a.gx + (long long)(t - 1) * 3 * V;
+  gx[v] += s0;
+  gx[V + v] += s1;
+  gx[2 * V + v] += s2;
+}
+
+__global__ void incidence_keys_kernel(const int *__restrict__ edges, int E, uint32_t *keys,
+                                      uint32_t *vals) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  keys[2 * e] = (uint32_t)edges[e];
+  vals[2 * e] = 2u * e;
+  keys[2 * e + 1] = (uint32_t)edges[E + e];
+  vals[2 * e + 1] = 2u * e + 1u;
+}
+
+__global__ void incidence_off_kernel(const uint32_t *__restrict__ keys, int n2, int V,
+                                     int *__restrict__ off) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > V) return;
+  int lo = 0, hi = n2;  // first position with key >= v
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (keys[mid] < (uint32_t)v) lo = mid + 1; else hi = mid;
+  }
+  off[v] = lo;
+}
+
+__global__ void assemble_kernel(AssembleArgs a) {
+  const int E = a.E;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int T = a.T;
+  double cd_max = -1.0, sum_pt = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const double c = a.losses[2 * t] + a.losses[2 * t + 1];
+    cd_max = c > cd_max ? c : cd_max;
+    sum_pt += c;
+    a.w[2 * t] = 1.0 / T;
+    a.w[2 * t + 1] = 1.0 / T;
+  }
+  const int e = *a.epoch;
+  const double delta = 1.0 - sqrt((double)e / (double)a.e_max);
+  double wc = 1.0, sum_tm = 0.0, l_iso = 0.0;
+  if (a.has_tm) {
+    for (int t = 0; t < T; ++t) {
+      const double c = a.losses[2 * (T + t)] + a.losses[2 * (T + t) + 1];
+      const double ex = c - cd_max > 0.0 ? c - cd_max : 0.0;
+      wc *= pow(1.0 / (1.0 + ex), delta);
+      a.wconf[t] = wc;
+      a.w[2 * (T + t)] = wc / T;
+      a.w[2 * (T + t) + 1] = wc / T;
+      sum_tm += wc * c;
+    }
+    if (E > 0) {
+      double s = 0.0;
+      for (int b = 0; b < kLossBlocks; ++b) s += a.iso_partials[b];
+      l_iso = (double)a.w_iso * s / ((double)T * (double)E);
+    }
+  } else {
+    for (int t = 0; t < T; ++t) a.wconf[t] = 1.0;
+  }
+  const double l_tr = (sum_tm + sum_pt) / T;
+  double terms[8] = {l_tr + l_iso, l_tr, l_iso, cd_max, sum_pt / T, sum_tm / T, wc, (double)e};
+  for (int i = 0; i < 8; ++i) {
+    a.terms[i] = terms[i];
+    if (a.user_terms) a.user_terms[i] = terms[i];
+  }
+}
+
+}  // namespace
+
+pdg_status launch_adam(const AdamLevels &lv, long long stack, int batch, float b1, float b2,
+                       float eps, const int *step_dev, int step_host, float *theta, float *m,
+                       float *v, const float *g, hipStream_t st) {
+  const long long total = stack * (long long)batch;
+  if (total <= 0) return PDG_OK;
+  adam_kernel<<<div_up(total, 256), 256, 0, st>>>(lv, stack, total, b1, b2, eps, step_dev,
+                                                  step_host, theta, m, v, g);
+  return launched("adam");
+}
+
+pdg_status launch_set_int(int *p, int value, hipStream_t st) {
+  set_int_kernel<<<1, 1, 0, st>>>(p, value);
+  return launched("set_int");
+}
+
+pdg_status launch_iso_edges(const IsoArgs &a, hipStream_t st) {
+  if (a.T <= 0 || a.E <= 0) return PDG_OK;
+  iso_edge_kernel<<<kLossBlocks, 256, 0, st>>>(a);
+  return launched("iso_edge");
+}
+
+pdg_status launch_iso_vertices(const IsoArgs &a, hipStream_t st) {
+  if (a.T <= 0 || a.E <= 0 || a.V <= 0) return PDG_OK;
+  iso_vertex_kernel<<<div_up((long long)a.T * a.V, 256), 256, 0, st>>>(a);
+  return launched("iso_vertex");
+}
+
+pdg_status launch_incidence(const int *edges, int E, int V, uint32_t *keys, uint32_t *vals,
+                            int *inc_off, void *sort_scratch, hipStream_t st) {
+  if (E > 0) {
+    incidence_keys_kernel<<<div_up(E, 256), 256, 0, st>>>(edges, E, keys, vals);
+    PDG_TRY(launched("incidence_keys"));
+    int bits = 1;
+    while ((1ll << bits) <= (long long)V) ++bits;
+    PDG_TRY(radix_sort(keys, vals, 2ll * E, bits, sort_scratch, st));
+  }
+  incidence_off_kernel<<<div_up(V + 1, 256), 256, 0, st>>>(keys, 2 * E, V, inc_off);
+  return launched("incidence_off");
+}
+
+pdg_status launch_assemble(const AssembleArgs &a, hipStream_t st) {
+  assemble_kernel<<<1, 64, 0, st>>>(a);
+  return launched("assemble");
+}
+
+}  // namespace pdg

@@ -1,0 +1,168 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs for gfx950.
+//
+// Used wherever the step needs a scatter-add to be deterministic: entries are
+// sorted by destination, then every run of equal keys is summed in entry
+// order by one thread (no floating-point atomics anywhere).
+//
+// Per 8-bit digit pass:
+//   hist    -- per 2048-entry tile, digit counts (LDS integer atomics: exact);
+//   scan    -- exclusive scan of the digit-major count table (one workgroup);
+//   scatter -- each tile ranks its entries stably (round-major, then wave,
+//              then lane order; lanes with equal digits are matched with eight
+//              wave64 ballots) and writes them to their final slots.
+#include "common.h"
+
+namespace pdg {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
+                                                              long long n, int shift,
+                                                              uint32_t *__restrict__ hist,
+                                                              int nblocks) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  long long base = (long long)blockIdx.x * kTile;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    long long i = base + r * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of `total` entries in place, one workgroup: every thread owns
+// a contiguous chunk; chunk sums are scanned in LDS.
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(uint32_t *__restrict__ a,
+                                                            long long total) {
+  __shared__ uint32_t sh[kScanThreads];
+  const int t = threadIdx.x;
+  long long chunk = (total + kScanThreads - 1) / kScanThreads;
+  long long lo = t * chunk;
+  long long hi = lo + chunk < total ? lo + chunk : total;
+  uint32_t s = 0;
+  for (long long i = lo; i < hi; ++i) s += a[i];
+  sh[t] = s;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    uint32_t v = t >= d ? sh[t - d] : 0u;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = sh[t] - s;  // exclusive prefix of this chunk
+  for (long long i = lo; i < hi; ++i) {
+    uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, long long n, int shift,
+    const uint32_t *__restrict__ hist, int nblocks) {
+  __shared__ uint32_t s_off[256];
+  __shared__ uint32_t s_cnt[kThreads / 64][256];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  s_off[tid] = hist[(long long)tid * nblocks + blockIdx.x];
+  long long base = (long long)blockIdx.x * kTile;
+  for (int r = 0; r < kItems; ++r) {
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s_cnt[w][tid] = 0;
+    long long i = base + r * kThreads + tid;
+    bool valid = i < n;
+    uint32_t k = valid ? kin[i] : 0u;
+    uint32_t d = (k >> shift) & 255u;
+    unsigned long long same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      unsigned long long m = __ballot((d >> b) & 1u);
+      same &= ((d >> b) & 1u) ? m : ~m;
+    }
+    int rank = __popcll(same & lt);
+    __syncthreads();
+    if (valid && rank == 0) s_cnt[wid][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_off[d] + (uint32_t)rank;
+      for (int w = 0; w < wid; ++w) pos += s_cnt[w][d];
+      kout[pos] = k;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) add += s_cnt[w][tid];
+    s_off[tid] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void copy_u32_kernel(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                                uint32_t *__restrict__ ao, uint32_t *__restrict__ bo,
+                                long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    ao[i] = a[i];
+    bo[i] = b[i];
+  }
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t radix_sort_bytes(long long n) {
+  long long nb = (n + kTile - 1) / kTile;
+  if (nb < 1) nb = 1;
+  return 2 * align256((size_t)n * 4) + align256((size_t)nb * 256 * 4);
+}
+
+pdg_status radix_sort(uint32_t *keys, uint32_t *vals, long long n, int bits, void *scratch,
+                      hipStream_t st) {
+  if (n <= 1) return PDG_OK;
+  if (n > (1ll << 31)) {
+    set_error("radix_sort: %lld entries exceed 2^31", n);
+    return PDG_EINVAL;
+  }
+  int passes = (bits + 7) / 8;
+  if (passes < 1) passes = 1;
+  if (passes > 4) passes = 4;
+  int nb = (int)((n + kTile - 1) / kTile);
+  char *s = (char *)scratch;
+  uint32_t *kalt = (uint32_t *)s;
+  uint32_t *valt = (uint32_t *)(s + align256((size_t)n * 4));
+  uint32_t *hist = (uint32_t *)(s + 2 * align256((size_t)n * 4));
+  uint32_t *ks = keys, *vs = vals, *kd = kalt, *vd = valt;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    radix_hist_kernel<<<nb, kThreads, 0, st>>>(ks, n, shift, hist, nb);
+    PDG_TRY(launched("radix_hist"));
+    scan_kernel<<<1, kScanThreads, 0, st>>>(hist, (long long)nb * 256);
+    PDG_TRY(launched("radix_scan"));
+    radix_scatter_kernel<<<nb, kThreads, 0, st>>>(ks, vs, kd, vd, n, shift, hist, nb);
+    PDG_TRY(launched("radix_scatter"));
+    uint32_t *t0 = ks, *t1 = vs;
+    ks = kd;
+    vs = vd;
+    kd = t0;
+    vd = t1;
+  }
+  if (ks != keys) {
+    copy_u32_kernel<<<div_up(n, 256), 256, 0, st>>>(ks, vs, keys, vals, n);
+    PDG_TRY(launched("radix_copy"));
+  }
+  return PDG_OK;
+}
+
+}  // namespace pdg

@@ -1,0 +1,168 @@
+"""One reconstruction request on the GPU: state, workspace and the step call.
+
+A ``Problem`` owns the device tensors of one request (input frames, template,
+grid parameters, Adam moments and the library workspace) and drives
+``pdg_step`` (include/pdg.h).  It follows the paper's problem statement
+(Sec. 3): a point-cloud sequence P_0..P_{F-1} with frame 0 as keyframe, an
+initial mesh X_0, and one multi-resolution grid stack per transition.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class HyperParams:
+    """Defaults are the paper's (Sec. 3.4 and 3.6)."""
+    alpha: float = 5.56
+    w_iso: float = 250.0
+    eta0: float = 5e-3
+    eta_growth: float = 1.1
+    lambda0: float = 0.25
+    lambda_growth: float = 1.5
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    e_max: int = 50
+
+    def to_c(self) -> L.Hyper:
+        h = L.Hyper()
+        for k in ("alpha", "w_iso", "eta0", "eta_growth", "lambda0", "lambda_growth", "beta1",
+                  "beta2", "eps"):
+            setattr(h, k, float(getattr(self, k)))
+        h.e_max = int(self.e_max)
+        return h
+
+
+class Problem:
+    """Device-resident state of one request and its optimisation step."""
+
+    def __init__(self, points: torch.Tensor, res, template: torch.Tensor | None = None,
+                 edges: torch.Tensor | None = None, hp: HyperParams | None = None,
+                 chamfer_mode: str = "fp32", precond: str = "cg", cg_iters: int = 0,
+                 cg_tol: float = 1e-7, level_scale: float | None = None,
+                 params: torch.Tensor | None = None):
+        self.hp = hp or HyperParams()
+        self.res = tuple(int(r) for r in res)
+        self.points = L._dev(points, torch.float32, "points")
+        if points.dim() != 3 or points.shape[1] != 3:
+            raise ValueError("points must be (F, 3, N)")
+        dev = points.device
+        self.frames, _, self.n = points.shape
+        self.T = self.frames - 1
+        self.P = L.grid_size(self.res)
+        if template is not None and template.shape[1] > 0:
+            self.template = L._dev(template, torch.float32, "template")
+            self.V = template.shape[1]
+            if edges is None:
+                edges = torch.zeros((2, 0), dtype=torch.int32, device=dev)
+            self.edges = L._dev(edges, torch.int32, "edges")
+            self.E = edges.shape[1]
+        else:
+            self.template, self.edges, self.V, self.E = None, None, 0, 0
+        if params is None:
+            params = torch.zeros((self.T, self.P), dtype=torch.float32, device=dev)
+        self.params = L._dev(params, torch.float32, "params")
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        d = L.ProblemDesc()
+        d.frames = self.frames
+        d.n = self.n
+        d.points = L._ptr(self.points)
+        d.verts = self.V
+        d.template_verts = L._ptr(self.template)
+        d.n_edges = self.E
+        d.edges = L._ptr(self.edges) if self.E > 0 else None
+        d.grid = L.grid_desc(self.res, level_scale)
+        d.hp = self.hp.to_c()
+        d.chamfer_mode = L.CHAMFER_MODES[chamfer_mode]
+        d.precond_method = L.PRECOND_METHODS[precond]
+        d.cg_iters = int(cg_iters)
+        d.cg_tol = float(cg_tol)
+        d.params = L._ptr(self.params)
+        d.adam_m = L._ptr(self.m)
+        d.adam_v = L._ptr(self.v)
+        nb = ctypes.c_size_t()
+        L.check(L.lib().pdg_problem_workspace(ctypes.byref(d), ctypes.byref(nb)),
+                "pdg_problem_workspace")
+        self.workspace = L._ws(nb.value, dev)
+        d.workspace = L._ptr(self.workspace)
+        d.workspace_bytes = nb.value
+        self._desc = d
+        h = ctypes.c_void_p()
+        L.check(L.lib().pdg_problem_create(ctypes.byref(d), L._stream(), ctypes.byref(h)),
+                "pdg_problem_create")
+        self._h = h
+
+    @property
+    def workspace_bytes(self) -> int:
+        return self.workspace.numel()
+
+    def state_bytes(self) -> int:
+        """Device bytes held by this request (state plus workspace)."""
+        tot = self.workspace.numel() + 3 * self.params.numel() * 4 + self.points.numel() * 4
+        if self.template is not None:
+            tot += self.template.numel() * 4 + self.edges.numel() * 4
+        return tot
+
+    def step(self, epoch: int, use_graph: bool = False, stream: torch.cuda.Stream | None = None):
+        st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+        L.check(L.lib().pdg_step(self._h, int(epoch), None, int(bool(use_graph)), st), "pdg_step")
+
+    def buffer(self, name: str) -> torch.Tensor:
+        """View of an intermediate buffer of the last step (see pdg_problem_buffer)."""
+        ptr = ctypes.c_void_p()
+        nb = ctypes.c_size_t()
+        L.check(L.lib().pdg_problem_buffer(self._h, L.BUFFERS[name], ctypes.byref(ptr),
+                                           ctypes.byref(nb)), "pdg_problem_buffer")
+        off = (ptr.value or self.workspace.data_ptr()) - self.workspace.data_ptr()
+        raw = self.workspace[off:off + nb.value]
+        T, N, V, P = self.T, self.n, self.V, self.P
+        if name in ("phat", "gphat"):
+            return raw.view(torch.float32).view(T, 3, N)
+        if name == "xhat":
+            return raw.view(torch.float32).view(T + 1, 3, V)
+        if name == "gxhat":
+            return raw.view(torch.float32).view(T, 3, V)
+        if name in ("grad", "pgrad"):
+            return raw.view(torch.float32).view(T, P)
+        if name == "nn":
+            return raw.view(torch.int32)
+        if name == "losses":
+            return raw.view(torch.float64).view(-1, 2)
+        if name in ("wconf", "terms"):
+            return raw.view(torch.float64)
+        raise KeyError(name)
+
+    def nn(self):
+        """Nearest-neighbour indices of the last step as a dict of (T, ...) tensors."""
+        raw = self.buffer("nn")
+        T, N, V = self.T, self.n, self.V
+        pt = raw[:T * 2 * N].view(T, 2 * N)
+        out = {"pt_ab": pt[:, :N], "pt_ba": pt[:, N:]}
+        if V > 0:
+            tm = raw[T * 2 * N:T * 2 * N + T * (V + N)].view(T, V + N)
+            out["tm_ab"] = tm[:, :V]
+            out["tm_ba"] = tm[:, V:]
+        return out
+
+    def terms(self) -> dict:
+        t = self.buffer("terms").cpu().tolist()
+        keys = ("loss", "l_transform", "l_iso", "cd_max", "pt_mean", "tm_mean", "wconf_T", "epoch")
+        return dict(zip(keys, t))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().pdg_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,65 @@
+"""GPU parity of pdg_precondition (CG) against the oracle's exact
+(I + lambda L)^-2 (Eq. 3), plus its invariants."""
+import numpy as np
+import pytest
+
+from oracle import precond as P
+from paper_2509_18097_amd import _lib as L
+from _gpu import assert_rel, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _lams(k):
+    return [0.25 * 1.5 ** l for l in range(k)]
+
+
+@pytest.mark.parametrize("res,batch", [((1, 2, 3, 5), 2), ((8, 16, 32), 1), ((16, 32, 64), 1),
+                                       ((9, 13), 3)])
+def test_cg_matches_exact(res, batch):
+    require_gpu()
+    rng = np.random.default_rng(sum(res) + batch)
+    g = rng.normal(size=batch * L.grid_size(res)).astype(np.float32)
+    print(f"precondition res={res} batch={batch}", flush=True)
+    out = host(L.precondition(dev(g), res, _lams(len(res)), batch=batch))
+    stack = L.grid_size(res)
+    ref = np.concatenate([P.apply_levels(g[b * stack:(b + 1) * stack], res, _lams(len(res)))
+                          for b in range(batch)])
+    off = 0
+    for r in res:
+        for b in range(batch):
+            sl = slice(b * stack + off, b * stack + off + 3 * r ** 3)
+            assert_rel(out[sl], ref[sl], 1e-5, f"R={r}")
+        off += 3 * r ** 3
+
+
+def test_cg_finest_level_128():
+    require_gpu()
+    res = (128,)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=L.grid_size(res)).astype(np.float32)
+    lam = [0.84375]
+    out = host(L.precondition(dev(g), res, lam))
+    ref = P.apply_levels(g, res, lam)
+    assert_rel(out, ref, 1e-5, "R=128")
+
+
+def test_invariants_on_gpu():
+    require_gpu()
+    res = (6, 12)
+    rng = np.random.default_rng(4)
+    g = rng.normal(size=L.grid_size(res)).astype(np.float32)
+    out = host(L.precondition(dev(g), res, [0.5, 1.0]))
+    off = 0
+    for r in res:
+        for c in range(3):
+            sl = slice(off + c * r ** 3, off + (c + 1) * r ** 3)
+            assert abs(out[sl].astype(np.float64).sum() - g[sl].astype(np.float64).sum()) <= \
+                1e-5 * np.abs(g[sl]).sum()
+        off += 3 * r ** 3
+    const = np.full(L.grid_size(res), 0.375, np.float32)
+    out = host(L.precondition(dev(const), res, [0.5, 1.0]))
+    assert np.max(np.abs(out - 0.375)) <= 1e-6
+    # lambda = 0 leaves the gradient untouched
+    out = host(L.precondition(dev(g), res, [0.0, 0.0]))
+    assert np.array_equal(out, g)

@@ -1,0 +1,143 @@
+"""GPU parity of one full optimisation step (pdg_step) against the oracle,
+stage by stage: each oracle stage is fed the GPU's float32 output of the
+previous stage, so nearest-neighbour decisions are compared on identical
+inputs (Sec. 3.1-3.6)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import sequence as S
+from paper_2509_18097_amd import _lib as L
+from paper_2509_18097_amd.problem import HyperParams, Problem
+from _gpu import assert_rel, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _theta0(T, res, seed, std=0.01):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, std, (T, L.grid_size(res))).astype(np.float32)
+
+
+def _check_positions(got, ref, src):
+    disp = np.max(np.abs(ref - src)) if ref.size else 0.0
+    tol = 1e-5 * disp + 8 * 2.0 ** -23 * np.abs(ref) + 1e-12
+    assert np.all(np.abs(got - ref) <= tol)
+
+
+def _stagewise(points, template, edges, res, theta0, epoch, e_max, mode="fp32"):
+    hp = HyperParams(e_max=e_max)
+    prob = Problem(dev(points), res, template=None if template is None else dev(template),
+                   edges=None if edges is None else dev(edges), hp=hp, chamfer_mode=mode,
+                   params=dev(theta0))
+    prob.step(epoch)
+    torch.cuda.synchronize()
+    phat = host(prob.buffer("phat"))
+    xhat = host(prob.buffer("xhat")) if template is not None else None
+    grad = host(prob.buffer("grad"))
+    pgrad = host(prob.buffer("pgrad"))
+    ohp = S.Hyper(e_max=e_max)
+    T = points.shape[0] - 1
+    z = np.zeros_like(theta0, dtype=np.float64)
+    r = S.step(points, template, edges, res, theta0, z, z, epoch, ohp, phat32=phat, xhat32=xhat,
+               grad_override=grad, pgrad_override=pgrad, workers=4)
+    # warps
+    _check_positions(phat, r.phat, points[:-1])
+    if template is not None:
+        # the oracle's chain restarts from the GPU's previous frame at every step
+        for t in range(1, T + 1):
+            from oracle import warp as W
+            ref = W.warp(theta0[t - 1], res, xhat[t - 1], 1.0 / len(res))
+            _check_positions(xhat[t], ref, xhat[t - 1])
+    # nearest neighbours, bit-exact on identical float32 inputs
+    nn = {k: host(v) for k, v in prob.nn().items()}
+    for k, v in r.nn.items():
+        assert np.array_equal(nn[k], v), k
+    # losses (float64)
+    losses = host(prob.buffer("losses"))
+    np.testing.assert_allclose(losses[:T], r.cd_pt, rtol=1e-10, atol=0)
+    if template is not None:
+        np.testing.assert_allclose(losses[T:2 * T], r.cd_tm, rtol=1e-10, atol=0)
+        np.testing.assert_allclose(host(prob.buffer("wconf")), r.w_conf, rtol=1e-12, atol=0)
+        assert_rel(host(prob.buffer("gxhat")), r.g_xhat, 1e-5, "dL/dX")
+    terms = prob.terms()
+    assert abs(terms["loss"] - r.loss) <= 1e-10 * abs(r.loss)
+    assert_rel(host(prob.buffer("gphat")), r.g_phat, 1e-5, "dL/dP^")
+    # grid gradient, preconditioned gradient, Adam
+    assert_rel(grad, r.grad, 1e-5, "dL/dG")
+    assert_rel(pgrad, r.pgrad, 1e-5, "preconditioned")
+    theta = host(prob.params)
+    eta_max = max(ohp.schedule(len(res))[0])
+    assert np.max(np.abs(theta - r.theta)) <= 1e-5 * eta_max
+    return prob, r
+
+
+def test_pair_step_c1_size():
+    """Single frame pair at its full size: 4,096 points, grids 8/16/32."""
+    require_gpu()
+    src, tgt = synth.pair_on_sphere(seed=0, n=4096)
+    res = (8, 16, 32)
+    _stagewise(np.stack([src, tgt]), None, None, res, _theta0(1, res, 1), epoch=0, e_max=50)
+
+
+def test_pair_step_ragged():
+    require_gpu()
+    src, tgt = synth.pair_on_sphere(seed=3, n=3001)
+    res = (1, 5, 12)
+    _stagewise(np.stack([src, tgt]), None, None, res, _theta0(1, res, 2), epoch=7, e_max=50)
+
+
+@pytest.mark.parametrize("epoch", [0, 3, 10])
+def test_sequence_step_with_template(epoch):
+    require_gpu()
+    seq = synth.deforming_sequence(seed=1, frames=5, n=1500, subdiv=2)
+    res = (4, 8, 16)
+    print(f"sequence step epoch={epoch}", flush=True)
+    _stagewise(seq.points, seq.template, seq.edges, res, _theta0(4, res, 3), epoch=epoch, e_max=10)
+
+
+def test_zero_grids_identical_frames_fixed_point():
+    require_gpu()
+    rng = np.random.default_rng(0)
+    p = rng.uniform(-0.8, 0.8, (3, 700)).astype(np.float32)
+    pts = np.stack([p, p, p])
+    _, _, e = synth.icosphere(1)
+    tmpl = p.copy()
+    edges = np.array([[0, 1, 2], [1, 2, 3]], np.int32)
+    res = (2, 4)
+    prob = Problem(dev(pts), res, template=dev(tmpl), edges=dev(edges))
+    prob.step(0)
+    assert prob.terms()["loss"] == 0.0
+    assert torch.count_nonzero(prob.buffer("grad")).item() == 0
+    assert torch.count_nonzero(prob.params).item() == 0
+    assert e.shape[0] == 2
+
+
+def test_graph_replay_equals_eager_and_is_deterministic():
+    require_gpu()
+    seq = synth.deforming_sequence(seed=2, frames=4, n=2000, subdiv=2)
+    res = (4, 8, 16)
+    th = _theta0(3, res, 5)
+    a = Problem(dev(seq.points), res, template=dev(seq.template), edges=dev(seq.edges),
+                params=dev(th))
+    b = Problem(dev(seq.points), res, template=dev(seq.template), edges=dev(seq.edges),
+                params=dev(th))
+    for e in range(4):
+        a.step(e, use_graph=False)
+        b.step(e, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a.params, b.params), e
+        assert torch.equal(a.buffer("terms"), b.buffer("terms")), e
+
+
+def test_pair_loss_decreases_over_iterations():
+    require_gpu()
+    src, tgt = synth.pair_on_sphere(seed=0, n=4096)
+    res = (8, 16, 32)
+    prob = Problem(dev(np.stack([src, tgt])), res, hp=HyperParams(e_max=50))
+    losses = []
+    for e in range(50):
+        prob.step(e, use_graph=True)
+        losses.append(prob.terms()["loss"])
+    assert losses[-1] < 0.5 * losses[0], losses[::10]

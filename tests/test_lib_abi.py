@@ -1,0 +1,103 @@
+"""The C-ABI library loads, exports every symbol include/pdg.h declares, and
+rejects invalid arguments on the host before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import conftest
+from paper_2509_18097_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pdg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_built():
+    assert conftest.BUILD_ERROR is None, conftest.BUILD_ERROR
+    assert os.path.exists(L.LIB_PATH)
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    decl = _declared()
+    assert len(decl) >= 15
+    h = ctypes.CDLL(L.LIB_PATH)
+    for name in decl:
+        assert hasattr(h, name), name
+        assert name in L.EXPORTS, name
+
+
+def test_version_and_grid_size():
+    lib = L.lib()
+    assert lib.pdg_version() >= 100
+    d = L.grid_desc((8, 16, 32))
+    assert lib.pdg_grid_size(ctypes.byref(d)) == 3 * (8 ** 3 + 16 ** 3 + 32 ** 3)
+    bad = L.grid_desc((8,))
+    bad.levels = 0
+    assert lib.pdg_grid_size(ctypes.byref(bad)) == -1
+
+
+def test_argument_errors_on_host():
+    lib = L.lib()
+    d = L.grid_desc((4, 8))
+    d.levels = 9
+    st = lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None)
+    assert st == L.EINVAL and "levels" in L.last_error()
+    d = L.grid_desc((4, 8))
+    d.channels = 6
+    assert lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None) == L.EUNSUPPORTED
+    d = L.grid_desc((4, 8))
+    assert lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None) == L.EINVAL
+    assert "NULL" in L.last_error()
+    assert lib.pdg_deform(ctypes.byref(d), None, None, 0, None, None) == L.OK  # empty is a no-op
+    nb = ctypes.c_size_t()
+    assert lib.pdg_chamfer_workspace(0, 5, 0, ctypes.byref(nb)) == L.EINVAL
+    assert lib.pdg_chamfer_workspace(5, 5, 7, ctypes.byref(nb)) == L.EINVAL
+    assert lib.pdg_chamfer_workspace(100, 50, 0, ctypes.byref(nb)) == L.OK and nb.value > 0
+    lam = (ctypes.c_float * 8)(-1.0, 1.0)
+    assert lib.pdg_precondition(ctypes.byref(d), lam, None, 1, 0, 0, 1e-7, None, 0, None) == L.EINVAL
+    lam = (ctypes.c_float * 8)(0.25, 0.375)
+    assert lib.pdg_precondition(ctypes.byref(d), lam, None, 1, 0, 0, 0.0, None, 0, None) == L.EINVAL
+    assert lib.pdg_precondition_workspace(ctypes.byref(d), 2, 0, ctypes.byref(nb)) == L.OK
+
+
+def test_problem_validation_on_host():
+    lib = L.lib()
+    pd = L.ProblemDesc()
+    pd.frames = 1
+    pd.n = 10
+    pd.grid = L.grid_desc((4, 8))
+    nb = ctypes.c_size_t()
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EINVAL
+    assert "frames" in L.last_error()
+    pd.frames = 3
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EINVAL  # NULL points
+    pd.points = 256
+    pd.params = 256
+    pd.adam_m = 256
+    pd.adam_v = 256
+    pd.hp.alpha, pd.hp.w_iso, pd.hp.eta0, pd.hp.eta_growth = 5.56, 250.0, 5e-3, 1.1
+    pd.hp.lambda0, pd.hp.lambda_growth, pd.hp.beta1, pd.hp.beta2 = 0.25, 1.5, 0.9, 0.999
+    pd.hp.eps, pd.hp.e_max = 1e-8, 50
+    pd.cg_tol = 1e-7
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.OK
+    assert nb.value > 0
+    pd.hp.beta1 = 1.0
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EINVAL
+    h = ctypes.c_void_p()
+    pd.hp.beta1 = 0.9
+    pd.workspace_bytes = 16
+    pd.workspace = 256
+    assert lib.pdg_problem_create(ctypes.byref(pd), None, ctypes.byref(h)) == L.ENOMEM
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", L.LIB_PATH + ".absent")
+    with pytest.raises(RuntimeError, match="no fallback"):
+        L.lib()
