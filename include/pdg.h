@@ -218,6 +218,23 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
  * first call for this stream. */
 pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t use_graph,
                     hipStream_t stream);
+/* One stage of pdg_step alone, in step order WARP, NN, LOSS, GRAD, SCATTER,
+ * PRECOND, ADAM (for profiling and stage-by-stage checks).  Each stage reads
+ * what the previous stages of the same or an earlier step left in the
+ * workspace; PRECOND rewrites the preconditioned gradient from the raw one and
+ * ADAM updates params/m/v, so replaying them alone changes the state exactly
+ * as the step would. */
+typedef enum {
+  PDG_STAGE_WARP = 0,     /* Eq. 1 and 8: P^_t and the template chain          */
+  PDG_STAGE_NN = 1,       /* Eq. 12: nearest neighbours of every Chamfer term   */
+  PDG_STAGE_LOSS = 2,     /* Eq. 9, 11, 13-18: losses and confidence weights    */
+  PDG_STAGE_GRAD = 3,     /* adjoints wrt the warped positions, reverse sweep   */
+  PDG_STAGE_SCATTER = 4,  /* transpose of Eq. 1 into the grid gradient          */
+  PDG_STAGE_PRECOND = 5,  /* Eq. 3                                              */
+  PDG_STAGE_ADAM = 6      /* Sec. 3.6                                           */
+} pdg_stage;
+pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream);
+
 /* Several problems' iterations in one call: each problem's step is enqueued
  * on its own stream from `streams` (count entries, [host]); the caller joins
  * them.  epochs: [host] int32[count]; loss_terms: [host] array of device

@@ -18,6 +18,7 @@ MAX_LEVELS = 8
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1}
 PRECOND_METHODS = {"cg": 0, "dct": 1}
+STAGES = ("warp", "nn", "loss", "grad", "scatter", "precond", "adam")
 BUFFERS = {"phat": 0, "xhat": 1, "nn": 2, "losses": 3, "wconf": 4, "grad": 5, "pgrad": 6,
            "gphat": 7, "gxhat": 8, "terms": 9}
 
@@ -76,6 +77,7 @@ _SIGS = {
     "pdg_problem_workspace": (_I32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(_SZ)]),
     "pdg_problem_create": (_I32, [ctypes.POINTER(ProblemDesc), _P, ctypes.POINTER(_P)]),
     "pdg_step": (_I32, [_P, _I32, _P, _I32, _P]),
+    "pdg_step_stage": (_I32, [_P, _I32, _P]),
     "pdg_step_batch": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_I32), ctypes.POINTER(_P),
                               _I32, ctypes.POINTER(_P)]),
     "pdg_problem_destroy": (_I32, [_P]),

@@ -400,82 +400,99 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol);
 }
 
-pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
-  const GridDev &g = p.g;
-  const long long T = p.T, N = p.N, V = p.V, P = p.P;
-  const pdg_hyper &h = p.d.hp;
-  // 1. warps (Eq. 1, Eq. 8)
-  PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T, st));
-  if (p.has_tm) {
-    PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
-    for (long long t = 0; t < T; ++t)
-      PDG_TRY(launch_warp(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0, V,
-                          p.xhat + (t + 1) * 3 * V, 0, V, V, 1, st));
-  }
-  // 2. nearest neighbours and Chamfer losses (Eq. 11-13)
-  PDG_TRY(launch_nn_exact(p.jobs, p.njobs, p.max_nq, st));
-  PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
+IsoArgs iso_args(pdg_problem &p) {
   IsoArgs ia;
   ia.xhat = p.xhat;
   ia.edges = p.d.edges;
-  ia.V = (int)V;
+  ia.V = (int)p.V;
   ia.E = (int)p.E;
-  ia.T = (int)T;
+  ia.T = p.T;
   ia.sig = p.sig;
   ia.u = p.u;
   ia.partials = p.iso_partials;
   ia.inc_off = p.inc_off;
   ia.inc = p.ivals;
   ia.gx = p.gxhat;
-  ia.coef = p.E > 0 ? (double)h.w_iso / ((double)T * (double)p.E) : 0.0;
-  // edge pass here (loss); the vertex pass adds its gradient after the
-  // Chamfer gradient has been written into gxhat
-  if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_edges(ia, st));
-  // 3. confidence weights and loss assembly (Eq. 9, 14-17)
-  AssembleArgs aa;
-  aa.losses = p.losses;
-  aa.iso_partials = p.iso_partials;
-  aa.T = (int)T;
-  aa.E = (int)p.E;
-  aa.has_tm = p.has_tm ? 1 : 0;
-  aa.epoch = p.epoch;
-  aa.e_max = h.e_max;
-  aa.w_iso = h.w_iso;
-  aa.w = p.w;
-  aa.wconf = p.wconf;
-  aa.terms = p.terms;
-  aa.user_terms = user_terms;
-  PDG_TRY(launch_assemble(aa, st));
-  // 4. gradient wrt warped positions: forward direction (overwrite), reverse
-  //    direction (sorted runs), isometry (vertex gather)
-  PDG_TRY(launch_chamfer_grad_fwd(p.segs, p.nseg, p.max_n, (float)h.alpha, p.w, st));
-  PDG_TRY(launch_chamfer_rev_keys(p.segs, p.nseg, p.max_m, p.b_base, p.rkeys, p.rvals, st));
-  PDG_TRY(radix_sort(p.rkeys, p.rvals, p.nrev,
-                     bits_for((unsigned long long)(T * N + T * V)), p.sort, st));
-  PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, nullptr, p.rkeys, p.rvals, p.nrev,
-                                     (float)h.alpha, p.w, st));
-  if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(ia, st));
-  // 5. reverse sweep of the template chain (adjoint of Eq. 8)
-  if (p.has_tm) {
-    PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
-    for (long long k = T - 1; k >= 1; --k)
-      PDG_TRY(launch_chain_adjoint(g, p.d.params + k * P, p.xhat + k * 3 * V, V,
-                                   p.lam + k * 3 * V, V, p.gxhat + (k - 1) * 3 * V, V,
-                                   p.lam + (k - 1) * 3 * V, V, V, st));
+  ia.coef = p.E > 0 ? (double)p.d.hp.w_iso / ((double)p.T * (double)p.E) : 0.0;
+  return ia;
+}
+
+// One stage of the step (the stages in order make one iteration).
+pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user_terms) {
+  const GridDev &g = p.g;
+  const long long T = p.T, N = p.N, V = p.V, P = p.P;
+  const pdg_hyper &h = p.d.hp;
+  switch (stage) {
+    case PDG_STAGE_WARP:  // P^_t = warp(G_t, P_{t-1}); X_t = warp(G_t, X_{t-1}) (Eq. 1, 8)
+      PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T,
+                          st));
+      if (p.has_tm) {
+        PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
+        for (long long t = 0; t < T; ++t)
+          PDG_TRY(launch_warp(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0, V,
+                              p.xhat + (t + 1) * 3 * V, 0, V, V, 1, st));
+      }
+      return PDG_OK;
+    case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
+      return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
+    case PDG_STAGE_LOSS: {  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
+      PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
+      if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_edges(iso_args(p), st));
+      AssembleArgs aa;
+      aa.losses = p.losses;
+      aa.iso_partials = p.iso_partials;
+      aa.T = (int)T;
+      aa.E = (int)p.E;
+      aa.has_tm = p.has_tm ? 1 : 0;
+      aa.epoch = p.epoch;
+      aa.e_max = h.e_max;
+      aa.w_iso = h.w_iso;
+      aa.w = p.w;
+      aa.wconf = p.wconf;
+      aa.terms = p.terms;
+      aa.user_terms = user_terms;
+      return launch_assemble(aa, st);
+    }
+    case PDG_STAGE_GRAD:  // dL/dP^, dL/dX (Chamfer adjoint, isometry), reverse sweep of Eq. 8
+      PDG_TRY(launch_chamfer_grad_fwd(p.segs, p.nseg, p.max_n, (float)h.alpha, p.w, st));
+      PDG_TRY(launch_chamfer_rev_keys(p.segs, p.nseg, p.max_m, p.b_base, p.rkeys, p.rvals, st));
+      PDG_TRY(radix_sort(p.rkeys, p.rvals, p.nrev,
+                         bits_for((unsigned long long)(T * N + T * V)), p.sort, st));
+      PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, nullptr, p.rkeys, p.rvals,
+                                         p.nrev, (float)h.alpha, p.w, st));
+      if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(iso_args(p), st));
+      if (p.has_tm) {
+        PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
+        for (long long k = T - 1; k >= 1; --k)
+          PDG_TRY(launch_chain_adjoint(g, p.d.params + k * P, p.xhat + k * 3 * V, V,
+                                       p.lam + k * 3 * V, V, p.gxhat + (k - 1) * 3 * V, V,
+                                       p.lam + (k - 1) * 3 * V, V, V, st));
+      }
+      return PDG_OK;
+    case PDG_STAGE_SCATTER:  // dL/dG: deterministic transpose of Eq. 1
+      PDG_TRY(launch_fill(p.grad, T * P, 0.f, st));
+      PDG_TRY(grid_scatter(g, p.d.points, 3 * N, N, N, (int)T, p.gphat, 3 * N, N, p.grad,
+                           p.pkeys, p.pvals, p.sort, true, st));
+      if (p.has_tm)
+        PDG_TRY(grid_scatter(g, p.xhat, 3 * V, V, V, (int)T, p.lam, 3 * V, V, p.grad, p.tkeys,
+                             p.tvals, p.sort, false, st));
+      return PDG_OK;
+    case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
+      PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
+      return run_cg(p.cgsys, (int)p.cg.sys.size(), p.cg.ntiles, p.cg.kmax, p.pgrad, T * P,
+                    p.cgws, st);
+    case PDG_STAGE_ADAM:  // Sec. 3.6
+      return launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
+                         p.d.adam_m, p.d.adam_v, p.pgrad, st);
+    default:
+      set_error("unknown stage %d", stage);
+      return PDG_EINVAL;
   }
-  // 6. deterministic scatter into the grids (transpose of Eq. 1)
-  PDG_TRY(launch_fill(p.grad, T * P, 0.f, st));
-  PDG_TRY(grid_scatter(g, p.d.points, 3 * N, N, N, (int)T, p.gphat, 3 * N, N, p.grad, p.pkeys,
-                       p.pvals, p.sort, true, st));
-  if (p.has_tm)
-    PDG_TRY(grid_scatter(g, p.xhat, 3 * V, V, V, (int)T, p.lam, 3 * V, V, p.grad, p.tkeys,
-                         p.tvals, p.sort, false, st));
-  // 7. preconditioner (Eq. 3) and Adam (Sec. 3.6)
-  PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
-  PDG_TRY(run_cg(p.cgsys, (int)p.cg.sys.size(), p.cg.ntiles, p.cg.kmax, p.pgrad, T * P, p.cgws,
-                 st));
-  PDG_TRY(launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
-                      p.d.adam_m, p.d.adam_v, p.pgrad, st));
+}
+
+pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
+  for (int s = PDG_STAGE_WARP; s <= PDG_STAGE_ADAM; ++s)
+    PDG_TRY(enqueue_stage(p, s, st, user_terms));
   return PDG_OK;
 }
 
@@ -868,6 +885,18 @@ pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t u
   }
   PDG_TRY_HIP(hipGraphLaunch(p->exec, stream));
   return PDG_OK;
+}
+
+pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream) {
+  if (!p) {
+    set_error("problem is NULL");
+    return PDG_EINVAL;
+  }
+  if (stage < PDG_STAGE_WARP || stage > PDG_STAGE_ADAM) {
+    set_error("unknown stage %d", stage);
+    return PDG_EINVAL;
+  }
+  return enqueue_stage(*p, stage, stream, nullptr);
 }
 
 pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *epochs,
