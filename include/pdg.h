@@ -22,7 +22,8 @@
  *   synchronisation.  pdg_last_error() returns a thread-local message for the
  *   most recent failing call.  No call allocates device memory except
  *   pdg_problem_create (a few KB of tables) -- scratch space comes from the
- *   caller through the `*_workspace` size queries.
+ *   caller through the `*_workspace` size queries; a workspace base must be
+ *   256-byte aligned (PDG_EINVAL otherwise).
  * - Calls on one stream are ordered; calls sharing a workspace must not
  *   overlap on different streams.
  */

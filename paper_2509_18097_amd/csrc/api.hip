@@ -99,6 +99,20 @@ int bits_for(unsigned long long maxkey) {
 
 bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
 
+// Workspaces are carved into 256-byte aligned buffers (float4 and double
+// accesses), so the base must be 256-byte aligned itself.
+pdg_status need_ws(const void *ws, size_t have, size_t want) {
+  if (!ws || have < want) {
+    set_error("workspace of %zu bytes < %zu needed", have, want);
+    return PDG_ENOMEM;
+  }
+  if (((uintptr_t)ws & 255) != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return PDG_EINVAL;
+  }
+  return PDG_OK;
+}
+
 pdg_status need(const void *p, const char *name) {
   if (!p) {
     set_error("%s is NULL", name);
@@ -133,10 +147,10 @@ pdg_status grid_scatter(const GridDev &g, const float *x, long long xstride, lon
   const long long nent = (long long)segs * g.levels * S;
   if (!keys_ready) {
     PDG_TRY(launch_scatter_keys(g, x, xstride, ldx, S, segs, keys, vals, st));
-    PDG_TRY(radix_sort(keys, vals, nent, bits_for((unsigned long long)segs * g.nodes), sort, st));
+    PDG_TRY(radix_sort(keys, vals, nent, 32, sort, st));
   }
-  for (int delta = 0; delta < 8; ++delta)
-    PDG_TRY(launch_scatter_pass(g, delta, keys, vals, nent, S, x, xstride, ldx, lam, lstride, ldl,
+  for (int cls = 0; cls < 8; ++cls)
+    PDG_TRY(launch_scatter_pass(g, cls, keys, vals, nent, S, x, xstride, ldx, lam, lstride, ldl,
                                 grad, st));
   return PDG_OK;
 }
@@ -164,12 +178,6 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m) {
 }
 
 // ---------------------------------------------------------- precondition --
-struct CGPlan {
-  std::vector<CGSys> sys;
-  int ntiles = 0;
-  int kmax = 0;
-};
-
 int cg_count(float lam, double tol) {
   const double kappa = 1.0 + 12.0 * (double)lam;
   const double sq = sqrt(kappa);
@@ -179,26 +187,15 @@ int cg_count(float lam, double tol) {
   return k < 1.0 ? 1 : (int)k;
 }
 
-CGPlan cg_plan(const GridDev &g, int batch, const float *lam, int iters, double tol) {
-  CGPlan p;
-  for (int b = 0; b < batch; ++b)
-    for (int l = 0; l < g.levels; ++l) {
-      const long long r3 = (long long)g.res[l] * g.res[l] * g.res[l];
-      // lam = 0: A = I, one CG iteration reproduces the input exactly
-      const int k = lam[l] == 0.0f ? 1 : (iters > 0 ? iters : cg_count(lam[l], tol));
-      for (int c = 0; c < 3; ++c) {
-        CGSys s;
-        s.base = (long long)b * g.size + g.off[l] + c * r3;
-        s.R = g.res[l];
-        s.iters = k;
-        s.lam = lam[l];
-        s.tile0 = p.ntiles;
-        p.ntiles += (int)((r3 + 1023) / 1024);
-        if (k > p.kmax) p.kmax = k;
-        p.sys.push_back(s);
-      }
-    }
-  return p;
+// Per-level iteration counts: iters > 0 fixes them; otherwise the a-priori
+// count for the A-norm tolerance from kappa <= 1 + 12 lambda.  lambda = 0
+// gives A = I, where one iteration reproduces the input exactly.
+CGPlanDev cg_plan(const GridDev &g, int batch, const float *lam, int iters, double tol,
+                  bool aligned16) {
+  int it[PDG_MAX_LEVELS];
+  for (int l = 0; l < g.levels; ++l)
+    it[l] = lam[l] == 0.0f ? 1 : (iters > 0 ? iters : cg_count(lam[l], tol));
+  return cg_make_plan(g, batch, lam, it, aligned16);
 }
 
 pdg_status check_precond_args(const pdg_grid_desc *d, const float *lambda, int32_t batch,
@@ -232,8 +229,8 @@ pdg_status check_precond_args(const pdg_grid_desc *d, const float *lambda, int32
   return PDG_OK;
 }
 
-size_t cg_ws_bytes(const CGPlan &p, long long floats) {
-  return a256(p.sys.size() * sizeof(CGSys)) + cg_bytes(floats, (int)p.sys.size(), p.ntiles);
+size_t cg_ws_bytes(const CGPlanDev &p, long long floats) {
+  return cg_bytes(floats, p.nsys, p.ntiles);
 }
 
 }  // namespace
@@ -260,11 +257,10 @@ struct pdg_problem {
   NNJob *jobs = nullptr;
   ChSeg *segs = nullptr;
   unsigned *b_base = nullptr;
-  CGSys *cgsys = nullptr;
   void *cgws = nullptr;
   int njobs = 0, nseg = 0, max_nq = 0, max_n = 0, max_m = 0;
   long long nrev = 0;
-  CGPlan cg;
+  CGPlanDev cg;
   AdamLevels adam;
   size_t ws_used = 0;
   // graph replay
@@ -320,8 +316,9 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   PDG_TRY(check_precond_args(&pd->grid, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
   const GridDev g = make_grid(pd->grid);
   const long long T = pd->frames - 1;
-  if ((unsigned long long)T * g.nodes >= (1ull << 32)) {
-    set_error("T * nodes = %lld does not fit the 32-bit scatter keys", T * g.nodes);
+  if ((unsigned long long)T * g.nodes >= (1ull << kScatterClassShift)) {
+    set_error("T * nodes = %lld does not fit the 29-bit node field of the scatter keys",
+              T * g.nodes);
     return PDG_EINVAL;
   }
   if ((unsigned long long)T * g.levels * (pd->n > pd->verts ? pd->n : pd->verts) >= (1ull << 31)) {
@@ -375,8 +372,7 @@ void layout(pdg_problem &p, Carve &c) {
   p.jobs = c.take<NNJob>(p.njobs);
   p.segs = c.take<ChSeg>(p.nseg);
   p.b_base = c.take<unsigned>(p.nseg);
-  p.cgsys = c.take<CGSys>((long long)p.cg.sys.size());
-  p.cgws = c.take<char>((long long)cg_bytes(T * P, (int)p.cg.sys.size(), p.cg.ntiles));
+  p.cgws = c.take<char>((long long)cg_bytes(T * P, p.cg.nsys, p.cg.ntiles));
 }
 
 void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
@@ -397,7 +393,8 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
     p.adam.off[l] = p.g.off[l];
   }
   p.adam.off[p.g.levels] = p.g.size;
-  p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol);
+  // every buffer the solver touches is carved at 256-byte alignment
+  p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol, true);
 }
 
 IsoArgs iso_args(pdg_problem &p) {
@@ -479,8 +476,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       return PDG_OK;
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
       PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
-      return run_cg(p.cgsys, (int)p.cg.sys.size(), p.cg.ntiles, p.cg.kmax, p.pgrad, T * P,
-                    p.cgws, st);
+      return run_cg(p.cg, p.pgrad, T * P, p.cgws, st);
     case PDG_STAGE_ADAM:  // Sec. 3.6
       return launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
                          p.d.adam_m, p.d.adam_v, p.pgrad, st);
@@ -546,7 +542,8 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
     return PDG_EINVAL;
   }
   const GridDev g = make_grid(*d);
-  if ((long long)d->levels * n >= (1ll << 31) || (unsigned long long)g.nodes >= (1ull << 32)) {
+  if ((long long)d->levels * n >= (1ll << 31) ||
+      (unsigned long long)g.nodes >= (1ull << kScatterClassShift)) {
     set_error("problem too large for 32-bit scatter entries");
     return PDG_EINVAL;
   }
@@ -559,10 +556,7 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
   if (ggrids) {
     Carve probe(nullptr);
     deform_bwd_layout(probe, d->levels, n);
-    if (!ws || ws_bytes < probe.off) {
-      set_error("workspace of %zu bytes < %zu needed", ws_bytes, probe.off);
-      return PDG_ENOMEM;
-    }
+    PDG_TRY(need_ws(ws, ws_bytes, probe.off));
     Carve c(ws);
     DeformBwdWs w = deform_bwd_layout(c, d->levels, n);
     PDG_TRY(launch_fill(ggrids, g.size, 0.f, stream));
@@ -609,10 +603,7 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
   PDG_TRY(need(nn_a, "nn_a"));
   PDG_TRY(need(nn_b, "nn_b"));
   if (ga) PDG_TRY(need(ga, "ga"));
-  if (!ws || ws_bytes < need_bytes) {
-    set_error("workspace of %zu bytes < %zu needed", ws_bytes, need_bytes);
-    return PDG_ENOMEM;
-  }
+  PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
   Carve c(ws);
   ChamferWs w = chamfer_layout(c, n, m);
   NNJob jobs[2];
@@ -670,7 +661,7 @@ pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int
   const GridDev g = make_grid(*d);
   float lam[PDG_MAX_LEVELS];
   for (int l = 0; l < d->levels; ++l) lam[l] = 1.0f;
-  CGPlan p = cg_plan(g, batch, lam, 1, 0.5);
+  CGPlanDev p = cg_plan(g, batch, lam, 1, 0.5, false);
   *bytes = cg_ws_bytes(p, g.size * batch);
   return PDG_OK;
 }
@@ -683,20 +674,11 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
   PDG_TRY(need(g, "g"));
   size_t nb = 0;
   PDG_TRY(pdg_precondition_workspace(d, batch, method, &nb));
-  if (!ws || ws_bytes < nb) {
-    set_error("workspace of %zu bytes < %zu needed", ws_bytes, nb);
-    return PDG_ENOMEM;
-  }
+  PDG_TRY(need_ws(ws, ws_bytes, nb));
   const GridDev gd = make_grid(*d);
-  CGPlan p = cg_plan(gd, batch, lambda, iters, tol);
-  const size_t tbytes = p.sys.size() * sizeof(CGSys);
-  char *w = (char *)ws;
-  for (size_t off = 0; off < tbytes; off += 2048) {
-    const size_t chunk = tbytes - off < 2048 ? tbytes - off : 2048;
-    PDG_TRY(upload_small(w + off, (const char *)p.sys.data() + off, chunk, stream));
-  }
-  return run_cg((const CGSys *)w, (int)p.sys.size(), p.ntiles, p.kmax, g, gd.size * batch,
-                w + ((tbytes + 255) & ~(size_t)255), stream);
+  const bool aligned16 = ((uintptr_t)g & 15) == 0;
+  CGPlanDev p = cg_plan(gd, batch, lambda, iters, tol, aligned16);
+  return run_cg(p, g, gd.size * batch, ws, stream);
 }
 
 pdg_status pdg_adam(const pdg_grid_desc *d, int32_t batch, const float *lr, float beta1,
@@ -752,10 +734,12 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   init_problem(*p, *pd);
   Carve probe(nullptr);
   layout(*p, probe);
-  if (!pd->workspace || pd->workspace_bytes < probe.off) {
-    set_error("workspace of %zu bytes < %zu needed", pd->workspace_bytes, probe.off);
-    delete p;
-    return PDG_ENOMEM;
+  {
+    pdg_status s = need_ws(pd->workspace, pd->workspace_bytes, probe.off);
+    if (s != PDG_OK) {
+      delete p;
+      return s;
+    }
   }
   Carve c(pd->workspace);
   layout(*p, c);
@@ -829,8 +813,6 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   if (e == hipSuccess) e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(ChSeg), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->jobs, jobs.data(), jobs.size() * sizeof(NNJob), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->b_base, bb.data(), bb.size() * sizeof(unsigned), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !p->cg.sys.empty())
-    e = hipMemcpy(p->cgsys, p->cg.sys.data(), p->cg.sys.size() * sizeof(CGSys), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     pdg_status s = hip_fail(e, "pdg_problem_create table upload");
     delete p;
@@ -839,8 +821,7 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   // static scatter entries of the input points (fixed positions)
   pdg_status s = launch_scatter_keys(p->g, pd->points, 3 * N, N, N, (int)T, p->pkeys, p->pvals, stream);
   if (s == PDG_OK)
-    s = radix_sort(p->pkeys, p->pvals, T * p->g.levels * N,
-                   bits_for((unsigned long long)T * p->g.nodes), p->sort, stream);
+    s = radix_sort(p->pkeys, p->pvals, T * p->g.levels * N, 32, p->sort, stream);
   if (s == PDG_OK && p->has_tm)
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);

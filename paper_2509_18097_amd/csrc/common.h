@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <string.h>
 
 #include "pdg.h"
 
@@ -82,8 +83,10 @@ pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const floa
                                 const float *lam, long long ldl, const float *gdir, long long ldd,
                                 float *lam_out, long long ldo, long long n, hipStream_t st);
 // Entry keys for the deterministic grid scatter: for sample s of segment
-// seg and level l (entry e = (seg*L + l)*S + s) the key is the global node id
-// of its base cell, seg*nodes + noff[l] + cell.
+// seg and level l (entry e = (seg*L + l)*S + s) the key is the parity class of
+// its base cell (bits 29..31) above the global node id of the base cell,
+// seg*nodes + noff[l] + cell (which must stay below 2^29).
+constexpr int kScatterClassShift = 29;
 pdg_status launch_scatter_keys(const GridDev &g, const float *x, long long xstride, long long ldx,
                                long long S, int segs, uint32_t *keys, uint32_t *vals,
                                hipStream_t st);
@@ -92,9 +95,10 @@ pdg_status launch_copy(float *dst, const float *src, long long count, hipStream_
 // Upload up to 2 KB of host bytes to device memory in stream order (the bytes
 // travel as a kernel argument, so the call is safe under graph capture).
 pdg_status upload_small(void *dst, const void *src, size_t bytes, hipStream_t st);
-// One corner pass of the scatter over sorted entries: every run of equal
-// keys adds level_scale * sum_s w_delta(s) * lam(s) to node base + delta.
-pdg_status launch_scatter_pass(const GridDev &g, int delta, const uint32_t *keys,
+// One parity-class pass of the scatter over sorted entries: every run of
+// equal keys of class `cls` adds level_scale * sum_s w_k(s) * lam(s) to its
+// 8 corner nodes k.
+pdg_status launch_scatter_pass(const GridDev &g, int cls, const uint32_t *keys,
                                const uint32_t *vals, long long nent, long long S, const float *x,
                                long long xstride, long long ldx, const float *lam,
                                long long lstride, long long ldl, float *grad, hipStream_t st);
@@ -135,16 +139,28 @@ pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigne
                                       const double *w, hipStream_t st);
 
 // precond.hip
-struct CGSys {               // one (stack, level, channel) system
-  long long base;            // float offset of the system in the batch
+struct CGLevel {             // one level of every stack in a preconditioner call
   int R;
-  int iters;
+  int shift;                 // log2(R), or -1 when R is not a power of two
+  int iters;                 // CG iterations per solve
   float lam;
-  int tile0;                 // first tile index of the system
+  long long off;             // float offset of the level in a stack
+  int tile0;                 // first tile (level-major numbering)
+  int tps;                   // tiles per system
+  int sys0;                  // first system (level-major: level, stack, channel)
+  int vec;                   // float4 path usable (R % 4 == 0, aligned)
 };
+struct CGPlanDev {
+  int levels;
+  int batch;
+  long long stack;           // floats per stack
+  int ntiles, nsys;
+  CGLevel lv[PDG_MAX_LEVELS];
+};
+CGPlanDev cg_make_plan(const GridDev &g, int batch, const float *lam, const int *iters,
+                       bool aligned16);
 size_t cg_bytes(long long floats, int nsys, int ntiles);
-pdg_status run_cg(const CGSys *sys_dev, int nsys, int ntiles, int kmax, float *g, long long floats,
-                  void *ws, hipStream_t st);
+pdg_status run_cg(const CGPlanDev &plan, float *g, long long floats, void *ws, hipStream_t st);
 
 // optim.hip
 struct AdamLevels {

@@ -3,15 +3,21 @@
 // Laplacian of the R^3 cell box with free boundary.
 //
 // Two conjugate-gradient solves per system, matrix-free, float32 vectors and
-// float64 inner products, with a fixed per-system iteration count (so the
-// whole solve is stream-ordered with no host synchronisation).  All systems
-// of all levels and stacks run in the same launches: a launch covers the
-// concatenated tiles of every system; each workgroup finds its system by a
-// binary search over the systems' first-tile table.
+// float64 inner products, with a fixed per-level iteration count (so the whole
+// solve is stream-ordered with no host synchronisation).
+//
+// Work decomposition: systems are numbered level-major (level, stack,
+// channel); a tile is 2048 consecutive cells of one system (whole x-rows for
+// R >= 64).  Each launch covers the tiles of the levels still iterating, with
+// the workgroup -> tile map made XCD-aware (consecutive workgroups land on
+// different XCDs, so each XCD gets a contiguous run of tiles and the z-planes
+// its stencil touches stay in its L2).  A thread owns float4 quads along x;
+// x-neighbours come from the quad itself plus two scalar loads, y/z
+// neighbours are float4 loads served mostly from cache.
 //
 // Per iteration (p' = r + beta p, ping-pong buffers for p):
-//   kernel A: p' from r and p, pq = <p', A p'> (A p' recomputed from p'
-//             at the seven stencil points), writes p';
+//   kernel A: p' from r and p, pq = <p', A p'> (A p' at the seven stencil
+//             points from r and p), writes p';
 //   reduce  : alpha = rr / pq;
 //   kernel B: x += alpha p', r -= alpha A p' (stencil on p'), rr' = <r, r>;
 //   reduce  : beta = rr' / rr.
@@ -23,8 +29,8 @@ namespace pdg {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kCells = 4;                 // consecutive x cells per thread
-constexpr int kTileCells = kThreads * kCells;
+constexpr int kQuads = 2;                            // float4 quads per thread
+constexpr int kTileCells = kThreads * 4 * kQuads;    // 2048
 
 struct CGState {
   float *x, *r, *p0, *p1;
@@ -32,21 +38,35 @@ struct CGState {
   double *rr, *alpha, *beta;   // [nsys]
 };
 
-__device__ __forceinline__ int find_sys(const CGSys *__restrict__ sys, int nsys, int tile) {
-  int lo = 0, hi = nsys - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (sys[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+struct Loc {                   // a workgroup's tile
+  int l;                       // level
+  int sys;                     // global system index
+  int lt;                      // tile within the system
+  long long base;              // float offset of the system
+};
+
+__device__ __forceinline__ bool locate(const CGPlanDev &P, int tile, Loc &o) {
+  for (int l = 0; l < P.levels; ++l) {
+    const CGLevel &L = P.lv[l];
+    const int nt = P.batch * 3 * L.tps;
+    if (tile >= L.tile0 && tile < L.tile0 + nt) {
+      const int local = tile - L.tile0;
+      const int s = local / L.tps;
+      o.l = l;
+      o.sys = L.sys0 + s;
+      o.lt = local - s * L.tps;
+      const long long r3 = (long long)L.R * L.R * L.R;
+      o.base = (long long)(s / 3) * P.stack + L.off + (long long)(s % 3) * r3;
+      return true;
+    }
   }
-  return lo;
+  return false;
 }
 
-// XCD-aware tile order: consecutive workgroup ids go to different XCDs, so
-// give each XCD a contiguous range of tiles (neighbouring z-planes stay in
-// the same L2).
-__device__ __forceinline__ int tile_of_block(int ntiles) {
-  const int per = (ntiles + 7) >> 3;
-  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+// workgroup -> tile inside [lo, lo + n): each XCD gets a contiguous range
+__device__ __forceinline__ int tile_of_block(int lo, int n) {
+  const int per = (n + 7) >> 3;
+  return lo + (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
 }
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -60,142 +80,211 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return t;
 }
 
-// (A v)(c) = v(c) + lam * sum_{nbr} (v(c) - v(nbr)) over in-box neighbours,
-// with v given by a functor.
-template <class F>
-__device__ __forceinline__ float apply_A(const F &v, float vc, int x, int y, int z, int R, int c,
-                                         float lam) {
-  const int R2 = R * R;
-  float s = 0.f;
-  if (x > 0) s += vc - v(c - 1);
-  if (x < R - 1) s += vc - v(c + 1);
-  if (y > 0) s += vc - v(c - R);
-  if (y < R - 1) s += vc - v(c + R);
-  if (z > 0) s += vc - v(c - R2);
-  if (z < R - 1) s += vc - v(c + R2);
-  return vc + lam * s;
+__device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+__device__ __forceinline__ float4 axpy4(float4 a, float b, float4 c) {
+  return make_float4(a.x + b * c.x, a.y + b * c.y, a.z + b * c.z, a.w + b * c.w);
 }
 
-__global__ __launch_bounds__(kThreads) void cg_init_kernel(const CGSys *__restrict__ sys, int nsys,
-                                                           int ntiles, const float *__restrict__ src,
+// Laplacian part sum_nbr (v - v_nbr) of a quad c given its neighbours; a
+// missing neighbour is passed as the cell itself (difference 0).
+__device__ __forceinline__ float4 lap4(float4 c, float xl, float xr, float4 ym, float4 yp,
+                                       float4 zm, float4 zp) {
+  float4 s;
+  s.x = (c.x - xl) + (c.x - c.y) + (c.x - ym.x) + (c.x - yp.x) + (c.x - zm.x) + (c.x - zp.x);
+  s.y = (c.y - c.x) + (c.y - c.z) + (c.y - ym.y) + (c.y - yp.y) + (c.y - zm.y) + (c.y - zp.y);
+  s.z = (c.z - c.y) + (c.z - c.w) + (c.z - ym.z) + (c.z - yp.z) + (c.z - zm.z) + (c.z - zp.z);
+  s.w = (c.w - c.z) + (c.w - xr) + (c.w - ym.w) + (c.w - yp.w) + (c.w - zm.w) + (c.w - zp.w);
+  return s;
+}
+
+__device__ __forceinline__ double dot4(float4 a, float4 b) {
+  return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
+}
+
+// generic cell coordinates (any R)
+__device__ __forceinline__ void coords(const CGLevel &L, int c, int &x, int &y, int &z) {
+  if (L.shift >= 0) {
+    x = c & (L.R - 1);
+    y = (c >> L.shift) & (L.R - 1);
+    z = c >> (2 * L.shift);
+  } else {
+    x = c % L.R;
+    y = (c / L.R) % L.R;
+    z = c / (L.R * L.R);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void cg_init_kernel(CGPlanDev P, int ntiles,
+                                                           const float *__restrict__ src,
                                                            float *__restrict__ r,
                                                            float *__restrict__ x,
                                                            double *__restrict__ rr_part) {
   __shared__ double sh[kThreads / 64];
-  const int tile = tile_of_block(ntiles);
-  if (tile >= ntiles) return;
-  const CGSys S = sys[find_sys(sys, nsys, tile)];
-  const long long n = (long long)S.R * S.R * S.R;
-  const long long c0 = (long long)(tile - S.tile0) * kTileCells + threadIdx.x * kCells;
+  const int tile = tile_of_block(0, ntiles);
+  Loc o;
+  if (tile >= ntiles || !locate(P, tile, o)) return;
+  const CGLevel &L = P.lv[o.l];
+  const int n = L.R * L.R * L.R;
   double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < kCells; ++k) {
-    const long long c = c0 + k;
+  for (int k = 0; k < 4 * kQuads; ++k) {
+    const int c = o.lt * kTileCells + k * kThreads + threadIdx.x;
     if (c < n) {
-      const float v = src[S.base + c];
-      r[S.base + c] = v;
-      x[S.base + c] = 0.f;
-      acc += (double)v * (double)v;
+      const float v = src[o.base + c];
+      r[o.base + c] = v;
+      x[o.base + c] = 0.f;
+      acc += (double)v * v;
     }
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) rr_part[tile] = t;
 }
 
-__global__ __launch_bounds__(kThreads) void cg_a_kernel(const CGSys *__restrict__ sys, int nsys,
-                                                        int ntiles, int k, CGState s,
-                                                        const float *__restrict__ pin,
+__global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
+                                                        CGState s, const float *__restrict__ pin,
                                                         float *__restrict__ pout) {
   __shared__ double sh[kThreads / 64];
-  const int tile = tile_of_block(ntiles);
-  if (tile >= ntiles) return;
-  const int si = find_sys(sys, nsys, tile);
-  const CGSys S = sys[si];
-  if (k >= S.iters) return;
-  const int R = S.R;
+  const int tile = tile_of_block(tile_lo, nlaunch);
+  Loc o;
+  if (tile >= tile_lo + nlaunch || !locate(P, tile, o)) return;
+  const CGLevel &L = P.lv[o.l];
+  if (k >= L.iters) return;
+  const int R = L.R;
   const int n = R * R * R;
-  const float beta = k == 0 ? 0.f : (float)s.beta[si];
-  const float *rr = s.r + S.base;
-  const float *pp = pin + S.base;
-  auto pn = [&](int c) { return k == 0 ? rr[c] : rr[c] + beta * pp[c]; };
-  const int c0 = (tile - S.tile0) * kTileCells + threadIdx.x * kCells;
+  const float beta = k == 0 ? 0.f : (float)s.beta[o.sys];
+  const float lam = L.lam;
+  const float *rr = s.r + o.base;
+  const float *pp = pin + o.base;
+  float *po = pout + o.base;
   double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < kCells; ++q) {
-    const int c = c0 + q;
-    if (c < n) {
-      const int x = c % R, y = (c / R) % R, z = c / (R * R);
-      const float vc = pn(c);
-      const float av = apply_A(pn, vc, x, y, z, R, c, S.lam);
-      pout[S.base + c] = vc;
-      acc += (double)vc * (double)av;
+  if (L.vec) {
+    const int RR = R * R;
+    for (int u = 0; u < kQuads; ++u) {
+      const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
+      if (q >= n) continue;
+      int x0, y, z;
+      coords(L, q, x0, y, z);
+      auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
+      auto pn4 = [&](int i) { return k == 0 ? ld4(rr + i) : axpy4(ld4(rr + i), beta, ld4(pp + i)); };
+      const float4 c = pn4(q);
+      const float xl = x0 > 0 ? pn(q - 1) : c.x;
+      const float xr = x0 + 4 < R ? pn(q + 4) : c.w;
+      const float4 ym = y > 0 ? pn4(q - R) : c;
+      const float4 yp = y < R - 1 ? pn4(q + R) : c;
+      const float4 zm = z > 0 ? pn4(q - RR) : c;
+      const float4 zp = z < R - 1 ? pn4(q + RR) : c;
+      const float4 ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
+      st4(po + q, c);
+      acc += dot4(c, ap);
+    }
+  } else {
+    auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
+    for (int e = 0; e < 4 * kQuads; ++e) {
+      const int c = o.lt * kTileCells + e * kThreads + threadIdx.x;
+      if (c >= n) continue;
+      int x, y, z;
+      coords(L, c, x, y, z);
+      const float v = pn(c);
+      float sm = 0.f;
+      if (x > 0) sm += v - pn(c - 1);
+      if (x < R - 1) sm += v - pn(c + 1);
+      if (y > 0) sm += v - pn(c - R);
+      if (y < R - 1) sm += v - pn(c + R);
+      if (z > 0) sm += v - pn(c - R * R);
+      if (z < R - 1) sm += v - pn(c + R * R);
+      po[c] = v;
+      acc += (double)v * (double)(v + lam * sm);
     }
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) s.pq_part[tile] = t;
 }
 
-__global__ __launch_bounds__(kThreads) void cg_b_kernel(const CGSys *__restrict__ sys, int nsys,
-                                                        int ntiles, int k, CGState s,
-                                                        const float *__restrict__ pcur) {
+__global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
+                                                        CGState s, const float *__restrict__ pcur) {
   __shared__ double sh[kThreads / 64];
-  const int tile = tile_of_block(ntiles);
-  if (tile >= ntiles) return;
-  const int si = find_sys(sys, nsys, tile);
-  const CGSys S = sys[si];
-  if (k >= S.iters) return;
-  const int R = S.R;
+  const int tile = tile_of_block(tile_lo, nlaunch);
+  Loc o;
+  if (tile >= tile_lo + nlaunch || !locate(P, tile, o)) return;
+  const CGLevel &L = P.lv[o.l];
+  if (k >= L.iters) return;
+  const int R = L.R;
   const int n = R * R * R;
-  const float alpha = (float)s.alpha[si];
-  const float *pp = pcur + S.base;
-  auto pv = [&](int c) { return pp[c]; };
-  const int c0 = (tile - S.tile0) * kTileCells + threadIdx.x * kCells;
+  const float alpha = (float)s.alpha[o.sys];
+  const float lam = L.lam;
+  const float *pp = pcur + o.base;
+  float *xx = s.x + o.base;
+  float *rr = s.r + o.base;
   double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < kCells; ++q) {
-    const int c = c0 + q;
-    if (c < n) {
-      const int x = c % R, y = (c / R) % R, z = c / (R * R);
-      const float vc = pp[c];
-      const float av = apply_A(pv, vc, x, y, z, R, c, S.lam);
-      const long long a = S.base + c;
-      s.x[a] += alpha * vc;
-      const float rn = s.r[a] - alpha * av;
-      s.r[a] = rn;
-      acc += (double)rn * (double)rn;
+  if (L.vec) {
+    const int RR = R * R;
+    for (int u = 0; u < kQuads; ++u) {
+      const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
+      if (q >= n) continue;
+      int x0, y, z;
+      coords(L, q, x0, y, z);
+      const float4 c = ld4(pp + q);
+      const float xl = x0 > 0 ? pp[q - 1] : c.x;
+      const float xr = x0 + 4 < R ? pp[q + 4] : c.w;
+      const float4 ym = y > 0 ? ld4(pp + q - R) : c;
+      const float4 yp = y < R - 1 ? ld4(pp + q + R) : c;
+      const float4 zm = z > 0 ? ld4(pp + q - RR) : c;
+      const float4 zp = z < R - 1 ? ld4(pp + q + RR) : c;
+      const float4 ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
+      st4(xx + q, axpy4(ld4(xx + q), alpha, c));
+      const float4 rn = axpy4(ld4(rr + q), -alpha, ap);
+      st4(rr + q, rn);
+      acc += dot4(rn, rn);
+    }
+  } else {
+    for (int e = 0; e < 4 * kQuads; ++e) {
+      const int c = o.lt * kTileCells + e * kThreads + threadIdx.x;
+      if (c >= n) continue;
+      int x, y, z;
+      coords(L, c, x, y, z);
+      const float v = pp[c];
+      float sm = 0.f;
+      if (x > 0) sm += v - pp[c - 1];
+      if (x < R - 1) sm += v - pp[c + 1];
+      if (y > 0) sm += v - pp[c - R];
+      if (y < R - 1) sm += v - pp[c + R];
+      if (z > 0) sm += v - pp[c - R * R];
+      if (z < R - 1) sm += v - pp[c + R * R];
+      xx[c] += alpha * v;
+      const float rn = rr[c] - alpha * (v + lam * sm);
+      rr[c] = rn;
+      acc += (double)rn * rn;
     }
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) s.rr_part[tile] = t;
 }
 
-__device__ __forceinline__ int tiles_of(const CGSys &S) {
-  const long long n = (long long)S.R * S.R * S.R;
-  return (int)((n + kTileCells - 1) / kTileCells);
-}
-
+// One workgroup per system of the launched levels.
 // mode 0: rr = sum rr_part (after init); mode 1: alpha = rr / sum pq_part;
 // mode 2: rr' = sum rr_part, beta = rr'/rr, rr = rr'.
-__global__ __launch_bounds__(kThreads) void cg_reduce_kernel(const CGSys *__restrict__ sys, int k,
-                                                             int mode, CGState s) {
+__global__ __launch_bounds__(kThreads) void cg_reduce_kernel(CGPlanDev P, int k, int mode,
+                                                             int sys_lo, CGState s) {
   __shared__ double sh[kThreads / 64];
-  const int si = blockIdx.x;
-  const CGSys S = sys[si];
-  if (mode != 0 && k >= S.iters) return;
+  const int sys = sys_lo + blockIdx.x;
+  int l = 0;
+  while (l + 1 < P.levels && sys >= P.lv[l + 1].sys0) ++l;
+  const CGLevel &L = P.lv[l];
+  if (mode != 0 && k >= L.iters) return;
   const double *part = mode == 1 ? s.pq_part : s.rr_part;
-  const int nt = tiles_of(S);
+  const int t0 = L.tile0 + (sys - L.sys0) * L.tps;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nt; i += kThreads) acc += part[S.tile0 + i];
+  for (int i = threadIdx.x; i < L.tps; i += kThreads) acc += part[t0 + i];
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) {
     if (mode == 0) {
-      s.rr[si] = t;
+      s.rr[sys] = t;
     } else if (mode == 1) {
-      s.alpha[si] = t > 0.0 ? s.rr[si] / t : 0.0;
+      s.alpha[sys] = t > 0.0 ? s.rr[sys] / t : 0.0;
     } else {
-      const double old = s.rr[si];
-      s.beta[si] = old > 0.0 ? t / old : 0.0;
-      s.rr[si] = t;
+      const double old = s.rr[sys];
+      s.beta[sys] = old > 0.0 ? t / old : 0.0;
+      s.rr[sys] = t;
     }
   }
 }
@@ -204,13 +293,42 @@ inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+CGPlanDev cg_make_plan(const GridDev &g, int batch, const float *lam, const int *iters,
+                       bool aligned16) {
+  CGPlanDev p;
+  memset(&p, 0, sizeof p);
+  p.levels = g.levels;
+  p.batch = batch;
+  p.stack = g.size;
+  int tile = 0, sys = 0;
+  for (int l = 0; l < g.levels; ++l) {
+    CGLevel &L = p.lv[l];
+    L.R = g.res[l];
+    L.shift = -1;
+    for (int s = 0; s < 12; ++s)
+      if ((1 << s) == L.R) L.shift = s;
+    L.iters = iters[l];
+    L.lam = lam[l];
+    L.off = g.off[l];
+    L.tile0 = tile;
+    const long long r3 = (long long)L.R * L.R * L.R;
+    L.tps = (int)((r3 + kTileCells - 1) / kTileCells);
+    L.sys0 = sys;
+    L.vec = aligned16 && L.R % 4 == 0 && g.size % 4 == 0 && g.off[l] % 4 == 0 && L.R >= 4;
+    tile += batch * 3 * L.tps;
+    sys += batch * 3;
+  }
+  p.ntiles = tile;
+  p.nsys = sys;
+  return p;
+}
+
 size_t cg_bytes(long long floats, int nsys, int ntiles) {
   return 4 * a256((size_t)floats * 4) + 2 * a256((size_t)ntiles * 8) + 3 * a256((size_t)nsys * 8);
 }
 
-pdg_status run_cg(const CGSys *sys, int nsys, int ntiles, int kmax, float *g, long long floats,
-                  void *ws, hipStream_t st) {
-  if (nsys <= 0 || ntiles <= 0) return PDG_OK;
+pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipStream_t st) {
+  if (P.nsys <= 0 || P.ntiles <= 0) return PDG_OK;
   char *w = (char *)ws;
   CGState s;
   s.x = (float *)w;
@@ -222,36 +340,49 @@ pdg_status run_cg(const CGSys *sys, int nsys, int ntiles, int kmax, float *g, lo
   s.p1 = (float *)w;
   w += a256((size_t)floats * 4);
   s.pq_part = (double *)w;
-  w += a256((size_t)ntiles * 8);
+  w += a256((size_t)P.ntiles * 8);
   s.rr_part = (double *)w;
-  w += a256((size_t)ntiles * 8);
+  w += a256((size_t)P.ntiles * 8);
   s.rr = (double *)w;
-  w += a256((size_t)nsys * 8);
+  w += a256((size_t)P.nsys * 8);
   s.alpha = (double *)w;
-  w += a256((size_t)nsys * 8);
+  w += a256((size_t)P.nsys * 8);
   s.beta = (double *)w;
-  const unsigned nb = (unsigned)(((ntiles + 7) / 8) * 8);
+  int kmax = 0;
+  for (int l = 0; l < P.levels; ++l) kmax = P.lv[l].iters > kmax ? P.lv[l].iters : kmax;
+  auto padded = [](int n) { return (unsigned)(((n + 7) / 8) * 8); };
   // solve 1: (I + lam L) y = g, y in s.x ; solve 2: (I + lam L) z = y, z in g
   for (int solve = 0; solve < 2; ++solve) {
     const float *src = solve == 0 ? g : s.x;
-    float *xdst = solve == 0 ? s.x : g;
-    // solve 2 starts from r = y: copy through cg_init with x = g
     CGState t = s;
-    t.x = xdst;
-    cg_init_kernel<<<nb, kThreads, 0, st>>>(sys, nsys, ntiles, src, t.r, t.x, t.rr_part);
+    t.x = solve == 0 ? s.x : g;
+    cg_init_kernel<<<padded(P.ntiles), kThreads, 0, st>>>(P, P.ntiles, src, t.r, t.x, t.rr_part);
     PDG_TRY(launched("cg_init"));
-    cg_reduce_kernel<<<nsys, kThreads, 0, st>>>(sys, 0, 0, t);
+    cg_reduce_kernel<<<P.nsys, kThreads, 0, st>>>(P, 0, 0, 0, t);
     PDG_TRY(launched("cg_reduce"));
     for (int k = 0; k < kmax; ++k) {
+      // launch only the span of levels that are still iterating
+      int lo = -1, hi = -1;
+      for (int l = 0; l < P.levels; ++l)
+        if (P.lv[l].iters > k) {
+          if (lo < 0) lo = l;
+          hi = l;
+        }
+      const int tile_lo = P.lv[lo].tile0;
+      const int tile_hi = P.lv[hi].tile0 + P.batch * 3 * P.lv[hi].tps;
+      const int sys_lo = P.lv[lo].sys0;
+      const int sys_hi = P.lv[hi].sys0 + P.batch * 3;
       float *pin = (k & 1) ? t.p1 : t.p0;
       float *pout = (k & 1) ? t.p0 : t.p1;
-      cg_a_kernel<<<nb, kThreads, 0, st>>>(sys, nsys, ntiles, k, t, pin, pout);
+      cg_a_kernel<<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(P, k, tile_lo, tile_hi - tile_lo,
+                                                                  t, pin, pout);
       PDG_TRY(launched("cg_a"));
-      cg_reduce_kernel<<<nsys, kThreads, 0, st>>>(sys, k, 1, t);
+      cg_reduce_kernel<<<sys_hi - sys_lo, kThreads, 0, st>>>(P, k, 1, sys_lo, t);
       PDG_TRY(launched("cg_reduce"));
-      cg_b_kernel<<<nb, kThreads, 0, st>>>(sys, nsys, ntiles, k, t, pout);
+      cg_b_kernel<<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(P, k, tile_lo, tile_hi - tile_lo,
+                                                                  t, pout);
       PDG_TRY(launched("cg_b"));
-      cg_reduce_kernel<<<nsys, kThreads, 0, st>>>(sys, k, 2, t);
+      cg_reduce_kernel<<<sys_hi - sys_lo, kThreads, 0, st>>>(P, k, 2, sys_lo, t);
       PDG_TRY(launched("cg_reduce"));
     }
   }

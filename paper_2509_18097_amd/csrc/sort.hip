@@ -38,7 +38,8 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__
 }
 
 // Exclusive scan of `total` entries in place, one workgroup: every thread owns
-// a contiguous chunk; chunk sums are scanned in LDS.
+// a contiguous chunk; chunk sums are scanned in LDS.  Used for short arrays
+// (the per-chunk sums of the multi-block scan below).
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(uint32_t *__restrict__ a,
                                                             long long total) {
   __shared__ uint32_t sh[kScanThreads];
@@ -61,6 +62,62 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(uint32_t *__restrict
     uint32_t v = a[i];
     a[i] = run;
     run += v;
+  }
+}
+
+// Multi-block exclusive scan: chunks of kScanChunk entries; phase 1 sums each
+// chunk, phase 2 scans the chunk sums (scan_kernel), phase 3 scans each chunk
+// from its offset.  Thread t of a chunk owns 4 consecutive entries.
+constexpr int kScanChunk = kScanThreads * 4;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_sums_kernel(const uint32_t *__restrict__ a,
+                                                                 long long total,
+                                                                 uint32_t *__restrict__ sums) {
+  __shared__ uint32_t sh[kScanThreads / 64];
+  const long long base = (long long)blockIdx.x * kScanChunk + 4ll * threadIdx.x;
+  uint32_t v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + k < total) v += a[base + k];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) t += sh[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(uint32_t *__restrict__ a,
+                                                                   long long total,
+                                                                   const uint32_t *__restrict__ offs) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const long long base = (long long)blockIdx.x * kScanChunk + 4ll * threadIdx.x;
+  uint32_t v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = base + k < total ? a[base + k] : 0u;
+  const uint32_t own = v[0] + v[1] + v[2] + v[3];
+  const uint32_t incl = wave_incl_scan(own);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t off = offs[blockIdx.x] + incl - own;
+  for (int i = 0; i < w; ++i) off += wsum[i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < total) a[base + k] = off;
+    off += v[k];
   }
 }
 
@@ -125,7 +182,9 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t radix_sort_bytes(long long n) {
   long long nb = (n + kTile - 1) / kTile;
   if (nb < 1) nb = 1;
-  return 2 * align256((size_t)n * 4) + align256((size_t)nb * 256 * 4);
+  const long long nchunks = (nb * 256 + kScanChunk - 1) / kScanChunk;
+  return 2 * align256((size_t)n * 4) + align256((size_t)nb * 256 * 4) +
+         align256((size_t)nchunks * 4);
 }
 
 pdg_status radix_sort(uint32_t *keys, uint32_t *vals, long long n, int bits, void *scratch,
@@ -143,13 +202,20 @@ pdg_status radix_sort(uint32_t *keys, uint32_t *vals, long long n, int bits, voi
   uint32_t *kalt = (uint32_t *)s;
   uint32_t *valt = (uint32_t *)(s + align256((size_t)n * 4));
   uint32_t *hist = (uint32_t *)(s + 2 * align256((size_t)n * 4));
+  const long long htotal = (long long)nb * 256;
+  const int nchunks = (int)((htotal + kScanChunk - 1) / kScanChunk);
+  uint32_t *sums = (uint32_t *)(s + 2 * align256((size_t)n * 4) + align256((size_t)htotal * 4));
   uint32_t *ks = keys, *vs = vals, *kd = kalt, *vd = valt;
   for (int p = 0; p < passes; ++p) {
     int shift = 8 * p;
     radix_hist_kernel<<<nb, kThreads, 0, st>>>(ks, n, shift, hist, nb);
     PDG_TRY(launched("radix_hist"));
-    scan_kernel<<<1, kScanThreads, 0, st>>>(hist, (long long)nb * 256);
-    PDG_TRY(launched("radix_scan"));
+    scan_sums_kernel<<<nchunks, kScanThreads, 0, st>>>(hist, htotal, sums);
+    PDG_TRY(launched("radix_scan_sums"));
+    scan_kernel<<<1, kScanThreads, 0, st>>>(sums, nchunks);
+    PDG_TRY(launched("radix_scan_top"));
+    scan_chunks_kernel<<<nchunks, kScanThreads, 0, st>>>(hist, htotal, sums);
+    PDG_TRY(launched("radix_scan_chunks"));
     radix_scatter_kernel<<<nb, kThreads, 0, st>>>(ks, vs, kd, vd, n, shift, hist, nb);
     PDG_TRY(launched("radix_scatter"));
     uint32_t *t0 = ks, *t1 = vs;

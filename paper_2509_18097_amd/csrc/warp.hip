@@ -117,6 +117,11 @@ __global__ __launch_bounds__(256) void chain_adjoint_kernel(
   lo[2 * ldo + i] = r2;
 }
 
+// Key of a scatter entry: the parity class of its base cell (3 bits) above
+// the global node id of the base cell.  Runs of one class have disjoint
+// 2x2x2 corner sets, so a class can be scattered in one pass without
+// conflicts; the classes run in a fixed order, which fixes the summation order
+// at every node.
 __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const float *__restrict__ x,
                                                            long long xstride, long long ldx,
                                                            long long S, uint32_t *__restrict__ keys,
@@ -129,6 +134,7 @@ __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const floa
   for (int l = 0; l < g.levels; ++l) {
     const int R = g.res[l];
     long long cell = 0;
+    uint32_t cls = 0;
     if (R > 1) {
       int ix, iy, iz;
       float f;
@@ -137,9 +143,10 @@ __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const floa
       stencil1(R, py, iy, f, in);
       stencil1(R, pz, iz, f, in);
       cell = ((long long)iz * R + iy) * R + ix;
+      cls = (uint32_t)((ix & 1) | ((iy & 1) << 1) | ((iz & 1) << 2));
     }
     long long e = ((long long)seg * g.levels + l) * S + s;
-    keys[e] = (uint32_t)(seg * g.nodes + g.noff[l] + cell);
+    keys[e] = (cls << kScatterClassShift) | (uint32_t)(seg * g.nodes + g.noff[l] + cell);
     vals[e] = (uint32_t)e;
   }
 }
@@ -166,49 +173,64 @@ __global__ void upload_kernel(Blob blob, unsigned char *__restrict__ dst, int n)
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = blob.b[i];
 }
 
+// One parity class: the first entry of every run of that class sums
+// w_corner(s) * lam(s) over its samples for all 8 corners and adds
+// level_scale times the sums to the 8 corner nodes.
 __global__ __launch_bounds__(256) void scatter_pass_kernel(
-    GridDev g, int delta, const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+    GridDev g, int cls, const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
     long long nent, long long S, const float *__restrict__ x, long long xstride, long long ldx,
     const float *__restrict__ lam, long long lstride, long long ldl, float *__restrict__ grad) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nent) return;
   const uint32_t key = keys[i];
+  if ((int)(key >> kScatterClassShift) != cls) return;
   if (i > 0 && keys[i - 1] == key) return;  // only the first entry of a run works
   const uint32_t e0 = vals[i];
   const long long segl = (long long)e0 / S;
   const int seg = (int)(segl / g.levels);
   const int l = (int)(segl % g.levels);
   const int R = g.res[l];
-  if (R == 1 && delta != 0) return;
-  const int dx = delta & 1, dy = (delta >> 1) & 1, dz = (delta >> 2) & 1;
   const float *X = x + seg * xstride;
   const float *Lm = lam + seg * lstride;
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  float a[8][3];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k][0] = a[k][1] = a[k][2] = 0.f;
   for (long long j = i; j < nent && keys[j] == key; ++j) {
     const long long s = (long long)vals[j] % S;
-    float w = 1.0f;
+    const float l0 = Lm[s], l1 = Lm[ldl + s], l2 = Lm[2 * ldl + s];
     if (R > 1) {
       int ii;
-      float f;
+      float fx, fy, fz;
       bool in;
-      stencil1(R, X[s], ii, f, in);
-      w *= dx ? f : 1.0f - f;
-      stencil1(R, X[ldx + s], ii, f, in);
-      w *= dy ? f : 1.0f - f;
-      stencil1(R, X[2 * ldx + s], ii, f, in);
-      w *= dz ? f : 1.0f - f;
+      stencil1(R, X[s], ii, fx, in);
+      stencil1(R, X[ldx + s], ii, fy, in);
+      stencil1(R, X[2 * ldx + s], ii, fz, in);
+      const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+      const float w[8] = {gx * gy * gz, fx * gy * gz, gx * fy * gz, fx * fy * gz,
+                          gx * gy * fz, fx * gy * fz, gx * fy * fz, fx * fy * fz};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        a[k][0] += w[k] * l0;
+        a[k][1] += w[k] * l1;
+        a[k][2] += w[k] * l2;
+      }
+    } else {
+      a[0][0] += l0;
+      a[0][1] += l1;
+      a[0][2] += l2;
     }
-    a0 += w * Lm[s];
-    a1 += w * Lm[ldl + s];
-    a2 += w * Lm[2 * ldl + s];
   }
-  const long long cell = (long long)key - (long long)seg * g.nodes - g.noff[l];
+  const long long cell =
+      (long long)(key & ((1u << kScatterClassShift) - 1u)) - (long long)seg * g.nodes - g.noff[l];
   const long long R2 = (long long)R * R, R3 = R2 * R;
-  const long long node = cell + (R > 1 ? (dx + (long long)dy * R + (long long)dz * R2) : 0);
   float *Gd = grad + (long long)seg * g.size + g.off[l];
-  Gd[node] += g.scale * a0;
-  Gd[R3 + node] += g.scale * a1;
-  Gd[2 * R3 + node] += g.scale * a2;
+  const int corners = R > 1 ? 8 : 1;
+  for (int k = 0; k < corners; ++k) {
+    const long long node = cell + (k & 1) + ((k >> 1) & 1) * R + ((k >> 2) & 1) * R2;
+    Gd[node] += g.scale * a[k][0];
+    Gd[R3 + node] += g.scale * a[k][1];
+    Gd[2 * R3 + node] += g.scale * a[k][2];
+  }
 }
 
 }  // namespace
@@ -270,12 +292,12 @@ pdg_status upload_small(void *dst, const void *src, size_t bytes, hipStream_t st
   return PDG_OK;
 }
 
-pdg_status launch_scatter_pass(const GridDev &g, int delta, const uint32_t *keys,
+pdg_status launch_scatter_pass(const GridDev &g, int cls, const uint32_t *keys,
                                const uint32_t *vals, long long nent, long long S, const float *x,
                                long long xstride, long long ldx, const float *lam,
                                long long lstride, long long ldl, float *grad, hipStream_t st) {
   if (nent <= 0) return PDG_OK;
-  scatter_pass_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, delta, keys, vals, nent, S, x, xstride,
+  scatter_pass_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, cls, keys, vals, nent, S, x, xstride,
                                                          ldx, lam, lstride, ldl, grad);
   return launched("scatter_pass");
 }
