@@ -163,9 +163,21 @@ struct ChamferWs {
   double *partials, *w_default;
   uint32_t *keys, *vals;
   void *sort;
+  ScreenSet *ssets;
+  ScreenJob *sjobs;
+  uint4 *pack_a, *pack_b;
+  unsigned *maxnorm;
 };
-ChamferWs chamfer_layout(Carve &c, long long n, long long m) {
+ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
   ChamferWs w;
+  memset(&w, 0, sizeof w);
+  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+    w.ssets = c.take<ScreenSet>(2);
+    w.sjobs = c.take<ScreenJob>(2);
+    w.pack_a = c.take<uint4>(2 * n);
+    w.pack_b = c.take<uint4>(2 * m);
+    w.maxnorm = c.take<unsigned>(2);
+  }
   w.jobs = c.take<NNJob>(2);
   w.segs = c.take<ChSeg>(1);
   w.b_base = c.take<unsigned>(1);
@@ -255,6 +267,11 @@ struct pdg_problem {
   uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
   void *sort = nullptr;
   NNJob *jobs = nullptr;
+  ScreenSet *ssets = nullptr;
+  ScreenJob *sjobs = nullptr;
+  uint4 *packs = nullptr;
+  unsigned *maxnorm = nullptr;
+  long long pack_rows = 0;
   ChSeg *segs = nullptr;
   unsigned *b_base = nullptr;
   void *cgws = nullptr;
@@ -299,10 +316,6 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   if (pd->chamfer_mode != PDG_CHAMFER_FP32 && pd->chamfer_mode != PDG_CHAMFER_BF16_SCREEN) {
     set_error("unknown chamfer mode %d", pd->chamfer_mode);
     return PDG_EINVAL;
-  }
-  if (pd->chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
-    set_error("BF16 screen is not built into this library");
-    return PDG_EUNSUPPORTED;
   }
   const pdg_hyper &h = pd->hp;
   if (!(h.alpha >= 0.0) || !isfinite(h.alpha) || !(h.w_iso >= 0.f) || !(h.eta0 > 0.f) || !(h.eta_growth > 0.f) ||
@@ -370,6 +383,14 @@ void layout(pdg_problem &p, Carve &c) {
   p.nseg = (int)(p.has_tm ? 2 * T : T);
   p.njobs = 2 * p.nseg;
   p.jobs = c.take<NNJob>(p.njobs);
+  if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
+    // every segment packs its moving set A and its fixed set B
+    p.pack_rows = T * (N + N) + (p.has_tm ? T * (V + N) : 0);
+    p.ssets = c.take<ScreenSet>(2 * p.nseg);
+    p.sjobs = c.take<ScreenJob>(p.njobs);
+    p.packs = c.take<uint4>(2 * p.pack_rows);
+    p.maxnorm = c.take<unsigned>(2 * p.nseg);
+  }
   p.segs = c.take<ChSeg>(p.nseg);
   p.b_base = c.take<unsigned>(p.nseg);
   p.cgws = c.take<char>((long long)cg_bytes(T * P, p.cg.nsys, p.cg.ntiles));
@@ -431,6 +452,12 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       }
       return PDG_OK;
     case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
+      if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
+        // screen warm-started from the previous iteration's assignment
+        PDG_TRY(launch_fill((float *)p.maxnorm, 2 * p.nseg, 0.f, st));
+        PDG_TRY(launch_screen_pack(p.ssets, 2 * p.nseg, p.max_nq, st));
+        return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
+      }
       return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
     case PDG_STAGE_LOSS: {  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
       PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
@@ -579,7 +606,7 @@ pdg_status pdg_chamfer_workspace(int64_t n, int64_t m, int32_t mode, size_t *byt
     return PDG_EINVAL;
   }
   Carve c(nullptr);
-  chamfer_layout(c, n, m);
+  chamfer_layout(c, n, m, mode);
   *bytes = c.off;
   return PDG_OK;
 }
@@ -589,10 +616,6 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
                        int32_t *nn_b, float *ga, void *ws, size_t ws_bytes, hipStream_t stream) {
   size_t need_bytes = 0;
   PDG_TRY(pdg_chamfer_workspace(n, m, mode, &need_bytes));
-  if (mode == PDG_CHAMFER_BF16_SCREEN) {
-    set_error("BF16 screen is not built into this library");
-    return PDG_EUNSUPPORTED;
-  }
   if (!(alpha >= 0.0) || !isfinite(alpha)) {
     set_error("alpha must be finite and >= 0");
     return PDG_EINVAL;
@@ -605,7 +628,7 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
   if (ga) PDG_TRY(need(ga, "ga"));
   PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
   Carve c(ws);
-  ChamferWs w = chamfer_layout(c, n, m);
+  ChamferWs w = chamfer_layout(c, n, m, mode);
   NNJob jobs[2];
   memset(jobs, 0, sizeof jobs);
   jobs[0].q = a;
@@ -634,7 +657,29 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
   PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
   PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
   PDG_TRY(upload_small(w.w_default, ones, sizeof ones, stream));
-  PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
+  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+    ScreenSet ss[2];
+    ScreenJob sj[2];
+    memset(ss, 0, sizeof ss);
+    memset(sj, 0, sizeof sj);
+    ss[0].x = a;
+    ss[0].n = (int)n;
+    ss[0].pack = w.pack_a;
+    ss[0].maxnorm = w.maxnorm;
+    ss[1].x = b;
+    ss[1].n = (int)m;
+    ss[1].pack = w.pack_b;
+    ss[1].maxnorm = w.maxnorm + 1;
+    sj[0] = ScreenJob{a, b, (int)n, (int)m, nn_a, w.pack_b, w.maxnorm + 1};
+    sj[1] = ScreenJob{b, a, (int)m, (int)n, nn_b, w.pack_a, w.maxnorm};
+    PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
+    PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
+    PDG_TRY(launch_fill((float *)w.maxnorm, 2, 0.f, stream));
+    PDG_TRY(launch_screen_pack(w.ssets, 2, (int)(n > m ? n : m), stream));
+    PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
+  } else {
+    PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
+  }
   PDG_TRY(launch_chamfer_loss(w.segs, 1, alpha, w.partials, loss, stream));
   if (ga) {
     const double *dw = dir_weight ? dir_weight : w.w_default;
@@ -793,6 +838,31 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     if (q.n > p->max_n) p->max_n = q.n;
     if (q.m > p->max_m) p->max_m = q.m;
   }
+  std::vector<ScreenSet> ssets;
+  std::vector<ScreenJob> sjobs;
+  if (p->packs) {
+    long long row = 0;
+    for (int s = 0; s < p->nseg; ++s) {
+      const ChSeg &q = segs[s];
+      ScreenSet sa, sb;
+      memset(&sa, 0, sizeof sa);
+      memset(&sb, 0, sizeof sb);
+      sa.x = q.a;
+      sa.n = q.n;
+      sa.pack = p->packs + 2 * row;
+      sa.maxnorm = p->maxnorm + 2 * s;
+      row += q.n;
+      sb.x = q.b;
+      sb.n = q.m;
+      sb.pack = p->packs + 2 * row;
+      sb.maxnorm = p->maxnorm + 2 * s + 1;
+      row += q.m;
+      ssets.push_back(sa);
+      ssets.push_back(sb);
+      sjobs.push_back(ScreenJob{q.a, q.b, q.n, q.m, q.nn_a, sb.pack, sb.maxnorm});
+      sjobs.push_back(ScreenJob{q.b, q.a, q.m, q.n, q.nn_b, sa.pack, sa.maxnorm});
+    }
+  }
   hipError_t e = hipSuccess;
   if (p->E > 0) {
     // edge indices index the template on the GPU: check their range once
@@ -813,6 +883,10 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   if (e == hipSuccess) e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(ChSeg), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->jobs, jobs.data(), jobs.size() * sizeof(NNJob), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->b_base, bb.data(), bb.size() * sizeof(unsigned), hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->packs)
+    e = hipMemcpy(p->ssets, ssets.data(), ssets.size() * sizeof(ScreenSet), hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->packs)
+    e = hipMemcpy(p->sjobs, sjobs.data(), sjobs.size() * sizeof(ScreenJob), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     pdg_status s = hip_fail(e, "pdg_problem_create table upload");
     delete p;

@@ -1,0 +1,259 @@
+// Nearest neighbours (paper Eq. 12) with a bf16 matrix-core screen and an
+// exact float32 re-rank: the served form of the Chamfer search.
+//
+// Screen.  For query q and candidate c the matrix cores evaluate
+//     S(q, c) = |c|^2 - 2 q.c           (|q|^2 is constant per query)
+// as one K = 16 row of v_mfma_f32_32x32x16_bf16 with float32 accumulation.
+// Each coordinate is split into two bf16 terms, x = x_hi + x_lo, and |c|^2
+// into three, which fills 12 of the 16 K slots:
+//     query row     [q_hi, q_hi, q_lo, 1, 1, 1, 0, 0, 0, 0]
+//     candidate row [-2c_hi, -2c_lo, -2c_hi, n_hi, n_mid, n_lo, 0 x 4]
+// (three coordinates per vector entry), so the only term dropped from q.c is
+// q_lo.c_lo.  With a = |q| and b = max |c| over the candidate set,
+//     |S + |q|^2 - |q - c|^2| <= eps(q) = 3e-5 a b + 2e-6 (a^2 + b^2) + 1e-6,
+// which covers the bf16 split and dropped term (6.02 * 2^-18 a b), the float32
+// accumulation of 16 terms (16 * 2^-24 (2.01 a b + b^2)), the float32
+// rounding of |c|^2 and |q|^2, and the float32 threshold arithmetic.
+//
+// Re-rank.  Every lane keeps the exact best (d2, index) of its query under the
+// library's contract (float32 difference form, no FMA, lowest index on ties).
+// A candidate can be skipped only if its screened lower bound exceeds the
+// current best, S + |q|^2 - eps > best (1 + 2^-20), which implies that its
+// contract distance is strictly larger (the contract value is within
+// 5 * 2^-24 relative of the true distance).  Every other candidate is
+// evaluated exactly, so the result equals the exact search bit for bit.
+// The scan may be warm-started from a previous assignment (any valid index
+// is an upper bound; it changes the work, never the result).
+//
+// Layout.  Queries are the B operand (32 columns per MFMA), candidates the A
+// operand (32 rows), so each lane holds 16 screened values of one query and
+// reduces them lane-locally; lanes l and l+32 hold the two row halves of the
+// same query and are merged at the end.  A workgroup (4 waves) owns 256
+// queries (two 32-query blocks per wave) and streams the packed candidates
+// through LDS in tiles of 256.
+#include "common.h"
+
+namespace pdg {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kThreads = 256;
+constexpr int kQPerBlock = 256;     // 4 waves x 2 blocks of 32 queries
+constexpr int kCTile = 256;         // candidates per LDS tile
+constexpr float kEpsAB = 3e-5f, kEpsSq = 2e-6f, kEpsAbs = 1e-6f;
+constexpr float kRelSlack = 1.0f + 1.0f / 1048576.0f;   // 1 + 2^-20
+
+__device__ __forceinline__ unsigned short bf16_rn(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);          // round to nearest even (finite inputs)
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ float d2_contract(float qx, float qy, float qz, float cx, float cy,
+                                             float cz) {
+#pragma clang fp contract(off)
+  const float dx = qx - cx;
+  const float dy = qy - cy;
+  const float dz = qz - cz;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+// Packed candidate row: 16 bf16 (32 B), plus the float32 coordinates for the
+// re-rank.  One thread per candidate; also max |c| over the set (float bits of
+// non-negative values order like unsigned integers, so an integer atomic max
+// is exact and order independent).
+__global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__ sets) {
+  const ScreenSet S = sets[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  float nrm = 0.f;
+  if (i < S.n) {
+    const long long n = S.n;
+    const float c[3] = {S.x[i], S.x[n + i], S.x[2 * n + i]};
+    unsigned short hi[3], lo[3];
+    for (int k = 0; k < 3; ++k) {
+      hi[k] = bf16_rn(c[k]);
+      lo[k] = bf16_rn(c[k] - bf16_f(hi[k]));
+    }
+    const float nn = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+    const unsigned short n0 = bf16_rn(nn);
+    const unsigned short n1 = bf16_rn(nn - bf16_f(n0));
+    const unsigned short n2 = bf16_rn((nn - bf16_f(n0)) - bf16_f(n1));
+    unsigned short row[16];
+    for (int k = 0; k < 3; ++k) {
+      row[k] = bf16_rn(-2.0f * bf16_f(hi[k]));
+      row[3 + k] = bf16_rn(-2.0f * bf16_f(lo[k]));
+      row[6 + k] = row[k];
+    }
+    row[9] = n0;
+    row[10] = n1;
+    row[11] = n2;
+    row[12] = row[13] = row[14] = row[15] = 0;
+    uint4 w0, w1;
+    w0.x = row[0] | ((unsigned)row[1] << 16);
+    w0.y = row[2] | ((unsigned)row[3] << 16);
+    w0.z = row[4] | ((unsigned)row[5] << 16);
+    w0.w = row[6] | ((unsigned)row[7] << 16);
+    w1.x = row[8] | ((unsigned)row[9] << 16);
+    w1.y = row[10] | ((unsigned)row[11] << 16);
+    w1.z = 0u;
+    w1.w = 0u;
+    S.pack[2 * i] = w0;
+    S.pack[2 * i + 1] = w1;
+    nrm = sqrtf(nn);
+  }
+  for (int o = 32; o > 0; o >>= 1) nrm = fmaxf(nrm, __shfl_xor(nrm, o, 64));
+  if ((threadIdx.x & 63) == 0 && nrm > 0.f) atomicMax(S.maxnorm, __float_as_uint(nrm));
+}
+
+struct QState {
+  float x, y, z, qn, eps, best, thr;
+  int idx;
+};
+
+__device__ __forceinline__ void set_thr(QState &s) { s.thr = s.best * kRelSlack - s.qn + s.eps; }
+
+// rows held by this lane for output register r of a 32x32 MFMA
+__device__ __forceinline__ int out_row(int r, int lane) {
+  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+
+__device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, int cbase, int nc,
+                                         const float4 *__restrict__ lc) {
+  float m = fminf(fminf(v[0], v[1]), v[2]);
+  m = fminf(fminf(m, v[3]), v[4]);
+  m = fminf(fminf(m, v[5]), v[6]);
+  m = fminf(fminf(m, v[7]), v[8]);
+  m = fminf(fminf(m, v[9]), v[10]);
+  m = fminf(fminf(m, v[11]), v[12]);
+  m = fminf(fminf(m, v[13]), v[14]);
+  m = fminf(m, v[15]);
+  if (!(m <= s.thr)) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = out_row(r, lane);
+    const int c = cbase + row;
+    if (v[r] <= s.thr && c < nc) {       // padded rows (c >= nc) never count
+      const float4 p = lc[row];
+      const float d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
+      if (d < s.best || (d == s.best && c < s.idx)) {
+        s.best = d;
+        s.idx = c;
+        set_thr(s);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__restrict__ jobs,
+                                                             int warm) {
+  const ScreenJob J = jobs[blockIdx.y];
+  const int q0 = blockIdx.x * kQPerBlock;
+  if (q0 >= J.nq) return;
+  __shared__ uint4 spack[kCTile * 2];
+  __shared__ float4 scoord[kCTile];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int half = lane >> 5;
+  const long long nq = J.nq, nc = J.nc;
+  const float cmax = __uint_as_float(*J.maxnorm);
+  QState st[2];
+  bf16x8 bq[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = q0 + wv * 64 + h * 32 + (lane & 31);
+    QState &s = st[h];
+    const bool ok = q < J.nq;
+    s.x = ok ? J.q[q] : 0.f;
+    s.y = ok ? J.q[nq + q] : 0.f;
+    s.z = ok ? J.q[2 * nq + q] : 0.f;
+    s.qn = (s.x * s.x + s.y * s.y) + s.z * s.z;
+    const float a = sqrtf(s.qn);
+    s.eps = kEpsAB * a * cmax + kEpsSq * (s.qn + cmax * cmax) + kEpsAbs;
+    s.best = __builtin_huge_valf();
+    s.idx = 0x7fffffff;
+    if (ok && warm) {
+      const int p = J.nn[q];
+      if (p >= 0 && p < J.nc) {
+        s.best = d2_contract(s.x, s.y, s.z, J.c[p], J.c[nc + p], J.c[2 * nc + p]);
+        s.idx = p;
+      }
+    }
+    set_thr(s);
+    // B operand: column (lane & 31), k-slots 8*half .. 8*half+7 of the query row
+    const float qc[3] = {s.x, s.y, s.z};
+    unsigned short hi[3], lo[3];
+    for (int k = 0; k < 3; ++k) {
+      hi[k] = bf16_rn(qc[k]);
+      lo[k] = bf16_rn(qc[k] - bf16_f(hi[k]));
+    }
+    const unsigned short one = 0x3F80;
+    unsigned short row[16] = {hi[0], hi[1], hi[2], hi[0], hi[1], hi[2], lo[0], lo[1],
+                              lo[2], one, one, one, 0, 0, 0, 0};
+    for (int e = 0; e < 8; ++e) {
+      const unsigned short b = row[8 * half + e];
+      bq[h][e] = *reinterpret_cast<const __bf16 *>(&b);
+    }
+  }
+  const uint4 far0 = make_uint4(0u, 0u, 0u, 0u);
+  const uint4 far1 = make_uint4(0x7F800000u, 0u, 0u, 0u);   // n_hi = +inf: S = +inf
+  for (int c0 = 0; c0 < J.nc; c0 += kCTile) {
+    __syncthreads();
+    {
+      const int c = c0 + tid;
+      if (c < J.nc) {
+        spack[2 * tid] = J.pack[2ll * c];
+        spack[2 * tid + 1] = J.pack[2ll * c + 1];
+        scoord[tid] = make_float4(J.c[c], J.c[nc + c], J.c[2 * nc + c], 0.f);
+      } else {
+        spack[2 * tid] = far0;
+        spack[2 * tid + 1] = far1;
+        scoord[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    const int left = (J.nc - c0 + 31) / 32;
+    const int nsub = left < kCTile / 32 ? left : kCTile / 32;
+    for (int sub = 0; sub < nsub; ++sub) {
+      const uint4 raw = spack[2 * (sub * 32 + (lane & 31)) + half];
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
+      const f32x16 z = {};
+      const f32x16 v0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[0], z, 0, 0, 0);
+      const f32x16 v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[1], z, 0, 0, 0);
+      consider(st[0], v0, lane, c0 + sub * 32, J.nc, scoord + sub * 32);
+      consider(st[1], v1, lane, c0 + sub * 32, J.nc, scoord + sub * 32);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    QState &s = st[h];
+    const float ob = __shfl_xor(s.best, 32, 64);
+    const int oi = __shfl_xor(s.idx, 32, 64);
+    if (ob < s.best || (ob == s.best && oi < s.idx)) {
+      s.best = ob;
+      s.idx = oi;
+    }
+    const int q = q0 + wv * 64 + h * 32 + (lane & 31);
+    if (half == 0 && q < J.nq) J.nn[q] = s.idx;
+  }
+}
+
+}  // namespace
+
+pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipStream_t st) {
+  if (nsets <= 0 || max_n <= 0) return PDG_OK;
+  dim3 grid(div_up(max_n, 256), nsets);
+  pack_kernel<<<grid, 256, 0, st>>>(sets);
+  return launched("screen_pack");
+}
+
+pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int warm,
+                            hipStream_t st) {
+  if (njobs <= 0 || max_nq <= 0) return PDG_OK;
+  dim3 grid(div_up(max_nq, kQPerBlock), njobs);
+  nn_screen_kernel<<<grid, kThreads, 0, st>>>(jobs, warm);
+  return launched("nn_screen");
+}
+
+}  // namespace pdg

@@ -121,6 +121,26 @@ struct NNJob {               // one directed nearest-neighbour search
   int pad[2];
 };
 pdg_status launch_nn_exact(const NNJob *jobs, int njobs, int max_nq, hipStream_t st);
+
+// chamfer_screen.hip: bf16 matrix-core screen + exact float32 re-rank
+struct ScreenSet {           // one point set to pack as screen candidates
+  const float *x;            // SoA [3][n]
+  int n;
+  int pad;
+  uint4 *pack;               // [n][2] packed bf16 rows (32 B per point)
+  unsigned *maxnorm;         // float bits of max |x| (zeroed before packing)
+};
+struct ScreenJob {           // one directed search over a packed candidate set
+  const float *q;
+  const float *c;
+  int nq, nc;
+  int *nn;                   // out; with warm start also the previous assignment
+  const uint4 *pack;         // packed rows of c
+  const unsigned *maxnorm;   // of c
+};
+pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipStream_t st);
+pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int warm,
+                            hipStream_t st);
 constexpr int kLossBlocks = 32;  // fixed partial count per (segment, direction)
 // partials[(seg*2+dir)*kLossBlocks + blk]; then losses[seg*2+dir] = mean.
 pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double *partials,

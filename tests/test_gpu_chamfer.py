@@ -21,8 +21,11 @@ def _clouds(n, m, seed):
     return a, b
 
 
+MODES = ["fp32", "bf16"]
+
+
 @pytest.mark.parametrize("n,m", SIZES)
-@pytest.mark.parametrize("mode", ["fp32"])
+@pytest.mark.parametrize("mode", MODES)
 def test_indices_and_losses(n, m, mode):
     require_gpu()
     a, b = _clouds(n, m, n * 7 + m)
@@ -39,7 +42,7 @@ def test_indices_and_losses(n, m, mode):
     assert abs(loss[1] - lb) <= 1e-10 * abs(lb) + 1e-300
 
 
-@pytest.mark.parametrize("mode", ["fp32"])
+@pytest.mark.parametrize("mode", MODES)
 def test_ties_go_to_lowest_index(mode):
     require_gpu()
     a, b = _clouds(3000, 2000, 3)
@@ -52,10 +55,11 @@ def test_ties_go_to_lowest_index(mode):
     assert np.array_equal(host(nb), C.nn_fp32(b, a))
 
 
-def test_identical_clouds_zero():
+@pytest.mark.parametrize("mode", MODES)
+def test_identical_clouds_zero(mode):
     require_gpu()
     a, _ = _clouds(2048, 1, 4)
-    loss, na, nb, ga = L.chamfer(dev(a), dev(a), need_grad=True)
+    loss, na, nb, ga = L.chamfer(dev(a), dev(a), mode=mode, need_grad=True)
     assert np.all(host(loss) == 0.0)
     assert np.array_equal(host(na), np.arange(2048)) and np.array_equal(host(nb), np.arange(2048))
     assert np.all(host(ga) == 0.0)
@@ -72,14 +76,15 @@ def test_gradient_matches_oracle(alpha):
     assert_rel(host(ga), ref, 1e-5, "chamfer gradient")
 
 
-def test_sequence_density_and_sampled_full_size():
-    """200k x 200k cloud pair (uniform cube, jitter 0.01): every index checked
-    on a random sample of queries against the brute-force oracle, losses
-    checked from the returned assignment."""
+@pytest.mark.parametrize("mode", MODES)
+def test_precision_pair_200k_sampled(mode):
+    """200k x 200k cloud pair (uniform cube, jitter 0.01): indices checked on a
+    random sample of queries against the brute-force oracle, losses checked
+    from the returned assignment."""
     require_gpu()
     p, q = synth.cloud_pair_cube(seed=0, n=200_000)
-    print("chamfer 200k x 200k", flush=True)
-    loss, na, nb, _ = L.chamfer(dev(p), dev(q))
+    print(f"chamfer 200k x 200k {mode}", flush=True)
+    loss, na, nb, _ = L.chamfer(dev(p), dev(q), mode=mode)
     na, nb, loss = host(na), host(nb), host(loss)
     rng = np.random.default_rng(0)
     for qs, cs, nn in ((p, q, na), (q, p, nb)):
@@ -88,3 +93,27 @@ def test_sequence_density_and_sampled_full_size():
         assert np.array_equal(nn[idx], ref)
     assert abs(loss[0] - C.direction_loss(p, q, na)) <= 1e-10 * loss[0]
     assert abs(loss[1] - C.direction_loss(q, p, nb)) <= 1e-10 * loss[1]
+
+
+def test_screen_equals_exact_everywhere_200k():
+    """The screened search returns exactly the exact search's indices on every
+    query of the 200k x 200k pair (both directions)."""
+    require_gpu()
+    p, q = synth.cloud_pair_cube(seed=1, n=200_000)
+    l0, a0, b0, _ = L.chamfer(dev(p), dev(q), mode="fp32")
+    l1, a1, b1, _ = L.chamfer(dev(p), dev(q), mode="bf16")
+    assert torch.equal(a0, a1) and torch.equal(b0, b1)
+    assert torch.equal(l0, l1)
+
+
+def test_screen_far_and_clustered_points():
+    """Coordinates far from the origin (large |x| widens the screen bound) and
+    many near-duplicates (narrow gaps) still give the exact indices."""
+    require_gpu()
+    rng = np.random.default_rng(9)
+    base = rng.uniform(-1, 1, (3, 64))
+    a = (np.repeat(base, 40, axis=1) + rng.normal(0, 1e-4, (3, 2560)) + 3.0).astype(np.float32)
+    b = (np.repeat(base, 30, axis=1) + rng.normal(0, 1e-4, (3, 1920)) + 3.0).astype(np.float32)
+    _, na, nb, _ = L.chamfer(dev(a), dev(b), mode="bf16")
+    assert np.array_equal(host(na), C.nn_fp32(a, b))
+    assert np.array_equal(host(nb), C.nn_fp32(b, a))

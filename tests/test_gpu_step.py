@@ -88,13 +88,30 @@ def test_pair_step_ragged():
     _stagewise(np.stack([src, tgt]), None, None, res, _theta0(1, res, 2), epoch=7, e_max=50)
 
 
-@pytest.mark.parametrize("epoch", [0, 3, 10])
-def test_sequence_step_with_template(epoch):
+@pytest.mark.parametrize("epoch,mode", [(0, "fp32"), (3, "fp32"), (10, "fp32"), (3, "bf16")])
+def test_sequence_step_with_template(epoch, mode):
     require_gpu()
     seq = synth.deforming_sequence(seed=1, frames=5, n=1500, subdiv=2)
     res = (4, 8, 16)
-    print(f"sequence step epoch={epoch}", flush=True)
-    _stagewise(seq.points, seq.template, seq.edges, res, _theta0(4, res, 3), epoch=epoch, e_max=10)
+    print(f"sequence step epoch={epoch} mode={mode}", flush=True)
+    _stagewise(seq.points, seq.template, seq.edges, res, _theta0(4, res, 3), epoch=epoch, e_max=10,
+               mode=mode)
+
+
+def test_screened_step_equals_exact_step_over_iterations():
+    """The served (bf16-screened, warm-started) form and the plain float32 form
+    produce bitwise identical iterations."""
+    require_gpu()
+    seq = synth.deforming_sequence(seed=4, frames=4, n=3000, subdiv=3)
+    res = (4, 8, 16, 32)
+    probs = [Problem(dev(seq.points), res, template=dev(seq.template), edges=dev(seq.edges),
+                     chamfer_mode=m) for m in ("fp32", "bf16")]
+    for e in range(5):
+        for p in probs:
+            p.step(e, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(probs[0].buffer("nn"), probs[1].buffer("nn")), e
+        assert torch.equal(probs[0].params, probs[1].params), e
 
 
 def test_zero_grids_identical_frames_fixed_point():
