@@ -36,7 +36,29 @@ FRAMES, NPTS, RES = 32, 50_000, (16, 32, 64, 128)
 # HBM3E 8 TB/s.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
+FP32_MFMA_PEAK_TFLOPS = 157.3
 PAIR_OPS = 8          # 3 sub + 3 mul + 2 add per pair under the difference-form contract
+PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
+# HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
+# factors from a 1 GiB copy), recorded in profiles/c2_step_bf16_dct_kernels.md for the
+# kernel source whose SHA-256 starts with the given prefix; reported only while the
+# source is unchanged.
+PMC_TRAFFIC = {
+    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "0fb962627afa7721",
+                         2 * 1409573.6 * 1024 + 23387.1 * 1024),
+}
+
+
+def pmc_traffic(kernel):
+    import hashlib
+    if kernel not in PMC_TRAFFIC:
+        return None
+    path, digest, nbytes = PMC_TRAFFIC[kernel]
+    with open(os.path.join(ROOT, path), "rb") as f:
+        if not hashlib.sha256(f.read()).hexdigest().startswith(digest):
+            return None
+    return round(nbytes)
 
 
 def parse():
@@ -46,12 +68,20 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--subdiv", type=int, default=6, choices=(4, 6),
                     help="template icosphere subdivisions (6: 40,962 vertices, 4: 2,562)")
-    ap.add_argument("--chamfer", default="fp32", choices=("fp32", "bf16"))
-    ap.add_argument("--precond", default="cg", choices=("cg", "dct"))
+    ap.add_argument("--chamfer", default="bf16", choices=("fp32", "bf16"),
+                    help="bf16: matrix-core screen + exact re-rank (same indices as fp32)")
+    ap.add_argument("--precond", default="dct", choices=("cg", "dct"),
+                    help="dct: exact spectral solve; cg: conjugate gradients, float64 dots")
+    ap.add_argument("--variants", default="fp32:cg,bf16:cg,fp32:dct",
+                    help="other chamfer:precond forms to time on the same GPU ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--serve", type=int, default=24, metavar="R",
+                    help="also serve the first R requests of the 256-request Poisson stream "
+                         "(4 requests/s, 20 iterations each); 0 skips, 256 is the full stream")
+    ap.add_argument("--serve-only", action="store_true", help="skip the sequence benchmark")
     return ap.parse_args()
 
 
@@ -130,6 +160,47 @@ def cg_bytes(prob):
     return total
 
 
+def dct_flops(prob):
+    """Matrix-core flops of one DCT preconditioner stage: six passes, each a
+    length-R contraction (2R flops) per grid value; R = 1 levels are skipped."""
+    T = prob.T
+    return sum(6 * 2 * r * T * 3 * r ** 3 for r in prob.res if r > 1)
+
+
+def roofline(prob, stages, chamfer, precond):
+    """Roofline of the two heavy stages; the dominant one is returned first."""
+    nn_ms, pre_ms = stages["nn"], stages["precond"]
+    pairs = nn_pairs(prob)
+    if chamfer == "bf16":
+        a = pairs * PAIR_MFMA_FLOPS / (nn_ms * 1e-3) / 1e12
+        nn = {"bound": "mfma", "achieved": round(a, 2), "peak": BF16_MFMA_PEAK_TFLOPS,
+              "unit": "TFLOP/s", "frac": round(a / BF16_MFMA_PEAK_TFLOPS, 4),
+              "traffic": pmc_traffic("nn_screen_kernel"),
+              "kernel": "nn_screen_kernel", "pairs_per_launch": pairs,
+              "pairs_per_s": round(pairs / (nn_ms * 1e-3), 1), "launch_ms": round(nn_ms, 4)}
+    else:
+        a = pairs * PAIR_OPS / (nn_ms * 1e-3) / 1e12
+        nn = {"bound": "alu", "achieved": round(a, 2), "peak": round(VALU_PEAK_TOPS, 2),
+              "unit": "TFLOP/s", "frac": round(a / VALU_PEAK_TOPS, 4), "traffic": None,
+              "kernel": "nn_exact_kernel", "pairs_per_launch": pairs,
+              "pairs_per_s": round(pairs / (nn_ms * 1e-3), 1), "launch_ms": round(nn_ms, 4)}
+    if precond == "dct":
+        f = dct_flops(prob)
+        a = f / (pre_ms * 1e-3) / 1e12
+        pre = {"bound": "mfma", "achieved": round(a, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(a / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+               "kernel": "dct_pass_kernel (24 launches) + gradient copy",
+               "flops_per_stage": f, "stage_ms": round(pre_ms, 4)}
+    else:
+        b = cg_bytes(prob)
+        a = b / (pre_ms * 1e-3) / 1e9
+        pre = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
+               "kernel": "cg_a_kernel/cg_b_kernel (+ reductions)", "bytes_per_stage": b,
+               "stage_ms": round(pre_ms, 4)}
+    return (nn, pre) if nn_ms >= pre_ms else (pre, nn)
+
+
 def cpu_baseline(seq, workers):
     """The oracle on one transition (t = 1) of the same workload, all stages,
     full sizes; scaled to iterations/s of the 31-transition step."""
@@ -169,6 +240,28 @@ def cpu_baseline(seq, workers):
     return dt
 
 
+def serve(count, chamfer, precond):
+    """Poisson stream of reconstruction requests (4/s; point counts log-uniform
+    in [2k, 200k]; 8..64 frames; 3-5 levels by point count), 20 iterations
+    each, continuous batching under an HBM budget of 60% of free memory."""
+    import torch
+    import synth
+    from paper_2509_18097_amd.serve import GpuExecutor, Server, poisson_requests
+    stream = synth.request_stream(seed=0, count=256)[:count]
+    t = time.perf_counter()
+    reqs = poisson_requests(stream, iterations=20)
+    gen_s = time.perf_counter() - t
+    free, _ = torch.cuda.mem_get_info()
+    ex = GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4)
+    st = Server(ex, budget_bytes=int(0.6 * free), max_slots=32).run(reqs)
+    out = st.summary()
+    out.update({"stream_requests": count, "iterations_per_request": 20,
+                "budget_bytes": int(0.6 * free), "input_generation_s": round(gen_s, 2),
+                "chamfer": chamfer, "precond": precond,
+                "load": round(st.makespan / st.arrival_span, 3) if st.arrival_span > 0 else None})
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+
 def copy_calibration():
     import torch
     from paper_2509_18097_amd import _lib as L  # noqa: F401  (loads nothing until used)
@@ -194,10 +287,14 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.serve_only:
+        print(json.dumps({"metric": METRIC, "serving": serve(args.serve, args.chamfer, args.precond)}))
+        return
     seq, prob = make_problem(args.subdiv, args.chamfer, args.precond)
     torch.cuda.synchronize()
     ms, wall = time_steps(prob, args.steps, args.warmup)
     value = 1000.0 / ms
+    terms = prob.terms()
     stages = {} if args.no_stages else time_stages(prob)
     result = {
         "metric": METRIC,
@@ -219,33 +316,38 @@ def main():
                    "frames": FRAMES, "points_per_frame": NPTS, "template_verts": prob.V,
                    "template_edges": prob.E, "grid_res": list(RES), "chamfer": args.chamfer,
                    "precond": args.precond, "graph_replay": True},
+        "loss_last_step": terms["loss"],
     }
     if stages:
         result["stages_ms"] = {k: round(v, 4) for k, v in stages.items()}
-        nn_ms = stages["nn"]
-        pre_ms = stages["precond"]
-        nn_tflops = nn_pairs(prob) * PAIR_OPS / (nn_ms * 1e-3) / 1e12
-        pre_gbs = cg_bytes(prob) / (pre_ms * 1e-3) / 1e9
-        nn_roof = {"bound": "alu", "achieved": round(nn_tflops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                   "unit": "TFLOP/s", "frac": round(nn_tflops / VALU_PEAK_TOPS, 4),
-                   "traffic": None, "kernel": "nn_exact_kernel",
-                   "pairs_per_launch": nn_pairs(prob), "launch_ms": round(nn_ms, 4)}
-        pre_roof = {"bound": "hbm", "achieved": round(pre_gbs, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(pre_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": "preconditioner stage (cg_a/cg_b)",
-                    "bytes_per_stage": cg_bytes(prob), "stage_ms": round(pre_ms, 4)}
-        dominant = max(("nn", "precond"), key=lambda k: stages[k])
-        result["roofline"] = nn_roof if dominant == "nn" else pre_roof
-        result["roofline_other"] = pre_roof if dominant == "nn" else nn_roof
+        result["roofline"], result["roofline_other"] = roofline(prob, stages, args.chamfer,
+                                                                args.precond)
+    T_, V_ = prob.T, prob.V
+    prob.close()
+    del prob
+    torch.cuda.empty_cache()
+    variants = {}
+    for v in [x for x in args.variants.split(",") if x]:
+        ch, pc = v.split(":")
+        _, vp = make_problem(args.subdiv, ch, pc)
+        vms, _ = time_steps(vp, max(3, args.steps // 2), 2)
+        variants[v] = {"ms_per_step": round(vms, 4), "iterations_per_s": round(1000.0 / vms, 4)}
+        vp.close()
+        del vp
+        torch.cuda.empty_cache()
+    if variants:
+        result["variants"] = variants
+    if args.serve > 0:
+        result["serving"] = serve(args.serve, args.chamfer, args.precond)
     if not args.no_cpu_baseline:
         workers = min(16, os.cpu_count() or 1)
         dt = cpu_baseline(seq, workers)
         result["cpu_baseline"] = {
-            "value": round(1.0 / (dt * prob.T), 6), "unit": "iterations/s", "cores": workers,
+            "value": round(1.0 / (dt * T_), 6), "unit": "iterations/s", "cores": workers,
             "kind": "oracle",
-            "sample": f"one of {prob.T} transitions (all stages at full size: 50k points, "
-                      f"{prob.V}-vertex template, 16..128^3 grids, DCT preconditioner), "
-                      f"{dt:.1f} s, scaled x{prob.T}"}
+            "sample": f"one of {T_} transitions (all stages at full size: 50k points, "
+                      f"{V_}-vertex template, 16..128^3 grids, DCT preconditioner), "
+                      f"{dt:.1f} s, scaled x{T_}"}
     print(json.dumps(result))
 
 

@@ -231,8 +231,12 @@ pdg_status check_precond_args(const pdg_grid_desc *d, const float *lambda, int32
     return PDG_EINVAL;
   }
   if (method == PDG_PRECOND_DCT) {
-    set_error("DCT preconditioner is not built into this library");
-    return PDG_EUNSUPPORTED;
+    for (int l = 0; l < d->levels; ++l)
+      if (d->res[l] > 256) {
+        set_error("DCT preconditioner supports R <= 256 (level %d has %d)", l, d->res[l]);
+        return PDG_EUNSUPPORTED;
+      }
+    return PDG_OK;
   }
   if (iters < 0 || (iters == 0 && !(tol > 0.0 && tol < 1.0))) {
     set_error("iters must be >= 0, and tol in (0,1) when iters == 0");
@@ -275,6 +279,8 @@ struct pdg_problem {
   ChSeg *segs = nullptr;
   unsigned *b_base = nullptr;
   void *cgws = nullptr;
+  void *dctws = nullptr;
+  float lambda_l[PDG_MAX_LEVELS];    // preconditioner weight per level
   int njobs = 0, nseg = 0, max_nq = 0, max_n = 0, max_m = 0;
   long long nrev = 0;
   CGPlanDev cg;
@@ -393,7 +399,10 @@ void layout(pdg_problem &p, Carve &c) {
   }
   p.segs = c.take<ChSeg>(p.nseg);
   p.b_base = c.take<unsigned>(p.nseg);
-  p.cgws = c.take<char>((long long)cg_bytes(T * P, p.cg.nsys, p.cg.ntiles));
+  if (p.d.precond_method == PDG_PRECOND_DCT)
+    p.dctws = c.take<char>((long long)dct_bytes(p.g));
+  else
+    p.cgws = c.take<char>((long long)cg_bytes(T * P, p.cg.nsys, p.cg.ntiles));
 }
 
 void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
@@ -406,7 +415,7 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   p.E = pd.verts > 0 ? pd.n_edges : 0;
   p.P = p.g.size;
   p.has_tm = p.V > 0;
-  float lam[PDG_MAX_LEVELS];
+  float *lam = p.lambda_l;
   p.adam.levels = p.g.levels;
   for (int l = 0; l < p.g.levels; ++l) {
     lam[l] = pd.hp.lambda0 * powf(pd.hp.lambda_growth, (float)l);
@@ -503,6 +512,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       return PDG_OK;
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
       PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
+      if (p.d.precond_method == PDG_PRECOND_DCT) return run_dct(g, (int)T, p.lambda_l, p.pgrad, p.dctws, st);
       return run_cg(p.cg, p.pgrad, T * P, p.cgws, st);
     case PDG_STAGE_ADAM:  // Sec. 3.6
       return launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
@@ -704,6 +714,10 @@ pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int
     return PDG_EINVAL;
   }
   const GridDev g = make_grid(*d);
+  if (method == PDG_PRECOND_DCT) {
+    *bytes = dct_bytes(g);
+    return PDG_OK;
+  }
   float lam[PDG_MAX_LEVELS];
   for (int l = 0; l < d->levels; ++l) lam[l] = 1.0f;
   CGPlanDev p = cg_plan(g, batch, lam, 1, 0.5, false);
@@ -721,6 +735,10 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
   PDG_TRY(pdg_precondition_workspace(d, batch, method, &nb));
   PDG_TRY(need_ws(ws, ws_bytes, nb));
   const GridDev gd = make_grid(*d);
+  if (method == PDG_PRECOND_DCT) {
+    PDG_TRY(dct_basis(gd, ws, stream));
+    return run_dct(gd, batch, lambda, g, ws, stream);
+  }
   const bool aligned16 = ((uintptr_t)g & 15) == 0;
   CGPlanDev p = cg_plan(gd, batch, lambda, iters, tol, aligned16);
   return run_cg(p, g, gd.size * batch, ws, stream);
@@ -899,6 +917,7 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   if (s == PDG_OK && p->has_tm)
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);
+  if (s == PDG_OK && p->dctws) s = dct_basis(p->g, p->dctws, stream);
   if (s == PDG_OK) s = launch_set_int(p->epoch, 0, stream);
   if (s != PDG_OK) {
     delete p;

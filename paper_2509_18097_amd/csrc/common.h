@@ -182,6 +182,12 @@ CGPlanDev cg_make_plan(const GridDev &g, int batch, const float *lam, const int 
 size_t cg_bytes(long long floats, int nsys, int ntiles);
 pdg_status run_cg(const CGPlanDev &plan, float *g, long long floats, void *ws, hipStream_t st);
 
+// dct.hip: exact (I + lam L)^-2 by the separable DCT-II (R <= 256)
+size_t dct_bytes(const GridDev &g);
+pdg_status dct_basis(const GridDev &g, void *ws, hipStream_t st);
+pdg_status run_dct(const GridDev &g, int batch, const float *lam, float *data, const void *ws,
+                   hipStream_t st);
+
 // optim.hip
 struct AdamLevels {
   int levels;

@@ -39,6 +39,29 @@ class HyperParams:
         return h
 
 
+def problem_bytes(frames: int, n: int, res, verts: int = 0, n_edges: int = 0,
+                  chamfer_mode: str = "fp32", precond: str = "cg") -> int:
+    """Device bytes one request needs: the library workspace (exact, from
+    pdg_problem_workspace) plus params, Adam moments, frames and template."""
+    d = L.ProblemDesc()
+    d.frames, d.n, d.verts, d.n_edges = int(frames), int(n), int(verts), int(n_edges)
+    fake = 256                      # sizing only: any aligned non-null address
+    d.points = d.params = d.adam_m = d.adam_v = fake
+    d.template_verts = fake if verts > 0 else None
+    d.edges = fake if n_edges > 0 else None
+    d.grid = L.grid_desc(res)
+    d.hp = HyperParams().to_c()
+    d.chamfer_mode = L.CHAMFER_MODES[chamfer_mode]
+    d.precond_method = L.PRECOND_METHODS[precond]
+    d.cg_tol = 1e-7
+    nb = ctypes.c_size_t()
+    L.check(L.lib().pdg_problem_workspace(ctypes.byref(d), ctypes.byref(nb)), "pdg_problem_workspace")
+    T = frames - 1
+    state = 3 * T * L.grid_size(res) * 4
+    data = frames * 3 * n * 4 + verts * 12 + n_edges * 8
+    return int(nb.value) + state + data
+
+
 class Problem:
     """Device-resident state of one request and its optimisation step."""
 
@@ -46,7 +69,7 @@ class Problem:
                  edges: torch.Tensor | None = None, hp: HyperParams | None = None,
                  chamfer_mode: str = "fp32", precond: str = "cg", cg_iters: int = 0,
                  cg_tol: float = 1e-7, level_scale: float | None = None,
-                 params: torch.Tensor | None = None):
+                 params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
         self.hp = hp or HyperParams()
         self.res = tuple(int(r) for r in res)
         self.points = L._dev(points, torch.float32, "points")
@@ -95,7 +118,8 @@ class Problem:
         d.workspace_bytes = nb.value
         self._desc = d
         h = ctypes.c_void_p()
-        L.check(L.lib().pdg_problem_create(ctypes.byref(d), L._stream(), ctypes.byref(h)),
+        st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+        L.check(L.lib().pdg_problem_create(ctypes.byref(d), st, ctypes.byref(h)),
                 "pdg_problem_create")
         self._h = h
 

@@ -26,11 +26,11 @@ def _check_positions(got, ref, src):
     assert np.all(np.abs(got - ref) <= tol)
 
 
-def _stagewise(points, template, edges, res, theta0, epoch, e_max, mode="fp32"):
+def _stagewise(points, template, edges, res, theta0, epoch, e_max, mode="fp32", precond="cg"):
     hp = HyperParams(e_max=e_max)
     prob = Problem(dev(points), res, template=None if template is None else dev(template),
                    edges=None if edges is None else dev(edges), hp=hp, chamfer_mode=mode,
-                   params=dev(theta0))
+                   params=dev(theta0), precond=precond)
     prob.step(epoch)
     torch.cuda.synchronize()
     phat = host(prob.buffer("phat"))
@@ -88,14 +88,16 @@ def test_pair_step_ragged():
     _stagewise(np.stack([src, tgt]), None, None, res, _theta0(1, res, 2), epoch=7, e_max=50)
 
 
-@pytest.mark.parametrize("epoch,mode", [(0, "fp32"), (3, "fp32"), (10, "fp32"), (3, "bf16")])
-def test_sequence_step_with_template(epoch, mode):
+@pytest.mark.parametrize("epoch,mode,precond", [(0, "fp32", "cg"), (3, "fp32", "cg"),
+                                               (10, "fp32", "cg"), (3, "bf16", "cg"),
+                                               (3, "bf16", "dct")])
+def test_sequence_step_with_template(epoch, mode, precond):
     require_gpu()
     seq = synth.deforming_sequence(seed=1, frames=5, n=1500, subdiv=2)
     res = (4, 8, 16)
-    print(f"sequence step epoch={epoch} mode={mode}", flush=True)
+    print(f"sequence step epoch={epoch} mode={mode} precond={precond}", flush=True)
     _stagewise(seq.points, seq.template, seq.edges, res, _theta0(4, res, 3), epoch=epoch, e_max=10,
-               mode=mode)
+               mode=mode, precond=precond)
 
 
 def test_screened_step_equals_exact_step_over_iterations():
