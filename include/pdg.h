@@ -123,6 +123,17 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
                        int32_t *nn_a, int32_t *nn_b, float *ga,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Adjoint of pdg_chamfer from saved indices (no new search):
+ *   ga <- d/da [dir_weight[0]*loss[0] + dir_weight[1]*loss[1]]  (OVERWRITTEN)
+ * with nn_a, nn_b as returned by pdg_chamfer for the same a, b.  dir_weight is
+ * a device double[2] (e.g. the upstream gradient of the two losses).  The
+ * reverse-direction sum at every point of a is taken in a fixed order
+ * (sorted runs, no atomics).  ws: pdg_chamfer_workspace(n, m, PDG_CHAMFER_FP32). */
+pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64_t m,
+                                double alpha, const int32_t *nn_a, const int32_t *nn_b,
+                                const double *dir_weight, float *ga, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* ---------------------------------------------------------- precondition --
  * Grid Sobolev preconditioner (paper Sec. 3.2, Eq. 3), in place:
  *   g_l <- (I + lambda[l] L_l)^{-2} g_l for every level l and channel of

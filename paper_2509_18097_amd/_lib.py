@@ -69,6 +69,7 @@ _SIGS = {
     "pdg_deform_backward": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "pdg_chamfer_workspace": (_I32, [_I64, _I64, _I32, ctypes.POINTER(_SZ)]),
     "pdg_chamfer": (_I32, [_P, _I64, _P, _I64, _D, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pdg_chamfer_backward": (_I32, [_P, _I64, _P, _I64, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "pdg_precondition_workspace": (_I32, [ctypes.POINTER(GridDesc), _I32, _I32, ctypes.POINTER(_SZ)]),
     "pdg_precondition": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_F), _P, _I32, _I32, _I32,
                                 _D, _P, _SZ, _P]),
@@ -201,6 +202,24 @@ def chamfer(a, b, alpha=5.56, mode="fp32", dir_weight=None, need_grad=False):
                             _ptr(nn_a), _ptr(nn_b), _ptr(ga), _ptr(ws), nb.value, _stream()),
           "pdg_chamfer")
     return loss, nn_a, nn_b, ga
+
+
+def chamfer_backward(a, b, nn_a, nn_b, dir_weight, alpha=5.56):
+    """d/da of dir_weight[0]*loss[0] + dir_weight[1]*loss[1] from saved indices."""
+    _dev(a, torch.float32, "a")
+    _dev(b, torch.float32, "b")
+    _dev(nn_a, torch.int32, "nn_a")
+    _dev(nn_b, torch.int32, "nn_b")
+    _dev(dir_weight, torch.float64, "dir_weight")
+    n, m = a.shape[1], b.shape[1]
+    nb = ctypes.c_size_t()
+    check(lib().pdg_chamfer_workspace(n, m, 0, ctypes.byref(nb)), "pdg_chamfer_workspace")
+    ws = _ws(nb.value, a.device)
+    ga = torch.empty_like(a)
+    check(lib().pdg_chamfer_backward(_ptr(a), n, _ptr(b), m, float(alpha), _ptr(nn_a), _ptr(nn_b),
+                                     _ptr(dir_weight), _ptr(ga), _ptr(ws), nb.value, _stream()),
+          "pdg_chamfer_backward")
+    return ga
 
 
 def precondition(g, res, lambdas, batch=1, method="cg", iters=0, tol=1e-7):

@@ -702,6 +702,44 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
   return PDG_OK;
 }
 
+pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64_t m,
+                                double alpha, const int32_t *nn_a, const int32_t *nn_b,
+                                const double *dir_weight, float *ga, void *ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_chamfer_workspace(n, m, PDG_CHAMFER_FP32, &need_bytes));
+  if (!(alpha >= 0.0) || !isfinite(alpha)) {
+    set_error("alpha must be finite and >= 0");
+    return PDG_EINVAL;
+  }
+  PDG_TRY(need(a, "a"));
+  PDG_TRY(need(b, "b"));
+  PDG_TRY(need(nn_a, "nn_a"));
+  PDG_TRY(need(nn_b, "nn_b"));
+  PDG_TRY(need(dir_weight, "dir_weight"));
+  PDG_TRY(need(ga, "ga"));
+  PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
+  Carve c(ws);
+  ChamferWs w = chamfer_layout(c, n, m, PDG_CHAMFER_FP32);
+  ChSeg seg;
+  memset(&seg, 0, sizeof seg);
+  seg.a = a;
+  seg.b = b;
+  seg.n = (int)n;
+  seg.m = (int)m;
+  seg.nn_a = const_cast<int32_t *>(nn_a);   // read only on this path
+  seg.nn_b = const_cast<int32_t *>(nn_b);
+  seg.ga = ga;
+  const unsigned bb = 0;
+  PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
+  PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
+  PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dir_weight, stream));
+  PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
+  PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
+  return launch_chamfer_rev_scatter(w.segs, 1, w.b_base, nullptr, w.keys, w.vals, m, (float)alpha,
+                                    dir_weight, stream);
+}
+
 pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int32_t method,
                                       size_t *bytes) {
   PDG_TRY(check_grid(d));
