@@ -267,11 +267,12 @@ pdg_status pdg_problem_destroy(pdg_problem *p);
  *   PDG_BUF_PGRAD  float [T][grid_size]  preconditioned gradient
  *   PDG_BUF_GPHAT  float [T][3][n]   dL/dP^_t
  *   PDG_BUF_GXHAT  float [T][3][V]   direct dL/dX_t (Chamfer + isometry), frames 1..T
- *   PDG_BUF_TERMS  double[8]         the loss terms of pdg_step */
+ *   PDG_BUF_TERMS  double[8]         the loss terms of pdg_step
+ *   PDG_BUF_LAM    float [T][3][V]   total dL/dX_t after the reverse sweep of Eq. 8 */
 typedef enum {
   PDG_BUF_PHAT = 0, PDG_BUF_XHAT = 1, PDG_BUF_NN = 2, PDG_BUF_LOSSES = 3,
   PDG_BUF_WCONF = 4, PDG_BUF_GRAD = 5, PDG_BUF_PGRAD = 6, PDG_BUF_GPHAT = 7,
-  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9
+  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9, PDG_BUF_LAM = 10
 } pdg_buffer;
 pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes);
 

@@ -1050,6 +1050,7 @@ pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, s
     case PDG_BUF_GPHAT: *ptr = p->gphat; *bytes = T * 3 * N * 4; break;
     case PDG_BUF_GXHAT: *ptr = p->gxhat; *bytes = T * 3 * V * 4; break;
     case PDG_BUF_TERMS: *ptr = p->terms; *bytes = 8 * 8; break;
+    case PDG_BUF_LAM: *ptr = p->lam; *bytes = T * 3 * V * 4; break;
     default:
       set_error("unknown buffer %d", which);
       return PDG_EINVAL;

@@ -156,7 +156,7 @@ class Problem:
             return raw.view(torch.float32).view(T, 3, N)
         if name == "xhat":
             return raw.view(torch.float32).view(T + 1, 3, V)
-        if name == "gxhat":
+        if name in ("gxhat", "lam"):
             return raw.view(torch.float32).view(T, 3, V)
         if name in ("grad", "pgrad"):
             return raw.view(torch.float32).view(T, P)

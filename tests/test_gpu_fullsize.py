@@ -1,0 +1,145 @@
+"""Parity at full size, in the configuration bench.py times: the 32-frame x
+50,000-point sequence with the 40,962-vertex template and grids 16..128^3,
+BF16-screened Chamfer, DCT preconditioner, graph replay.  Two iterations are
+run; every stage of the second is checked against the oracle on outputs it
+can compute one by one (sampled points, sampled transitions), each oracle
+stage fed the GPU's float32 inputs to that stage."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import adam as A
+from oracle import chamfer as C
+from oracle import precond as P
+from oracle import sequence as S
+from oracle import warp as W
+from paper_2509_18097_amd.problem import HyperParams, Problem
+from _gpu import assert_rel, dev, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+RES = (16, 32, 64, 128)
+
+
+@pytest.fixture(scope="module")
+def run():
+    require_gpu()
+    seq = synth.deforming_sequence(seed=0, frames=32, n=50_000, subdiv=6)
+    prob = Problem(dev(seq.points), RES, template=dev(seq.template), edges=dev(seq.edges),
+                   hp=HyperParams(e_max=50), chamfer_mode="bf16", precond="dct")
+    print("full-size sequence: step 0", flush=True)
+    prob.step(0, use_graph=True)
+    torch.cuda.synchronize()
+    theta1, m1, v1 = host(prob.params), host(prob.m), host(prob.v)
+    print("full-size sequence: step 1", flush=True)
+    prob.step(1, use_graph=True)
+    torch.cuda.synchronize()
+    out = {k: host(prob.buffer(k)) for k in ("phat", "xhat", "losses", "wconf", "grad", "pgrad",
+                                              "gphat", "gxhat", "lam", "terms")}
+    out["nn"] = {k: host(v) for k, v in prob.nn().items()}
+    out["theta2"], out["m2"], out["v2"] = host(prob.params), host(prob.m), host(prob.v)
+    prob.close()
+    return seq, theta1, m1, v1, out
+
+
+def test_warps_sampled(run):
+    seq, th, _, _, o = run
+    rng = np.random.default_rng(0)
+    for t in (0, 13, 30):
+        idx = rng.choice(50_000, 500, replace=False)
+        ref = W.warp(th[t], RES, seq.points[t][:, idx], 0.25)
+        d = np.abs(o["phat"][t][:, idx] - ref)
+        assert np.all(d <= 1e-5 * np.abs(ref - seq.points[t][:, idx]).max() + 4e-7 * np.abs(ref))
+        vi = rng.choice(40_962, 500, replace=False)
+        ref = W.warp(th[t], RES, o["xhat"][t][:, vi], 0.25)
+        d = np.abs(o["xhat"][t + 1][:, vi] - ref)
+        assert np.all(d <= 1e-5 * np.abs(ref - o["xhat"][t][:, vi]).max() + 4e-7 * np.abs(ref))
+
+
+def test_nearest_neighbours_sampled(run):
+    seq, _, _, _, o = run
+    rng = np.random.default_rng(1)
+    for t in (0, 17, 30):
+        tgt = seq.points[t + 1]
+        for q, c, key in ((o["phat"][t], tgt, "pt_ab"), (tgt, o["phat"][t], "pt_ba"),
+                          (o["xhat"][t + 1], tgt, "tm_ab"), (tgt, o["xhat"][t + 1], "tm_ba")):
+            idx = rng.choice(q.shape[1], 150, replace=False)
+            assert np.array_equal(o["nn"][key][t][idx], C.nn_fp32(q[:, idx], c, workers=8)), (t, key)
+
+
+def test_losses_confidence_and_terms(run):
+    seq, _, _, _, o = run
+    T = 31
+    cd = np.zeros((2 * T, 2))
+    for t in range(T):
+        tgt = seq.points[t + 1]
+        cd[t] = (C.direction_loss(o["phat"][t], tgt, o["nn"]["pt_ab"][t]),
+                 C.direction_loss(tgt, o["phat"][t], o["nn"]["pt_ba"][t]))
+        cd[T + t] = (C.direction_loss(o["xhat"][t + 1], tgt, o["nn"]["tm_ab"][t]),
+                     C.direction_loss(tgt, o["xhat"][t + 1], o["nn"]["tm_ba"][t]))
+    np.testing.assert_allclose(o["losses"], cd, rtol=1e-10, atol=0)
+    w, cd_max, _ = S.confidence(cd[T:].sum(1), cd[:T].sum(1), 1, 50)
+    np.testing.assert_allclose(o["wconf"], w, rtol=1e-12)
+    l_iso, _ = S.isometry(o["xhat"], seq.edges, 250.0)
+    loss = float(np.mean(w * cd[T:].sum(1) + cd[:T].sum(1)) + l_iso)
+    assert abs(o["terms"][0] - loss) <= 1e-9 * loss
+    assert abs(o["terms"][3] - cd_max) <= 1e-12 * cd_max
+
+
+def _rel(got, ref):
+    d = np.asarray(got, np.float64) - ref
+    return max(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300),
+               np.max(np.abs(d)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _off_kinks(x, res, margin=1e-4):
+    """Samples not within `margin` (in cell units) of a cell-centre plane of any
+    level: there the position Jacobian is one-sided and float32 and float64 may
+    pick different sides."""
+    ok = np.ones(x.shape[1], bool)
+    for r in res:
+        u = (x.astype(np.float64) + 1.0) * r / 2.0 - 0.5
+        ok &= np.all(np.abs(u - np.round(u)) > margin, axis=0)
+    return ok
+
+
+def test_gradients_sampled_transitions(run):
+    seq, th, _, _, o = run
+    T = 31
+    w = o["wconf"]
+    _, g_iso = S.isometry(o["xhat"], seq.edges, 250.0)
+    lams = [0.25 * 1.5 ** l for l in range(4)]
+    errs = {}
+    for t in (0, 21, 30):
+        tgt = seq.points[t + 1]
+        gp = C.gradient(o["phat"][t], tgt, o["nn"]["pt_ab"][t], o["nn"]["pt_ba"][t], 5.56,
+                        1 / T, 1 / T)
+        errs[f"dL/dP^ t={t}"] = _rel(o["gphat"][t], gp)
+        gx = C.gradient(o["xhat"][t + 1], tgt, o["nn"]["tm_ab"][t], o["nn"]["tm_ba"][t], 5.56,
+                        w[t] / T, w[t] / T) + g_iso[t + 1]
+        errs[f"dL/dX t={t}"] = _rel(o["gxhat"][t], gx)
+        if t < T - 1:
+            # one step of the reverse sweep of the chain, from the GPU's later adjoint
+            ok = _off_kinks(o["xhat"][t + 1], RES)
+            lam = o["gxhat"][t] + W.position_adjoint(th[t + 1], RES, o["xhat"][t + 1],
+                                                     o["lam"][t + 1], 0.25)
+            errs[f"chain adjoint t={t} ({(~ok).sum()} samples on kinks masked)"] = \
+                _rel(o["lam"][t][:, ok], lam[:, ok])
+        ref = W.grid_adjoint(RES, seq.points[t], o["gphat"][t], 0.25) + \
+            W.grid_adjoint(RES, o["xhat"][t], o["lam"][t], 0.25)
+        errs[f"dL/dG t={t}"] = _rel(o["grad"][t], ref)
+        errs[f"precond t={t}"] = _rel(o["pgrad"][t], P.apply_levels(o["grad"][t], RES, lams))
+    for k, v in errs.items():
+        print(f"{k}: {v:.2e}", flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_adam_full(run):
+    _, th, m, v, o = run
+    etas = [5e-3 * 1.1 ** l for l in range(4)]
+    off = 0
+    for l, r in enumerate(RES):
+        sl = slice(off, off + 3 * r ** 3)
+        ref, rm, rv = A.update(th[:, sl], m[:, sl], v[:, sl], o["pgrad"][:, sl], etas[l], 2)
+        assert np.max(np.abs(o["theta2"][:, sl] - ref)) <= 1e-5 * etas[l]
+        off += 3 * r ** 3
