@@ -82,6 +82,8 @@ def parse():
                     help="also serve the first R requests of the 256-request Poisson stream "
                          "(4 requests/s, 20 iterations each); 0 skips, 256 is the full stream")
     ap.add_argument("--serve-only", action="store_true", help="skip the sequence benchmark")
+    ap.add_argument("--serve-slots", type=int, default=32,
+                    help="maximum requests resident and iterating at once")
     return ap.parse_args()
 
 
@@ -240,7 +242,7 @@ def cpu_baseline(seq, workers):
     return dt
 
 
-def serve(count, chamfer, precond):
+def serve(count, chamfer, precond, slots=32):
     """Poisson stream of reconstruction requests (4/s; point counts log-uniform
     in [2k, 200k]; 8..64 frames; 3-5 levels by point count), 20 iterations
     each, continuous batching under an HBM budget of 60% of free memory."""
@@ -253,11 +255,11 @@ def serve(count, chamfer, precond):
     gen_s = time.perf_counter() - t
     free, _ = torch.cuda.mem_get_info()
     ex = GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4)
-    st = Server(ex, budget_bytes=int(0.6 * free), max_slots=32).run(reqs)
+    st = Server(ex, budget_bytes=int(0.6 * free), max_slots=slots).run(reqs)
     out = st.summary()
     out.update({"stream_requests": count, "iterations_per_request": 20,
                 "budget_bytes": int(0.6 * free), "input_generation_s": round(gen_s, 2),
-                "chamfer": chamfer, "precond": precond,
+                "chamfer": chamfer, "precond": precond, "max_slots": slots,
                 "load": round(st.makespan / st.arrival_span, 3) if st.arrival_span > 0 else None})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
@@ -288,7 +290,8 @@ def main():
         copy_calibration()
         return
     if args.serve_only:
-        print(json.dumps({"metric": METRIC, "serving": serve(args.serve, args.chamfer, args.precond)}))
+        print(json.dumps({"metric": METRIC, "serving": serve(args.serve, args.chamfer, args.precond,
+                                                                 args.serve_slots)}))
         return
     seq, prob = make_problem(args.subdiv, args.chamfer, args.precond)
     torch.cuda.synchronize()
@@ -338,7 +341,7 @@ def main():
     if variants:
         result["variants"] = variants
     if args.serve > 0:
-        result["serving"] = serve(args.serve, args.chamfer, args.precond)
+        result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:
         workers = min(16, os.cpu_count() or 1)
         dt = cpu_baseline(seq, workers)

@@ -32,6 +32,9 @@ FLAGS = [
     # packed FP32 instructions have given silently wrong results on this
     # hardware generation: keep hipcc from forming them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results straight into VGPRs (no v_accvgpr_read copies); the
+    # kernels consume every MFMA result with VALU instructions
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
 
 

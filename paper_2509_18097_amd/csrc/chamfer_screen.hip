@@ -29,8 +29,12 @@
 // operand (32 rows), so each lane holds 16 screened values of one query and
 // reduces them lane-locally; lanes l and l+32 hold the two row halves of the
 // same query and are merged at the end.  A workgroup (4 waves) owns 256
-// queries (two 32-query blocks per wave) and streams the packed candidates
-// through LDS in tiles of 256.
+// queries (two 32-query blocks per wave, so one LDS read of a candidate
+// fragment feeds two MFMAs) and streams the packed candidates through LDS in
+// tiles of 256: the next tile is fetched into registers while the current one
+// is screened, then written to the other LDS buffer.  The rare exact re-rank
+// reads candidate coordinates from global memory (L2); staging them in LDS
+// measured no faster.
 #include "common.h"
 
 namespace pdg {
@@ -39,9 +43,21 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+#ifndef PDG_SCREEN_QB
+#define PDG_SCREEN_QB 2
+#endif
+#ifndef PDG_SCREEN_TILE
+#define PDG_SCREEN_TILE 256
+#endif
+#ifndef PDG_SCREEN_LDS_COORDS
+#define PDG_SCREEN_LDS_COORDS 0
+#endif
 constexpr int kThreads = 256;
-constexpr int kQPerBlock = 256;     // 4 waves x 2 blocks of 32 queries
-constexpr int kCTile = 256;         // candidates per LDS tile
+constexpr int kQB = PDG_SCREEN_QB;  // 32-query blocks per wave
+constexpr int kQPerBlock = 4 * 32 * kQB;
+constexpr int kCTile = PDG_SCREEN_TILE;   // candidates per LDS tile
+constexpr int kPerThread = kCTile / kThreads;
+constexpr bool kLdsCoords = PDG_SCREEN_LDS_COORDS != 0;   // re-rank coordinates in LDS
 constexpr float kEpsAB = 3e-5f, kEpsSq = 2e-6f, kEpsAbs = 1e-6f;
 constexpr float kRelSlack = 1.0f + 1.0f / 1048576.0f;   // 1 + 2^-20
 
@@ -121,7 +137,8 @@ __device__ __forceinline__ int out_row(int r, int lane) {
 }
 
 __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, int cbase, int nc,
-                                         const float4 *__restrict__ lc) {
+                                         const float4 *__restrict__ lc,
+                                         const float *__restrict__ cx, long long ldc) {
   float m = fminf(fminf(v[0], v[1]), v[2]);
   m = fminf(fminf(m, v[3]), v[4]);
   m = fminf(fminf(m, v[5]), v[6]);
@@ -131,19 +148,64 @@ __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, i
   m = fminf(fminf(m, v[13]), v[14]);
   m = fminf(m, v[15]);
   if (!(m <= s.thr)) return;
+  // rare path: rows whose screened value passes the current threshold (the
+  // threshold only tightens below, so re-ranking all of them is safe)
+  unsigned mask = 0;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < 16; ++r) mask |= (v[r] <= s.thr ? 1u : 0u) << r;
+  while (mask) {
+    const int r = __builtin_ctz(mask);
+    mask &= mask - 1;
     const int row = out_row(r, lane);
     const int c = cbase + row;
-    if (v[r] <= s.thr && c < nc) {       // padded rows (c >= nc) never count
+    if (c >= nc) continue;             // padded rows never count
+    float d;
+    if (kLdsCoords) {
       const float4 p = lc[row];
-      const float d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
-      if (d < s.best || (d == s.best && c < s.idx)) {
-        s.best = d;
-        s.idx = c;
-        set_thr(s);
-      }
+      d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
+    } else {
+      d = d2_contract(s.x, s.y, s.z, cx[c], cx[ldc + c], cx[2 * ldc + c]);
     }
+    if (d < s.best || (d == s.best && c < s.idx)) {
+      s.best = d;
+      s.idx = c;
+      set_thr(s);
+    }
+  }
+}
+
+// this thread's share of a tile: packed rows of candidates c0 + tid + k*256
+struct TileRegs {
+  uint4 w[kPerThread][2];
+  float4 p[kLdsCoords ? kPerThread : 1];
+};
+
+__device__ __forceinline__ void fetch_tile(const ScreenJob &J, int c0, TileRegs &t) {
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int c = c0 + k * kThreads + (int)threadIdx.x;
+    if (c < J.nc) {
+      t.w[k][0] = J.pack[2ll * c];
+      t.w[k][1] = J.pack[2ll * c + 1];
+      if (kLdsCoords) {
+        const long long nc = J.nc;
+        t.p[k] = make_float4(J.c[c], J.c[nc + c], J.c[2 * nc + c], 0.f);
+      }
+    } else {
+      t.w[k][0] = make_uint4(0u, 0u, 0u, 0u);
+      t.w[k][1] = make_uint4(0x7F800000u, 0u, 0u, 0u);   // n_hi = +inf: S = +inf
+      if (kLdsCoords) t.p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+}
+
+__device__ __forceinline__ void store_tile(const TileRegs &t, uint4 *spack, float4 *scoord) {
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int i = k * kThreads + (int)threadIdx.x;
+    spack[2 * i] = t.w[k][0];
+    spack[2 * i + 1] = t.w[k][1];
+    if (kLdsCoords) scoord[i] = t.p[k];
   }
 }
 
@@ -152,17 +214,17 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
   const ScreenJob J = jobs[blockIdx.y];
   const int q0 = blockIdx.x * kQPerBlock;
   if (q0 >= J.nq) return;
-  __shared__ uint4 spack[kCTile * 2];
-  __shared__ float4 scoord[kCTile];
+  __shared__ uint4 spack[2][kCTile * 2];
+  __shared__ float4 scoord[2][kLdsCoords ? kCTile : 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int half = lane >> 5;
   const long long nq = J.nq, nc = J.nc;
   const float cmax = __uint_as_float(*J.maxnorm);
-  QState st[2];
-  bf16x8 bq[2];
+  QState st[kQB];
+  bf16x8 bq[kQB];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int q = q0 + wv * 64 + h * 32 + (lane & 31);
+  for (int h = 0; h < kQB; ++h) {
+    const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);
     QState &s = st[h];
     const bool ok = q < J.nq;
     s.x = ok ? J.q[q] : 0.f;
@@ -196,37 +258,33 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
       bq[h][e] = *reinterpret_cast<const __bf16 *>(&b);
     }
   }
-  const uint4 far0 = make_uint4(0u, 0u, 0u, 0u);
-  const uint4 far1 = make_uint4(0x7F800000u, 0u, 0u, 0u);   // n_hi = +inf: S = +inf
+  TileRegs regs;
+  fetch_tile(J, 0, regs);
+  store_tile(regs, spack[0], scoord[0]);
+  int buf = 0;
   for (int c0 = 0; c0 < J.nc; c0 += kCTile) {
-    __syncthreads();
-    {
-      const int c = c0 + tid;
-      if (c < J.nc) {
-        spack[2 * tid] = J.pack[2ll * c];
-        spack[2 * tid + 1] = J.pack[2ll * c + 1];
-        scoord[tid] = make_float4(J.c[c], J.c[nc + c], J.c[2 * nc + c], 0.f);
-      } else {
-        spack[2 * tid] = far0;
-        spack[2 * tid + 1] = far1;
-        scoord[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-    }
-    __syncthreads();
+    __syncthreads();                      // tile c0 is in spack[buf]; spack[buf^1] is free
+    const bool more = c0 + kCTile < J.nc;
+    if (more) fetch_tile(J, c0 + kCTile, regs);   // in flight while this tile is screened
     const int left = (J.nc - c0 + 31) / 32;
     const int nsub = left < kCTile / 32 ? left : kCTile / 32;
     for (int sub = 0; sub < nsub; ++sub) {
-      const uint4 raw = spack[2 * (sub * 32 + (lane & 31)) + half];
+      const uint4 raw = spack[buf][2 * (sub * 32 + (lane & 31)) + half];
       const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
       const f32x16 z = {};
-      const f32x16 v0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[0], z, 0, 0, 0);
-      const f32x16 v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[1], z, 0, 0, 0);
-      consider(st[0], v0, lane, c0 + sub * 32, J.nc, scoord + sub * 32);
-      consider(st[1], v1, lane, c0 + sub * 32, J.nc, scoord + sub * 32);
+      f32x16 v[kQB];
+#pragma unroll
+      for (int h = 0; h < kQB; ++h)
+        v[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < kQB; ++h)
+        consider(st[h], v[h], lane, c0 + sub * 32, J.nc, scoord[buf] + sub * 32, J.c, nc);
     }
+    if (more) store_tile(regs, spack[buf ^ 1], scoord[buf ^ 1]);
+    buf ^= 1;
   }
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < kQB; ++h) {
     QState &s = st[h];
     const float ob = __shfl_xor(s.best, 32, 64);
     const int oi = __shfl_xor(s.idx, 32, 64);
@@ -234,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
       s.best = ob;
       s.idx = oi;
     }
-    const int q = q0 + wv * 64 + h * 32 + (lane & 31);
+    const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);
     if (half == 0 && q < J.nq) J.nn[q] = s.idx;
   }
 }

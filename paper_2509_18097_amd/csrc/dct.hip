@@ -39,12 +39,23 @@ struct PassArgs {
   float lam;
 };
 
-template <int NB>
+// NB: output blocks of 32 (R <= 32 NB); LDSM: stage the R x R operand in LDS.
+// Inputs are fetched kChunk K-steps at a time (independent loads in flight)
+// before the matching MFMAs.
+constexpr int kChunk = 16;
+
+template <int NB, bool LDSM>
 __global__ __launch_bounds__(kThreads) void dct_pass_kernel(PassArgs a) {
+  extern __shared__ float smt[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int j = lane & 31, h = lane >> 5;
   const int R = a.R;
+  if (LDSM) {
+    for (int i = threadIdx.x; i < R * R; i += kThreads) smt[i] = a.mt[i];
+    __syncthreads();
+  }
+  const float *mt = LDSM ? smt : a.mt;
   const long long R2 = (long long)R * R, R3 = R2 * R;
   const long long line = ((long long)blockIdx.x * 4 + wv) * 32 + j;
   const bool valid = line < a.lines;
@@ -73,24 +84,35 @@ __global__ __launch_bounds__(kThreads) void dct_pass_kernel(PassArgs a) {
   f32x16 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = (f32x16){};
-  for (int k0 = 0; k0 < R; k0 += 2) {
-    const int xin = k0 + h;
-    float in = 0.f;
-    if (valid && xin < R) {
-      in = a.g[base + xin * E];
-      if (a.scale) {
-        const float d = 1.0f + a.lam * (sfix + a.mu[xin]);
-        in = in / (d * d);
+  for (int k0 = 0; k0 < R; k0 += 2 * kChunk) {
+    float in[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) {
+      const int xin = k0 + 2 * c + h;
+      in[c] = (valid && xin < R) ? a.g[base + xin * E] : 0.f;
+    }
+    if (a.scale) {
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        const int xin = k0 + 2 * c + h;
+        if (xin < R) {
+          const float d = 1.0f + a.lam * (sfix + a.mu[xin]);
+          in[c] = in[c] / (d * d);
+        }
       }
     }
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int ko = b * 32 + j;
-      const float m = (xin < R && ko < R) ? a.mt[(long long)xin * R + ko] : 0.f;
-      if (a.axis == 0)
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(in, m, acc[b], 0, 0, 0);
-      else
-        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(m, in, acc[b], 0, 0, 0);
+    for (int c = 0; c < kChunk; ++c) {
+      const int xin = k0 + 2 * c + h;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int ko = b * 32 + j;
+        const float m = (xin < R && ko < R) ? mt[xin * R + ko] : 0.f;
+        if (a.axis == 0)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(in[c], m, acc[b], 0, 0, 0);
+        else
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(m, in[c], acc[b], 0, 0, 0);
+      }
     }
   }
   // D[i][jj]: lane holds rows i = 8 (r/4) + 4 h + (r%4), column jj = lane & 31
@@ -137,7 +159,12 @@ __global__ void dct_basis_kernel(int R, float *c, float *ct, float *mu) {
 template <int NB>
 pdg_status launch_pass(const PassArgs &a, hipStream_t st) {
   const long long blocks = (a.lines + 127) / 128;
-  dct_pass_kernel<NB><<<(unsigned)blocks, kThreads, 0, st>>>(a);
+  if (a.R <= 128) {
+    const size_t shmem = (size_t)a.R * a.R * sizeof(float);
+    dct_pass_kernel<NB, true><<<(unsigned)blocks, kThreads, shmem, st>>>(a);
+  } else {
+    dct_pass_kernel<NB, false><<<(unsigned)blocks, kThreads, 0, st>>>(a);
+  }
   return launched("dct_pass");
 }
 
