@@ -163,8 +163,9 @@ def cg_bytes(prob):
 
 
 def dct_flops(prob):
-    """Matrix-core flops of one DCT preconditioner stage: six passes, each a
-    length-R contraction (2R flops) per grid value; R = 1 levels are skipped."""
+    """Matrix-core flops of one DCT preconditioner stage: six 1-D transforms
+    (three forward, three inverse), each a length-R contraction (2R flops) per
+    grid value; R = 1 levels are skipped."""
     T = prob.T
     return sum(6 * 2 * r * T * 3 * r ** 3 for r in prob.res if r > 1)
 
@@ -191,7 +192,7 @@ def roofline(prob, stages, chamfer, precond):
         a = f / (pre_ms * 1e-3) / 1e12
         pre = {"bound": "mfma", "achieved": round(a, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                "unit": "TFLOP/s", "frac": round(a / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-               "kernel": "dct_pass_kernel (24 launches) + gradient copy",
+               "kernel": "dct_plane_kernel x2 + dct_pencil_kernel per level (12 launches)",
                "flops_per_stage": f, "stage_ms": round(pre_ms, 4)}
     else:
         b = cg_bytes(prob)

@@ -511,8 +511,9 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
                              p.tvals, p.sort, false, st));
       return PDG_OK;
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
+      if (p.d.precond_method == PDG_PRECOND_DCT)
+        return run_dct(g, (int)T, p.lambda_l, p.grad, p.pgrad, p.dctws, st);
       PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
-      if (p.d.precond_method == PDG_PRECOND_DCT) return run_dct(g, (int)T, p.lambda_l, p.pgrad, p.dctws, st);
       return run_cg(p.cg, p.pgrad, T * P, p.cgws, st);
     case PDG_STAGE_ADAM:  // Sec. 3.6
       return launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
@@ -775,7 +776,7 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
   const GridDev gd = make_grid(*d);
   if (method == PDG_PRECOND_DCT) {
     PDG_TRY(dct_basis(gd, ws, stream));
-    return run_dct(gd, batch, lambda, g, ws, stream);
+    return run_dct(gd, batch, lambda, g, g, ws, stream);
   }
   const bool aligned16 = ((uintptr_t)g & 15) == 0;
   CGPlanDev p = cg_plan(gd, batch, lambda, iters, tol, aligned16);

@@ -185,8 +185,9 @@ pdg_status run_cg(const CGPlanDev &plan, float *g, long long floats, void *ws, h
 // dct.hip: exact (I + lam L)^-2 by the separable DCT-II (R <= 256)
 size_t dct_bytes(const GridDev &g);
 pdg_status dct_basis(const GridDev &g, void *ws, hipStream_t st);
-pdg_status run_dct(const GridDev &g, int batch, const float *lam, float *data, const void *ws,
-                   hipStream_t st);
+// src -> data (src may equal data)
+pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *src, float *data,
+                   const void *ws, hipStream_t st);
 
 // optim.hip
 struct AdamLevels {
