@@ -128,31 +128,44 @@ pdg_status need(const void *p, const char *name) {
 // ------------------------------------------------------ deform backward --
 struct DeformBwdWs {
   uint32_t *keys, *vals;
+  int *pstart;
   void *sort;
 };
-DeformBwdWs deform_bwd_layout(Carve &c, int levels, long long n) {
+DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
   DeformBwdWs w;
-  const long long ne = (long long)levels * n;
+  const long long ne = (long long)g.levels * n;
   w.keys = c.take<uint32_t>(ne);
   w.vals = c.take<uint32_t>(ne);
+  w.pstart = c.take<int>(row_count(g) + 1);
   w.sort = c.take<char>((long long)radix_sort_bytes(ne));
   return w;
 }
 
-// Deterministic grid scatter of `segs` sample segments with S samples each.
-pdg_status grid_scatter(const GridDev &g, const float *x, long long xstride, long long ldx,
-                        long long S, int segs, const float *lam, long long lstride, long long ldl,
-                        float *grad, uint32_t *keys, uint32_t *vals, void *sort, bool keys_ready,
-                        hipStream_t st) {
-  const long long nent = (long long)segs * g.levels * S;
-  if (!keys_ready) {
-    PDG_TRY(launch_scatter_keys(g, x, xstride, ldx, S, segs, keys, vals, st));
-    PDG_TRY(radix_sort(keys, vals, nent, 32, sort, st));
-  }
-  for (int cls = 0; cls < 8; ++cls)
-    PDG_TRY(launch_scatter_pass(g, cls, keys, vals, nent, S, x, xstride, ldx, lam, lstride, ldl,
-                                grad, st));
-  return PDG_OK;
+// Builds the sorted entries and plane table of one scatter list (skipped for
+// lists whose sample positions never change).
+pdg_status scatter_entries(const GridDev &g, int segs, const ScatterList &L, uint32_t *keys,
+                           uint32_t *vals, int *pstart, void *sort, hipStream_t st) {
+  const long long nent = (long long)segs * g.levels * L.S;
+  PDG_TRY(launch_scatter_keys(g, L.x, L.xstride, L.ldx, L.S, segs, keys, vals, st));
+  PDG_TRY(radix_sort(keys, vals, nent, 32, sort, st));
+  return launch_row_table(g, keys, nent, segs, pstart, st);
+}
+
+ScatterList scatter_list(const uint32_t *keys, const uint32_t *vals, const int *pstart,
+                         long long S, const float *x, long long xstride, long long ldx,
+                         const float *lam, long long lstride, long long ldl) {
+  ScatterList L;
+  L.keys = keys;
+  L.vals = vals;
+  L.pstart = pstart;
+  L.S = S;
+  L.x = x;
+  L.xstride = xstride;
+  L.ldx = ldx;
+  L.lam = lam;
+  L.lstride = lstride;
+  L.ldl = ldl;
+  return L;
 }
 
 // --------------------------------------------------------------- chamfer --
@@ -268,6 +281,7 @@ struct pdg_problem {
   double *losses = nullptr, *w = nullptr, *wconf = nullptr, *terms = nullptr;
   double *partials = nullptr, *iso_partials = nullptr;
   uint32_t *pkeys = nullptr, *pvals = nullptr, *tkeys = nullptr, *tvals = nullptr;
+  int *pstart_p = nullptr, *pstart_t = nullptr;   // row tables (points, template)
   uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
   void *sort = nullptr;
   NNJob *jobs = nullptr;
@@ -335,9 +349,8 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   PDG_TRY(check_precond_args(&pd->grid, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
   const GridDev g = make_grid(pd->grid);
   const long long T = pd->frames - 1;
-  if ((unsigned long long)T * g.nodes >= (1ull << kScatterClassShift)) {
-    set_error("T * nodes = %lld does not fit the 29-bit node field of the scatter keys",
-              T * g.nodes);
+  if ((unsigned long long)T * g.nodes >= (1ull << 32)) {
+    set_error("T * nodes = %lld does not fit the 32-bit scatter keys", T * g.nodes);
     return PDG_EINVAL;
   }
   if ((unsigned long long)T * g.levels * (pd->n > pd->verts ? pd->n : pd->verts) >= (1ull << 31)) {
@@ -376,6 +389,8 @@ void layout(pdg_problem &p, Carve &c) {
   p.pvals = c.take<uint32_t>(T * L * N);
   p.tkeys = c.take<uint32_t>(T * L * V);
   p.tvals = c.take<uint32_t>(T * L * V);
+  p.pstart_p = c.take<int>(T * row_count(p.g) + 1);
+  p.pstart_t = c.take<int>(T * row_count(p.g) + 1);
   p.nrev = T * N * (p.has_tm ? 2 : 1);
   p.rkeys = c.take<uint32_t>(p.nrev);
   p.rvals = c.take<uint32_t>(p.nrev);
@@ -502,14 +517,19 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
                                        p.lam + (k - 1) * 3 * V, V, V, st));
       }
       return PDG_OK;
-    case PDG_STAGE_SCATTER:  // dL/dG: deterministic transpose of Eq. 1
-      PDG_TRY(launch_fill(p.grad, T * P, 0.f, st));
-      PDG_TRY(grid_scatter(g, p.d.points, 3 * N, N, N, (int)T, p.gphat, 3 * N, N, p.grad,
-                           p.pkeys, p.pvals, p.sort, true, st));
-      if (p.has_tm)
-        PDG_TRY(grid_scatter(g, p.xhat, 3 * V, V, V, (int)T, p.lam, 3 * V, V, p.grad, p.tkeys,
-                             p.tvals, p.sort, false, st));
-      return PDG_OK;
+    case PDG_STAGE_SCATTER: {  // dL/dG: deterministic transpose of Eq. 1
+      ScatterLists sl;
+      sl.count = 1;
+      sl.list[0] = scatter_list(p.pkeys, p.pvals, p.pstart_p, N, p.d.points, 3 * N, N, p.gphat,
+                                3 * N, N);
+      if (p.has_tm) {
+        sl.list[1] = scatter_list(p.tkeys, p.tvals, p.pstart_t, V, p.xhat, 3 * V, V, p.lam,
+                                  3 * V, V);
+        sl.count = 2;
+        PDG_TRY(scatter_entries(g, (int)T, sl.list[1], p.tkeys, p.tvals, p.pstart_t, p.sort, st));
+      }
+      return launch_gather(g, (int)T, sl, p.grad, st);
+    }
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
       if (p.d.precond_method == PDG_PRECOND_DCT)
         return run_dct(g, (int)T, p.lambda_l, p.grad, p.pgrad, p.dctws, st);
@@ -566,7 +586,7 @@ pdg_status pdg_deform_backward_workspace(const pdg_grid_desc *d, int64_t n, size
     return PDG_EINVAL;
   }
   Carve c(nullptr);
-  deform_bwd_layout(c, d->levels, n);
+  deform_bwd_layout(c, make_grid(*d), n);
   *bytes = c.off;
   return PDG_OK;
 }
@@ -581,7 +601,7 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
   }
   const GridDev g = make_grid(*d);
   if ((long long)d->levels * n >= (1ll << 31) ||
-      (unsigned long long)g.nodes >= (1ull << kScatterClassShift)) {
+      (unsigned long long)g.nodes >= (1ull << 32)) {
     set_error("problem too large for 32-bit scatter entries");
     return PDG_EINVAL;
   }
@@ -593,14 +613,18 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
   }
   if (ggrids) {
     Carve probe(nullptr);
-    deform_bwd_layout(probe, d->levels, n);
+    deform_bwd_layout(probe, g, n);
     PDG_TRY(need_ws(ws, ws_bytes, probe.off));
     Carve c(ws);
-    DeformBwdWs w = deform_bwd_layout(c, d->levels, n);
-    PDG_TRY(launch_fill(ggrids, g.size, 0.f, stream));
-    if (n > 0)
-      PDG_TRY(grid_scatter(g, x, 0, n, n, 1, gout, 0, n, ggrids, w.keys, w.vals, w.sort, false,
-                           stream));
+    DeformBwdWs w = deform_bwd_layout(c, g, n);
+    ScatterLists sl;
+    memset(&sl, 0, sizeof sl);
+    if (n > 0) {
+      sl.count = 1;
+      sl.list[0] = scatter_list(w.keys, w.vals, w.pstart, n, x, 0, n, gout, 0, n);
+      PDG_TRY(scatter_entries(g, 1, sl.list[0], w.keys, w.vals, w.pstart, w.sort, stream));
+    }
+    PDG_TRY(launch_gather(g, 1, sl, ggrids, stream));
   }
   if (gx && n > 0)
     PDG_TRY(launch_chain_adjoint(g, grids, x, n, gout, n, nullptr, 0, gx, n, n, stream));
@@ -950,9 +974,9 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     return s;
   }
   // static scatter entries of the input points (fixed positions)
-  pdg_status s = launch_scatter_keys(p->g, pd->points, 3 * N, N, N, (int)T, p->pkeys, p->pvals, stream);
-  if (s == PDG_OK)
-    s = radix_sort(p->pkeys, p->pvals, T * p->g.levels * N, 32, p->sort, stream);
+  pdg_status s = scatter_entries(
+      p->g, (int)T, scatter_list(p->pkeys, p->pvals, p->pstart_p, N, pd->points, 3 * N, N, nullptr, 0, 0),
+      p->pkeys, p->pvals, p->pstart_p, p->sort, stream);
   if (s == PDG_OK && p->has_tm)
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);

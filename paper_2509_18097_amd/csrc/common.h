@@ -62,6 +62,15 @@ __device__ __forceinline__ void stencil1(int R, float s, int &i0, float &f, bool
   f = u - (float)i;
 }
 
+// Weight of corner k (bit 0: +x, bit 1: +y, bit 2: +z) of the trilinear
+// stencil with fractions (fx, fy, fz).
+__device__ __forceinline__ float corner_weight(int k, float fx, float fy, float fz) {
+  const float wx = (k & 1) ? fx : 1.0f - fx;
+  const float wy = (k & 2) ? fy : 1.0f - fy;
+  const float wz = (k & 4) ? fz : 1.0f - fz;
+  return (wx * wy) * wz;
+}
+
 inline unsigned div_up(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
 // ------------------------------------------------------------ radix sort --
@@ -83,25 +92,44 @@ pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const floa
                                 const float *lam, long long ldl, const float *gdir, long long ldd,
                                 float *lam_out, long long ldo, long long n, hipStream_t st);
 // Entry keys for the deterministic grid scatter: for sample s of segment
-// seg and level l (entry e = (seg*L + l)*S + s) the key is the parity class of
-// its base cell (bits 29..31) above the global node id of the base cell,
-// seg*nodes + noff[l] + cell (which must stay below 2^29).
-constexpr int kScatterClassShift = 29;
+// seg and level l (entry e = (seg*L + l)*S + s) the key is the global node id
+// of the base cell, seg*nodes + noff[l] + cell (below 2^32), the value e.
 pdg_status launch_scatter_keys(const GridDev &g, const float *x, long long xstride, long long ldx,
                                long long S, int segs, uint32_t *keys, uint32_t *vals,
                                hipStream_t st);
+// Cell rows per segment: RS2 = R_0^2 + ... + R_{L-1}^2.
+long long row_count(const GridDev &g);
+// Row table of sorted keys: rstart[q], q = 0..segs*RS2, is the first entry of
+// row q = seg*RS2 + R_0^2 + ... + R_{l-1}^2 + z*R + y ((z, y) of the base
+// cell) or later.
+pdg_status launch_row_table(const GridDev &g, const uint32_t *keys, long long nent, int segs,
+                            int *rstart, hipStream_t st);
 pdg_status launch_fill(float *p, long long count, float value, hipStream_t st);
 pdg_status launch_copy(float *dst, const float *src, long long count, hipStream_t st);
 // Upload up to 2 KB of host bytes to device memory in stream order (the bytes
 // travel as a kernel argument, so the call is safe under graph capture).
 pdg_status upload_small(void *dst, const void *src, size_t bytes, hipStream_t st);
-// One parity-class pass of the scatter over sorted entries: every run of
-// equal keys of class `cls` adds level_scale * sum_s w_k(s) * lam(s) to its
-// 8 corner nodes k.
-pdg_status launch_scatter_pass(const GridDev &g, int cls, const uint32_t *keys,
-                               const uint32_t *vals, long long nent, long long S, const float *x,
-                               long long xstride, long long ldx, const float *lam,
-                               long long lstride, long long ldl, float *grad, hipStream_t st);
+// One list of sorted scatter entries (S samples per segment) and the values
+// scattered: sample s of segment seg sits at x[seg*xstride + c*ldx + s] and
+// carries lam[seg*lstride + c*ldl + s], c = 0..2.
+struct ScatterList {
+  const uint32_t *keys, *vals;
+  const int *pstart;           // row table of the keys
+  long long S;
+  const float *x;
+  long long xstride, ldx;
+  const float *lam;
+  long long lstride, ldl;
+};
+struct ScatterLists {
+  ScatterList list[2];
+  int count;
+};
+// grad = level_scale * sum_s w_k(s) lam(s) over the samples s of every list
+// that have node k as a corner of their base cell, for every node of `segs`
+// stacks (grad is overwritten; deterministic summation order).
+pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, float *grad,
+                         hipStream_t st);
 
 // chamfer.hip
 struct ChSeg {               // one (moving A, fixed B) Chamfer pair

@@ -117,11 +117,10 @@ __global__ __launch_bounds__(256) void chain_adjoint_kernel(
   lo[2 * ldo + i] = r2;
 }
 
-// Key of a scatter entry: the parity class of its base cell (3 bits) above
-// the global node id of the base cell.  Runs of one class have disjoint
-// 2x2x2 corner sets, so a class can be scattered in one pass without
-// conflicts; the classes run in a fixed order, which fixes the summation order
-// at every node.
+// Key of a scatter entry: the global node id of its base cell,
+// seg*nodes + noff[l] + cell.  Sorted keys put the entries of one
+// (segment, level, cell plane) next to each other and runs of equal keys
+// gather the samples of one cell.
 __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const float *__restrict__ x,
                                                            long long xstride, long long ldx,
                                                            long long S, uint32_t *__restrict__ keys,
@@ -134,7 +133,6 @@ __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const floa
   for (int l = 0; l < g.levels; ++l) {
     const int R = g.res[l];
     long long cell = 0;
-    uint32_t cls = 0;
     if (R > 1) {
       int ix, iy, iz;
       float f;
@@ -143,12 +141,36 @@ __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const floa
       stencil1(R, py, iy, f, in);
       stencil1(R, pz, iz, f, in);
       cell = ((long long)iz * R + iy) * R + ix;
-      cls = (uint32_t)((ix & 1) | ((iy & 1) << 1) | ((iz & 1) << 2));
     }
     long long e = ((long long)seg * g.levels + l) * S + s;
-    keys[e] = (cls << kScatterClassShift) | (uint32_t)(seg * g.nodes + g.noff[l] + cell);
+    keys[e] = (uint32_t)(seg * g.nodes + g.noff[l] + cell);
     vals[e] = (uint32_t)e;
   }
+}
+
+// Row index of a key: seg * RS2 + (R_0^2 + ... + R_{l-1}^2) + z * R + y of
+// the base cell (z, y, x).
+__device__ __forceinline__ long long key_row(const GridDev &g, uint32_t key, long long RS2) {
+  const long long seg = key / g.nodes;
+  const long long rem = key - seg * g.nodes;
+  int l = g.levels - 1;
+  while (l > 0 && g.noff[l] > rem) --l;
+  long long roff = 0;
+  for (int k = 0; k < l; ++k) roff += (long long)g.res[k] * g.res[k];
+  return seg * RS2 + roff + (rem - g.noff[l]) / g.res[l];
+}
+
+// rstart[q] = first sorted entry whose row index is >= q, q = 0..nrows
+// (rstart[nrows] = nent): thread i writes the table slots between the row of
+// entry i-1 and the row of entry i.
+__global__ __launch_bounds__(256) void row_table_kernel(GridDev g, const uint32_t *__restrict__ keys,
+                                                        long long nent, long long RS2,
+                                                        long long nrows, int *__restrict__ rstart) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > nent) return;
+  const long long cur = i < nent ? key_row(g, keys[i], RS2) : nrows;
+  const long long prev = i > 0 ? key_row(g, keys[i - 1], RS2) : -1;
+  for (long long q = prev + 1; q <= cur; ++q) rstart[q] = (int)i;
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ p, long long n, float v) {
@@ -173,63 +195,179 @@ __global__ void upload_kernel(Blob blob, unsigned char *__restrict__ dst, int n)
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = blob.b[i];
 }
 
-// One parity class: the first entry of every run of that class sums
-// w_corner(s) * lam(s) over its samples for all 8 corners and adds
-// level_scale times the sums to the 8 corner nodes.
-__global__ __launch_bounds__(256) void scatter_pass_kernel(
-    GridDev g, int cls, const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-    long long nent, long long S, const float *__restrict__ x, long long xstride, long long ldx,
-    const float *__restrict__ lam, long long lstride, long long ldl, float *__restrict__ grad) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nent) return;
-  const uint32_t key = keys[i];
-  if ((int)(key >> kScatterClassShift) != cls) return;
-  if (i > 0 && keys[i - 1] == key) return;  // only the first entry of a run works
-  const uint32_t e0 = vals[i];
-  const long long segl = (long long)e0 / S;
-  const int seg = (int)(segl / g.levels);
-  const int l = (int)(segl % g.levels);
-  const int R = g.res[l];
-  const float *X = x + seg * xstride;
-  const float *Lm = lam + seg * lstride;
-  float a[8][3];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) a[k][0] = a[k][1] = a[k][2] = 0.f;
-  for (long long j = i; j < nent && keys[j] == key; ++j) {
-    const long long s = (long long)vals[j] % S;
-    const float l0 = Lm[s], l1 = Lm[ldl + s], l2 = Lm[2 * ldl + s];
-    if (R > 1) {
-      int ii;
-      float fx, fy, fz;
-      bool in;
-      stencil1(R, X[s], ii, fx, in);
-      stencil1(R, X[ldx + s], ii, fy, in);
-      stencil1(R, X[2 * ldx + s], ii, fz, in);
-      const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
-      const float w[8] = {gx * gy * gz, fx * gy * gz, gx * fy * gz, fx * fy * gz,
-                          gx * gy * fz, fx * gy * fz, gx * fy * fz, fx * fy * fz};
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        a[k][0] += w[k] * l0;
-        a[k][1] += w[k] * l1;
-        a[k][2] += w[k] * l2;
+// Gather form of the scatter: one block per (segment, level, node plane z,
+// band of node rows y0..y1-1) writes all three channels of that band, every
+// node exactly once (no zero fill, no read-modify-write in HBM).
+//
+// The band's nodes are corners of the cells in cell planes z-1 (corner
+// dz = 1) and z (dz = 0) with cell rows y0-1..y1-1; the row table gives the
+// entries of each (list, cell plane) as one contiguous range.  The ranges are
+// walked 256 entries at a time: every thread forms its entry's 12 products
+// w_k(s) * lam_c(s) (4 corners of its dz, 3 channels; exact in float64), a
+// segmented inclusive scan over the chunk in float64 (fixed Hillis-Steele
+// pattern, segments = runs of equal (range, key) pairs, which are contiguous
+// because every range is sorted) leaves each run's sums at its last
+// entry (a run cut by the chunk end hands its sums to the next chunk), and then, for each range (list, cell
+// plane) and each (x, y) parity class in turn with a barrier in between, the
+// runs that end there add level_scale times their sums to their corners inside
+// the band held in LDS.  The runs of one range and class belong to distinct
+// cells of one cell plane with equal (x, y) parity, so their corners are
+// disjoint; every step's order is fixed by the sorted entries, so the result
+// does not depend on scheduling.
+constexpr int kGatherThreads = 256;
+constexpr int kBandFloats = 2048;          // LDS floats per channel of a band
+constexpr unsigned long long kNoSeg = ~0ull;   // no (range, key) pair takes this value
+
+struct GatherPlan {
+  int levels;
+  int R[PDG_MAX_LEVELS];
+  int B[PDG_MAX_LEVELS];                   // node rows per band
+  int nb[PDG_MAX_LEVELS];                  // bands per plane
+  long long bfirst[PDG_MAX_LEVELS + 1];    // first block of each level
+  long long roff2[PDG_MAX_LEVELS];         // first row of each level in a segment
+  long long RS2;                           // rows per segment
+};
+
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, GatherPlan gp,
+                                                                ScatterLists sl,
+                                                                float *__restrict__ grad) {
+  __shared__ float band[3 * kBandFloats];
+  __shared__ double buf[12][kGatherThreads];
+  __shared__ unsigned long long skey[kGatherThreads + 1];   // (range << 32) | key
+  __shared__ double carry[2][12];
+  const long long blk = blockIdx.x;
+  int l = 0;
+  while (l + 1 < gp.levels && blk >= gp.bfirst[l + 1]) ++l;
+  const int R = gp.R[l], B = gp.B[l], nb = gp.nb[l];
+  const long long local = blk - gp.bfirst[l];
+  const int bi = (int)(local % nb);
+  const long long rest = local / nb;
+  const int z = (int)(rest % R);
+  const long long seg = rest / R;
+  const int y0 = bi * B, y1 = y0 + B < R ? y0 + B : R, rows = y1 - y0;
+  const int t = threadIdx.x;
+  const int band_n = rows * R;
+  for (int i = t; i < 3 * band_n; i += kGatherThreads) band[i] = 0.f;
+
+  // the (list, cell plane) ranges of this band, in a fixed order
+  __shared__ int rlo[4], rlen[4], rli[4], rdz[4], s_nr, s_total;
+  if (t == 0) {
+    int nr = 0, total = 0;
+    const int zc_max = R > 1 ? R - 2 : 0;
+    const int cy_lo = y0 > 0 ? y0 - 1 : 0, cy_hi = y1 - 1 < zc_max ? y1 - 1 : zc_max;
+    for (int li = 0; li < sl.count; ++li)
+      for (int pass = 0; pass < 2; ++pass) {
+        const int zc = z - 1 + pass;
+        if (zc < 0 || zc > zc_max || cy_lo > cy_hi) continue;
+        const long long row = seg * gp.RS2 + gp.roff2[l] + (long long)zc * R;
+        const int lo = sl.list[li].pstart[row + cy_lo], hi = sl.list[li].pstart[row + cy_hi + 1];
+        if (hi <= lo) continue;
+        rlo[nr] = lo;
+        rlen[nr] = hi - lo;
+        rli[nr] = li;
+        rdz[nr] = z - zc;
+        total += hi - lo;
+        ++nr;
       }
-    } else {
-      a[0][0] += l0;
-      a[0][1] += l1;
-      a[0][2] += l2;
-    }
+    s_nr = nr;
+    s_total = total;
   }
-  const long long cell =
-      (long long)(key & ((1u << kScatterClassShift) - 1u)) - (long long)seg * g.nodes - g.noff[l];
+  const long long kbase = seg * g.nodes + g.noff[l];
+  bool carried = false;
+  __syncthreads();
+  const int total = s_total, nr = s_nr;
+  for (int c0 = 0, chunk = 0; c0 < total; c0 += kGatherThreads, ++chunk) {
+    const int n = total - c0 < kGatherThreads ? total - c0 : kGatherThreads;
+    double p[12];
+    unsigned long long key = kNoSeg;
+    int my_range = -1;
+    if (t < n) {
+      int v = c0 + t, r = 0;
+      while (v >= rlen[r]) v -= rlen[r++];
+      const ScatterList &L = sl.list[rli[r]];
+      const int i = rlo[r] + v;
+      my_range = r;
+      key = ((unsigned long long)r << 32) | L.keys[i];
+      const uint32_t s = L.vals[i] % (uint32_t)L.S;
+      const float *X = L.x + seg * L.xstride;
+      const float *Lm = L.lam + seg * L.lstride;
+      float fx = 0.f, fy = 0.f, fz = 0.f;
+      if (R > 1) {
+        int ii;
+        bool in;
+        stencil1(R, X[s], ii, fx, in);
+        stencil1(R, X[L.ldx + s], ii, fy, in);
+        stencil1(R, X[2 * L.ldx + s], ii, fz, in);
+      }
+      const float lv[3] = {Lm[s], Lm[L.ldl + s], Lm[2 * L.ldl + s]};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float w = corner_weight(q | (rdz[r] << 2), fx, fy, fz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[4 * c + q] = (double)w * (double)lv[c];
+      }
+      if (t == 0 && carried) {
+#pragma unroll
+        for (int v2 = 0; v2 < 12; ++v2) p[v2] = carry[(chunk + 1) & 1][v2] + p[v2];
+      }
+      skey[t] = key;
+    }
+    if (t == 0) {
+      unsigned long long nk = kNoSeg;
+      if (c0 + n < total) {
+        int v = c0 + n, r = 0;
+        while (v >= rlen[r]) v -= rlen[r++];
+        nk = ((unsigned long long)r << 32) | sl.list[rli[r]].keys[rlo[r] + v];
+      }
+      skey[n] = nk;
+    }
+    __syncthreads();
+    for (int off = 1; off < n; off <<= 1) {
+      if (t < n) {
+#pragma unroll
+        for (int v2 = 0; v2 < 12; ++v2) buf[v2][t] = p[v2];
+      }
+      __syncthreads();
+      if (t < n && t >= off && skey[t - off] == key) {
+#pragma unroll
+        for (int v2 = 0; v2 < 12; ++v2) p[v2] = buf[v2][t - off] + p[v2];
+      }
+      __syncthreads();
+    }
+    const bool next_carried = skey[n - 1] == skey[n];
+    const bool last = t < n && skey[t + 1] != key;     // last entry of its run in this chunk
+    if (t == n - 1 && next_carried) {
+#pragma unroll
+      for (int v2 = 0; v2 < 12; ++v2) carry[chunk & 1][v2] = p[v2];
+    }
+    const int cell = last ? (int)((long long)(uint32_t)key - kbase) : 0;
+    const int cx = cell % R, cy = (cell / R) % R;
+    const int cls = last ? (cx & 1) | ((cy & 1) << 1) : -1;
+    for (int rr = 0; rr < nr; ++rr)
+      for (int cxy = 0; cxy < 4; ++cxy) {
+        if (cls == cxy && my_range == rr) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int x = cx + (q & 1), y = cy + (q >> 1);
+            if (x < R && y >= y0 && y < y1) {
+              const int o = (y - y0) * R + x;
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                band[c * band_n + o] = __fmaf_rn(g.scale, (float)p[4 * c + q], band[c * band_n + o]);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    carried = next_carried;
+  }
+  __syncthreads();
   const long long R2 = (long long)R * R, R3 = R2 * R;
-  float *Gd = grad + (long long)seg * g.size + g.off[l];
-  const int corners = R > 1 ? 8 : 1;
-  for (int k = 0; k < corners; ++k) {
-    const long long node = cell + (k & 1) + ((k >> 1) & 1) * R + ((k >> 2) & 1) * R2;
-    Gd[node] += g.scale * a[k][0];
-    Gd[R3 + node] += g.scale * a[k][1];
-    Gd[2 * R3 + node] += g.scale * a[k][2];
+  float *Gd = grad + seg * g.size + g.off[l] + (long long)z * R2 + (long long)y0 * R;
+  for (int i = t; i < band_n; i += kGatherThreads) {
+    Gd[i] = band[i];
+    Gd[R3 + i] = band[band_n + i];
+    Gd[2 * R3 + i] = band[2 * band_n + i];
   }
 }
 
@@ -292,14 +430,48 @@ pdg_status upload_small(void *dst, const void *src, size_t bytes, hipStream_t st
   return PDG_OK;
 }
 
-pdg_status launch_scatter_pass(const GridDev &g, int cls, const uint32_t *keys,
-                               const uint32_t *vals, long long nent, long long S, const float *x,
-                               long long xstride, long long ldx, const float *lam,
-                               long long lstride, long long ldl, float *grad, hipStream_t st) {
-  if (nent <= 0) return PDG_OK;
-  scatter_pass_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, cls, keys, vals, nent, S, x, xstride,
-                                                         ldx, lam, lstride, ldl, grad);
-  return launched("scatter_pass");
+long long row_count(const GridDev &g) {
+  long long rs = 0;
+  for (int l = 0; l < g.levels; ++l) rs += (long long)g.res[l] * g.res[l];
+  return rs;
+}
+
+pdg_status launch_row_table(const GridDev &g, const uint32_t *keys, long long nent, int segs,
+                            int *rstart, hipStream_t st) {
+  const long long RS2 = row_count(g);
+  row_table_kernel<<<div_up(nent + 1, 256), 256, 0, st>>>(g, keys, nent, RS2,
+                                                            (long long)segs * RS2, rstart);
+  return launched("row_table");
+}
+
+pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, float *grad,
+                         hipStream_t st) {
+  if (segs <= 0) return PDG_OK;
+  GatherPlan gp;
+  memset(&gp, 0, sizeof gp);
+  gp.levels = g.levels;
+  gp.RS2 = row_count(g);
+  long long blocks = 0, roff = 0;
+  for (int l = 0; l < g.levels; ++l) {
+    const int R = g.res[l];
+    int B = kBandFloats / R;
+    if (B < 1) B = 1;
+    if (B > R) B = R;
+    gp.R[l] = R;
+    gp.B[l] = B;
+    gp.nb[l] = (R + B - 1) / B;
+    gp.bfirst[l] = blocks;
+    gp.roff2[l] = roff;
+    blocks += (long long)segs * R * gp.nb[l];
+    roff += (long long)R * R;
+  }
+  gp.bfirst[g.levels] = blocks;
+  if (blocks >= (1ll << 31)) {
+    set_error("grid gather needs %lld blocks (limit 2^31)", blocks);
+    return PDG_EINVAL;
+  }
+  gather_kernel<<<(unsigned)blocks, kGatherThreads, 0, st>>>(g, gp, sl, grad);
+  return launched("gather");
 }
 
 }  // namespace pdg
