@@ -268,11 +268,14 @@ pdg_status pdg_problem_destroy(pdg_problem *p);
  *   PDG_BUF_GPHAT  float [T][3][n]   dL/dP^_t
  *   PDG_BUF_GXHAT  float [T][3][V]   direct dL/dX_t (Chamfer + isometry), frames 1..T
  *   PDG_BUF_TERMS  double[8]         the loss terms of pdg_step
- *   PDG_BUF_LAM    float [T][3][V]   total dL/dX_t after the reverse sweep of Eq. 8 */
+ *   PDG_BUF_LAM    float [T][3][V]   total dL/dX_t after the reverse sweep of Eq. 8
+ *   PDG_BUF_SCREEN_TILES uint64[1]   256 x 256 candidate tiles screened by the
+ *                  bf16 screen, summed over every step since creation (0 bytes
+ *                  for the float32 mode) */
 typedef enum {
   PDG_BUF_PHAT = 0, PDG_BUF_XHAT = 1, PDG_BUF_NN = 2, PDG_BUF_LOSSES = 3,
   PDG_BUF_WCONF = 4, PDG_BUF_GRAD = 5, PDG_BUF_PGRAD = 6, PDG_BUF_GPHAT = 7,
-  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9, PDG_BUF_LAM = 10
+  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9, PDG_BUF_LAM = 10, PDG_BUF_SCREEN_TILES = 11
 } pdg_buffer;
 pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes);
 

@@ -20,7 +20,7 @@ CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1}
 PRECOND_METHODS = {"cg": 0, "dct": 1}
 STAGES = ("warp", "nn", "loss", "grad", "scatter", "precond", "adam")
 BUFFERS = {"phat": 0, "xhat": 1, "nn": 2, "losses": 3, "wconf": 4, "grad": 5, "pgrad": 6,
-           "gphat": 7, "gxhat": 8, "terms": 9, "lam": 10}
+           "gphat": 7, "gxhat": 8, "terms": 9, "lam": 10, "screen_tiles": 11}
 
 
 class PdgError(RuntimeError):

@@ -169,6 +169,37 @@ ScatterList scatter_list(const uint32_t *keys, const uint32_t *vals, const int *
 }
 
 // --------------------------------------------------------------- chamfer --
+ScreenSet screen_set(const float *x, long long n, const int *perm, uint4 *pack, float4 *coords,
+                     float4 *boxes, unsigned *maxnorm) {
+  ScreenSet S;
+  memset(&S, 0, sizeof S);
+  S.x = x;
+  S.n = (int)n;
+  S.perm = perm;
+  S.pack = pack;
+  S.coords = coords;
+  S.boxes = boxes;
+  S.maxnorm = maxnorm;
+  return S;
+}
+// queries from set Q, candidates from set C
+ScreenJob screen_job(const ScreenSet &Q, const ScreenSet &C, int *nn, unsigned long long *tiles) {
+  ScreenJob J;
+  memset(&J, 0, sizeof J);
+  J.c = C.x;
+  J.q = Q.coords;
+  J.qboxes = Q.boxes;
+  J.nq = Q.n;
+  J.nc = C.n;
+  J.nn = nn;
+  J.pack = C.pack;
+  J.cc = C.coords;
+  J.cboxes = C.boxes;
+  J.maxnorm = C.maxnorm;
+  J.tiles = tiles;
+  return J;
+}
+
 struct ChamferWs {
   NNJob *jobs;
   ChSeg *segs;
@@ -179,6 +210,8 @@ struct ChamferWs {
   ScreenSet *ssets;
   ScreenJob *sjobs;
   uint4 *pack_a, *pack_b;
+  float4 *coords_a, *coords_b, *boxes_a, *boxes_b;
+  uint32_t *perm_a, *perm_b;
   unsigned *maxnorm;
 };
 ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
@@ -189,16 +222,23 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
     w.sjobs = c.take<ScreenJob>(2);
     w.pack_a = c.take<uint4>(2 * n);
     w.pack_b = c.take<uint4>(2 * m);
+    w.coords_a = c.take<float4>(n);
+    w.coords_b = c.take<float4>(m);
+    w.boxes_a = c.take<float4>(2 * screen_tiles(n));
+    w.boxes_b = c.take<float4>(2 * screen_tiles(m));
+    w.perm_a = c.take<uint32_t>(n);
+    w.perm_b = c.take<uint32_t>(m);
     w.maxnorm = c.take<unsigned>(2);
   }
+  const long long nk = mode == PDG_CHAMFER_BF16_SCREEN && n > m ? n : m;   // sort entries
   w.jobs = c.take<NNJob>(2);
   w.segs = c.take<ChSeg>(1);
   w.b_base = c.take<unsigned>(1);
   w.partials = c.take<double>(2 * kLossBlocks);
   w.w_default = c.take<double>(2);
-  w.keys = c.take<uint32_t>(m);
-  w.vals = c.take<uint32_t>(m);
-  w.sort = c.take<char>((long long)radix_sort_bytes(m));
+  w.keys = c.take<uint32_t>(nk);
+  w.vals = c.take<uint32_t>(nk);
+  w.sort = c.take<char>((long long)radix_sort_bytes(nk));
   return w;
 }
 
@@ -285,11 +325,14 @@ struct pdg_problem {
   uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
   void *sort = nullptr;
   NNJob *jobs = nullptr;
-  ScreenSet *ssets = nullptr;
+  ScreenSet *ssets = nullptr;          // nseg moving sets, then T fixed frames
   ScreenJob *sjobs = nullptr;
   uint4 *packs = nullptr;
+  float4 *coords = nullptr, *boxes = nullptr;
+  int *fperm = nullptr, *tperm = nullptr;   // Morton order of every frame / of X_0
   unsigned *maxnorm = nullptr;
-  long long pack_rows = 0;
+  unsigned long long *tiles = nullptr;     // candidate tiles screened (all steps)
+  long long pack_rows = 0, box_tiles = 0;
   ChSeg *segs = nullptr;
   unsigned *b_base = nullptr;
   void *cgws = nullptr;
@@ -406,11 +449,18 @@ void layout(pdg_problem &p, Carve &c) {
   p.jobs = c.take<NNJob>(p.njobs);
   if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
     // every segment packs its moving set A and its fixed set B
-    p.pack_rows = T * (N + N) + (p.has_tm ? T * (V + N) : 0);
-    p.ssets = c.take<ScreenSet>(2 * p.nseg);
+    // moving sets (P^_t, then X_t) are packed every step, the frames P_1..P_T once
+    p.pack_rows = T * N + (p.has_tm ? T * V : 0) + T * N;
+    p.box_tiles = T * screen_tiles(N) + (p.has_tm ? T * screen_tiles(V) : 0) + T * screen_tiles(N);
+    p.ssets = c.take<ScreenSet>(p.nseg + T);
     p.sjobs = c.take<ScreenJob>(p.njobs);
     p.packs = c.take<uint4>(2 * p.pack_rows);
-    p.maxnorm = c.take<unsigned>(2 * p.nseg);
+    p.coords = c.take<float4>(p.pack_rows);
+    p.boxes = c.take<float4>(2 * p.box_tiles);
+    p.maxnorm = c.take<unsigned>(p.nseg + T);
+    p.fperm = c.take<int>(F * N);
+    p.tperm = c.take<int>(V);
+    p.tiles = c.take<unsigned long long>(1);
   }
   p.segs = c.take<ChSeg>(p.nseg);
   p.b_base = c.take<unsigned>(p.nseg);
@@ -478,8 +528,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
     case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
         // screen warm-started from the previous iteration's assignment
-        PDG_TRY(launch_fill((float *)p.maxnorm, 2 * p.nseg, 0.f, st));
-        PDG_TRY(launch_screen_pack(p.ssets, 2 * p.nseg, p.max_nq, st));
+        PDG_TRY(launch_fill((float *)p.maxnorm, p.nseg, 0.f, st));
+        PDG_TRY(launch_screen_pack(p.ssets, p.nseg, p.max_n, st));
         return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
       }
       return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
@@ -697,16 +747,15 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
     ScreenJob sj[2];
     memset(ss, 0, sizeof ss);
     memset(sj, 0, sizeof sj);
-    ss[0].x = a;
-    ss[0].n = (int)n;
-    ss[0].pack = w.pack_a;
-    ss[0].maxnorm = w.maxnorm;
-    ss[1].x = b;
-    ss[1].n = (int)m;
-    ss[1].pack = w.pack_b;
-    ss[1].maxnorm = w.maxnorm + 1;
-    sj[0] = ScreenJob{a, b, (int)n, (int)m, nn_a, w.pack_b, w.maxnorm + 1};
-    sj[1] = ScreenJob{b, a, (int)m, (int)n, nn_b, w.pack_a, w.maxnorm};
+    // Morton order of both sets (the sorted index arrays are the permutations)
+    PDG_TRY(launch_morton(a, n, (int)n, w.keys, w.perm_a, stream));
+    PDG_TRY(radix_sort(w.keys, w.perm_a, n, 30, w.sort, stream));
+    PDG_TRY(launch_morton(b, m, (int)m, w.keys, w.perm_b, stream));
+    PDG_TRY(radix_sort(w.keys, w.perm_b, m, 30, w.sort, stream));
+    ss[0] = screen_set(a, n, (const int *)w.perm_a, w.pack_a, w.coords_a, w.boxes_a, w.maxnorm);
+    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b, w.maxnorm + 1);
+    sj[0] = screen_job(ss[0], ss[1], nn_a, nullptr);
+    sj[1] = screen_job(ss[1], ss[0], nn_b, nullptr);
     PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
     PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
     PDG_TRY(launch_fill((float *)w.maxnorm, 2, 0.f, stream));
@@ -922,26 +971,24 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   std::vector<ScreenSet> ssets;
   std::vector<ScreenJob> sjobs;
   if (p->packs) {
-    long long row = 0;
+    long long row = 0, tile = 0;
+    auto add_set = [&](const float *x, long long n, const int *perm, unsigned *mx) {
+      ssets.push_back(screen_set(x, n, perm, p->packs + 2 * row, p->coords + row,
+                                 p->boxes + 2 * tile, mx));
+      row += n;
+      tile += screen_tiles(n);
+    };
+    for (int s = 0; s < p->nseg; ++s) {        // moving sets: P^_t keeps P_t's order, X_t X_0's
+      const ChSeg &q = segs[s];
+      add_set(q.a, q.n, s < T ? p->fperm + (long long)s * N : p->tperm, p->maxnorm + s);
+    }
+    for (long long t = 0; t < T; ++t)          // fixed frames P_1..P_T
+      add_set(pd->points + (t + 1) * 3 * N, N, p->fperm + (t + 1) * N, p->maxnorm + p->nseg + t);
     for (int s = 0; s < p->nseg; ++s) {
       const ChSeg &q = segs[s];
-      ScreenSet sa, sb;
-      memset(&sa, 0, sizeof sa);
-      memset(&sb, 0, sizeof sb);
-      sa.x = q.a;
-      sa.n = q.n;
-      sa.pack = p->packs + 2 * row;
-      sa.maxnorm = p->maxnorm + 2 * s;
-      row += q.n;
-      sb.x = q.b;
-      sb.n = q.m;
-      sb.pack = p->packs + 2 * row;
-      sb.maxnorm = p->maxnorm + 2 * s + 1;
-      row += q.m;
-      ssets.push_back(sa);
-      ssets.push_back(sb);
-      sjobs.push_back(ScreenJob{q.a, q.b, q.n, q.m, q.nn_a, sb.pack, sb.maxnorm});
-      sjobs.push_back(ScreenJob{q.b, q.a, q.m, q.n, q.nn_b, sa.pack, sa.maxnorm});
+      const ScreenSet &A = ssets[s], &B = ssets[p->nseg + s % T];
+      sjobs.push_back(screen_job(A, B, q.nn_a, p->tiles));
+      sjobs.push_back(screen_job(B, A, q.nn_b, p->tiles));
     }
   }
   hipError_t e = hipSuccess;
@@ -973,8 +1020,25 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     delete p;
     return s;
   }
+  pdg_status s = PDG_OK;
+  if (p->packs) {
+    // Morton order of every frame and of the template, then the fixed frames'
+    // packs (their rows, coordinates and boxes never change)
+    for (long long f = 0; f < p->F && s == PDG_OK; ++f) {
+      uint32_t *perm = (uint32_t *)(p->fperm + f * N);
+      s = launch_morton(pd->points + f * 3 * N, N, (int)N, p->rkeys, perm, stream);
+      if (s == PDG_OK) s = radix_sort(p->rkeys, perm, N, 30, p->sort, stream);
+    }
+    if (s == PDG_OK && p->has_tm) {
+      s = launch_morton(pd->template_verts, V, (int)V, p->tkeys, (uint32_t *)p->tperm, stream);
+      if (s == PDG_OK) s = radix_sort(p->tkeys, (uint32_t *)p->tperm, V, 30, p->sort, stream);
+    }
+    if (s == PDG_OK) s = launch_fill((float *)p->maxnorm + p->nseg, T, 0.f, stream);
+    if (s == PDG_OK) s = launch_screen_pack(p->ssets + p->nseg, (int)T, (int)N, stream);
+    if (s == PDG_OK) s = launch_fill((float *)p->tiles, 2, 0.f, stream);
+  }
   // static scatter entries of the input points (fixed positions)
-  pdg_status s = scatter_entries(
+  if (s == PDG_OK) s = scatter_entries(
       p->g, (int)T, scatter_list(p->pkeys, p->pvals, p->pstart_p, N, pd->points, 3 * N, N, nullptr, 0, 0),
       p->pkeys, p->pvals, p->pstart_p, p->sort, stream);
   if (s == PDG_OK && p->has_tm)
@@ -1076,6 +1140,7 @@ pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, s
     case PDG_BUF_GXHAT: *ptr = p->gxhat; *bytes = T * 3 * V * 4; break;
     case PDG_BUF_TERMS: *ptr = p->terms; *bytes = 8 * 8; break;
     case PDG_BUF_LAM: *ptr = p->lam; *bytes = T * 3 * V * 4; break;
+    case PDG_BUF_SCREEN_TILES: *ptr = p->tiles; *bytes = p->tiles ? 8 : 0; break;
     default:
       set_error("unknown buffer %d", which);
       return PDG_EINVAL;

@@ -33,8 +33,21 @@
 // fragment feeds two MFMAs) and streams the packed candidates through LDS in
 // tiles of 256: the next tile is fetched into registers while the current one
 // is screened, then written to the other LDS buffer.  The rare exact re-rank
-// reads candidate coordinates from global memory (L2); staging them in LDS
-// measured no faster.
+// reads candidate coordinates from global memory (L2).
+//
+// Tile culling.  Both point sets are packed in Morton order (the permutation
+// is computed once for a fixed set and reused for its smooth deformations), so
+// a tile of 256 consecutive points is spatially compact, and the pack records
+// each tile's bounding box.  A candidate tile is skipped for a query tile when
+// the squared distance between the two boxes, times (1 - 2^-20), exceeds every
+// query's current best: the box distance bounds every pair's true distance from
+// below, the contract distance is within 5 * 2^-24 relative of the true one and
+// the float32 box distance within 6 * 2^-24, so a skipped candidate is strictly
+// farther than the best and can be neither the nearest nor a tie.  Tiles are
+// listed by that test against the warm-start bests, visited starting from the
+// candidate tile of the same Morton rank, and re-tested against the improving
+// bests before each visit.  Ties are broken on the original indices, which the
+// packed coordinates carry, so the result is the exact search's bit for bit.
 #include "common.h"
 
 namespace pdg {
@@ -49,15 +62,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #ifndef PDG_SCREEN_TILE
 #define PDG_SCREEN_TILE 256
 #endif
-#ifndef PDG_SCREEN_LDS_COORDS
-#define PDG_SCREEN_LDS_COORDS 0
-#endif
 constexpr int kThreads = 256;
 constexpr int kQB = PDG_SCREEN_QB;  // 32-query blocks per wave
 constexpr int kQPerBlock = 4 * 32 * kQB;
 constexpr int kCTile = PDG_SCREEN_TILE;   // candidates per LDS tile
 constexpr int kPerThread = kCTile / kThreads;
-constexpr bool kLdsCoords = PDG_SCREEN_LDS_COORDS != 0;   // re-rank coordinates in LDS
+constexpr int kTile = 256;          // points per box tile (query block and candidate tile)
+static_assert(kQPerBlock == kTile && kCTile == kTile, "box tiles must match the screen tiles");
+constexpr int kListMax = 1024;      // candidate tiles listed per pass of the cull
+constexpr float kCullSlack = 1.0f - 1.0f / 1048576.0f;   // 1 - 2^-20
 constexpr float kEpsAB = 3e-5f, kEpsSq = 2e-6f, kEpsAbs = 1e-6f;
 constexpr float kRelSlack = 1.0f + 1.0f / 1048576.0f;   // 1 + 2^-20
 
@@ -77,21 +90,52 @@ __device__ __forceinline__ float d2_contract(float qx, float qy, float qz, float
   return (dx * dx + dy * dy) + dz * dz;
 }
 
-// Packed candidate row: 16 bf16 (32 B), plus the float32 coordinates for the
-// re-rank.  One thread per candidate; also max |c| over the set (float bits of
-// non-negative values order like unsigned integers, so an integer atomic max
-// is exact and order independent).
+// 30-bit Morton code of a point over [-1, 1]^3 (10 bits per axis, clamped).
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ __forceinline__ uint32_t morton_cell(float s) {
+  const float u = (s + 1.0f) * 512.0f;
+  return u <= 0.0f ? 0u : (u >= 1023.0f ? 1023u : (uint32_t)u);
+}
+__global__ __launch_bounds__(256) void morton_kernel(const float *__restrict__ x, long long ld, int n,
+                                                     uint32_t *__restrict__ keys,
+                                                     uint32_t *__restrict__ vals) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = (spread10(morton_cell(x[i])) << 2) | (spread10(morton_cell(x[ld + i])) << 1) |
+            spread10(morton_cell(x[2 * ld + i]));
+  vals[i] = (uint32_t)i;
+}
+
+// One thread per packed position i (original point perm[i]): the packed bf16
+// row (32 B), the float32 coordinates with the original index, max |c| over
+// the set (float bits of non-negative values order like unsigned integers, so
+// an integer atomic max is exact and order independent), and, one block per
+// 256-point tile, the tile's bounding box.
 __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__ sets) {
+  __shared__ float red[6][4];
   const ScreenSet S = sets[blockIdx.y];
+  if ((long long)blockIdx.x * 256 >= S.n) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   float nrm = 0.f;
+  float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
+  float hi3[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
   if (i < S.n) {
     const long long n = S.n;
-    const float c[3] = {S.x[i], S.x[n + i], S.x[2 * n + i]};
-    unsigned short hi[3], lo[3];
+    const int o = S.perm ? S.perm[i] : i;
+    const float c[3] = {S.x[o], S.x[n + o], S.x[2 * n + o]};
+    unsigned short hi[3], lw[3];
     for (int k = 0; k < 3; ++k) {
       hi[k] = bf16_rn(c[k]);
-      lo[k] = bf16_rn(c[k] - bf16_f(hi[k]));
+      lw[k] = bf16_rn(c[k] - bf16_f(hi[k]));
+      lo[k] = c[k];
+      hi3[k] = c[k];
     }
     const float nn = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
     const unsigned short n0 = bf16_rn(nn);
@@ -100,7 +144,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     unsigned short row[16];
     for (int k = 0; k < 3; ++k) {
       row[k] = bf16_rn(-2.0f * bf16_f(hi[k]));
-      row[3 + k] = bf16_rn(-2.0f * bf16_f(lo[k]));
+      row[3 + k] = bf16_rn(-2.0f * bf16_f(lw[k]));
       row[6 + k] = row[k];
     }
     row[9] = n0;
@@ -118,10 +162,44 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     w1.w = 0u;
     S.pack[2 * i] = w0;
     S.pack[2 * i + 1] = w1;
+    S.coords[i] = make_float4(c[0], c[1], c[2], __int_as_float(o));
     nrm = sqrtf(nn);
   }
-  for (int o = 32; o > 0; o >>= 1) nrm = fmaxf(nrm, __shfl_xor(nrm, o, 64));
-  if ((threadIdx.x & 63) == 0 && nrm > 0.f) atomicMax(S.maxnorm, __float_as_uint(nrm));
+  for (int o = 32; o > 0; o >>= 1) {
+    nrm = fmaxf(nrm, __shfl_xor(nrm, o, 64));
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
+      hi3[k] = fmaxf(hi3[k], __shfl_xor(hi3[k], o, 64));
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    if (nrm > 0.f) atomicMax(S.maxnorm, __float_as_uint(nrm));
+    for (int k = 0; k < 3; ++k) {
+      red[k][wv] = lo[k];
+      red[3 + k][wv] = hi3[k];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b[6];
+    for (int k = 0; k < 3; ++k) {
+      b[k] = fminf(fminf(red[k][0], red[k][1]), fminf(red[k][2], red[k][3]));
+      b[3 + k] = fmaxf(fmaxf(red[3 + k][0], red[3 + k][1]), fmaxf(red[3 + k][2], red[3 + k][3]));
+    }
+    S.boxes[2 * blockIdx.x] = make_float4(b[0], b[1], b[2], 0.f);
+    S.boxes[2 * blockIdx.x + 1] = make_float4(b[3], b[4], b[5], 0.f);
+  }
+}
+
+// Squared distance between two axis-aligned boxes (0 when they overlap).
+__device__ __forceinline__ float box_lb(const float4 &amin, const float4 &amax, const float4 &bmin,
+                                        const float4 &bmax) {
+#pragma clang fp contract(off)
+  const float dx = fmaxf(fmaxf(amin.x - bmax.x, bmin.x - amax.x), 0.f);
+  const float dy = fmaxf(fmaxf(amin.y - bmax.y, bmin.y - amax.y), 0.f);
+  const float dz = fmaxf(fmaxf(amin.z - bmax.z, bmin.z - amax.z), 0.f);
+  return (dx * dx + dy * dy) + dz * dz;
 }
 
 struct QState {
@@ -137,8 +215,7 @@ __device__ __forceinline__ int out_row(int r, int lane) {
 }
 
 __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, int cbase, int nc,
-                                         const float4 *__restrict__ lc,
-                                         const float *__restrict__ cx, long long ldc) {
+                                         const float4 *__restrict__ cc) {
   float m = fminf(fminf(v[0], v[1]), v[2]);
   m = fminf(fminf(m, v[3]), v[4]);
   m = fminf(fminf(m, v[5]), v[6]);
@@ -156,19 +233,14 @@ __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, i
   while (mask) {
     const int r = __builtin_ctz(mask);
     mask &= mask - 1;
-    const int row = out_row(r, lane);
-    const int c = cbase + row;
+    const int c = cbase + out_row(r, lane);
     if (c >= nc) continue;             // padded rows never count
-    float d;
-    if (kLdsCoords) {
-      const float4 p = lc[row];
-      d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
-    } else {
-      d = d2_contract(s.x, s.y, s.z, cx[c], cx[ldc + c], cx[2 * ldc + c]);
-    }
-    if (d < s.best || (d == s.best && c < s.idx)) {
+    const float4 p = cc[c];
+    const float d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
+    const int o = __float_as_int(p.w);
+    if (d < s.best || (d == s.best && o < s.idx)) {
       s.best = d;
-      s.idx = c;
+      s.idx = o;
       set_thr(s);
     }
   }
@@ -177,7 +249,6 @@ __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, i
 // this thread's share of a tile: packed rows of candidates c0 + tid + k*256
 struct TileRegs {
   uint4 w[kPerThread][2];
-  float4 p[kLdsCoords ? kPerThread : 1];
 };
 
 __device__ __forceinline__ void fetch_tile(const ScreenJob &J, int c0, TileRegs &t) {
@@ -187,26 +258,30 @@ __device__ __forceinline__ void fetch_tile(const ScreenJob &J, int c0, TileRegs 
     if (c < J.nc) {
       t.w[k][0] = J.pack[2ll * c];
       t.w[k][1] = J.pack[2ll * c + 1];
-      if (kLdsCoords) {
-        const long long nc = J.nc;
-        t.p[k] = make_float4(J.c[c], J.c[nc + c], J.c[2 * nc + c], 0.f);
-      }
     } else {
       t.w[k][0] = make_uint4(0u, 0u, 0u, 0u);
       t.w[k][1] = make_uint4(0x7F800000u, 0u, 0u, 0u);   // n_hi = +inf: S = +inf
-      if (kLdsCoords) t.p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
 }
 
-__device__ __forceinline__ void store_tile(const TileRegs &t, uint4 *spack, float4 *scoord) {
+__device__ __forceinline__ void store_tile(const TileRegs &t, uint4 *spack) {
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const int i = k * kThreads + (int)threadIdx.x;
     spack[2 * i] = t.w[k][0];
     spack[2 * i + 1] = t.w[k][1];
-    if (kLdsCoords) scoord[i] = t.p[k];
   }
+}
+
+// Largest current best of this wave's valid queries (lanes without a query
+// report 0); the block maximum bounds every query's best from above.
+__device__ __forceinline__ float wave_best_max(const QState *st, const bool *ok) {
+  float m = 0.f;
+#pragma unroll
+  for (int h = 0; h < kQB; ++h) m = ok[h] ? fmaxf(m, st[h].best) : m;
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  return m;
 }
 
 __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__restrict__ jobs,
@@ -215,28 +290,35 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
   const int q0 = blockIdx.x * kQPerBlock;
   if (q0 >= J.nq) return;
   __shared__ uint4 spack[2][kCTile * 2];
-  __shared__ float4 scoord[2][kLdsCoords ? kCTile : 1];
+  __shared__ int tlist[kListMax];
+  __shared__ float tlb[kListMax];
+  __shared__ float wmax[2][4];
+  __shared__ int s_count;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int half = lane >> 5;
-  const long long nq = J.nq, nc = J.nc;
+  const long long nc = J.nc;
   const float cmax = __uint_as_float(*J.maxnorm);
   QState st[kQB];
+  bool ok[kQB];
+  int qorig[kQB];
   bf16x8 bq[kQB];
 #pragma unroll
   for (int h = 0; h < kQB; ++h) {
-    const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);
+    const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);   // packed position
     QState &s = st[h];
-    const bool ok = q < J.nq;
-    s.x = ok ? J.q[q] : 0.f;
-    s.y = ok ? J.q[nq + q] : 0.f;
-    s.z = ok ? J.q[2 * nq + q] : 0.f;
+    ok[h] = q < J.nq;
+    const float4 qc = ok[h] ? J.q[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    qorig[h] = __float_as_int(qc.w);
+    s.x = qc.x;
+    s.y = qc.y;
+    s.z = qc.z;
     s.qn = (s.x * s.x + s.y * s.y) + s.z * s.z;
     const float a = sqrtf(s.qn);
     s.eps = kEpsAB * a * cmax + kEpsSq * (s.qn + cmax * cmax) + kEpsAbs;
     s.best = __builtin_huge_valf();
     s.idx = 0x7fffffff;
-    if (ok && warm) {
-      const int p = J.nn[q];
+    if (ok[h] && warm) {
+      const int p = J.nn[qorig[h]];
       if (p >= 0 && p < J.nc) {
         s.best = d2_contract(s.x, s.y, s.z, J.c[p], J.c[nc + p], J.c[2 * nc + p]);
         s.idx = p;
@@ -244,11 +326,11 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
     }
     set_thr(s);
     // B operand: column (lane & 31), k-slots 8*half .. 8*half+7 of the query row
-    const float qc[3] = {s.x, s.y, s.z};
+    const float qv[3] = {s.x, s.y, s.z};
     unsigned short hi[3], lo[3];
     for (int k = 0; k < 3; ++k) {
-      hi[k] = bf16_rn(qc[k]);
-      lo[k] = bf16_rn(qc[k] - bf16_f(hi[k]));
+      hi[k] = bf16_rn(qv[k]);
+      lo[k] = bf16_rn(qv[k] - bf16_f(hi[k]));
     }
     const unsigned short one = 0x3F80;
     unsigned short row[16] = {hi[0], hi[1], hi[2], hi[0], hi[1], hi[2], lo[0], lo[1],
@@ -258,30 +340,84 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
       bq[h][e] = *reinterpret_cast<const __bf16 *>(&b);
     }
   }
+  const float4 qmin = J.qboxes[2 * blockIdx.x], qmax = J.qboxes[2 * blockIdx.x + 1];
+  const int ntiles = (J.nc + kTile - 1) / kTile;
+  const int qtiles = (J.nq + kTile - 1) / kTile;
+  const int start = (int)((long long)blockIdx.x * ntiles / qtiles);
+  {
+    const float m = wave_best_max(st, ok);
+    if (lane == 0) wmax[0][wv] = m;
+  }
+  __syncthreads();
+  float bmax = fmaxf(fmaxf(wmax[0][0], wmax[0][1]), fmaxf(wmax[0][2], wmax[0][3]));
+  int it = 1;                   // parity of the wmax buffer written next
+  unsigned screened = 0;
   TileRegs regs;
-  fetch_tile(J, 0, regs);
-  store_tile(regs, spack[0], scoord[0]);
-  int buf = 0;
-  for (int c0 = 0; c0 < J.nc; c0 += kCTile) {
-    __syncthreads();                      // tile c0 is in spack[buf]; spack[buf^1] is free
-    const bool more = c0 + kCTile < J.nc;
-    if (more) fetch_tile(J, c0 + kCTile, regs);   // in flight while this tile is screened
-    const int left = (J.nc - c0 + 31) / 32;
-    const int nsub = left < kCTile / 32 ? left : kCTile / 32;
-    for (int sub = 0; sub < nsub; ++sub) {
-      const uint4 raw = spack[buf][2 * (sub * 32 + (lane & 31)) + half];
-      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
-      const f32x16 z = {};
-      f32x16 v[kQB];
-#pragma unroll
-      for (int h = 0; h < kQB; ++h)
-        v[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
-#pragma unroll
-      for (int h = 0; h < kQB; ++h)
-        consider(st[h], v[h], lane, c0 + sub * 32, J.nc, scoord[buf] + sub * 32, J.c, nc);
+  for (int base = 0; base < ntiles; base += kListMax) {
+    const int span = ntiles - base < kListMax ? ntiles - base : kListMax;
+    if (wv == 0) {              // list the tiles that pass the box test, in visiting order
+      int count = 0;
+      for (int k0 = 0; k0 < span; k0 += 64) {
+        const int k = k0 + lane;
+        bool pass = false;
+        float lb = 0.f;
+        int tile = 0;
+        if (k < span) {
+          tile = (start + base + k) % ntiles;
+          lb = box_lb(qmin, qmax, J.cboxes[2 * tile], J.cboxes[2 * tile + 1]);
+          pass = !(lb * kCullSlack > bmax);
+        }
+        const unsigned long long m = __ballot(pass);
+        const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+        if (pass) {
+          tlist[pos] = tile;
+          tlb[pos] = lb;
+        }
+        count += __popcll(m);
+      }
+      if (lane == 0) s_count = count;
     }
-    if (more) store_tile(regs, spack[buf ^ 1], scoord[buf ^ 1]);
-    buf ^= 1;
+    __syncthreads();
+    const int count = s_count;
+    int i = 0;
+    while (i < count && tlb[i] * kCullSlack > bmax) ++i;
+    if (i < count) {
+      fetch_tile(J, tlist[i] * kTile, regs);
+      store_tile(regs, spack[0]);
+    }
+    int buf = 0;
+    while (i < count) {
+      {
+        const float m = wave_best_max(st, ok);
+        if (lane == 0) wmax[it & 1][wv] = m;
+      }
+      __syncthreads();          // tile tlist[i] is in spack[buf]; the other buffer is free
+      bmax = fmaxf(fmaxf(wmax[it & 1][0], wmax[it & 1][1]), fmaxf(wmax[it & 1][2], wmax[it & 1][3]));
+      ++it;
+      int nxt = i + 1;
+      while (nxt < count && tlb[nxt] * kCullSlack > bmax) ++nxt;
+      const bool more = nxt < count;
+      if (more) fetch_tile(J, tlist[nxt] * kTile, regs);   // in flight while this tile is screened
+      const int c0 = tlist[i] * kTile;
+      const int left = (J.nc - c0 + 31) / 32;
+      const int nsub = left < kCTile / 32 ? left : kCTile / 32;
+      for (int sub = 0; sub < nsub; ++sub) {
+        const uint4 raw = spack[buf][2 * (sub * 32 + (lane & 31)) + half];
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
+        const f32x16 z = {};
+        f32x16 v[kQB];
+#pragma unroll
+        for (int h = 0; h < kQB; ++h)
+          v[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
+#pragma unroll
+        for (int h = 0; h < kQB; ++h) consider(st[h], v[h], lane, c0 + sub * 32, J.nc, J.cc);
+      }
+      if (more) store_tile(regs, spack[buf ^ 1]);
+      buf ^= 1;
+      i = nxt;
+      ++screened;
+    }
+    __syncthreads();            // the list is rebuilt next
   }
 #pragma unroll
   for (int h = 0; h < kQB; ++h) {
@@ -292,12 +428,19 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
       s.best = ob;
       s.idx = oi;
     }
-    const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);
-    if (half == 0 && q < J.nq) J.nn[q] = s.idx;
+    if (half == 0 && ok[h]) J.nn[qorig[h]] = s.idx;
   }
+  if (J.tiles && tid == 0) atomicAdd(J.tiles, (unsigned long long)screened);
 }
 
 }  // namespace
+
+pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, uint32_t *vals,
+                         hipStream_t st) {
+  if (n <= 0) return PDG_OK;
+  morton_kernel<<<div_up(n, 256), 256, 0, st>>>(x, ld, n, keys, vals);
+  return launched("morton");
+}
 
 pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipStream_t st) {
   if (nsets <= 0 || max_n <= 0) return PDG_OK;

@@ -150,22 +150,34 @@ struct NNJob {               // one directed nearest-neighbour search
 };
 pdg_status launch_nn_exact(const NNJob *jobs, int njobs, int max_nq, hipStream_t st);
 
-// chamfer_screen.hip: bf16 matrix-core screen + exact float32 re-rank
-struct ScreenSet {           // one point set to pack as screen candidates
-  const float *x;            // SoA [3][n]
+// chamfer_screen.hip: bf16 matrix-core screen + exact float32 re-rank with
+// box culling over Morton-ordered 256-point tiles
+struct ScreenSet {           // one point set packed as screen candidates and queries
+  const float *x;            // SoA [3][n], original order
   int n;
   int pad;
-  uint4 *pack;               // [n][2] packed bf16 rows (32 B per point)
+  const int *perm;           // [n] packed position -> original index (nullable: identity)
+  uint4 *pack;               // [n][2] packed bf16 rows (32 B per point), packed order
+  float4 *coords;            // [n] (x, y, z, original index as int bits), packed order
+  float4 *boxes;             // [ceil(n/256)][2] min and max corner of each 256-point tile
   unsigned *maxnorm;         // float bits of max |x| (zeroed before packing)
 };
-struct ScreenJob {           // one directed search over a packed candidate set
-  const float *q;
-  const float *c;
+struct ScreenJob {           // one directed search: packed queries over packed candidates
+  const float *c;            // candidates SoA [3][nc], original order (warm start)
+  const float4 *q;           // query coords, packed order
+  const float4 *qboxes;      // query tile boxes
   int nq, nc;
-  int *nn;                   // out; with warm start also the previous assignment
-  const uint4 *pack;         // packed rows of c
-  const unsigned *maxnorm;   // of c
+  int *nn;                   // [nq] original order; out, and the warm start when enabled
+  const uint4 *pack;         // candidate rows, packed order
+  const float4 *cc;          // candidate coords, packed order
+  const float4 *cboxes;      // candidate tile boxes
+  const unsigned *maxnorm;   // of the candidates
+  unsigned long long *tiles; // nullable: += candidate tiles screened
 };
+inline long long screen_tiles(long long n) { return (n + 255) / 256; }
+// keys = 30-bit Morton codes over [-1, 1]^3 of x ([3][ld] SoA, n points), vals = index
+pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, uint32_t *vals,
+                         hipStream_t st);
 pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipStream_t st);
 pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int warm,
                             hipStream_t st);

@@ -166,6 +166,8 @@ class Problem:
             return raw.view(torch.float64).view(-1, 2)
         if name in ("wconf", "terms"):
             return raw.view(torch.float64)
+        if name == "screen_tiles":
+            return raw.view(torch.int64)
         raise KeyError(name)
 
     def nn(self):
