@@ -128,6 +128,7 @@ def time_stages(prob, reps=3):
     for name in L.STAGES:
         prob.stage(name)                 # warm
         torch.cuda.synchronize()
+        t0 = screen_tiles(prob)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(st)
@@ -136,7 +137,16 @@ def time_stages(prob, reps=3):
         b.record(st)
         torch.cuda.synchronize()
         out[name] = a.elapsed_time(b) / reps
+        if name == "nn" and t0 is not None:
+            out["nn_tiles"] = (screen_tiles(prob) - t0) / reps
     return out
+
+
+def screen_tiles(prob):
+    """Candidate tiles screened so far (bf16 mode), else None."""
+    if prob.chamfer_mode != "bf16":
+        return None
+    return int(prob.buffer("screen_tiles").item())
 
 
 def nn_pairs(prob):
@@ -175,11 +185,16 @@ def roofline(prob, stages, chamfer, precond):
     nn_ms, pre_ms = stages["nn"], stages["precond"]
     pairs = nn_pairs(prob)
     if chamfer == "bf16":
-        a = pairs * PAIR_MFMA_FLOPS / (nn_ms * 1e-3) / 1e12
+        # pairs the matrix cores screened: 256 x 256 per candidate tile that
+        # survived the box cull (padding included); `pairs_per_launch` is the
+        # brute-force pair count the exact result stands for
+        screened = stages["nn_tiles"] * 256 * 256
+        a = screened * PAIR_MFMA_FLOPS / (nn_ms * 1e-3) / 1e12
         nn = {"bound": "mfma", "achieved": round(a, 2), "peak": BF16_MFMA_PEAK_TFLOPS,
               "unit": "TFLOP/s", "frac": round(a / BF16_MFMA_PEAK_TFLOPS, 4),
               "traffic": pmc_traffic("nn_screen_kernel"),
-              "kernel": "nn_screen_kernel", "pairs_per_launch": pairs,
+              "kernel": "nn_screen_kernel", "pairs_screened_per_launch": int(screened),
+              "pairs_per_launch": pairs, "cull_fraction": round(1 - screened / pairs, 4),
               "pairs_per_s": round(pairs / (nn_ms * 1e-3), 1), "launch_ms": round(nn_ms, 4)}
     else:
         a = pairs * PAIR_OPS / (nn_ms * 1e-3) / 1e12

@@ -147,48 +147,54 @@ __global__ __launch_bounds__(kThreads) void dct_pass_kernel(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused passes for R <= 128: a z-plane (R x R, rows padded by one float so that
-// column reads hit distinct LDS banks) or 32 z-pencils live in LDS and receive
-// two transforms per HBM round trip.  Every wave owns one row of 32 x 32 output
-// tiles; operands come from LDS (data) and the cached basis (coefficients).
+// Fused passes for R <= 128.  A block of 8 waves keeps the basis C in LDS
+// (pitch R + 1, so that reading it along either index hits distinct banks)
+// and loops over its share of the work:
+//   plane kernel   one z-plane (R x R, pitch R + 1) in LDS gets two transforms,
+//                  along x then along y;
+//   pencil kernel  64 z-pencils (R x 64) in LDS get the forward z transform,
+//                  the spectral scale and the inverse z transform.
+// Outputs are 32 x 32 tiles (v_mfma_f32_32x32x2_f32); wave w owns tiles
+// w and w + 8 of the (row band, column tile) grid.  Operands of 8 MFMA steps
+// are read from LDS before their matrix-core operations.
 struct FusedArgs {
   const float *src;            // input of the pass
   float *dst;                  // output of the pass (may equal src)
-  long long stack, off, planes;   // planes = batch * 3 * R (z-planes or pencil groups)
-  const float *cf;             // [in][out] = C^T  (forward coefficients)
-  const float *ci;             // [in][out] = C    (inverse coefficients)
+  long long stack, off, planes;   // planes = batch * 3 * R
+  const float *c;              // C[k][x], R x R row-major
   const float *mu;
   int R;
   float lam;
 };
 
 constexpr int kFusedMaxR = 128;
-
-// acc[t][i][j] = sum_k A(i0 + i, k) B(k, 32 t + j), k < R, for the NT tiles of
-// one 32-row band; A and B are functors that return 0 outside the valid range.
-// K is consumed kCh MFMA steps at a time: all operands of a chunk are loaded
-// (independent loads in flight) before its NT x kCh matrix-core operations.
+constexpr int kBig = 512;              // threads of a fused block (8 waves)
 constexpr int kCh = 8;
 
-template <int NT, class FA, class FB>
-__device__ __forceinline__ void band_gemm(int R, int i0, const FA &a, const FB &b, f32x16 (&acc)[NT]) {
-  const int lane = threadIdx.x & 63, jj = lane & 31, h = lane >> 5;
+// acc[p] = sum_k A(k) B_p(k) over k < K (a multiple of 16) for NP tiles that
+// share their rows (one row band): this lane's operands are A(k) = a[k * sak]
+// and B_p(k) = b[p][k * sbk] (lanes 32..63 take the odd k of each MFMA step).
+template <int NP>
+__device__ __forceinline__ void band_gemm(int K, const float *a, int sak, const float *const *b,
+                                          int sbk, f32x16 (&acc)[NP]) {
+  const int h = (threadIdx.x >> 5) & 1;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = (f32x16){};
-  for (int k0 = 0; k0 < R; k0 += 2 * kCh) {
-    float av[kCh], bv[kCh][NT];
+  for (int p = 0; p < NP; ++p) acc[p] = (f32x16){};
+#pragma unroll 1
+  for (int k0 = 0; k0 < K; k0 += 2 * kCh) {
+    float av[kCh], bv[NP][kCh];
 #pragma unroll
     for (int c = 0; c < kCh; ++c) {
       const int k = k0 + 2 * c + h;
-      av[c] = a(i0 + jj, k);
+      av[c] = a[k * sak];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) bv[c][t] = b(k, 32 * t + jj);
+      for (int p = 0; p < NP; ++p) bv[p][c] = b[p][k * sbk];
     }
 #pragma unroll
     for (int c = 0; c < kCh; ++c)
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[c], bv[c][t], acc[t], 0, 0, 0);
+      for (int p = 0; p < NP; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[c], bv[p][c], acc[p], 0, 0, 0);
   }
 }
 
@@ -198,114 +204,305 @@ __device__ __forceinline__ int trow(int r) {
   return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
-// Two transforms of one z-plane held in LDS: along x (t[y][k] = sum_x in[y][x] M[x][k])
-// then along y (out[k'][k] = sum_y M[y][k'] t[y][k]), M = [in][out] coefficients
-// (forward: C^T, inverse: C).  NT = ceil(R / 32) <= 4; wave w owns output band w
-// (rows 32 w .. 32 w + 31, all NT column tiles) in both phases.
-template <int NT>
-__global__ __launch_bounds__(kThreads) void dct_plane_kernel(FusedArgs a, int inverse) {
-  __shared__ float sp[kFusedMaxR * (kFusedMaxR + 1)];
-  const int R = a.R, P = R + 1;
-  const long long plane = blockIdx.x;
-  if (plane >= a.planes) return;
-  const long long sys = plane / R, z = plane % R;
-  const long long R2 = (long long)R * R, R3 = R2 * R;
-  const long long base = (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
-  const float *m = inverse ? a.ci : a.cf;
-  for (int i = threadIdx.x; i < R * R; i += kThreads) sp[(i / R) * P + i % R] = a.src[base + i];
-  __syncthreads();
-  const int ti = threadIdx.x >> 6, col = threadIdx.x & 31;
-  f32x16 acc[NT];
-  auto ax = [&](int y, int x) { return (y < R && x < R) ? sp[y * P + x] : 0.f; };
-  auto bx = [&](int x, int k) { return (x < R && k < R) ? m[x * R + k] : 0.f; };
-  if (ti < NT) band_gemm<NT>(R, ti * 32, ax, bx, acc);
-  __syncthreads();
-  if (ti < NT) {
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int y = ti * 32 + trow(r), k = tj * 32 + col;
-        if (y < R && k < R) sp[y * P + k] = acc[tj][r];
-      }
-  }
-  __syncthreads();
-  auto ay = [&](int kk, int y) { return (kk < R && y < R) ? m[y * R + kk] : 0.f; };
-  auto by = [&](int y, int k) { return (y < R && k < R) ? sp[y * P + k] : 0.f; };
-  if (ti < NT) {
-    band_gemm<NT>(R, ti * 32, ay, by, acc);
-#pragma unroll
-    for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int kk = ti * 32 + trow(r), k = tj * 32 + col;
-        if (kk < R && k < R) a.dst[base + (long long)kk * R + k] = acc[tj][r];
-      }
+// C into LDS as sc[k * P + x] for k, x < RP (zero outside R x R)
+__device__ __forceinline__ void load_basis(float *sc, const float *c, int R, int RP, int P) {
+  for (int i = threadIdx.x; i < RP * RP; i += kBig) {
+    const int k = i / RP, x = i % RP;
+    sc[k * P + x] = (k < R && x < R) ? c[k * R + x] : 0.f;
   }
 }
 
-// Forward z, scale by (1 + lam (mu_x + mu_y + mu_z))^-2, inverse z for 32
-// consecutive (y, x) pencils of one system, in place on dst.  Wave w owns the
-// 32 output rows (z frequencies, then z) of band w.
-__global__ __launch_bounds__(kThreads) void dct_pencil_kernel(FusedArgs a) {
-  __shared__ float sp[kFusedMaxR * 32];
-  const int R = a.R;
-  const long long R2 = (long long)R * R, R3 = R2 * R;
-  const long long groups = (R2 + 31) / 32;         // pencil groups per system
-  const long long g = blockIdx.x;
-  if (g >= a.planes / R * groups) return;
-  const long long sys = g / groups;
-  const long long line0 = (g % groups) * 32;       // first (y, x) line = y * R + x
-  const long long base = (sys / 3) * a.stack + a.off + (sys % 3) * R3;
-  for (int i = threadIdx.x; i < R * 32; i += kThreads) {
-    const int z = i / 32, j = i % 32;
-    const long long ln = line0 + j;
-    sp[z * 32 + j] = ln < R2 ? a.dst[base + z * R2 + ln] : 0.f;
-  }
-  __syncthreads();
-  const int T = (R + 31) / 32, ti = threadIdx.x >> 6, j = threadIdx.x & 31;
-  const long long ln = line0 + j;
-  auto af = [&](int kz, int z) { return (kz < R && z < R) ? a.cf[z * R + kz] : 0.f; };
-  auto bp = [&](int z, int c) { return z < R ? sp[z * 32 + c] : 0.f; };
-  f32x16 acc[1];
-  if (ti < T) band_gemm<1>(R, ti * 32, af, bp, acc);
-  __syncthreads();
-  if (ti < T) {
-    float sxy = 0.f;
-    if (ln < R2) sxy = a.mu[ln / R] + a.mu[ln % R];
+// sp[(i / w) * pitch + i % w] = in[(i / w) * ld + i % w] for i < n: kLoadU loads in
+// flight per thread before their LDS stores
+constexpr int kLoadU = 8;
+__device__ __forceinline__ void load_rows(float *sp, int pitch, const float *in, long long ld, int w,
+                                          int n) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += kLoadU * kBig) {
+    float v[kLoadU];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int kz = ti * 32 + trow(r);
-      if (kz < R) {
-        const float d = 1.0f + a.lam * (sxy + a.mu[kz]);
-        sp[kz * 32 + j] = ln < R2 ? acc[0][r] / (d * d) : 0.f;
-      }
+    for (int u = 0; u < kLoadU; ++u) {
+      const int i = i0 + u * kBig;
+      v[u] = i < n ? in[(i / w) * ld + i % w] : 0.f;
     }
-  }
-  __syncthreads();
-  auto ai = [&](int z, int kz) { return (z < R && kz < R) ? a.ci[kz * R + z] : 0.f; };
-  if (ti < T) {
-    band_gemm<1>(R, ti * 32, ai, bp, acc);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int z = ti * 32 + trow(r);
-      if (z < R && ln < R2) a.dst[base + z * R2 + ln] = acc[0][r];
+    for (int u = 0; u < kLoadU; ++u) {
+      const int i = i0 + u * kBig;
+      if (i < n) sp[(i / w) * pitch + i % w] = v[u];
     }
   }
 }
 
-pdg_status launch_plane(const FusedArgs &f, int inverse, hipStream_t st) {
-  const unsigned blocks = (unsigned)f.planes;
-  switch ((f.R + 31) / 32) {
-    case 1: dct_plane_kernel<1><<<blocks, kThreads, 0, st>>>(f, inverse); break;
-    case 2: dct_plane_kernel<2><<<blocks, kThreads, 0, st>>>(f, inverse); break;
-    case 3: dct_plane_kernel<3><<<blocks, kThreads, 0, st>>>(f, inverse); break;
-    case 4: dct_plane_kernel<4><<<blocks, kThreads, 0, st>>>(f, inverse); break;
-    default:
-      set_error("fused DCT passes need R <= %d (got %d)", kFusedMaxR, f.R);
-      return PDG_EUNSUPPORTED;
+// Work split of an NT x NC grid of 32 x 32 output tiles over the 8 waves:
+// with NT * NC == 16 wave w owns the two tiles (w / 2, 2 (w % 2) + {0, 1})
+// of one row band; otherwise tiles w and w + 8, one at a time.
+template <int NT, int NC>
+struct Split {
+  static constexpr bool kPair = NT * NC == 16 && NC % 2 == 0;
+  static constexpr int NP = kPair ? 2 : 1;
+  static constexpr int kRounds = kPair ? 1 : (NT * NC + 7) / 8;
+  // tile of round `rnd` for this wave: (band, first column tile), or false
+  __device__ static bool tile(int rnd, int &band, int &ct) {
+    const int w = threadIdx.x >> 6;
+    if (kPair) {
+      constexpr int half = kPair ? NC / 2 : 1;
+      band = w / half;
+      ct = 2 * (w % half);
+      return true;
+    }
+    const int t = w + 8 * rnd;
+    band = t / NC;
+    ct = t % NC;
+    return t < NT * NC;
   }
+};
+
+// Two transforms of z-planes held in LDS (padded to RP = 32 NT with zeros):
+// along x, t[y][k] = sum_x in[y][x] M(x, k), then along y,
+// out[k'][k] = sum_y M(y, k') t[y][k]; M(in, out) = C[out][in] forward,
+// C[in][out] inverse.  The first transform's tiles are written over the plane
+// after a barrier; the second's go straight to HBM while the next plane is in
+// flight into registers.
+template <int NT, bool FULL>
+__global__ __launch_bounds__(kBig) void dct_plane_kernel(FusedArgs a, int inverse) {
+  using S = Split<NT, NT>;
+  constexpr int RP = 32 * NT, P = RP + 1, NP = S::NP;
+  extern __shared__ float lds[];
+  const int R = FULL ? RP : a.R;     // FULL: R == 32 NT (no partial tiles)
+  float *sc = lds;                 // basis, RP x P
+  float *sp = lds + RP * P;        // plane, RP x P
+  const long long R2 = (long long)R * R, R3 = R2 * R;
+  load_basis(sc, a.c, R, RP, P);
+  for (int i = threadIdx.x; i < RP * P; i += kBig) sp[i] = 0.f;   // padding stays zero
+  const int col = threadIdx.x & 31;
+  const int sbx = inverse ? P : 1, say = inverse ? P : 1;
+  auto plane_base = [&](long long plane) {
+    const long long sys = plane / R, z = plane % R;
+    return (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
+  };
+  __syncthreads();
+  long long plane = blockIdx.x;
+  if (plane < a.planes) load_rows(sp, P, a.src + plane_base(plane), R, R, R * R);
+  __syncthreads();
+  for (; plane < a.planes; plane += gridDim.x) {
+    const long long base = plane_base(plane);
+    f32x16 acc[S::kRounds][NP];
+#pragma unroll
+    for (int rnd = 0; rnd < S::kRounds; ++rnd) {
+      int band, ct;
+      if (S::tile(rnd, band, ct)) {
+        const int i = 32 * band + col;
+        const float *bx[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int j = 32 * (ct + p) + col;
+          bx[p] = inverse ? sc + j : sc + j * P;      // B(x = k, k = j) = M(x, j)
+        }
+        band_gemm<NP>(RP, sp + i * P, 1, bx, sbx, acc[rnd]);   // A(y = i, x = k)
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rnd = 0; rnd < S::kRounds; ++rnd) {
+      int band, ct;
+      if (S::tile(rnd, band, ct)) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int k = 32 * (ct + p) + col;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int y = 32 * band + trow(r);
+            if (FULL || (y < R && k < R)) sp[y * P + k] = acc[rnd][p][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // the next plane is fetched into registers while the second transform runs
+    constexpr int kPre = RP * RP / kBig;
+    const long long next = plane + gridDim.x;
+    float pre[kPre];
+    if (next < a.planes) {
+      const float *in = a.src + plane_base(next);
+#pragma unroll
+      for (int e = 0; e < kPre; ++e) {
+        const int i = threadIdx.x + e * kBig;
+        pre[e] = (FULL || i < R * R) ? in[i] : 0.f;
+      }
+    }
+    float *out = a.dst + base;
+#pragma unroll
+    for (int rnd = 0; rnd < S::kRounds; ++rnd) {
+      int band, ct;
+      if (S::tile(rnd, band, ct)) {
+        const int i = 32 * band + col;
+        const float *by[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) by[p] = sp + 32 * (ct + p) + col;   // B(y = k, k = j)
+        f32x16 o[NP];
+        band_gemm<NP>(RP, inverse ? sc + i : sc + i * P, say, by, P, o);   // A(k' = i, y = k)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int k = 32 * (ct + p) + col;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int kk = 32 * band + trow(r);
+            if (FULL || (kk < R && k < R)) out[kk * R + k] = o[p][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (next < a.planes) {
+#pragma unroll
+      for (int e = 0; e < kPre; ++e) {
+        const int i = threadIdx.x + e * kBig;
+        if (FULL || i < R * R) sp[(i / R) * P + i % R] = pre[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Forward z, scale by (1 + lam (mu_x + mu_y + mu_z))^-2, inverse z for groups
+// of 64 consecutive (y, x) pencils of one system, in place on dst.
+constexpr int kPencils = 64;
+constexpr int kPP = kPencils + 1;      // LDS pitch of a pencil row
+
+template <int NT, bool FULL>
+__global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
+  using S = Split<NT, kPencils / 32>;
+  constexpr int RP = 32 * NT, P = RP + 1, NP = S::NP;
+  extern __shared__ float lds[];
+  const int R = FULL ? RP : a.R;     // FULL: R == 32 NT (R^2 is a multiple of 64)
+  float *sc = lds;                 // basis, RP x P
+  float *sq = lds + RP * P;        // pencils, RP x kPP (rows >= R stay zero)
+  const long long R2 = (long long)R * R, R3 = R2 * R;
+  const long long groups = (R2 + kPencils - 1) / kPencils;   // per system
+  const long long total = a.planes / R * groups;
+  load_basis(sc, a.c, R, RP, P);
+  for (int i = threadIdx.x; i < RP * kPP; i += kBig) sq[i] = 0.f;
+  const int col = threadIdx.x & 31;
+  const int r2 = (int)R2;
+  auto group_ptr = [&](long long g, int &nl) {
+    const long long sys = g / groups;
+    const long long line0 = (g % groups) * kPencils;   // first (y, x) line = y * R + x
+    nl = R2 - line0 < kPencils ? (int)(R2 - line0) : kPencils;
+    return a.dst + (sys / 3) * a.stack + a.off + (sys % 3) * R3 + line0;
+  };
+  constexpr int kPre = RP * kPencils / kBig;
+  float pre[kPre];
+  auto fetch = [&](long long g) {
+    int nl;
+    const float *in = group_ptr(g, nl);
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+      const int i = threadIdx.x + e * kBig, z = i / kPencils, j = i % kPencils;
+      pre[e] = (FULL || (z < R && j < nl)) ? in[z * r2 + j] : 0.f;
+    }
+  };
+  if (blockIdx.x < total) fetch(blockIdx.x);
+  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+    const long long line0 = (g % groups) * kPencils;
+    int nl;
+    float *d0 = group_ptr(g, nl);
+    __syncthreads();               // the previous group's reads of sq are done
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+      const int i = threadIdx.x + e * kBig, z = i / kPencils, j = i % kPencils;
+      if (FULL || z < R) sq[z * kPP + j] = pre[e];
+    }
+    __syncthreads();
+    if (g + gridDim.x < total) fetch(g + gridDim.x);   // in flight during this group
+    f32x16 acc[S::kRounds][NP];
+#pragma unroll
+    for (int rnd = 0; rnd < S::kRounds; ++rnd) {
+      int band, ct;
+      if (S::tile(rnd, band, ct)) {
+        const float *bp[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bp[p] = sq + 32 * (ct + p) + col;   // B(z = k, j)
+        band_gemm<NP>(RP, sc + (32 * band + col) * P, 1, bp, kPP, acc[rnd]);   // C[kz][z]
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rnd = 0; rnd < S::kRounds; ++rnd) {
+      int band, ct;
+      if (S::tile(rnd, band, ct)) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int j = 32 * (ct + p) + col;
+          const int ln = (int)line0 + j;
+          float sxy = 0.f;
+          if (FULL || j < nl) sxy = a.mu[ln / R] + a.mu[ln % R];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int kz = 32 * band + trow(r);
+            if (FULL || kz < R) {
+              const float d = 1.0f + a.lam * (sxy + a.mu[kz]);
+              sq[kz * kPP + j] = (FULL || j < nl) ? acc[rnd][p][r] / (d * d) : 0.f;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rnd = 0; rnd < S::kRounds; ++rnd) {
+      int band, ct;
+      if (S::tile(rnd, band, ct)) {
+        const float *bp[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bp[p] = sq + 32 * (ct + p) + col;
+        f32x16 o[NP];
+        band_gemm<NP>(RP, sc + 32 * band + col, P, bp, kPP, o);   // A(z = i, kz = k) = C[kz][z]
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const int j = 32 * (ct + p) + col;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int z = 32 * band + trow(r);
+            if (FULL || (z < R && j < nl)) d0[z * r2 + j] = o[p][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+int padded(int R) { return 32 * ((R + 31) / 32); }
+size_t plane_lds(int R) { return (size_t)2 * padded(R) * (padded(R) + 1) * sizeof(float); }
+size_t pencil_lds(int R) { return (size_t)(padded(R) * (padded(R) + 1) + padded(R) * kPP) * sizeof(float); }
+
+template <int NT, bool FULL>
+pdg_status fused_level(const FusedArgs &f0, hipStream_t st) {
+  static bool attrs = false;
+  if (!attrs) {
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_kernel<NT, FULL>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)plane_lds(32 * NT)));
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_pencil_kernel<NT, FULL>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)pencil_lds(32 * NT)));
+    attrs = true;
+  }
+  FusedArgs f = f0;
+  const int R = f.R;
+  const long long groups = f.planes / R * (((long long)R * R + kPencils - 1) / kPencils);
+  const unsigned gp = (unsigned)(f.planes < 2048 ? f.planes : 2048);
+  const unsigned gg = (unsigned)(groups < 2048 ? groups : 2048);
+  dct_plane_kernel<NT, FULL><<<gp, kBig, plane_lds(R), st>>>(f, 0);
+  PDG_TRY(launched("dct_plane"));
+  f.src = f.dst;
+  dct_pencil_kernel<NT, FULL><<<gg, kBig, pencil_lds(R), st>>>(f);
+  PDG_TRY(launched("dct_pencil"));
+  dct_plane_kernel<NT, FULL><<<gp, kBig, plane_lds(R), st>>>(f, 1);
   return launched("dct_plane");
+}
+
+template <int NT>
+pdg_status fused_level(const FusedArgs &f, hipStream_t st) {
+  return f.R == 32 * NT ? fused_level<NT, true>(f, st) : fused_level<NT, false>(f, st);
 }
 
 // basis C[k][x] (row-major), its transpose, and mu_k, in float64 then rounded
@@ -406,17 +603,16 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       f.stack = g.size;
       f.off = g.off[l];
       f.planes = (long long)batch * 3 * R;
-      f.cf = ct;
-      f.ci = c;
+      f.c = c;
       f.mu = mu;
       f.R = R;
       f.lam = lam[l];
-      const long long groups = (long long)batch * 3 * (((long long)R * R + 31) / 32);
-      PDG_TRY(launch_plane(f, 0, st));
-      f.src = data;
-      dct_pencil_kernel<<<(unsigned)groups, kThreads, 0, st>>>(f);
-      PDG_TRY(launched("dct_pencil"));
-      PDG_TRY(launch_plane(f, 1, st));
+      switch ((R + 31) / 32) {
+        case 1: PDG_TRY(fused_level<1>(f, st)); break;
+        case 2: PDG_TRY(fused_level<2>(f, st)); break;
+        case 3: PDG_TRY(fused_level<3>(f, st)); break;
+        default: PDG_TRY(fused_level<4>(f, st)); break;
+      }
       continue;
     }
     PassArgs a;

@@ -72,6 +72,8 @@ class Problem:
                  params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
         self.hp = hp or HyperParams()
         self.res = tuple(int(r) for r in res)
+        self.chamfer_mode = chamfer_mode
+        self.precond = precond
         self.points = L._dev(points, torch.float32, "points")
         if points.dim() != 3 or points.shape[1] != 3:
             raise ValueError("points must be (F, 3, N)")
