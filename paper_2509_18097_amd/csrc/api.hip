@@ -129,6 +129,8 @@ pdg_status need(const void *p, const char *name) {
 struct DeformBwdWs {
   uint32_t *keys, *vals;
   int *pstart;
+  float4 *ent;
+  float2 *ent2;
   void *sort;
 };
 DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
@@ -137,6 +139,8 @@ DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
   w.keys = c.take<uint32_t>(ne);
   w.vals = c.take<uint32_t>(ne);
   w.pstart = c.take<int>(row_count(g) + 1);
+  w.ent = c.take<float4>(ne);
+  w.ent2 = c.take<float2>(ne);
   w.sort = c.take<char>((long long)radix_sort_bytes(ne));
   return w;
 }
@@ -153,8 +157,11 @@ pdg_status scatter_entries(const GridDev &g, int segs, const ScatterList &L, uin
 
 ScatterList scatter_list(const uint32_t *keys, const uint32_t *vals, const int *pstart,
                          long long S, const float *x, long long xstride, long long ldx,
-                         const float *lam, long long lstride, long long ldl) {
+                         const float *lam, long long lstride, long long ldl, float4 *ent,
+                         float2 *ent2) {
   ScatterList L;
+  L.ent = ent;
+  L.ent2 = ent2;
   L.keys = keys;
   L.vals = vals;
   L.pstart = pstart;
@@ -322,6 +329,8 @@ struct pdg_problem {
   double *partials = nullptr, *iso_partials = nullptr;
   uint32_t *pkeys = nullptr, *pvals = nullptr, *tkeys = nullptr, *tvals = nullptr;
   int *pstart_p = nullptr, *pstart_t = nullptr;   // row tables (points, template)
+  float4 *ent_p = nullptr, *ent_t = nullptr;       // staged scatter entries
+  float2 *ent2_p = nullptr, *ent2_t = nullptr;
   uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
   void *sort = nullptr;
   NNJob *jobs = nullptr;
@@ -434,6 +443,10 @@ void layout(pdg_problem &p, Carve &c) {
   p.tvals = c.take<uint32_t>(T * L * V);
   p.pstart_p = c.take<int>(T * row_count(p.g) + 1);
   p.pstart_t = c.take<int>(T * row_count(p.g) + 1);
+  p.ent_p = c.take<float4>(T * L * N);
+  p.ent2_p = c.take<float2>(T * L * N);
+  p.ent_t = c.take<float4>(T * L * V);
+  p.ent2_t = c.take<float2>(T * L * V);
   p.nrev = T * N * (p.has_tm ? 2 : 1);
   p.rkeys = c.take<uint32_t>(p.nrev);
   p.rvals = c.take<uint32_t>(p.nrev);
@@ -571,12 +584,14 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       ScatterLists sl;
       sl.count = 1;
       sl.list[0] = scatter_list(p.pkeys, p.pvals, p.pstart_p, N, p.d.points, 3 * N, N, p.gphat,
-                                3 * N, N);
+                                3 * N, N, p.ent_p, p.ent2_p);
+      PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[0], st));
       if (p.has_tm) {
         sl.list[1] = scatter_list(p.tkeys, p.tvals, p.pstart_t, V, p.xhat, 3 * V, V, p.lam,
-                                  3 * V, V);
+                                  3 * V, V, p.ent_t, p.ent2_t);
         sl.count = 2;
         PDG_TRY(scatter_entries(g, (int)T, sl.list[1], p.tkeys, p.tvals, p.pstart_t, p.sort, st));
+        PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[1], st));
       }
       return launch_gather(g, (int)T, sl, p.grad, st);
     }
@@ -671,8 +686,9 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
     memset(&sl, 0, sizeof sl);
     if (n > 0) {
       sl.count = 1;
-      sl.list[0] = scatter_list(w.keys, w.vals, w.pstart, n, x, 0, n, gout, 0, n);
+      sl.list[0] = scatter_list(w.keys, w.vals, w.pstart, n, x, 0, n, gout, 0, n, w.ent, w.ent2);
       PDG_TRY(scatter_entries(g, 1, sl.list[0], w.keys, w.vals, w.pstart, w.sort, stream));
+      PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
     }
     PDG_TRY(launch_gather(g, 1, sl, ggrids, stream));
   }
@@ -1039,7 +1055,9 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
   }
   // static scatter entries of the input points (fixed positions)
   if (s == PDG_OK) s = scatter_entries(
-      p->g, (int)T, scatter_list(p->pkeys, p->pvals, p->pstart_p, N, pd->points, 3 * N, N, nullptr, 0, 0),
+      p->g, (int)T,
+      scatter_list(p->pkeys, p->pvals, p->pstart_p, N, pd->points, 3 * N, N, nullptr, 0, 0,
+                   nullptr, nullptr),
       p->pkeys, p->pvals, p->pstart_p, p->sort, stream);
   if (s == PDG_OK && p->has_tm)
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,

@@ -120,11 +120,16 @@ struct ScatterList {
   long long xstride, ldx;
   const float *lam;
   long long lstride, ldl;
+  float4 *ent;                 // [nent] staged (fx, fy, fz, lam0) in sorted order
+  float2 *ent2;                // [nent] staged (lam1, lam2)
 };
 struct ScatterLists {
   ScatterList list[2];
   int count;
 };
+// Stages every sorted entry of a list: the stencil fractions of its sample on
+// its level and the three values scattered (ent, ent2).
+pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L, hipStream_t st);
 // grad = level_scale * sum_s w_k(s) lam(s) over the samples s of every list
 // that have node k as a corner of their base cell, for every node of `segs`
 // stacks (grad is overwritten; deterministic summation order).

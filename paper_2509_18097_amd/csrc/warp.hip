@@ -149,28 +149,29 @@ __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const floa
 }
 
 // Row index of a key: seg * RS2 + (R_0^2 + ... + R_{l-1}^2) + z * R + y of
-// the base cell (z, y, x).
-__device__ __forceinline__ long long key_row(const GridDev &g, uint32_t key, long long RS2) {
-  const long long seg = key / g.nodes;
-  const long long rem = key - seg * g.nodes;
+// the base cell (z, y, x).  Keys, node counts and row counts fit 32 bits.
+__device__ __forceinline__ uint32_t key_row(const GridDev &g, uint32_t key, uint32_t RS2) {
+  const uint32_t nodes = (uint32_t)g.nodes;
+  const uint32_t seg = key / nodes;
+  const uint32_t rem = key - seg * nodes;
   int l = g.levels - 1;
-  while (l > 0 && g.noff[l] > rem) --l;
-  long long roff = 0;
-  for (int k = 0; k < l; ++k) roff += (long long)g.res[k] * g.res[k];
-  return seg * RS2 + roff + (rem - g.noff[l]) / g.res[l];
+  while (l > 0 && (uint32_t)g.noff[l] > rem) --l;
+  uint32_t roff = 0;
+  for (int k = 0; k < l; ++k) roff += (uint32_t)(g.res[k] * g.res[k]);
+  return seg * RS2 + roff + (rem - (uint32_t)g.noff[l]) / (uint32_t)g.res[l];
 }
 
 // rstart[q] = first sorted entry whose row index is >= q, q = 0..nrows
 // (rstart[nrows] = nent): thread i writes the table slots between the row of
 // entry i-1 and the row of entry i.
 __global__ __launch_bounds__(256) void row_table_kernel(GridDev g, const uint32_t *__restrict__ keys,
-                                                        long long nent, long long RS2,
-                                                        long long nrows, int *__restrict__ rstart) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                        int nent, uint32_t RS2, uint32_t nrows,
+                                                        int *__restrict__ rstart) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > nent) return;
-  const long long cur = i < nent ? key_row(g, keys[i], RS2) : nrows;
-  const long long prev = i > 0 ? key_row(g, keys[i - 1], RS2) : -1;
-  for (long long q = prev + 1; q <= cur; ++q) rstart[q] = (int)i;
+  const uint32_t cur = i < nent ? key_row(g, keys[i], RS2) : nrows;
+  const long long prev = i > 0 ? (long long)key_row(g, keys[i - 1], RS2) : -1;
+  for (long long q = prev + 1; q <= (long long)cur; ++q) rstart[q] = i;
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ p, long long n, float v) {
@@ -195,6 +196,29 @@ __global__ void upload_kernel(Blob blob, unsigned char *__restrict__ dst, int n)
   for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = blob.b[i];
 }
 
+// ent[i] = (fx, fy, fz, lam0), ent2[i] = (lam1, lam2) of sorted entry i.
+__global__ __launch_bounds__(256) void scatter_stage_kernel(GridDev g, ScatterList L, int nent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nent) return;
+  const uint32_t e = L.vals[i], S = (uint32_t)L.S;
+  const uint32_t segl = e / S;
+  const uint32_t seg = segl / (uint32_t)g.levels;
+  const int R = g.res[segl - seg * (uint32_t)g.levels];
+  const uint32_t s = e - segl * S;
+  const float *X = L.x + (long long)seg * L.xstride;
+  const float *Lm = L.lam + (long long)seg * L.lstride;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  if (R > 1) {
+    int ii;
+    bool in;
+    stencil1(R, X[s], ii, fx, in);
+    stencil1(R, X[L.ldx + s], ii, fy, in);
+    stencil1(R, X[2 * L.ldx + s], ii, fz, in);
+  }
+  L.ent[i] = make_float4(fx, fy, fz, Lm[s]);
+  L.ent2[i] = make_float2(Lm[L.ldl + s], Lm[2 * L.ldl + s]);
+}
+
 // Gather form of the scatter: one block per (segment, level, node plane z,
 // band of node rows y0..y1-1) writes all three channels of that band, every
 // node exactly once (no zero fill, no read-modify-write in HBM).
@@ -217,6 +241,7 @@ __global__ void upload_kernel(Blob blob, unsigned char *__restrict__ dst, int n)
 constexpr int kGatherThreads = 256;
 constexpr int kBandFloats = 2048;          // LDS floats per channel of a band
 constexpr unsigned long long kNoSeg = ~0ull;   // no (range, key) pair takes this value
+constexpr uint32_t kNoKey32 = 0xffffffffu;
 
 struct GatherPlan {
   int levels;
@@ -232,9 +257,10 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, Gathe
                                                                 ScatterLists sl,
                                                                 float *__restrict__ grad) {
   __shared__ float band[3 * kBandFloats];
-  __shared__ double buf[12][kGatherThreads];
+  __shared__ double wtail[kGatherThreads / 64][12];   // per-wave scan totals
   __shared__ unsigned long long skey[kGatherThreads + 1];   // (range << 32) | key
   __shared__ double carry[2][12];
+  __shared__ unsigned s_mask[2];             // (range, class) rounds with runs ending
   const long long blk = blockIdx.x;
   int l = 0;
   while (l + 1 < gp.levels && blk >= gp.bfirst[l + 1]) ++l;
@@ -249,60 +275,80 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, Gathe
   const int band_n = rows * R;
   for (int i = t; i < 3 * band_n; i += kGatherThreads) band[i] = 0.f;
 
-  // the (list, cell plane) ranges of this band, in a fixed order
-  __shared__ int rlo[4], rlen[4], rli[4], rdz[4], s_nr, s_total;
+  // the (list, cell plane) ranges of this band, in a fixed order; their
+  // bounds are fetched by eight threads at once
+  __shared__ int rlo[4], rlen[4], rli[4], rdz[4], s_total, s_bound[8];
+  const int zc_max = R > 1 ? R - 2 : 0;
+  const int cy_lo = y0 > 0 ? y0 - 1 : 0, cy_hi = y1 - 1 < zc_max ? y1 - 1 : zc_max;
+  if (t < 8) {
+    const int li = t >> 2, pass = (t >> 1) & 1, hi = t & 1;
+    const int zc = z - 1 + pass;
+    int v = 0;
+    if (li < sl.count && zc >= 0 && zc <= zc_max && cy_lo <= cy_hi) {
+      const long long row = seg * gp.RS2 + gp.roff2[l] + (long long)zc * R;
+      v = sl.list[li].pstart[row + (hi ? cy_hi + 1 : cy_lo)];
+    }
+    s_bound[t] = v;
+  }
+  __syncthreads();
   if (t == 0) {
     int nr = 0, total = 0;
-    const int zc_max = R > 1 ? R - 2 : 0;
-    const int cy_lo = y0 > 0 ? y0 - 1 : 0, cy_hi = y1 - 1 < zc_max ? y1 - 1 : zc_max;
-    for (int li = 0; li < sl.count; ++li)
-      for (int pass = 0; pass < 2; ++pass) {
-        const int zc = z - 1 + pass;
-        if (zc < 0 || zc > zc_max || cy_lo > cy_hi) continue;
-        const long long row = seg * gp.RS2 + gp.roff2[l] + (long long)zc * R;
-        const int lo = sl.list[li].pstart[row + cy_lo], hi = sl.list[li].pstart[row + cy_hi + 1];
-        if (hi <= lo) continue;
-        rlo[nr] = lo;
-        rlen[nr] = hi - lo;
-        rli[nr] = li;
-        rdz[nr] = z - zc;
-        total += hi - lo;
-        ++nr;
-      }
-    s_nr = nr;
+    for (int q = 0; q < 4; ++q) {
+      const int lo = s_bound[2 * q], hi = s_bound[2 * q + 1];
+      if (hi <= lo) continue;
+      rlo[nr] = lo;
+      rlen[nr] = hi - lo;
+      rli[nr] = q >> 1;
+      rdz[nr] = 1 - (q & 1);                 // cell plane z - 1: dz = 1; z: dz = 0
+      total += hi - lo;
+      ++nr;
+    }
     s_total = total;
   }
   const long long kbase = seg * g.nodes + g.noff[l];
   bool carried = false;
   __syncthreads();
-  const int total = s_total, nr = s_nr;
+  const int total = s_total;
+  // entry v of the concatenated ranges: (range, sorted index)
+  auto locate = [&](int v, int &r) {
+    r = 0;
+    while (v >= rlen[r]) v -= rlen[r++];
+    return rlo[r] + v;
+  };
+  // this thread's entry of the next chunk, fetched one chunk ahead
+  uint32_t nkey = kNoKey32;
+  float4 ne = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 ne2 = make_float2(0.f, 0.f);
+  int nrng = 0;
+  auto fetch = [&](int v) {
+    if (v < total) {
+      const int i = locate(v, nrng);
+      const ScatterList &L = sl.list[rli[nrng]];
+      nkey = L.keys[i];
+      ne = L.ent[i];
+      ne2 = L.ent2[i];
+    }
+  };
+  fetch(t);
   for (int c0 = 0, chunk = 0; c0 < total; c0 += kGatherThreads, ++chunk) {
     const int n = total - c0 < kGatherThreads ? total - c0 : kGatherThreads;
+    const uint32_t ckey = nkey;
+    const float4 ce = ne;
+    const float2 ce2 = ne2;
+    const int crng = nrng;
+    nkey = kNoKey32;
+    fetch(c0 + kGatherThreads + t);        // in flight during this chunk
+    if (t == 0) s_mask[chunk & 1] = 0u;
     double p[12];
     unsigned long long key = kNoSeg;
     int my_range = -1;
     if (t < n) {
-      int v = c0 + t, r = 0;
-      while (v >= rlen[r]) v -= rlen[r++];
-      const ScatterList &L = sl.list[rli[r]];
-      const int i = rlo[r] + v;
-      my_range = r;
-      key = ((unsigned long long)r << 32) | L.keys[i];
-      const uint32_t s = L.vals[i] % (uint32_t)L.S;
-      const float *X = L.x + seg * L.xstride;
-      const float *Lm = L.lam + seg * L.lstride;
-      float fx = 0.f, fy = 0.f, fz = 0.f;
-      if (R > 1) {
-        int ii;
-        bool in;
-        stencil1(R, X[s], ii, fx, in);
-        stencil1(R, X[L.ldx + s], ii, fy, in);
-        stencil1(R, X[2 * L.ldx + s], ii, fz, in);
-      }
-      const float lv[3] = {Lm[s], Lm[L.ldl + s], Lm[2 * L.ldl + s]};
+      my_range = crng;
+      key = ((unsigned long long)crng << 32) | ckey;
+      const float lv[3] = {ce.w, ce2.x, ce2.y};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float w = corner_weight(q | (rdz[r] << 2), fx, fy, fz);
+        const float w = corner_weight(q | (rdz[crng] << 2), ce.x, ce.y, ce.z);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[4 * c + q] = (double)w * (double)lv[c];
       }
@@ -313,26 +359,47 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, Gathe
       skey[t] = key;
     }
     if (t == 0) {
-      unsigned long long nk = kNoSeg;
-      if (c0 + n < total) {
-        int v = c0 + n, r = 0;
-        while (v >= rlen[r]) v -= rlen[r++];
-        nk = ((unsigned long long)r << 32) | sl.list[rli[r]].keys[rlo[r] + v];
-      }
-      skey[n] = nk;
+      // the next chunk's first entry is this thread's prefetched one
+      skey[n] = c0 + n < total ? (((unsigned long long)nrng << 32) | nkey) : kNoSeg;
     }
-    __syncthreads();
-    for (int off = 1; off < n; off <<= 1) {
-      if (t < n) {
+    if (t >= n) {
 #pragma unroll
-        for (int v2 = 0; v2 < 12; ++v2) buf[v2][t] = p[v2];
-      }
-      __syncthreads();
-      if (t < n && t >= off && skey[t - off] == key) {
+      for (int v2 = 0; v2 < 12; ++v2) p[v2] = 0.0;
+    }
+    // segmented inclusive scan within the wave (equal keys are contiguous, so
+    // equal keys at distance `off` mean one run in between)
+    const int lane = t & 63, wv = t >> 6;
+    const unsigned klo = (unsigned)key, khi = (unsigned)(key >> 32);
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned olo = __shfl_up(klo, off, 64), ohi = __shfl_up(khi, off, 64);
+      const bool same = lane >= off && olo == klo && ohi == khi;
 #pragma unroll
-        for (int v2 = 0; v2 < 12; ++v2) p[v2] = buf[v2][t - off] + p[v2];
+      for (int v2 = 0; v2 < 12; ++v2) {
+        const double o = __shfl_up(p[v2], off, 64);
+        if (same) p[v2] = o + p[v2];
       }
-      __syncthreads();
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int v2 = 0; v2 < 12; ++v2) wtail[wv][v2] = p[v2];
+    }
+    __syncthreads();                         // skey, wave tails
+    // carry into this wave's leading run from the (fully used) waves before it
+    if (wv > 0 && 64 * wv < n) {
+      const unsigned long long k0 = skey[64 * wv];
+      if (key == k0) {
+        double cin[12];
+#pragma unroll
+        for (int v2 = 0; v2 < 12; ++v2) cin[v2] = 0.0;
+        for (int j = wv - 1; j >= 0; --j) {
+          if (skey[64 * j + 63] != k0) break;
+#pragma unroll
+          for (int v2 = 0; v2 < 12; ++v2) cin[v2] += wtail[j][v2];
+          if (skey[64 * j] != k0) break;       // the run starts inside wave j
+        }
+#pragma unroll
+        for (int v2 = 0; v2 < 12; ++v2) p[v2] = cin[v2] + p[v2];
+      }
     }
     const bool next_carried = skey[n - 1] == skey[n];
     const bool last = t < n && skey[t + 1] != key;     // last entry of its run in this chunk
@@ -343,22 +410,25 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, Gathe
     const int cell = last ? (int)((long long)(uint32_t)key - kbase) : 0;
     const int cx = cell % R, cy = (cell / R) % R;
     const int cls = last ? (cx & 1) | ((cy & 1) << 1) : -1;
-    for (int rr = 0; rr < nr; ++rr)
-      for (int cxy = 0; cxy < 4; ++cxy) {
-        if (cls == cxy && my_range == rr) {
+    if (cls >= 0) atomicOr(&s_mask[chunk & 1], 1u << (4 * my_range + cls));
+    __syncthreads();
+    // only the (range, class) rounds that have runs ending in this chunk
+    for (unsigned m = s_mask[chunk & 1]; m; m &= m - 1) {
+      const int bit = __builtin_ctz(m);
+      if (cls == (bit & 3) && my_range == (bit >> 2)) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int x = cx + (q & 1), y = cy + (q >> 1);
-            if (x < R && y >= y0 && y < y1) {
-              const int o = (y - y0) * R + x;
+        for (int q = 0; q < 4; ++q) {
+          const int x = cx + (q & 1), y = cy + (q >> 1);
+          if (x < R && y >= y0 && y < y1) {
+            const int o = (y - y0) * R + x;
 #pragma unroll
-              for (int c = 0; c < 3; ++c)
-                band[c * band_n + o] = __fmaf_rn(g.scale, (float)p[4 * c + q], band[c * band_n + o]);
-            }
+            for (int c = 0; c < 3; ++c)
+              band[c * band_n + o] = __fmaf_rn(g.scale, (float)p[4 * c + q], band[c * band_n + o]);
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
+    }
     carried = next_carried;
   }
   __syncthreads();
@@ -439,9 +509,16 @@ long long row_count(const GridDev &g) {
 pdg_status launch_row_table(const GridDev &g, const uint32_t *keys, long long nent, int segs,
                             int *rstart, hipStream_t st) {
   const long long RS2 = row_count(g);
-  row_table_kernel<<<div_up(nent + 1, 256), 256, 0, st>>>(g, keys, nent, RS2,
-                                                            (long long)segs * RS2, rstart);
+  row_table_kernel<<<div_up(nent + 1, 256), 256, 0, st>>>(g, keys, (int)nent, (uint32_t)RS2,
+                                                            (uint32_t)(segs * RS2), rstart);
   return launched("row_table");
+}
+
+pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L, hipStream_t st) {
+  const long long nent = (long long)segs * g.levels * L.S;
+  if (nent <= 0) return PDG_OK;
+  scatter_stage_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, L, (int)nent);
+  return launched("scatter_stage");
 }
 
 pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, float *grad,
