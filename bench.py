@@ -41,12 +41,12 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 PAIR_OPS = 8          # 3 sub + 3 mul + 2 add per pair under the difference-form contract
 PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
-# factors from a 1 GiB copy), recorded in profiles/c2_step_bf16_dct_kernels.md for the
-# kernel source whose SHA-256 starts with the given prefix; reported only while the
-# source is unchanged.
+# factors from a 1 GiB copy; mean over the 8 timed steps), recorded in
+# profiles/nn_screen_c2_bf16_dct.md for the kernel source whose SHA-256 starts
+# with the given prefix; reported only while the source is unchanged.
 PMC_TRAFFIC = {
-    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "0fb962627afa7721",
-                         2 * 1409573.6 * 1024 + 23387.1 * 1024),
+    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "38b3de73ddda65ce",
+                         (2 * 245306.25 + 85034.796875) * 1024),
 }
 
 
@@ -119,26 +119,31 @@ def time_steps(prob, steps, warmup):
 
 
 def time_stages(prob, reps=3):
-    """Each stage alone, `reps` times, bracketed by events on the stream it is
-    enqueued on (torch's current stream)."""
+    """Per-stage times inside real iterations: each rep runs the seven stages
+    in step order, with an event recorded between consecutive stages on the
+    stream they are enqueued on (torch's current stream), so every stage sees
+    the state an iteration gives it (e.g. the nearest-neighbour screen is warm
+    started from the previous iteration's assignment, not from its own)."""
     import torch
     from paper_2509_18097_amd import _lib as L
     st = torch.cuda.current_stream()
-    out = {}
-    for name in L.STAGES:
-        prob.stage(name)                 # warm
-        torch.cuda.synchronize()
-        t0 = screen_tiles(prob)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(st)
-        for _ in range(reps):
+    names = L.STAGES
+    for name in names:                   # warm
+        prob.stage(name)
+    torch.cuda.synchronize()
+    out = {name: 0.0 for name in names}
+    t0 = screen_tiles(prob)              # only the NN stage advances the counter
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ev[0].record(st)
+        for k, name in enumerate(names):
             prob.stage(name)
-        b.record(st)
+            ev[k + 1].record(st)
         torch.cuda.synchronize()
-        out[name] = a.elapsed_time(b) / reps
-        if name == "nn" and t0 is not None:
-            out["nn_tiles"] = (screen_tiles(prob) - t0) / reps
+        for k, name in enumerate(names):
+            out[name] += ev[k].elapsed_time(ev[k + 1]) / reps
+    if t0 is not None:
+        out["nn_tiles"] = (screen_tiles(prob) - t0) / reps
     return out
 
 
@@ -181,7 +186,10 @@ def dct_flops(prob):
 
 
 def roofline(prob, stages, chamfer, precond):
-    """Roofline of the two heavy stages; the dominant one is returned first."""
+    """Roofline of the nearest-neighbour kernel (the NN stage is exactly one
+    launch of it; the largest per-step kernel share in the committed
+    rocprofv3 summary) and, second, of the preconditioner stage (several
+    launches, reported as one unit)."""
     nn_ms, pre_ms = stages["nn"], stages["precond"]
     pairs = nn_pairs(prob)
     if chamfer == "bf16":
@@ -216,7 +224,7 @@ def roofline(prob, stages, chamfer, precond):
                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
                "kernel": "cg_a_kernel/cg_b_kernel (+ reductions)", "bytes_per_stage": b,
                "stage_ms": round(pre_ms, 4)}
-    return (nn, pre) if nn_ms >= pre_ms else (pre, nn)
+    return nn, pre
 
 
 def cpu_baseline(seq, workers):

@@ -237,8 +237,10 @@ pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t u
  * ADAM updates params/m/v, so replaying them alone changes the state exactly
  * as the step would. */
 typedef enum {
-  PDG_STAGE_WARP = 0,     /* Eq. 1 and 8: P^_t and the template chain          */
-  PDG_STAGE_NN = 1,       /* Eq. 12: nearest neighbours of every Chamfer term   */
+  PDG_STAGE_WARP = 0,     /* Eq. 1 and 8: P^_t and the template chain (and, in
+                             the bf16 mode, the screen packs of the warped sets) */
+  PDG_STAGE_NN = 1,       /* Eq. 12: nearest neighbours of every Chamfer term
+                             (one kernel launch)                                */
   PDG_STAGE_LOSS = 2,     /* Eq. 9, 11, 13-18: losses and confidence weights    */
   PDG_STAGE_GRAD = 3,     /* adjoints wrt the warped positions, reverse sweep   */
   PDG_STAGE_SCATTER = 4,  /* transpose of Eq. 1 into the grid gradient          */

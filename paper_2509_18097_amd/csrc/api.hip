@@ -231,8 +231,8 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
     w.pack_b = c.take<uint4>(2 * m);
     w.coords_a = c.take<float4>(n);
     w.coords_b = c.take<float4>(m);
-    w.boxes_a = c.take<float4>(2 * screen_tiles(n));
-    w.boxes_b = c.take<float4>(2 * screen_tiles(m));
+    w.boxes_a = c.take<float4>(screen_box_count(n));
+    w.boxes_b = c.take<float4>(screen_box_count(m));
     w.perm_a = c.take<uint32_t>(n);
     w.perm_b = c.take<uint32_t>(m);
     w.maxnorm = c.take<unsigned>(2);
@@ -427,7 +427,7 @@ void layout(pdg_problem &p, Carve &c) {
   p.wconf = c.take<double>(T);
   p.terms = c.take<double>(8);
   p.partials = c.take<double>(4 * T * kLossBlocks);
-  p.iso_partials = c.take<double>(kLossBlocks);
+  p.iso_partials = c.take<double>(kIsoBlocks);
   p.grad = c.take<float>(T * P);
   p.pgrad = c.take<float>(T * P);
   p.gphat = c.take<float>(T * 3 * N);
@@ -464,12 +464,12 @@ void layout(pdg_problem &p, Carve &c) {
     // every segment packs its moving set A and its fixed set B
     // moving sets (P^_t, then X_t) are packed every step, the frames P_1..P_T once
     p.pack_rows = T * N + (p.has_tm ? T * V : 0) + T * N;
-    p.box_tiles = T * screen_tiles(N) + (p.has_tm ? T * screen_tiles(V) : 0) + T * screen_tiles(N);
+    p.box_tiles = T * screen_box_count(N) + (p.has_tm ? T * screen_box_count(V) : 0) + T * screen_box_count(N);
     p.ssets = c.take<ScreenSet>(p.nseg + T);
     p.sjobs = c.take<ScreenJob>(p.njobs);
     p.packs = c.take<uint4>(2 * p.pack_rows);
     p.coords = c.take<float4>(p.pack_rows);
-    p.boxes = c.take<float4>(2 * p.box_tiles);
+    p.boxes = c.take<float4>(p.box_tiles);
     p.maxnorm = c.take<unsigned>(p.nseg + T);
     p.fperm = c.take<int>(F * N);
     p.tperm = c.take<int>(V);
@@ -537,14 +537,15 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
           PDG_TRY(launch_warp(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0, V,
                               p.xhat + (t + 1) * 3 * V, 0, V, V, 1, st));
       }
-      return PDG_OK;
-    case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
-        // screen warm-started from the previous iteration's assignment
+        // screen packs of the moving sets (P^_t, X_t), which change every step
         PDG_TRY(launch_fill((float *)p.maxnorm, p.nseg, 0.f, st));
         PDG_TRY(launch_screen_pack(p.ssets, p.nseg, p.max_n, st));
-        return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
       }
+      return PDG_OK;
+    case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
+      if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN)   // warm start: last step's assignment
+        return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
       return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
     case PDG_STAGE_LOSS: {  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
       PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
@@ -990,9 +991,9 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     long long row = 0, tile = 0;
     auto add_set = [&](const float *x, long long n, const int *perm, unsigned *mx) {
       ssets.push_back(screen_set(x, n, perm, p->packs + 2 * row, p->coords + row,
-                                 p->boxes + 2 * tile, mx));
+                                 p->boxes + tile, mx));
       row += n;
-      tile += screen_tiles(n);
+      tile += screen_box_count(n);
     };
     for (int s = 0; s < p->nseg; ++s) {        // moving sets: P^_t keeps P_t's order, X_t X_0's
       const ChSeg &q = segs[s];

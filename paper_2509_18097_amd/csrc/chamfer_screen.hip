@@ -284,10 +284,23 @@ __device__ __forceinline__ float wave_best_max(const QState *st, const bool *ok)
   return m;
 }
 
+// Workgroups are dealt to the 8 XCDs round robin; remap the linear block id so
+// that each XCD takes one contiguous run of (job, query tile) pairs: Morton-
+// adjacent query tiles visit mostly the same candidate tiles, which then stay
+// in that XCD's L2.
+constexpr int kXcds = 8;
+
+// The grid is 1-D with a multiple of 8 blocks, so lin -> tile is a bijection;
+// tile = job * qt + query tile, tiles >= nblk do nothing.
 __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__restrict__ jobs,
-                                                             int warm) {
-  const ScreenJob J = jobs[blockIdx.y];
-  const int q0 = blockIdx.x * kQPerBlock;
+                                                             int warm, unsigned qt, unsigned nblk) {
+  const unsigned lin = blockIdx.x;
+  const unsigned per = gridDim.x / kXcds;
+  const unsigned tile = (lin % kXcds) * per + lin / kXcds;
+  if (tile >= nblk) return;
+  const unsigned bx = tile % qt, by = tile / qt;
+  const ScreenJob J = jobs[by];
+  const int q0 = bx * kQPerBlock;
   if (q0 >= J.nq) return;
   __shared__ uint4 spack[2][kCTile * 2];
   __shared__ int tlist[kListMax];
@@ -340,10 +353,10 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
       bq[h][e] = *reinterpret_cast<const __bf16 *>(&b);
     }
   }
-  const float4 qmin = J.qboxes[2 * blockIdx.x], qmax = J.qboxes[2 * blockIdx.x + 1];
+  const float4 qmin = J.qboxes[2 * bx], qmax = J.qboxes[2 * bx + 1];
   const int ntiles = (J.nc + kTile - 1) / kTile;
   const int qtiles = (J.nq + kTile - 1) / kTile;
-  const int start = (int)((long long)blockIdx.x * ntiles / qtiles);
+  const int start = (int)((long long)bx * ntiles / qtiles);
   {
     const float m = wave_best_max(st, ok);
     if (lane == 0) wmax[0][wv] = m;
@@ -452,8 +465,14 @@ pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipSt
 pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int warm,
                             hipStream_t st) {
   if (njobs <= 0 || max_nq <= 0) return PDG_OK;
-  dim3 grid(div_up(max_nq, kQPerBlock), njobs);
-  nn_screen_kernel<<<grid, kThreads, 0, st>>>(jobs, warm);
+  const unsigned qt = div_up(max_nq, kQPerBlock);
+  const unsigned long long nblk = (unsigned long long)qt * njobs;
+  const unsigned long long padded = (nblk + kXcds - 1) / kXcds * kXcds;
+  if (padded >= (1ull << 31)) {
+    set_error("nn screen: %llu workgroups exceed the launch limit", padded);
+    return PDG_EINVAL;
+  }
+  nn_screen_kernel<<<(unsigned)padded, kThreads, 0, st>>>(jobs, warm, qt, (unsigned)nblk);
   return launched("nn_screen");
 }
 

@@ -180,6 +180,8 @@ struct ScreenJob {           // one directed search: packed queries over packed 
   unsigned long long *tiles; // nullable: += candidate tiles screened
 };
 inline long long screen_tiles(long long n) { return (n + 255) / 256; }
+// float4 entries of a set's box array (min and max corner per tile)
+inline long long screen_box_count(long long n) { return 2 * screen_tiles(n); }
 // keys = 30-bit Morton codes over [-1, 1]^3 of x ([3][ld] SoA, n points), vals = index
 pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, uint32_t *vals,
                          hipStream_t st);
@@ -187,6 +189,7 @@ pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipSt
 pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int warm,
                             hipStream_t st);
 constexpr int kLossBlocks = 32;  // fixed partial count per (segment, direction)
+constexpr int kIsoBlocks = 1024; // fixed partial count of the isometry loss
 // partials[(seg*2+dir)*kLossBlocks + blk]; then losses[seg*2+dir] = mean.
 pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double *partials,
                                double *losses, hipStream_t st);
@@ -250,7 +253,7 @@ struct IsoArgs {
   int V, E, T;
   float *sig;          // [T][E]   sign of the length change at frame t
   float *u;            // [T][3][E] unit edge vector at frame t
-  double *partials;    // [kLossBlocks]
+  double *partials;    // [kIsoBlocks]
   const int *inc_off;  // [V+1] incidence offsets
   const uint32_t *inc; // [2E] sorted incidences: edge*2 + side
   float *gx;           // [T][3][V] direct gradient (accumulated into)

@@ -218,7 +218,7 @@ __global__ void assemble_kernel(AssembleArgs a) {
     }
     if (E > 0) {
       double s = 0.0;
-      for (int b = 0; b < kLossBlocks; ++b) s += a.iso_partials[b];
+      for (int b = 0; b < kIsoBlocks; ++b) s += a.iso_partials[b];
       l_iso = (double)a.w_iso * s / ((double)T * (double)E);
     }
   } else {
@@ -263,7 +263,7 @@ pdg_status launch_set_int(int *p, int value, hipStream_t st) {
 
 pdg_status launch_iso_edges(const IsoArgs &a, hipStream_t st) {
   if (a.T <= 0 || a.E <= 0) return PDG_OK;
-  iso_edge_kernel<<<kLossBlocks, 256, 0, st>>>(a);
+  iso_edge_kernel<<<kIsoBlocks, 256, 0, st>>>(a);
   return launched("iso_edge");
 }
 
