@@ -179,10 +179,11 @@ def cg_bytes(prob):
 
 def dct_flops(prob):
     """Matrix-core flops of one DCT preconditioner stage: six 1-D transforms
-    (three forward, three inverse), each a length-R contraction (2R flops) per
-    grid value; R = 1 levels are skipped."""
+    (three forward, three inverse) per grid value; a dense length-R transform
+    is 2R flops per value, the even/odd form used for R = 64 and 128 half of
+    that (two length-R/2 products); R = 1 levels are skipped."""
     T = prob.T
-    return sum(6 * 2 * r * T * 3 * r ** 3 for r in prob.res if r > 1)
+    return sum(6 * (r if r in (64, 128) else 2 * r) * T * 3 * r ** 3 for r in prob.res if r > 1)
 
 
 def roofline(prob, stages, chamfer, precond):
@@ -215,7 +216,7 @@ def roofline(prob, stages, chamfer, precond):
         a = f / (pre_ms * 1e-3) / 1e12
         pre = {"bound": "mfma", "achieved": round(a, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                "unit": "TFLOP/s", "frac": round(a / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-               "kernel": "dct_plane_kernel x2 + dct_pencil_kernel per level (12 launches)",
+               "kernel": "DCT stage: plane, pencil, plane kernels per level (12 launches)",
                "flops_per_stage": f, "stage_ms": round(pre_ms, 4)}
     else:
         b = cg_bytes(prob)

@@ -531,12 +531,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
     case PDG_STAGE_WARP:  // P^_t = warp(G_t, P_{t-1}); X_t = warp(G_t, X_{t-1}) (Eq. 1, 8)
       PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T,
                           st));
-      if (p.has_tm) {
-        PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
-        for (long long t = 0; t < T; ++t)
-          PDG_TRY(launch_warp(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0, V,
-                              p.xhat + (t + 1) * 3 * V, 0, V, V, 1, st));
-      }
+      if (p.has_tm)
+        PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T, st));
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
         // screen packs of the moving sets (P^_t, X_t), which change every step
         PDG_TRY(launch_fill((float *)p.maxnorm, p.nseg, 0.f, st));
@@ -573,13 +569,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, nullptr, p.rkeys, p.rvals,
                                          p.nrev, (float)h.alpha, p.w, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(iso_args(p), st));
-      if (p.has_tm) {
-        PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
-        for (long long k = T - 1; k >= 1; --k)
-          PDG_TRY(launch_chain_adjoint(g, p.d.params + k * P, p.xhat + k * 3 * V, V,
-                                       p.lam + k * 3 * V, V, p.gxhat + (k - 1) * 3 * V, V,
-                                       p.lam + (k - 1) * 3 * V, V, V, st));
-      }
+      if (p.has_tm)
+        PDG_TRY(launch_chain_reverse(g, p.d.params, P, p.xhat, p.gxhat, p.lam, V, (int)T, st));
       return PDG_OK;
     case PDG_STAGE_SCATTER: {  // dL/dG: deterministic transpose of Eq. 1
       ScatterLists sl;

@@ -46,7 +46,8 @@
 // farther than the best and can be neither the nearest nor a tie.  Tiles are
 // listed by that test against the warm-start bests, visited starting from the
 // candidate tile of the same Morton rank, and re-tested against the improving
-// bests before each visit.  Ties are broken on the original indices, which the
+// bests before each visit; each wave also skips a visited tile whose box
+// distance to its own 64 queries exceeds their largest best.  Ties are broken on the original indices, which the
 // packed coordinates carry, so the result is the exact search's bit for bit.
 #include "common.h"
 
@@ -354,6 +355,24 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
     }
   }
   const float4 qmin = J.qboxes[2 * bx], qmax = J.qboxes[2 * bx + 1];
+  // this wave's 64 queries: their box (wave-uniform)
+  float4 wmin = make_float4(__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), 0.f);
+  float4 wmaxc = make_float4(-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf(), 0.f);
+#pragma unroll
+  for (int h = 0; h < kQB; ++h)
+    if (ok[h]) {
+      wmin = make_float4(fminf(wmin.x, st[h].x), fminf(wmin.y, st[h].y), fminf(wmin.z, st[h].z), 0.f);
+      wmaxc = make_float4(fmaxf(wmaxc.x, st[h].x), fmaxf(wmaxc.y, st[h].y), fmaxf(wmaxc.z, st[h].z), 0.f);
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    wmin.x = fminf(wmin.x, __shfl_xor(wmin.x, o, 64));
+    wmin.y = fminf(wmin.y, __shfl_xor(wmin.y, o, 64));
+    wmin.z = fminf(wmin.z, __shfl_xor(wmin.z, o, 64));
+    wmaxc.x = fmaxf(wmaxc.x, __shfl_xor(wmaxc.x, o, 64));
+    wmaxc.y = fmaxf(wmaxc.y, __shfl_xor(wmaxc.y, o, 64));
+    wmaxc.z = fmaxf(wmaxc.z, __shfl_xor(wmaxc.z, o, 64));
+  }
+  const bool wany = wmin.x <= wmaxc.x;       // the wave has at least one query
   const int ntiles = (J.nc + kTile - 1) / kTile;
   const int qtiles = (J.nq + kTile - 1) / kTile;
   const int start = (int)((long long)bx * ntiles / qtiles);
@@ -400,10 +419,9 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
     }
     int buf = 0;
     while (i < count) {
-      {
-        const float m = wave_best_max(st, ok);
-        if (lane == 0) wmax[it & 1][wv] = m;
-      }
+      const float wbest = wave_best_max(st, ok);
+      if (lane == 0) wmax[it & 1][wv] = wbest;
+      const float4 tmin = J.cboxes[2 * tlist[i]], tmax = J.cboxes[2 * tlist[i] + 1];
       __syncthreads();          // tile tlist[i] is in spack[buf]; the other buffer is free
       bmax = fmaxf(fmaxf(wmax[it & 1][0], wmax[it & 1][1]), fmaxf(wmax[it & 1][2], wmax[it & 1][3]));
       ++it;
@@ -413,7 +431,9 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
       if (more) fetch_tile(J, tlist[nxt] * kTile, regs);   // in flight while this tile is screened
       const int c0 = tlist[i] * kTile;
       const int left = (J.nc - c0 + 31) / 32;
-      const int nsub = left < kCTile / 32 ? left : kCTile / 32;
+      // the wave skips a tile that cannot beat any of its own queries' bests
+      const bool wskip = !wany || box_lb(wmin, wmaxc, tmin, tmax) * kCullSlack > wbest;
+      const int nsub = wskip ? 0 : (left < kCTile / 32 ? left : kCTile / 32);
       for (int sub = 0; sub < nsub; ++sub) {
         const uint4 raw = spack[buf][2 * (sub * 32 + (lane & 31)) + half];
         const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);

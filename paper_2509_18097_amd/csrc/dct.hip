@@ -470,6 +470,364 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Even/odd form for R = 64 and 128.  C[k][R-1-x] = (-1)^k C[k][x], so a
+// forward transform needs only the left half of C on folded inputs,
+//   out[2p] = sum_{x<R/2} C[2p][x] (in[x] + in[R-1-x]),
+//   out[2p+1] = sum_{x<R/2} C[2p+1][x] (in[x] - in[R-1-x]),
+// and an inverse one two half products combined,
+//   E[x] = sum_p C[2p][x] s[2p], O[x] = sum_p C[2p+1][x] s[2p+1],
+//   out[x] = E[x] + O[x], out[R-1-x] = E[x] - O[x]   (x < R/2):
+// half the matrix-core work of the dense form.  Between the passes the spectra
+// are kept in the order [even frequencies | odd frequencies] along each axis
+// (index p stands for frequency 2p below R/2 and 2(p - R/2) + 1 above), which
+// the scale and the inverse passes read consistently.  LDS holds the two half
+// bases Ce[p][x] = C[2p][x], Co[p][x] = C[2p+1][x] (x < R/2, pitch R/2 + 1).
+constexpr int kPencilsEO = 128;
+constexpr int kPQ = kPencilsEO + 1;
+
+__device__ __forceinline__ void load_basis_eo(float *sh, const float *c, int R, int RH, int PH) {
+  for (int i = threadIdx.x; i < R * RH; i += kBig) {
+    const int k = i / RH, x = i % RH;
+    sh[(k & 1) * RH * PH + (k >> 1) * PH + x] = c[k * R + x];
+  }
+}
+
+__device__ __forceinline__ float mu_perm(const float *mu, int p, int RH) {
+  return mu[p < RH ? 2 * p : 2 * (p - RH) + 1];
+}
+
+// acc[p] = sum_k A(k) B_p(k) over k < K (a multiple of 16) with
+//   A(k) = a0[k sa] (+ sga a1[-k sa] with FA),  B_p(k) = b0[p][k sb] (+ sgb b1[p][-k sb] with FB);
+// the NP tiles share A.
+template <int NP, bool FA, bool FB>
+__device__ __forceinline__ void fold_gemm(int K, const float *a0, const float *a1, int sa, float sga,
+                                          const float *const *b0, const float *const *b1, int sb,
+                                          float sgb, f32x16 (&acc)[NP]) {
+  const int h = (threadIdx.x >> 5) & 1;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = (f32x16){};
+#pragma unroll 1
+  for (int k0 = 0; k0 < K; k0 += 2 * kCh) {
+    float av[kCh], bv[NP][kCh];
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) {
+      const int k = k0 + 2 * c + h;
+      av[c] = FA ? a0[k * sa] + sga * a1[-k * sa] : a0[k * sa];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) bv[p][c] = FB ? b0[p][k * sb] + sgb * b1[p][-k * sb] : b0[p][k * sb];
+    }
+#pragma unroll
+    for (int c = 0; c < kCh; ++c)
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        acc[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[c], bv[p][c], acc[p], 0, 0, 0);
+  }
+}
+
+// e = sum_k ae[k sa] be[k sb], o = sum_k ao[k sa] bo[k sb] over k < K.
+__device__ __forceinline__ void eo_gemm(int K, const float *ae, const float *ao, int sa,
+                                        const float *be, const float *bo, int sb, f32x16 &e,
+                                        f32x16 &o) {
+  const int h = (threadIdx.x >> 5) & 1;
+  e = (f32x16){};
+  o = (f32x16){};
+#pragma unroll 1
+  for (int k0 = 0; k0 < K; k0 += 2 * kCh) {
+    float a[2][kCh], b[2][kCh];
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) {
+      const int k = k0 + 2 * c + h;
+      a[0][c] = ae[k * sa];
+      b[0][c] = be[k * sb];
+      a[1][c] = ao[k * sa];
+      b[1][c] = bo[k * sb];
+    }
+#pragma unroll
+    for (int c = 0; c < kCh; ++c) {
+      e = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][c], b[0][c], e, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][c], b[1][c], o, 0, 0, 0);
+    }
+  }
+}
+
+// Forward x and y transforms of z-planes: natural (y, x) in, spectra (q, p) out.
+template <int NT>
+__global__ __launch_bounds__(kBig) void dct_plane_eo_fwd_kernel(FusedArgs a) {
+  constexpr int R = 32 * NT, RH = R / 2, P = R + 1, PH = RH + 1, NH = NT / 2;
+  constexpr int NP = NT == 4 ? 2 : 1;          // tiles per wave (one row band)
+  extern __shared__ float lds[];
+  float *sh = lds;                             // Ce, Co
+  float *sp = lds + 2 * RH * PH;               // plane, R x P
+  constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  load_basis_eo(sh, a.c, R, RH, PH);
+  const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
+  const bool act = NT == 4 || w < 4;
+  const int band = w >> 1, ct0 = NT == 4 ? 2 * (w & 1) : (w & 1);
+  auto plane_base = [&](long long plane) {
+    const long long sys = plane / R, z = plane % R;
+    return (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
+  };
+  long long plane = blockIdx.x;
+  if (plane < a.planes) load_rows(sp, P, a.src + plane_base(plane), R, R, R * R);
+  __syncthreads();
+  for (; plane < a.planes; plane += gridDim.x) {
+    const long long base = plane_base(plane);
+    f32x16 acc[NP];
+    if (act) {
+      // along x: t[y][p] = sum_{x<RH} (in[y][x] +- in[y][R-1-x]) C[k(p)][x]
+      const float sg = ct0 < NH ? 1.f : -1.f;
+      const float *a0 = sp + (32 * band + col) * P;
+      const float *b0[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int pc = 32 * (ct0 + p) + col;
+        b0[p] = sh + (pc < RH ? 0 : RH * PH) + (pc % RH) * PH;     // C[k(pc)][x] along x
+      }
+      fold_gemm<NP, true, false>(RH, a0, a0 + R - 1, 1, sg, b0, b0, 1, 0.f, acc);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int pc = 32 * (ct0 + p) + col;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sp[(32 * band + trow(r)) * P + pc] = acc[p][r];
+      }
+    }
+    __syncthreads();
+    constexpr int kPre = R * R / kBig;
+    const long long next = plane + gridDim.x;
+    float pre[kPre];
+    if (next < a.planes) {
+      const float *in = a.src + plane_base(next);
+#pragma unroll
+      for (int e = 0; e < kPre; ++e) pre[e] = in[threadIdx.x + e * kBig];
+    }
+    if (act) {
+      // along y: out[q][p] = sum_{y<RH} C[k(q)][y] (t[y][p] +- t[R-1-y][p])
+      const float sg = band < NH ? 1.f : -1.f;
+      const int qr = 32 * band + col;
+      const float *a0 = sh + (qr < RH ? 0 : RH * PH) + (qr % RH) * PH;   // C[k(q)][y] along y
+      const float *b0[NP], *b1[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int pc = 32 * (ct0 + p) + col;
+        b0[p] = sp + pc;
+        b1[p] = sp + (R - 1) * P + pc;
+      }
+      fold_gemm<NP, false, true>(RH, a0, a0, 1, 0.f, b0, b1, P, sg, acc);
+      float *out = a.dst + base;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int pc = 32 * (ct0 + p) + col;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) out[(32 * band + trow(r)) * R + pc] = acc[p][r];
+      }
+    }
+    __syncthreads();
+    if (next < a.planes) {
+#pragma unroll
+      for (int e = 0; e < kPre; ++e) {
+        const int i = threadIdx.x + e * kBig;
+        sp[(i / R) * P + i % R] = pre[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse y and x transforms: spectra (q, p) in, natural (y, x) out.
+template <int NT>
+__global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a) {
+  constexpr int R = 32 * NT, RH = R / 2, P = R + 1, PH = RH + 1, NH = NT / 2;
+  extern __shared__ float lds[];
+  float *sh = lds;
+  float *sp = lds + 2 * RH * PH;
+  constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  load_basis_eo(sh, a.c, R, RH, PH);
+  const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
+  const bool act = w < NT * NH;                // NT * NH = NH * NT items per phase
+  auto plane_base = [&](long long plane) {
+    const long long sys = plane / R, z = plane % R;
+    return (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
+  };
+  long long plane = blockIdx.x;
+  if (plane < a.planes) load_rows(sp, P, a.src + plane_base(plane), R, R, R * R);
+  __syncthreads();
+  for (; plane < a.planes; plane += gridDim.x) {
+    const long long base = plane_base(plane);
+    f32x16 e, o;
+    // along x (item: spectral row band qb, spatial column tile xt < NH):
+    // t[q][x] = E + O, t[q][R-1-x] = E - O
+    const int qb = w / NH, xt = w % NH;
+    if (act) {
+      const float *arow = sp + (32 * qb + col) * P;
+      eo_gemm(RH, arow, arow + RH, 1, sh + 32 * xt + col, sh + RH * PH + 32 * xt + col, PH, e, o);
+    }
+    __syncthreads();
+    if (act) {
+      const int x = 32 * xt + col;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int q = 32 * qb + trow(r);
+        sp[q * P + x] = e[r] + o[r];
+        sp[q * P + R - 1 - x] = e[r] - o[r];
+      }
+    }
+    __syncthreads();
+    constexpr int kPre = R * R / kBig;
+    const long long next = plane + gridDim.x;
+    float pre[kPre];
+    if (next < a.planes) {
+      const float *in = a.src + plane_base(next);
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) pre[k] = in[threadIdx.x + k * kBig];
+    }
+    // along y (item: spatial row band yb < NH, column tile xc):
+    // out[y][x] = E + O, out[R-1-y][x] = E - O
+    const int yb = w / NT, xc = w % NT;
+    if (act) {
+      const int y = 32 * yb + col, x = 32 * xc + col;
+      eo_gemm(RH, sh + y, sh + RH * PH + y, PH, sp + x, sp + RH * P + x, P, e, o);
+      float *out = a.dst + base;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int yy = 32 * yb + trow(r);
+        out[yy * R + x] = e[r] + o[r];
+        out[(R - 1 - yy) * R + x] = e[r] - o[r];
+      }
+    }
+    __syncthreads();
+    if (next < a.planes) {
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) {
+        const int i = threadIdx.x + k * kBig;
+        sp[(i / R) * P + i % R] = pre[k];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Forward z, spectral scale, inverse z for groups of 128 (qy, qx) lines of
+// one system, in place on dst (spectral order in y and x, natural z).
+template <int NT>
+__global__ __launch_bounds__(kBig) void dct_pencil_eo_kernel(FusedArgs a) {
+  constexpr int R = 32 * NT, RH = R / 2, PH = RH + 1, NH = NT / 2, JT = kPencilsEO / 32;
+  constexpr int NP = NT == 4 ? 2 : 1;
+  extern __shared__ float lds[];
+  float *sh = lds;
+  float *sq = lds + 2 * RH * PH;               // R x kPQ
+  constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  constexpr long long groups = R2 / kPencilsEO;   // per system
+  const long long total = a.planes / R * groups;
+  load_basis_eo(sh, a.c, R, RH, PH);
+  const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
+  // forward tiles: row band fb, column tiles fc0 .. fc0 + NP - 1
+  const int fb = NT == 4 ? (w >> 1) : (w >> 2), fc0 = NT == 4 ? 2 * (w & 1) : (w & 3);
+  // inverse items: spatial row band ib < NH, column tile ic
+  const int ib = w / JT, ic = w % JT;
+  const bool iact = w < NH * JT;
+  auto group_ptr = [&](long long g) {
+    const long long sys = g / groups;
+    return a.dst + (sys / 3) * a.stack + a.off + (sys % 3) * R3 + (g % groups) * kPencilsEO;
+  };
+  constexpr int kPre = R * kPencilsEO / kBig;
+  float pre[kPre];
+  auto fetch = [&](long long g) {
+    const float *in = group_ptr(g);
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+      const int i = threadIdx.x + e * kBig;
+      pre[e] = in[(i / kPencilsEO) * R2 + i % kPencilsEO];
+    }
+  };
+  if (blockIdx.x < total) fetch(blockIdx.x);
+  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+    const long long line0 = (g % groups) * kPencilsEO;
+    float *d0 = group_ptr(g);
+    __syncthreads();               // the previous group's reads of sq are done
+#pragma unroll
+    for (int e = 0; e < kPre; ++e) {
+      const int i = threadIdx.x + e * kBig;
+      sq[(i / kPencilsEO) * kPQ + i % kPencilsEO] = pre[e];
+    }
+    __syncthreads();
+    if (g + gridDim.x < total) fetch(g + gridDim.x);   // in flight during this group
+    // forward z: F[qz][j] = sum_{z<RH} C[k(qz)][z] (s[z][j] +- s[R-1-z][j])
+    f32x16 acc[NP];
+    {
+      const float sg = fb < NH ? 1.f : -1.f;
+      const int qr = 32 * fb + col;
+      const float *a0 = sh + (qr < RH ? 0 : RH * PH) + (qr % RH) * PH;
+      const float *b0[NP], *b1[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int j = 32 * (fc0 + p) + col;
+        b0[p] = sq + j;
+        b1[p] = sq + (R - 1) * kPQ + j;
+      }
+      fold_gemm<NP, false, true>(RH, a0, a0, 1, 0.f, b0, b1, kPQ, sg, acc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int j = 32 * (fc0 + p) + col;
+      const int ln = (int)line0 + j;                 // qy * R + qx
+      const float sxy = mu_perm(a.mu, ln / R, RH) + mu_perm(a.mu, ln % R, RH);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int qz = 32 * fb + trow(r);
+        const float d = 1.0f + a.lam * (sxy + mu_perm(a.mu, qz, RH));
+        sq[qz * kPQ + j] = acc[p][r] / (d * d);
+      }
+    }
+    __syncthreads();
+    // inverse z: out[z] = E + O, out[R-1-z] = E - O
+    if (iact) {
+      f32x16 e, o;
+      const int z = 32 * ib + col, j = 32 * ic + col;
+      eo_gemm(RH, sh + z, sh + RH * PH + z, PH, sq + j, sq + RH * kPQ + j, kPQ, e, o);
+      const int r2 = (int)R2;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int zz = 32 * ib + trow(r);
+        d0[zz * r2 + j] = e[r] + o[r];
+        d0[(R - 1 - zz) * r2 + j] = e[r] - o[r];
+      }
+    }
+  }
+}
+
+template <int NT>
+pdg_status eo_level(const FusedArgs &f0, hipStream_t st) {
+  constexpr int R = 32 * NT, RH = R / 2;
+  const size_t plane = (size_t)(2 * RH * (RH + 1) + R * (R + 1)) * sizeof(float);
+  const size_t pencil = (size_t)(2 * RH * (RH + 1) + R * kPQ) * sizeof(float);
+  static bool attrs = false;
+  if (!attrs) {
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_fwd_kernel<NT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_inv_kernel<NT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_pencil_eo_kernel<NT>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil));
+    attrs = true;
+  }
+  FusedArgs f = f0;
+  const long long groups = f.planes / R * ((long long)R * R / kPencilsEO);
+  const unsigned gp = (unsigned)(f.planes < 2048 ? f.planes : 2048);
+  const unsigned gg = (unsigned)(groups < 2048 ? groups : 2048);
+  dct_plane_eo_fwd_kernel<NT><<<gp, kBig, plane, st>>>(f);
+  PDG_TRY(launched("dct_plane_eo_fwd"));
+  f.src = f.dst;
+  dct_pencil_eo_kernel<NT><<<gg, kBig, pencil, st>>>(f);
+  PDG_TRY(launched("dct_pencil_eo"));
+  dct_plane_eo_inv_kernel<NT><<<gp, kBig, plane, st>>>(f);
+  return launched("dct_plane_eo_inv");
+}
+
 int padded(int R) { return 32 * ((R + 31) / 32); }
 size_t plane_lds(int R) { return (size_t)2 * padded(R) * (padded(R) + 1) * sizeof(float); }
 size_t pencil_lds(int R) { return (size_t)(padded(R) * (padded(R) + 1) + padded(R) * kPP) * sizeof(float); }
@@ -607,6 +965,14 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       f.mu = mu;
       f.R = R;
       f.lam = lam[l];
+      if (R == 128) {
+        PDG_TRY(eo_level<4>(f, st));
+        continue;
+      }
+      if (R == 64) {
+        PDG_TRY(eo_level<2>(f, st));
+        continue;
+      }
       switch ((R + 31) / 32) {
         case 1: PDG_TRY(fused_level<1>(f, st)); break;
         case 2: PDG_TRY(fused_level<2>(f, st)); break;

@@ -41,18 +41,9 @@ __device__ __forceinline__ void level_value(const float *__restrict__ L, int R, 
   v2 = a2;
 }
 
-__global__ __launch_bounds__(256) void warp_kernel(GridDev g, const float *__restrict__ grids,
-                                                   long long gstride, const float *__restrict__ x,
-                                                   long long xstride, long long ldx,
-                                                   float *__restrict__ out, long long ostride,
-                                                   long long ldo, long long n) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int b = blockIdx.y;
-  const float *G = grids + b * gstride;
-  const float *X = x + b * xstride;
-  float *O = out + b * ostride;
-  const float px = X[i], py = X[ldx + i], pz = X[2 * ldx + i];
+// x + level_scale * sum_l D_l(x) (Eq. 1) at one point.
+__device__ __forceinline__ void warp_point(const GridDev &g, const float *__restrict__ G, float px,
+                                           float py, float pz, float &ox, float &oy, float &oz) {
   float d0 = 0.f, d1 = 0.f, d2 = 0.f;
   for (int l = 0; l < g.levels; ++l) {
     float v0, v1, v2;
@@ -61,20 +52,15 @@ __global__ __launch_bounds__(256) void warp_kernel(GridDev g, const float *__res
     d1 += v1;
     d2 += v2;
   }
-  O[i] = px + g.scale * d0;
-  O[ldo + i] = py + g.scale * d1;
-  O[2 * ldo + i] = pz + g.scale * d2;
+  ox = px + g.scale * d0;
+  oy = py + g.scale * d1;
+  oz = pz + g.scale * d2;
 }
 
-// lam_out = gdir + lam + (dD/dx)^T lam.
-__global__ __launch_bounds__(256) void chain_adjoint_kernel(
-    GridDev g, const float *__restrict__ G, const float *__restrict__ x, long long ldx,
-    const float *__restrict__ lam, long long ldl, const float *__restrict__ gdir, long long ldd,
-    float *__restrict__ lo, long long ldo, long long n) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float px = x[i], py = x[ldx + i], pz = x[2 * ldx + i];
-  const float l0 = lam[i], l1 = lam[ldl + i], l2 = lam[2 * ldl + i];
+// lam + level_scale * (dD/dx)^T lam at one point (the position adjoint of Eq. 1).
+__device__ __forceinline__ void adjoint_point(const GridDev &g, const float *__restrict__ G, float px,
+                                              float py, float pz, float l0, float l1, float l2,
+                                              float &r0, float &r1, float &r2) {
   float j0 = 0.f, j1 = 0.f, j2 = 0.f;  // (dD/dx)^T lam, before level_scale
   for (int l = 0; l < g.levels; ++l) {
     const int R = g.res[l];
@@ -106,7 +92,35 @@ __global__ __launch_bounds__(256) void chain_adjoint_kernel(
     if (iny) j1 += h * dy;
     if (inz) j2 += h * dz;
   }
-  float r0 = l0 + g.scale * j0, r1 = l1 + g.scale * j1, r2 = l2 + g.scale * j2;
+  r0 = l0 + g.scale * j0;
+  r1 = l1 + g.scale * j1;
+  r2 = l2 + g.scale * j2;
+}
+
+__global__ __launch_bounds__(256) void warp_kernel(GridDev g, const float *__restrict__ grids,
+                                                   long long gstride, const float *__restrict__ x,
+                                                   long long xstride, long long ldx,
+                                                   float *__restrict__ out, long long ostride,
+                                                   long long ldo, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = blockIdx.y;
+  const float *X = x + b * xstride;
+  float *O = out + b * ostride;
+  warp_point(g, grids + b * gstride, X[i], X[ldx + i], X[2 * ldx + i], O[i], O[ldo + i],
+             O[2 * ldo + i]);
+}
+
+// lam_out = gdir + lam + (dD/dx)^T lam.
+__global__ __launch_bounds__(256) void chain_adjoint_kernel(
+    GridDev g, const float *__restrict__ G, const float *__restrict__ x, long long ldx,
+    const float *__restrict__ lam, long long ldl, const float *__restrict__ gdir, long long ldd,
+    float *__restrict__ lo, long long ldo, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float r0, r1, r2;
+  adjoint_point(g, G, x[i], x[ldx + i], x[2 * ldx + i], lam[i], lam[ldl + i], lam[2 * ldl + i],
+                r0, r1, r2);
   if (gdir) {
     r0 += gdir[i];
     r1 += gdir[ldd + i];
@@ -115,6 +129,66 @@ __global__ __launch_bounds__(256) void chain_adjoint_kernel(
   lo[i] = r0;
   lo[ldo + i] = r1;
   lo[2 * ldo + i] = r2;
+}
+
+// The template chain of Eq. 8, X_{t+1} = warp(G_t, X_t) for t = 0..T-1 (X_0
+// copied to frame 0): one thread per vertex walks its whole chain (the chain of
+// a vertex is sequential, different vertices are independent).
+__global__ __launch_bounds__(256) void chain_warp_kernel(GridDev g, const float *__restrict__ params,
+                                                         long long P, const float *__restrict__ x0,
+                                                         float *__restrict__ xhat, long long V, int T) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  float px = x0[v], py = x0[V + v], pz = x0[2 * V + v];
+  xhat[v] = px;
+  xhat[V + v] = py;
+  xhat[2 * V + v] = pz;
+  for (int t = 0; t < T; ++t) {
+    float ox, oy, oz;
+    warp_point(g, params + t * P, px, py, pz, ox, oy, oz);
+    float *o = xhat + (long long)(t + 1) * 3 * V;
+    o[v] = ox;
+    o[V + v] = oy;
+    o[2 * V + v] = oz;
+    px = ox;
+    py = oy;
+    pz = oz;
+  }
+}
+
+// Reverse sweep of the chain: lam_{T-1} = gd_{T-1} and, for k = T-1 .. 1,
+// lam_{k-1} = gd_{k-1} + lam_k + (dD_k/dx)^T lam_k at X_k (grids k), one thread
+// per vertex; lam_t is the total adjoint of X_{t+1} (frames 1..T).
+__global__ __launch_bounds__(256) void chain_reverse_kernel(GridDev g,
+                                                            const float *__restrict__ params,
+                                                            long long P,
+                                                            const float *__restrict__ xhat,
+                                                            const float *__restrict__ gd,
+                                                            float *__restrict__ lam, long long V,
+                                                            int T) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const long long s3 = 3 * V;
+  float l0 = gd[(T - 1) * s3 + v], l1 = gd[(T - 1) * s3 + V + v], l2 = gd[(T - 1) * s3 + 2 * V + v];
+  lam[(T - 1) * s3 + v] = l0;
+  lam[(T - 1) * s3 + V + v] = l1;
+  lam[(T - 1) * s3 + 2 * V + v] = l2;
+  for (int k = T - 1; k >= 1; --k) {
+    const float *x = xhat + k * s3;
+    float r0, r1, r2;
+    adjoint_point(g, params + k * P, x[v], x[V + v], x[2 * V + v], l0, l1, l2, r0, r1, r2);
+    const float *d = gd + (k - 1) * s3;
+    r0 += d[v];
+    r1 += d[V + v];
+    r2 += d[2 * V + v];
+    float *o = lam + (k - 1) * s3;
+    o[v] = r0;
+    o[V + v] = r1;
+    o[2 * V + v] = r2;
+    l0 = r0;
+    l1 = r1;
+    l2 = r2;
+  }
 }
 
 // Key of a scatter entry: the global node id of its base cell,
@@ -410,7 +484,12 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, Gathe
     const int cell = last ? (int)((long long)(uint32_t)key - kbase) : 0;
     const int cx = cell % R, cy = (cell / R) % R;
     const int cls = last ? (cx & 1) | ((cy & 1) << 1) : -1;
-    if (cls >= 0) atomicOr(&s_mask[chunk & 1], 1u << (4 * my_range + cls));
+    {
+      // rounds present: OR over the wave first, then one LDS atomic per wave
+      unsigned bits = cls >= 0 ? 1u << (4 * my_range + cls) : 0u;
+      for (int o = 32; o > 0; o >>= 1) bits |= __shfl_xor(bits, o, 64);
+      if (lane == 0 && bits) atomicOr(&s_mask[chunk & 1], bits);
+    }
     __syncthreads();
     // only the (range, class) rounds that have runs ending in this chunk
     for (unsigned m = s_mask[chunk & 1]; m; m &= m - 1) {
@@ -459,6 +538,21 @@ pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const floa
   chain_adjoint_kernel<<<div_up(n, 256), 256, 0, st>>>(g, grids, x, ldx, lam, ldl, gdir, ldd,
                                                        lam_out, ldo, n);
   return launched("chain_adjoint");
+}
+
+pdg_status launch_chain_warp(const GridDev &g, const float *params, long long P, const float *x0,
+                             float *xhat, long long V, int T, hipStream_t st) {
+  if (V <= 0) return PDG_OK;
+  chain_warp_kernel<<<div_up(V, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T);
+  return launched("chain_warp");
+}
+
+pdg_status launch_chain_reverse(const GridDev &g, const float *params, long long P,
+                                const float *xhat, const float *gd, float *lam, long long V, int T,
+                                hipStream_t st) {
+  if (V <= 0 || T <= 0) return PDG_OK;
+  chain_reverse_kernel<<<div_up(V, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam, V, T);
+  return launched("chain_reverse");
 }
 
 pdg_status launch_scatter_keys(const GridDev &g, const float *x, long long xstride, long long ldx,
