@@ -131,34 +131,88 @@ __global__ __launch_bounds__(256) void chain_adjoint_kernel(
   lo[2 * ldo + i] = r2;
 }
 
-// The template chain of Eq. 8, X_{t+1} = warp(G_t, X_t) for t = 0..T-1 (X_0
-// copied to frame 0): one thread per vertex walks its whole chain (the chain of
-// a vertex is sequential, different vertices are independent).
+// Per-level parts of warp_point and adjoint_point, so that the levels of one
+// point can be gathered by different lanes.
+__device__ __forceinline__ void level_jt(const float *__restrict__ L, int R, float px, float py,
+                                         float pz, float l0, float l1, float l2, float &j0,
+                                         float &j1, float &j2) {
+  j0 = j1 = j2 = 0.f;
+  if (R == 1) return;
+  int ix, iy, iz;
+  float fx, fy, fz;
+  bool inx, iny, inz;
+  stencil1(R, px, ix, fx, inx);
+  stencil1(R, py, iy, fy, iny);
+  stencil1(R, pz, iz, fz, inz);
+  const long long R2 = (long long)R * R, R3 = R2 * R;
+  const long long b = (iz * R2) + (long long)iy * R + ix;
+  const long long o[8] = {0, 1, R, R + 1, R2, R2 + 1, R2 + R, R2 + R + 1};
+  float s[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    s[k] = l0 * L[b + o[k]] + l1 * L[R3 + b + o[k]] + l2 * L[2 * R3 + b + o[k]];
+  const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+  const float h = 0.5f * (float)R;
+  float dx = (s[1] - s[0]) * gy * gz + (s[3] - s[2]) * fy * gz + (s[5] - s[4]) * gy * fz +
+             (s[7] - s[6]) * fy * fz;
+  float dy = (s[2] - s[0]) * gx * gz + (s[3] - s[1]) * fx * gz + (s[6] - s[4]) * gx * fz +
+             (s[7] - s[5]) * fx * fz;
+  float dz = (s[4] - s[0]) * gx * gy + (s[5] - s[1]) * fx * gy + (s[6] - s[2]) * gx * fy +
+             (s[7] - s[3]) * fx * fy;
+  if (inx) j0 = h * dx;
+  if (iny) j1 = h * dy;
+  if (inz) j2 = h * dz;
+}
+
+// Template chains, one group of kChainLanes lanes per vertex: lane l of the
+// group gathers level l, lane 0 adds the levels in order (the same sums as
+// warp_point / adjoint_point) and hands the new point to the group.
+constexpr int kChainLanes = PDG_MAX_LEVELS;
+
+// X_{t+1} = warp(G_t, X_t) for t = 0..T-1, X_0 copied to frame 0 (Eq. 8).
 __global__ __launch_bounds__(256) void chain_warp_kernel(GridDev g, const float *__restrict__ params,
                                                          long long P, const float *__restrict__ x0,
                                                          float *__restrict__ xhat, long long V, int T) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
-  float px = x0[v], py = x0[V + v], pz = x0[2 * V + v];
-  xhat[v] = px;
-  xhat[V + v] = py;
-  xhat[2 * V + v] = pz;
+  const long long v = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kChainLanes;
+  const int l = threadIdx.x % kChainLanes;
+  const int lead = (threadIdx.x & 63) - l;       // group leader lane in the wave
+  const bool ok = v < V;
+  float px = 0.f, py = 0.f, pz = 0.f;
+  if (ok) {
+    px = x0[v];
+    py = x0[V + v];
+    pz = x0[2 * V + v];
+    if (l == 0) {
+      xhat[v] = px;
+      xhat[V + v] = py;
+      xhat[2 * V + v] = pz;
+    }
+  }
   for (int t = 0; t < T; ++t) {
-    float ox, oy, oz;
-    warp_point(g, params + t * P, px, py, pz, ox, oy, oz);
-    float *o = xhat + (long long)(t + 1) * 3 * V;
-    o[v] = ox;
-    o[V + v] = oy;
-    o[2 * V + v] = oz;
-    px = ox;
-    py = oy;
-    pz = oz;
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    if (ok && l < g.levels)
+      level_value(params + t * P + g.off[l], g.res[l], px, py, pz, v0, v1, v2);
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+    for (int k = 0; k < g.levels; ++k) {         // in level order, as warp_point
+      d0 += __shfl(v0, lead + k, 64);
+      d1 += __shfl(v1, lead + k, 64);
+      d2 += __shfl(v2, lead + k, 64);
+    }
+    px = px + g.scale * d0;
+    py = py + g.scale * d1;
+    pz = pz + g.scale * d2;
+    if (ok && l == 0) {
+      float *o = xhat + (long long)(t + 1) * 3 * V;
+      o[v] = px;
+      o[V + v] = py;
+      o[2 * V + v] = pz;
+    }
   }
 }
 
 // Reverse sweep of the chain: lam_{T-1} = gd_{T-1} and, for k = T-1 .. 1,
-// lam_{k-1} = gd_{k-1} + lam_k + (dD_k/dx)^T lam_k at X_k (grids k), one thread
-// per vertex; lam_t is the total adjoint of X_{t+1} (frames 1..T).
+// lam_{k-1} = gd_{k-1} + lam_k + (dD_k/dx)^T lam_k at X_k (grids k); lam_t is
+// the total adjoint of X_{t+1} (frames 1..T).
 __global__ __launch_bounds__(256) void chain_reverse_kernel(GridDev g,
                                                             const float *__restrict__ params,
                                                             long long P,
@@ -166,25 +220,51 @@ __global__ __launch_bounds__(256) void chain_reverse_kernel(GridDev g,
                                                             const float *__restrict__ gd,
                                                             float *__restrict__ lam, long long V,
                                                             int T) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V) return;
+  const long long v = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kChainLanes;
+  const int l = threadIdx.x % kChainLanes;
+  const int lead = (threadIdx.x & 63) - l;
+  const bool ok = v < V;
   const long long s3 = 3 * V;
-  float l0 = gd[(T - 1) * s3 + v], l1 = gd[(T - 1) * s3 + V + v], l2 = gd[(T - 1) * s3 + 2 * V + v];
-  lam[(T - 1) * s3 + v] = l0;
-  lam[(T - 1) * s3 + V + v] = l1;
-  lam[(T - 1) * s3 + 2 * V + v] = l2;
+  float l0 = 0.f, l1 = 0.f, l2 = 0.f;
+  if (ok) {
+    l0 = gd[(T - 1) * s3 + v];
+    l1 = gd[(T - 1) * s3 + V + v];
+    l2 = gd[(T - 1) * s3 + 2 * V + v];
+    if (l == 0) {
+      lam[(T - 1) * s3 + v] = l0;
+      lam[(T - 1) * s3 + V + v] = l1;
+      lam[(T - 1) * s3 + 2 * V + v] = l2;
+    }
+  }
   for (int k = T - 1; k >= 1; --k) {
-    const float *x = xhat + k * s3;
-    float r0, r1, r2;
-    adjoint_point(g, params + k * P, x[v], x[V + v], x[2 * V + v], l0, l1, l2, r0, r1, r2);
-    const float *d = gd + (k - 1) * s3;
-    r0 += d[v];
-    r1 += d[V + v];
-    r2 += d[2 * V + v];
-    float *o = lam + (k - 1) * s3;
-    o[v] = r0;
-    o[V + v] = r1;
-    o[2 * V + v] = r2;
+    float j0 = 0.f, j1 = 0.f, j2 = 0.f;
+    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+    if (ok) {
+      const float *x = xhat + k * s3;
+      if (l < g.levels)
+        level_jt(params + k * P + g.off[l], g.res[l], x[v], x[V + v], x[2 * V + v], l0, l1, l2,
+                 j0, j1, j2);
+      const float *d = gd + (k - 1) * s3;
+      d0 = d[v];
+      d1 = d[V + v];
+      d2 = d[2 * V + v];
+    }
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int q = 0; q < g.levels; ++q) {         // in level order, as adjoint_point
+      s0 += __shfl(j0, lead + q, 64);
+      s1 += __shfl(j1, lead + q, 64);
+      s2 += __shfl(j2, lead + q, 64);
+    }
+    float r0 = l0 + g.scale * s0, r1 = l1 + g.scale * s1, r2 = l2 + g.scale * s2;
+    r0 += d0;
+    r1 += d1;
+    r2 += d2;
+    if (ok && l == 0) {
+      float *o = lam + (k - 1) * s3;
+      o[v] = r0;
+      o[V + v] = r1;
+      o[2 * V + v] = r2;
+    }
     l0 = r0;
     l1 = r1;
     l2 = r2;
@@ -543,7 +623,7 @@ pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const floa
 pdg_status launch_chain_warp(const GridDev &g, const float *params, long long P, const float *x0,
                              float *xhat, long long V, int T, hipStream_t st) {
   if (V <= 0) return PDG_OK;
-  chain_warp_kernel<<<div_up(V, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T);
+  chain_warp_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T);
   return launched("chain_warp");
 }
 
@@ -551,7 +631,8 @@ pdg_status launch_chain_reverse(const GridDev &g, const float *params, long long
                                 const float *xhat, const float *gd, float *lam, long long V, int T,
                                 hipStream_t st) {
   if (V <= 0 || T <= 0) return PDG_OK;
-  chain_reverse_kernel<<<div_up(V, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam, V, T);
+  chain_reverse_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam,
+                                                                      V, T);
   return launched("chain_reverse");
 }
 
