@@ -293,7 +293,7 @@ constexpr int kXcds = 8;
 
 // The grid is 1-D with a multiple of 8 blocks, so lin -> tile is a bijection;
 // tile = job * qt + query tile, tiles >= nblk do nothing.
-__global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__restrict__ jobs,
+__global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob *__restrict__ jobs,
                                                              int warm, unsigned qt, unsigned nblk) {
   const unsigned lin = blockIdx.x;
   const unsigned per = gridDim.x / kXcds;
@@ -372,6 +372,13 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
     wmaxc.y = fmaxf(wmaxc.y, __shfl_xor(wmaxc.y, o, 64));
     wmaxc.z = fmaxf(wmaxc.z, __shfl_xor(wmaxc.z, o, 64));
   }
+  // wave-uniform: keep it in scalar registers
+  wmin = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmin.x))),
+                     __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmin.y))),
+                     __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmin.z))), 0.f);
+  wmaxc = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmaxc.x))),
+                      __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmaxc.y))),
+                      __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmaxc.z))), 0.f);
   const bool wany = wmin.x <= wmaxc.x;       // the wave has at least one query
   const int ntiles = (J.nc + kTile - 1) / kTile;
   const int qtiles = (J.nq + kTile - 1) / kTile;
@@ -438,12 +445,11 @@ __global__ __launch_bounds__(kThreads) void nn_screen_kernel(const ScreenJob *__
         const uint4 raw = spack[buf][2 * (sub * 32 + (lane & 31)) + half];
         const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
         const f32x16 z = {};
-        f32x16 v[kQB];
 #pragma unroll
-        for (int h = 0; h < kQB; ++h)
-          v[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
-#pragma unroll
-        for (int h = 0; h < kQB; ++h) consider(st[h], v[h], lane, c0 + sub * 32, J.nc, J.cc);
+        for (int h = 0; h < kQB; ++h) {   // one result live at a time (register budget)
+          const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
+          consider(st[h], v, lane, c0 + sub * 32, J.nc, J.cc);
+        }
       }
       if (more) store_tile(regs, spack[buf ^ 1]);
       buf ^= 1;

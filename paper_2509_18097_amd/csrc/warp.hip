@@ -407,7 +407,7 @@ struct GatherPlan {
   long long RS2;                           // rows per segment
 };
 
-__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GridDev g, GatherPlan gp,
+__global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, GatherPlan gp,
                                                                 ScatterLists sl,
                                                                 float *__restrict__ grad) {
   __shared__ float band[3 * kBandFloats];
