@@ -131,6 +131,7 @@ struct DeformBwdWs {
   int *pstart;
   float4 *ent;
   float2 *ent2;
+  float *gscratch;
   void *sort;
 };
 DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
@@ -141,6 +142,7 @@ DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
   w.pstart = c.take<int>(row_count(g) + 1);
   w.ent = c.take<float4>(ne);
   w.ent2 = c.take<float2>(ne);
+  w.gscratch = c.take<float>((long long)(gather_scratch_bytes(g, 1, n) / sizeof(float)));
   w.sort = c.take<char>((long long)radix_sort_bytes(ne));
   return w;
 }
@@ -331,6 +333,7 @@ struct pdg_problem {
   int *pstart_p = nullptr, *pstart_t = nullptr;   // row tables (points, template)
   float4 *ent_p = nullptr, *ent_t = nullptr;       // staged scatter entries
   float2 *ent2_p = nullptr, *ent2_t = nullptr;
+  float *gscratch = nullptr;                       // partial bands of the split gather
   uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
   void *sort = nullptr;
   NNJob *jobs = nullptr;
@@ -447,6 +450,7 @@ void layout(pdg_problem &p, Carve &c) {
   p.ent2_p = c.take<float2>(T * L * N);
   p.ent_t = c.take<float4>(T * L * V);
   p.ent2_t = c.take<float2>(T * L * V);
+  p.gscratch = c.take<float>((long long)(gather_scratch_bytes(p.g, (int)T, N + V) / sizeof(float)));
   p.nrev = T * N * (p.has_tm ? 2 : 1);
   p.rkeys = c.take<uint32_t>(p.nrev);
   p.rvals = c.take<uint32_t>(p.nrev);
@@ -585,7 +589,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
         PDG_TRY(scatter_entries(g, (int)T, sl.list[1], p.tkeys, p.tvals, p.pstart_t, p.sort, st));
         PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[1], st));
       }
-      return launch_gather(g, (int)T, sl, p.grad, st);
+      return launch_gather(g, (int)T, sl, N + V, p.grad, p.gscratch, st);
     }
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
       if (p.d.precond_method == PDG_PRECOND_DCT)
@@ -682,7 +686,7 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
       PDG_TRY(scatter_entries(g, 1, sl.list[0], w.keys, w.vals, w.pstart, w.sort, stream));
       PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
     }
-    PDG_TRY(launch_gather(g, 1, sl, ggrids, stream));
+    PDG_TRY(launch_gather(g, 1, sl, n, ggrids, w.gscratch, stream));
   }
   if (gx && n > 0)
     PDG_TRY(launch_chain_adjoint(g, grids, x, n, gout, n, nullptr, 0, gx, n, n, stream));

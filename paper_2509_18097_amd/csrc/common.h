@@ -142,8 +142,11 @@ pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L
 // grad = level_scale * sum_s w_k(s) lam(s) over the samples s of every list
 // that have node k as a corner of their base cell, for every node of `segs`
 // stacks (grad is overwritten; deterministic summation order).
-pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, float *grad,
-                         hipStream_t st);
+// samples: sample count per segment over all lists (sizes the work split);
+// scratch: gather_scratch_bytes(g, segs, samples) bytes (nullable when 0).
+size_t gather_scratch_bytes(const GridDev &g, int segs, long long samples);
+pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, long long samples,
+                         float *grad, float *scratch, hipStream_t st);
 
 // chamfer.hip
 struct ChSeg {               // one (moving A, fixed B) Chamfer pair

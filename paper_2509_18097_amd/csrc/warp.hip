@@ -397,19 +397,31 @@ constexpr int kBandFloats = 2048;          // LDS floats per channel of a band
 constexpr unsigned long long kNoSeg = ~0ull;   // no (range, key) pair takes this value
 constexpr uint32_t kNoKey32 = 0xffffffffu;
 
+}  // namespace
+
+// Gather plan: per level the band height, the bands per plane, the pieces K a
+// band's entries are split into (K > 1 writes partial bands to scratch, summed
+// in piece order afterwards), the first block and the scratch offset.
 struct GatherPlan {
   int levels;
+  int segs;
   int R[PDG_MAX_LEVELS];
   int B[PDG_MAX_LEVELS];                   // node rows per band
   int nb[PDG_MAX_LEVELS];                  // bands per plane
+  int K[PDG_MAX_LEVELS];                   // pieces per band
   long long bfirst[PDG_MAX_LEVELS + 1];    // first block of each level
   long long roff2[PDG_MAX_LEVELS];         // first row of each level in a segment
+  long long sof[PDG_MAX_LEVELS];           // scratch float offset of each level
   long long RS2;                           // rows per segment
+  long long scratch;                       // scratch floats in all
 };
+
+namespace {
 
 __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, GatherPlan gp,
                                                                 ScatterLists sl,
-                                                                float *__restrict__ grad) {
+                                                                float *__restrict__ grad,
+                                                                float *__restrict__ scratch) {
   __shared__ float band[3 * kBandFloats];
   __shared__ double wtail[kGatherThreads / 64][12];   // per-wave scan totals
   __shared__ unsigned long long skey[kGatherThreads + 1];   // (range << 32) | key
@@ -418,8 +430,10 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
   const long long blk = blockIdx.x;
   int l = 0;
   while (l + 1 < gp.levels && blk >= gp.bfirst[l + 1]) ++l;
-  const int R = gp.R[l], B = gp.B[l], nb = gp.nb[l];
-  const long long local = blk - gp.bfirst[l];
+  const int R = gp.R[l], B = gp.B[l], nb = gp.nb[l], K = gp.K[l];
+  long long local = blk - gp.bfirst[l];
+  const int piece = (int)(local % K);
+  local /= K;
   const int bi = (int)(local % nb);
   const long long rest = local / nb;
   const int z = (int)(rest % R);
@@ -462,7 +476,9 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
   const long long kbase = seg * g.nodes + g.noff[l];
   bool carried = false;
   __syncthreads();
-  const int total = s_total;
+  // this piece's part of the concatenated ranges: entries [cbeg, total)
+  const int cbeg = (int)((long long)s_total * piece / K);
+  const int total = (int)((long long)s_total * (piece + 1) / K);
   // entry v of the concatenated ranges: (range, sorted index)
   auto locate = [&](int v, int &r) {
     r = 0;
@@ -483,8 +499,8 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
       ne2 = L.ent2[i];
     }
   };
-  fetch(t);
-  for (int c0 = 0, chunk = 0; c0 < total; c0 += kGatherThreads, ++chunk) {
+  fetch(cbeg + t);
+  for (int c0 = cbeg, chunk = 0; c0 < total; c0 += kGatherThreads, ++chunk) {
     const int n = total - c0 < kGatherThreads ? total - c0 : kGatherThreads;
     const uint32_t ckey = nkey;
     const float4 ce = ne;
@@ -592,11 +608,35 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
   }
   __syncthreads();
   const long long R2 = (long long)R * R, R3 = R2 * R;
-  float *Gd = grad + seg * g.size + g.off[l] + (long long)z * R2 + (long long)y0 * R;
+  float *Gd = (K == 1 ? grad + seg * g.size + g.off[l]
+                      : scratch + gp.sof[l] + ((long long)piece * gp.segs + seg) * 3 * R3) +
+              (long long)z * R2 + (long long)y0 * R;
   for (int i = t; i < band_n; i += kGatherThreads) {
     Gd[i] = band[i];
     Gd[R3 + i] = band[band_n + i];
     Gd[2 * R3 + i] = band[2 * band_n + i];
+  }
+}
+
+// grad = sum over pieces k (in order) of the partial bands, for the levels
+// split into K > 1 pieces; one thread per (level part, float).
+__global__ __launch_bounds__(256) void gather_reduce_kernel(GridDev g, GatherPlan gp,
+                                                            const float *__restrict__ scratch,
+                                                            float *__restrict__ grad) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int l = 0; l < gp.levels; ++l) {
+    if (gp.K[l] == 1) continue;
+    const long long per = 3 * (long long)gp.R[l] * gp.R[l] * gp.R[l];   // floats per segment
+    const long long n = per * gp.segs;
+    if (i < n) {
+      const long long seg = i / per, c = i - seg * per;
+      const float *src = scratch + gp.sof[l] + i;
+      float v = src[0];
+      for (int k = 1; k < gp.K[l]; ++k) v += src[(long long)k * n];
+      grad[seg * g.size + g.off[l] + c] = v;
+      return;
+    }
+    i -= n;
   }
 }
 
@@ -696,34 +736,67 @@ pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L
   return launched("scatter_stage");
 }
 
-pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, float *grad,
-                         hipStream_t st) {
-  if (segs <= 0) return PDG_OK;
+GatherPlan gather_plan(const GridDev &g, int segs, long long samples) {
   GatherPlan gp;
   memset(&gp, 0, sizeof gp);
   gp.levels = g.levels;
+  gp.segs = segs;
   gp.RS2 = row_count(g);
-  long long blocks = 0, roff = 0;
+  long long blocks = 0, roff = 0, sof = 0;
   for (int l = 0; l < g.levels; ++l) {
     const int R = g.res[l];
     int B = kBandFloats / R;
     if (B < 1) B = 1;
     if (B > R) B = R;
+    // entries of a band if the samples spread evenly: two cell planes of
+    // B + 1 rows; split into pieces of about three chunks (at most 16)
+    const double per_band = 2.0 * (double)samples * (B + 1) / ((double)R * R);
+    int K = (int)(per_band / (3.0 * kGatherThreads));
+    if (K < 1) K = 1;
+    if (K > 16) K = 16;
     gp.R[l] = R;
     gp.B[l] = B;
     gp.nb[l] = (R + B - 1) / B;
+    gp.K[l] = K;
     gp.bfirst[l] = blocks;
     gp.roff2[l] = roff;
-    blocks += (long long)segs * R * gp.nb[l];
+    gp.sof[l] = sof;
+    blocks += (long long)segs * R * gp.nb[l] * K;
     roff += (long long)R * R;
+    if (K > 1) sof += (long long)K * segs * 3 * R * R * R;
   }
   gp.bfirst[g.levels] = blocks;
+  gp.scratch = sof;
+  return gp;
+}
+
+size_t gather_scratch_bytes(const GridDev &g, int segs, long long samples) {
+  return (size_t)gather_plan(g, segs, samples).scratch * sizeof(float);
+}
+
+pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, long long samples,
+                         float *grad, float *scratch, hipStream_t st) {
+  if (segs <= 0) return PDG_OK;
+  const GatherPlan gp = gather_plan(g, segs, samples);
+  const long long blocks = gp.bfirst[g.levels];
   if (blocks >= (1ll << 31)) {
     set_error("grid gather needs %lld blocks (limit 2^31)", blocks);
     return PDG_EINVAL;
   }
-  gather_kernel<<<(unsigned)blocks, kGatherThreads, 0, st>>>(g, gp, sl, grad);
-  return launched("gather");
+  if (gp.scratch > 0 && !scratch) {
+    set_error("grid gather needs %lld floats of scratch", gp.scratch);
+    return PDG_EINVAL;
+  }
+  gather_kernel<<<(unsigned)blocks, kGatherThreads, 0, st>>>(g, gp, sl, grad, scratch);
+  PDG_TRY(launched("gather"));
+  long long red = 0;
+  for (int l = 0; l < g.levels; ++l)
+    if (gp.K[l] > 1) red += 3ll * g.res[l] * g.res[l] * g.res[l] * segs;
+  if (red > 0) {
+    gather_reduce_kernel<<<div_up(red, 256), 256, 0, st>>>(g, gp, scratch, grad);
+    PDG_TRY(launched("gather_reduce"));
+  }
+  return PDG_OK;
 }
 
 }  // namespace pdg
