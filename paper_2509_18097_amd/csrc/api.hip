@@ -215,6 +215,7 @@ struct ChamferWs {
   unsigned *b_base;
   double *partials, *w_default;
   uint32_t *keys, *vals;
+  float4 *rpart;
   void *sort;
   ScreenSet *ssets;
   ScreenJob *sjobs;
@@ -237,7 +238,7 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
     w.boxes_b = c.take<float4>(screen_box_count(m));
     w.perm_a = c.take<uint32_t>(n);
     w.perm_b = c.take<uint32_t>(m);
-    w.maxnorm = c.take<unsigned>(2);
+    w.maxnorm = c.take<unsigned>(2 * kMaxnormStride);
   }
   const long long nk = mode == PDG_CHAMFER_BF16_SCREEN && n > m ? n : m;   // sort entries
   w.jobs = c.take<NNJob>(2);
@@ -247,6 +248,7 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
   w.w_default = c.take<double>(2);
   w.keys = c.take<uint32_t>(nk);
   w.vals = c.take<uint32_t>(nk);
+  w.rpart = c.take<float4>(2 * rev_part_count(nk));
   w.sort = c.take<char>((long long)radix_sort_bytes(nk));
   return w;
 }
@@ -335,6 +337,7 @@ struct pdg_problem {
   float2 *ent2_p = nullptr, *ent2_t = nullptr;
   float *gscratch = nullptr;                       // partial bands of the split gather
   uint32_t *rkeys = nullptr, *rvals = nullptr, *ikeys = nullptr, *ivals = nullptr;
+  float4 *rpart = nullptr;                         // run partials of the reverse scatter
   void *sort = nullptr;
   NNJob *jobs = nullptr;
   ScreenSet *ssets = nullptr;          // nseg moving sets, then T fixed frames
@@ -454,6 +457,7 @@ void layout(pdg_problem &p, Carve &c) {
   p.nrev = T * N * (p.has_tm ? 2 : 1);
   p.rkeys = c.take<uint32_t>(p.nrev);
   p.rvals = c.take<uint32_t>(p.nrev);
+  p.rpart = c.take<float4>(2 * rev_part_count(p.nrev));
   p.ikeys = c.take<uint32_t>(2 * E);
   p.ivals = c.take<uint32_t>(2 * E);
   long long smax = T * L * N;
@@ -474,7 +478,7 @@ void layout(pdg_problem &p, Carve &c) {
     p.packs = c.take<uint4>(2 * p.pack_rows);
     p.coords = c.take<float4>(p.pack_rows);
     p.boxes = c.take<float4>(p.box_tiles);
-    p.maxnorm = c.take<unsigned>(p.nseg + T);
+    p.maxnorm = c.take<unsigned>((p.nseg + T) * kMaxnormStride);
     p.fperm = c.take<int>(F * N);
     p.tperm = c.take<int>(V);
     p.tiles = c.take<unsigned long long>(1);
@@ -539,7 +543,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
         PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T, st));
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
         // screen packs of the moving sets (P^_t, X_t), which change every step
-        PDG_TRY(launch_fill((float *)p.maxnorm, p.nseg, 0.f, st));
+        PDG_TRY(launch_fill((float *)p.maxnorm, (long long)p.nseg * kMaxnormStride, 0.f, st));
         PDG_TRY(launch_screen_pack(p.ssets, p.nseg, p.max_n, st));
       }
       return PDG_OK;
@@ -570,8 +574,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       PDG_TRY(launch_chamfer_rev_keys(p.segs, p.nseg, p.max_m, p.b_base, p.rkeys, p.rvals, st));
       PDG_TRY(radix_sort(p.rkeys, p.rvals, p.nrev,
                          bits_for((unsigned long long)(T * N + T * V)), p.sort, st));
-      PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, nullptr, p.rkeys, p.rvals,
-                                         p.nrev, (float)h.alpha, p.w, st));
+      PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, p.rkeys, p.rvals, p.nrev,
+                                         (float)h.alpha, p.w, p.rpart, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(iso_args(p), st));
       if (p.has_tm)
         PDG_TRY(launch_chain_reverse(g, p.d.params, P, p.xhat, p.gxhat, p.lam, V, (int)T, st));
@@ -765,12 +769,13 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
     PDG_TRY(launch_morton(b, m, (int)m, w.keys, w.perm_b, stream));
     PDG_TRY(radix_sort(w.keys, w.perm_b, m, 30, w.sort, stream));
     ss[0] = screen_set(a, n, (const int *)w.perm_a, w.pack_a, w.coords_a, w.boxes_a, w.maxnorm);
-    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b, w.maxnorm + 1);
+    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b,
+                       w.maxnorm + kMaxnormStride);
     sj[0] = screen_job(ss[0], ss[1], nn_a, nullptr);
     sj[1] = screen_job(ss[1], ss[0], nn_b, nullptr);
     PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
     PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
-    PDG_TRY(launch_fill((float *)w.maxnorm, 2, 0.f, stream));
+    PDG_TRY(launch_fill((float *)w.maxnorm, 2 * kMaxnormStride, 0.f, stream));
     PDG_TRY(launch_screen_pack(w.ssets, 2, (int)(n > m ? n : m), stream));
     PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
   } else {
@@ -782,8 +787,8 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
     PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dw, stream));
     PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
     PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
-    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, nullptr, w.keys, w.vals, m,
-                                       (float)alpha, dw, stream));
+    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha, dw,
+                                       w.rpart, stream));
   }
   return PDG_OK;
 }
@@ -822,8 +827,8 @@ pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64
   PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dir_weight, stream));
   PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
   PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
-  return launch_chamfer_rev_scatter(w.segs, 1, w.b_base, nullptr, w.keys, w.vals, m, (float)alpha,
-                                    dir_weight, stream);
+  return launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha,
+                                    dir_weight, w.rpart, stream);
 }
 
 pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int32_t method,
@@ -992,10 +997,12 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     };
     for (int s = 0; s < p->nseg; ++s) {        // moving sets: P^_t keeps P_t's order, X_t X_0's
       const ChSeg &q = segs[s];
-      add_set(q.a, q.n, s < T ? p->fperm + (long long)s * N : p->tperm, p->maxnorm + s);
+      add_set(q.a, q.n, s < T ? p->fperm + (long long)s * N : p->tperm,
+              p->maxnorm + (long long)s * kMaxnormStride);
     }
     for (long long t = 0; t < T; ++t)          // fixed frames P_1..P_T
-      add_set(pd->points + (t + 1) * 3 * N, N, p->fperm + (t + 1) * N, p->maxnorm + p->nseg + t);
+      add_set(pd->points + (t + 1) * 3 * N, N, p->fperm + (t + 1) * N,
+              p->maxnorm + (p->nseg + t) * kMaxnormStride);
     for (int s = 0; s < p->nseg; ++s) {
       const ChSeg &q = segs[s];
       const ScreenSet &A = ssets[s], &B = ssets[p->nseg + s % T];
@@ -1045,7 +1052,8 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
       s = launch_morton(pd->template_verts, V, (int)V, p->tkeys, (uint32_t *)p->tperm, stream);
       if (s == PDG_OK) s = radix_sort(p->tkeys, (uint32_t *)p->tperm, V, 30, p->sort, stream);
     }
-    if (s == PDG_OK) s = launch_fill((float *)p->maxnorm + p->nseg, T, 0.f, stream);
+    if (s == PDG_OK) s = launch_fill((float *)p->maxnorm + (long long)p->nseg * kMaxnormStride,
+                                     T * kMaxnormStride, 0.f, stream);
     if (s == PDG_OK) s = launch_screen_pack(p->ssets + p->nseg, (int)T, (int)N, stream);
     if (s == PDG_OK) s = launch_fill((float *)p->tiles, 2, 0.f, stream);
   }

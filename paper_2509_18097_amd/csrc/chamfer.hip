@@ -165,42 +165,142 @@ __global__ __launch_bounds__(256) void chamfer_rev_keys_kernel(const ChSeg *__re
   vals[g] = g;
 }
 
-__global__ __launch_bounds__(256) void chamfer_rev_scatter_kernel(
-    const ChSeg *__restrict__ segs, int nseg, const unsigned *__restrict__ b_base,
-    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, long long nent,
-    float alpha, const double *__restrict__ w) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nent) return;
-  const uint32_t key = keys[i];
-  if (i > 0 && keys[i - 1] == key) return;
-  // segment of this run: the b index determines it (b_base is increasing)
-  const unsigned g0 = vals[i];
+// Global segment of b index g0 (b_base is increasing).
+__device__ __forceinline__ int rev_segment(const unsigned *__restrict__ b_base, int nseg,
+                                           unsigned g0) {
   int lo = 0, hi = nseg - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (b_base[mid] <= g0) lo = mid; else hi = mid - 1;
+    if (b_base[mid] <= g0)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
-  const ChSeg S = segs[lo];
+  return lo;
+}
+
+constexpr int kRevThreads = 256;
+
+// Reverse direction of the adjoint: sorted entry i (key = a index, value = b
+// index) contributes coef * (a - b) to ga[key].  One workgroup per 256
+// entries: a segmented scan over equal keys sums each run inside the block;
+// a run that starts and ends in the block is added to ga by its last thread,
+// the part of a run that entered from an earlier block goes to head[block],
+// and the part of a run that leaves the block goes to tail[block] (joined by
+// rev_join_kernel in block order).
+__global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
+    const ChSeg *__restrict__ segs, int nseg, const unsigned *__restrict__ b_base,
+    const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, long long nent,
+    float alpha, const double *__restrict__ w, float4 *__restrict__ head,
+    float4 *__restrict__ tail) {
+  __shared__ uint32_t skey[kRevThreads + 1];
+  __shared__ float wtail[kRevThreads / 64][3];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const long long b0 = (long long)blockIdx.x * kRevThreads;
+  const long long i = b0 + t;
+  const bool valid = i < nent;
+  const uint32_t key = valid ? keys[i] : 0xffffffffu;
+  float v[3] = {0.f, 0.f, 0.f};
+  int sg = 0;
+  if (valid) {
+    const unsigned g0 = vals[i];
+    sg = rev_segment(b_base, nseg, g0);
+    const ChSeg S = segs[sg];
+    if (S.ga != nullptr) {
+      const long long n = S.n, m = S.m;
+      const int ai = (int)(key - S.a_base);
+      const int j = (int)(g0 - b_base[sg]);
+      const float cw = (float)(w[2 * sg + 1] / (double)S.m);
+      const float dx = S.a[ai] - S.b[j];
+      const float dy = S.a[n + ai] - S.b[m + j];
+      const float dz = S.a[2 * n + ai] - S.b[2 * m + j];
+      const float d2 = dx * dx + dy * dy + dz * dz;
+      const float coef = cw * expf(-alpha * d2) * (1.0f - alpha * d2) * 2.0f;
+      v[0] = coef * dx;
+      v[1] = coef * dy;
+      v[2] = coef * dz;
+    }
+  }
+  skey[t] = key;
+  if (t == 0) skey[kRevThreads] = b0 + kRevThreads < nent ? keys[b0 + kRevThreads] : 0xffffffffu;
+  // segmented inclusive scan within the wave (equal keys are contiguous)
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t ok = __shfl_up(key, off, 64);
+    const bool same = lane >= off && ok == key;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float o = __shfl_up(v[c], off, 64);
+      if (same) v[c] = o + v[c];
+    }
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) wtail[wv][c] = v[c];
+  }
+  __syncthreads();
+  // carry into this wave's leading run from the waves before it
+  if (wv > 0 && key == skey[64 * wv]) {
+    float cin[3] = {0.f, 0.f, 0.f};
+    for (int j = wv - 1; j >= 0; --j) {
+      if (skey[64 * j + 63] != key) break;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cin[c] += wtail[j][c];
+      if (skey[64 * j] != key) break;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = cin[c] + v[c];
+  }
+  if (!valid || (skey[t + 1] == key && t + 1 < kRevThreads)) return;   // not the run's last here
+  const bool ends = skey[t + 1] != key;                 // run ends inside this block
+  const bool entered = blockIdx.x > 0 && key == skey[0] && keys[b0 - 1] == key;
+  if (entered) {
+    head[blockIdx.x] = make_float4(v[0], v[1], v[2], 0.f);
+  } else if (!ends) {
+    tail[blockIdx.x] = make_float4(v[0], v[1], v[2], 0.f);
+  } else {
+    const ChSeg &S = segs[sg];
+    if (S.ga == nullptr) return;
+    const long long n = S.n;
+    const int ai = (int)(key - S.a_base);
+    S.ga[ai] += v[0];
+    S.ga[n + ai] += v[1];
+    S.ga[2 * n + ai] += v[2];
+  }
+}
+
+// Runs that cross block boundaries: for each block whose last run started in
+// it and continues, tail[b] + head[b + 1] + ... in block order is added to ga.
+__global__ __launch_bounds__(256) void rev_join_kernel(const ChSeg *__restrict__ segs, int nseg,
+                                                       const unsigned *__restrict__ b_base,
+                                                       const uint32_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ vals,
+                                                       long long nent, int nblocks,
+                                                       const float4 *__restrict__ head,
+                                                       const float4 *__restrict__ tail) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  const long long b0 = (long long)b * kRevThreads;
+  const long long last = b0 + kRevThreads - 1 < nent ? b0 + kRevThreads - 1 : nent - 1;
+  const uint32_t key = keys[last];
+  if (last + 1 >= nent || keys[last + 1] != key) return;   // the last run ends in block b
+  if (b > 0 && keys[b0] == key && keys[b0 - 1] == key) return;   // started before block b
+  float4 s = tail[b];
+  for (int b2 = b + 1; b2 < nblocks; ++b2) {
+    const float4 h = head[b2];
+    s.x += h.x;
+    s.y += h.y;
+    s.z += h.z;
+    const long long e2 = (long long)b2 * kRevThreads + kRevThreads - 1;
+    if (e2 + 1 >= nent || keys[e2 + 1] != key) break;
+  }
+  const int sg = rev_segment(b_base, nseg, vals[last]);
+  const ChSeg &S = segs[sg];
   if (S.ga == nullptr) return;
-  const long long n = S.n, m = S.m;
+  const long long n = S.n;
   const int ai = (int)(key - S.a_base);
-  const float ax = S.a[ai], ay = S.a[n + ai], az = S.a[2 * n + ai];
-  const float cw = (float)(w[2 * lo + 1] / (double)S.m);
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-  for (long long k = i; k < nent && keys[k] == key; ++k) {
-    const int j = (int)(vals[k] - b_base[lo]);
-    const float dx = ax - S.b[j];
-    const float dy = ay - S.b[m + j];
-    const float dz = az - S.b[2 * m + j];
-    const float s = dx * dx + dy * dy + dz * dz;
-    const float coef = cw * expf(-alpha * s) * (1.0f - alpha * s) * 2.0f;
-    s0 += coef * dx;
-    s1 += coef * dy;
-    s2 += coef * dz;
-  }
-  S.ga[ai] += s0;
-  S.ga[n + ai] += s1;
-  S.ga[2 * n + ai] += s2;
+  S.ga[ai] += s.x;
+  S.ga[n + ai] += s.y;
+  S.ga[2 * n + ai] += s.z;
 }
 
 }  // namespace
@@ -238,14 +338,23 @@ pdg_status launch_chamfer_rev_keys(const ChSeg *segs, int nseg, int max_m, const
   return launched("chamfer_rev_keys");
 }
 
+long long rev_part_count(long long nent) { return (nent + kRevThreads - 1) / kRevThreads; }
+
 pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigned *b_base,
-                                      const unsigned * /*unused*/, const uint32_t *keys,
-                                      const uint32_t *vals, long long nent, float alpha,
-                                      const double *w, hipStream_t st) {
+                                      const uint32_t *keys, const uint32_t *vals, long long nent,
+                                      float alpha, const double *w, float4 *part, hipStream_t st) {
   if (nent <= 0) return PDG_OK;
-  chamfer_rev_scatter_kernel<<<div_up(nent, 256), 256, 0, st>>>(segs, nseg, b_base, keys, vals,
-                                                                nent, alpha, w);
-  return launched("chamfer_rev_scatter");
+  const long long nb = rev_part_count(nent);
+  if (nb >= (1ll << 31)) {
+    set_error("chamfer reverse scatter: %lld entries exceed the launch limit", nent);
+    return PDG_EINVAL;
+  }
+  chamfer_rev_scatter_kernel<<<(unsigned)nb, kRevThreads, 0, st>>>(segs, nseg, b_base, keys, vals,
+                                                                  nent, alpha, w, part, part + nb);
+  PDG_TRY(launched("chamfer_rev_scatter"));
+  rev_join_kernel<<<div_up(nb, 256), 256, 0, st>>>(segs, nseg, b_base, keys, vals, nent, (int)nb,
+                                                   part, part + nb);
+  return launched("chamfer_rev_join");
 }
 
 }  // namespace pdg

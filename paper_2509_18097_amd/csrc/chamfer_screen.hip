@@ -117,10 +117,10 @@ __global__ __launch_bounds__(256) void morton_kernel(const float *__restrict__ x
 // One thread per packed position i (original point perm[i]): the packed bf16
 // row (32 B), the float32 coordinates with the original index, max |c| over
 // the set (float bits of non-negative values order like unsigned integers, so
-// an integer atomic max is exact and order independent), and, one block per
-// 256-point tile, the tile's bounding box.
+// an integer atomic max is exact and order independent; one per block), and,
+// one block per 256-point tile, the tile's bounding box.
 __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__ sets) {
-  __shared__ float red[6][4];
+  __shared__ float red[7][4];
   const ScreenSet S = sets[blockIdx.y];
   if ((long long)blockIdx.x * 256 >= S.n) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) {
-    if (nrm > 0.f) atomicMax(S.maxnorm, __float_as_uint(nrm));
+    red[6][wv] = nrm;
     for (int k = 0; k < 3; ++k) {
       red[k][wv] = lo[k];
       red[3 + k][wv] = hi3[k];
@@ -188,6 +188,9 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
       b[k] = fminf(fminf(red[k][0], red[k][1]), fminf(red[k][2], red[k][3]));
       b[3 + k] = fmaxf(fmaxf(red[3 + k][0], red[3 + k][1]), fmaxf(red[3 + k][2], red[3 + k][3]));
     }
+    // one atomic per block; each set's maximum sits on a cache line of its own
+    const float m = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
+    if (m > 0.f) atomicMax(S.maxnorm, __float_as_uint(m));
     S.boxes[2 * blockIdx.x] = make_float4(b[0], b[1], b[2], 0.f);
     S.boxes[2 * blockIdx.x + 1] = make_float4(b[3], b[4], b[5], 0.f);
   }

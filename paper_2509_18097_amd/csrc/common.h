@@ -177,7 +177,7 @@ struct ScreenSet {           // one point set packed as screen candidates and qu
   uint4 *pack;               // [n][2] packed bf16 rows (32 B per point), packed order
   float4 *coords;            // [n] (x, y, z, original index as int bits), packed order
   float4 *boxes;             // [ceil(n/256)][2] min and max corner of each 256-point tile
-  unsigned *maxnorm;         // float bits of max |x| (zeroed before packing)
+  unsigned *maxnorm;         // float bits of max |x| (zeroed before packing; sets kMaxnormStride apart)
 };
 struct ScreenJob {           // one directed search: packed queries over packed candidates
   const float *c;            // candidates SoA [3][nc], original order (warm start)
@@ -192,6 +192,9 @@ struct ScreenJob {           // one directed search: packed queries over packed 
   unsigned long long *tiles; // nullable: += candidate tiles screened
 };
 inline long long screen_tiles(long long n) { return (n + 255) / 256; }
+// per-set max-norm words sit this many words apart (one 128-byte line each),
+// so the packing atomics of different sets do not meet on one cache line
+constexpr int kMaxnormStride = 32;
 // float4 entries of a set's box array (min and max corner per tile)
 inline long long screen_box_count(long long n) { return 2 * screen_tiles(n); }
 // keys = 30-bit Morton codes over [-1, 1]^3 of x ([3][ld] SoA, n points), vals = index
@@ -213,10 +216,12 @@ pdg_status launch_chamfer_grad_fwd(const ChSeg *segs, int nseg, int max_n, float
 pdg_status launch_chamfer_rev_keys(const ChSeg *segs, int nseg, int max_m,
                                    const unsigned *b_base, uint32_t *keys, uint32_t *vals,
                                    hipStream_t st);
+// Sorted (keys, vals) from launch_chamfer_rev_keys; part: 2 * rev_part_count(nent)
+// float4 of scratch (run partials of workgroups).
+long long rev_part_count(long long nent);
 pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigned *b_base,
-                                      const unsigned *a_base_sorted, const uint32_t *keys,
-                                      const uint32_t *vals, long long nent, float alpha,
-                                      const double *w, hipStream_t st);
+                                      const uint32_t *keys, const uint32_t *vals, long long nent,
+                                      float alpha, const double *w, float4 *part, hipStream_t st);
 
 // precond.hip
 struct CGLevel {             // one level of every stack in a preconditioner call

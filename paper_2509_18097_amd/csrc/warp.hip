@@ -304,28 +304,36 @@ __global__ __launch_bounds__(256) void scatter_keys_kernel(GridDev g, const floa
 
 // Row index of a key: seg * RS2 + (R_0^2 + ... + R_{l-1}^2) + z * R + y of
 // the base cell (z, y, x).  Keys, node counts and row counts fit 32 bits.
-__device__ __forceinline__ uint32_t key_row(const GridDev &g, uint32_t key, uint32_t RS2) {
-  const uint32_t nodes = (uint32_t)g.nodes;
-  const uint32_t seg = key / nodes;
-  const uint32_t rem = key - seg * nodes;
-  int l = g.levels - 1;
-  while (l > 0 && (uint32_t)g.noff[l] > rem) --l;
-  uint32_t roff = 0;
-  for (int k = 0; k < l; ++k) roff += (uint32_t)(g.res[k] * g.res[k]);
-  return seg * RS2 + roff + (rem - (uint32_t)g.noff[l]) / (uint32_t)g.res[l];
-}
-
 // rstart[q] = first sorted entry whose row index is >= q, q = 0..nrows
-// (rstart[nrows] = nent): thread i writes the table slots between the row of
-// entry i-1 and the row of entry i.
+// (rstart[nrows] = nent): one thread per row, a binary search for the row's
+// first key (row r of level l in segment seg starts at key
+// seg * nodes + noff[l] + r * R_l).
 __global__ __launch_bounds__(256) void row_table_kernel(GridDev g, const uint32_t *__restrict__ keys,
                                                         int nent, uint32_t RS2, uint32_t nrows,
                                                         int *__restrict__ rstart) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > nent) return;
-  const uint32_t cur = i < nent ? key_row(g, keys[i], RS2) : nrows;
-  const long long prev = i > 0 ? (long long)key_row(g, keys[i - 1], RS2) : -1;
-  for (long long q = prev + 1; q <= (long long)cur; ++q) rstart[q] = i;
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > nrows) return;
+  if (q == nrows) {
+    rstart[q] = nent;
+    return;
+  }
+  const uint32_t seg = q / RS2;
+  uint32_t r = q - seg * RS2;
+  int l = 0;
+  while (l + 1 < g.levels && r >= (uint32_t)(g.res[l] * g.res[l])) {
+    r -= (uint32_t)(g.res[l] * g.res[l]);
+    ++l;
+  }
+  const uint32_t k0 = seg * (uint32_t)g.nodes + (uint32_t)g.noff[l] + r * (uint32_t)g.res[l];
+  int lo = 0, hi = nent;
+  while (lo < hi) {
+    const int mid = (int)(((unsigned)lo + (unsigned)hi) >> 1);
+    if (keys[mid] < k0)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  rstart[q] = lo;
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(float *__restrict__ p, long long n, float v) {
@@ -724,8 +732,9 @@ long long row_count(const GridDev &g) {
 pdg_status launch_row_table(const GridDev &g, const uint32_t *keys, long long nent, int segs,
                             int *rstart, hipStream_t st) {
   const long long RS2 = row_count(g);
-  row_table_kernel<<<div_up(nent + 1, 256), 256, 0, st>>>(g, keys, (int)nent, (uint32_t)RS2,
-                                                            (uint32_t)(segs * RS2), rstart);
+  const long long nrows = segs * RS2;
+  row_table_kernel<<<div_up(nrows + 1, 256), 256, 0, st>>>(g, keys, (int)nent, (uint32_t)RS2,
+                                                             (uint32_t)nrows, rstart);
   return launched("row_table");
 }
 
