@@ -389,11 +389,13 @@ __global__ __launch_bounds__(256) void scatter_stage_kernel(GridDev g, ScatterLi
 // dz = 1) and z (dz = 0) with cell rows y0-1..y1-1; the row table gives the
 // entries of each (list, cell plane) as one contiguous range.  The ranges are
 // walked 256 entries at a time: every thread forms its entry's 12 products
-// w_k(s) * lam_c(s) (4 corners of its dz, 3 channels; exact in float64), a
-// segmented inclusive scan over the chunk in float64 (fixed Hillis-Steele
-// pattern, segments = runs of equal (range, key) pairs, which are contiguous
-// because every range is sorted) leaves each run's sums at its last
-// entry (a run cut by the chunk end hands its sums to the next chunk), and then, for each range (list, cell
+// w_k(s) * lam_c(s) (4 corners of its dz, 3 channels), a segmented inclusive
+// scan over the chunk in float32 (segments = runs of equal (range, key)
+// pairs, which are contiguous because every range is sorted; a fixed
+// Hillis-Steele pattern inside rows of 16 lanes, then in row order across
+// the wave, then across waves) leaves each run's sums at its last entry (a
+// run cut by the chunk end hands its sums to the next chunk), and then, for
+// each range (list, cell
 // plane) and each (x, y) parity class in turn with a barrier in between, the
 // runs that end there add level_scale times their sums to their corners inside
 // the band held in LDS.  The runs of one range and class belong to distinct
@@ -404,6 +406,21 @@ constexpr int kGatherThreads = 256;
 constexpr int kBandFloats = 2048;          // LDS floats per channel of a band
 constexpr unsigned long long kNoSeg = ~0ull;   // no (range, key) pair takes this value
 constexpr uint32_t kNoKey32 = 0xffffffffu;
+
+// One Hillis-Steele step of a segmented inclusive scan inside rows of 16
+// lanes: lane l adds lane l - D's partial when both lie in one row and one
+// run (head = first lane of l's run).  The row shift is a DPP move, so all
+// lanes must be active.
+template <int D>
+__device__ __forceinline__ void row_scan_step(float (&p)[12], int lane, int head) {
+  const bool take = (lane & 15) >= D && lane - D >= head;
+#pragma unroll
+  for (int v = 0; v < 12; ++v) {
+    const float o = __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(p[v]), 0x110 + D, 0xf, 0xf, false));
+    p[v] = take ? p[v] + o : p[v];
+  }
+}
 
 }  // namespace
 
@@ -431,9 +448,9 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
                                                                 float *__restrict__ grad,
                                                                 float *__restrict__ scratch) {
   __shared__ float band[3 * kBandFloats];
-  __shared__ double wtail[kGatherThreads / 64][12];   // per-wave scan totals
+  __shared__ float wtail[kGatherThreads / 64][12];   // per-wave scan totals
   __shared__ unsigned long long skey[kGatherThreads + 1];   // (range << 32) | key
-  __shared__ double carry[2][12];
+  __shared__ float carry[2][12];
   __shared__ unsigned s_mask[2];             // (range, class) rounds with runs ending
   const long long blk = blockIdx.x;
   int l = 0;
@@ -517,7 +534,7 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
     nkey = kNoKey32;
     fetch(c0 + kGatherThreads + t);        // in flight during this chunk
     if (t == 0) s_mask[chunk & 1] = 0u;
-    double p[12];
+    float p[12];
     unsigned long long key = kNoSeg;
     int my_range = -1;
     if (t < n) {
@@ -528,7 +545,7 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
       for (int q = 0; q < 4; ++q) {
         const float w = corner_weight(q | (rdz[crng] << 2), ce.x, ce.y, ce.z);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p[4 * c + q] = (double)w * (double)lv[c];
+        for (int c = 0; c < 3; ++c) p[4 * c + q] = w * lv[c];
       }
       if (t == 0 && carried) {
 #pragma unroll
@@ -542,19 +559,31 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
     }
     if (t >= n) {
 #pragma unroll
-      for (int v2 = 0; v2 < 12; ++v2) p[v2] = 0.0;
+      for (int v2 = 0; v2 < 12; ++v2) p[v2] = 0.f;
     }
-    // segmented inclusive scan within the wave (equal keys are contiguous, so
-    // equal keys at distance `off` mean one run in between)
+    // segmented inclusive scan within the wave (all lanes active here)
     const int lane = t & 63, wv = t >> 6;
-    const unsigned klo = (unsigned)key, khi = (unsigned)(key >> 32);
-    for (int off = 1; off < 64; off <<= 1) {
-      const unsigned olo = __shfl_up(klo, off, 64), ohi = __shfl_up(khi, off, 64);
-      const bool same = lane >= off && olo == klo && ohi == khi;
+    int head;                                // first lane of this lane's run
+    {
+      const unsigned klo = (unsigned)key, khi = (unsigned)(key >> 32);
+      const unsigned plo = __shfl_up(klo, 1, 64), phi = __shfl_up(khi, 1, 64);
+      const unsigned long long starts = __ballot(lane == 0 || plo != klo || phi != khi);
+      const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1;
+      head = 63 - __clzll(starts & upto);
+    }
+    row_scan_step<1>(p, lane, head);
+    row_scan_step<2>(p, lane, head);
+    row_scan_step<4>(p, lane, head);
+    row_scan_step<8>(p, lane, head);
+    // across rows in order: the last lane of row r - 1 already holds its
+    // run's sum up to there
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+      const bool take = (lane >> 4) == r && head <= 16 * r - 1;
 #pragma unroll
       for (int v2 = 0; v2 < 12; ++v2) {
-        const double o = __shfl_up(p[v2], off, 64);
-        if (same) p[v2] = o + p[v2];
+        const float o = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p[v2]), 16 * r - 1));
+        p[v2] = take ? o + p[v2] : p[v2];
       }
     }
     if (lane == 63) {
@@ -566,9 +595,9 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
     if (wv > 0 && 64 * wv < n) {
       const unsigned long long k0 = skey[64 * wv];
       if (key == k0) {
-        double cin[12];
+        float cin[12];
 #pragma unroll
-        for (int v2 = 0; v2 < 12; ++v2) cin[v2] = 0.0;
+        for (int v2 = 0; v2 < 12; ++v2) cin[v2] = 0.f;
         for (int j = wv - 1; j >= 0; --j) {
           if (skey[64 * j + 63] != k0) break;
 #pragma unroll
@@ -606,7 +635,7 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
             const int o = (y - y0) * R + x;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-              band[c * band_n + o] = __fmaf_rn(g.scale, (float)p[4 * c + q], band[c * band_n + o]);
+              band[c * band_n + o] = __fmaf_rn(g.scale, p[4 * c + q], band[c * band_n + o]);
           }
         }
       }
