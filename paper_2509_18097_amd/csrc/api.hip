@@ -357,6 +357,7 @@ struct pdg_problem {
   long long nrev = 0;
   CGPlanDev cg;
   AdamLevels adam;
+  unsigned fused = 0u;                             // levels whose Adam ran in the preconditioner
   size_t ws_used = 0;
   // graph replay
   hipStream_t cap = nullptr;
@@ -531,7 +532,10 @@ IsoArgs iso_args(pdg_problem &p) {
 }
 
 // One stage of the step (the stages in order make one iteration).
-pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user_terms) {
+// fuse: part of a full step (the preconditioner may apply Adam itself, see
+// run_dct); false for stages enqueued one at a time.
+pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user_terms,
+                         bool fuse) {
   const GridDev &g = p.g;
   const long long T = p.T, N = p.N, V = p.V, P = p.P;
   const pdg_hyper &h = p.d.hp;
@@ -596,13 +600,27 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       return launch_gather(g, (int)T, sl, N + V, p.grad, p.gscratch, st);
     }
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
-      if (p.d.precond_method == PDG_PRECOND_DCT)
-        return run_dct(g, (int)T, p.lambda_l, p.grad, p.pgrad, p.dctws, st);
+      p.fused = 0u;
+      if (p.d.precond_method == PDG_PRECOND_DCT) {
+        if (!fuse) return run_dct(g, (int)T, p.lambda_l, p.grad, p.pgrad, p.dctws, st);
+        // full step: levels whose last inverse pass can apply Adam do so
+        AdamFuse af;
+        af.th = p.d.params;
+        af.m = p.d.adam_m;
+        af.v = p.d.adam_v;
+        af.lv = p.adam;
+        af.b1 = h.beta1;
+        af.b2 = h.beta2;
+        af.eps = h.eps;
+        af.step_dev = p.epoch;
+        af.step_host = 0;
+        return run_dct(g, (int)T, p.lambda_l, p.grad, p.pgrad, p.dctws, st, &af, &p.fused);
+      }
       PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
       return run_cg(p.cg, p.pgrad, T * P, p.cgws, st);
-    case PDG_STAGE_ADAM:  // Sec. 3.6
-      return launch_adam(p.adam, P, (int)T, h.beta1, h.beta2, h.eps, p.epoch, 0, p.d.params,
-                         p.d.adam_m, p.d.adam_v, p.pgrad, st);
+    case PDG_STAGE_ADAM:  // Sec. 3.6 (levels not already updated by the preconditioner)
+      return launch_adam_levels(p.adam, fuse ? p.fused : 0u, P, (int)T, h.beta1, h.beta2, h.eps,
+                                p.epoch, 0, p.d.params, p.d.adam_m, p.d.adam_v, p.pgrad, st);
     default:
       set_error("unknown stage %d", stage);
       return PDG_EINVAL;
@@ -611,7 +629,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
 
 pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
   for (int s = PDG_STAGE_WARP; s <= PDG_STAGE_ADAM; ++s)
-    PDG_TRY(enqueue_stage(p, s, st, user_terms));
+    PDG_TRY(enqueue_stage(p, s, st, user_terms, true));
   return PDG_OK;
 }
 
@@ -1119,7 +1137,7 @@ pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream) {
     set_error("unknown stage %d", stage);
     return PDG_EINVAL;
   }
-  return enqueue_stage(*p, stage, stream, nullptr);
+  return enqueue_stage(*p, stage, stream, nullptr, false);
 }
 
 pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *epochs,

@@ -250,19 +250,61 @@ pdg_status run_cg(const CGPlanDev &plan, float *g, long long floats, void *ws, h
 // dct.hip: exact (I + lam L)^-2 by the separable DCT-II (R <= 256)
 size_t dct_bytes(const GridDev &g);
 pdg_status dct_basis(const GridDev &g, void *ws, hipStream_t st);
-// src -> data (src may equal data)
-pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *src, float *data,
-                   const void *ws, hipStream_t st);
+// Adam (paper Sec. 3.6) on one value: the moments m, v are updated in
+// place and the new parameter is returned; bc1, bc2 are 1 - beta^k.
+__device__ __forceinline__ float adam_one(float b1, float b2, float eps, float lr, float bc1,
+                                          float bc2, float gi, float &m, float &v, float th) {
+  const float mi = b1 * m + (1.0f - b1) * gi;
+  const float vi = b2 * v + (1.0f - b2) * gi * gi;
+  m = mi;
+  v = vi;
+  const float mh = mi / bc1;
+  const float vh = vi / bc2;
+  return th - lr * mh / (sqrtf(vh) + eps);
+}
+// Bias corrections of step k = *step_dev + 1 (or step_host when step_dev is
+// null) into sbc[0..1] (shared); every thread of the block must call it.
+__device__ __forceinline__ void adam_bias(float b1, float b2, const int *step_dev, int step_host,
+                                          float *sbc) {
+  if (threadIdx.x == 0) {
+    const int k = step_dev ? (*step_dev + 1) : step_host;
+    sbc[0] = (float)(1.0 - pow((double)b1, (double)k));
+    sbc[1] = (float)(1.0 - pow((double)b2, (double)k));
+  }
+  __syncthreads();
+}
 
-// optim.hip
 struct AdamLevels {
   int levels;
   long long off[PDG_MAX_LEVELS + 1];
   float lr[PDG_MAX_LEVELS];
 };
+// Adam applied by the last pass of the preconditioner: params, moments and
+// per-level rates laid out like the preconditioned gradient.
+struct AdamFuse {
+  float *th, *m, *v;
+  AdamLevels lv;
+  float b1, b2, eps;
+  const int *step_dev;
+  int step_host;
+};
+
+// src -> data (src may equal data).  With adam non-null, levels whose last
+// pass can apply Adam to the preconditioned values (while still writing them
+// to data) do so; their bits are set in *fused (levels not set need
+// launch_adam_levels afterwards).
+pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *src, float *data,
+                   const void *ws, hipStream_t st, const AdamFuse *adam = nullptr,
+                   unsigned *fused = nullptr);
+
+// optim.hip
 pdg_status launch_adam(const AdamLevels &lv, long long stack, int batch, float b1, float b2,
                        float eps, const int *step_dev, int step_host, float *theta, float *m,
                        float *v, const float *g, hipStream_t st);
+// The same for the levels whose bit in skip is clear.
+pdg_status launch_adam_levels(const AdamLevels &lv, unsigned skip, long long stack, int batch,
+                              float b1, float b2, float eps, const int *step_dev, int step_host,
+                              float *theta, float *m, float *v, const float *g, hipStream_t st);
 pdg_status launch_set_int(int *p, int value, hipStream_t st);
 struct IsoArgs {
   const float *xhat;   // [F][3][V]

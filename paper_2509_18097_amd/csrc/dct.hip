@@ -167,6 +167,14 @@ struct FusedArgs {
   float lam;
 };
 
+// Adam epilogue of the last inverse pass of one level.
+struct AdamEpi {
+  float *th, *m, *v;
+  float lr, b1, b2, eps;
+  const int *step_dev;
+  int step_host;
+};
+
 constexpr int kFusedMaxR = 128;
 constexpr int kBig = 512;              // threads of a fused block (8 waves)
 constexpr int kCh = 8;
@@ -627,24 +635,35 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_fwd_kernel(FusedArgs a) {
     }
     __syncthreads();
     if (next < a.planes) {
+      float *pb = sp + (threadIdx.x / R) * P + threadIdx.x % R;   // kBig is a multiple of R
 #pragma unroll
-      for (int e = 0; e < kPre; ++e) {
-        const int i = threadIdx.x + e * kBig;
-        sp[(i / R) * P + i % R] = pre[e];
-      }
+      for (int e = 0; e < kPre; ++e) pb[e * (kBig / R) * P] = pre[e];
     }
     __syncthreads();
   }
 }
 
-// Inverse y and x transforms: spectra (q, p) in, natural (y, x) out.
-template <int NT>
-__global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a) {
+// Inverse y and x transforms: spectra (q, p) in, natural (y, x) out.  With
+// ADAM the outputs (still written to dst) also drive an Adam step of the
+// parameters at the same positions: each thread loads its float4 groups of
+// parameters and first moments when the plane starts and of second moments
+// before the y product, so that the loads overlap the products, and the y
+// products reach the linear epilogue through LDS.
+template <int NT, bool ADAM>
+__global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a, AdamEpi ad) {
   constexpr int R = 32 * NT, RH = R / 2, P = R + 1, PH = RH + 1, NH = NT / 2;
+  constexpr int kV = R * R / (4 * kBig);        // float4 groups per thread and plane
   extern __shared__ float lds[];
   float *sh = lds;
   float *sp = lds + 2 * RH * PH;
   constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  float bc1 = 1.f, bc2 = 1.f;
+  if constexpr (ADAM) {
+    __shared__ float sbc[2];
+    adam_bias(ad.b1, ad.b2, ad.step_dev, ad.step_host, sbc);
+    bc1 = sbc[0];
+    bc2 = sbc[1];
+  }
   load_basis_eo(sh, a.c, R, RH, PH);
   const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
   const bool act = w < NT * NH;                // NT * NH = NH * NT items per phase
@@ -657,6 +676,15 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a) {
   __syncthreads();
   for (; plane < a.planes; plane += gridDim.x) {
     const long long base = plane_base(plane);
+    float4 th[ADAM ? kV : 1], mo[ADAM ? kV : 1], vo[ADAM ? kV : 1];
+    if constexpr (ADAM) {
+#pragma unroll
+      for (int k = 0; k < kV; ++k) {
+        const unsigned i = 4u * (threadIdx.x + k * kBig);
+        th[k] = *reinterpret_cast<const float4 *>(ad.th + base + i);
+        mo[k] = *reinterpret_cast<const float4 *>(ad.m + base + i);
+      }
+    }
     f32x16 e, o;
     // along x (item: spectral row band qb, spatial column tile xt < NH):
     // t[q][x] = E + O, t[q][R-1-x] = E - O
@@ -679,17 +707,63 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a) {
     constexpr int kPre = R * R / kBig;
     const long long next = plane + gridDim.x;
     float pre[kPre];
-    if (next < a.planes) {
-      const float *in = a.src + plane_base(next);
+    auto prefetch = [&]() {
+      if (next < a.planes) {
+        const float *in = a.src + plane_base(next);
 #pragma unroll
-      for (int k = 0; k < kPre; ++k) pre[k] = in[threadIdx.x + k * kBig];
+        for (int k = 0; k < kPre; ++k) pre[k] = in[threadIdx.x + k * kBig];
+      }
+    };
+    if constexpr (!ADAM) prefetch();           // (with ADAM after the y product: registers)
+    if constexpr (ADAM) {                      // second moments: one product ahead
+#pragma unroll
+      for (int k = 0; k < kV; ++k)
+        vo[k] = *reinterpret_cast<const float4 *>(ad.v + base + 4u * (threadIdx.x + k * kBig));
     }
     // along y (item: spatial row band yb < NH, column tile xc):
     // out[y][x] = E + O, out[R-1-y][x] = E - O
     const int yb = w / NT, xc = w % NT;
     if (act) {
-      const int y = 32 * yb + col, x = 32 * xc + col;
-      eo_gemm(RH, sh + y, sh + RH * PH + y, PH, sp + x, sp + RH * P + x, P, e, o);
+      const int y = 32 * yb + col;
+      eo_gemm(RH, sh + y, sh + RH * PH + y, PH, sp + 32 * xc + col, sp + RH * P + 32 * xc + col, P,
+              e, o);
+    }
+    if constexpr (ADAM) {
+      prefetch();
+      __syncthreads();                         // every product has read sp
+      if (act) {
+        // rows 32 yb + trow(r) and R - 1 - (32 yb + trow(r)), trow(r) =
+        // 4 (lane / 32) + c_r with c_r = 8 (r / 4) + r % 4 in 0..27: two lane
+        // bases and compile-time offsets
+        const int h4 = 4 * ((threadIdx.x & 63) >> 5);
+        float *top = sp + (32 * yb + h4) * P + 32 * xc + col;
+        float *bot = sp + (R - 1 - 32 * yb - h4 - 27) * P + 32 * xc + col;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int cr = 8 * (r >> 2) + (r & 3);
+          top[cr * P] = e[r] + o[r];
+          bot[(27 - cr) * P] = e[r] - o[r];
+        }
+      }
+      __syncthreads();
+      // thread's group k starts at row (4 t) / R + k (4 kBig / R), column (4 t) % R
+      const float *gb = sp + (4 * threadIdx.x / R) * P + (4 * threadIdx.x) % R;
+#pragma unroll
+      for (int k = 0; k < kV; ++k) {
+        const unsigned i = 4u * (threadIdx.x + k * kBig);
+        const float *gr = gb + k * (4 * kBig / R) * P;
+        const float4 gv = make_float4(gr[0], gr[1], gr[2], gr[3]);
+        *reinterpret_cast<float4 *>(a.dst + base + i) = gv;
+        th[k].x = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.x, mo[k].x, vo[k].x, th[k].x);
+        th[k].y = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.y, mo[k].y, vo[k].y, th[k].y);
+        th[k].z = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.z, mo[k].z, vo[k].z, th[k].z);
+        th[k].w = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.w, mo[k].w, vo[k].w, th[k].w);
+        *reinterpret_cast<float4 *>(ad.th + base + i) = th[k];
+        *reinterpret_cast<float4 *>(ad.m + base + i) = mo[k];
+        *reinterpret_cast<float4 *>(ad.v + base + i) = vo[k];
+      }
+    } else if (act) {
+      const int x = 32 * xc + col;
       float *out = a.dst + base;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -700,11 +774,9 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a) {
     }
     __syncthreads();
     if (next < a.planes) {
+      float *pb = sp + (threadIdx.x / R) * P + threadIdx.x % R;   // kBig is a multiple of R
 #pragma unroll
-      for (int k = 0; k < kPre; ++k) {
-        const int i = threadIdx.x + k * kBig;
-        sp[(i / R) * P + i % R] = pre[k];
-      }
+      for (int k = 0; k < kPre; ++k) pb[k * (kBig / R) * P] = pre[k];
     }
     __syncthreads();
   }
@@ -801,7 +873,7 @@ __global__ __launch_bounds__(kBig) void dct_pencil_eo_kernel(FusedArgs a) {
 }
 
 template <int NT>
-pdg_status eo_level(const FusedArgs &f0, hipStream_t st) {
+pdg_status eo_level(const FusedArgs &f0, const AdamEpi *ad, hipStream_t st) {
   constexpr int R = 32 * NT, RH = R / 2;
   const size_t plane = (size_t)(2 * RH * (RH + 1) + R * (R + 1)) * sizeof(float);
   const size_t pencil = (size_t)(2 * RH * (RH + 1) + R * kPQ) * sizeof(float);
@@ -809,7 +881,9 @@ pdg_status eo_level(const FusedArgs &f0, hipStream_t st) {
   if (!attrs) {
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_fwd_kernel<NT>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
-    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_inv_kernel<NT>,
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_inv_kernel<NT, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_inv_kernel<NT, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_pencil_eo_kernel<NT>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil));
@@ -824,7 +898,13 @@ pdg_status eo_level(const FusedArgs &f0, hipStream_t st) {
   f.src = f.dst;
   dct_pencil_eo_kernel<NT><<<gg, kBig, pencil, st>>>(f);
   PDG_TRY(launched("dct_pencil_eo"));
-  dct_plane_eo_inv_kernel<NT><<<gp, kBig, plane, st>>>(f);
+  if (ad) {
+    dct_plane_eo_inv_kernel<NT, true><<<gp, kBig, plane, st>>>(f, *ad);
+  } else {
+    AdamEpi none;
+    memset(&none, 0, sizeof none);
+    dct_plane_eo_inv_kernel<NT, false><<<gp, kBig, plane, st>>>(f, none);
+  }
   return launched("dct_plane_eo_inv");
 }
 
@@ -934,7 +1014,8 @@ pdg_status dct_basis(const GridDev &g, void *ws, hipStream_t st) {
 }
 
 pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *src, float *data,
-                   const void *ws, hipStream_t st) {
+                   const void *ws, hipStream_t st, const AdamFuse *adam, unsigned *fused) {
+  if (fused) *fused = 0u;
   // Out of place only when every level runs the fused passes (whose first
   // pass reads src); otherwise copy once and work in place.
   bool fused_all = true;
@@ -965,12 +1046,24 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       f.mu = mu;
       f.R = R;
       f.lam = lam[l];
-      if (R == 128) {
-        PDG_TRY(eo_level<4>(f, st));
-        continue;
-      }
-      if (R == 64) {
-        PDG_TRY(eo_level<2>(f, st));
+      if (R == 128 || R == 64) {
+        AdamEpi ad;
+        if (adam) {
+          ad.th = adam->th;
+          ad.m = adam->m;
+          ad.v = adam->v;
+          ad.lr = adam->lv.lr[l];
+          ad.b1 = adam->b1;
+          ad.b2 = adam->b2;
+          ad.eps = adam->eps;
+          ad.step_dev = adam->step_dev;
+          ad.step_host = adam->step_host;
+          if (fused) *fused |= 1u << l;
+        }
+        if (R == 128)
+          PDG_TRY(eo_level<4>(f, adam ? &ad : nullptr, st));
+        else
+          PDG_TRY(eo_level<2>(f, adam ? &ad : nullptr, st));
         continue;
       }
       switch ((R + 31) / 32) {

@@ -5,27 +5,6 @@
 namespace pdg {
 namespace {
 
-__device__ __forceinline__ void adam_bias(float b1, float b2, const int *step_dev, int step_host,
-                                          float *sbc) {
-  if (threadIdx.x == 0) {
-    const int k = step_dev ? (*step_dev + 1) : step_host;
-    sbc[0] = (float)(1.0 - pow((double)b1, (double)k));
-    sbc[1] = (float)(1.0 - pow((double)b2, (double)k));
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ float adam_one(float b1, float b2, float eps, float lr, float bc1,
-                                          float bc2, float gi, float &m, float &v, float th) {
-  const float mi = b1 * m + (1.0f - b1) * gi;
-  const float vi = b2 * v + (1.0f - b2) * gi * gi;
-  m = mi;
-  v = vi;
-  const float mh = mi / bc1;
-  const float vh = vi / bc2;
-  return th - lr * mh / (sqrtf(vh) + eps);
-}
-
 __device__ __forceinline__ int level_of(const AdamLevels &lv, long long w) {
   int l = 0;
   while (l + 1 < lv.levels && w >= lv.off[l + 1]) ++l;
@@ -35,8 +14,8 @@ __device__ __forceinline__ int level_of(const AdamLevels &lv, long long w) {
 // kAdamGroups groups of four consecutive values of stack blockIdx.y per thread (all
 // loads issued before the arithmetic); stack % 4 == 0 and 16-byte aligned arrays.
 constexpr int kAdamGroups = 1;
-__global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long stack, float b1,
-                                                    float b2, float eps,
+__global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long stack, long long c0,
+                                                    long long c1, float b1, float b2, float eps,
                                                     const int *__restrict__ step_dev, int step_host,
                                                     float *__restrict__ th, float *__restrict__ m,
                                                     float *__restrict__ v,
@@ -44,13 +23,13 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
   __shared__ float sbc[2];
   adam_bias(b1, b2, step_dev, step_host, sbc);
   const float bc1 = sbc[0], bc2 = sbc[1];
-  const long long w0 = (long long)blockIdx.x * blockDim.x * 4 * kAdamGroups + threadIdx.x * 4;
+  const long long w0 = c0 + (long long)blockIdx.x * blockDim.x * 4 * kAdamGroups + threadIdx.x * 4;
   const long long base = (long long)blockIdx.y * stack;
   float4 gi[kAdamGroups], mi[kAdamGroups], vi[kAdamGroups], ti[kAdamGroups];
 #pragma unroll
   for (int q = 0; q < kAdamGroups; ++q) {
     const long long w = w0 + (long long)q * blockDim.x * 4;
-    if (w < stack) {
+    if (w < c1) {
       gi[q] = *reinterpret_cast<const float4 *>(g + base + w);
       mi[q] = *reinterpret_cast<const float4 *>(m + base + w);
       vi[q] = *reinterpret_cast<const float4 *>(v + base + w);
@@ -60,7 +39,7 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
 #pragma unroll
   for (int q = 0; q < kAdamGroups; ++q) {
     const long long w = w0 + (long long)q * blockDim.x * 4;
-    if (w >= stack) continue;
+    if (w >= c1) continue;
     ti[q].x = adam_one(b1, b2, eps, lv.lr[level_of(lv, w)], bc1, bc2, gi[q].x, mi[q].x, vi[q].x, ti[q].x);
     ti[q].y = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 1)], bc1, bc2, gi[q].y, mi[q].y, vi[q].y, ti[q].y);
     ti[q].z = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 2)], bc1, bc2, gi[q].z, mi[q].z, vi[q].z, ti[q].z);
@@ -72,16 +51,16 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
 }
 
 // One value per thread (any layout).
-__global__ __launch_bounds__(256) void adam_kernel(AdamLevels lv, long long stack, float b1,
-                                                   float b2, float eps,
+__global__ __launch_bounds__(256) void adam_kernel(AdamLevels lv, long long stack, long long c0,
+                                                   long long c1, float b1, float b2, float eps,
                                                    const int *__restrict__ step_dev, int step_host,
                                                    float *__restrict__ th, float *__restrict__ m,
                                                    float *__restrict__ v,
                                                    const float *__restrict__ g) {
   __shared__ float sbc[2];
   adam_bias(b1, b2, step_dev, step_host, sbc);
-  const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= stack) return;
+  const long long w = c0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= c1) return;
   const long long i = (long long)blockIdx.y * stack + w;
   float mi = m[i], vi = v[i];
   th[i] = adam_one(b1, b2, eps, lv.lr[level_of(lv, w)], sbc[0], sbc[1], g[i], mi, vi, th[i]);
@@ -234,24 +213,55 @@ __global__ void assemble_kernel(AssembleArgs a) {
 
 }  // namespace
 
-pdg_status launch_adam(const AdamLevels &lv, long long stack, int batch, float b1, float b2,
-                       float eps, const int *step_dev, int step_host, float *theta, float *m,
-                       float *v, const float *g, hipStream_t st) {
-  if (stack <= 0 || batch <= 0) return PDG_OK;
-  const bool vec = stack % 4 == 0 && ((uintptr_t)theta | (uintptr_t)m | (uintptr_t)v | (uintptr_t)g) % 16 == 0;
+namespace {
+// Adam over columns [c0, c1) of every stack.
+pdg_status adam_cols(const AdamLevels &lv, long long stack, long long c0, long long c1, int batch,
+                     float b1, float b2, float eps, const int *step_dev, int step_host,
+                     float *theta, float *m, float *v, const float *g, hipStream_t st) {
+  if (c1 <= c0 || batch <= 0) return PDG_OK;
+  const bool vec = stack % 4 == 0 && c0 % 4 == 0 && c1 % 4 == 0 &&
+                   ((uintptr_t)theta | (uintptr_t)m | (uintptr_t)v | (uintptr_t)g) % 16 == 0;
+  const long long cols = c1 - c0;
   for (int b0 = 0; b0 < batch; b0 += 65535) {      // grid.y limit
     const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
     const long long o = (long long)b0 * stack;
     if (vec) {
-      dim3 grid(div_up(stack / 4, 256 * kAdamGroups), nb);
-      adam4_kernel<<<grid, 256, 0, st>>>(lv, stack, b1, b2, eps, step_dev, step_host, theta + o,
-                                         m + o, v + o, g + o);
+      dim3 grid(div_up(cols / 4, 256 * kAdamGroups), nb);
+      adam4_kernel<<<grid, 256, 0, st>>>(lv, stack, c0, c1, b1, b2, eps, step_dev, step_host,
+                                         theta + o, m + o, v + o, g + o);
     } else {
-      dim3 grid(div_up(stack, 256), nb);
-      adam_kernel<<<grid, 256, 0, st>>>(lv, stack, b1, b2, eps, step_dev, step_host, theta + o,
-                                        m + o, v + o, g + o);
+      dim3 grid(div_up(cols, 256), nb);
+      adam_kernel<<<grid, 256, 0, st>>>(lv, stack, c0, c1, b1, b2, eps, step_dev, step_host,
+                                        theta + o, m + o, v + o, g + o);
     }
     PDG_TRY(launched("adam"));
+  }
+  return PDG_OK;
+}
+}  // namespace
+
+pdg_status launch_adam(const AdamLevels &lv, long long stack, int batch, float b1, float b2,
+                       float eps, const int *step_dev, int step_host, float *theta, float *m,
+                       float *v, const float *g, hipStream_t st) {
+  if (stack <= 0 || batch <= 0) return PDG_OK;
+  return adam_cols(lv, stack, 0, stack, batch, b1, b2, eps, step_dev, step_host, theta, m, v, g,
+                   st);
+}
+
+pdg_status launch_adam_levels(const AdamLevels &lv, unsigned skip, long long stack, int batch,
+                              float b1, float b2, float eps, const int *step_dev, int step_host,
+                              float *theta, float *m, float *v, const float *g, hipStream_t st) {
+  // one launch per maximal run of levels that are not skipped
+  for (int l = 0; l < lv.levels;) {
+    if ((skip >> l) & 1u) {
+      ++l;
+      continue;
+    }
+    int e = l;
+    while (e < lv.levels && !((skip >> e) & 1u)) ++e;
+    PDG_TRY(adam_cols(lv, stack, lv.off[l], lv.off[e], batch, b1, b2, eps, step_dev, step_host,
+                      theta, m, v, g, st));
+    l = e;
   }
   return PDG_OK;
 }
