@@ -119,15 +119,17 @@ def time_steps(prob, steps, warmup):
 
 
 def time_stages(prob, reps=3):
-    """Per-stage times inside real iterations: each rep runs the seven stages
-    in step order, with an event recorded between consecutive stages on the
-    stream they are enqueued on (torch's current stream), so every stage sees
-    the state an iteration gives it (e.g. the nearest-neighbour screen is warm
-    started from the previous iteration's assignment, not from its own)."""
+    """Per-stage times inside real iterations: each rep runs the stages in
+    step order as the full step runs them (the last being "precond_adam", the
+    preconditioner with Adam fused into its last pass where it can), with an
+    event recorded between consecutive stages on the stream they are
+    enqueued on (torch's current stream), so every stage sees the state an
+    iteration gives it (e.g. the nearest-neighbour screen is warm started
+    from the previous iteration's assignment, not from its own).  The
+    preconditioner and Adam are also timed alone ("precond", "adam")."""
     import torch
-    from paper_2509_18097_amd import _lib as L
     st = torch.cuda.current_stream()
-    names = L.STAGES
+    names = ("warp", "nn", "loss", "grad", "scatter", "precond_adam")
     for name in names:                   # warm
         prob.stage(name)
     torch.cuda.synchronize()
@@ -144,6 +146,17 @@ def time_stages(prob, reps=3):
             out[name] += ev[k].elapsed_time(ev[k + 1]) / reps
     if t0 is not None:
         out["nn_tiles"] = (screen_tiles(prob) - t0) / reps
+    alone = ("precond", "adam")
+    out.update({name: 0.0 for name in alone})
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(alone) + 1)]
+        ev[0].record(st)
+        for k, name in enumerate(alone):
+            prob.stage(name)
+            ev[k + 1].record(st)
+        torch.cuda.synchronize()
+        for k, name in enumerate(alone):
+            out[name] += ev[k].elapsed_time(ev[k + 1]) / reps
     return out
 
 

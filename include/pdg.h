@@ -227,7 +227,9 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
  * (device double[8], nullable) receives {L, L_transform, L_iso, cd_max,
  * sum_t CD_R(P^_t,P_t)/T, sum_t w_conf CD_R(X_t,P_t)/T, w_conf(T), epoch}.
  * With use_graph != 0 the step is replayed from a HIP graph captured on the
- * first call for this stream. */
+ * first call for this stream.  With the DCT preconditioner the last inverse
+ * pass of each 64^3 and 128^3 level applies Adam to the values it writes
+ * (same arithmetic as the Adam stage, so the same parameters bit for bit). */
 pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t use_graph,
                     hipStream_t stream);
 /* One stage of pdg_step alone, in step order WARP, NN, LOSS, GRAD, SCATTER,
@@ -235,7 +237,8 @@ pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t u
  * what the previous stages of the same or an earlier step left in the
  * workspace; PRECOND rewrites the preconditioned gradient from the raw one and
  * ADAM updates params/m/v, so replaying them alone changes the state exactly
- * as the step would. */
+ * as the step would.  PRECOND_ADAM runs PRECOND and ADAM as pdg_step does
+ * (Adam inside the preconditioner's last pass where it can). */
 typedef enum {
   PDG_STAGE_WARP = 0,     /* Eq. 1 and 8: P^_t and the template chain (and, in
                              the bf16 mode, the screen packs of the warped sets) */
@@ -245,7 +248,8 @@ typedef enum {
   PDG_STAGE_GRAD = 3,     /* adjoints wrt the warped positions, reverse sweep   */
   PDG_STAGE_SCATTER = 4,  /* transpose of Eq. 1 into the grid gradient          */
   PDG_STAGE_PRECOND = 5,  /* Eq. 3                                              */
-  PDG_STAGE_ADAM = 6      /* Sec. 3.6                                           */
+  PDG_STAGE_ADAM = 6,     /* Sec. 3.6                                           */
+  PDG_STAGE_PRECOND_ADAM = 7   /* PRECOND then ADAM as in pdg_step              */
 } pdg_stage;
 pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream);
 

@@ -19,6 +19,9 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1}
 PRECOND_METHODS = {"cg": 0, "dct": 1}
 STAGES = ("warp", "nn", "loss", "grad", "scatter", "precond", "adam")
+# stage ids of pdg_step_stage: the seven stages and "precond_adam" (the last
+# two as pdg_step runs them)
+STAGE_IDS = {**{n: i for i, n in enumerate(STAGES)}, "precond_adam": 7}
 BUFFERS = {"phat": 0, "xhat": 1, "nn": 2, "losses": 3, "wconf": 4, "grad": 5, "pgrad": 6,
            "gphat": 7, "gxhat": 8, "terms": 9, "lam": 10, "screen_tiles": 11}
 

@@ -480,10 +480,10 @@ void layout(pdg_problem &p, Carve &c) {
     p.coords = c.take<float4>(p.pack_rows);
     p.boxes = c.take<float4>(p.box_tiles);
     p.maxnorm = c.take<unsigned>((p.nseg + T) * kMaxnormStride);
-    p.fperm = c.take<int>(F * N);
-    p.tperm = c.take<int>(V);
     p.tiles = c.take<unsigned long long>(1);
   }
+  p.fperm = c.take<int>(F * N);
+  p.tperm = c.take<int>(V);
   p.segs = c.take<ChSeg>(p.nseg);
   p.b_base = c.take<unsigned>(p.nseg);
   if (p.d.precond_method == PDG_PRECOND_DCT)
@@ -541,10 +541,12 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
   const pdg_hyper &h = p.d.hp;
   switch (stage) {
     case PDG_STAGE_WARP:  // P^_t = warp(G_t, P_{t-1}); X_t = warp(G_t, X_{t-1}) (Eq. 1, 8)
+      // points and vertices in Morton order of P_t and X_0 (cache reuse of grid cells)
       PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T,
-                          st));
+                          st, p.fperm, N));
       if (p.has_tm)
-        PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T, st));
+        PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T,
+                                  p.tperm, st));
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
         // screen packs of the moving sets (P^_t, X_t), which change every step
         PDG_TRY(launch_fill((float *)p.maxnorm, (long long)p.nseg * kMaxnormStride, 0.f, st));
@@ -582,7 +584,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
                                          (float)h.alpha, p.w, p.rpart, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(iso_args(p), st));
       if (p.has_tm)
-        PDG_TRY(launch_chain_reverse(g, p.d.params, P, p.xhat, p.gxhat, p.lam, V, (int)T, st));
+        PDG_TRY(launch_chain_reverse(g, p.d.params, P, p.xhat, p.gxhat, p.lam, V, (int)T,
+                                     p.tperm, st));
       return PDG_OK;
     case PDG_STAGE_SCATTER: {  // dL/dG: deterministic transpose of Eq. 1
       ScatterLists sl;
@@ -631,6 +634,11 @@ pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
   for (int s = PDG_STAGE_WARP; s <= PDG_STAGE_ADAM; ++s)
     PDG_TRY(enqueue_stage(p, s, st, user_terms, true));
   return PDG_OK;
+}
+
+pdg_status enqueue_precond_adam(pdg_problem &p, hipStream_t st) {
+  PDG_TRY(enqueue_stage(p, PDG_STAGE_PRECOND, st, nullptr, true));
+  return enqueue_stage(p, PDG_STAGE_ADAM, st, nullptr, true);
 }
 
 }  // namespace
@@ -1058,18 +1066,19 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     return s;
   }
   pdg_status s = PDG_OK;
+  // Morton order of every frame and of the template (processing order of the
+  // warps and the screen packs' row order)
+  for (long long f = 0; f < p->F && s == PDG_OK; ++f) {
+    uint32_t *perm = (uint32_t *)(p->fperm + f * N);
+    s = launch_morton(pd->points + f * 3 * N, N, (int)N, p->rkeys, perm, stream);
+    if (s == PDG_OK) s = radix_sort(p->rkeys, perm, N, 30, p->sort, stream);
+  }
+  if (s == PDG_OK && p->has_tm) {
+    s = launch_morton(pd->template_verts, V, (int)V, p->tkeys, (uint32_t *)p->tperm, stream);
+    if (s == PDG_OK) s = radix_sort(p->tkeys, (uint32_t *)p->tperm, V, 30, p->sort, stream);
+  }
   if (p->packs) {
-    // Morton order of every frame and of the template, then the fixed frames'
-    // packs (their rows, coordinates and boxes never change)
-    for (long long f = 0; f < p->F && s == PDG_OK; ++f) {
-      uint32_t *perm = (uint32_t *)(p->fperm + f * N);
-      s = launch_morton(pd->points + f * 3 * N, N, (int)N, p->rkeys, perm, stream);
-      if (s == PDG_OK) s = radix_sort(p->rkeys, perm, N, 30, p->sort, stream);
-    }
-    if (s == PDG_OK && p->has_tm) {
-      s = launch_morton(pd->template_verts, V, (int)V, p->tkeys, (uint32_t *)p->tperm, stream);
-      if (s == PDG_OK) s = radix_sort(p->tkeys, (uint32_t *)p->tperm, V, 30, p->sort, stream);
-    }
+    // the fixed frames' packs (their rows, coordinates and boxes never change)
     if (s == PDG_OK) s = launch_fill((float *)p->maxnorm + (long long)p->nseg * kMaxnormStride,
                                      T * kMaxnormStride, 0.f, stream);
     if (s == PDG_OK) s = launch_screen_pack(p->ssets + p->nseg, (int)T, (int)N, stream);
@@ -1133,10 +1142,11 @@ pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream) {
     set_error("problem is NULL");
     return PDG_EINVAL;
   }
-  if (stage < PDG_STAGE_WARP || stage > PDG_STAGE_ADAM) {
+  if (stage < PDG_STAGE_WARP || stage > PDG_STAGE_PRECOND_ADAM) {
     set_error("unknown stage %d", stage);
     return PDG_EINVAL;
   }
+  if (stage == PDG_STAGE_PRECOND_ADAM) return enqueue_precond_adam(*p, stream);
   return enqueue_stage(*p, stage, stream, nullptr, false);
 }
 

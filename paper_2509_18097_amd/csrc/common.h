@@ -84,22 +84,27 @@ pdg_status radix_sort(uint32_t *keys, uint32_t *vals, long long n, int bits, voi
 
 // ------------------------------------------------------------- launchers --
 // warp.hip
+// order (nullable): batch b processes its points in the order
+// order[b * order_stride + 0 .. n-1] (a spatial order gathers grid cells
+// with better cache reuse; the result does not depend on it).
 pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, const float *x,
                        long long xstride, long long ldx, float *out, long long ostride,
-                       long long ldo, long long n, int batch, hipStream_t st);
+                       long long ldo, long long n, int batch, hipStream_t st,
+                       const int *order = nullptr, long long order_stride = 0);
 // lam_out = gdir (nullable) + lam + J^T lam at positions x under `grids`.
 pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const float *x, long long ldx,
                                 const float *lam, long long ldl, const float *gdir, long long ldd,
                                 float *lam_out, long long ldo, long long n, hipStream_t st);
 // Template chain of Eq. 8 for all transitions in one launch: xhat[0] = x0,
 // xhat[t+1] = warp(params + t*P, xhat[t]) ([F][3][V] SoA).
+// order (nullable): vertex processing order, as for launch_warp.
 pdg_status launch_chain_warp(const GridDev &g, const float *params, long long P, const float *x0,
-                             float *xhat, long long V, int T, hipStream_t st);
+                             float *xhat, long long V, int T, const int *order, hipStream_t st);
 // Its reverse sweep: lam[T-1] = gd[T-1], lam[k-1] = gd[k-1] + lam[k] + J_k^T lam[k],
 // J_k the Jacobian of grids k at xhat[k] (xhat: frames 0..T).
 pdg_status launch_chain_reverse(const GridDev &g, const float *params, long long P,
                                 const float *xhat, const float *gd, float *lam, long long V, int T,
-                                hipStream_t st);
+                                const int *order, hipStream_t st);
 // Entry keys for the deterministic grid scatter: for sample s of segment
 // seg and level l (entry e = (seg*L + l)*S + s) the key is the global node id
 // of the base cell, seg*nodes + noff[l] + cell (below 2^32), the value e.

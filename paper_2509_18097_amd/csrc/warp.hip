@@ -97,14 +97,19 @@ __device__ __forceinline__ void adjoint_point(const GridDev &g, const float *__r
   r2 = l2 + g.scale * j2;
 }
 
+// Thread i of batch b warps point order[b * order_stride + i] (or i): a
+// spatial order keeps the grid cells of neighbouring threads close.
 __global__ __launch_bounds__(256) void warp_kernel(GridDev g, const float *__restrict__ grids,
                                                    long long gstride, const float *__restrict__ x,
                                                    long long xstride, long long ldx,
                                                    float *__restrict__ out, long long ostride,
-                                                   long long ldo, long long n) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+                                                   long long ldo, long long n,
+                                                   const int *__restrict__ order,
+                                                   long long order_stride) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
   const int b = blockIdx.y;
+  const long long i = order ? order[b * order_stride + t] : t;
   const float *X = x + b * xstride;
   float *O = out + b * ostride;
   warp_point(g, grids + b * gstride, X[i], X[ldx + i], X[2 * ldx + i], O[i], O[ldo + i],
@@ -172,11 +177,13 @@ constexpr int kChainLanes = PDG_MAX_LEVELS;
 // X_{t+1} = warp(G_t, X_t) for t = 0..T-1, X_0 copied to frame 0 (Eq. 8).
 __global__ __launch_bounds__(256) void chain_warp_kernel(GridDev g, const float *__restrict__ params,
                                                          long long P, const float *__restrict__ x0,
-                                                         float *__restrict__ xhat, long long V, int T) {
-  const long long v = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kChainLanes;
+                                                         float *__restrict__ xhat, long long V, int T,
+                                                         const int *__restrict__ order) {
+  const long long item = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kChainLanes;
   const int l = threadIdx.x % kChainLanes;
   const int lead = (threadIdx.x & 63) - l;       // group leader lane in the wave
-  const bool ok = v < V;
+  const bool ok = item < V;
+  const long long v = ok && order ? order[item] : item;   // vertex (spatial order)
   float px = 0.f, py = 0.f, pz = 0.f;
   if (ok) {
     px = x0[v];
@@ -219,11 +226,12 @@ __global__ __launch_bounds__(256) void chain_reverse_kernel(GridDev g,
                                                             const float *__restrict__ xhat,
                                                             const float *__restrict__ gd,
                                                             float *__restrict__ lam, long long V,
-                                                            int T) {
-  const long long v = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kChainLanes;
+                                                            int T, const int *__restrict__ order) {
+  const long long item = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kChainLanes;
   const int l = threadIdx.x % kChainLanes;
   const int lead = (threadIdx.x & 63) - l;
-  const bool ok = v < V;
+  const bool ok = item < V;
+  const long long v = ok && order ? order[item] : item;   // vertex (spatial order)
   const long long s3 = 3 * V;
   float l0 = 0.f, l1 = 0.f, l2 = 0.f;
   if (ok) {
@@ -681,10 +689,12 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(GridDev g, GatherPla
 
 pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, const float *x,
                        long long xstride, long long ldx, float *out, long long ostride,
-                       long long ldo, long long n, int batch, hipStream_t st) {
+                       long long ldo, long long n, int batch, hipStream_t st, const int *order,
+                       long long order_stride) {
   if (n <= 0 || batch <= 0) return PDG_OK;
   dim3 grid(div_up(n, 256), batch);
-  warp_kernel<<<grid, 256, 0, st>>>(g, grids, gstride, x, xstride, ldx, out, ostride, ldo, n);
+  warp_kernel<<<grid, 256, 0, st>>>(g, grids, gstride, x, xstride, ldx, out, ostride, ldo, n,
+                                    order, order_stride);
   return launched("warp");
 }
 
@@ -698,18 +708,19 @@ pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const floa
 }
 
 pdg_status launch_chain_warp(const GridDev &g, const float *params, long long P, const float *x0,
-                             float *xhat, long long V, int T, hipStream_t st) {
+                             float *xhat, long long V, int T, const int *order, hipStream_t st) {
   if (V <= 0) return PDG_OK;
-  chain_warp_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T);
+  chain_warp_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T,
+                                                                   order);
   return launched("chain_warp");
 }
 
 pdg_status launch_chain_reverse(const GridDev &g, const float *params, long long P,
                                 const float *xhat, const float *gd, float *lam, long long V, int T,
-                                hipStream_t st) {
+                                const int *order, hipStream_t st) {
   if (V <= 0 || T <= 0) return PDG_OK;
   chain_reverse_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam,
-                                                                      V, T);
+                                                                      V, T, order);
   return launched("chain_reverse");
 }
 

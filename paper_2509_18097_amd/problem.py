@@ -141,9 +141,10 @@ class Problem:
         L.check(L.lib().pdg_step(self._h, int(epoch), None, int(bool(use_graph)), st), "pdg_step")
 
     def stage(self, name: str, stream: torch.cuda.Stream | None = None):
-        """Enqueue one stage of the step alone (see pdg_step_stage)."""
+        """Enqueue one stage of the step alone (see pdg_step_stage); names are
+        those of _lib.STAGES and "precond_adam"."""
         st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
-        L.check(L.lib().pdg_step_stage(self._h, L.STAGES.index(name), st), "pdg_step_stage")
+        L.check(L.lib().pdg_step_stage(self._h, L.STAGE_IDS[name], st), "pdg_step_stage")
 
     def buffer(self, name: str) -> torch.Tensor:
         """View of an intermediate buffer of the last step (see pdg_problem_buffer)."""
