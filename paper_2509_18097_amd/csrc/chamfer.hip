@@ -27,6 +27,7 @@ __device__ __forceinline__ float d2_contract(float qx, float qy, float qz, float
 
 __global__ __launch_bounds__(kNNThreads) void nn_exact_kernel(const NNJob *__restrict__ jobs) {
   const NNJob J = jobs[blockIdx.y];
+  const PDG_GLOBAL float *jq = glb(J.q), *jc = glb(J.c);
   const int q0 = blockIdx.x * kQTile;
   if (q0 >= J.nq) return;
   __shared__ float4 sc[kCTile];
@@ -37,9 +38,9 @@ __global__ __launch_bounds__(kNNThreads) void nn_exact_kernel(const NNJob *__res
   for (int k = 0; k < kQPT; ++k) {
     const int qi = q0 + k * kNNThreads + tid;
     const bool ok = qi < J.nq;
-    qx[k] = ok ? J.q[qi] : 0.f;
-    qy[k] = ok ? J.q[(long long)J.nq + qi] : 0.f;
-    qz[k] = ok ? J.q[2ll * J.nq + qi] : 0.f;
+    qx[k] = ok ? jq[qi] : 0.f;
+    qy[k] = ok ? jq[(long long)J.nq + qi] : 0.f;
+    qz[k] = ok ? jq[2ll * J.nq + qi] : 0.f;
     best[k] = __builtin_huge_valf();
     bi[k] = 0;
   }
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kNNThreads) void nn_exact_kernel(const NNJob *__res
     const int cnt = (J.nc - c0) < kCTile ? (J.nc - c0) : kCTile;
     __syncthreads();
     for (int j = tid; j < cnt; j += kNNThreads)
-      sc[j] = make_float4(J.c[c0 + j], J.c[nc + c0 + j], J.c[2 * nc + c0 + j], 0.f);
+      sc[j] = make_float4(jc[c0 + j], jc[nc + c0 + j], jc[2 * nc + c0 + j], 0.f);
     __syncthreads();
     int j = 0;
     for (; j + 4 <= cnt; j += 4) {
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(kNNThreads) void nn_exact_kernel(const NNJob *__res
 #pragma unroll
   for (int k = 0; k < kQPT; ++k) {
     const int qi = q0 + k * kNNThreads + tid;
-    if (qi < J.nq) J.nn[qi] = bi[k];
+    if (qi < J.nq) glb(J.nn)[qi] = bi[k];
   }
 }
 
@@ -103,11 +104,11 @@ __global__ __launch_bounds__(256) void chamfer_loss_kernel(const ChSeg *__restri
   __shared__ double sh[4];
   const ChSeg S = segs[blockIdx.y];
   const int dir = blockIdx.z;
-  const float *q = dir == 0 ? S.a : S.b;
-  const float *c = dir == 0 ? S.b : S.a;
+  const PDG_GLOBAL float *q = glb(dir == 0 ? S.a : S.b);
+  const PDG_GLOBAL float *c = glb(dir == 0 ? S.b : S.a);
   const int nq = dir == 0 ? S.n : S.m;
   const long long nc = dir == 0 ? S.m : S.n;
-  const int *nn = dir == 0 ? S.nn_a : S.nn_b;
+  const PDG_GLOBAL int *nn = glb(dir == 0 ? S.nn_a : S.nn_b);
   double acc = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < nq; i += kLossBlocks * 256) {
     const int j = nn[i];
@@ -138,18 +139,21 @@ __global__ __launch_bounds__(256) void chamfer_grad_fwd_kernel(const ChSeg *__re
                                                                const double *__restrict__ w) {
   const int seg = blockIdx.y;
   const ChSeg S = segs[seg];
+  const PDG_GLOBAL float *Sa = glb(S.a), *Sb = glb(S.b);
+  const PDG_GLOBAL int *Snn = glb(S.nn_a);
+  PDG_GLOBAL float *Sga = glb(S.ga);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= S.n || S.ga == nullptr) return;
   const long long m = S.m, n = S.n;
-  const int j = S.nn_a[i];
-  const float dx = S.a[i] - S.b[j];
-  const float dy = S.a[n + i] - S.b[m + j];
-  const float dz = S.a[2 * n + i] - S.b[2 * m + j];
+  const int j = Snn[i];
+  const float dx = Sa[i] - Sb[j];
+  const float dy = Sa[n + i] - Sb[m + j];
+  const float dz = Sa[2 * n + i] - Sb[2 * m + j];
   const float s = dx * dx + dy * dy + dz * dz;
   const float coef = (float)(w[2 * seg] / (double)S.n) * expf(-alpha * s) * (1.0f - alpha * s) * 2.0f;
-  S.ga[i] = coef * dx;
-  S.ga[n + i] = coef * dy;
-  S.ga[2 * n + i] = coef * dz;
+  Sga[i] = coef * dx;
+  Sga[n + i] = coef * dy;
+  Sga[2 * n + i] = coef * dz;
 }
 
 __global__ __launch_bounds__(256) void chamfer_rev_keys_kernel(const ChSeg *__restrict__ segs,
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(256) void chamfer_rev_keys_kernel(const ChSeg *__re
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= S.m) return;
   const unsigned g = b_base[seg] + (unsigned)j;
-  keys[g] = S.a_base + (unsigned)S.nn_b[j];
+  keys[g] = S.a_base + (unsigned)glb(S.nn_b)[j];
   vals[g] = g;
 }
 
@@ -207,13 +211,14 @@ __global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
     sg = rev_segment(b_base, nseg, g0);
     const ChSeg S = segs[sg];
     if (S.ga != nullptr) {
+      const PDG_GLOBAL float *Sa = glb(S.a), *Sb = glb(S.b);
       const long long n = S.n, m = S.m;
       const int ai = (int)(key - S.a_base);
       const int j = (int)(g0 - b_base[sg]);
       const float cw = (float)(w[2 * sg + 1] / (double)S.m);
-      const float dx = S.a[ai] - S.b[j];
-      const float dy = S.a[n + ai] - S.b[m + j];
-      const float dz = S.a[2 * n + ai] - S.b[2 * m + j];
+      const float dx = Sa[ai] - Sb[j];
+      const float dy = Sa[n + ai] - Sb[m + j];
+      const float dz = Sa[2 * n + ai] - Sb[2 * m + j];
       const float d2 = dx * dx + dy * dy + dz * dz;
       const float coef = cw * expf(-alpha * d2) * (1.0f - alpha * d2) * 2.0f;
       v[0] = coef * dx;
@@ -262,9 +267,10 @@ __global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
     if (S.ga == nullptr) return;
     const long long n = S.n;
     const int ai = (int)(key - S.a_base);
-    S.ga[ai] += v[0];
-    S.ga[n + ai] += v[1];
-    S.ga[2 * n + ai] += v[2];
+    PDG_GLOBAL float *ga = glb(S.ga);
+    ga[ai] += v[0];
+    ga[n + ai] += v[1];
+    ga[2 * n + ai] += v[2];
   }
 }
 
@@ -298,9 +304,10 @@ __global__ __launch_bounds__(256) void rev_join_kernel(const ChSeg *__restrict__
   if (S.ga == nullptr) return;
   const long long n = S.n;
   const int ai = (int)(key - S.a_base);
-  S.ga[ai] += s.x;
-  S.ga[n + ai] += s.y;
-  S.ga[2 * n + ai] += s.z;
+  PDG_GLOBAL float *ga = glb(S.ga);
+  ga[ai] += s.x;
+  ga[n + ai] += s.y;
+  ga[2 * n + ai] += s.z;
 }
 
 }  // namespace

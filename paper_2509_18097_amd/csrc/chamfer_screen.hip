@@ -123,14 +123,19 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
   __shared__ float red[7][4];
   const ScreenSet S = sets[blockIdx.y];
   if ((long long)blockIdx.x * 256 >= S.n) return;
+  const PDG_GLOBAL float *sx = glb(S.x);
+  const PDG_GLOBAL int *sperm = glb(S.perm);
+  PDG_GLOBAL uint4 *spk = glb(S.pack);
+  PDG_GLOBAL float4 *scoords = glb(S.coords);
+  PDG_GLOBAL float4 *sboxes = glb(S.boxes);
   const int i = blockIdx.x * 256 + threadIdx.x;
   float nrm = 0.f;
   float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
   float hi3[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
   if (i < S.n) {
     const long long n = S.n;
-    const int o = S.perm ? S.perm[i] : i;
-    const float c[3] = {S.x[o], S.x[n + o], S.x[2 * n + o]};
+    const int o = S.perm ? sperm[i] : i;
+    const float c[3] = {sx[o], sx[n + o], sx[2 * n + o]};
     unsigned short hi[3], lw[3];
     for (int k = 0; k < 3; ++k) {
       hi[k] = bf16_rn(c[k]);
@@ -161,9 +166,9 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     w1.y = row[10] | ((unsigned)row[11] << 16);
     w1.z = 0u;
     w1.w = 0u;
-    S.pack[2 * i] = w0;
-    S.pack[2 * i + 1] = w1;
-    S.coords[i] = make_float4(c[0], c[1], c[2], __int_as_float(o));
+    spk[2 * i] = w0;
+    spk[2 * i + 1] = w1;
+    scoords[i] = make_float4(c[0], c[1], c[2], __int_as_float(o));
     nrm = sqrtf(nn);
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -190,9 +195,9 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     }
     // one atomic per block; each set's maximum sits on a cache line of its own
     const float m = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-    if (m > 0.f) atomicMax(S.maxnorm, __float_as_uint(m));
-    S.boxes[2 * blockIdx.x] = make_float4(b[0], b[1], b[2], 0.f);
-    S.boxes[2 * blockIdx.x + 1] = make_float4(b[3], b[4], b[5], 0.f);
+    if (m > 0.f) atomicMax(glb(S.maxnorm), __float_as_uint(m));
+    sboxes[2 * blockIdx.x] = make_float4(b[0], b[1], b[2], 0.f);
+    sboxes[2 * blockIdx.x + 1] = make_float4(b[3], b[4], b[5], 0.f);
   }
 }
 
@@ -219,7 +224,7 @@ __device__ __forceinline__ int out_row(int r, int lane) {
 }
 
 __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, int cbase, int nc,
-                                         const float4 *__restrict__ cc) {
+                                         const PDG_GLOBAL float4 *__restrict__ cc) {
   float m = fminf(fminf(v[0], v[1]), v[2]);
   m = fminf(fminf(m, v[3]), v[4]);
   m = fminf(fminf(m, v[5]), v[6]);
@@ -255,14 +260,17 @@ struct TileRegs {
   uint4 w[kPerThread][2];
 };
 
-__device__ __forceinline__ void fetch_tile(const ScreenJob &J, int c0, TileRegs &t) {
+__device__ __forceinline__ void fetch_tile(const PDG_GLOBAL uint4 *pack, int nc, int c0,
+                                           TileRegs &t) {
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
+    // every lane loads (rows past the end re-read the last row), so the
+    // number of loads in flight is the same on every path
     const int c = c0 + k * kThreads + (int)threadIdx.x;
-    if (c < J.nc) {
-      t.w[k][0] = J.pack[2ll * c];
-      t.w[k][1] = J.pack[2ll * c + 1];
-    } else {
+    const long long cl = c < nc ? c : nc - 1;
+    t.w[k][0] = pack[2 * cl];
+    t.w[k][1] = pack[2 * cl + 1];
+    if (c >= nc) {
       t.w[k][0] = make_uint4(0u, 0u, 0u, 0u);
       t.w[k][1] = make_uint4(0x7F800000u, 0u, 0u, 0u);   // n_hi = +inf: S = +inf
     }
@@ -306,6 +314,11 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
   const ScreenJob J = jobs[by];
   const int q0 = bx * kQPerBlock;
   if (q0 >= J.nq) return;
+  const PDG_GLOBAL float4 *jq = glb(J.q), *jcc = glb(J.cc);
+  const PDG_GLOBAL float4 *jqboxes = glb(J.qboxes), *jcboxes = glb(J.cboxes);
+  const PDG_GLOBAL float *jc = glb(J.c);
+  const PDG_GLOBAL uint4 *jpack = glb(J.pack);
+  PDG_GLOBAL int *jnn = glb(J.nn);
   __shared__ uint4 spack[2][kCTile * 2];
   __shared__ int tlist[kListMax];
   __shared__ float tlb[kListMax];
@@ -314,7 +327,7 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int half = lane >> 5;
   const long long nc = J.nc;
-  const float cmax = __uint_as_float(*J.maxnorm);
+  const float cmax = __uint_as_float(*glb(J.maxnorm));
   QState st[kQB];
   bool ok[kQB];
   int qorig[kQB];
@@ -324,7 +337,8 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
     const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);   // packed position
     QState &s = st[h];
     ok[h] = q < J.nq;
-    const float4 qc = ok[h] ? J.q[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 qc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok[h]) qc = jq[q];
     qorig[h] = __float_as_int(qc.w);
     s.x = qc.x;
     s.y = qc.y;
@@ -335,9 +349,9 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
     s.best = __builtin_huge_valf();
     s.idx = 0x7fffffff;
     if (ok[h] && warm) {
-      const int p = J.nn[qorig[h]];
+      const int p = jnn[qorig[h]];
       if (p >= 0 && p < J.nc) {
-        s.best = d2_contract(s.x, s.y, s.z, J.c[p], J.c[nc + p], J.c[2 * nc + p]);
+        s.best = d2_contract(s.x, s.y, s.z, jc[p], jc[nc + p], jc[2 * nc + p]);
         s.idx = p;
       }
     }
@@ -357,7 +371,7 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
       bq[h][e] = *reinterpret_cast<const __bf16 *>(&b);
     }
   }
-  const float4 qmin = J.qboxes[2 * bx], qmax = J.qboxes[2 * bx + 1];
+  const float4 qmin = jqboxes[2 * bx], qmax = jqboxes[2 * bx + 1];
   // this wave's 64 queries: their box (wave-uniform)
   float4 wmin = make_float4(__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), 0.f);
   float4 wmaxc = make_float4(-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf(), 0.f);
@@ -406,7 +420,7 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
         int tile = 0;
         if (k < span) {
           tile = (start + base + k) % ntiles;
-          lb = box_lb(qmin, qmax, J.cboxes[2 * tile], J.cboxes[2 * tile + 1]);
+          lb = box_lb(qmin, qmax, jcboxes[2 * tile], jcboxes[2 * tile + 1]);
           pass = !(lb * kCullSlack > bmax);
         }
         const unsigned long long m = __ballot(pass);
@@ -423,22 +437,28 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
     const int count = s_count;
     int i = 0;
     while (i < count && tlb[i] * kCullSlack > bmax) ++i;
+    float4 tmin = make_float4(0.f, 0.f, 0.f, 0.f), tmax = tmin;   // box of tile tlist[i]
     if (i < count) {
-      fetch_tile(J, tlist[i] * kTile, regs);
+      fetch_tile(jpack, J.nc, tlist[i] * kTile, regs);
+      tmin = jcboxes[2 * tlist[i]];
+      tmax = jcboxes[2 * tlist[i] + 1];
       store_tile(regs, spack[0]);
     }
     int buf = 0;
     while (i < count) {
       const float wbest = wave_best_max(st, ok);
       if (lane == 0) wmax[it & 1][wv] = wbest;
-      const float4 tmin = J.cboxes[2 * tlist[i]], tmax = J.cboxes[2 * tlist[i] + 1];
       __syncthreads();          // tile tlist[i] is in spack[buf]; the other buffer is free
       bmax = fmaxf(fmaxf(wmax[it & 1][0], wmax[it & 1][1]), fmaxf(wmax[it & 1][2], wmax[it & 1][3]));
       ++it;
       int nxt = i + 1;
       while (nxt < count && tlb[nxt] * kCullSlack > bmax) ++nxt;
       const bool more = nxt < count;
-      if (more) fetch_tile(J, tlist[nxt] * kTile, regs);   // in flight while this tile is screened
+      // the next tile and its box, in flight while this tile is screened
+      // (issued on every path; without a next tile this one is read again)
+      const int ft = tlist[more ? nxt : i];
+      fetch_tile(jpack, J.nc, ft * kTile, regs);
+      const float4 nmin = jcboxes[2 * ft], nmax = jcboxes[2 * ft + 1];
       const int c0 = tlist[i] * kTile;
       const int left = (J.nc - c0 + 31) / 32;
       // the wave skips a tile that cannot beat any of its own queries' bests
@@ -451,12 +471,14 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
 #pragma unroll
         for (int h = 0; h < kQB; ++h) {   // one result live at a time (register budget)
           const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
-          consider(st[h], v, lane, c0 + sub * 32, J.nc, J.cc);
+          consider(st[h], v, lane, c0 + sub * 32, J.nc, jcc);
         }
       }
       if (more) store_tile(regs, spack[buf ^ 1]);
       buf ^= 1;
       i = nxt;
+      tmin = nmin;
+      tmax = nmax;
       ++screened;
     }
     __syncthreads();            // the list is rebuilt next
@@ -470,9 +492,9 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
       s.best = ob;
       s.idx = oi;
     }
-    if (half == 0 && ok[h]) J.nn[qorig[h]] = s.idx;
+    if (half == 0 && ok[h]) jnn[qorig[h]] = s.idx;
   }
-  if (J.tiles && tid == 0) atomicAdd(J.tiles, (unsigned long long)screened);
+  if (J.tiles && tid == 0) atomicAdd(glb(J.tiles), (unsigned long long)screened);
 }
 
 }  // namespace

@@ -73,6 +73,23 @@ __device__ __forceinline__ float corner_weight(int k, float fx, float fy, float 
 
 inline unsigned div_up(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// Pointers that kernels read from device-side tables (job and segment
+// descriptors) are generic to the compiler, which then emits flat memory
+// instructions and, unable to tell their counters apart, waits for all
+// outstanding loads before each use.  Every such pointer addresses global
+// memory; glb() states that, so global instructions with exact waits are used.
+// (The qualifier means something only to the device pass; the host pass,
+// which parses device code without generating it, sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PDG_GLOBAL __attribute__((address_space(1)))
+#else
+#define PDG_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ PDG_GLOBAL T *glb(T *p) {
+  return (PDG_GLOBAL T *)p;
+}
+
 // ------------------------------------------------------------ radix sort --
 // Stable LSD radix sort of (key, value) pairs on uint32 keys, 8 bits a pass.
 // Scratch: two key/value buffers of n entries plus a histogram.
