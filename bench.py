@@ -45,8 +45,8 @@ PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # profiles/nn_screen_c2_bf16_dct.md for the kernel source whose SHA-256 starts
 # with the given prefix; reported only while the source is unchanged.
 PMC_TRAFFIC = {
-    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "38b3de73ddda65ce",
-                         (2 * 245306.25 + 85034.796875) * 1024),
+    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "9adbdf7d44b7a1b0",
+                         (2 * 266410.5 + 107645.25) * 1024),
 }
 
 
