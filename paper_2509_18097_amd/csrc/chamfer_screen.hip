@@ -286,14 +286,28 @@ __device__ __forceinline__ void store_tile(const TileRegs &t, uint4 *spack) {
   }
 }
 
+template <int D>
+__device__ __forceinline__ float row_shr(float x) {   // lane l - D of its row of 16, else 0
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + D, 0xf, 0xf, true));
+}
+
 // Largest current best of this wave's valid queries (lanes without a query
 // report 0); the block maximum bounds every query's best from above.
 __device__ __forceinline__ float wave_best_max(const QState *st, const bool *ok) {
   float m = 0.f;
 #pragma unroll
   for (int h = 0; h < kQB; ++h) m = ok[h] ? fmaxf(m, st[h].best) : m;
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-  return m;
+  // row maxima by DPP shifts (bests are >= 0, so the zeros shifted in are
+  // harmless; all lanes are active here), then the four row ends read out
+  m = fmaxf(m, row_shr<1>(m));
+  m = fmaxf(m, row_shr<2>(m));
+  m = fmaxf(m, row_shr<4>(m));
+  m = fmaxf(m, row_shr<8>(m));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 15));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 31));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 47));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
+  return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
 }
 
 // Workgroups are dealt to the 8 XCDs round robin; remap the linear block id so
@@ -464,8 +478,12 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
       // the wave skips a tile that cannot beat any of its own queries' bests
       const bool wskip = !wany || box_lb(wmin, wmaxc, tmin, tmax) * kCullSlack > wbest;
       const int nsub = wskip ? 0 : (left < kCTile / 32 ? left : kCTile / 32);
+      // the next sub-tile's operand is read from LDS before this one's products
+      uint4 nraw = spack[buf][2 * (lane & 31) + half];
       for (int sub = 0; sub < nsub; ++sub) {
-        const uint4 raw = spack[buf][2 * (sub * 32 + (lane & 31)) + half];
+        const uint4 raw = nraw;
+        const int ns = sub + 1 < nsub ? sub + 1 : sub;
+        nraw = spack[buf][2 * (ns * 32 + (lane & 31)) + half];
         const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
         const f32x16 z = {};
 #pragma unroll
