@@ -10,6 +10,8 @@ Modules (each function cites the passage of the paper it follows):
 
 * ``warp``      -- multi-resolution trilinear deformation (Sec. 3.1, Eq. 1),
                    its grid adjoint and position Jacobian.
+* ``cayley``    -- six-channel cells [z; t] with the Cayley rotation (Sec. 3.3,
+                   Eq. 4-7): warp x' = R(z^) x + t^ and both adjoints.
 * ``chamfer``   -- robust Chamfer distance (Sec. 3.4, Eq. 11-13): brute-force
                    nearest neighbours, per-direction losses and gradients.
 * ``precond``   -- grid Sobolev preconditioner (I + lambda L)^-2 (Sec. 3.2,
@@ -21,4 +23,4 @@ Modules (each function cites the passage of the paper it follows):
 Readings of the paper where it is silent or ambiguous are listed in the
 module docstrings where they are used.
 """
-from . import warp, chamfer, precond, adam, sequence  # noqa: F401
+from . import warp, cayley, chamfer, precond, adam, sequence  # noqa: F401
