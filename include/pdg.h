@@ -10,8 +10,9 @@
  *   consecutive rows of n floats (x row, y row, z row).  Rows of a set must be
  *   4-byte aligned; 16-byte alignment of the set base is recommended.
  * - A grid stack ("transition grid", paper Sec. 3.1) packs its levels one
- *   after another; level l holds 3 channels of R_l^3 float32 values, each
- *   channel a dense R x R x R block with x fastest:
+ *   after another; level l holds C channels of R_l^3 float32 values (C = 3,
+ *   or 6 where a call says so), each channel a dense R x R x R block with x
+ *   fastest:
  *       value(c, z, y, x) at  level_offset(l) + ((c*R + z)*R + y)*R + x.
  *   Values are cell-centred on the cube [-1,1]^3 (centre of cell i is
  *   -1 + (2i+1)/R) and sampling clamps to the hull of the cell centres.
@@ -46,7 +47,7 @@ typedef enum {
   PDG_EUNSUPPORTED = 4   /* valid request that this build does not implement */
 } pdg_status;
 
-#define PDG_MAX_LEVELS 8
+#define PDG_MAX_LEVELS 16   /* the paper uses L = 10 (Sec. 3.1) */
 
 /* [host] Thread-local message describing the last failing call ("" if none). */
 const char *pdg_last_error(void);
@@ -56,8 +57,12 @@ int32_t pdg_version(void);
 /* Multi-resolution grid stack (paper Sec. 3.1, Eq. 1).
  *   levels      : L, 1..PDG_MAX_LEVELS.
  *   res[l]      : cells per axis of level l (>= 1; R = 1 is a constant level).
- *   channels    : must be 3 (translation per cell: the Cayley rotation of
- *                 Eq. 4-7 with z = 0, where R(0) = I).
+ *   channels    : 3 -- a translation t per cell (the Cayley rotation of
+ *                 Eq. 4-7 with z = 0, where R(0) = I); every call takes it.
+ *                 6 -- the full cell vector T = [z0 z1 z2 tx ty tz] of Eq. 4
+ *                 (channel order as written there); pdg_grid_size,
+ *                 pdg_deform and pdg_deform_backward(+_workspace) take it,
+ *                 the other calls return PDG_EUNSUPPORTED.
  *   level_scale : factor applied to the sum over levels; 1/L reproduces the
  *                 averaging of Eq. 1. */
 typedef struct {
@@ -67,12 +72,15 @@ typedef struct {
   float level_scale;
 } pdg_grid_desc;
 
-/* [host] Number of float32 values in one grid stack (3 * sum_l R_l^3), or -1. */
+/* [host] Number of float32 values in one grid stack (C * sum_l R_l^3), or -1. */
 int64_t pdg_grid_size(const pdg_grid_desc *d);
 
 /* ---------------------------------------------------------------- deform --
  * Warp (paper Eq. 1 with the translation form of Eq. 7):
  *     out_i = x_i + level_scale * sum_l trilerp(G_l, x_i).
+ * With six channels (Sec. 3.3, Eq. 4-7): [z^; t^] = level_scale * sum_l
+ * trilerp(G_l, x_i) and out_i = R(z^) x_i + t^ with the Cayley rotation
+ * R(z) = (I + Z)(I - Z)^{-1} (Eq. 5, Z of Eq. 6) acting about the origin.
  * grids: one packed stack; x, out: SoA [3][n]; n >= 0 (n = 0 is a no-op).
  * out may alias x. */
 pdg_status pdg_deform(const pdg_grid_desc *d, const float *grids, const float *x,
@@ -87,6 +95,10 @@ pdg_status pdg_deform_backward_workspace(const pdg_grid_desc *d, int64_t n, size
  *                        the result is bitwise reproducible -- no atomics);
  *   gx     (nullable) <- gout + J^T gout, with J the position Jacobian of the
  *                        displacement (zero along clamped axes).
+ * With six channels the rotation channels receive level_scale * A^T u with
+ * u = d<gout, out>/dz^, the translation channels level_scale * A^T gout, and
+ * gx = R^T gout + J^T [u; gout] (J the Jacobian of the interpolated cell
+ * vector); grids is then needed for ggrids too.
  * ws: device workspace of at least pdg_deform_backward_workspace() bytes
  * (needed only when ggrids != NULL). */
 pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const float *x,

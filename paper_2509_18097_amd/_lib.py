@@ -13,7 +13,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdg.so")
-MAX_LEVELS = 8
+MAX_LEVELS = 16                # PDG_MAX_LEVELS of include/pdg.h
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1}
@@ -128,8 +128,9 @@ def grid_desc(res, level_scale=None, channels=3) -> GridDesc:
     return d
 
 
-def grid_size(res) -> int:
-    return 3 * sum(int(r) ** 3 for r in res)
+def grid_size(res, channels=3) -> int:
+    """Floats of one packed stack: channels (3: translation, 6: [z; t]) per cell."""
+    return channels * sum(int(r) ** 3 for r in res)
 
 
 def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
@@ -154,12 +155,14 @@ def _ws(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def deform(grids: torch.Tensor, x: torch.Tensor, res, level_scale=None, out=None) -> torch.Tensor:
-    """x + level_scale * sum_l trilerp(G_l, x) (Eq. 1); x SoA (3, n) float32."""
-    d = grid_desc(res, level_scale)
+def deform(grids: torch.Tensor, x: torch.Tensor, res, level_scale=None, out=None,
+           channels=3) -> torch.Tensor:
+    """x + level_scale * sum_l trilerp(G_l, x) (Eq. 1) for channels = 3; for
+    channels = 6 (cells [z; t], Eq. 4-7) R(z^) x + t^.  x SoA (3, n) float32."""
+    d = grid_desc(res, level_scale, channels)
     _dev(grids, torch.float32, "grids")
     _dev(x, torch.float32, "x")
-    if grids.numel() != grid_size(res) or x.dim() != 2 or x.shape[0] != 3:
+    if grids.numel() != grid_size(res, channels) or x.dim() != 2 or x.shape[0] != 3:
         raise ValueError("grids must hold one packed stack and x must be (3, n)")
     out = torch.empty_like(x) if out is None else _dev(out, torch.float32, "out")
     check(lib().pdg_deform(ctypes.byref(d), _ptr(grids), _ptr(x), x.shape[1], _ptr(out), _stream()),
@@ -167,9 +170,10 @@ def deform(grids: torch.Tensor, x: torch.Tensor, res, level_scale=None, out=None
     return out
 
 
-def deform_backward(grids, x, gout, res, level_scale=None, need_grids=True, need_x=True):
-    """(dL/dG, dL/dx) for an upstream dL/dout (Eq. 1 transposed)."""
-    d = grid_desc(res, level_scale)
+def deform_backward(grids, x, gout, res, level_scale=None, need_grids=True, need_x=True,
+                    channels=3):
+    """(dL/dG, dL/dx) for an upstream dL/dout (the adjoint of ``deform``)."""
+    d = grid_desc(res, level_scale, channels)
     _dev(grids, torch.float32, "grids")
     _dev(x, torch.float32, "x")
     _dev(gout, torch.float32, "gout")

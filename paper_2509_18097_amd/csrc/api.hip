@@ -29,7 +29,7 @@ pdg_status hip_fail(hipError_t e, const char *what) {
   return PDG_EHIP;
 }
 
-pdg_status check_grid(const pdg_grid_desc *d) {
+pdg_status check_grid(const pdg_grid_desc *d, bool six_ok) {
   if (!d) {
     set_error("grid descriptor is NULL");
     return PDG_EINVAL;
@@ -38,10 +38,15 @@ pdg_status check_grid(const pdg_grid_desc *d) {
     set_error("levels = %d outside 1..%d", d->levels, PDG_MAX_LEVELS);
     return PDG_EINVAL;
   }
-  if (d->channels != 3) {
-    set_error("channels = %d: only the 3-channel translation grid is implemented",
+  if (d->channels == 6 && !six_ok) {
+    set_error("six-channel (Cayley) grids are implemented by pdg_deform and "
+              "pdg_deform_backward only");
+    return PDG_EUNSUPPORTED;
+  }
+  if (d->channels != 3 && d->channels != 6) {
+    set_error("channels = %d: must be 3 (translation) or 6 (Cayley rotation + translation)",
               d->channels);
-    return d->channels == 6 ? PDG_EUNSUPPORTED : PDG_EINVAL;
+    return PDG_EINVAL;
   }
   for (int l = 0; l < d->levels; ++l)
     if (d->res[l] < 1 || d->res[l] > 1024) {
@@ -59,13 +64,14 @@ GridDev make_grid(const pdg_grid_desc &d) {
   GridDev g;
   memset(&g, 0, sizeof g);
   g.levels = d.levels;
+  g.ch = d.channels;
   long long off = 0, noff = 0;
   for (int l = 0; l < d.levels; ++l) {
     const long long r3 = (long long)d.res[l] * d.res[l] * d.res[l];
     g.res[l] = d.res[l];
     g.off[l] = off;
     g.noff[l] = noff;
-    off += 3 * r3;
+    off += g.ch * r3;
     noff += r3;
   }
   g.size = off;
@@ -132,6 +138,7 @@ struct DeformBwdWs {
   float4 *ent;
   float2 *ent2;
   float *gscratch;
+  float *u;                  // six-channel cells: d<g, out>/dz^, [3][n]
   void *sort;
 };
 DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
@@ -143,6 +150,7 @@ DeformBwdWs deform_bwd_layout(Carve &c, const GridDev &g, long long n) {
   w.ent = c.take<float4>(ne);
   w.ent2 = c.take<float2>(ne);
   w.gscratch = c.take<float>((long long)(gather_scratch_bytes(g, 1, n) / sizeof(float)));
+  w.u = g.ch == 6 ? c.take<float>(3 * n) : nullptr;
   w.sort = c.take<char>((long long)radix_sort_bytes(ne));
   return w;
 }
@@ -651,13 +659,13 @@ const char *pdg_last_error(void) { return g_err.c_str(); }
 int32_t pdg_version(void) { return 100; }
 
 int64_t pdg_grid_size(const pdg_grid_desc *d) {
-  if (check_grid(d) != PDG_OK) return -1;
+  if (check_grid(d, true) != PDG_OK) return -1;
   return make_grid(*d).size;
 }
 
 pdg_status pdg_deform(const pdg_grid_desc *d, const float *grids, const float *x, int64_t n,
                       float *out, hipStream_t stream) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));
   if (n < 0 || n >= (1ll << 40)) {
     set_error("n = %lld invalid", (long long)n);
     return PDG_EINVAL;
@@ -667,11 +675,12 @@ pdg_status pdg_deform(const pdg_grid_desc *d, const float *grids, const float *x
   PDG_TRY(need(x, "x"));
   PDG_TRY(need(out, "out"));
   const GridDev g = make_grid(*d);
+  if (g.ch == 6) return launch_warp6(g, grids, x, out, n, stream);
   return launch_warp(g, grids, 0, x, 0, n, out, 0, n, n, 1, stream);
 }
 
 pdg_status pdg_deform_backward_workspace(const pdg_grid_desc *d, int64_t n, size_t *bytes) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));
   if (!bytes || n < 0) {
     set_error("bytes is NULL or n < 0");
     return PDG_EINVAL;
@@ -685,7 +694,7 @@ pdg_status pdg_deform_backward_workspace(const pdg_grid_desc *d, int64_t n, size
 pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const float *x,
                                int64_t n, const float *gout, float *ggrids, float *gx, void *ws,
                                size_t ws_bytes, hipStream_t stream) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));
   if (n < 0) {
     set_error("n < 0");
     return PDG_EINVAL;
@@ -697,7 +706,7 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
     return PDG_EINVAL;
   }
   if (ggrids) PDG_TRY(need(ggrids, "ggrids"));
-  if (gx) PDG_TRY(need(grids, "grids"));
+  if (gx || (ggrids && g.ch == 6)) PDG_TRY(need(grids, "grids"));   // the rotation needs G
   if (n > 0) {
     PDG_TRY(need(x, "x"));
     PDG_TRY(need(gout, "gout"));
@@ -714,12 +723,29 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
       sl.count = 1;
       sl.list[0] = scatter_list(w.keys, w.vals, w.pstart, n, x, 0, n, gout, 0, n, w.ent, w.ent2);
       PDG_TRY(scatter_entries(g, 1, sl.list[0], w.keys, w.vals, w.pstart, w.sort, stream));
-      PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
     }
+    if (g.ch == 6) {
+      // rotation channels from d<g, out>/dz^ (with gx, in the same pass),
+      // then the translation channels from g itself, on the same entries
+      PDG_TRY(launch_adjoint6(g, grids, x, gout, w.u, gx, n, stream));
+      if (n > 0) {
+        sl.list[0].lam = w.u;
+        PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
+      }
+      PDG_TRY(launch_gather(g, 1, sl, n, ggrids, w.gscratch, stream, 0));
+      if (n > 0) {
+        sl.list[0].lam = gout;
+        PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
+      }
+      return launch_gather(g, 1, sl, n, ggrids, w.gscratch, stream, 3);
+    }
+    if (n > 0) PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
     PDG_TRY(launch_gather(g, 1, sl, n, ggrids, w.gscratch, stream));
   }
-  if (gx && n > 0)
+  if (gx && n > 0) {
+    if (g.ch == 6) return launch_adjoint6(g, grids, x, gout, nullptr, gx, n, stream);
     PDG_TRY(launch_chain_adjoint(g, grids, x, n, gout, n, nullptr, 0, gx, n, n, stream));
+  }
   return PDG_OK;
 }
 

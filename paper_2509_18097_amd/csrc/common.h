@@ -39,16 +39,18 @@ inline pdg_status launched(const char *what) {
 // (one channel) inside the stack's node numbering.
 struct GridDev {
   int levels;
+  int ch;                            // channels per cell: 3 (t) or 6 ([z; t], Eq. 4)
   int res[PDG_MAX_LEVELS];
-  long long off[PDG_MAX_LEVELS];     // float offset of level l (3 channels)
+  long long off[PDG_MAX_LEVELS];     // float offset of level l (ch channels)
   long long noff[PDG_MAX_LEVELS];    // node offset of level l (per channel)
-  long long size;                    // floats per stack = 3 * nodes
+  long long size;                    // floats per stack = ch * nodes
   long long nodes;                   // nodes per stack (per channel)
   float scale;
 };
 
 GridDev make_grid(const pdg_grid_desc &d);
-pdg_status check_grid(const pdg_grid_desc *d);
+// six_ok: the caller implements six-channel (Cayley) cells.
+pdg_status check_grid(const pdg_grid_desc *d, bool six_ok = false);
 
 // Trilinear stencil of coordinate s on a level with R >= 2 cells per axis:
 // cell-centred values, border clamp to the hull of the centres.
@@ -104,6 +106,14 @@ pdg_status radix_sort(uint32_t *keys, uint32_t *vals, long long n, int bits, voi
 // order (nullable): batch b processes its points in the order
 // order[b * order_stride + 0 .. n-1] (a spatial order gathers grid cells
 // with better cache reuse; the result does not depend on it).
+// Six-channel cells (Eq. 4-7): out = R(z^) x + t^ with [z^; t^] = level_scale *
+// sum_l trilerp(G_l, x); x, out SoA [3][n] (out may alias x).
+pdg_status launch_warp6(const GridDev &g, const float *grids, const float *x, float *out,
+                        long long n, hipStream_t st);
+// Its adjoint for an upstream gradient g (SoA [3][n]): u (nullable) receives
+// d<g, out>/dz^ ([3][n]); gx (nullable) receives d<g, out>/dx.
+pdg_status launch_adjoint6(const GridDev &g, const float *grids, const float *x,
+                           const float *gout, float *u, float *gx, long long n, hipStream_t st);
 pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, const float *x,
                        long long xstride, long long ldx, float *out, long long ostride,
                        long long ldo, long long n, int batch, hipStream_t st,
@@ -167,8 +177,9 @@ pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L
 // samples: sample count per segment over all lists (sizes the work split);
 // scratch: gather_scratch_bytes(g, segs, samples) bytes (nullable when 0).
 size_t gather_scratch_bytes(const GridDev &g, int segs, long long samples);
+// ch0: first of the three channels written (0 or 3 for six-channel cells).
 pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, long long samples,
-                         float *grad, float *scratch, hipStream_t st);
+                         float *grad, float *scratch, hipStream_t st, int ch0 = 0);
 
 // chamfer.hip
 struct ChSeg {               // one (moving A, fixed B) Chamfer pair

@@ -1,5 +1,6 @@
 // Multi-resolution trilinear warp (paper Sec. 3.1, Eq. 1; translation form
-// of Eq. 7-8), its position adjoint and the deterministic grid scatter.
+// of Eq. 7-8, and the six-channel cells of Sec. 3.3, Eq. 4-7), its position
+// adjoint and the deterministic grid scatter.
 //
 // Data layout: samples SoA [3][ld]; a grid stack packs levels one after the
 // other, each level 3 dense channels of R^3 floats with x fastest.
@@ -97,6 +98,156 @@ __device__ __forceinline__ void adjoint_point(const GridDev &g, const float *__r
   r2 = l2 + g.scale * j2;
 }
 
+// ---- six-channel cells (Sec. 3.3, Eq. 4-7): T = [z; t] per cell ---------
+
+// One level's interpolated cell vector (6 channels, z then t) at s.
+__device__ __forceinline__ void level_value6(const float *__restrict__ L, int R, float sx,
+                                             float sy, float sz, float (&v)[6]) {
+  if (R == 1) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] = L[c];
+    return;
+  }
+  int ix, iy, iz;
+  float fx, fy, fz;
+  bool in;
+  stencil1(R, sx, ix, fx, in);
+  stencil1(R, sy, iy, fy, in);
+  stencil1(R, sz, iz, fz, in);
+  const long long R2 = (long long)R * R, R3 = R2 * R;
+  const long long b = (iz * R2) + (long long)iy * R + ix;
+  const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+  const float w[8] = {gx * gy * gz, fx * gy * gz, gx * fy * gz, fx * fy * gz,
+                      gx * gy * fz, fx * gy * fz, gx * fy * fz, fx * fy * fz};
+  const long long o[8] = {0, 1, R, R + 1, R2, R2 + 1, R2 + R, R2 + R + 1};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a += w[k] * L[c * R3 + b + o[k]];
+    v[c] = a;
+  }
+}
+
+// sum_l trilerp(G_l, p) of the six channels; [z^; t^] is level_scale times it (Eq. 1).
+__device__ __forceinline__ void cell_sum(const GridDev &g, const float *__restrict__ G, float px,
+                                         float py, float pz, float (&acc)[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) acc[c] = 0.f;
+  for (int l = 0; l < g.levels; ++l) {
+    float v[6];
+    level_value6(G + g.off[l], g.res[l], px, py, pz, v);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += v[c];
+  }
+}
+
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// out = R(z^) p + t^, R in the closed form of the Cayley map (Eq. 5):
+// R p = p + 2 (z x p + z x (z x p)) / (1 + |z|^2).
+__global__ __launch_bounds__(256) void warp6_kernel(GridDev g, const float *__restrict__ G,
+                                                    const float *__restrict__ x,
+                                                    float *__restrict__ out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float3 p = make_float3(x[i], x[n + i], x[2 * n + i]);
+  float T[6];
+  cell_sum(g, G, p.x, p.y, p.z, T);
+  const float3 z = make_float3(g.scale * T[0], g.scale * T[1], g.scale * T[2]);
+  const float3 c1 = cross3(z, p), c2 = cross3(z, c1);
+  const float k = 2.0f / (1.0f + dot3(z, z));
+  // t^ added as level_scale * sum, as the translation warp does
+  out[i] = (p.x + k * (c1.x + c2.x)) + g.scale * T[3];
+  out[n + i] = (p.y + k * (c1.y + c2.y)) + g.scale * T[4];
+  out[2 * n + i] = (p.z + k * (c1.z + c2.z)) + g.scale * T[5];
+}
+
+// sum_c lam_c d/dp trilerp(L_c, p) for one level (zero along clamped axes).
+__device__ __forceinline__ void level_jt6(const float *__restrict__ L, int R, float px, float py,
+                                          float pz, const float (&lam)[6], float &j0, float &j1,
+                                          float &j2) {
+  j0 = j1 = j2 = 0.f;
+  if (R == 1) return;
+  int ix, iy, iz;
+  float fx, fy, fz;
+  bool inx, iny, inz;
+  stencil1(R, px, ix, fx, inx);
+  stencil1(R, py, iy, fy, iny);
+  stencil1(R, pz, iz, fz, inz);
+  const long long R2 = (long long)R * R, R3 = R2 * R;
+  const long long b = (iz * R2) + (long long)iy * R + ix;
+  const long long o[8] = {0, 1, R, R + 1, R2, R2 + 1, R2 + R, R2 + R + 1};
+  float s[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    float a = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a += lam[c] * L[c * R3 + b + o[k]];
+    s[k] = a;
+  }
+  const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+  const float h = 0.5f * (float)R;
+  const float dx = (s[1] - s[0]) * gy * gz + (s[3] - s[2]) * fy * gz + (s[5] - s[4]) * gy * fz +
+                   (s[7] - s[6]) * fy * fz;
+  const float dy = (s[2] - s[0]) * gx * gz + (s[3] - s[1]) * fx * gz + (s[6] - s[4]) * gx * fz +
+                   (s[7] - s[5]) * fx * fz;
+  const float dz = (s[4] - s[0]) * gx * gy + (s[5] - s[1]) * fx * gy + (s[6] - s[2]) * gx * fy +
+                   (s[7] - s[3]) * fx * fy;
+  if (inx) j0 = h * dx;
+  if (iny) j1 = h * dy;
+  if (inz) j2 = h * dz;
+}
+
+// Adjoint of warp6 for an upstream gradient q = dL/dout:
+//   u  = dL/dz^ = (2/d) (p x q + (z x p) x q + p x (q x z)) - (4/d^2) (q . N) z,
+//        N = z x p + z x (z x p), d = 1 + |z|^2   (the derivative of R p);
+//   gx = R^T q + level_scale * sum_l sum_c [u; q]_c grad trilerp(G_l,c, p),
+//        R^T q = q + (2/d) (z x (z x q) - z x q).
+__global__ __launch_bounds__(256) void adjoint6_kernel(GridDev g, const float *__restrict__ G,
+                                                       const float *__restrict__ x,
+                                                       const float *__restrict__ gout,
+                                                       float *__restrict__ uo,
+                                                       float *__restrict__ gx, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float3 p = make_float3(x[i], x[n + i], x[2 * n + i]);
+  const float3 q = make_float3(gout[i], gout[n + i], gout[2 * n + i]);
+  float T[6];
+  cell_sum(g, G, p.x, p.y, p.z, T);
+  const float3 z = make_float3(g.scale * T[0], g.scale * T[1], g.scale * T[2]);
+  const float d = 1.0f + dot3(z, z);
+  const float3 zp = cross3(z, p), zzp = cross3(z, zp);
+  const float3 N = make_float3(zp.x + zzp.x, zp.y + zzp.y, zp.z + zzp.z);
+  const float3 a1 = cross3(p, q), a2 = cross3(zp, q), a3 = cross3(p, cross3(q, z));
+  const float ca = 2.0f / d, cz = 4.0f * dot3(q, N) / (d * d);
+  const float u[3] = {ca * (a1.x + a2.x + a3.x) - cz * z.x, ca * (a1.y + a2.y + a3.y) - cz * z.y,
+                      ca * (a1.z + a2.z + a3.z) - cz * z.z};
+  if (uo) {
+    uo[i] = u[0];
+    uo[n + i] = u[1];
+    uo[2 * n + i] = u[2];
+  }
+  if (gx) {
+    const float3 zq = cross3(z, q), zzq = cross3(z, zq);
+    const float lam[6] = {u[0], u[1], u[2], q.x, q.y, q.z};
+    float j0 = 0.f, j1 = 0.f, j2 = 0.f;
+    for (int l = 0; l < g.levels; ++l) {
+      float a, b, c;
+      level_jt6(G + g.off[l], g.res[l], p.x, p.y, p.z, lam, a, b, c);
+      j0 += a;
+      j1 += b;
+      j2 += c;
+    }
+    gx[i] = (q.x + ca * (zzq.x - zq.x)) + g.scale * j0;
+    gx[n + i] = (q.y + ca * (zzq.y - zq.y)) + g.scale * j1;
+    gx[2 * n + i] = (q.z + ca * (zzq.z - zq.z)) + g.scale * j2;
+  }
+}
+
 // Thread i of batch b warps point order[b * order_stride + i] (or i): a
 // spatial order keeps the grid cells of neighbouring threads close.
 __global__ __launch_bounds__(256) void warp_kernel(GridDev g, const float *__restrict__ grids,
@@ -169,12 +320,14 @@ __device__ __forceinline__ void level_jt(const float *__restrict__ L, int R, flo
   if (inz) j2 = h * dz;
 }
 
-// Template chains, one group of kChainLanes lanes per vertex: lane l of the
-// group gathers level l, lane 0 adds the levels in order (the same sums as
-// warp_point / adjoint_point) and hands the new point to the group.
-constexpr int kChainLanes = PDG_MAX_LEVELS;
+// Template chains, one group of kChainLanes lanes per vertex (8, or 16 for
+// more than eight levels; a divisor of the wave): lane l of the group gathers
+// level l, lane 0 adds the levels in order (the same sums as warp_point /
+// adjoint_point) and hands the new point to the group.
+static_assert(PDG_MAX_LEVELS <= 16, "chain groups hold at most 16 levels");
 
 // X_{t+1} = warp(G_t, X_t) for t = 0..T-1, X_0 copied to frame 0 (Eq. 8).
+template <int kChainLanes>
 __global__ __launch_bounds__(256) void chain_warp_kernel(GridDev g, const float *__restrict__ params,
                                                          long long P, const float *__restrict__ x0,
                                                          float *__restrict__ xhat, long long V, int T,
@@ -220,6 +373,7 @@ __global__ __launch_bounds__(256) void chain_warp_kernel(GridDev g, const float 
 // Reverse sweep of the chain: lam_{T-1} = gd_{T-1} and, for k = T-1 .. 1,
 // lam_{k-1} = gd_{k-1} + lam_k + (dD_k/dx)^T lam_k at X_k (grids k); lam_t is
 // the total adjoint of X_{t+1} (frames 1..T).
+template <int kChainLanes>
 __global__ __launch_bounds__(256) void chain_reverse_kernel(GridDev g,
                                                             const float *__restrict__ params,
                                                             long long P,
@@ -447,6 +601,7 @@ struct GatherPlan {
   long long sof[PDG_MAX_LEVELS];           // scratch float offset of each level
   long long RS2;                           // rows per segment
   long long scratch;                       // scratch floats in all
+  int ch0;                                 // first channel written (of g.ch)
 };
 
 namespace {
@@ -653,7 +808,7 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
   }
   __syncthreads();
   const long long R2 = (long long)R * R, R3 = R2 * R;
-  float *Gd = (K == 1 ? grad + seg * g.size + g.off[l]
+  float *Gd = (K == 1 ? grad + seg * g.size + g.off[l] + gp.ch0 * R3
                       : scratch + gp.sof[l] + ((long long)piece * gp.segs + seg) * 3 * R3) +
               (long long)z * R2 + (long long)y0 * R;
   for (int i = t; i < band_n; i += kGatherThreads) {
@@ -671,14 +826,15 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(GridDev g, GatherPla
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (int l = 0; l < gp.levels; ++l) {
     if (gp.K[l] == 1) continue;
-    const long long per = 3 * (long long)gp.R[l] * gp.R[l] * gp.R[l];   // floats per segment
+    const long long r3 = (long long)gp.R[l] * gp.R[l] * gp.R[l];
+    const long long per = 3 * r3;                   // floats per segment (three channels)
     const long long n = per * gp.segs;
     if (i < n) {
       const long long seg = i / per, c = i - seg * per;
       const float *src = scratch + gp.sof[l] + i;
       float v = src[0];
       for (int k = 1; k < gp.K[l]; ++k) v += src[(long long)k * n];
-      grad[seg * g.size + g.off[l] + c] = v;
+      grad[seg * g.size + g.off[l] + gp.ch0 * r3 + c] = v;
       return;
     }
     i -= n;
@@ -698,6 +854,20 @@ pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, 
   return launched("warp");
 }
 
+pdg_status launch_warp6(const GridDev &g, const float *grids, const float *x, float *out,
+                        long long n, hipStream_t st) {
+  if (n <= 0) return PDG_OK;
+  warp6_kernel<<<div_up(n, 256), 256, 0, st>>>(g, grids, x, out, n);
+  return launched("warp6");
+}
+
+pdg_status launch_adjoint6(const GridDev &g, const float *grids, const float *x,
+                           const float *gout, float *u, float *gx, long long n, hipStream_t st) {
+  if (n <= 0 || (!u && !gx)) return PDG_OK;
+  adjoint6_kernel<<<div_up(n, 256), 256, 0, st>>>(g, grids, x, gout, u, gx, n);
+  return launched("adjoint6");
+}
+
 pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const float *x, long long ldx,
                                 const float *lam, long long ldl, const float *gdir, long long ldd,
                                 float *lam_out, long long ldo, long long n, hipStream_t st) {
@@ -710,8 +880,10 @@ pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const floa
 pdg_status launch_chain_warp(const GridDev &g, const float *params, long long P, const float *x0,
                              float *xhat, long long V, int T, const int *order, hipStream_t st) {
   if (V <= 0) return PDG_OK;
-  chain_warp_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T,
-                                                                   order);
+  if (g.levels <= 8)
+    chain_warp_kernel<8><<<div_up(V * 8, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T, order);
+  else
+    chain_warp_kernel<16><<<div_up(V * 16, 256), 256, 0, st>>>(g, params, P, x0, xhat, V, T, order);
   return launched("chain_warp");
 }
 
@@ -719,8 +891,12 @@ pdg_status launch_chain_reverse(const GridDev &g, const float *params, long long
                                 const float *xhat, const float *gd, float *lam, long long V, int T,
                                 const int *order, hipStream_t st) {
   if (V <= 0 || T <= 0) return PDG_OK;
-  chain_reverse_kernel<<<div_up(V * kChainLanes, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam,
-                                                                      V, T, order);
+  if (g.levels <= 8)
+    chain_reverse_kernel<8><<<div_up(V * 8, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam, V, T,
+                                                                order);
+  else
+    chain_reverse_kernel<16><<<div_up(V * 16, 256), 256, 0, st>>>(g, params, P, xhat, gd, lam, V,
+                                                                  T, order);
   return launched("chain_reverse");
 }
 
@@ -824,9 +1000,14 @@ size_t gather_scratch_bytes(const GridDev &g, int segs, long long samples) {
 }
 
 pdg_status launch_gather(const GridDev &g, int segs, const ScatterLists &sl, long long samples,
-                         float *grad, float *scratch, hipStream_t st) {
+                         float *grad, float *scratch, hipStream_t st, int ch0) {
   if (segs <= 0) return PDG_OK;
-  const GatherPlan gp = gather_plan(g, segs, samples);
+  if (ch0 < 0 || ch0 + 3 > g.ch) {
+    set_error("gather: channels %d..%d outside the %d of the grid", ch0, ch0 + 2, g.ch);
+    return PDG_EINVAL;
+  }
+  GatherPlan gp = gather_plan(g, segs, samples);
+  gp.ch0 = ch0;
   const long long blocks = gp.bfirst[g.levels];
   if (blocks >= (1ll << 31)) {
     set_error("grid gather needs %lld blocks (limit 2^31)", blocks);

@@ -45,12 +45,20 @@ def test_version_and_grid_size():
 def test_argument_errors_on_host():
     lib = L.lib()
     d = L.grid_desc((4, 8))
-    d.levels = 9
+    d.levels = L.MAX_LEVELS + 1
     st = lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None)
     assert st == L.EINVAL and "levels" in L.last_error()
     d = L.grid_desc((4, 8))
-    d.channels = 6
-    assert lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None) == L.EUNSUPPORTED
+    d.channels = 5
+    assert lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None) == L.EINVAL
+    # six-channel (Cayley) cells: taken by the deform calls, refused elsewhere
+    d = L.grid_desc((4, 8), channels=6)
+    assert lib.pdg_grid_size(ctypes.byref(d)) == 6 * (4 ** 3 + 8 ** 3)
+    assert lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None) == L.EINVAL
+    assert "NULL" in L.last_error()
+    nb6 = ctypes.c_size_t()
+    assert lib.pdg_deform_backward_workspace(ctypes.byref(d), 100, ctypes.byref(nb6)) == L.OK
+    assert lib.pdg_precondition_workspace(ctypes.byref(d), 1, 0, ctypes.byref(nb6)) == L.EUNSUPPORTED
     d = L.grid_desc((4, 8))
     assert lib.pdg_deform(ctypes.byref(d), None, None, 10, None, None) == L.EINVAL
     assert "NULL" in L.last_error()
