@@ -38,6 +38,7 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VALU_PEAK_TFLOPS = 157.3     # vector FP32, an FMA counted as two flops
 PAIR_OPS = 8          # 3 sub + 3 mul + 2 add per pair under the difference-form contract
 PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
@@ -76,6 +77,8 @@ def parse():
                     help="other chamfer:precond forms to time on the same GPU ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
+    ap.add_argument("--no-cayley", action="store_true",
+                    help="skip the six-channel (Cayley) deform timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serve", type=int, default=24, metavar="R",
@@ -241,6 +244,56 @@ def roofline(prob, stages, chamfer, precond):
     return nn, pre
 
 
+CAYLEY_RES = tuple(2 * l - 1 for l in range(1, 11))   # the paper's grid: L = 10, R = 2l - 1
+CAYLEY_N = 1_000_000
+
+
+def time_cayley6(reps=10):
+    """Six-channel cells (Sec. 3.3, Eq. 4-7) on the paper's grid (L = 10,
+    R = 1, 3, ..., 19): pdg_deform and pdg_deform_backward (grid and position
+    adjoints) of 1,000,000 points uniform in [-1, 1]^3, grid values N(0, 0.2^2).
+    The grid (0.48 MB) stays in L2, so the forward is bound by the vector ALU:
+    per point and level 48 interpolation FMAs (6 channels x 8 corners) and 16
+    flops of weights, plus ~40 flops of the rotation."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2509_18097_amd import _lib as L
+    res, n = CAYLEY_RES, CAYLEY_N
+    rng = np.random.default_rng(0)
+    g = torch.from_numpy(synth.grid_stack(0, res, std=0.2, channels=6)).cuda()
+    x = torch.from_numpy(rng.uniform(-1.0, 1.0, (3, n)).astype(np.float32)).cuda()
+    q = torch.from_numpy(rng.normal(size=(3, n)).astype(np.float32)).cuda()
+    out = torch.empty_like(x)
+    for _ in range(2):
+        L.deform(g, x, res, out=out, channels=6)
+        L.deform_backward(g, x, q, res, channels=6)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(st)
+    for _ in range(reps):
+        L.deform(g, x, res, out=out, channels=6)
+    ev[1].record(st)
+    for _ in range(reps):
+        L.deform_backward(g, x, q, res, channels=6)
+    ev[2].record(st)
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / reps
+    bwd = ev[1].elapsed_time(ev[2]) / reps
+    flops = n * (len(res) * (2 * 48 + 16) + 40)
+    a = flops / (fwd * 1e-3) / 1e12
+    return {"workload": "six-channel Cayley cells, paper grid L = 10 (R = 1..19), "
+                        "1,000,000 points in [-1,1]^3",
+            "fwd_ms": round(fwd, 4), "bwd_ms": round(bwd, 4),
+            "points_per_s_fwd": round(n / (fwd * 1e-3), 1),
+            "points_per_s_fwd_bwd": round(n / ((fwd + bwd) * 1e-3), 1),
+            "fwd_roofline": {"bound": "alu", "achieved": round(a, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(a / FP32_VALU_PEAK_TFLOPS, 4),
+                             "traffic": None, "kernel": "warp6_kernel",
+                             "flops_per_launch": flops}}
+
+
 def cpu_baseline(seq, workers):
     """The oracle on one transition (t = 1) of the same workload, all stages,
     full sizes; scaled to iterations/s of the 31-transition step."""
@@ -378,6 +431,8 @@ def main():
         torch.cuda.empty_cache()
     if variants:
         result["variants"] = variants
+    if not args.no_cayley:
+        result["cayley6"] = time_cayley6()
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:

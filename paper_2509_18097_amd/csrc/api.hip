@@ -161,7 +161,8 @@ pdg_status scatter_entries(const GridDev &g, int segs, const ScatterList &L, uin
                            uint32_t *vals, int *pstart, void *sort, hipStream_t st) {
   const long long nent = (long long)segs * g.levels * L.S;
   PDG_TRY(launch_scatter_keys(g, L.x, L.xstride, L.ldx, L.S, segs, keys, vals, st));
-  PDG_TRY(radix_sort(keys, vals, nent, 32, sort, st));
+  // keys are below segs * nodes: sort only the bits they can set
+  PDG_TRY(radix_sort(keys, vals, nent, bits_for((unsigned long long)segs * g.nodes - 1), sort, st));
   return launch_row_table(g, keys, nent, segs, pstart, st);
 }
 
@@ -735,7 +736,7 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
       PDG_TRY(launch_gather(g, 1, sl, n, ggrids, w.gscratch, stream, 0));
       if (n > 0) {
         sl.list[0].lam = gout;
-        PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream));
+        PDG_TRY(launch_scatter_stage(g, 1, sl.list[0], stream, true));
       }
       return launch_gather(g, 1, sl, n, ggrids, w.gscratch, stream, 3);
     }

@@ -170,7 +170,9 @@ struct ScatterLists {
 };
 // Stages every sorted entry of a list: the stencil fractions of its sample on
 // its level and the three values scattered (ent, ent2).
-pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L, hipStream_t st);
+// lam_only: re-stage only the adjoint values of entries staged before.
+pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L, hipStream_t st,
+                                bool lam_only = false);
 // grad = level_scale * sum_s w_k(s) lam(s) over the samples s of every list
 // that have node k as a corner of their base cell, for every node of `segs`
 // stacks (grad is overwritten; deterministic summation order).

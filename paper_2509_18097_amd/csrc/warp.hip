@@ -521,7 +521,10 @@ __global__ void upload_kernel(Blob blob, unsigned char *__restrict__ dst, int n)
 }
 
 // ent[i] = (fx, fy, fz, lam0), ent2[i] = (lam1, lam2) of sorted entry i.
-__global__ __launch_bounds__(256) void scatter_stage_kernel(GridDev g, ScatterList L, int nent) {
+// lam_only: the fractions staged by an earlier call on the same entries are
+// kept (read back from ent) and only the adjoint values are staged anew.
+__global__ __launch_bounds__(256) void scatter_stage_kernel(GridDev g, ScatterList L, int nent,
+                                                            int lam_only) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nent) return;
   const uint32_t e = L.vals[i], S = (uint32_t)L.S;
@@ -532,7 +535,12 @@ __global__ __launch_bounds__(256) void scatter_stage_kernel(GridDev g, ScatterLi
   const float *X = L.x + (long long)seg * L.xstride;
   const float *Lm = L.lam + (long long)seg * L.lstride;
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  if (R > 1) {
+  if (lam_only) {
+    const float4 old = L.ent[i];
+    fx = old.x;
+    fy = old.y;
+    fz = old.z;
+  } else if (R > 1) {
     int ii;
     bool in;
     stencil1(R, X[s], ii, fx, in);
@@ -832,8 +840,18 @@ __global__ __launch_bounds__(256) void gather_reduce_kernel(GridDev g, GatherPla
     if (i < n) {
       const long long seg = i / per, c = i - seg * per;
       const float *src = scratch + gp.sof[l] + i;
+      // pieces added in order; their loads issued sixteen at a time
+      const int K = gp.K[l];
       float v = src[0];
-      for (int k = 1; k < gp.K[l]; ++k) v += src[(long long)k * n];
+      int k = 1;
+      for (; k + 16 <= K; k += 16) {
+        float t[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) t[j] = src[(long long)(k + j) * n];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v += t[j];
+      }
+      for (; k < K; ++k) v += src[(long long)k * n];
       grad[seg * g.size + g.off[l] + gp.ch0 * r3 + c] = v;
       return;
     }
@@ -954,10 +972,11 @@ pdg_status launch_row_table(const GridDev &g, const uint32_t *keys, long long ne
   return launched("row_table");
 }
 
-pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L, hipStream_t st) {
+pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L, hipStream_t st,
+                                bool lam_only) {
   const long long nent = (long long)segs * g.levels * L.S;
   if (nent <= 0) return PDG_OK;
-  scatter_stage_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, L, (int)nent);
+  scatter_stage_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, L, (int)nent, lam_only ? 1 : 0);
   return launched("scatter_stage");
 }
 
@@ -974,11 +993,16 @@ GatherPlan gather_plan(const GridDev &g, int segs, long long samples) {
     if (B < 1) B = 1;
     if (B > R) B = R;
     // entries of a band if the samples spread evenly: two cell planes of
-    // B + 1 rows; split into pieces of about three chunks (at most 16)
+    // B + 1 rows; split into pieces of about three chunks, at most 16 or as
+    // many as 2^22 floats of partial bands allow (coarse levels of many
+    // samples), at most 512
     const double per_band = 2.0 * (double)samples * (B + 1) / ((double)R * R);
-    int K = (int)(per_band / (3.0 * kGatherThreads));
-    if (K < 1) K = 1;
-    if (K > 16) K = 16;
+    const double per_piece = 3.0 * (double)R * R * R * segs;
+    double kmax = (double)(1 << 22) / per_piece;
+    kmax = kmax < 16.0 ? 16.0 : (kmax > 512.0 ? 512.0 : kmax);
+    double kf = per_band / (3.0 * kGatherThreads);
+    kf = kf < 1.0 ? 1.0 : (kf > kmax ? kmax : kf);
+    const int K = (int)kf;
     gp.R[l] = R;
     gp.B[l] = B;
     gp.nb[l] = (R + B - 1) / B;
