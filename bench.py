@@ -294,6 +294,30 @@ def time_cayley6(reps=10):
                              "flops_per_launch": flops}}
 
 
+def time_keyframe(seq, reps=20):
+    """Keyframe selection (Sec. 3.5, Eq. 19-20) over the sequence's frames:
+    one bit per occupied 128^3 voxel and frame, population counts, the
+    weighted argmax.  Algorithmic HBM bytes: the points once (12 B each) and
+    the bitsets written and read once (2 x 256 KiB per frame)."""
+    import torch
+    from paper_2509_18097_amd import _lib as L
+    pts = torch.from_numpy(seq.points).cuda()
+    key, _ = L.keyframe(pts)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        L.keyframe(pts)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    f, n = pts.shape[0], pts.shape[2]
+    nbytes = 12 * f * n + 2 * f * 128 ** 3 // 8
+    return {"workload": f"{f} frames x {n} points", "ms": round(ms, 4),
+            "key": int(key.item()), "gb_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(seq, workers):
     """The oracle on one transition (t = 1) of the same workload, all stages,
     full sizes; scaled to iterations/s of the 31-transition step."""
@@ -433,6 +457,7 @@ def main():
         result["variants"] = variants
     if not args.no_cayley:
         result["cayley6"] = time_cayley6()
+        result["keyframe"] = time_keyframe(seq)
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:

@@ -105,6 +105,21 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
                                int64_t n, const float *gout, float *ggrids, float *gx,
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* -------------------------------------------------------------- keyframe --
+ * Keyframe selection (paper Sec. 3.5, Eq. 19-20):
+ *   t_key = argmax_t exp(-gamma (t - T/2)^2) |G(P_t)|,  T = frames - 1,
+ * with |G(P_t)| the number of occupied voxels of a 128^3 grid over [-1,1]^3
+ * (voxel of a coordinate: floor((s + 1) * 64) in float32, clamped to 0..127;
+ * NaN coordinates count in voxel 0).  The first frame wins ties.
+ * points: [frames][3][n] SoA; 1 <= frames <= 65535; n >= 0.
+ * counts (nullable): int64[frames] <- |G(P_t)| (exact);  key: int32[1] <- t_key.
+ * gamma >= 0 and finite (the paper: 0.001).
+ * ws: device workspace of at least pdg_keyframe_workspace() bytes. */
+pdg_status pdg_keyframe_workspace(int32_t frames, size_t *bytes);
+pdg_status pdg_keyframe(const float *points, int32_t frames, int64_t n, double gamma,
+                        int64_t *counts, int32_t *key, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
 /* --------------------------------------------------------------- chamfer --
  * Robust bidirectional Chamfer distance (paper Sec. 3.4, Eq. 11-13) between a
  * moving set A (n points) and a fixed set B (m points):

@@ -70,6 +70,8 @@ _SIGS = {
     "pdg_deform": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P]),
     "pdg_deform_backward_workspace": (_I32, [ctypes.POINTER(GridDesc), _I64, ctypes.POINTER(_SZ)]),
     "pdg_deform_backward": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "pdg_keyframe_workspace": (_I32, [_I32, ctypes.POINTER(_SZ)]),
+    "pdg_keyframe": (_I32, [_P, _I32, _I64, _D, _P, _P, _P, _SZ, _P]),
     "pdg_chamfer_workspace": (_I32, [_I64, _I64, _I32, ctypes.POINTER(_SZ)]),
     "pdg_chamfer": (_I32, [_P, _I64, _P, _I64, _D, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "pdg_chamfer_backward": (_I32, [_P, _I64, _P, _I64, _D, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -188,6 +190,23 @@ def deform_backward(grids, x, gout, res, level_scale=None, need_grids=True, need
                                     _ptr(gx), _ptr(ws), nb.value if ws is not None else 0,
                                     _stream()), "pdg_deform_backward")
     return gg, gx
+
+
+def keyframe(points: torch.Tensor, gamma: float = 0.001):
+    """Keyframe selection (Sec. 3.5, Eq. 19-20) of points (F, 3, N) float32:
+    returns (t_key int32 (1,), occupied-voxel counts int64 (F,)) on the device."""
+    _dev(points, torch.float32, "points")
+    if points.dim() != 3 or points.shape[1] != 3:
+        raise ValueError("points must be (F, 3, N)")
+    f, n = points.shape[0], points.shape[2]
+    nb = ctypes.c_size_t()
+    check(lib().pdg_keyframe_workspace(f, ctypes.byref(nb)), "pdg_keyframe_workspace")
+    ws = _ws(nb.value, points.device)
+    key = torch.empty(1, dtype=torch.int32, device=points.device)
+    counts = torch.empty(f, dtype=torch.int64, device=points.device)
+    check(lib().pdg_keyframe(_ptr(points), f, n, float(gamma), _ptr(counts), _ptr(key), _ptr(ws),
+                             nb.value, _stream()), "pdg_keyframe")
+    return key, counts
 
 
 def chamfer(a, b, alpha=5.56, mode="fp32", dir_weight=None, need_grad=False):

@@ -750,6 +750,31 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
   return PDG_OK;
 }
 
+pdg_status pdg_keyframe_workspace(int32_t frames, size_t *bytes) {
+  if (!bytes || frames < 1 || frames > 65535) {
+    set_error("bytes NULL or frames outside 1..65535");
+    return PDG_EINVAL;
+  }
+  *bytes = keyframe_bytes(frames);
+  return PDG_OK;
+}
+
+pdg_status pdg_keyframe(const float *points, int32_t frames, int64_t n, double gamma,
+                        int64_t *counts, int32_t *key, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_keyframe_workspace(frames, &need_bytes));
+  if (n < 0 || n >= (1ll << 40) || !(gamma >= 0.0) || !isfinite(gamma)) {
+    set_error("n < 0 or gamma not finite and >= 0");
+    return PDG_EINVAL;
+  }
+  if (n > 0) PDG_TRY(need(points, "points"));
+  PDG_TRY(need(key, "key"));
+  if (counts) PDG_TRY(need(counts, "counts"));
+  PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
+  return launch_keyframe(points, frames, n, gamma, (long long *)counts, key, ws, stream);
+}
+
 pdg_status pdg_chamfer_workspace(int64_t n, int64_t m, int32_t mode, size_t *bytes) {
   if (!bytes || n < 1 || m < 1 || n >= (1ll << 31) || m >= (1ll << 31)) {
     set_error("bytes NULL or n, m outside [1, 2^31)");

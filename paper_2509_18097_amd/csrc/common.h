@@ -332,6 +332,11 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
                    const void *ws, hipStream_t st, const AdamFuse *adam = nullptr,
                    unsigned *fused = nullptr);
 
+// keyframe.hip: Eq. 19-20 (occupied 128^3 voxels per frame, weighted argmax)
+size_t keyframe_bytes(int frames);
+pdg_status launch_keyframe(const float *points, int frames, long long n, double gamma,
+                           long long *counts, int *key, void *ws, hipStream_t st);
+
 // optim.hip
 pdg_status launch_adam(const AdamLevels &lv, long long stack, int batch, float b1, float b2,
                        float eps, const int *step_dev, int step_host, float *theta, float *m,
