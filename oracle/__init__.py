@@ -19,10 +19,12 @@ Modules (each function cites the passage of the paper it follows):
 * ``adam``      -- Adam with bias correction (Sec. 3.6).
 * ``keyframe``  -- keyframe selection by weighted 128^3 occupancy (Sec. 3.5,
                    Eq. 19-20).
+* ``mesh``      -- the mesh-vertex preconditioner (I + lambda L)^-2 with the
+                   mesh Laplacian (Sec. 3.2, 3.6).
 * ``sequence``  -- isometry loss (Eq. 18), confidence weights (Eq. 15-17),
                    loss assembly (Eq. 9, 14) and one full optimisation step.
 
 Readings of the paper where it is silent or ambiguous are listed in the
 module docstrings where they are used.
 """
-from . import warp, cayley, chamfer, precond, adam, sequence, keyframe  # noqa: F401
+from . import warp, cayley, chamfer, precond, adam, sequence, keyframe, mesh  # noqa: F401
