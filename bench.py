@@ -294,6 +294,31 @@ def time_cayley6(reps=10):
                              "flops_per_launch": flops}}
 
 
+def time_mesh_precond(seq, reps=10):
+    """The mesh-vertex preconditioner (I + 16 L)^-2 (Sec. 3.2, 3.6) on the
+    template (40,962 vertices, 122,880 edges, degrees <= 6): two Chebyshev
+    solves of 117 steps each at tol 1e-7, one launch per step."""
+    import numpy as np
+    import torch
+    from paper_2509_18097_amd import _lib as L
+    edges = torch.from_numpy(np.ascontiguousarray(seq.edges, dtype=np.int32)).cuda()
+    v = seq.template.shape[1]
+    dmax = int(np.bincount(np.asarray(seq.edges).reshape(-1), minlength=v).max())
+    g = torch.from_numpy(np.random.default_rng(0).normal(size=(3, v)).astype(np.float32)).cuda()
+    out = torch.empty_like(g)
+    L.mesh_precondition(g, edges, dmax, 16.0, out=out)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        L.mesh_precondition(g, edges, dmax, 16.0, out=out)
+    b.record(st)
+    torch.cuda.synchronize()
+    return {"workload": f"template mesh, {v} vertices, {edges.shape[1]} edges, lambda 16",
+            "ms": round(a.elapsed_time(b) / reps, 4), "max_degree": dmax}
+
+
 def time_keyframe(seq, reps=20):
     """Keyframe selection (Sec. 3.5, Eq. 19-20) over the sequence's frames:
     one bit per occupied 128^3 voxel and frame, population counts, the
@@ -458,6 +483,7 @@ def main():
     if not args.no_cayley:
         result["cayley6"] = time_cayley6()
         result["keyframe"] = time_keyframe(seq)
+        result["mesh_precond"] = time_mesh_precond(seq)
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:

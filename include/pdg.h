@@ -105,6 +105,24 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
                                int64_t n, const float *gout, float *ggrids, float *gx,
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------ mesh --
+ * Mesh-vertex preconditioner (paper Sec. 3.2 applied to the vertices of X_0;
+ * Sec. 3.6: lambda = 16):
+ *   out = (I + lambda L)^{-2} g  per channel,  L = D - A of the edge graph.
+ * V >= 0 vertices; edges: int32 [2][E] (each undirected edge listed once; an
+ * edge listed twice counts twice; edges with an endpoint outside [0, V) are
+ * ignored); g, out: SoA [3][V] float32 (out may alias g); lambda >= 0.
+ * max_degree: [host] an upper bound on every vertex degree; it fixes the
+ * spectrum bound [1, 1 + 2 lambda max_degree] of I + lambda L on which each of
+ * the two solves runs a Chebyshev iteration in float64 (a degree above the
+ * bound voids the convergence guarantee).  iters: iterations per solve, or 0
+ * for the smallest count whose a-priori error bound 2 rho^k is below tol.
+ * ws: device workspace of at least pdg_mesh_precondition_workspace() bytes. */
+pdg_status pdg_mesh_precondition_workspace(int64_t V, int64_t E, size_t *bytes);
+pdg_status pdg_mesh_precondition(int64_t V, const int32_t *edges, int64_t E, float lambda,
+                                 int32_t max_degree, int32_t iters, double tol, const float *g,
+                                 float *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* -------------------------------------------------------------- keyframe --
  * Keyframe selection (paper Sec. 3.5, Eq. 19-20):
  *   t_key = argmax_t exp(-gamma (t - T/2)^2) |G(P_t)|,  T = frames - 1,

@@ -70,6 +70,8 @@ _SIGS = {
     "pdg_deform": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P]),
     "pdg_deform_backward_workspace": (_I32, [ctypes.POINTER(GridDesc), _I64, ctypes.POINTER(_SZ)]),
     "pdg_deform_backward": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "pdg_mesh_precondition_workspace": (_I32, [_I64, _I64, ctypes.POINTER(_SZ)]),
+    "pdg_mesh_precondition": (_I32, [_I64, _P, _I64, _F, _I32, _I32, _D, _P, _P, _P, _SZ, _P]),
     "pdg_keyframe_workspace": (_I32, [_I32, ctypes.POINTER(_SZ)]),
     "pdg_keyframe": (_I32, [_P, _I32, _I64, _D, _P, _P, _P, _SZ, _P]),
     "pdg_chamfer_workspace": (_I32, [_I64, _I64, _I32, ctypes.POINTER(_SZ)]),
@@ -190,6 +192,26 @@ def deform_backward(grids, x, gout, res, level_scale=None, need_grids=True, need
                                     _ptr(gx), _ptr(ws), nb.value if ws is not None else 0,
                                     _stream()), "pdg_deform_backward")
     return gg, gx
+
+
+def mesh_precondition(g: torch.Tensor, edges: torch.Tensor, max_degree: int, lam: float = 16.0,
+                      iters: int = 0, tol: float = 1e-7, out=None) -> torch.Tensor:
+    """(I + lam L)^-2 g for the mesh Laplacian of edges (2, E) int32; g (3, V)
+    float32; max_degree bounds every vertex degree (Sec. 3.2, 3.6)."""
+    _dev(g, torch.float32, "g")
+    _dev(edges, torch.int32, "edges")
+    if g.dim() != 2 or g.shape[0] != 3 or edges.dim() != 2 or edges.shape[0] != 2:
+        raise ValueError("g must be (3, V) and edges (2, E)")
+    v, e = g.shape[1], edges.shape[1]
+    out = torch.empty_like(g) if out is None else _dev(out, torch.float32, "out")
+    nb = ctypes.c_size_t()
+    check(lib().pdg_mesh_precondition_workspace(v, e, ctypes.byref(nb)),
+          "pdg_mesh_precondition_workspace")
+    ws = _ws(nb.value, g.device)
+    check(lib().pdg_mesh_precondition(v, _ptr(edges) if e > 0 else None, e, float(lam),
+                                      int(max_degree), int(iters), float(tol), _ptr(g), _ptr(out),
+                                      _ptr(ws), nb.value, _stream()), "pdg_mesh_precondition")
+    return out
 
 
 def keyframe(points: torch.Tensor, gamma: float = 0.001):

@@ -82,21 +82,6 @@ GridDev make_grid(const pdg_grid_desc &d) {
 
 namespace {
 
-inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Bump allocator over a caller workspace; with base == nullptr it only sizes.
-struct Carve {
-  char *base;
-  size_t off = 0;
-  explicit Carve(void *b) : base((char *)b) {}
-  template <class T>
-  T *take(long long count) {
-    T *p = base ? (T *)(base + off) : nullptr;
-    off += a256((size_t)(count > 0 ? count : 0) * sizeof(T));
-    return p;
-  }
-};
-
 int bits_for(unsigned long long maxkey) {
   int b = 1;
   while (b < 32 && (1ull << b) <= maxkey) ++b;
@@ -748,6 +733,36 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
     PDG_TRY(launch_chain_adjoint(g, grids, x, n, gout, n, nullptr, 0, gx, n, n, stream));
   }
   return PDG_OK;
+}
+
+pdg_status pdg_mesh_precondition_workspace(int64_t V, int64_t E, size_t *bytes) {
+  if (!bytes || V < 0 || E < 0 || V >= (1ll << 31) - 1 || E >= (1ll << 30)) {
+    set_error("bytes NULL or V, E outside [0, 2^31 - 1), [0, 2^30)");
+    return PDG_EINVAL;
+  }
+  *bytes = mesh_precond_bytes(V, E);
+  return PDG_OK;
+}
+
+pdg_status pdg_mesh_precondition(int64_t V, const int32_t *edges, int64_t E, float lambda,
+                                 int32_t max_degree, int32_t iters, double tol, const float *g,
+                                 float *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_mesh_precondition_workspace(V, E, &need_bytes));
+  if (!(lambda >= 0.0f) || !isfinite(lambda) || max_degree < 0 || iters < 0 ||
+      (iters == 0 && !(tol > 0.0 && tol < 1.0))) {
+    set_error("lambda must be finite and >= 0, max_degree and iters >= 0, tol in (0, 1)");
+    return PDG_EINVAL;
+  }
+  if (V == 0) return PDG_OK;
+  PDG_TRY(need(g, "g"));
+  PDG_TRY(need(out, "out"));
+  if (E > 0) PDG_TRY(need(edges, "edges"));
+  PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
+  const int k = iters > 0 ? iters
+                          : cheb_iterations(1.0 + 2.0 * (double)lambda * (double)max_degree, tol);
+  return launch_mesh_precondition(V, (const int *)edges, E, lambda, max_degree, k, g, out, ws,
+                                  stream);
 }
 
 pdg_status pdg_keyframe_workspace(int32_t frames, size_t *bytes) {

@@ -75,6 +75,21 @@ __device__ __forceinline__ float corner_weight(int k, float fx, float fy, float 
 
 inline unsigned div_up(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over a caller workspace; with base == nullptr it only sizes.
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base((char *)b) {}
+  template <class T>
+  T *take(long long count) {
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += a256((size_t)(count > 0 ? count : 0) * sizeof(T));
+    return p;
+  }
+};
+
 // Pointers that kernels read from device-side tables (job and segment
 // descriptors) are generic to the compiler, which then emits flat memory
 // instructions and, unable to tell their counters apart, waits for all
@@ -331,6 +346,13 @@ struct AdamFuse {
 pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *src, float *data,
                    const void *ws, hipStream_t st, const AdamFuse *adam = nullptr,
                    unsigned *fused = nullptr);
+
+// mesh.hip: (I + lambda L)^-2 on a mesh's vertices by two Chebyshev solves
+size_t mesh_precond_bytes(long long V, long long E);
+int cheb_iterations(double kappa, double tol);
+pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, float lambda,
+                                    int max_degree, int iters, const float *g, float *out,
+                                    void *ws, hipStream_t st);
 
 // keyframe.hip: Eq. 19-20 (occupied 128^3 voxels per frame, weighted argmax)
 size_t keyframe_bytes(int frames);

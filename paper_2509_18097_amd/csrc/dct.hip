@@ -984,7 +984,6 @@ pdg_status pass(const PassArgs &a, hipStream_t st) {
   }
 }
 
-inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 

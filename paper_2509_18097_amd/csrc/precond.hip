@@ -289,7 +289,6 @@ __global__ __launch_bounds__(kThreads) void cg_reduce_kernel(CGPlanDev P, int k,
   }
 }
 
-inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
