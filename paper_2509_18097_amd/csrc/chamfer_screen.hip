@@ -225,14 +225,11 @@ __device__ __forceinline__ int out_row(int r, int lane) {
 
 __device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, int cbase, int nc,
                                          const PDG_GLOBAL float4 *__restrict__ cc) {
-  float m = fminf(fminf(v[0], v[1]), v[2]);
-  m = fminf(fminf(m, v[3]), v[4]);
-  m = fminf(fminf(m, v[5]), v[6]);
-  m = fminf(fminf(m, v[7]), v[8]);
-  m = fminf(fminf(m, v[9]), v[10]);
-  m = fminf(fminf(m, v[11]), v[12]);
-  m = fminf(fminf(m, v[13]), v[14]);
-  m = fminf(m, v[15]);
+  // (the chain starts from +inf, a canonical value, so that no product needs
+  // a canonicalising instruction before the three-operand minima)
+  float m = __builtin_huge_valf();
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) m = fminf(fminf(m, v[r]), v[r + 1]);
   if (!(m <= s.thr)) return;
   // rare path: rows whose screened value passes the current threshold (the
   // threshold only tightens below, so re-ranking all of them is safe)
