@@ -273,8 +273,11 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
  * sum_t CD_R(P^_t,P_t)/T, sum_t w_conf CD_R(X_t,P_t)/T, w_conf(T), epoch}.
  * With use_graph != 0 the step is replayed from a HIP graph captured on the
  * first call for this stream.  With the DCT preconditioner the last inverse
- * pass of each 64^3 and 128^3 level applies Adam to the values it writes
- * (same arithmetic as the Adam stage, so the same parameters bit for bit). */
+ * pass of each 64^3 and 128^3 level applies Adam to the values it computes
+ * (same arithmetic as the Adam stage, so the same parameters bit for bit)
+ * and does not store them: after pdg_step those levels of PDG_BUF_PGRAD are
+ * not the preconditioned gradient (pdg_step_stage(PDG_STAGE_PRECOND) fills
+ * them from PDG_BUF_GRAD without touching the parameters). */
 pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t use_graph,
                     hipStream_t stream);
 /* One stage of pdg_step alone, in step order WARP, NN, LOSS, GRAD, SCATTER,
@@ -315,7 +318,10 @@ pdg_status pdg_problem_destroy(pdg_problem *p);
  *   PDG_BUF_LOSSES double[T][4]      CD directions: P^->P, P->P^, X->P, P->X
  *   PDG_BUF_WCONF  double[T]
  *   PDG_BUF_GRAD   float [T][grid_size]  raw gradient dL/dG
- *   PDG_BUF_PGRAD  float [T][grid_size]  preconditioned gradient
+ *   PDG_BUF_PGRAD  float [T][grid_size]  preconditioned gradient (after
+ *                                        pdg_step with the DCT preconditioner
+ *                                        only for levels other than 64^3 and
+ *                                        128^3; see pdg_step)
  *   PDG_BUF_GPHAT  float [T][3][n]   dL/dP^_t
  *   PDG_BUF_GXHAT  float [T][3][V]   direct dL/dX_t (Chamfer + isometry), frames 1..T
  *   PDG_BUF_TERMS  double[8]         the loss terms of pdg_step

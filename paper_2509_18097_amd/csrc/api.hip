@@ -586,7 +586,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       sl.count = 1;
       sl.list[0] = scatter_list(p.pkeys, p.pvals, p.pstart_p, N, p.d.points, 3 * N, N, p.gphat,
                                 3 * N, N, p.ent_p, p.ent2_p);
-      PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[0], st));
+      PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[0], st, true));   // fractions staged at creation
       if (p.has_tm) {
         sl.list[1] = scatter_list(p.tkeys, p.tvals, p.pstart_t, V, p.xhat, 3 * V, V, p.lam,
                                   3 * V, V, p.ent_t, p.ent2_t);
@@ -1151,12 +1151,14 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     if (s == PDG_OK) s = launch_screen_pack(p->ssets + p->nseg, (int)T, (int)N, stream);
     if (s == PDG_OK) s = launch_fill((float *)p->tiles, 2, 0.f, stream);
   }
-  // static scatter entries of the input points (fixed positions)
-  if (s == PDG_OK) s = scatter_entries(
-      p->g, (int)T,
-      scatter_list(p->pkeys, p->pvals, p->pstart_p, N, pd->points, 3 * N, N, nullptr, 0, 0,
-                   nullptr, nullptr),
-      p->pkeys, p->pvals, p->pstart_p, p->sort, stream);
+  // static scatter entries of the input points (fixed positions): keys, row
+  // table and the stencil fractions (the steps re-stage only the adjoints)
+  if (s == PDG_OK) {
+    const ScatterList pl = scatter_list(p->pkeys, p->pvals, p->pstart_p, N, pd->points, 3 * N, N,
+                                        p->gphat, 3 * N, N, p->ent_p, p->ent2_p);
+    s = scatter_entries(p->g, (int)T, pl, p->pkeys, p->pvals, p->pstart_p, p->sort, stream);
+    if (s == PDG_OK) s = launch_scatter_stage(p->g, (int)T, pl, stream);
+  }
   if (s == PDG_OK && p->has_tm)
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);

@@ -340,9 +340,9 @@ struct AdamFuse {
 };
 
 // src -> data (src may equal data).  With adam non-null, levels whose last
-// pass can apply Adam to the preconditioned values (while still writing them
-// to data) do so; their bits are set in *fused (levels not set need
-// launch_adam_levels afterwards).
+// pass can apply Adam to the preconditioned values do so instead of writing
+// them to data (data then holds those levels' spectra); their bits are set in
+// *fused (levels not set need launch_adam_levels afterwards).
 pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *src, float *data,
                    const void *ws, hipStream_t st, const AdamFuse *adam = nullptr,
                    unsigned *fused = nullptr);

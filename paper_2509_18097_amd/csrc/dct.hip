@@ -644,8 +644,8 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_fwd_kernel(FusedArgs a) {
 }
 
 // Inverse y and x transforms: spectra (q, p) in, natural (y, x) out.  With
-// ADAM the outputs (still written to dst) also drive an Adam step of the
-// parameters at the same positions: each thread loads its float4 groups of
+// ADAM the outputs are not stored: they drive an Adam step of the
+// parameters at the same positions instead: each thread loads its float4 groups of
 // parameters and first moments when the plane starts and of second moments
 // before the y product, so that the loads overlap the products, and the y
 // products reach the linear epilogue through LDS.
@@ -753,7 +753,6 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a, Ada
         const unsigned i = 4u * (threadIdx.x + k * kBig);
         const float *gr = gb + k * (4 * kBig / R) * P;
         const float4 gv = make_float4(gr[0], gr[1], gr[2], gr[3]);
-        *reinterpret_cast<float4 *>(a.dst + base + i) = gv;
         th[k].x = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.x, mo[k].x, vo[k].x, th[k].x);
         th[k].y = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.y, mo[k].y, vo[k].y, th[k].y);
         th[k].z = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.z, mo[k].z, vo[k].z, th[k].z);

@@ -33,6 +33,7 @@ def run():
     theta1, m1, v1 = host(prob.params), host(prob.m), host(prob.v)
     print("full-size sequence: step 1", flush=True)
     prob.step(1, use_graph=True)
+    prob.stage("precond")      # the full step does not store the fused levels' gradient
     torch.cuda.synchronize()
     out = {k: host(prob.buffer(k)) for k in ("phat", "xhat", "losses", "wconf", "grad", "pgrad",
                                               "gphat", "gxhat", "lam", "terms")}
