@@ -98,19 +98,30 @@ __device__ __forceinline__ double block_sum_f64(double v, double *sh) {
   return t;
 }
 
+// Workgroups are dealt to the eight XCDs in turn by linear id; the kLossBlocks
+// workgroups of one (segment, direction) job are mapped to one XCD (id 8k + x
+// is block k % kLossBlocks of job (k / kLossBlocks) * 8 + x), so its L2 holds
+// the job's candidate set once instead of every XCD fetching it.
+constexpr int kLossXcds = 8;
+
 __global__ __launch_bounds__(256) void chamfer_loss_kernel(const ChSeg *__restrict__ segs,
-                                                           double alpha,
+                                                           int njobs, double alpha,
                                                            double *__restrict__ partials) {
   __shared__ double sh[4];
-  const ChSeg S = segs[blockIdx.y];
-  const int dir = blockIdx.z;
+  const unsigned x = blockIdx.x % kLossXcds, k = blockIdx.x / kLossXcds;
+  const int job = (int)((k / kLossBlocks) * kLossXcds + x);
+  const int blk = (int)(k % kLossBlocks);
+  if (job >= njobs) return;
+  const int seg = job >> 1;
+  const ChSeg S = segs[seg];
+  const int dir = job & 1;
   const PDG_GLOBAL float *q = glb(dir == 0 ? S.a : S.b);
   const PDG_GLOBAL float *c = glb(dir == 0 ? S.b : S.a);
   const int nq = dir == 0 ? S.n : S.m;
   const long long nc = dir == 0 ? S.m : S.n;
   const PDG_GLOBAL int *nn = glb(dir == 0 ? S.nn_a : S.nn_b);
   double acc = 0.0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < nq; i += kLossBlocks * 256) {
+  for (int i = blk * 256 + threadIdx.x; i < nq; i += kLossBlocks * 256) {
     const int j = nn[i];
     const double dx = (double)q[i] - (double)c[j];
     const double dy = (double)q[nq + i] - (double)c[nc + j];
@@ -120,7 +131,7 @@ __global__ __launch_bounds__(256) void chamfer_loss_kernel(const ChSeg *__restri
   }
   double t = block_sum_f64(acc, sh);
   if (threadIdx.x == 0)
-    partials[((long long)blockIdx.y * 2 + dir) * kLossBlocks + blockIdx.x] = t;
+    partials[((long long)seg * 2 + dir) * kLossBlocks + blk] = t;
 }
 
 __global__ void chamfer_loss_final_kernel(const ChSeg *__restrict__ segs, int nseg,
@@ -134,15 +145,19 @@ __global__ void chamfer_loss_final_kernel(const ChSeg *__restrict__ segs, int ns
   losses[k] = t / (double)((k & 1) ? S.m : S.n);
 }
 
+// One segment's nb workgroups on one XCD, as for the loss.
 __global__ __launch_bounds__(256) void chamfer_grad_fwd_kernel(const ChSeg *__restrict__ segs,
-                                                               float alpha,
+                                                               int nseg, unsigned nb, float alpha,
                                                                const double *__restrict__ w) {
-  const int seg = blockIdx.y;
+  const unsigned x = blockIdx.x % kLossXcds, k = blockIdx.x / kLossXcds;
+  const int seg = (int)((k / nb) * kLossXcds + x);
+  const unsigned blk = k % nb;
+  if (seg >= nseg) return;
   const ChSeg S = segs[seg];
   const PDG_GLOBAL float *Sa = glb(S.a), *Sb = glb(S.b);
   const PDG_GLOBAL int *Snn = glb(S.nn_a);
   PDG_GLOBAL float *Sga = glb(S.ga);
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = (int)blk * 256 + threadIdx.x;
   if (i >= S.n || S.ga == nullptr) return;
   const long long m = S.m, n = S.n;
   const int j = Snn[i];
@@ -322,8 +337,9 @@ pdg_status launch_nn_exact(const NNJob *jobs, int njobs, int max_nq, hipStream_t
 pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double *partials,
                                double *losses, hipStream_t st) {
   if (nseg <= 0) return PDG_OK;
-  dim3 grid(kLossBlocks, nseg, 2);
-  chamfer_loss_kernel<<<grid, 256, 0, st>>>(segs, alpha, partials);
+  const int njobs = 2 * nseg;
+  const long long blocks = (long long)(njobs + kLossXcds - 1) / kLossXcds * kLossXcds * kLossBlocks;
+  chamfer_loss_kernel<<<(unsigned)blocks, 256, 0, st>>>(segs, njobs, alpha, partials);
   PDG_TRY(launched("chamfer_loss"));
   chamfer_loss_final_kernel<<<div_up(2 * nseg, 64), 64, 0, st>>>(segs, nseg, partials, losses);
   return launched("chamfer_loss_final");
@@ -332,8 +348,9 @@ pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double
 pdg_status launch_chamfer_grad_fwd(const ChSeg *segs, int nseg, int max_n, float alpha,
                                    const double *w, hipStream_t st) {
   if (nseg <= 0 || max_n <= 0) return PDG_OK;
-  dim3 grid(div_up(max_n, 256), nseg);
-  chamfer_grad_fwd_kernel<<<grid, 256, 0, st>>>(segs, alpha, w);
+  const unsigned nb = div_up(max_n, 256);
+  const long long blocks = (long long)(nseg + kLossXcds - 1) / kLossXcds * kLossXcds * nb;
+  chamfer_grad_fwd_kernel<<<(unsigned)blocks, 256, 0, st>>>(segs, nseg, nb, alpha, w);
   return launched("chamfer_grad_fwd");
 }
 
