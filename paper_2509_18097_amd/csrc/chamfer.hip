@@ -98,30 +98,24 @@ __device__ __forceinline__ double block_sum_f64(double v, double *sh) {
   return t;
 }
 
-// Workgroups are dealt to the eight XCDs in turn by linear id; the kLossBlocks
-// workgroups of one (segment, direction) job are mapped to one XCD (id 8k + x
-// is block k % kLossBlocks of job (k / kLossBlocks) * 8 + x), so its L2 holds
-// the job's candidate set once instead of every XCD fetching it.
-constexpr int kLossXcds = 8;
-
+// The kLossBlocks workgroups of one (segment, direction) job run on one XCD
+// (job_block), so its L2 holds the job's candidate set once.
 __global__ __launch_bounds__(256) void chamfer_loss_kernel(const ChSeg *__restrict__ segs,
                                                            int njobs, double alpha,
                                                            double *__restrict__ partials) {
   __shared__ double sh[4];
-  const unsigned x = blockIdx.x % kLossXcds, k = blockIdx.x / kLossXcds;
-  const int job = (int)((k / kLossBlocks) * kLossXcds + x);
-  const int blk = (int)(k % kLossBlocks);
-  if (job >= njobs) return;
-  const int seg = job >> 1;
+  unsigned job, blk;
+  if (!job_block(blockIdx.x, (unsigned)njobs, kLossBlocks, job, blk)) return;
+  const int seg = (int)job >> 1;
   const ChSeg S = segs[seg];
-  const int dir = job & 1;
+  const int dir = (int)job & 1;
   const PDG_GLOBAL float *q = glb(dir == 0 ? S.a : S.b);
   const PDG_GLOBAL float *c = glb(dir == 0 ? S.b : S.a);
   const int nq = dir == 0 ? S.n : S.m;
   const long long nc = dir == 0 ? S.m : S.n;
   const PDG_GLOBAL int *nn = glb(dir == 0 ? S.nn_a : S.nn_b);
   double acc = 0.0;
-  for (int i = blk * 256 + threadIdx.x; i < nq; i += kLossBlocks * 256) {
+  for (int i = (int)blk * 256 + threadIdx.x; i < nq; i += kLossBlocks * 256) {
     const int j = nn[i];
     const double dx = (double)q[i] - (double)c[j];
     const double dy = (double)q[nq + i] - (double)c[nc + j];
@@ -149,10 +143,9 @@ __global__ void chamfer_loss_final_kernel(const ChSeg *__restrict__ segs, int ns
 __global__ __launch_bounds__(256) void chamfer_grad_fwd_kernel(const ChSeg *__restrict__ segs,
                                                                int nseg, unsigned nb, float alpha,
                                                                const double *__restrict__ w) {
-  const unsigned x = blockIdx.x % kLossXcds, k = blockIdx.x / kLossXcds;
-  const int seg = (int)((k / nb) * kLossXcds + x);
-  const unsigned blk = k % nb;
-  if (seg >= nseg) return;
+  unsigned job, blk;
+  if (!job_block(blockIdx.x, (unsigned)nseg, nb, job, blk)) return;
+  const int seg = (int)job;
   const ChSeg S = segs[seg];
   const PDG_GLOBAL float *Sa = glb(S.a), *Sb = glb(S.b);
   const PDG_GLOBAL int *Snn = glb(S.nn_a);
@@ -215,7 +208,10 @@ __global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
   __shared__ uint32_t skey[kRevThreads + 1];
   __shared__ float wtail[kRevThreads / 64][3];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const long long b0 = (long long)blockIdx.x * kRevThreads;
+  // consecutive blocks (one segment's sorted entries) on one XCD
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  if ((long long)blk * kRevThreads >= nent) return;
+  const long long b0 = (long long)blk * kRevThreads;
   const long long i = b0 + t;
   const bool valid = i < nent;
   const uint32_t key = valid ? keys[i] : 0xffffffffu;
@@ -272,11 +268,11 @@ __global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
   }
   if (!valid || (skey[t + 1] == key && t + 1 < kRevThreads)) return;   // not the run's last here
   const bool ends = skey[t + 1] != key;                 // run ends inside this block
-  const bool entered = blockIdx.x > 0 && key == skey[0] && keys[b0 - 1] == key;
+  const bool entered = blk > 0 && key == skey[0] && keys[b0 - 1] == key;
   if (entered) {
-    head[blockIdx.x] = make_float4(v[0], v[1], v[2], 0.f);
+    head[blk] = make_float4(v[0], v[1], v[2], 0.f);
   } else if (!ends) {
-    tail[blockIdx.x] = make_float4(v[0], v[1], v[2], 0.f);
+    tail[blk] = make_float4(v[0], v[1], v[2], 0.f);
   } else {
     const ChSeg &S = segs[sg];
     if (S.ga == nullptr) return;
@@ -338,8 +334,8 @@ pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double
                                double *losses, hipStream_t st) {
   if (nseg <= 0) return PDG_OK;
   const int njobs = 2 * nseg;
-  const long long blocks = (long long)(njobs + kLossXcds - 1) / kLossXcds * kLossXcds * kLossBlocks;
-  chamfer_loss_kernel<<<(unsigned)blocks, 256, 0, st>>>(segs, njobs, alpha, partials);
+  chamfer_loss_kernel<<<(unsigned)job_grid(njobs, kLossBlocks), 256, 0, st>>>(segs, njobs, alpha,
+                                                                              partials);
   PDG_TRY(launched("chamfer_loss"));
   chamfer_loss_final_kernel<<<div_up(2 * nseg, 64), 64, 0, st>>>(segs, nseg, partials, losses);
   return launched("chamfer_loss_final");
@@ -349,8 +345,7 @@ pdg_status launch_chamfer_grad_fwd(const ChSeg *segs, int nseg, int max_n, float
                                    const double *w, hipStream_t st) {
   if (nseg <= 0 || max_n <= 0) return PDG_OK;
   const unsigned nb = div_up(max_n, 256);
-  const long long blocks = (long long)(nseg + kLossXcds - 1) / kLossXcds * kLossXcds * nb;
-  chamfer_grad_fwd_kernel<<<(unsigned)blocks, 256, 0, st>>>(segs, nseg, nb, alpha, w);
+  chamfer_grad_fwd_kernel<<<(unsigned)job_grid(nseg, nb), 256, 0, st>>>(segs, nseg, nb, alpha, w);
   return launched("chamfer_grad_fwd");
 }
 
@@ -373,7 +368,7 @@ pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigne
     set_error("chamfer reverse scatter: %lld entries exceed the launch limit", nent);
     return PDG_EINVAL;
   }
-  chamfer_rev_scatter_kernel<<<(unsigned)nb, kRevThreads, 0, st>>>(segs, nseg, b_base, keys, vals,
+  chamfer_rev_scatter_kernel<<<xcd_pad(nb), kRevThreads, 0, st>>>(segs, nseg, b_base, keys, vals,
                                                                   nent, alpha, w, part, part + nb);
   PDG_TRY(launched("chamfer_rev_scatter"));
   rev_join_kernel<<<div_up(nb, 256), 256, 0, st>>>(segs, nseg, b_base, keys, vals, nent, (int)nb,

@@ -119,16 +119,19 @@ __global__ __launch_bounds__(256) void morton_kernel(const float *__restrict__ x
 // the set (float bits of non-negative values order like unsigned integers, so
 // an integer atomic max is exact and order independent; one per block), and,
 // one block per 256-point tile, the tile's bounding box.
-__global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__ sets) {
+__global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__ sets, int nsets,
+                                                   unsigned nb) {
   __shared__ float red[7][4];
-  const ScreenSet S = sets[blockIdx.y];
-  if ((long long)blockIdx.x * 256 >= S.n) return;
+  unsigned job, tb;                   // one set's workgroups on one XCD
+  if (!job_block(blockIdx.x, (unsigned)nsets, nb, job, tb)) return;
+  const ScreenSet S = sets[job];
+  if ((long long)tb * 256 >= S.n) return;
   const PDG_GLOBAL float *sx = glb(S.x);
   const PDG_GLOBAL int *sperm = glb(S.perm);
   PDG_GLOBAL uint4 *spk = glb(S.pack);
   PDG_GLOBAL float4 *scoords = glb(S.coords);
   PDG_GLOBAL float4 *sboxes = glb(S.boxes);
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = tb * 256 + threadIdx.x;
   float nrm = 0.f;
   float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
   float hi3[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
@@ -196,8 +199,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     // one atomic per block; each set's maximum sits on a cache line of its own
     const float m = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
     if (m > 0.f) atomicMax(glb(S.maxnorm), __float_as_uint(m));
-    sboxes[2 * blockIdx.x] = make_float4(b[0], b[1], b[2], 0.f);
-    sboxes[2 * blockIdx.x + 1] = make_float4(b[3], b[4], b[5], 0.f);
+    sboxes[2 * tb] = make_float4(b[0], b[1], b[2], 0.f);
+    sboxes[2 * tb + 1] = make_float4(b[3], b[4], b[5], 0.f);
   }
 }
 
@@ -523,8 +526,8 @@ pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, ui
 
 pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipStream_t st) {
   if (nsets <= 0 || max_n <= 0) return PDG_OK;
-  dim3 grid(div_up(max_n, 256), nsets);
-  pack_kernel<<<grid, 256, 0, st>>>(sets);
+  const unsigned nb = div_up(max_n, 256);
+  pack_kernel<<<(unsigned)job_grid(nsets, nb), 256, 0, st>>>(sets, nsets, nb);
   return launched("screen_pack");
 }
 

@@ -77,6 +77,37 @@ inline unsigned div_up(long long a, long long b) { return (unsigned)((a + b - 1)
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workgroups are dealt to the eight XCDs (each with its own L2) in turn by
+// linear id.  job_block maps workgroup lin of a grid of job_grid(njobs, nb)
+// workgroups to (job, block < nb): with at least eight jobs every workgroup of
+// a job runs on one XCD (its data cached in one L2); with fewer, job-major
+// order.  It returns false for padding workgroups.
+constexpr unsigned kXcdCount = 8;
+__device__ __forceinline__ bool job_block(unsigned lin, unsigned njobs, unsigned nb, unsigned &job,
+                                          unsigned &blk) {
+  if (njobs >= kXcdCount) {
+    const unsigned x = lin % kXcdCount, k = lin / kXcdCount;
+    job = (k / nb) * kXcdCount + x;
+    blk = k % nb;
+  } else {
+    job = lin / nb;
+    blk = lin % nb;
+  }
+  return job < njobs;
+}
+inline unsigned long long job_grid(unsigned njobs, unsigned nb) {
+  return njobs >= kXcdCount ? (unsigned long long)(njobs + kXcdCount - 1) / kXcdCount * kXcdCount * nb
+                            : (unsigned long long)njobs * nb;
+}
+// For a 1-D grid of xcd_pad(n) workgroups: logical block of workgroup lin such
+// that each XCD takes one contiguous range (consecutive blocks share an L2).
+inline unsigned xcd_pad(unsigned long long n) {
+  return (unsigned)((n + kXcdCount - 1) / kXcdCount * kXcdCount);
+}
+__device__ __forceinline__ unsigned xcd_block(unsigned lin, unsigned padded) {
+  return (lin % kXcdCount) * (padded / kXcdCount) + lin / kXcdCount;
+}
+
 // Bump allocator over a caller workspace; with base == nullptr it only sizes.
 struct Carve {
   char *base;

@@ -256,10 +256,13 @@ __global__ __launch_bounds__(256) void warp_kernel(GridDev g, const float *__res
                                                    float *__restrict__ out, long long ostride,
                                                    long long ldo, long long n,
                                                    const int *__restrict__ order,
-                                                   long long order_stride) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                   long long order_stride, int batch,
+                                                   unsigned nb) {
+  unsigned job, blk;                  // one batch entry's workgroups on one XCD
+  if (!job_block(blockIdx.x, (unsigned)batch, nb, job, blk)) return;
+  const long long t = (long long)blk * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const int b = blockIdx.y;
+  const int b = (int)job;
   const long long i = order ? order[b * order_stride + t] : t;
   const float *X = x + b * xstride;
   float *O = out + b * ostride;
@@ -525,7 +528,8 @@ __global__ void upload_kernel(Blob blob, unsigned char *__restrict__ dst, int n)
 // kept (read back from ent) and only the adjoint values are staged anew.
 __global__ __launch_bounds__(256) void scatter_stage_kernel(GridDev g, ScatterList L, int nent,
                                                             int lam_only) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // consecutive blocks (one segment's sorted entries) on one XCD
+  const long long i = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= nent) return;
   const uint32_t e = L.vals[i], S = (uint32_t)L.S;
   const uint32_t segl = e / S;
@@ -866,9 +870,14 @@ pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, 
                        long long ldo, long long n, int batch, hipStream_t st, const int *order,
                        long long order_stride) {
   if (n <= 0 || batch <= 0) return PDG_OK;
-  dim3 grid(div_up(n, 256), batch);
-  warp_kernel<<<grid, 256, 0, st>>>(g, grids, gstride, x, xstride, ldx, out, ostride, ldo, n,
-                                    order, order_stride);
+  const unsigned nb = div_up(n, 256);
+  const unsigned long long blocks = job_grid(batch, nb);
+  if (blocks >= (1ull << 31)) {
+    set_error("warp: %llu workgroups exceed the launch limit", blocks);
+    return PDG_EINVAL;
+  }
+  warp_kernel<<<(unsigned)blocks, 256, 0, st>>>(g, grids, gstride, x, xstride, ldx, out, ostride,
+                                                ldo, n, order, order_stride, batch, nb);
   return launched("warp");
 }
 
@@ -976,7 +985,8 @@ pdg_status launch_scatter_stage(const GridDev &g, int segs, const ScatterList &L
                                 bool lam_only) {
   const long long nent = (long long)segs * g.levels * L.S;
   if (nent <= 0) return PDG_OK;
-  scatter_stage_kernel<<<div_up(nent, 256), 256, 0, st>>>(g, L, (int)nent, lam_only ? 1 : 0);
+  scatter_stage_kernel<<<xcd_pad(div_up(nent, 256)), 256, 0, st>>>(g, L, (int)nent,
+                                                                   lam_only ? 1 : 0);
   return launched("scatter_stage");
 }
 
