@@ -1003,14 +1003,14 @@ GatherPlan gather_plan(const GridDev &g, int segs, long long samples) {
     if (B < 1) B = 1;
     if (B > R) B = R;
     // entries of a band if the samples spread evenly: two cell planes of
-    // B + 1 rows; split into pieces of about three chunks, at most 16 or as
+    // B + 1 rows; split into pieces of about six chunks, at most 16 or as
     // many as 2^22 floats of partial bands allow (coarse levels of many
     // samples), at most 512
     const double per_band = 2.0 * (double)samples * (B + 1) / ((double)R * R);
     const double per_piece = 3.0 * (double)R * R * R * segs;
     double kmax = (double)(1 << 22) / per_piece;
     kmax = kmax < 16.0 ? 16.0 : (kmax > 512.0 ? 512.0 : kmax);
-    double kf = per_band / (3.0 * kGatherThreads);
+    double kf = per_band / (6.0 * kGatherThreads);
     kf = kf < 1.0 ? 1.0 : (kf > kmax ? kmax : kf);
     const int K = (int)kf;
     gp.R[l] = R;
