@@ -16,6 +16,8 @@ Modules (each function cites the passage of the paper it follows):
                    nearest neighbours, per-direction losses and gradients.
 * ``precond``   -- grid Sobolev preconditioner (I + lambda L)^-2 (Sec. 3.2,
                    Eq. 3): dense Cholesky and the DCT-II closed form.
+* ``prune``     -- pruned grids (Sec. 3.6): active cells by occupancy and a
+                   three-cell halo, the preconditioner on the induced graph.
 * ``adam``      -- Adam with bias correction (Sec. 3.6).
 * ``keyframe``  -- keyframe selection by weighted 128^3 occupancy (Sec. 3.5,
                    Eq. 19-20).
@@ -27,4 +29,4 @@ Modules (each function cites the passage of the paper it follows):
 Readings of the paper where it is silent or ambiguous are listed in the
 module docstrings where they are used.
 """
-from . import warp, cayley, chamfer, precond, adam, sequence, keyframe, mesh  # noqa: F401
+from . import warp, cayley, chamfer, precond, adam, sequence, keyframe, mesh, prune  # noqa: F401

@@ -36,6 +36,7 @@ import numpy as np
 from . import adam as _adam
 from . import chamfer as _ch
 from . import precond as _pc
+from . import prune as _pr
 from . import warp as _wp
 
 
@@ -121,7 +122,7 @@ class StepResult:
 
 def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hyper(),
          phat32=None, xhat32=None, workers: int = 1, precond_method: str = "dct",
-         grad_override=None, pgrad_override=None) -> StepResult:
+         grad_override=None, pgrad_override=None, masks=None) -> StepResult:
     """One iteration: warp, Chamfer + isometry losses, gradient, preconditioner, Adam.
 
     points (F, 3, N) float32; template (3, V) float32 or None; edges (2, E);
@@ -132,6 +133,8 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     be compared on identical inputs); by default the oracle's own float64
     positions are rounded to float32.  ``grad_override`` / ``pgrad_override``
     replace the raw / preconditioned gradient fed to the following stage.
+    ``masks`` ([t][level] boolean [r, r, r], see ``prune``) prunes the grids:
+    the preconditioner acts on the kept cells only and is zero elsewhere.
     """
     points = np.asarray(points)
     f = points.shape[0]
@@ -207,8 +210,12 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
                 lam = g_x[t - 1] + _wp.position_adjoint(theta[t], res, chain_pos[t], lam, ls)
     r.grad = grad
     g_in = grad if grad_override is None else np.asarray(grad_override, np.float64)
-    pgrad = np.stack([_pc.apply_levels(g_in[t], res, lams, precond_method)
-                      for t in range(t_count)])
+    if masks is None:
+        pgrad = np.stack([_pc.apply_levels(g_in[t], res, lams, precond_method)
+                          for t in range(t_count)])
+    else:
+        pgrad = np.stack([_pr.apply_levels_masked(g_in[t], res, lams, masks[t])
+                          for t in range(t_count)])
     r.pgrad = pgrad
     p_in = pgrad if pgrad_override is None else np.asarray(pgrad_override, np.float64)
     th, mm, vv = np.empty_like(theta), np.empty_like(theta), np.empty_like(theta)
