@@ -90,7 +90,7 @@ def parse():
     return ap.parse_args()
 
 
-def make_problem(subdiv, chamfer, precond):
+def make_problem(subdiv, chamfer, precond, prune_halo=None):
     import torch
     import synth
     from paper_2509_18097_amd.problem import HyperParams, Problem
@@ -98,7 +98,7 @@ def make_problem(subdiv, chamfer, precond):
     prob = Problem(torch.from_numpy(seq.points).cuda(), RES,
                    template=torch.from_numpy(seq.template).cuda(),
                    edges=torch.from_numpy(seq.edges).cuda(), hp=HyperParams(e_max=50),
-                   chamfer_mode=chamfer, precond=precond)
+                   chamfer_mode=chamfer, precond=precond, prune_halo=prune_halo)
     return seq, prob
 
 
@@ -319,6 +319,45 @@ def time_mesh_precond(seq, reps=10):
             "ms": round(a.elapsed_time(b) / reps, 4), "max_degree": dmax}
 
 
+def time_pruned(subdiv, chamfer, steps=6, reps=5):
+    """Pruned grids (Sec. 3.6) on the headline sequence: kept-cell masks of
+    every transition from the two frames it connects with a three-cell halo,
+    and the full step with the conjugate-gradient preconditioner on the kept
+    cells' graph (tiles without a kept cell skipped).  The dense step with the
+    same preconditioner is timed beside it."""
+    import torch
+    from paper_2509_18097_amd import _lib as L
+    out = {}
+    for name, halo in (("dense_cg", None), ("pruned_cg", 3)):
+        seq, prob = make_problem(subdiv, chamfer, "cg", prune_halo=halo)
+        ms, _ = time_steps(prob, steps, 2)
+        st = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(reps):
+            prob.stage("precond")
+        b.record(st)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": round(ms, 4), "precond_ms": round(a.elapsed_time(b) / reps, 4)}
+        if halo is not None:
+            kept = prob.kept_cells.sum().item()
+            cells = prob.T * sum(r ** 3 for r in RES)
+            a.record(st)
+            for _ in range(reps):
+                L.prune_mask(prob.points, RES, 2, halo)
+            b.record(st)
+            torch.cuda.synchronize()
+            out[name].update({"halo": halo, "kept_fraction": round(kept / cells, 4),
+                              "kept_fraction_per_level": [
+                                  round(v, 4) for v in (prob.kept_cells.sum(0).double().cpu()
+                                                        / (prob.T * torch.tensor(RES) ** 3)).tolist()],
+                              "mask_ms": round(a.elapsed_time(b) / reps, 4)})
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+    return out
+
+
 def time_keyframe(seq, reps=20):
     """Keyframe selection (Sec. 3.5, Eq. 19-20) over the sequence's frames:
     one bit per occupied 128^3 voxel and frame, population counts, the
@@ -484,6 +523,7 @@ def main():
         result["cayley6"] = time_cayley6()
         result["keyframe"] = time_keyframe(seq)
         result["mesh_precond"] = time_mesh_precond(seq)
+        result["pruned"] = time_pruned(args.subdiv, args.chamfer)
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:

@@ -199,6 +199,40 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
                             int32_t batch, int32_t method, int32_t iters, double tol,
                             void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* --------------------------------------------------------------- pruning --
+ * Pruned grids (paper Sec. 3.6, implementation details): a cell of a level is
+ * kept when an input point lies in it or within `halo` cells of such a cell
+ * along every axis (the paper: halo 3); pruned cells hold zero and are not
+ * optimised.  The cell of a point along an axis is floor((s + 1) R / 2)
+ * clamped to 0..R-1, decided in float32 (a NaN coordinate: cell 0).
+ *
+ * Mask layout (one stack): every level in order, ceil(R^3 / 32) uint32 words
+ * each; cell c = (z R + y) R + x of a level is bit (c & 31) of its word
+ * c >> 5.  pdg_prune_mask_words gives the words per stack; stacks follow each
+ * other at that stride. */
+pdg_status pdg_prune_mask_words(const pdg_grid_desc *d, int64_t *words /*[host]*/);
+pdg_status pdg_prune_workspace(const pdg_grid_desc *d, int32_t stacks, size_t *bytes);
+/* Masks of `stacks` grid stacks: stack b is pruned by frames b .. b+span-1 of
+ * points [stacks + span - 1][3][n] (span 2: the grid of a transition by the
+ * two frames it connects).  mask: [stacks][words] (written whole); active
+ * (nullable): int64 [stacks][levels] kept cells per level; halo 0..16;
+ * 0 <= n < 2^31; stacks + span - 1 <= 65535.  ws: pdg_prune_workspace bytes. */
+pdg_status pdg_prune_mask(const pdg_grid_desc *d, int32_t stacks, int32_t span,
+                          const float *points, int64_t n, int32_t halo, uint32_t *mask,
+                          int64_t *active, void *ws, size_t ws_bytes, hipStream_t stream);
+/* Preconditioner of pruned grids (Eq. 3 on the kept cells), in place:
+ *   g_l <- (I + lambda[l] L_S)^{-2} g_l on the kept cells S of every level,
+ *   channel and stack, 0 on the pruned ones,
+ * L_S the combinatorial Laplacian of the 6-neighbour graph the kept cells
+ * induce (a pruned neighbour counts as absent).  Conjugate gradients as
+ * PDG_PRECOND_CG (iters, tol, the a-priori count: every eigenvalue of L_S is
+ * below 12 as well); mask as pdg_prune_mask writes it, for `batch` stacks;
+ * ws: pdg_precondition_workspace(d, batch, PDG_PRECOND_CG) bytes. */
+pdg_status pdg_precondition_pruned(const pdg_grid_desc *d, const float *lambda, float *g,
+                                   int32_t batch, int32_t iters, double tol,
+                                   const uint32_t *mask, void *ws, size_t ws_bytes,
+                                   hipStream_t stream);
+
 /* ------------------------------------------------------------------ adam --
  * Adam with bias correction (paper Sec. 3.6) over `batch` packed stacks with
  * a per-level learning rate: for every value of level l,
@@ -253,6 +287,14 @@ typedef struct {
   int32_t precond_method;     /* pdg_precond_method                           */
   int32_t cg_iters;           /* 0: a-priori count per level for cg_tol       */
   double cg_tol;              /* e.g. 1e-7                                    */
+  const uint32_t *prune_mask; /* [T][pdg_prune_mask_words] kept-cell bits of
+                                 every transition's grids (pruned grids, see
+                                 pdg_prune_mask; needs PDG_PRECOND_CG), or
+                                 NULL for dense grids.  pdg_problem_create
+                                 zeroes params, adam_m and adam_v on pruned
+                                 cells; the preconditioner then acts on the
+                                 graph of the kept cells and leaves the
+                                 pruned ones at zero.                         */
   float *params;              /* [T][grid_size] theta                         */
   float *adam_m;              /* [T][grid_size]                               */
   float *adam_v;              /* [T][grid_size]                               */

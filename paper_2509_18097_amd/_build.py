@@ -24,7 +24,7 @@ LIB = os.path.join(PKG, "libpdg.so")
 ARCH = "gfx950"
 
 SOURCES = ["sort.hip", "warp.hip", "chamfer.hip", "chamfer_screen.hip", "precond.hip",
-           "dct.hip", "optim.hip", "keyframe.hip", "mesh.hip", "api.hip"]
+           "dct.hip", "optim.hip", "keyframe.hip", "mesh.hip", "prune.hip", "api.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

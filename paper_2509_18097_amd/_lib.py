@@ -50,7 +50,8 @@ class ProblemDesc(ctypes.Structure):
                 ("n_edges", ctypes.c_int32), ("edges", ctypes.c_void_p),
                 ("grid", GridDesc), ("hp", Hyper), ("chamfer_mode", ctypes.c_int32),
                 ("precond_method", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
-                ("cg_tol", ctypes.c_double), ("params", ctypes.c_void_p),
+                ("cg_tol", ctypes.c_double), ("prune_mask", ctypes.c_void_p),
+                ("params", ctypes.c_void_p),
                 ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
@@ -80,6 +81,12 @@ _SIGS = {
     "pdg_precondition_workspace": (_I32, [ctypes.POINTER(GridDesc), _I32, _I32, ctypes.POINTER(_SZ)]),
     "pdg_precondition": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_F), _P, _I32, _I32, _I32,
                                 _D, _P, _SZ, _P]),
+    "pdg_prune_mask_words": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_I64)]),
+    "pdg_prune_workspace": (_I32, [ctypes.POINTER(GridDesc), _I32, ctypes.POINTER(_SZ)]),
+    "pdg_prune_mask": (_I32, [ctypes.POINTER(GridDesc), _I32, _I32, _P, _I64, _I32, _P, _P, _P, _SZ,
+                              _P]),
+    "pdg_precondition_pruned": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_F), _P, _I32, _I32,
+                                       _D, _P, _P, _SZ, _P]),
     "pdg_adam": (_I32, [ctypes.POINTER(GridDesc), _I32, ctypes.POINTER(_F), _F, _F, _F, _I32, _P,
                         _P, _P, _P, _P]),
     "pdg_problem_workspace": (_I32, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(_SZ)]),
@@ -284,6 +291,60 @@ def precondition(g, res, lambdas, batch=1, method="cg", iters=0, tol=1e-7):
     ws = _ws(nb.value, g.device)
     check(lib().pdg_precondition(ctypes.byref(d), lam, _ptr(g), batch, md, iters, tol, _ptr(ws),
                                  nb.value, _stream()), "pdg_precondition")
+    return g
+
+
+def prune_mask_words(res) -> int:
+    """uint32 words of one stack's pruning mask (one bit per cell and level)."""
+    d = grid_desc(res, 1.0)
+    w = ctypes.c_int64()
+    check(lib().pdg_prune_mask_words(ctypes.byref(d), ctypes.byref(w)), "pdg_prune_mask_words")
+    return w.value
+
+
+def prune_mask(points: torch.Tensor, res, span: int = 2, halo: int = 3):
+    """Pruned grids (Sec. 3.6): kept-cell masks of the stacks b = 0 .. F - span,
+    stack b pruned by frames b .. b + span - 1 of points (F, 3, N) float32.
+    Returns (mask int32 (stacks, words) holding the uint32 bits, kept cells
+    int64 (stacks, levels))."""
+    _dev(points, torch.float32, "points")
+    if points.dim() != 3 or points.shape[1] != 3:
+        raise ValueError("points must be (F, 3, N)")
+    stacks = points.shape[0] - span + 1
+    if stacks < 0:
+        raise ValueError("fewer frames than span - 1")
+    d = grid_desc(res, 1.0)
+    words = prune_mask_words(res)
+    mask = torch.empty((max(stacks, 0), words), dtype=torch.int32, device=points.device)
+    active = torch.empty((max(stacks, 0), len(res)), dtype=torch.int64, device=points.device)
+    nb = ctypes.c_size_t()
+    check(lib().pdg_prune_workspace(ctypes.byref(d), max(stacks, 0), ctypes.byref(nb)),
+          "pdg_prune_workspace")
+    ws = _ws(nb.value, points.device)
+    check(lib().pdg_prune_mask(ctypes.byref(d), max(stacks, 0), span, _ptr(points), points.shape[2],
+                               halo, _ptr(mask), _ptr(active), _ptr(ws), nb.value, _stream()),
+          "pdg_prune_mask")
+    return mask, active
+
+
+def precondition_pruned(g, res, lambdas, mask, batch=1, iters=0, tol=1e-7):
+    """In place g <- (I + lambda_l L_S)^-2 g on the kept cells of every level
+    (Eq. 3 on pruned grids), 0 on pruned cells; mask as ``prune_mask``."""
+    d = grid_desc(res, 1.0)
+    _dev(g, torch.float32, "g")
+    _dev(mask, torch.int32, "mask")
+    if g.numel() != batch * grid_size(res):
+        raise ValueError("g must hold `batch` packed stacks")
+    if mask.numel() != batch * prune_mask_words(res):
+        raise ValueError("mask must hold `batch` stacks of prune_mask_words(res) words")
+    lam = (ctypes.c_float * MAX_LEVELS)(*[float(v) for v in lambdas])
+    nb = ctypes.c_size_t()
+    check(lib().pdg_precondition_workspace(ctypes.byref(d), batch, PRECOND_METHODS["cg"],
+                                           ctypes.byref(nb)), "pdg_precondition_workspace")
+    ws = _ws(nb.value, g.device)
+    check(lib().pdg_precondition_pruned(ctypes.byref(d), lam, _ptr(g), batch, iters, tol,
+                                        _ptr(mask), _ptr(ws), nb.value, _stream()),
+          "pdg_precondition_pruned")
     return g
 
 

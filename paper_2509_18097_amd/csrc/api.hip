@@ -400,6 +400,10 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   float lam[PDG_MAX_LEVELS];
   for (int l = 0; l < pd->grid.levels; ++l) lam[l] = pd->hp.lambda0 * powf(pd->hp.lambda_growth, (float)l);
   PDG_TRY(check_precond_args(&pd->grid, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
+  if (pd->prune_mask && pd->precond_method != PDG_PRECOND_CG) {
+    set_error("pruned grids need the conjugate-gradient preconditioner");
+    return PDG_EUNSUPPORTED;
+  }
   const GridDev g = make_grid(pd->grid);
   const long long T = pd->frames - 1;
   if ((unsigned long long)T * g.nodes >= (1ull << 32)) {
@@ -506,6 +510,7 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   p.adam.off[p.g.levels] = p.g.size;
   // every buffer the solver touches is carved at 256-byte alignment
   p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol, true);
+  if (pd.prune_mask) cg_set_mask(p.cg, p.g, pd.prune_mask);
 }
 
 IsoArgs iso_args(pdg_problem &p) {
@@ -966,6 +971,62 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
   return run_cg(p, g, gd.size * batch, ws, stream);
 }
 
+pdg_status pdg_prune_mask_words(const pdg_grid_desc *d, int64_t *words) {
+  PDG_TRY(check_grid(d));
+  PDG_TRY(need(words, "words"));
+  *words = mask_stack_words(make_grid(*d));
+  return PDG_OK;
+}
+
+pdg_status pdg_prune_workspace(const pdg_grid_desc *d, int32_t stacks, size_t *bytes) {
+  PDG_TRY(check_grid(d));
+  if (!bytes || stacks < 0) {
+    set_error("bytes NULL or stacks < 0");
+    return PDG_EINVAL;
+  }
+  *bytes = prune_bytes(make_grid(*d), stacks);
+  return PDG_OK;
+}
+
+pdg_status pdg_prune_mask(const pdg_grid_desc *d, int32_t stacks, int32_t span, const float *points,
+                          int64_t n, int32_t halo, uint32_t *mask, int64_t *active, void *ws,
+                          size_t ws_bytes, hipStream_t stream) {
+  PDG_TRY(check_grid(d));
+  if (stacks < 0 || span < 1 || n < 0 || n >= (1ll << 31) || halo < 0 || halo > 16) {
+    set_error("prune: stacks >= 0, span >= 1, 0 <= n < 2^31 and 0 <= halo <= 16 required");
+    return PDG_EINVAL;
+  }
+  const long long frames = (long long)stacks + span - 1;
+  if (frames > 65535) {
+    set_error("prune: %lld frames exceed the grid's 65535", frames);
+    return PDG_EINVAL;
+  }
+  if (stacks == 0) return PDG_OK;
+  PDG_TRY(need(mask, "mask"));
+  if (n > 0) PDG_TRY(need(points, "points"));
+  const GridDev g = make_grid(*d);
+  PDG_TRY(need_ws(ws, ws_bytes, prune_bytes(g, stacks)));
+  return launch_prune_mask(g, stacks, span, points, n, halo, mask, (long long *)active, ws,
+                           stream);
+}
+
+pdg_status pdg_precondition_pruned(const pdg_grid_desc *d, const float *lambda, float *g,
+                                   int32_t batch, int32_t iters, double tol, const uint32_t *mask,
+                                   void *ws, size_t ws_bytes, hipStream_t stream) {
+  PDG_TRY(check_precond_args(d, lambda, batch, PDG_PRECOND_CG, iters, tol));
+  if (batch == 0) return PDG_OK;
+  PDG_TRY(need(g, "g"));
+  PDG_TRY(need(mask, "mask"));
+  size_t nb = 0;
+  PDG_TRY(pdg_precondition_workspace(d, batch, PDG_PRECOND_CG, &nb));
+  PDG_TRY(need_ws(ws, ws_bytes, nb));
+  const GridDev gd = make_grid(*d);
+  const bool aligned16 = ((uintptr_t)g & 15) == 0;
+  CGPlanDev p = cg_plan(gd, batch, lambda, iters, tol, aligned16);
+  cg_set_mask(p, gd, mask);
+  return run_cg(p, g, gd.size * batch, ws, stream);
+}
+
 pdg_status pdg_adam(const pdg_grid_desc *d, int32_t batch, const float *lr, float beta1,
                     float beta2, float eps, int32_t step, float *theta, float *m, float *v,
                     const float *g, hipStream_t stream) {
@@ -1163,6 +1224,10 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);
   if (s == PDG_OK && p->dctws) s = dct_basis(p->g, p->dctws, stream);
+  // pruned grids: pruned cells hold zero and keep zero moments
+  if (pd->prune_mask)
+    for (float *buf : {pd->params, pd->adam_m, pd->adam_v})
+      if (s == PDG_OK) s = launch_mask_apply(p->g, (int)T, pd->prune_mask, buf, stream);
   if (s == PDG_OK) s = launch_set_int(p->epoch, 0, stream);
   if (s != PDG_OK) {
     delete p;

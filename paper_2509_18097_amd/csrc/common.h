@@ -315,12 +315,15 @@ struct CGLevel {             // one level of every stack in a preconditioner cal
   int tps;                   // tiles per system
   int sys0;                  // first system (level-major: level, stack, channel)
   int vec;                   // float4 path usable (R % 4 == 0, aligned)
+  long long moff;            // word offset of the level in a stack's pruning mask
 };
 struct CGPlanDev {
   int levels;
   int batch;
   long long stack;           // floats per stack
   int ntiles, nsys;
+  const uint32_t *mask;      // pruning masks [batch][mstack] words, or null (box)
+  long long mstack;          // mask words per stack
   CGLevel lv[PDG_MAX_LEVELS];
 };
 CGPlanDev cg_make_plan(const GridDev &g, int batch, const float *lam, const int *iters,
@@ -384,6 +387,22 @@ int cheb_iterations(double kappa, double tol);
 pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, float lambda,
                                     int max_degree, int iters, const float *g, float *out,
                                     void *ws, hipStream_t st);
+
+// prune.hip: pruned grids.  A stack's mask holds one bit per cell of every
+// level (levels packed in order, mask_words(R) words each; bit c of a level is
+// bit c & 31 of its word c >> 5, c = (z R + y) R + x).
+__host__ __device__ inline long long mask_words(int R) { return ((long long)R * R * R + 31) / 32; }
+long long mask_stack_words(const GridDev &g);
+size_t prune_bytes(const GridDev &g, int stacks);
+pdg_status launch_prune_mask(const GridDev &g, int stacks, int span, const float *points,
+                             long long n, int halo, uint32_t *mask, long long *active, void *ws,
+                             hipStream_t st);
+// values of pruned cells (every channel) of `batch` stacks set to zero
+pdg_status launch_mask_apply(const GridDev &g, int batch, const uint32_t *mask, float *data,
+                             hipStream_t st);
+// plan fields for masked conjugate gradients (run_cg then solves on the
+// graphs the kept cells induce)
+void cg_set_mask(CGPlanDev &p, const GridDev &g, const uint32_t *mask);
 
 // keyframe.hip: Eq. 19-20 (occupied 128^3 voxels per frame, weighted argmax)
 size_t keyframe_bytes(int frames);

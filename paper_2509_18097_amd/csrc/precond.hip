@@ -23,6 +23,14 @@
 //   reduce  : beta = rr' / rr.
 // HBM traffic per cell and iteration: A reads r, p and writes p' (12 B);
 // B reads p', x, r and writes x, r (20 B).
+//
+// Pruned grids (Sec. 3.6): with a mask the operator is I + lam L_S, L_S the
+// Laplacian of the graph the kept cells induce.  The residual starts at zero
+// on pruned cells and A p' is zero there, so r, p and x stay zero on them; a
+// kept cell sees a pruned neighbour as missing (the neighbour's value is
+// replaced by the cell's own, difference 0, selected and never multiplied, so
+// stale values never enter).  Tiles without a kept cell return at once: their
+// p buffers are never written, and no kept cell reads them.
 #include "common.h"
 
 namespace pdg {
@@ -43,6 +51,7 @@ struct Loc {                   // a workgroup's tile
   int sys;                     // global system index
   int lt;                      // tile within the system
   long long base;              // float offset of the system
+  const uint32_t *mk;          // the level's mask words of the system's stack
 };
 
 __device__ __forceinline__ bool locate(const CGPlanDev &P, int tile, Loc &o) {
@@ -57,6 +66,7 @@ __device__ __forceinline__ bool locate(const CGPlanDev &P, int tile, Loc &o) {
       o.lt = local - s * L.tps;
       const long long r3 = (long long)L.R * L.R * L.R;
       o.base = (long long)(s / 3) * P.stack + L.off + (long long)(s % 3) * r3;
+      o.mk = P.mask ? P.mask + (long long)(s / 3) * P.mstack + L.moff : nullptr;
       return true;
     }
   }
@@ -102,6 +112,51 @@ __device__ __forceinline__ double dot4(float4 a, float4 b) {
   return (double)a.x * b.x + (double)a.y * b.y + (double)a.z * b.z + (double)a.w * b.w;
 }
 
+// kept-cell bits (pruned grids)
+__device__ __forceinline__ unsigned bit1(const uint32_t *mk, int c) { return (mk[c >> 5] >> (c & 31)) & 1u; }
+// the four bits of cells q .. q + 3 (q % 4 == 0: one word)
+__device__ __forceinline__ unsigned nib4(const uint32_t *mk, int q) { return (mk[q >> 5] >> (q & 31)) & 15u; }
+
+// Laplacian part on the induced graph: as lap4, with a neighbour whose bit is
+// clear (pruned, or outside the box) treated as missing.  xl/xr: bits of the
+// x-neighbours of the quad's ends; own, ym..zp: four-bit masks.
+__device__ __forceinline__ float4 lap4m(float4 c, float xl, float xr, float4 ym, float4 yp,
+                                        float4 zm, float4 zp, unsigned own, unsigned bl,
+                                        unsigned br, unsigned bym, unsigned byp, unsigned bzm,
+                                        unsigned bzp) {
+  auto d = [](float self, unsigned on, float nb) { return on ? self - nb : 0.0f; };
+  float4 s;
+  s.x = d(c.x, bl, xl) + d(c.x, own & 2u, c.y) + d(c.x, bym & 1u, ym.x) + d(c.x, byp & 1u, yp.x) +
+        d(c.x, bzm & 1u, zm.x) + d(c.x, bzp & 1u, zp.x);
+  s.y = d(c.y, own & 1u, c.x) + d(c.y, own & 4u, c.z) + d(c.y, bym & 2u, ym.y) +
+        d(c.y, byp & 2u, yp.y) + d(c.y, bzm & 2u, zm.y) + d(c.y, bzp & 2u, zp.y);
+  s.z = d(c.z, own & 2u, c.y) + d(c.z, own & 8u, c.w) + d(c.z, bym & 4u, ym.z) +
+        d(c.z, byp & 4u, yp.z) + d(c.z, bzm & 4u, zm.z) + d(c.z, bzp & 4u, zp.z);
+  s.w = d(c.w, own & 4u, c.z) + d(c.w, br, xr) + d(c.w, bym & 8u, ym.w) + d(c.w, byp & 8u, yp.w) +
+        d(c.w, bzm & 8u, zm.w) + d(c.w, bzp & 8u, zp.w);
+  return s;
+}
+
+// A p on the induced graph (zero on pruned cells)
+__device__ __forceinline__ float4 apply4m(float4 c, float lam, float4 lap, unsigned own) {
+  return make_float4((own & 1u) ? c.x + lam * lap.x : 0.0f, (own & 2u) ? c.y + lam * lap.y : 0.0f,
+                     (own & 4u) ? c.z + lam * lap.z : 0.0f, (own & 8u) ? c.w + lam * lap.w : 0.0f);
+}
+
+__device__ __forceinline__ float4 keep4(float4 c, unsigned own) {
+  return make_float4((own & 1u) ? c.x : 0.0f, (own & 2u) ? c.y : 0.0f, (own & 4u) ? c.z : 0.0f,
+                     (own & 8u) ? c.w : 0.0f);
+}
+
+// true when the workgroup's tile holds a kept cell (block-uniform)
+__device__ __forceinline__ bool tile_kept(const uint32_t *mk, int lt, int n) {
+  const int w0 = lt * (kTileCells / 32);
+  const int nw = (n + 31) / 32;
+  const int w = w0 + (int)threadIdx.x;
+  const uint32_t v = (threadIdx.x < kTileCells / 32 && w < nw) ? mk[w] : 0u;
+  return __syncthreads_or(v != 0u) != 0;
+}
+
 // generic cell coordinates (any R)
 __device__ __forceinline__ void coords(const CGLevel &L, int c, int &x, int &y, int &z) {
   if (L.shift >= 0) {
@@ -130,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CGPlanDev P, int ntil
   for (int k = 0; k < 4 * kQuads; ++k) {
     const int c = o.lt * kTileCells + k * kThreads + threadIdx.x;
     if (c < n) {
-      const float v = src[o.base + c];
+      const float v = (o.mk && !bit1(o.mk, c)) ? 0.0f : src[o.base + c];
       r[o.base + c] = v;
       x[o.base + c] = 0.f;
       acc += (double)v * v;
@@ -140,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CGPlanDev P, int ntil
   if (threadIdx.x == 0) rr_part[tile] = t;
 }
 
+template <bool MASK>
 __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
                                                         CGState s, const float *__restrict__ pin,
                                                         float *__restrict__ pout) {
@@ -151,6 +207,10 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
   if (k >= L.iters) return;
   const int R = L.R;
   const int n = R * R * R;
+  if (MASK && !tile_kept(o.mk, o.lt, n)) {
+    if (threadIdx.x == 0) s.pq_part[tile] = 0.0;
+    return;
+  }
   const float beta = k == 0 ? 0.f : (float)s.beta[o.sys];
   const float lam = L.lam;
   const float *rr = s.r + o.base;
@@ -166,32 +226,50 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
       coords(L, q, x0, y, z);
       auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
       auto pn4 = [&](int i) { return k == 0 ? ld4(rr + i) : axpy4(ld4(rr + i), beta, ld4(pp + i)); };
-      const float4 c = pn4(q);
+      float4 c = pn4(q);
       const float xl = x0 > 0 ? pn(q - 1) : c.x;
       const float xr = x0 + 4 < R ? pn(q + 4) : c.w;
       const float4 ym = y > 0 ? pn4(q - R) : c;
       const float4 yp = y < R - 1 ? pn4(q + R) : c;
       const float4 zm = z > 0 ? pn4(q - RR) : c;
       const float4 zp = z < R - 1 ? pn4(q + RR) : c;
-      const float4 ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
+      float4 ap;
+      if (MASK) {
+        const unsigned own = nib4(o.mk, q);
+        const unsigned bl = x0 > 0 ? bit1(o.mk, q - 1) : 0u;
+        const unsigned br = x0 + 4 < R ? bit1(o.mk, q + 4) : 0u;
+        const unsigned bym = y > 0 ? nib4(o.mk, q - R) : 0u;
+        const unsigned byp = y < R - 1 ? nib4(o.mk, q + R) : 0u;
+        const unsigned bzm = z > 0 ? nib4(o.mk, q - RR) : 0u;
+        const unsigned bzp = z < R - 1 ? nib4(o.mk, q + RR) : 0u;
+        c = keep4(c, own);
+        ap = apply4m(c, lam, lap4m(c, xl, xr, ym, yp, zm, zp, own, bl, br, bym, byp, bzm, bzp), own);
+      } else {
+        ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
+      }
       st4(po + q, c);
       acc += dot4(c, ap);
     }
   } else {
     auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
+    auto on = [&](int i) { return !MASK || bit1(o.mk, i) != 0u; };
     for (int e = 0; e < 4 * kQuads; ++e) {
       const int c = o.lt * kTileCells + e * kThreads + threadIdx.x;
       if (c >= n) continue;
+      if (MASK && !on(c)) {
+        po[c] = 0.f;
+        continue;
+      }
       int x, y, z;
       coords(L, c, x, y, z);
       const float v = pn(c);
       float sm = 0.f;
-      if (x > 0) sm += v - pn(c - 1);
-      if (x < R - 1) sm += v - pn(c + 1);
-      if (y > 0) sm += v - pn(c - R);
-      if (y < R - 1) sm += v - pn(c + R);
-      if (z > 0) sm += v - pn(c - R * R);
-      if (z < R - 1) sm += v - pn(c + R * R);
+      if (x > 0 && on(c - 1)) sm += v - pn(c - 1);
+      if (x < R - 1 && on(c + 1)) sm += v - pn(c + 1);
+      if (y > 0 && on(c - R)) sm += v - pn(c - R);
+      if (y < R - 1 && on(c + R)) sm += v - pn(c + R);
+      if (z > 0 && on(c - R * R)) sm += v - pn(c - R * R);
+      if (z < R - 1 && on(c + R * R)) sm += v - pn(c + R * R);
       po[c] = v;
       acc += (double)v * (double)(v + lam * sm);
     }
@@ -200,6 +278,7 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
   if (threadIdx.x == 0) s.pq_part[tile] = t;
 }
 
+template <bool MASK>
 __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
                                                         CGState s, const float *__restrict__ pcur) {
   __shared__ double sh[kThreads / 64];
@@ -210,6 +289,10 @@ __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int 
   if (k >= L.iters) return;
   const int R = L.R;
   const int n = R * R * R;
+  if (MASK && !tile_kept(o.mk, o.lt, n)) {
+    if (threadIdx.x == 0) s.rr_part[tile] = 0.0;
+    return;
+  }
   const float alpha = (float)s.alpha[o.sys];
   const float lam = L.lam;
   const float *pp = pcur + o.base;
@@ -230,26 +313,40 @@ __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int 
       const float4 yp = y < R - 1 ? ld4(pp + q + R) : c;
       const float4 zm = z > 0 ? ld4(pp + q - RR) : c;
       const float4 zp = z < R - 1 ? ld4(pp + q + RR) : c;
-      const float4 ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
+      float4 ap;
+      if (MASK) {
+        const unsigned own = nib4(o.mk, q);
+        const unsigned bl = x0 > 0 ? bit1(o.mk, q - 1) : 0u;
+        const unsigned br = x0 + 4 < R ? bit1(o.mk, q + 4) : 0u;
+        const unsigned bym = y > 0 ? nib4(o.mk, q - R) : 0u;
+        const unsigned byp = y < R - 1 ? nib4(o.mk, q + R) : 0u;
+        const unsigned bzm = z > 0 ? nib4(o.mk, q - RR) : 0u;
+        const unsigned bzp = z < R - 1 ? nib4(o.mk, q + RR) : 0u;
+        ap = apply4m(c, lam, lap4m(c, xl, xr, ym, yp, zm, zp, own, bl, br, bym, byp, bzm, bzp), own);
+      } else {
+        ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
+      }
       st4(xx + q, axpy4(ld4(xx + q), alpha, c));
       const float4 rn = axpy4(ld4(rr + q), -alpha, ap);
       st4(rr + q, rn);
       acc += dot4(rn, rn);
     }
   } else {
+    auto on = [&](int i) { return !MASK || bit1(o.mk, i) != 0u; };
     for (int e = 0; e < 4 * kQuads; ++e) {
       const int c = o.lt * kTileCells + e * kThreads + threadIdx.x;
       if (c >= n) continue;
+      if (MASK && !on(c)) continue;
       int x, y, z;
       coords(L, c, x, y, z);
       const float v = pp[c];
       float sm = 0.f;
-      if (x > 0) sm += v - pp[c - 1];
-      if (x < R - 1) sm += v - pp[c + 1];
-      if (y > 0) sm += v - pp[c - R];
-      if (y < R - 1) sm += v - pp[c + R];
-      if (z > 0) sm += v - pp[c - R * R];
-      if (z < R - 1) sm += v - pp[c + R * R];
+      if (x > 0 && on(c - 1)) sm += v - pp[c - 1];
+      if (x < R - 1 && on(c + 1)) sm += v - pp[c + 1];
+      if (y > 0 && on(c - R)) sm += v - pp[c - R];
+      if (y < R - 1 && on(c + R)) sm += v - pp[c + R];
+      if (z > 0 && on(c - R * R)) sm += v - pp[c - R * R];
+      if (z < R - 1 && on(c + R * R)) sm += v - pp[c + R * R];
       xx[c] += alpha * v;
       const float rn = rr[c] - alpha * (v + lam * sm);
       rr[c] = rn;
@@ -373,13 +470,21 @@ pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipS
       const int sys_hi = P.lv[hi].sys0 + P.batch * 3;
       float *pin = (k & 1) ? t.p1 : t.p0;
       float *pout = (k & 1) ? t.p0 : t.p1;
-      cg_a_kernel<<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(P, k, tile_lo, tile_hi - tile_lo,
-                                                                  t, pin, pout);
+      if (P.mask)
+        cg_a_kernel<true><<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(
+            P, k, tile_lo, tile_hi - tile_lo, t, pin, pout);
+      else
+        cg_a_kernel<false><<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(
+            P, k, tile_lo, tile_hi - tile_lo, t, pin, pout);
       PDG_TRY(launched("cg_a"));
       cg_reduce_kernel<<<sys_hi - sys_lo, kThreads, 0, st>>>(P, k, 1, sys_lo, t);
       PDG_TRY(launched("cg_reduce"));
-      cg_b_kernel<<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(P, k, tile_lo, tile_hi - tile_lo,
-                                                                  t, pout);
+      if (P.mask)
+        cg_b_kernel<true><<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(
+            P, k, tile_lo, tile_hi - tile_lo, t, pout);
+      else
+        cg_b_kernel<false><<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(
+            P, k, tile_lo, tile_hi - tile_lo, t, pout);
       PDG_TRY(launched("cg_b"));
       cg_reduce_kernel<<<sys_hi - sys_lo, kThreads, 0, st>>>(P, k, 2, sys_lo, t);
       PDG_TRY(launched("cg_reduce"));

@@ -69,7 +69,11 @@ class Problem:
                  edges: torch.Tensor | None = None, hp: HyperParams | None = None,
                  chamfer_mode: str = "fp32", precond: str = "cg", cg_iters: int = 0,
                  cg_tol: float = 1e-7, level_scale: float | None = None,
-                 params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None):
+                 params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
+                 prune_mask: torch.Tensor | None = None, prune_halo: int | None = None):
+        """prune_mask (T, words) int32 as ``prune_mask`` writes it, or prune_halo
+        (the paper: 3) to build it from each transition's two frames, makes the
+        grids pruned (Sec. 3.6; conjugate-gradient preconditioner only)."""
         self.hp = hp or HyperParams()
         self.res = tuple(int(r) for r in res)
         self.chamfer_mode = chamfer_mode
@@ -109,6 +113,16 @@ class Problem:
         d.precond_method = L.PRECOND_METHODS[precond]
         d.cg_iters = int(cg_iters)
         d.cg_tol = float(cg_tol)
+        if prune_mask is None and prune_halo is not None:
+            with torch.cuda.stream(stream or torch.cuda.current_stream()):
+                prune_mask, self.kept_cells = L.prune_mask(self.points, self.res, 2,
+                                                           int(prune_halo))
+        self.prune_mask = None
+        if prune_mask is not None:
+            self.prune_mask = L._dev(prune_mask, torch.int32, "prune_mask")
+            if prune_mask.numel() != self.T * L.prune_mask_words(self.res):
+                raise ValueError("prune_mask must hold T stacks of prune_mask_words(res) words")
+            d.prune_mask = L._ptr(self.prune_mask)
         d.params = L._ptr(self.params)
         d.adam_m = L._ptr(self.m)
         d.adam_v = L._ptr(self.v)

@@ -74,6 +74,30 @@ def test_argument_errors_on_host():
     assert lib.pdg_precondition_workspace(ctypes.byref(d), 2, 0, ctypes.byref(nb)) == L.OK
 
 
+def test_prune_validation_on_host():
+    lib = L.lib()
+    d = L.grid_desc((1, 3, 8, 32))
+    w = ctypes.c_int64()
+    assert lib.pdg_prune_mask_words(ctypes.byref(d), ctypes.byref(w)) == L.OK
+    assert w.value == 1 + 1 + 16 + 1024 == L.prune_mask_words((1, 3, 8, 32))
+    nb = ctypes.c_size_t()
+    assert lib.pdg_prune_workspace(ctypes.byref(d), 3, ctypes.byref(nb)) == L.OK
+    assert nb.value >= 2 * 3 * w.value * 4
+    # halo out of range, span < 1, NULL mask, too small a workspace: nothing runs
+    assert lib.pdg_prune_mask(ctypes.byref(d), 2, 2, None, 0, 17, None, None, None, 0, None) == L.EINVAL
+    assert lib.pdg_prune_mask(ctypes.byref(d), 2, 0, None, 0, 3, None, None, None, 0, None) == L.EINVAL
+    assert lib.pdg_prune_mask(ctypes.byref(d), 2, 2, None, 0, 3, None, None, None, 0, None) == L.EINVAL
+    assert lib.pdg_prune_mask(ctypes.byref(d), 2, 2, None, 0, 3, 256, None, 256, 8, None) == L.ENOMEM
+    assert lib.pdg_prune_mask(ctypes.byref(d), 0, 2, None, 0, 3, None, None, None, 0, None) == L.OK
+    lam = (ctypes.c_float * 16)(0.25, 0.375, 0.5, 0.75)
+    assert lib.pdg_precondition_pruned(ctypes.byref(d), lam, 256, 1, 0, 1e-7, None, None, 0,
+                                       None) == L.EINVAL
+    assert lib.pdg_precondition_pruned(ctypes.byref(d), lam, 256, 1, 0, 1e-7, 256, 256, 8,
+                                       None) == L.ENOMEM
+    d6 = L.grid_desc((4, 8), channels=6)
+    assert lib.pdg_prune_mask_words(ctypes.byref(d6), ctypes.byref(w)) == L.EUNSUPPORTED
+
+
 def test_problem_validation_on_host():
     lib = L.lib()
     pd = L.ProblemDesc()
@@ -102,6 +126,13 @@ def test_problem_validation_on_host():
     pd.workspace_bytes = 16
     pd.workspace = 256
     assert lib.pdg_problem_create(ctypes.byref(pd), None, ctypes.byref(h)) == L.ENOMEM
+    # pruned grids need the conjugate-gradient preconditioner
+    pd.prune_mask = 256
+    pd.precond_method = L.PRECOND_METHODS["dct"]
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EUNSUPPORTED
+    assert "pruned" in L.last_error()
+    pd.precond_method = L.PRECOND_METHODS["cg"]
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.OK
 
 
 def test_missing_library_fails_loudly(monkeypatch):
