@@ -73,12 +73,16 @@ def parse():
                     help="bf16: matrix-core screen + exact re-rank (same indices as fp32)")
     ap.add_argument("--precond", default="dct", choices=("cg", "dct"),
                     help="dct: exact spectral solve; cg: conjugate gradients, float64 dots")
+    ap.add_argument("--prune", type=int, default=None, metavar="HALO",
+                    help="pruned grids for the timed step: kept cells = occupied + HALO-cell "
+                         "cube (the paper: 3); needs --precond cg")
     ap.add_argument("--variants", default="fp32:cg,bf16:cg,fp32:dct",
                     help="other chamfer:precond forms to time on the same GPU ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
-    ap.add_argument("--no-cayley", action="store_true",
-                    help="skip the six-channel (Cayley) deform timing")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings beside the step (six-channel deform, keyframe, "
+                         "mesh preconditioner, pruned grids)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serve", type=int, default=24, metavar="R",
@@ -180,16 +184,20 @@ def cg_bytes(prob):
     """Algorithmic HBM bytes of one preconditioner stage: the copy of the raw
     gradient (8 B/value), and per solve an init pass (12 B/value) plus per
     iteration 12 B (kernel A: read r, p; write p') + 20 B (kernel B: read p',
-    x, r; write x, r) per value of every system still iterating."""
+    x, r; write x, r) per value of every system still iterating.  With pruned
+    grids the iterations count only the kept cells (what a solve on the kept
+    set alone must move)."""
     T = prob.T
     total = 8 * T * prob.P
+    kept = getattr(prob, "kept_cells", None) if prob.prune_mask is not None else None
     for l, r in enumerate(prob.res):
         lam = prob.hp.lambda0 * prob.hp.lambda_growth ** l
         kappa = 1.0 + 12.0 * lam         # a-priori CG count (as the library computes it)
         rho = (math.sqrt(kappa) - 1.0) / (math.sqrt(kappa) + 1.0)
         k = math.ceil(math.log(2.0 / 1e-7) / -math.log(rho))
         cells = T * 3 * r ** 3
-        total += 2 * (12 * cells + k * 32 * cells)
+        it_cells = cells if kept is None else 3 * int(kept[:, l].sum().item())
+        total += 2 * (12 * cells + k * 32 * it_cells)
     return total
 
 
@@ -240,7 +248,7 @@ def roofline(prob, stages, chamfer, precond):
         pre = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
                "kernel": "cg_a_kernel/cg_b_kernel (+ reductions)", "bytes_per_stage": b,
-               "stage_ms": round(pre_ms, 4)}
+               "stage_ms": round(pre_ms, 4), "pruned": prob.prune_mask is not None}
     return nn, pre
 
 
@@ -472,7 +480,9 @@ def main():
         print(json.dumps({"metric": METRIC, "serving": serve(args.serve, args.chamfer, args.precond,
                                                                  args.serve_slots)}))
         return
-    seq, prob = make_problem(args.subdiv, args.chamfer, args.precond)
+    if args.prune is not None and args.precond != "cg":
+        sys.exit("--prune needs --precond cg (the DCT solve needs the full box)")
+    seq, prob = make_problem(args.subdiv, args.chamfer, args.precond, args.prune)
     torch.cuda.synchronize()
     ms, wall = time_steps(prob, args.steps, args.warmup)
     value = 1000.0 / ms
@@ -497,7 +507,8 @@ def main():
                                f"{'/'.join(str(r) for r in RES)}^3 x 3 ch per transition",
                    "frames": FRAMES, "points_per_frame": NPTS, "template_verts": prob.V,
                    "template_edges": prob.E, "grid_res": list(RES), "chamfer": args.chamfer,
-                   "precond": args.precond, "graph_replay": True},
+                   "precond": args.precond, "graph_replay": True,
+                   **({"prune_halo": args.prune} if args.prune is not None else {})},
         "loss_last_step": terms["loss"],
     }
     if stages:
@@ -519,7 +530,7 @@ def main():
         torch.cuda.empty_cache()
     if variants:
         result["variants"] = variants
-    if not args.no_cayley:
+    if not args.no_extras:
         result["cayley6"] = time_cayley6()
         result["keyframe"] = time_keyframe(seq)
         result["mesh_precond"] = time_mesh_precond(seq)
