@@ -10,8 +10,8 @@ Follows the paper's Sec. 3.3-3.6:
   with delta = 1 - sqrt(e / e_max) (Eq. 15-16) and
   cd_max = max_t CD_R(sg(P^_t), P_t) (Eq. 17);
 * L_iso = 1/(T |E|) sum_t sum_(i,j) | |x_i,t - x_j,t| - |x_i,t-1 - x_j,t-1| | (Eq. 18);
-* L = L_transform + w_iso L_iso, w_iso = 250 (Eq. 9, without L_mesh: the
-  initial mesh is held fixed on this path);
+* L = L_transform + w_iso L_iso, w_iso = 250 (Eq. 9), plus L_mesh =
+  CD_R(X_0, P_0) (Eq. 10) when X_0 is optimised (``x0_state``);
 * gradients preconditioned per level by (I + lambda_l L_l)^{-2} (Eq. 3) and
   applied by Adam with a per-level learning rate (Sec. 3.6).
 
@@ -35,6 +35,7 @@ import numpy as np
 
 from . import adam as _adam
 from . import chamfer as _ch
+from . import mesh as _mesh
 from . import precond as _pc
 from . import prune as _pr
 from . import warp as _wp
@@ -53,6 +54,8 @@ class Hyper:
     eps: float = 1e-8
     e_max: int = 50
     level_scale: float | None = None     # 1/L (Eq. 1) when None
+    mesh_lambda: float = 16.0     # Sec. 3.6: X_0's preconditioner weight
+    mesh_lr: float = 1e-4         # Sec. 3.6: X_0's learning rate
 
     def schedule(self, levels: int):
         etas = [self.eta0 * self.eta_growth ** l for l in range(levels)]
@@ -118,11 +121,20 @@ class StepResult:
     v: np.ndarray = None
     g_phat: np.ndarray = None         # (T, 3, N) dL/dP^_t
     g_xhat: np.ndarray = None         # (T, 3, V) dL/dX_t (direct terms, frames 1..T)
+    # optimisation of X_0 (Eq. 9-10, Sec. 3.6), when asked for
+    l_mesh: float = 0.0
+    nn0: tuple = None                 # (nn of X_0 in P_0, nn of P_0 in X_0)
+    g_x0: np.ndarray = None           # (3, V) dL_mesh/dX_0
+    pg_x0: np.ndarray = None          # (3, V) (I + mesh_lambda L)^-2 g_x0
+    x0: np.ndarray = None             # (3, V) X_0 after Adam
+    x0_m: np.ndarray = None
+    x0_v: np.ndarray = None
 
 
 def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hyper(),
          phat32=None, xhat32=None, workers: int = 1, precond_method: str = "dct",
-         grad_override=None, pgrad_override=None, masks=None) -> StepResult:
+         grad_override=None, pgrad_override=None, masks=None, x0_state=None,
+         gx0_override=None, pgx0_override=None) -> StepResult:
     """One iteration: warp, Chamfer + isometry losses, gradient, preconditioner, Adam.
 
     points (F, 3, N) float32; template (3, V) float32 or None; edges (2, E);
@@ -135,6 +147,13 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     replace the raw / preconditioned gradient fed to the following stage.
     ``masks`` ([t][level] boolean [r, r, r], see ``prune``) prunes the grids:
     the preconditioner acts on the kept cells only and is zero elsewhere.
+    ``x0_state`` = (m, v), the Adam moments of X_0, optimises X_0 as well:
+    L gains L_mesh = CD_R(X_0, P_0) (Eq. 9-10), whose gradient alone moves X_0
+    (reading: the mesh follows the keyframe's points; the chain's terms are
+    not differentiated with respect to X_0), preconditioned by
+    (I + mesh_lambda L)^-2 with the mesh Laplacian and applied by Adam with
+    mesh_lr (Sec. 3.6).  ``gx0_override`` / ``pgx0_override`` replace the raw /
+    preconditioned X_0 gradient fed to the next stage.
     """
     points = np.asarray(points)
     f = points.shape[0]
@@ -227,4 +246,17 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
             epoch + 1, hp.beta1, hp.beta2, hp.eps)
         off += 3 * rr ** 3
     r.theta, r.m, r.v = th, mm, vv
+    if x0_state is not None and has_tm:
+        x0 = np.asarray(template, np.float32)
+        p0 = points[0]
+        l_ab, l_ba, na, nb = _ch.chamfer(x0, p0, hp.alpha, workers=workers)
+        r.l_mesh = float(l_ab + l_ba)
+        r.loss += r.l_mesh
+        r.nn0 = (na, nb)
+        r.g_x0 = _ch.gradient(x0, p0, na, nb, hp.alpha, 1.0, 1.0)
+        g_in = r.g_x0 if gx0_override is None else np.asarray(gx0_override, np.float64)
+        r.pg_x0 = _mesh.precondition(x0.shape[1], edges, hp.mesh_lambda, g_in)
+        p_in = r.pg_x0 if pgx0_override is None else np.asarray(pgx0_override, np.float64)
+        r.x0, r.x0_m, r.x0_v = _adam.update(x0, x0_state[0], x0_state[1], p_in, hp.mesh_lr,
+                                            epoch + 1, hp.beta1, hp.beta2, hp.eps)
     return r

@@ -175,3 +175,39 @@ def test_step_loss_decreases_on_pair():
         losses.append(r.loss)
         th, m, v = r.theta, r.m, r.v
     assert losses[-1] < 0.8 * losses[0]
+
+
+def test_template_step_pieces():
+    """X_0 optimised (Eq. 9-10, Sec. 3.6): L gains CD_R(X_0, P_0); its gradient
+    by central differences; the mesh preconditioner applied to it; Adam's
+    first step moves every coordinate by -mesh_lr * sign(g) (bias corrections
+    cancel); the paper's mesh constants."""
+    from oracle import mesh as M
+    h = S.Hyper()
+    assert h.mesh_lr == GOLD["mesh_lr"]["value"] and h.mesh_lambda == GOLD["mesh_lambda"]["value"]
+    seq = synth.deforming_sequence(seed=3, frames=3, n=300, subdiv=1)
+    res = (4, 8)
+    T = 2
+    P = 3 * sum(r ** 3 for r in res)
+    z = np.zeros((T, P))
+    x0 = seq.template.astype(np.float32)
+    base = S.step(seq.points, x0, seq.edges, res, z, z, z, 0, h)
+    r = S.step(seq.points, x0, seq.edges, res, z, z, z, 0, h,
+               x0_state=(np.zeros(x0.shape), np.zeros(x0.shape)))
+    la, lb, _, _ = C.chamfer(x0, seq.points[0])
+    assert r.l_mesh == pytest.approx(la + lb, rel=1e-14)
+    assert r.loss == pytest.approx(base.loss + r.l_mesh, rel=1e-14)
+    np.testing.assert_array_equal(r.theta, base.theta)        # the grids' update is unchanged
+    # gradient of L_mesh by central differences (assignment stable at h = 1e-6)
+    x64 = x0.astype(np.float64)
+    for c, i in ((0, 3), (1, 17), (2, 40)):
+        e = np.zeros_like(x64)
+        e[c, i] = 1e-6
+        lp = sum(C.chamfer(x64 + e, seq.points[0])[:2])
+        lm = sum(C.chamfer(x64 - e, seq.points[0])[:2])
+        assert r.g_x0[c, i] == pytest.approx((lp - lm) / 2e-6, rel=1e-5, abs=1e-9)
+    np.testing.assert_allclose(r.pg_x0, M.precondition(x0.shape[1], seq.edges, 16.0, r.g_x0),
+                               rtol=0, atol=1e-15)
+    step = x64 - r.x0
+    expect = h.mesh_lr * r.pg_x0 / (np.abs(r.pg_x0) + h.eps)
+    np.testing.assert_allclose(step, expect, rtol=1e-9, atol=1e-15)
