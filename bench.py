@@ -94,7 +94,7 @@ def parse():
     return ap.parse_args()
 
 
-def make_problem(subdiv, chamfer, precond, prune_halo=None):
+def make_problem(subdiv, chamfer, precond, prune_halo=None, optimize_template=False):
     import torch
     import synth
     from paper_2509_18097_amd.problem import HyperParams, Problem
@@ -102,7 +102,8 @@ def make_problem(subdiv, chamfer, precond, prune_halo=None):
     prob = Problem(torch.from_numpy(seq.points).cuda(), RES,
                    template=torch.from_numpy(seq.template).cuda(),
                    edges=torch.from_numpy(seq.edges).cuda(), hp=HyperParams(e_max=50),
-                   chamfer_mode=chamfer, precond=precond, prune_halo=prune_halo)
+                   chamfer_mode=chamfer, precond=precond, prune_halo=prune_halo,
+                   optimize_template=optimize_template)
     return seq, prob
 
 
@@ -366,6 +367,29 @@ def time_pruned(subdiv, chamfer, steps=6, reps=5):
     return out
 
 
+def time_template(subdiv, chamfer, precond, steps=10, reps=5):
+    """The headline step with X_0 optimised as well (Eq. 9-10, Sec. 3.6): the
+    TEMPLATE stage adds L_mesh = CD_R(X_0, P_0) with its gradient (40,962
+    vertices against 50,000 points), the mesh preconditioner (two Chebyshev
+    solves) and Adam on X_0."""
+    import torch
+    _, prob = make_problem(subdiv, chamfer, precond, optimize_template=True)
+    ms, _ = time_steps(prob, steps, 2)
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        prob.stage("template")
+    b.record(st)
+    torch.cuda.synchronize()
+    out = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1000.0 / ms, 4),
+           "template_stage_ms": round(a.elapsed_time(b) / reps, 4)}
+    prob.close()
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_keyframe(seq, reps=20):
     """Keyframe selection (Sec. 3.5, Eq. 19-20) over the sequence's frames:
     one bit per occupied 128^3 voxel and frame, population counts, the
@@ -535,6 +559,7 @@ def main():
         result["keyframe"] = time_keyframe(seq)
         result["mesh_precond"] = time_mesh_precond(seq)
         result["pruned"] = time_pruned(args.subdiv, args.chamfer)
+        result["template_opt"] = time_template(args.subdiv, args.chamfer, args.precond)
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:

@@ -271,6 +271,8 @@ typedef struct {
   float lambda_growth;  /* 1.5 (+50% per finer level)                         */
   float beta1, beta2, eps;   /* 0.9, 0.999, 1e-8                              */
   int32_t e_max;        /* total epochs for delta = 1 - sqrt(e/e_max) (Eq. 16) */
+  float mesh_lambda;    /* Sec. 3.6, 16: (I + mesh_lambda L)^-2 on X_0's gradient */
+  float mesh_lr;        /* Sec. 3.6, 1e-4: Adam learning rate of X_0            */
 } pdg_hyper;
 
 typedef struct {
@@ -298,6 +300,9 @@ typedef struct {
   float *params;              /* [T][grid_size] theta                         */
   float *adam_m;              /* [T][grid_size]                               */
   float *adam_v;              /* [T][grid_size]                               */
+  float *template_adam_m;     /* [3][V] Adam moments of X_0, or NULL; with    */
+  float *template_adam_v;     /* both set X_0 is optimised too (Eq. 9-10):    */
+                              /* template_verts is then updated in place      */
   void *workspace;            /* >= pdg_problem_workspace() bytes             */
   size_t workspace_bytes;
 } pdg_problem_desc;
@@ -311,8 +316,17 @@ pdg_status pdg_problem_workspace(const pdg_problem_desc *pd, size_t *bytes);
  * `stream`.  *out receives an opaque handle. */
 pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out);
 /* One iteration at 0-based epoch `epoch` (0 <= epoch <= e_max).  loss_terms
- * (device double[8], nullable) receives {L, L_transform, L_iso, cd_max,
- * sum_t CD_R(P^_t,P_t)/T, sum_t w_conf CD_R(X_t,P_t)/T, w_conf(T), epoch}.
+ * (device double[9], nullable) receives {L, L_transform, L_iso, cd_max,
+ * sum_t CD_R(P^_t,P_t)/T, sum_t w_conf CD_R(X_t,P_t)/T, w_conf(T), epoch,
+ * L_mesh} (L_mesh and its share of L are 0 unless X_0 is optimised).
+ * Optimising X_0 (template_adam_m/v set) adds, after the grids' Adam, the
+ * TEMPLATE stage: L_mesh = CD_R(X_0, P_0) (Eq. 10) in the problem's Chamfer
+ * mode, its gradient with respect to X_0, (I + mesh_lambda L)^-2 with the
+ * mesh Laplacian of the edge list (two Chebyshev solves as in
+ * pdg_mesh_precondition, tolerance 1e-7) and Adam with mesh_lr.  X_0 enters
+ * the template chain of the next step; the chain's own terms are not
+ * differentiated with respect to X_0 (the mesh follows the keyframe's
+ * points only).
  * With use_graph != 0 the step is replayed from a HIP graph captured on the
  * first call for this stream.  With the DCT preconditioner the last inverse
  * pass of each 64^3 and 128^3 level applies Adam to the values it computes
@@ -339,7 +353,10 @@ typedef enum {
   PDG_STAGE_SCATTER = 4,  /* transpose of Eq. 1 into the grid gradient          */
   PDG_STAGE_PRECOND = 5,  /* Eq. 3                                              */
   PDG_STAGE_ADAM = 6,     /* Sec. 3.6                                           */
-  PDG_STAGE_PRECOND_ADAM = 7   /* PRECOND then ADAM as in pdg_step              */
+  PDG_STAGE_PRECOND_ADAM = 7,  /* PRECOND then ADAM as in pdg_step             */
+  PDG_STAGE_TEMPLATE = 8  /* Eq. 10 and Sec. 3.6: X_0's loss, gradient, mesh
+                             preconditioner and Adam (only when X_0 is
+                             optimised; PDG_EINVAL otherwise)                  */
 } pdg_stage;
 pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream);
 
@@ -366,15 +383,21 @@ pdg_status pdg_problem_destroy(pdg_problem *p);
  *                                        128^3; see pdg_step)
  *   PDG_BUF_GPHAT  float [T][3][n]   dL/dP^_t
  *   PDG_BUF_GXHAT  float [T][3][V]   direct dL/dX_t (Chamfer + isometry), frames 1..T
- *   PDG_BUF_TERMS  double[8]         the loss terms of pdg_step
+ *   PDG_BUF_TERMS  double[9]         the loss terms of pdg_step
  *   PDG_BUF_LAM    float [T][3][V]   total dL/dX_t after the reverse sweep of Eq. 8
  *   PDG_BUF_SCREEN_TILES uint64[1]   256 x 256 candidate tiles screened by the
  *                  bf16 screen, summed over every step since creation (0 bytes
- *                  for the float32 mode) */
+ *                  for the float32 mode)
+ * When X_0 is optimised (0 bytes otherwise), from the last TEMPLATE stage:
+ *   PDG_BUF_NN0    int32 [V + n]     nn of X_0 in P_0, then nn of P_0 in X_0
+ *   PDG_BUF_LOSS0  double[2]         CD directions X_0->P_0, P_0->X_0
+ *   PDG_BUF_GX0    float [3][V]      dL_mesh/dX_0
+ *   PDG_BUF_PGX0   float [3][V]      (I + mesh_lambda L)^-2 dL_mesh/dX_0 */
 typedef enum {
   PDG_BUF_PHAT = 0, PDG_BUF_XHAT = 1, PDG_BUF_NN = 2, PDG_BUF_LOSSES = 3,
   PDG_BUF_WCONF = 4, PDG_BUF_GRAD = 5, PDG_BUF_PGRAD = 6, PDG_BUF_GPHAT = 7,
-  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9, PDG_BUF_LAM = 10, PDG_BUF_SCREEN_TILES = 11
+  PDG_BUF_GXHAT = 8, PDG_BUF_TERMS = 9, PDG_BUF_LAM = 10, PDG_BUF_SCREEN_TILES = 11,
+  PDG_BUF_NN0 = 12, PDG_BUF_LOSS0 = 13, PDG_BUF_GX0 = 14, PDG_BUF_PGX0 = 15
 } pdg_buffer;
 pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes);
 

@@ -21,9 +21,10 @@ PRECOND_METHODS = {"cg": 0, "dct": 1}
 STAGES = ("warp", "nn", "loss", "grad", "scatter", "precond", "adam")
 # stage ids of pdg_step_stage: the seven stages and "precond_adam" (the last
 # two as pdg_step runs them)
-STAGE_IDS = {**{n: i for i, n in enumerate(STAGES)}, "precond_adam": 7}
+STAGE_IDS = {**{n: i for i, n in enumerate(STAGES)}, "precond_adam": 7, "template": 8}
 BUFFERS = {"phat": 0, "xhat": 1, "nn": 2, "losses": 3, "wconf": 4, "grad": 5, "pgrad": 6,
-           "gphat": 7, "gxhat": 8, "terms": 9, "lam": 10, "screen_tiles": 11}
+           "gphat": 7, "gxhat": 8, "terms": 9, "lam": 10, "screen_tiles": 11, "nn0": 12,
+           "loss0": 13, "gx0": 14, "pgx0": 15}
 
 
 class PdgError(RuntimeError):
@@ -41,7 +42,8 @@ class Hyper(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("w_iso", ctypes.c_float), ("eta0", ctypes.c_float),
                 ("eta_growth", ctypes.c_float), ("lambda0", ctypes.c_float),
                 ("lambda_growth", ctypes.c_float), ("beta1", ctypes.c_float),
-                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("e_max", ctypes.c_int32)]
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("e_max", ctypes.c_int32),
+                ("mesh_lambda", ctypes.c_float), ("mesh_lr", ctypes.c_float)]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -53,6 +55,7 @@ class ProblemDesc(ctypes.Structure):
                 ("cg_tol", ctypes.c_double), ("prune_mask", ctypes.c_void_p),
                 ("params", ctypes.c_void_p),
                 ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("template_adam_m", ctypes.c_void_p), ("template_adam_v", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 

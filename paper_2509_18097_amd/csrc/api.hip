@@ -247,6 +247,76 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
   return w;
 }
 
+// Both directions of the robust Chamfer distance of a (n) and b (m) with the
+// loss and, when ga is set, the gradient with respect to a (the body of
+// pdg_chamfer, on a carved workspace).
+pdg_status enqueue_chamfer(const ChamferWs &w, const float *a, long long n, const float *b,
+                           long long m, double alpha, int mode, const double *dir_weight,
+                           double *loss, int32_t *nn_a, int32_t *nn_b, float *ga,
+                           hipStream_t stream) {
+  NNJob jobs[2];
+  memset(jobs, 0, sizeof jobs);
+  jobs[0].q = a;
+  jobs[0].c = b;
+  jobs[0].nq = (int)n;
+  jobs[0].nc = (int)m;
+  jobs[0].nn = nn_a;
+  jobs[1].q = b;
+  jobs[1].c = a;
+  jobs[1].nq = (int)m;
+  jobs[1].nc = (int)n;
+  jobs[1].nn = nn_b;
+  ChSeg seg;
+  memset(&seg, 0, sizeof seg);
+  seg.a = a;
+  seg.b = b;
+  seg.n = (int)n;
+  seg.m = (int)m;
+  seg.nn_a = nn_a;
+  seg.nn_b = nn_b;
+  seg.ga = ga;
+  seg.a_base = 0;
+  const unsigned bb = 0;
+  const double ones[2] = {1.0, 1.0};
+  PDG_TRY(upload_small(w.jobs, jobs, sizeof jobs, stream));
+  PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
+  PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
+  PDG_TRY(upload_small(w.w_default, ones, sizeof ones, stream));
+  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+    ScreenSet ss[2];
+    ScreenJob sj[2];
+    memset(ss, 0, sizeof ss);
+    memset(sj, 0, sizeof sj);
+    // Morton order of both sets (the sorted index arrays are the permutations)
+    PDG_TRY(launch_morton(a, n, (int)n, w.keys, w.perm_a, stream));
+    PDG_TRY(radix_sort(w.keys, w.perm_a, n, 30, w.sort, stream));
+    PDG_TRY(launch_morton(b, m, (int)m, w.keys, w.perm_b, stream));
+    PDG_TRY(radix_sort(w.keys, w.perm_b, m, 30, w.sort, stream));
+    ss[0] = screen_set(a, n, (const int *)w.perm_a, w.pack_a, w.coords_a, w.boxes_a, w.maxnorm);
+    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b,
+                       w.maxnorm + kMaxnormStride);
+    sj[0] = screen_job(ss[0], ss[1], nn_a, nullptr);
+    sj[1] = screen_job(ss[1], ss[0], nn_b, nullptr);
+    PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
+    PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
+    PDG_TRY(launch_fill((float *)w.maxnorm, 2 * kMaxnormStride, 0.f, stream));
+    PDG_TRY(launch_screen_pack(w.ssets, 2, (int)(n > m ? n : m), stream));
+    PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
+  } else {
+    PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
+  }
+  PDG_TRY(launch_chamfer_loss(w.segs, 1, alpha, w.partials, loss, stream));
+  if (ga) {
+    const double *dw = dir_weight ? dir_weight : w.w_default;
+    PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dw, stream));
+    PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
+    PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
+    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha, dw,
+                                       w.rpart, stream));
+  }
+  return PDG_OK;
+}
+
 // ---------------------------------------------------------- precondition --
 int cg_count(float lam, double tol) {
   const double kappa = 1.0 + 12.0 * (double)lam;
@@ -352,6 +422,14 @@ struct pdg_problem {
   CGPlanDev cg;
   AdamLevels adam;
   unsigned fused = 0u;                             // levels whose Adam ran in the preconditioner
+  // optimisation of X_0 (Eq. 10, Sec. 3.6)
+  bool opt_x0 = false;
+  float *gx0 = nullptr, *pgx0 = nullptr;           // dL_mesh/dX_0, preconditioned
+  int *nn0 = nullptr;                              // [V + N]
+  double *loss0 = nullptr;                         // [2]
+  ChamferWs cw0;                                   // Chamfer workspace of (X_0, P_0)
+  void *meshws = nullptr;
+  int max_degree = 0, mesh_iters = 0;
   size_t ws_used = 0;
   // graph replay
   hipStream_t cap = nullptr;
@@ -400,6 +478,13 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   float lam[PDG_MAX_LEVELS];
   for (int l = 0; l < pd->grid.levels; ++l) lam[l] = pd->hp.lambda0 * powf(pd->hp.lambda_growth, (float)l);
   PDG_TRY(check_precond_args(&pd->grid, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
+  if ((pd->template_adam_m || pd->template_adam_v) &&
+      (!pd->template_adam_m || !pd->template_adam_v || pd->verts < 1 ||
+       !(pd->hp.mesh_lambda >= 0.f) || !isfinite(pd->hp.mesh_lambda) || !(pd->hp.mesh_lr > 0.f))) {
+    set_error("optimising X_0 needs both template Adam moments, verts >= 1, mesh_lambda >= 0 "
+              "and mesh_lr > 0");
+    return PDG_EINVAL;
+  }
   if (pd->prune_mask && pd->precond_method != PDG_PRECOND_CG) {
     set_error("pruned grids need the conjugate-gradient preconditioner");
     return PDG_EUNSUPPORTED;
@@ -430,7 +515,7 @@ void layout(pdg_problem &p, Carve &c) {
   p.losses = c.take<double>(4 * T);
   p.w = c.take<double>(4 * T);
   p.wconf = c.take<double>(T);
-  p.terms = c.take<double>(8);
+  p.terms = c.take<double>(kTerms);
   p.partials = c.take<double>(4 * T * kLossBlocks);
   p.iso_partials = c.take<double>(kIsoBlocks);
   p.grad = c.take<float>(T * P);
@@ -464,6 +549,14 @@ void layout(pdg_problem &p, Carve &c) {
   if (p.nrev > smax) smax = p.nrev;
   if (2 * E > smax) smax = 2 * E;
   p.sort = c.take<char>((long long)radix_sort_bytes(smax));
+  if (p.opt_x0) {
+    p.gx0 = c.take<float>(3 * V);
+    p.pgx0 = c.take<float>(3 * V);
+    p.nn0 = c.take<int>(V + N);
+    p.loss0 = c.take<double>(2);
+    p.cw0 = chamfer_layout(c, V, N, p.d.chamfer_mode);
+    p.meshws = c.take<char>((long long)mesh_precond_bytes(V, E));
+  }
   p.nseg = (int)(p.has_tm ? 2 * T : T);
   p.njobs = 2 * p.nseg;
   p.jobs = c.take<NNJob>(p.njobs);
@@ -500,6 +593,7 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   p.E = pd.verts > 0 ? pd.n_edges : 0;
   p.P = p.g.size;
   p.has_tm = p.V > 0;
+  p.opt_x0 = p.has_tm && pd.template_adam_m && pd.template_adam_v;
   float *lam = p.lambda_l;
   p.adam.levels = p.g.levels;
   for (int l = 0; l < p.g.levels; ++l) {
@@ -623,6 +717,27 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
     case PDG_STAGE_ADAM:  // Sec. 3.6 (levels not already updated by the preconditioner)
       return launch_adam_levels(p.adam, fuse ? p.fused : 0u, P, (int)T, h.beta1, h.beta2, h.eps,
                                 p.epoch, 0, p.d.params, p.d.adam_m, p.d.adam_v, p.pgrad, st);
+    case PDG_STAGE_TEMPLATE: {  // X_0: L_mesh = CD_R(X_0, P_0) (Eq. 10), Sec. 3.6
+      if (!p.opt_x0) {
+        set_error("the TEMPLATE stage needs X_0 to be optimised (template Adam moments)");
+        return PDG_EINVAL;
+      }
+      float *x0 = const_cast<float *>(p.d.template_verts);
+      PDG_TRY(enqueue_chamfer(p.cw0, x0, V, p.d.points, N, h.alpha, p.d.chamfer_mode, nullptr,
+                              p.loss0, p.nn0, p.nn0 + V, p.gx0, st));
+      PDG_TRY(launch_mesh_terms(p.terms, user_terms, p.loss0, st));
+      // (I + mesh_lambda L)^-2 with the mesh Laplacian, then Adam with mesh_lr
+      PDG_TRY(launch_mesh_precondition(V, p.d.edges, p.E, h.mesh_lambda, p.max_degree,
+                                       p.mesh_iters, p.gx0, p.pgx0, p.meshws, st));
+      AdamLevels al;
+      memset(&al, 0, sizeof al);
+      al.levels = 1;
+      al.off[0] = 0;
+      al.off[1] = 3 * V;
+      al.lr[0] = h.mesh_lr;
+      return launch_adam(al, 3 * V, 1, h.beta1, h.beta2, h.eps, p.epoch, 0, x0,
+                         p.d.template_adam_m, p.d.template_adam_v, p.pgx0, st);
+    }
     default:
       set_error("unknown stage %d", stage);
       return PDG_EINVAL;
@@ -632,6 +747,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
 pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
   for (int s = PDG_STAGE_WARP; s <= PDG_STAGE_ADAM; ++s)
     PDG_TRY(enqueue_stage(p, s, st, user_terms, true));
+  if (p.opt_x0) PDG_TRY(enqueue_stage(p, PDG_STAGE_TEMPLATE, st, user_terms, true));
   return PDG_OK;
 }
 
@@ -828,67 +944,7 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
   PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
   Carve c(ws);
   ChamferWs w = chamfer_layout(c, n, m, mode);
-  NNJob jobs[2];
-  memset(jobs, 0, sizeof jobs);
-  jobs[0].q = a;
-  jobs[0].c = b;
-  jobs[0].nq = (int)n;
-  jobs[0].nc = (int)m;
-  jobs[0].nn = nn_a;
-  jobs[1].q = b;
-  jobs[1].c = a;
-  jobs[1].nq = (int)m;
-  jobs[1].nc = (int)n;
-  jobs[1].nn = nn_b;
-  ChSeg seg;
-  memset(&seg, 0, sizeof seg);
-  seg.a = a;
-  seg.b = b;
-  seg.n = (int)n;
-  seg.m = (int)m;
-  seg.nn_a = nn_a;
-  seg.nn_b = nn_b;
-  seg.ga = ga;
-  seg.a_base = 0;
-  const unsigned bb = 0;
-  const double ones[2] = {1.0, 1.0};
-  PDG_TRY(upload_small(w.jobs, jobs, sizeof jobs, stream));
-  PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
-  PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
-  PDG_TRY(upload_small(w.w_default, ones, sizeof ones, stream));
-  if (mode == PDG_CHAMFER_BF16_SCREEN) {
-    ScreenSet ss[2];
-    ScreenJob sj[2];
-    memset(ss, 0, sizeof ss);
-    memset(sj, 0, sizeof sj);
-    // Morton order of both sets (the sorted index arrays are the permutations)
-    PDG_TRY(launch_morton(a, n, (int)n, w.keys, w.perm_a, stream));
-    PDG_TRY(radix_sort(w.keys, w.perm_a, n, 30, w.sort, stream));
-    PDG_TRY(launch_morton(b, m, (int)m, w.keys, w.perm_b, stream));
-    PDG_TRY(radix_sort(w.keys, w.perm_b, m, 30, w.sort, stream));
-    ss[0] = screen_set(a, n, (const int *)w.perm_a, w.pack_a, w.coords_a, w.boxes_a, w.maxnorm);
-    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b,
-                       w.maxnorm + kMaxnormStride);
-    sj[0] = screen_job(ss[0], ss[1], nn_a, nullptr);
-    sj[1] = screen_job(ss[1], ss[0], nn_b, nullptr);
-    PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
-    PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
-    PDG_TRY(launch_fill((float *)w.maxnorm, 2 * kMaxnormStride, 0.f, stream));
-    PDG_TRY(launch_screen_pack(w.ssets, 2, (int)(n > m ? n : m), stream));
-    PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
-  } else {
-    PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
-  }
-  PDG_TRY(launch_chamfer_loss(w.segs, 1, alpha, w.partials, loss, stream));
-  if (ga) {
-    const double *dw = dir_weight ? dir_weight : w.w_default;
-    PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dw, stream));
-    PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
-    PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
-    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha, dw,
-                                       w.rpart, stream));
-  }
-  return PDG_OK;
+  return enqueue_chamfer(w, a, n, b, m, alpha, mode, dir_weight, loss, nn_a, nn_b, ga, stream);
 }
 
 pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64_t m,
@@ -1180,7 +1236,14 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
         delete p;
         return PDG_EINVAL;
       }
+    if (p->opt_x0) {  // the Gershgorin bound of the mesh preconditioner needs d_max
+      std::vector<int> deg(V, 0);
+      for (size_t i = 0; i < eh.size(); ++i) ++deg[eh[i]];
+      for (long long v = 0; v < V; ++v) p->max_degree = deg[v] > p->max_degree ? deg[v] : p->max_degree;
+    }
   }
+  if (p->opt_x0)
+    p->mesh_iters = cheb_iterations(1.0 + 2.0 * (double)pd->hp.mesh_lambda * p->max_degree, 1e-7);
   if (e == hipSuccess) e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(ChSeg), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->jobs, jobs.data(), jobs.size() * sizeof(NNJob), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->b_base, bb.data(), bb.size() * sizeof(unsigned), hipMemcpyHostToDevice);
@@ -1276,7 +1339,7 @@ pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream) {
     set_error("problem is NULL");
     return PDG_EINVAL;
   }
-  if (stage < PDG_STAGE_WARP || stage > PDG_STAGE_PRECOND_ADAM) {
+  if (stage < PDG_STAGE_WARP || stage > PDG_STAGE_TEMPLATE) {
     set_error("unknown stage %d", stage);
     return PDG_EINVAL;
   }
@@ -1322,9 +1385,13 @@ pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, s
     case PDG_BUF_PGRAD: *ptr = p->pgrad; *bytes = T * P * 4; break;
     case PDG_BUF_GPHAT: *ptr = p->gphat; *bytes = T * 3 * N * 4; break;
     case PDG_BUF_GXHAT: *ptr = p->gxhat; *bytes = T * 3 * V * 4; break;
-    case PDG_BUF_TERMS: *ptr = p->terms; *bytes = 8 * 8; break;
+    case PDG_BUF_TERMS: *ptr = p->terms; *bytes = kTerms * 8; break;
     case PDG_BUF_LAM: *ptr = p->lam; *bytes = T * 3 * V * 4; break;
     case PDG_BUF_SCREEN_TILES: *ptr = p->tiles; *bytes = p->tiles ? 8 : 0; break;
+    case PDG_BUF_NN0: *ptr = p->nn0; *bytes = p->opt_x0 ? (V + N) * 4 : 0; break;
+    case PDG_BUF_LOSS0: *ptr = p->loss0; *bytes = p->opt_x0 ? 16 : 0; break;
+    case PDG_BUF_GX0: *ptr = p->gx0; *bytes = p->opt_x0 ? 3 * V * 4 : 0; break;
+    case PDG_BUF_PGX0: *ptr = p->pgx0; *bytes = p->opt_x0 ? 3 * V * 4 : 0; break;
     default:
       set_error("unknown buffer %d", which);
       return PDG_EINVAL;

@@ -451,5 +451,11 @@ struct AssembleArgs {
   double *user_terms;        // out [8] nullable
 };
 pdg_status launch_assemble(const AssembleArgs &a, hipStream_t st);
+constexpr int kTerms = 9;  // loss terms of a step: L, L_transform, L_iso, cd_max,
+                           // point mean, template mean, w_conf(T), epoch, L_mesh
+// X_0 optimised (Eq. 9-10): terms[8] = L_mesh = loss0[0] + loss0[1] and
+// terms[0] = terms[1] + terms[2] + terms[8]; the same two slots of user
+// (nullable).
+pdg_status launch_mesh_terms(double *terms, double *user, const double *loss0, hipStream_t st);
 
 }  // namespace pdg

@@ -204,14 +204,31 @@ __global__ void assemble_kernel(AssembleArgs a) {
     for (int t = 0; t < T; ++t) a.wconf[t] = 1.0;
   }
   const double l_tr = (sum_tm + sum_pt) / T;
-  double terms[8] = {l_tr + l_iso, l_tr, l_iso, cd_max, sum_pt / T, sum_tm / T, wc, (double)e};
-  for (int i = 0; i < 8; ++i) {
+  double terms[kTerms] = {l_tr + l_iso, l_tr, l_iso, cd_max, sum_pt / T, sum_tm / T, wc, (double)e,
+                          0.0};
+  for (int i = 0; i < kTerms; ++i) {
     a.terms[i] = terms[i];
     if (a.user_terms) a.user_terms[i] = terms[i];
   }
 }
 
+__global__ void mesh_terms_kernel(double *terms, double *user, const double *loss0) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double lm = loss0[0] + loss0[1];
+  terms[8] = lm;
+  terms[0] = terms[1] + terms[2] + lm;
+  if (user) {
+    user[8] = lm;
+    user[0] = terms[0];
+  }
+}
+
 }  // namespace
+
+pdg_status launch_mesh_terms(double *terms, double *user, const double *loss0, hipStream_t st) {
+  mesh_terms_kernel<<<1, 64, 0, st>>>(terms, user, loss0);
+  return launched("mesh_terms");
+}
 
 namespace {
 // Adam over columns [c0, c1) of every stack.

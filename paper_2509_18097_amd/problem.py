@@ -29,11 +29,13 @@ class HyperParams:
     beta2: float = 0.999
     eps: float = 1e-8
     e_max: int = 50
+    mesh_lambda: float = 16.0
+    mesh_lr: float = 1e-4
 
     def to_c(self) -> L.Hyper:
         h = L.Hyper()
         for k in ("alpha", "w_iso", "eta0", "eta_growth", "lambda0", "lambda_growth", "beta1",
-                  "beta2", "eps"):
+                  "beta2", "eps", "mesh_lambda", "mesh_lr"):
             setattr(h, k, float(getattr(self, k)))
         h.e_max = int(self.e_max)
         return h
@@ -70,10 +72,13 @@ class Problem:
                  chamfer_mode: str = "fp32", precond: str = "cg", cg_iters: int = 0,
                  cg_tol: float = 1e-7, level_scale: float | None = None,
                  params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
-                 prune_mask: torch.Tensor | None = None, prune_halo: int | None = None):
+                 prune_mask: torch.Tensor | None = None, prune_halo: int | None = None,
+                 optimize_template: bool = False):
         """prune_mask (T, words) int32 as ``prune_mask`` writes it, or prune_halo
         (the paper: 3) to build it from each transition's two frames, makes the
-        grids pruned (Sec. 3.6; conjugate-gradient preconditioner only)."""
+        grids pruned (Sec. 3.6; conjugate-gradient preconditioner only).
+        optimize_template also optimises X_0 (Eq. 9-10, Sec. 3.6) on a copy of
+        ``template`` (``self.template``), with Adam moments ``template_m/v``."""
         self.hp = hp or HyperParams()
         self.res = tuple(int(r) for r in res)
         self.chamfer_mode = chamfer_mode
@@ -87,6 +92,8 @@ class Problem:
         self.P = L.grid_size(self.res)
         if template is not None and template.shape[1] > 0:
             self.template = L._dev(template, torch.float32, "template")
+            if optimize_template:
+                self.template = self.template.clone()
             self.V = template.shape[1]
             if edges is None:
                 edges = torch.zeros((2, 0), dtype=torch.int32, device=dev)
@@ -123,6 +130,14 @@ class Problem:
             if prune_mask.numel() != self.T * L.prune_mask_words(self.res):
                 raise ValueError("prune_mask must hold T stacks of prune_mask_words(res) words")
             d.prune_mask = L._ptr(self.prune_mask)
+        self.template_m = self.template_v = None
+        if optimize_template:
+            if self.template is None:
+                raise ValueError("optimize_template needs a template")
+            self.template_m = torch.zeros_like(self.template)
+            self.template_v = torch.zeros_like(self.template)
+            d.template_adam_m = L._ptr(self.template_m)
+            d.template_adam_v = L._ptr(self.template_v)
         d.params = L._ptr(self.params)
         d.adam_m = L._ptr(self.m)
         d.adam_v = L._ptr(self.v)
@@ -185,6 +200,12 @@ class Problem:
             return raw.view(torch.float64)
         if name == "screen_tiles":
             return raw.view(torch.int64)
+        if name == "nn0":
+            return raw.view(torch.int32)
+        if name == "loss0":
+            return raw.view(torch.float64)
+        if name in ("gx0", "pgx0"):
+            return raw.view(torch.float32).view(3, V)
         raise KeyError(name)
 
     def nn(self):
@@ -201,7 +222,8 @@ class Problem:
 
     def terms(self) -> dict:
         t = self.buffer("terms").cpu().tolist()
-        keys = ("loss", "l_transform", "l_iso", "cd_max", "pt_mean", "tm_mean", "wconf_T", "epoch")
+        keys = ("loss", "l_transform", "l_iso", "cd_max", "pt_mean", "tm_mean", "wconf_T", "epoch",
+                "l_mesh")
         return dict(zip(keys, t))
 
     def close(self):

@@ -126,6 +126,11 @@ def test_problem_validation_on_host():
     pd.workspace_bytes = 16
     pd.workspace = 256
     assert lib.pdg_problem_create(ctypes.byref(pd), None, ctypes.byref(h)) == L.ENOMEM
+    # X_0 optimisation needs both moments and a positive learning rate
+    pd.template_adam_m = 256
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EINVAL
+    assert "X_0" in L.last_error()
+    pd.template_adam_m = None
     # pruned grids need the conjugate-gradient preconditioner
     pd.prune_mask = 256
     pd.precond_method = L.PRECOND_METHODS["dct"]
