@@ -94,10 +94,11 @@ def isometry(xhat: np.ndarray, edges: np.ndarray, w_iso: float = 1.0):
     return w_iso * loss, g
 
 
-def confidence(cd_tm, cd_pt, epoch: int, e_max: int):
-    """Eq. 15-17.  Returns (w_conf (T,), cd_max, delta)."""
+def confidence(cd_tm, cd_pt, epoch: int, e_max: int, cd_max: float | None = None):
+    """Eq. 15-17.  Returns (w_conf (T,), cd_max, delta); cd_max, when given,
+    replaces the maximum of cd_pt (a sequence of several chains shares it)."""
     cd_tm = np.asarray(cd_tm, np.float64)
-    cd_max = float(np.max(cd_pt))
+    cd_max = float(np.max(cd_pt)) if cd_max is None else float(cd_max)
     delta = 1.0 - np.sqrt(epoch / e_max)
     factors = (1.0 / (1.0 + np.maximum(0.0, cd_tm - cd_max))) ** delta
     return np.cumprod(factors), cd_max, float(delta)
@@ -134,7 +135,8 @@ class StepResult:
 def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hyper(),
          phat32=None, xhat32=None, workers: int = 1, precond_method: str = "dct",
          grad_override=None, pgrad_override=None, masks=None, x0_state=None,
-         gx0_override=None, pgx0_override=None) -> StepResult:
+         gx0_override=None, pgx0_override=None, t_norm: int | None = None,
+         cd_max: float | None = None) -> StepResult:
     """One iteration: warp, Chamfer + isometry losses, gradient, preconditioner, Adam.
 
     points (F, 3, N) float32; template (3, V) float32 or None; edges (2, E);
@@ -154,6 +156,9 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     (I + mesh_lambda L)^-2 with the mesh Laplacian and applied by Adam with
     mesh_lr (Sec. 3.6).  ``gx0_override`` / ``pgx0_override`` replace the raw /
     preconditioned X_0 gradient fed to the next stage.
+    ``t_norm`` / ``cd_max`` (one chain of a sequence propagated both ways from
+    its keyframe, see ``step_keyframe``) replace T in the 1/T of Eq. 14 and
+    Eq. 18 and the chain's own cd_max of Eq. 17.
     """
     points = np.asarray(points)
     f = points.shape[0]
@@ -163,6 +168,7 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     etas, lams = hp.schedule(levels)
     theta = np.asarray(theta, np.float64)
     has_tm = template is not None and np.asarray(template).shape[1] > 0
+    tn = t_count if t_norm is None else int(t_norm)
 
     phat = np.stack([_wp.warp(theta[t], res, points[t], ls) for t in range(t_count)])
     xhat = None
@@ -203,22 +209,24 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     pt = cd_pt.sum(axis=1)
     tm = cd_tm.sum(axis=1)
     if has_tm:
-        w_conf, cd_max, _ = confidence(tm, pt, epoch, hp.e_max)
+        w_conf, cd_max, _ = confidence(tm, pt, epoch, hp.e_max, cd_max)
         l_iso, g_iso = isometry(x_nn, edges, hp.w_iso)
+        l_iso, g_iso = l_iso * t_count / tn, g_iso * (t_count / tn)
     else:
-        w_conf, cd_max, l_iso, g_iso = np.ones(t_count), float(np.max(pt)), 0.0, None
+        w_conf, l_iso, g_iso = np.ones(t_count), 0.0, None
+        cd_max = float(np.max(pt)) if cd_max is None else float(cd_max)
     r.w_conf, r.cd_max, r.l_iso = w_conf, cd_max, l_iso
-    r.loss = float(np.mean(w_conf * tm + pt) + l_iso) if has_tm else float(np.mean(pt))
+    r.loss = float(np.sum(w_conf * tm + pt) / tn + l_iso) if has_tm else float(np.sum(pt) / tn)
 
     # gradients of the loss with respect to the warped positions
     g_phat = np.stack([_ch.gradient(p_nn[t], points[t + 1], r.nn["pt_ab"][t], r.nn["pt_ba"][t],
-                                    hp.alpha, 1.0 / t_count, 1.0 / t_count)
+                                    hp.alpha, 1.0 / tn, 1.0 / tn)
                        for t in range(t_count)])
     r.g_phat = g_phat
     grad = np.stack([_wp.grid_adjoint(res, points[t], g_phat[t], ls) for t in range(t_count)])
     if has_tm:
         g_x = np.stack([_ch.gradient(x_nn[t + 1], points[t + 1], r.nn["tm_ab"][t], r.nn["tm_ba"][t],
-                                     hp.alpha, w_conf[t] / t_count, w_conf[t] / t_count)
+                                     hp.alpha, w_conf[t] / tn, w_conf[t] / tn)
                         for t in range(t_count)]) + g_iso[1:]
         r.g_xhat = g_x
         chain_pos = x_nn
@@ -260,3 +268,80 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
         r.x0, r.x0_m, r.x0_v = _adam.update(x0, x0_state[0], x0_state[1], p_in, hp.mesh_lr,
                                             epoch + 1, hp.beta1, hp.beta2, hp.eps)
     return r
+
+
+@dataclass
+class KeyframeResult:
+    branches: list                    # [backward, forward] StepResult or None
+    loss: float = 0.0
+    cd_max: float = 0.0
+    theta: np.ndarray = None          # (T, P) chain order: backward, then forward
+    m: np.ndarray = None
+    v: np.ndarray = None
+
+
+def chains(frames: int, keyframe: int):
+    """Frame order of the two chains leaving keyframe k (Sec. 3.3, end): the
+    backward chain k, k-1, .., 0 and the forward chain k, k+1, .., F-1; a
+    chain of one frame holds no transition."""
+    return list(range(keyframe, -1, -1)), list(range(keyframe, frames))
+
+
+def step_keyframe(points, template, edges, res, theta, m, v, epoch: int, keyframe: int,
+                  hp: Hyper = Hyper(), workers: int = 1, precond_method: str = "dct",
+                  overrides=(None, None), x0_state=None) -> KeyframeResult:
+    """One iteration of a sequence whose initial mesh X_0 sits at frame k:
+    the transformations are propagated backward from k to frame 0 and forward
+    from k to frame F-1 (the mechanism of Eq. 8 applied in reverse, Sec. 3.3).
+
+    Readings: the T = F - 1 grids are ordered by chain, the backward chain's
+    (frame k - b + 1 -> k - b, b = 1..k) first, then the forward chain's
+    (frame k + f - 1 -> k + f); Eq. 14 and 18 normalise by the total T; cd_max
+    of Eq. 17 is the maximum over every transition of both chains; the
+    confidence products of Eq. 15 run outward from the keyframe along each
+    chain; L_mesh (when X_0 is optimised) is counted once, with the forward
+    chain (the backward one when k = F - 1).
+
+    overrides: per chain, a dict of ``step``'s float32 overrides (phat32,
+    xhat32, grad_override, pgrad_override, gx0_override, pgx0_override).
+    """
+    points = np.asarray(points)
+    f = points.shape[0]
+    t_all = f - 1
+    order = chains(f, keyframe)
+    theta = np.asarray(theta, np.float64)
+    m = np.asarray(m, np.float64)
+    v = np.asarray(v, np.float64)
+    ls = hp.scale(len(res))
+    # cd_max over both chains (the point term of every transition, Eq. 17)
+    pt_all = []
+    t0 = 0
+    for c, fr in enumerate(order):
+        ov = overrides[c] or {}
+        for b in range(len(fr) - 1):
+            if ov.get("phat32") is not None:
+                a = np.asarray(ov["phat32"][b], np.float32)
+            else:
+                a = _wp.warp(theta[t0 + b], res, points[fr[b]], ls).astype(np.float32)
+            la, lb, _, _ = _ch.chamfer(a, points[fr[b + 1]], hp.alpha, workers=workers)
+            pt_all.append(la + lb)
+        t0 += len(fr) - 1
+    cd_max = float(np.max(pt_all))
+    out = KeyframeResult(branches=[None, None], cd_max=cd_max)
+    th, mm, vv = np.empty_like(theta), np.empty_like(theta), np.empty_like(theta)
+    t0 = 0
+    mesh_chain = 1 if len(order[1]) > 1 else 0
+    for c, fr in enumerate(order):
+        tc = len(fr) - 1
+        if tc == 0:
+            continue
+        sl = slice(t0, t0 + tc)
+        r = step(points[fr], template, edges, res, theta[sl], m[sl], v[sl], epoch, hp,
+                 workers=workers, precond_method=precond_method, t_norm=t_all, cd_max=cd_max,
+                 x0_state=x0_state if c == mesh_chain else None, **(overrides[c] or {}))
+        out.branches[c] = r
+        out.loss += r.loss
+        th[sl], mm[sl], vv[sl] = r.theta, r.m, r.v
+        t0 += tc
+    out.theta, out.m, out.v = th, mm, vv
+    return out

@@ -211,3 +211,88 @@ def test_template_step_pieces():
     step = x64 - r.x0
     expect = h.mesh_lr * r.pg_x0 / (np.abs(r.pg_x0) + h.eps)
     np.testing.assert_allclose(step, expect, rtol=1e-9, atol=1e-15)
+
+
+def _frozen_two_way(seq, res, theta, kr, k, hp):
+    """Loss of a step propagated both ways from keyframe k, as a function of
+    the grid values (chain order: backward chain, then forward chain), with
+    the assignments and confidence weights held at ``kr``'s values; 1/T and
+    the isometry normalisation use the total T = F - 1."""
+    pts = seq.points
+    f = pts.shape[0]
+    T = f - 1
+    e = seq.edges.shape[1]
+    ls = hp.scale(len(res))
+    tot, iso, t0 = 0.0, 0.0, 0
+    for c, fr in enumerate((list(range(k, -1, -1)), list(range(k, f)))):
+        r = kr.branches[c]
+        if r is None:
+            continue
+        xs = [seq.template.astype(np.float64)]
+        for b in range(len(fr) - 1):
+            xs.append(W.warp(theta[t0 + b], res, xs[b], ls))
+        for b in range(len(fr) - 1):
+            ph = W.warp(theta[t0 + b], res, pts[fr[b]], ls)
+            tgt = pts[fr[b + 1]]
+            cpt = C.direction_loss(ph, tgt, r.nn["pt_ab"][b], hp.alpha) + \
+                C.direction_loss(tgt, ph, r.nn["pt_ba"][b], hp.alpha)
+            ctm = C.direction_loss(xs[b + 1], tgt, r.nn["tm_ab"][b], hp.alpha) + \
+                C.direction_loss(tgt, xs[b + 1], r.nn["tm_ba"][b], hp.alpha)
+            tot += r.w_conf[b] * ctm + cpt
+            i, j = seq.edges
+            l1 = np.linalg.norm(xs[b + 1][:, i] - xs[b + 1][:, j], axis=0)
+            l0 = np.linalg.norm(xs[b][:, i] - xs[b][:, j], axis=0)
+            iso += np.sum(np.abs(l1 - l0))
+        t0 += len(fr) - 1
+    return tot / T + hp.w_iso * iso / (T * e)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_two_way_step_gradient_and_coupling(k):
+    """Reverse-time propagation (Sec. 3.3, end) from keyframe k of 4 frames:
+    the gradient of both chains' grids by central differences of the whole
+    loss; cd_max is the maximum point term over both chains; each chain's
+    confidence weights are the products outward from the keyframe."""
+    seq = _tiny_sequence(frames=4, n=40, subdiv=1, seed=8)
+    res = (1, 2, 4)
+    hp = S.Hyper(e_max=10)
+    rng = np.random.default_rng(9)
+    tot = 3 * sum(r ** 3 for r in res)
+    theta = rng.normal(0, 0.02, (3, tot))
+    z = np.zeros_like(theta)
+    kr = S.step_keyframe(seq.points, seq.template, seq.edges, res, theta, z, z, 2, k, hp)
+    pts = [kr.branches[c].cd_pt.sum(axis=1) for c in (0, 1) if kr.branches[c] is not None]
+    assert kr.cd_max == max(float(np.max(p)) for p in pts)
+    delta = 1.0 - np.sqrt(2 / 10)
+    for r in kr.branches:
+        if r is None:
+            continue
+        tm = r.cd_tm.sum(axis=1)
+        w = np.cumprod((1.0 + np.maximum(0.0, tm - kr.cd_max)) ** -delta)
+        np.testing.assert_allclose(r.w_conf, w, rtol=1e-14)
+    grads = np.concatenate([r.grad for r in kr.branches if r is not None])
+    h = 1e-5
+    for t in range(3):
+        for q in rng.choice(tot, 4, replace=False):
+            tp, tq = theta.copy(), theta.copy()
+            tp[t, q] += h
+            tq[t, q] -= h
+            fd = (_frozen_two_way(seq, res, tp, kr, k, hp) -
+                  _frozen_two_way(seq, res, tq, kr, k, hp)) / (2 * h)
+            assert abs(fd - grads[t, q]) <= 2e-4 * max(abs(fd), 1e-3), (t, q, fd, grads[t, q])
+
+
+def test_two_way_ends_reduce_to_one_chain():
+    seq = _tiny_sequence(frames=4, n=40, subdiv=1, seed=10)
+    res = (2, 4)
+    hp = S.Hyper(e_max=10)
+    theta = np.random.default_rng(11).normal(0, 0.02, (3, 3 * (8 + 64)))
+    z = np.zeros_like(theta)
+    fwd = S.step(seq.points, seq.template, seq.edges, res, theta, z, z, 1, hp)
+    k0 = S.step_keyframe(seq.points, seq.template, seq.edges, res, theta, z, z, 1, 0, hp)
+    assert k0.branches[0] is None and k0.loss == fwd.loss
+    np.testing.assert_array_equal(k0.theta, fwd.theta)
+    rev = S.step(seq.points[::-1], seq.template, seq.edges, res, theta, z, z, 1, hp)
+    k3 = S.step_keyframe(seq.points, seq.template, seq.edges, res, theta, z, z, 1, 3, hp)
+    assert k3.branches[1] is None and k3.loss == rev.loss
+    np.testing.assert_array_equal(k3.theta, rev.theta)
