@@ -94,7 +94,7 @@ def parse():
     return ap.parse_args()
 
 
-def make_problem(subdiv, chamfer, precond, prune_halo=None, optimize_template=False):
+def make_problem(subdiv, chamfer, precond, prune_halo=None, optimize_template=False, keyframe=0):
     import torch
     import synth
     from paper_2509_18097_amd.problem import HyperParams, Problem
@@ -103,7 +103,7 @@ def make_problem(subdiv, chamfer, precond, prune_halo=None, optimize_template=Fa
                    template=torch.from_numpy(seq.template).cuda(),
                    edges=torch.from_numpy(seq.edges).cuda(), hp=HyperParams(e_max=50),
                    chamfer_mode=chamfer, precond=precond, prune_halo=prune_halo,
-                   optimize_template=optimize_template)
+                   optimize_template=optimize_template, keyframe=keyframe)
     return seq, prob
 
 
@@ -390,6 +390,21 @@ def time_template(subdiv, chamfer, precond, steps=10, reps=5):
     return out
 
 
+def time_two_way(subdiv, chamfer, precond, keyframe, steps=10):
+    """The headline sequence with X_0 at a middle frame, propagated both ways
+    (Sec. 3.3, end): a backward chain of `keyframe` transitions and a forward
+    chain of the rest, one problem, one graph per step."""
+    import torch
+    _, prob = make_problem(subdiv, chamfer, precond, keyframe=keyframe)
+    ms, _ = time_steps(prob, steps, 2)
+    out = {"keyframe": keyframe, "ms_per_step": round(ms, 4),
+           "iterations_per_s": round(1000.0 / ms, 4)}
+    prob.close()
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_keyframe(seq, reps=20):
     """Keyframe selection (Sec. 3.5, Eq. 19-20) over the sequence's frames:
     one bit per occupied 128^3 voxel and frame, population counts, the
@@ -560,6 +575,7 @@ def main():
         result["mesh_precond"] = time_mesh_precond(seq)
         result["pruned"] = time_pruned(args.subdiv, args.chamfer)
         result["template_opt"] = time_template(args.subdiv, args.chamfer, args.precond)
+        result["two_way"] = time_two_way(args.subdiv, args.chamfer, args.precond, FRAMES // 2)
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:

@@ -303,6 +303,20 @@ typedef struct {
   float *template_adam_m;     /* [3][V] Adam moments of X_0, or NULL; with    */
   float *template_adam_v;     /* both set X_0 is optimised too (Eq. 9-10):    */
                               /* template_verts is then updated in place      */
+  int32_t keyframe;           /* k in [0, F): X_0 is the mesh of frame k.  With
+                                 k > 0 the grids propagate X_0 both ways (the
+                                 mechanism of Eq. 8 in reverse, Sec. 3.3): a
+                                 backward chain k -> k-1 -> .. -> 0 and a
+                                 forward chain k -> .. -> F-1; the T = F-1
+                                 stacks of params / adam_m / adam_v /
+                                 prune_mask are in chain order: the backward
+                                 chain's (frame k-b+1 -> k-b, b = 1..k), then
+                                 the forward chain's (frame k+f-1 -> k+f).
+                                 Eq. 14 and 18 normalise by the total T, cd_max
+                                 (Eq. 17) spans both chains, the confidence
+                                 products (Eq. 15) run outward from k along
+                                 each; X_0 is optimised (if asked) with the
+                                 forward chain, the backward one if k = F-1.  */
   void *workspace;            /* >= pdg_problem_workspace() bytes             */
   size_t workspace_bytes;
 } pdg_problem_desc;
@@ -400,6 +414,14 @@ typedef enum {
   PDG_BUF_NN0 = 12, PDG_BUF_LOSS0 = 13, PDG_BUF_GX0 = 14, PDG_BUF_PGX0 = 15
 } pdg_buffer;
 pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes);
+/* The chains of a problem: which = 0 the backward chain (NULL when the
+ * keyframe is 0), which = 1 the forward chain (NULL when the keyframe is the
+ * last frame; the problem itself when the keyframe is 0).  A chain handle
+ * serves pdg_problem_buffer for its own intermediate buffers, with its frames
+ * in chain order (the backward chain's frame b is frame k - b); the problem
+ * handle of a keyframe k > 0 serves only PDG_BUF_TERMS (the sequence's terms).
+ * Chain handles belong to the problem (no destroy, no step). */
+pdg_status pdg_problem_branch(const pdg_problem *p, int32_t which, pdg_problem **chain);
 
 #ifdef __cplusplus
 }

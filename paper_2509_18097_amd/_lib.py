@@ -56,6 +56,7 @@ class ProblemDesc(ctypes.Structure):
                 ("params", ctypes.c_void_p),
                 ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
                 ("template_adam_m", ctypes.c_void_p), ("template_adam_v", ctypes.c_void_p),
+                ("keyframe", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -100,6 +101,7 @@ _SIGS = {
                               _I32, ctypes.POINTER(_P)]),
     "pdg_problem_destroy": (_I32, [_P]),
     "pdg_problem_buffer": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
+    "pdg_problem_branch": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
 }
 EXPORTS = tuple(_SIGS)
 

@@ -430,6 +430,17 @@ struct pdg_problem {
   ChamferWs cw0;                                   // Chamfer workspace of (X_0, P_0)
   void *meshws = nullptr;
   int max_degree = 0, mesh_iters = 0;
+  // Eq. 14 and 17 across the two chains of a sequence whose keyframe lies
+  // inside it (reverse-time propagation): the 1/T count and the other chain
+  long long Tn = 0;
+  const double *partner_losses = nullptr;
+  int partner_T = 0;
+  // such a sequence is a joint handle over the backward (0) and forward (1)
+  // chains; the backward chain reads a reversed copy of frames k..0
+  bool joint = false;
+  pdg_problem *child[2] = {nullptr, nullptr};
+  float *rev_points = nullptr;
+  double *jterms = nullptr;
   size_t ws_used = 0;
   // graph replay
   hipStream_t cap = nullptr;
@@ -448,6 +459,10 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   PDG_TRY(check_grid(&pd->grid));
   if (pd->frames < 2) {
     set_error("frames = %d: need at least 2", pd->frames);
+    return PDG_EINVAL;
+  }
+  if (pd->keyframe < 0 || pd->keyframe >= pd->frames) {
+    set_error("keyframe = %d outside [0, frames)", pd->keyframe);
     return PDG_EINVAL;
   }
   if (pd->n < 1 || pd->n >= (1ll << 31)) {
@@ -594,6 +609,7 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   p.P = p.g.size;
   p.has_tm = p.V > 0;
   p.opt_x0 = p.has_tm && pd.template_adam_m && pd.template_adam_v;
+  p.Tn = p.T;
   float *lam = p.lambda_l;
   p.adam.levels = p.g.levels;
   for (int l = 0; l < p.g.levels; ++l) {
@@ -620,9 +636,14 @@ IsoArgs iso_args(pdg_problem &p) {
   ia.inc_off = p.inc_off;
   ia.inc = p.ivals;
   ia.gx = p.gxhat;
-  ia.coef = p.E > 0 ? (double)p.d.hp.w_iso / ((double)p.T * (double)p.E) : 0.0;
+  ia.coef = p.E > 0 ? (double)p.d.hp.w_iso / ((double)p.Tn * (double)p.E) : 0.0;
   return ia;
 }
+
+// The loss stage in two halves (a sequence's two chains both compute their
+// terms before either assembles: cd_max spans both).
+constexpr int kStageLossTerms = 100;
+constexpr int kStageAssemble = 101;
 
 // One stage of the step (the stages in order make one iteration).
 // fuse: part of a full step (the preconditioner may apply Adam itself, see
@@ -650,9 +671,14 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN)   // warm start: last step's assignment
         return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
       return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
-    case PDG_STAGE_LOSS: {  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
+    case PDG_STAGE_LOSS:  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
+      PDG_TRY(enqueue_stage(p, kStageLossTerms, st, user_terms, fuse));
+      return enqueue_stage(p, kStageAssemble, st, user_terms, fuse);
+    case kStageLossTerms:  // the Chamfer terms and the isometry partials
       PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_edges(iso_args(p), st));
+      return PDG_OK;
+    case kStageAssemble: {  // cd_max, w_conf, L
       AssembleArgs aa;
       aa.losses = p.losses;
       aa.iso_partials = p.iso_partials;
@@ -666,6 +692,9 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       aa.wconf = p.wconf;
       aa.terms = p.terms;
       aa.user_terms = user_terms;
+      aa.Tn = (int)p.Tn;
+      aa.partner_losses = p.partner_losses;
+      aa.partner_T = p.partner_T;
       return launch_assemble(aa, st);
     }
     case PDG_STAGE_GRAD:  // dL/dP^, dL/dX (Chamfer adjoint, isometry), reverse sweep of Eq. 8
@@ -744,16 +773,54 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
   }
 }
 
+pdg_status enqueue_precond_adam(pdg_problem &p, hipStream_t st) {
+  PDG_TRY(enqueue_stage(p, PDG_STAGE_PRECOND, st, nullptr, true));
+  return enqueue_stage(p, PDG_STAGE_ADAM, st, nullptr, true);
+}
+
+// A stage of a sequence propagated both ways: the stage on each chain (the
+// loss stage's halves interleaved), then the sequence's terms.
+pdg_status enqueue_joint_stage(pdg_problem &J, int stage, hipStream_t st, double *user_terms,
+                               bool fuse) {
+  pdg_problem *const *ch = J.child;
+  if (stage == PDG_STAGE_LOSS) {
+    for (int c = 0; c < 2; ++c)
+      if (ch[c]) PDG_TRY(enqueue_stage(*ch[c], kStageLossTerms, st, nullptr, fuse));
+    for (int c = 0; c < 2; ++c)
+      if (ch[c]) PDG_TRY(enqueue_stage(*ch[c], kStageAssemble, st, nullptr, fuse));
+  } else if (stage == PDG_STAGE_TEMPLATE) {
+    pdg_problem *m = ch[1] && ch[1]->opt_x0 ? ch[1] : ch[0];
+    if (!m || !m->opt_x0) {
+      set_error("the TEMPLATE stage needs X_0 to be optimised (template Adam moments)");
+      return PDG_EINVAL;
+    }
+    PDG_TRY(enqueue_stage(*m, stage, st, nullptr, fuse));
+  } else {
+    for (int c = 0; c < 2; ++c)
+      if (ch[c]) {
+        if (stage == PDG_STAGE_PRECOND_ADAM)
+          PDG_TRY(enqueue_precond_adam(*ch[c], st));
+        else
+          PDG_TRY(enqueue_stage(*ch[c], stage, st, nullptr, fuse));
+      }
+  }
+  if (stage == PDG_STAGE_LOSS || stage == PDG_STAGE_TEMPLATE)
+    return launch_joint_terms(ch[0] ? ch[0]->terms : nullptr, ch[1] ? ch[1]->terms : nullptr,
+                              J.jterms, user_terms, st);
+  return PDG_OK;
+}
+
 pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
+  if (p.joint) {
+    for (int s = PDG_STAGE_WARP; s <= PDG_STAGE_ADAM; ++s)
+      PDG_TRY(enqueue_joint_stage(p, s, st, user_terms, true));
+    if (p.opt_x0) PDG_TRY(enqueue_joint_stage(p, PDG_STAGE_TEMPLATE, st, user_terms, true));
+    return PDG_OK;
+  }
   for (int s = PDG_STAGE_WARP; s <= PDG_STAGE_ADAM; ++s)
     PDG_TRY(enqueue_stage(p, s, st, user_terms, true));
   if (p.opt_x0) PDG_TRY(enqueue_stage(p, PDG_STAGE_TEMPLATE, st, user_terms, true));
   return PDG_OK;
-}
-
-pdg_status enqueue_precond_adam(pdg_problem &p, hipStream_t st) {
-  PDG_TRY(enqueue_stage(p, PDG_STAGE_PRECOND, st, nullptr, true));
-  return enqueue_stage(p, PDG_STAGE_ADAM, st, nullptr, true);
 }
 
 }  // namespace
@@ -1108,12 +1175,80 @@ pdg_status pdg_adam(const pdg_grid_desc *d, int32_t batch, const float *lr, floa
   return launch_adam(lv, gd.size, batch, beta1, beta2, eps, nullptr, step, theta, m, v, g, stream);
 }
 
+namespace pdg {
+namespace {
+
+// One chain of a sequence propagated both ways from keyframe k: the backward
+// chain (c = 0) reads frames k, k-1, .., 0 from `rev` and owns the first k
+// grid stacks; the forward chain (c = 1) reads frames k .. F-1 in place and
+// owns the rest.  X_0 is optimised with the forward chain (with the backward
+// one when k = F - 1).
+pdg_problem_desc chain_desc(const pdg_problem_desc &pd, int c, const float *rev) {
+  pdg_problem_desc d = pd;
+  d.keyframe = 0;
+  d.workspace = nullptr;
+  d.workspace_bytes = 0;
+  const long long k = pd.keyframe, N = pd.n;
+  const GridDev g = make_grid(pd.grid);
+  if (c == 0) {
+    d.frames = (int32_t)(k + 1);
+    d.points = rev;
+    if (pd.frames - 1 - k > 0) d.template_adam_m = d.template_adam_v = nullptr;
+  } else {
+    d.frames = (int32_t)(pd.frames - k);
+    d.points = pd.points + k * 3 * N;
+    d.params = pd.params + k * g.size;
+    d.adam_m = pd.adam_m + k * g.size;
+    d.adam_v = pd.adam_v + k * g.size;
+    if (pd.prune_mask) d.prune_mask = pd.prune_mask + k * mask_stack_words(g);
+  }
+  return d;
+}
+
+bool chain_exists(const pdg_problem_desc &pd, int c) {
+  return c == 0 ? pd.keyframe >= 1 : pd.keyframe <= pd.frames - 2;
+}
+
+}  // namespace
+}  // namespace pdg
+
+static pdg_status chain_workspace(const pdg_problem_desc *pd, size_t *bytes);
+static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out);
+
+static pdg_status joint_layout(const pdg_problem_desc *pd, Carve &c, float **rev, double **jterms,
+                               size_t chain_bytes[2]) {
+  const long long k = pd->keyframe, N = pd->n;
+  *rev = c.take<float>((k + 1) * 3 * N);
+  *jterms = c.take<double>(kTerms);
+  for (int i = 0; i < 2; ++i) {
+    chain_bytes[i] = 0;
+    if (!chain_exists(*pd, i)) continue;
+    const pdg_problem_desc d = chain_desc(*pd, i, *rev ? *rev : (const float *)pd->points);
+    PDG_TRY(chain_workspace(&d, &chain_bytes[i]));
+    c.take<char>((long long)chain_bytes[i]);
+  }
+  return PDG_OK;
+}
+
 pdg_status pdg_problem_workspace(const pdg_problem_desc *pd, size_t *bytes) {
   PDG_TRY(check_problem(pd));
   if (!bytes) {
     set_error("bytes is NULL");
     return PDG_EINVAL;
   }
+  if (pd->keyframe > 0) {
+    Carve c(nullptr);
+    float *rev = nullptr;
+    double *jt = nullptr;
+    size_t cb[2];
+    PDG_TRY(joint_layout(pd, c, &rev, &jt, cb));
+    *bytes = c.off;
+    return PDG_OK;
+  }
+  return chain_workspace(pd, bytes);
+}
+
+static pdg_status chain_workspace(const pdg_problem_desc *pd, size_t *bytes) {
   pdg_problem p;
   init_problem(p, *pd);
   Carve c(nullptr);
@@ -1128,6 +1263,58 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
     set_error("out is NULL");
     return PDG_EINVAL;
   }
+  if (pd->keyframe == 0) return create_chain(pd, stream, out);
+  // reverse-time propagation: two chains leave the keyframe
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_problem_workspace(pd, &need_bytes));
+  PDG_TRY(need_ws(pd->workspace, pd->workspace_bytes, need_bytes));
+  pdg_problem *J = new (std::nothrow) pdg_problem;
+  if (!J) {
+    set_error("host allocation failed");
+    return PDG_ENOMEM;
+  }
+  J->joint = true;
+  J->d = *pd;
+  J->F = pd->frames;
+  J->T = pd->frames - 1;
+  J->N = pd->n;
+  J->V = pd->verts;
+  J->has_tm = pd->verts > 0;
+  J->opt_x0 = J->has_tm && pd->template_adam_m && pd->template_adam_v;
+  Carve c(pd->workspace);
+  const long long k = pd->keyframe, N = pd->n;
+  J->rev_points = c.take<float>((k + 1) * 3 * N);
+  J->jterms = c.take<double>(kTerms);
+  pdg_status s = PDG_OK;
+  for (long long b = 0; b <= k && s == PDG_OK; ++b)   // frames k, k-1, .., 0
+    s = launch_copy(J->rev_points + b * 3 * N, pd->points + (k - b) * 3 * N, 3 * N, stream);
+  for (int i = 0; i < 2 && s == PDG_OK; ++i) {
+    if (!chain_exists(*pd, i)) continue;
+    pdg_problem_desc d = chain_desc(*pd, i, J->rev_points);
+    size_t cb = 0;
+    s = chain_workspace(&d, &cb);
+    if (s != PDG_OK) break;
+    d.workspace = c.take<char>((long long)cb);
+    d.workspace_bytes = cb;
+    s = create_chain(&d, stream, &J->child[i]);
+    if (s == PDG_OK) J->child[i]->Tn = J->T;
+  }
+  if (s != PDG_OK) {
+    (void)pdg_problem_destroy(J);
+    return s;
+  }
+  if (J->child[0] && J->child[1]) {
+    J->child[0]->partner_losses = J->child[1]->losses;
+    J->child[0]->partner_T = J->child[1]->T;
+    J->child[1]->partner_losses = J->child[0]->losses;
+    J->child[1]->partner_T = J->child[0]->T;
+  }
+  J->ws_used = c.off;
+  *out = J;
+  return PDG_OK;
+}
+
+static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out) {
   pdg_problem *p = new (std::nothrow) pdg_problem;
   if (!p) {
     set_error("host allocation failed");
@@ -1310,7 +1497,12 @@ pdg_status pdg_step(pdg_problem *p, int32_t epoch, double *loss_terms, int32_t u
     set_error("epoch %d outside [0, e_max = %d]", epoch, p->d.hp.e_max);
     return PDG_EINVAL;
   }
-  PDG_TRY(launch_set_int(p->epoch, epoch, stream));
+  if (p->joint) {
+    for (int c = 0; c < 2; ++c)
+      if (p->child[c]) PDG_TRY(launch_set_int(p->child[c]->epoch, epoch, stream));
+  } else {
+    PDG_TRY(launch_set_int(p->epoch, epoch, stream));
+  }
   if (!use_graph) return enqueue_step(*p, stream, loss_terms);
   if (loss_terms) {
     set_error("loss_terms must be NULL with use_graph (read PDG_BUF terms instead)");
@@ -1343,6 +1535,7 @@ pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream) {
     set_error("unknown stage %d", stage);
     return PDG_EINVAL;
   }
+  if (p->joint) return enqueue_joint_stage(*p, stage, stream, nullptr, false);
   if (stage == PDG_STAGE_PRECOND_ADAM) return enqueue_precond_adam(*p, stream);
   return enqueue_stage(*p, stage, stream, nullptr, false);
 }
@@ -1362,6 +1555,7 @@ pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *
 
 pdg_status pdg_problem_destroy(pdg_problem *p) {
   if (!p) return PDG_OK;
+  for (int c = 0; c < 2; ++c) (void)pdg_problem_destroy(p->child[c]);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) (void)hipStreamDestroy(p->cap);
@@ -1369,10 +1563,32 @@ pdg_status pdg_problem_destroy(pdg_problem *p) {
   return PDG_OK;
 }
 
+pdg_status pdg_problem_branch(const pdg_problem *p, int32_t which, pdg_problem **chain) {
+  if (!p || !chain || which < 0 || which > 1) {
+    set_error("NULL argument or which outside {0, 1}");
+    return PDG_EINVAL;
+  }
+  if (p->joint)
+    *chain = p->child[which];
+  else
+    *chain = which == 1 ? const_cast<pdg_problem *>(p) : nullptr;
+  return PDG_OK;
+}
+
 pdg_status pdg_problem_buffer(const pdg_problem *p, int32_t which, void **ptr, size_t *bytes) {
   if (!p || !ptr || !bytes) {
     set_error("NULL argument");
     return PDG_EINVAL;
+  }
+  if (p->joint) {
+    if (which != PDG_BUF_TERMS) {
+      set_error("a sequence propagated both ways keeps its buffers per chain: "
+                "see pdg_problem_branch");
+      return PDG_EINVAL;
+    }
+    *ptr = p->jterms;
+    *bytes = kTerms * 8;
+    return PDG_OK;
   }
   const long long T = p->T, N = p->N, V = p->V, P = p->P;
   switch (which) {

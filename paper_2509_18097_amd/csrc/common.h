@@ -447,8 +447,12 @@ struct AssembleArgs {
   float w_iso;
   double *w;                 // out [seg][2] gradient weights
   double *wconf;             // out [T]
-  double *terms;             // out [8]
-  double *user_terms;        // out [8] nullable
+  double *terms;             // out [kTerms]
+  double *user_terms;        // out [kTerms] nullable
+  int Tn;                    // the 1/T of Eq. 14 (the sequence's T; T unless the
+                             // chain is one of two leaving a keyframe)
+  const double *partner_losses;  // the other chain's losses (its point terms
+  int partner_T;                 // enter cd_max, Eq. 17), or null / 0
 };
 pdg_status launch_assemble(const AssembleArgs &a, hipStream_t st);
 constexpr int kTerms = 9;  // loss terms of a step: L, L_transform, L_iso, cd_max,
@@ -457,5 +461,10 @@ constexpr int kTerms = 9;  // loss terms of a step: L, L_transform, L_iso, cd_ma
 // terms[0] = terms[1] + terms[2] + terms[8]; the same two slots of user
 // (nullable).
 pdg_status launch_mesh_terms(double *terms, double *user, const double *loss0, hipStream_t st);
+// Terms of a sequence propagated both ways from its keyframe from those of its
+// backward (tb) and forward (tf) chains (either nullable): sums, the shared
+// cd_max, w_conf and epoch of the forward chain (else the backward one).
+pdg_status launch_joint_terms(const double *tb, const double *tf, double *out, double *user,
+                              hipStream_t st);
 
 }  // namespace pdg

@@ -174,13 +174,18 @@ __global__ void assemble_kernel(AssembleArgs a) {
   const int E = a.E;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int T = a.T;
+  const int Tn = a.Tn;
   double cd_max = -1.0, sum_pt = 0.0;
   for (int t = 0; t < T; ++t) {
     const double c = a.losses[2 * t] + a.losses[2 * t + 1];
     cd_max = c > cd_max ? c : cd_max;
     sum_pt += c;
-    a.w[2 * t] = 1.0 / T;
-    a.w[2 * t + 1] = 1.0 / T;
+    a.w[2 * t] = 1.0 / Tn;
+    a.w[2 * t + 1] = 1.0 / Tn;
+  }
+  for (int t = 0; t < a.partner_T; ++t) {   // the other chain's point terms (Eq. 17)
+    const double c = a.partner_losses[2 * t] + a.partner_losses[2 * t + 1];
+    cd_max = c > cd_max ? c : cd_max;
   }
   const int e = *a.epoch;
   const double delta = 1.0 - sqrt((double)e / (double)a.e_max);
@@ -191,24 +196,39 @@ __global__ void assemble_kernel(AssembleArgs a) {
       const double ex = c - cd_max > 0.0 ? c - cd_max : 0.0;
       wc *= pow(1.0 / (1.0 + ex), delta);
       a.wconf[t] = wc;
-      a.w[2 * (T + t)] = wc / T;
-      a.w[2 * (T + t) + 1] = wc / T;
+      a.w[2 * (T + t)] = wc / Tn;
+      a.w[2 * (T + t) + 1] = wc / Tn;
       sum_tm += wc * c;
     }
     if (E > 0) {
       double s = 0.0;
       for (int b = 0; b < kIsoBlocks; ++b) s += a.iso_partials[b];
-      l_iso = (double)a.w_iso * s / ((double)T * (double)E);
+      l_iso = (double)a.w_iso * s / ((double)Tn * (double)E);
     }
   } else {
     for (int t = 0; t < T; ++t) a.wconf[t] = 1.0;
   }
-  const double l_tr = (sum_tm + sum_pt) / T;
-  double terms[kTerms] = {l_tr + l_iso, l_tr, l_iso, cd_max, sum_pt / T, sum_tm / T, wc, (double)e,
-                          0.0};
+  const double l_tr = (sum_tm + sum_pt) / Tn;
+  double terms[kTerms] = {l_tr + l_iso, l_tr, l_iso, cd_max, sum_pt / Tn, sum_tm / Tn, wc,
+                          (double)e, 0.0};
   for (int i = 0; i < kTerms; ++i) {
     a.terms[i] = terms[i];
     if (a.user_terms) a.user_terms[i] = terms[i];
+  }
+}
+
+__global__ void joint_terms_kernel(const double *tb, const double *tf, double *out,
+                                   double *user) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double *last = tf ? tf : tb;
+  double t[kTerms];
+  for (int i = 0; i < kTerms; ++i) t[i] = (tb ? tb[i] : 0.0) + (tf ? tf[i] : 0.0);
+  t[3] = last[3];   // cd_max: the same in both chains
+  t[6] = last[6];
+  t[7] = last[7];
+  for (int i = 0; i < kTerms; ++i) {
+    out[i] = t[i];
+    if (user) user[i] = t[i];
   }
 }
 
@@ -224,6 +244,12 @@ __global__ void mesh_terms_kernel(double *terms, double *user, const double *los
 }
 
 }  // namespace
+
+pdg_status launch_joint_terms(const double *tb, const double *tf, double *out, double *user,
+                              hipStream_t st) {
+  joint_terms_kernel<<<1, 64, 0, st>>>(tb, tf, out, user);
+  return launched("joint_terms");
+}
 
 pdg_status launch_mesh_terms(double *terms, double *user, const double *loss0, hipStream_t st) {
   mesh_terms_kernel<<<1, 64, 0, st>>>(terms, user, loss0);

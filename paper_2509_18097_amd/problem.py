@@ -73,13 +73,17 @@ class Problem:
                  cg_tol: float = 1e-7, level_scale: float | None = None,
                  params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
                  prune_mask: torch.Tensor | None = None, prune_halo: int | None = None,
-                 optimize_template: bool = False):
+                 optimize_template: bool = False, keyframe: int = 0):
         """prune_mask (T, words) int32 as ``prune_mask`` writes it, or prune_halo
         (the paper: 3) to build it from each transition's two frames, makes the
         grids pruned (Sec. 3.6; conjugate-gradient preconditioner only).
         optimize_template also optimises X_0 (Eq. 9-10, Sec. 3.6) on a copy of
-        ``template`` (``self.template``), with Adam moments ``template_m/v``."""
+        ``template`` (``self.template``), with Adam moments ``template_m/v``.
+        keyframe k > 0 places X_0 at frame k and propagates both ways (the
+        grids, masks and moments in chain order: the backward chain's first,
+        see pdg_problem_desc.keyframe); ``branch(0/1)`` gives each chain."""
         self.hp = hp or HyperParams()
+        self.keyframe = int(keyframe)
         self.res = tuple(int(r) for r in res)
         self.chamfer_mode = chamfer_mode
         self.precond = precond
@@ -120,10 +124,19 @@ class Problem:
         d.precond_method = L.PRECOND_METHODS[precond]
         d.cg_iters = int(cg_iters)
         d.cg_tol = float(cg_tol)
+        d.keyframe = self.keyframe
         if prune_mask is None and prune_halo is not None:
             with torch.cuda.stream(stream or torch.cuda.current_stream()):
                 prune_mask, self.kept_cells = L.prune_mask(self.points, self.res, 2,
                                                            int(prune_halo))
+            if self.keyframe > 0:
+                # stack j of the masks joins frames j and j + 1: chain order is
+                # j = k-1, .., 0 (backward chain), then k, .., T-1
+                k = self.keyframe
+                order = torch.tensor(list(range(k - 1, -1, -1)) + list(range(k, self.T)),
+                                     device=dev)
+                prune_mask = prune_mask[order].contiguous()
+                self.kept_cells = self.kept_cells[order].contiguous()
         self.prune_mask = None
         if prune_mask is not None:
             self.prune_mask = L._dev(prune_mask, torch.int32, "prune_mask")
@@ -177,48 +190,23 @@ class Problem:
 
     def buffer(self, name: str) -> torch.Tensor:
         """View of an intermediate buffer of the last step (see pdg_problem_buffer)."""
-        ptr = ctypes.c_void_p()
-        nb = ctypes.c_size_t()
-        L.check(L.lib().pdg_problem_buffer(self._h, L.BUFFERS[name], ctypes.byref(ptr),
-                                           ctypes.byref(nb)), "pdg_problem_buffer")
-        off = (ptr.value or self.workspace.data_ptr()) - self.workspace.data_ptr()
-        raw = self.workspace[off:off + nb.value]
-        T, N, V, P = self.T, self.n, self.V, self.P
-        if name in ("phat", "gphat"):
-            return raw.view(torch.float32).view(T, 3, N)
-        if name == "xhat":
-            return raw.view(torch.float32).view(T + 1, 3, V)
-        if name in ("gxhat", "lam"):
-            return raw.view(torch.float32).view(T, 3, V)
-        if name in ("grad", "pgrad"):
-            return raw.view(torch.float32).view(T, P)
-        if name == "nn":
-            return raw.view(torch.int32)
-        if name == "losses":
-            return raw.view(torch.float64).view(-1, 2)
-        if name in ("wconf", "terms"):
-            return raw.view(torch.float64)
-        if name == "screen_tiles":
-            return raw.view(torch.int64)
-        if name == "nn0":
-            return raw.view(torch.int32)
-        if name == "loss0":
-            return raw.view(torch.float64)
-        if name in ("gx0", "pgx0"):
-            return raw.view(torch.float32).view(3, V)
-        raise KeyError(name)
+        return _buffer(self, self._h, self.T, name)
 
     def nn(self):
         """Nearest-neighbour indices of the last step as a dict of (T, ...) tensors."""
-        raw = self.buffer("nn")
-        T, N, V = self.T, self.n, self.V
-        pt = raw[:T * 2 * N].view(T, 2 * N)
-        out = {"pt_ab": pt[:, :N], "pt_ba": pt[:, N:]}
-        if V > 0:
-            tm = raw[T * 2 * N:T * 2 * N + T * (V + N)].view(T, V + N)
-            out["tm_ab"] = tm[:, :V]
-            out["tm_ba"] = tm[:, V:]
-        return out
+        return _nn(self.buffer("nn"), self.T, self.n, self.V)
+
+    def branch(self, which: int) -> "Chain | None":
+        """The backward (0) or forward (1) chain of a sequence propagated both
+        ways from its keyframe (see pdg_problem_branch), or None."""
+        h = ctypes.c_void_p()
+        L.check(L.lib().pdg_problem_branch(self._h, int(which), ctypes.byref(h)),
+                "pdg_problem_branch")
+        if not h.value:
+            return None
+        k = self.keyframe
+        T = (k if which == 0 else self.T - k) if k > 0 else self.T
+        return Chain(self, h, T)
 
     def terms(self) -> dict:
         t = self.buffer("terms").cpu().tolist()
@@ -236,3 +224,58 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class Chain:
+    """One chain of a problem (its buffers; the frames in chain order)."""
+
+    def __init__(self, prob: Problem, handle, T: int):
+        self.prob, self._h, self.T = prob, handle, T
+        self.n, self.V, self.P = prob.n, prob.V, prob.P
+        self.workspace = prob.workspace
+
+    def buffer(self, name: str) -> torch.Tensor:
+        return _buffer(self, self._h, self.T, name)
+
+    def nn(self):
+        return _nn(self.buffer("nn"), self.T, self.n, self.V)
+
+
+def _buffer(owner, handle, T: int, name: str) -> torch.Tensor:
+    ptr = ctypes.c_void_p()
+    nb = ctypes.c_size_t()
+    L.check(L.lib().pdg_problem_buffer(handle, L.BUFFERS[name], ctypes.byref(ptr),
+                                       ctypes.byref(nb)), "pdg_problem_buffer")
+    ws = owner.workspace
+    off = (ptr.value or ws.data_ptr()) - ws.data_ptr()
+    raw = ws[off:off + nb.value]
+    N, V, P = owner.n, owner.V, owner.P
+    if name in ("phat", "gphat"):
+        return raw.view(torch.float32).view(T, 3, N)
+    if name == "xhat":
+        return raw.view(torch.float32).view(T + 1, 3, V)
+    if name in ("gxhat", "lam"):
+        return raw.view(torch.float32).view(T, 3, V)
+    if name in ("grad", "pgrad"):
+        return raw.view(torch.float32).view(T, P)
+    if name in ("nn", "nn0"):
+        return raw.view(torch.int32)
+    if name == "losses":
+        return raw.view(torch.float64).view(-1, 2)
+    if name in ("wconf", "terms", "loss0"):
+        return raw.view(torch.float64)
+    if name == "screen_tiles":
+        return raw.view(torch.int64)
+    if name in ("gx0", "pgx0"):
+        return raw.view(torch.float32).view(3, V)
+    raise KeyError(name)
+
+
+def _nn(raw, T: int, N: int, V: int) -> dict:
+    pt = raw[:T * 2 * N].view(T, 2 * N)
+    out = {"pt_ab": pt[:, :N], "pt_ba": pt[:, N:]}
+    if V > 0:
+        tm = raw[T * 2 * N:T * 2 * N + T * (V + N)].view(T, V + N)
+        out["tm_ab"] = tm[:, :V]
+        out["tm_ba"] = tm[:, V:]
+    return out

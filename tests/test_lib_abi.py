@@ -126,6 +126,15 @@ def test_problem_validation_on_host():
     pd.workspace_bytes = 16
     pd.workspace = 256
     assert lib.pdg_problem_create(ctypes.byref(pd), None, ctypes.byref(h)) == L.ENOMEM
+    # the keyframe lies in [0, frames)
+    pd.keyframe = 3
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EINVAL
+    assert "keyframe" in L.last_error()
+    pd.keyframe = 1
+    nb1 = ctypes.c_size_t()
+    assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb1)) == L.OK
+    assert nb1.value > 0
+    pd.keyframe = 0
     # X_0 optimisation needs both moments and a positive learning rate
     pd.template_adam_m = 256
     assert lib.pdg_problem_workspace(ctypes.byref(pd), ctypes.byref(nb)) == L.EINVAL
