@@ -170,44 +170,76 @@ __global__ void incidence_off_kernel(const uint32_t *__restrict__ keys, int n2, 
   off[v] = lo;
 }
 
-__global__ void assemble_kernel(AssembleArgs a) {
-  const int E = a.E;
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int T = a.T;
-  const int Tn = a.Tn;
-  double cd_max = -1.0, sum_pt = 0.0;
-  for (int t = 0; t < T; ++t) {
+// Lane-strided partials summed in lane order (the result on lane 0).
+__device__ __forceinline__ double lane_ordered_sum(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 64; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// One wave: the loads and the confidence factors lane-parallel, the
+// cumulative product and the sums in a fixed order.
+__global__ __launch_bounds__(64) void assemble_kernel(AssembleArgs a) {
+  __shared__ double sh[64], fac[64], cc[64];
+  const int lane = threadIdx.x;
+  const int E = a.E, T = a.T, Tn = a.Tn;
+  double cm = -1.0, sp = 0.0;
+  for (int t = lane; t < T; t += 64) {
     const double c = a.losses[2 * t] + a.losses[2 * t + 1];
-    cd_max = c > cd_max ? c : cd_max;
-    sum_pt += c;
+    cm = c > cm ? c : cm;
+    sp += c;
     a.w[2 * t] = 1.0 / Tn;
     a.w[2 * t + 1] = 1.0 / Tn;
   }
-  for (int t = 0; t < a.partner_T; ++t) {   // the other chain's point terms (Eq. 17)
+  for (int t = lane; t < a.partner_T; t += 64) {   // the other chain's point terms (Eq. 17)
     const double c = a.partner_losses[2 * t] + a.partner_losses[2 * t + 1];
-    cd_max = c > cd_max ? c : cd_max;
+    cm = c > cm ? c : cm;
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double u = __shfl_xor(cm, o, 64);
+    cm = u > cm ? u : cm;
+  }
+  const double cd_max = cm;
+  const double sum_pt = lane_ordered_sum(sp, sh);
   const int e = *a.epoch;
   const double delta = 1.0 - sqrt((double)e / (double)a.e_max);
   double wc = 1.0, sum_tm = 0.0, l_iso = 0.0;
   if (a.has_tm) {
-    for (int t = 0; t < T; ++t) {
-      const double c = a.losses[2 * (T + t)] + a.losses[2 * (T + t) + 1];
-      const double ex = c - cd_max > 0.0 ? c - cd_max : 0.0;
-      wc *= pow(1.0 / (1.0 + ex), delta);
-      a.wconf[t] = wc;
-      a.w[2 * (T + t)] = wc / Tn;
-      a.w[2 * (T + t) + 1] = wc / Tn;
-      sum_tm += wc * c;
+    for (int t0 = 0; t0 < T; t0 += 64) {
+      const int t = t0 + lane;
+      if (t < T) {
+        const double c = a.losses[2 * (T + t)] + a.losses[2 * (T + t) + 1];
+        const double ex = c - cd_max > 0.0 ? c - cd_max : 0.0;
+        fac[lane] = pow(1.0 / (1.0 + ex), delta);
+        cc[lane] = c;
+      }
+      __syncthreads();
+      if (lane == 0) {
+        const int n = T - t0 < 64 ? T - t0 : 64;
+        for (int j = 0; j < n; ++j) {
+          wc *= fac[j];
+          a.wconf[t0 + j] = wc;
+          a.w[2 * (T + t0 + j)] = wc / Tn;
+          a.w[2 * (T + t0 + j) + 1] = wc / Tn;
+          sum_tm += wc * cc[j];
+        }
+      }
+      __syncthreads();
     }
     if (E > 0) {
       double s = 0.0;
-      for (int b = 0; b < kIsoBlocks; ++b) s += a.iso_partials[b];
+      for (int b = lane; b < kIsoBlocks; b += 64) s += a.iso_partials[b];
+      s = lane_ordered_sum(s, sh);
       l_iso = (double)a.w_iso * s / ((double)Tn * (double)E);
     }
   } else {
-    for (int t = 0; t < T; ++t) a.wconf[t] = 1.0;
+    for (int t = lane; t < T; t += 64) a.wconf[t] = 1.0;
   }
+  if (lane != 0) return;
   const double l_tr = (sum_tm + sum_pt) / Tn;
   double terms[kTerms] = {l_tr + l_iso, l_tr, l_iso, cd_max, sum_pt / Tn, sum_tm / Tn, wc,
                           (double)e, 0.0};
