@@ -91,14 +91,15 @@ def apply_dct(g: np.ndarray, r: int, lam: float) -> np.ndarray:
     return out.reshape(g.shape)
 
 
-def apply_levels(flat: np.ndarray, res, lams, method: str = "dct") -> np.ndarray:
-    """Precondition one transition's packed gradient level by level (Eq. 3)."""
+def apply_levels(flat: np.ndarray, res, lams, method: str = "dct", channels: int = 3) -> np.ndarray:
+    """Precondition one transition's packed gradient level by level (Eq. 3),
+    every channel of a level alike."""
     fn = apply_dct if method == "dct" else apply_dense
     out, off = [], 0
     flat = np.asarray(flat, dtype=np.float64)
     for r, lam in zip(res, lams):
-        n = 3 * r ** 3
-        out.append(fn(flat[off:off + n].reshape(3, r ** 3), r, lam).reshape(-1))
+        n = channels * r ** 3
+        out.append(fn(flat[off:off + n].reshape(channels, r ** 3), r, lam).reshape(-1))
         off += n
     return np.concatenate(out)
 

@@ -34,6 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import adam as _adam
+from . import cayley as _cy
 from . import chamfer as _ch
 from . import mesh as _mesh
 from . import precond as _pc
@@ -136,7 +137,7 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
          phat32=None, xhat32=None, workers: int = 1, precond_method: str = "dct",
          grad_override=None, pgrad_override=None, masks=None, x0_state=None,
          gx0_override=None, pgx0_override=None, t_norm: int | None = None,
-         cd_max: float | None = None) -> StepResult:
+         cd_max: float | None = None, channels: int = 3) -> StepResult:
     """One iteration: warp, Chamfer + isometry losses, gradient, preconditioner, Adam.
 
     points (F, 3, N) float32; template (3, V) float32 or None; edges (2, E);
@@ -159,6 +160,9 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     ``t_norm`` / ``cd_max`` (one chain of a sequence propagated both ways from
     its keyframe, see ``step_keyframe``) replace T in the 1/T of Eq. 14 and
     Eq. 18 and the chain's own cd_max of Eq. 17.
+    ``channels`` = 6 takes the paper's own cells [z; t] (Eq. 4-7, ``cayley``):
+    every warp is x' = R(z^) x + t^, the adjoints are the rotation-aware ones,
+    and the preconditioner and Adam treat all six channels of a level alike.
     """
     points = np.asarray(points)
     f = points.shape[0]
@@ -169,14 +173,32 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     theta = np.asarray(theta, np.float64)
     has_tm = template is not None and np.asarray(template).shape[1] > 0
     tn = t_count if t_norm is None else int(t_norm)
+    if channels == 6:
+        def warp_fn(th, x):
+            return _cy.warp6(th, res, x, ls)
 
-    phat = np.stack([_wp.warp(theta[t], res, points[t], ls) for t in range(t_count)])
+        def grid_adj(th, x, g):
+            return _cy.grid_adjoint6(th, res, x, g, ls)
+
+        def pos_adj(th, x, g):
+            return _cy.position_adjoint6(th, res, x, g, ls)
+    else:
+        def warp_fn(th, x):
+            return _wp.warp(th, res, x, ls)
+
+        def grid_adj(th, x, g):
+            return _wp.grid_adjoint(res, x, g, ls)
+
+        def pos_adj(th, x, g):
+            return _wp.position_adjoint(th, res, x, g, ls)
+
+    phat = np.stack([warp_fn(theta[t], points[t]) for t in range(t_count)])
     xhat = None
     if has_tm:
         xs = [np.asarray(template, np.float64)]
         for t in range(t_count):
             src = xs[t] if xhat32 is None else np.asarray(xhat32[t], np.float64)
-            xs.append(_wp.warp(theta[t], res, src, ls))
+            xs.append(warp_fn(theta[t], src))
         xhat = np.stack(xs)
     p_nn = phat.astype(np.float32) if phat32 is None else np.asarray(phat32, np.float32)
     x_nn = None
@@ -223,7 +245,7 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
                                     hp.alpha, 1.0 / tn, 1.0 / tn)
                        for t in range(t_count)])
     r.g_phat = g_phat
-    grad = np.stack([_wp.grid_adjoint(res, points[t], g_phat[t], ls) for t in range(t_count)])
+    grad = np.stack([grid_adj(theta[t], points[t], g_phat[t]) for t in range(t_count)])
     if has_tm:
         g_x = np.stack([_ch.gradient(x_nn[t + 1], points[t + 1], r.nn["tm_ab"][t], r.nn["tm_ba"][t],
                                      hp.alpha, w_conf[t] / tn, w_conf[t] / tn)
@@ -232,13 +254,13 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
         chain_pos = x_nn
         lam = g_x[t_count - 1]
         for t in range(t_count - 1, -1, -1):
-            grad[t] += _wp.grid_adjoint(res, chain_pos[t], lam, ls)
+            grad[t] += grid_adj(theta[t], chain_pos[t], lam)
             if t > 0:
-                lam = g_x[t - 1] + _wp.position_adjoint(theta[t], res, chain_pos[t], lam, ls)
+                lam = g_x[t - 1] + pos_adj(theta[t], chain_pos[t], lam)
     r.grad = grad
     g_in = grad if grad_override is None else np.asarray(grad_override, np.float64)
     if masks is None:
-        pgrad = np.stack([_pc.apply_levels(g_in[t], res, lams, precond_method)
+        pgrad = np.stack([_pc.apply_levels(g_in[t], res, lams, precond_method, channels)
                           for t in range(t_count)])
     else:
         pgrad = np.stack([_pr.apply_levels_masked(g_in[t], res, lams, masks[t])
@@ -248,11 +270,11 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     th, mm, vv = np.empty_like(theta), np.empty_like(theta), np.empty_like(theta)
     off = 0
     for l, rr in enumerate(res):
-        sl = slice(off, off + 3 * rr ** 3)
+        sl = slice(off, off + channels * rr ** 3)
         th[:, sl], mm[:, sl], vv[:, sl] = _adam.update(
             theta[:, sl], np.asarray(m)[:, sl], np.asarray(v)[:, sl], p_in[:, sl], etas[l],
             epoch + 1, hp.beta1, hp.beta2, hp.eps)
-        off += 3 * rr ** 3
+        off += channels * rr ** 3
     r.theta, r.m, r.v = th, mm, vv
     if x0_state is not None and has_tm:
         x0 = np.asarray(template, np.float32)

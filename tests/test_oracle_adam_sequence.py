@@ -296,3 +296,57 @@ def test_two_way_ends_reduce_to_one_chain():
     k3 = S.step_keyframe(seq.points, seq.template, seq.edges, res, theta, z, z, 1, 3, hp)
     assert k3.branches[1] is None and k3.loss == rev.loss
     np.testing.assert_array_equal(k3.theta, rev.theta)
+
+
+def _frozen_loss6(seq, res, theta, ref, hp):
+    """As _frozen_loss for the six-channel cells (x' = R(z^) x + t^)."""
+    from oracle import cayley as CY
+    pts = seq.points
+    t_count = pts.shape[0] - 1
+    ls = hp.scale(len(res))
+    tot = 0.0
+    xs = [seq.template.astype(np.float64)]
+    for t in range(t_count):
+        xs.append(CY.warp6(theta[t], res, xs[t], ls))
+    for t in range(t_count):
+        ph = CY.warp6(theta[t], res, pts[t], ls)
+        tgt = pts[t + 1]
+        cpt = C.direction_loss(ph, tgt, ref.nn["pt_ab"][t], hp.alpha) + \
+            C.direction_loss(tgt, ph, ref.nn["pt_ba"][t], hp.alpha)
+        ctm = C.direction_loss(xs[t + 1], tgt, ref.nn["tm_ab"][t], hp.alpha) + \
+            C.direction_loss(tgt, xs[t + 1], ref.nn["tm_ba"][t], hp.alpha)
+        tot += ref.w_conf[t] * ctm + cpt
+    return tot / t_count + S.isometry(np.stack(xs), seq.edges, hp.w_iso)[0]
+
+
+def test_step_six_channel_gradient_finite_difference():
+    """The paper's cells (Eq. 4-7) in the full step: the reverse sweep through
+    the rotation-aware adjoints against central differences of the loss, on
+    rotation (z) and translation (t) channels alike; the preconditioner and
+    Adam treat the six channels of a level alike."""
+    from oracle import precond as PC
+    seq = _tiny_sequence(frames=3, n=40, subdiv=1, seed=21)
+    res = (1, 2, 4)
+    hp = S.Hyper(e_max=10)
+    rng = np.random.default_rng(22)
+    tot = 6 * sum(r ** 3 for r in res)
+    theta = rng.normal(0, 0.05, (2, tot))
+    z = np.zeros_like(theta)
+    ref = S.step(seq.points, seq.template, seq.edges, res, theta, z, z, epoch=1, hp=hp,
+                 channels=6)
+    h = 1e-5
+    for t in range(2):
+        for k in rng.choice(tot, 6, replace=False):
+            tp, tm = theta.copy(), theta.copy()
+            tp[t, k] += h
+            tm[t, k] -= h
+            fd = (_frozen_loss6(seq, res, tp, ref, hp) - _frozen_loss6(seq, res, tm, ref, hp)) / (2 * h)
+            assert abs(fd - ref.grad[t, k]) <= 2e-4 * max(abs(fd), 1e-3), (t, k, fd, ref.grad[t, k])
+    # the preconditioner acts on each of the six channels of a level as on the three
+    lams = hp.schedule(len(res))[1]
+    off = 0
+    for r, lam in zip(res, lams):
+        blk = ref.grad[0][off:off + 6 * r ** 3].reshape(6, r ** 3)
+        np.testing.assert_allclose(ref.pgrad[0][off:off + 6 * r ** 3].reshape(6, -1),
+                                   PC.apply_dct(blk, r, lam), atol=1e-15)
+        off += 6 * r ** 3
