@@ -422,6 +422,10 @@ struct pdg_problem {
   CGPlanDev cg;
   AdamLevels adam;
   unsigned fused = 0u;                             // levels whose Adam ran in the preconditioner
+  // six-channel cells [z; t] (Eq. 4-7): rotation adjoints of the point and
+  // template samples, and the conjugate-gradient plan of the t half
+  float *u_p = nullptr, *u_t = nullptr;
+  CGPlanDev cg_t;
   // optimisation of X_0 (Eq. 10, Sec. 3.6)
   bool opt_x0 = false;
   float *gx0 = nullptr, *pgx0 = nullptr;           // dL_mesh/dX_0, preconditioned
@@ -456,7 +460,11 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
     set_error("problem descriptor is NULL");
     return PDG_EINVAL;
   }
-  PDG_TRY(check_grid(&pd->grid));
+  PDG_TRY(check_grid(&pd->grid, true));
+  if (pd->grid.channels == 6 && pd->prune_mask) {
+    set_error("pruned grids are three-channel only");
+    return PDG_EUNSUPPORTED;
+  }
   if (pd->frames < 2) {
     set_error("frames = %d: need at least 2", pd->frames);
     return PDG_EINVAL;
@@ -492,7 +500,9 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   }
   float lam[PDG_MAX_LEVELS];
   for (int l = 0; l < pd->grid.levels; ++l) lam[l] = pd->hp.lambda0 * powf(pd->hp.lambda_growth, (float)l);
-  PDG_TRY(check_precond_args(&pd->grid, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
+  pdg_grid_desc d3 = pd->grid;   // six channels are preconditioned as two three-channel halves
+  d3.channels = 3;
+  PDG_TRY(check_precond_args(&d3, lam, 1, pd->precond_method, pd->cg_iters, pd->cg_tol));
   if ((pd->template_adam_m || pd->template_adam_v) &&
       (!pd->template_adam_m || !pd->template_adam_v || pd->verts < 1 ||
        !(pd->hp.mesh_lambda >= 0.f) || !isfinite(pd->hp.mesh_lambda) || !(pd->hp.mesh_lr > 0.f))) {
@@ -564,6 +574,10 @@ void layout(pdg_problem &p, Carve &c) {
   if (p.nrev > smax) smax = p.nrev;
   if (2 * E > smax) smax = 2 * E;
   p.sort = c.take<char>((long long)radix_sort_bytes(smax));
+  if (p.g.ch == 6) {
+    p.u_p = c.take<float>(T * 3 * N);
+    p.u_t = c.take<float>(T * 3 * V);
+  }
   if (p.opt_x0) {
     p.gx0 = c.take<float>(3 * V);
     p.pgx0 = c.take<float>(3 * V);
@@ -619,7 +633,12 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   }
   p.adam.off[p.g.levels] = p.g.size;
   // every buffer the solver touches is carved at 256-byte alignment
-  p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol, true);
+  if (p.g.ch == 6) {   // each half of the six channels is preconditioned as a grid
+    p.cg = cg_plan(half_view(p.g, 0), p.T, lam, pd.cg_iters, pd.cg_tol, true);
+    p.cg_t = cg_plan(half_view(p.g, 1), p.T, lam, pd.cg_iters, pd.cg_tol, true);
+  } else {
+    p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol, true);
+  }
   if (pd.prune_mask) cg_set_mask(p.cg, p.g, pd.prune_mask);
 }
 
@@ -655,12 +674,24 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
   const pdg_hyper &h = p.d.hp;
   switch (stage) {
     case PDG_STAGE_WARP:  // P^_t = warp(G_t, P_{t-1}); X_t = warp(G_t, X_{t-1}) (Eq. 1, 8)
-      // points and vertices in Morton order of P_t and X_0 (cache reuse of grid cells)
-      PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T,
-                          st, p.fperm, N));
-      if (p.has_tm)
-        PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T,
-                                  p.tperm, st));
+      if (g.ch == 6) {   // x' = R(z^) x + t^ (Eq. 5-7), one launch per transition
+        for (long long t = 0; t < T; ++t)
+          PDG_TRY(launch_warp6(g, p.d.params + t * P, p.d.points + t * 3 * N, p.phat + t * 3 * N,
+                               N, st));
+        if (p.has_tm) {
+          PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
+          for (long long t = 0; t < T; ++t)
+            PDG_TRY(launch_warp6(g, p.d.params + t * P, p.xhat + t * 3 * V,
+                                 p.xhat + (t + 1) * 3 * V, V, st));
+        }
+      } else {
+        // points and vertices in Morton order of P_t and X_0 (cache reuse of grid cells)
+        PDG_TRY(launch_warp(g, p.d.params, P, p.d.points, 3 * N, N, p.phat, 3 * N, N, N, (int)T,
+                            st, p.fperm, N));
+        if (p.has_tm)
+          PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T,
+                                    p.tperm, st));
+      }
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
         // screen packs of the moving sets (P^_t, X_t), which change every step
         PDG_TRY(launch_fill((float *)p.maxnorm, (long long)p.nseg * kMaxnormStride, 0.f, st));
@@ -705,6 +736,23 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, p.rkeys, p.rvals, p.nrev,
                                          (float)h.alpha, p.w, p.rpart, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(iso_args(p), st));
+      if (g.ch == 6) {
+        // reverse sweep of Eq. 8 one transition at a time: lam_{t-1} = direct
+        // + J_t^T lam_t, with the rotation adjoint u_t of every vertex on the way
+        if (p.has_tm) {
+          PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
+          for (long long t = T - 1; t >= 0; --t) {
+            float *prev = t > 0 ? p.lam + (t - 1) * 3 * V : nullptr;
+            PDG_TRY(launch_adjoint6(g, p.d.params + t * P, p.xhat + t * 3 * V, p.lam + t * 3 * V,
+                                    p.u_t + t * 3 * V, prev, V, st));
+            if (prev) PDG_TRY(launch_add(prev, p.gxhat + (t - 1) * 3 * V, 3 * V, st));
+          }
+        }
+        for (long long t = 0; t < T; ++t)
+          PDG_TRY(launch_adjoint6(g, p.d.params + t * P, p.d.points + t * 3 * N,
+                                  p.gphat + t * 3 * N, p.u_p + t * 3 * N, nullptr, N, st));
+        return PDG_OK;
+      }
       if (p.has_tm)
         PDG_TRY(launch_chain_reverse(g, p.d.params, P, p.xhat, p.gxhat, p.lam, V, (int)T,
                                      p.tperm, st));
@@ -722,10 +770,30 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
         PDG_TRY(scatter_entries(g, (int)T, sl.list[1], p.tkeys, p.tvals, p.pstart_t, p.sort, st));
         PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[1], st));
       }
-      return launch_gather(g, (int)T, sl, N + V, p.grad, p.gscratch, st);
+      if (g.ch != 6) return launch_gather(g, (int)T, sl, N + V, p.grad, p.gscratch, st);
+      // six channels: translation channels from the position adjoints, then
+      // the rotation channels from u on the same sorted entries
+      PDG_TRY(launch_gather(g, (int)T, sl, N + V, p.grad, p.gscratch, st, 3));
+      sl.list[0].lam = p.u_p;
+      PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[0], st, true));
+      if (p.has_tm) {
+        sl.list[1].lam = p.u_t;
+        PDG_TRY(launch_scatter_stage(g, (int)T, sl.list[1], st, true));
+      }
+      return launch_gather(g, (int)T, sl, N + V, p.grad, p.gscratch, st, 0);
     }
     case PDG_STAGE_PRECOND:  // (I + lambda_l L_l)^-2 (Eq. 3)
       p.fused = 0u;
+      if (g.ch == 6) {   // each half of the six channels as a three-channel grid
+        PDG_TRY(launch_copy(p.pgrad, p.grad, T * P, st));
+        for (int half = 0; half < 2; ++half) {
+          if (p.d.precond_method == PDG_PRECOND_DCT)
+            PDG_TRY(run_dct(half_view(g, half), (int)T, p.lambda_l, p.pgrad, p.pgrad, p.dctws, st));
+          else
+            PDG_TRY(run_cg(half ? p.cg_t : p.cg, p.pgrad, T * P, p.cgws, st));
+        }
+        return PDG_OK;
+      }
       if (p.d.precond_method == PDG_PRECOND_DCT) {
         if (!fuse) return run_dct(g, (int)T, p.lambda_l, p.grad, p.pgrad, p.dctws, st);
         // full step: levels whose last inverse pass can apply Adam do so
@@ -1054,7 +1122,7 @@ pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64
 
 pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int32_t method,
                                       size_t *bytes) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));
   if (!bytes || batch < 0) {
     set_error("bytes NULL or batch < 0");
     return PDG_EINVAL;
@@ -1070,7 +1138,7 @@ pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int
   }
   float lam[PDG_MAX_LEVELS];
   for (int l = 0; l < d->levels; ++l) lam[l] = 1.0f;
-  CGPlanDev p = cg_plan(g, batch, lam, 1, 0.5, false);
+  CGPlanDev p = cg_plan(g.ch == 6 ? half_view(g, 0) : g, batch, lam, 1, 0.5, false);
   *bytes = cg_ws_bytes(p, g.size * batch);
   return PDG_OK;
 }
@@ -1078,20 +1146,29 @@ pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int
 pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *g, int32_t batch,
                             int32_t method, int32_t iters, double tol, void *ws, size_t ws_bytes,
                             hipStream_t stream) {
-  PDG_TRY(check_precond_args(d, lambda, batch, method, iters, tol));
+  PDG_TRY(check_grid(d, true));
+  pdg_grid_desc d3 = *d;   // six channels: the rotation and translation halves as grids
+  d3.channels = 3;
+  PDG_TRY(check_precond_args(&d3, lambda, batch, method, iters, tol));
   if (batch == 0) return PDG_OK;
   PDG_TRY(need(g, "g"));
   size_t nb = 0;
   PDG_TRY(pdg_precondition_workspace(d, batch, method, &nb));
   PDG_TRY(need_ws(ws, ws_bytes, nb));
   const GridDev gd = make_grid(*d);
+  const int halves = gd.ch == 6 ? 2 : 1;
   if (method == PDG_PRECOND_DCT) {
     PDG_TRY(dct_basis(gd, ws, stream));
-    return run_dct(gd, batch, lambda, g, g, ws, stream);
+    for (int h = 0; h < halves; ++h)
+      PDG_TRY(run_dct(halves == 2 ? half_view(gd, h) : gd, batch, lambda, g, g, ws, stream));
+    return PDG_OK;
   }
   const bool aligned16 = ((uintptr_t)g & 15) == 0;
-  CGPlanDev p = cg_plan(gd, batch, lambda, iters, tol, aligned16);
-  return run_cg(p, g, gd.size * batch, ws, stream);
+  for (int h = 0; h < halves; ++h) {
+    CGPlanDev p = cg_plan(halves == 2 ? half_view(gd, h) : gd, batch, lambda, iters, tol, aligned16);
+    PDG_TRY(run_cg(p, g, gd.size * batch, ws, stream));
+  }
+  return PDG_OK;
 }
 
 pdg_status pdg_prune_mask_words(const pdg_grid_desc *d, int64_t *words) {

@@ -192,6 +192,12 @@ long long row_count(const GridDev &g);
 pdg_status launch_row_table(const GridDev &g, const uint32_t *keys, long long nent, int segs,
                             int *rstart, hipStream_t st);
 pdg_status launch_fill(float *p, long long count, float value, hipStream_t st);
+// dst += src (count floats)
+pdg_status launch_add(float *dst, const float *src, long long count, hipStream_t st);
+// Three-channel view of half of a six-channel grid (half 0: the rotation
+// channels z, 1: the translation channels t of every level), same stack
+// stride: the preconditioner treats each half as a grid of its own.
+GridDev half_view(const GridDev &g, int half);
 pdg_status launch_copy(float *dst, const float *src, long long count, hipStream_t st);
 // Upload up to 2 KB of host bytes to device memory in stream order (the bytes
 // travel as a kernel argument, so the call is safe under graph capture).

@@ -942,6 +942,31 @@ pdg_status launch_fill(float *p, long long count, float value, hipStream_t st) {
   return launched("fill");
 }
 
+namespace {
+__global__ __launch_bounds__(256) void add_kernel(float *__restrict__ dst,
+                                                  const float *__restrict__ src, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] += src[i];
+}
+}  // namespace
+
+pdg_status launch_add(float *dst, const float *src, long long count, hipStream_t st) {
+  if (count <= 0) return PDG_OK;
+  long long blocks = div_up(count, 256);
+  if (blocks > 65536) blocks = 65536;
+  add_kernel<<<(unsigned)blocks, 256, 0, st>>>(dst, src, count);
+  return launched("add");
+}
+
+GridDev half_view(const GridDev &g, int half) {
+  GridDev v = g;
+  v.ch = 3;
+  for (int l = 0; l < g.levels; ++l)
+    v.off[l] = g.off[l] + (long long)half * 3 * g.res[l] * g.res[l] * g.res[l];
+  return v;
+}
+
 pdg_status launch_copy(float *dst, const float *src, long long count, hipStream_t st) {
   if (count <= 0) return PDG_OK;
   long long blocks = div_up(count, 256);

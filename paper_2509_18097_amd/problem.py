@@ -73,7 +73,7 @@ class Problem:
                  cg_tol: float = 1e-7, level_scale: float | None = None,
                  params: torch.Tensor | None = None, stream: torch.cuda.Stream | None = None,
                  prune_mask: torch.Tensor | None = None, prune_halo: int | None = None,
-                 optimize_template: bool = False, keyframe: int = 0):
+                 optimize_template: bool = False, keyframe: int = 0, channels: int = 3):
         """prune_mask (T, words) int32 as ``prune_mask`` writes it, or prune_halo
         (the paper: 3) to build it from each transition's two frames, makes the
         grids pruned (Sec. 3.6; conjugate-gradient preconditioner only).
@@ -81,7 +81,9 @@ class Problem:
         ``template`` (``self.template``), with Adam moments ``template_m/v``.
         keyframe k > 0 places X_0 at frame k and propagates both ways (the
         grids, masks and moments in chain order: the backward chain's first,
-        see pdg_problem_desc.keyframe); ``branch(0/1)`` gives each chain."""
+        see pdg_problem_desc.keyframe); ``branch(0/1)`` gives each chain.
+        channels = 6 takes the paper's own cells [z; t] (Eq. 4-7): params of
+        grid_size(res, 6) floats per transition."""
         self.hp = hp or HyperParams()
         self.keyframe = int(keyframe)
         self.res = tuple(int(r) for r in res)
@@ -93,7 +95,8 @@ class Problem:
         dev = points.device
         self.frames, _, self.n = points.shape
         self.T = self.frames - 1
-        self.P = L.grid_size(self.res)
+        self.channels = int(channels)
+        self.P = L.grid_size(self.res, self.channels)
         if template is not None and template.shape[1] > 0:
             self.template = L._dev(template, torch.float32, "template")
             if optimize_template:
@@ -118,7 +121,7 @@ class Problem:
         d.template_verts = L._ptr(self.template)
         d.n_edges = self.E
         d.edges = L._ptr(self.edges) if self.E > 0 else None
-        d.grid = L.grid_desc(self.res, level_scale)
+        d.grid = L.grid_desc(self.res, level_scale, self.channels)
         d.hp = self.hp.to_c()
         d.chamfer_mode = L.CHAMFER_MODES[chamfer_mode]
         d.precond_method = L.PRECOND_METHODS[precond]
