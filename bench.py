@@ -76,6 +76,12 @@ def parse():
     ap.add_argument("--prune", type=int, default=None, metavar="HALO",
                     help="pruned grids for the timed step: kept cells = occupied + HALO-cell "
                          "cube (the paper: 3); needs --precond cg")
+    ap.add_argument("--optimize-template", action="store_true",
+                    help="optimise X_0 too in the timed step (Eq. 9-10, Sec. 3.6)")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="the timed step on the paper's grid: six-channel cells, R = 2l - 1, L = 10")
+    ap.add_argument("--keyframe", type=int, default=0,
+                    help="X_0 at this frame, propagated both ways (Sec. 3.3); 0: forward only")
     ap.add_argument("--variants", default="fp32:cg,bf16:cg,fp32:dct",
                     help="other chamfer:precond forms to time on the same GPU ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,16 +100,18 @@ def parse():
     return ap.parse_args()
 
 
-def make_problem(subdiv, chamfer, precond, prune_halo=None, optimize_template=False, keyframe=0):
+def make_problem(subdiv, chamfer, precond, prune_halo=None, optimize_template=False, keyframe=0,
+                 paper_grid=False):
     import torch
     import synth
     from paper_2509_18097_amd.problem import HyperParams, Problem
     seq = synth.deforming_sequence(seed=0, frames=FRAMES, n=NPTS, subdiv=subdiv)
-    prob = Problem(torch.from_numpy(seq.points).cuda(), RES,
+    prob = Problem(torch.from_numpy(seq.points).cuda(), CAYLEY_RES if paper_grid else RES,
                    template=torch.from_numpy(seq.template).cuda(),
                    edges=torch.from_numpy(seq.edges).cuda(), hp=HyperParams(e_max=50),
                    chamfer_mode=chamfer, precond=precond, prune_halo=prune_halo,
-                   optimize_template=optimize_template, keyframe=keyframe)
+                   optimize_template=optimize_template, keyframe=keyframe,
+                   channels=6 if paper_grid else 3)
     return seq, prob
 
 
@@ -138,6 +146,8 @@ def time_stages(prob, reps=3):
     import torch
     st = torch.cuda.current_stream()
     names = ("warp", "nn", "loss", "grad", "scatter", "precond_adam")
+    if getattr(prob, "template_m", None) is not None:
+        names += ("template",)
     for name in names:                   # warm
         prob.stage(name)
     torch.cuda.synchronize()
@@ -172,6 +182,9 @@ def screen_tiles(prob):
     """Candidate tiles screened so far (bf16 mode), else None."""
     if prob.chamfer_mode != "bf16":
         return None
+    if prob.keyframe > 0:
+        return sum(int(ch.buffer("screen_tiles").item())
+                   for ch in (prob.branch(0), prob.branch(1)) if ch is not None)
     return int(prob.buffer("screen_tiles").item())
 
 
@@ -196,7 +209,7 @@ def cg_bytes(prob):
         kappa = 1.0 + 12.0 * lam         # a-priori CG count (as the library computes it)
         rho = (math.sqrt(kappa) - 1.0) / (math.sqrt(kappa) + 1.0)
         k = math.ceil(math.log(2.0 / 1e-7) / -math.log(rho))
-        cells = T * 3 * r ** 3
+        cells = T * prob.channels * r ** 3
         it_cells = cells if kept is None else 3 * int(kept[:, l].sum().item())
         total += 2 * (12 * cells + k * 32 * it_cells)
     return total
@@ -208,7 +221,8 @@ def dct_flops(prob):
     is 2R flops per value, the even/odd form used for R = 64 and 128 half of
     that (two length-R/2 products); R = 1 levels are skipped."""
     T = prob.T
-    return sum(6 * (r if r in (64, 128) else 2 * r) * T * 3 * r ** 3 for r in prob.res if r > 1)
+    return sum(6 * (r if r in (64, 128) else 2 * r) * T * prob.channels * r ** 3
+               for r in prob.res if r > 1)
 
 
 def roofline(prob, stages, chamfer, precond):
@@ -405,6 +419,27 @@ def time_two_way(subdiv, chamfer, precond, keyframe, steps=10):
     return out
 
 
+def time_step6(subdiv, chamfer, precond, steps=10):
+    """The headline sequence on the paper's own grid: six-channel cells [z; t]
+    (Eq. 4-7) on the 2l - 1 schedule with L = 10 (R = 1, 3, .., 19), full step
+    (rotation-aware warps and adjoints, both halves preconditioned)."""
+    import torch
+    import synth
+    from paper_2509_18097_amd.problem import HyperParams, Problem
+    seq = synth.deforming_sequence(seed=0, frames=FRAMES, n=NPTS, subdiv=subdiv)
+    prob = Problem(torch.from_numpy(seq.points).cuda(), CAYLEY_RES,
+                   template=torch.from_numpy(seq.template).cuda(),
+                   edges=torch.from_numpy(seq.edges).cuda(), hp=HyperParams(e_max=50),
+                   chamfer_mode=chamfer, precond=precond, channels=6)
+    ms, _ = time_steps(prob, steps, 2)
+    out = {"grid": "six-channel cells, R = 2l - 1, L = 10", "ms_per_step": round(ms, 4),
+           "iterations_per_s": round(1000.0 / ms, 4)}
+    prob.close()
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_keyframe(seq, reps=20):
     """Keyframe selection (Sec. 3.5, Eq. 19-20) over the sequence's frames:
     one bit per occupied 128^3 voxel and frame, population counts, the
@@ -521,7 +556,8 @@ def main():
         return
     if args.prune is not None and args.precond != "cg":
         sys.exit("--prune needs --precond cg (the DCT solve needs the full box)")
-    seq, prob = make_problem(args.subdiv, args.chamfer, args.precond, args.prune)
+    seq, prob = make_problem(args.subdiv, args.chamfer, args.precond, args.prune,
+                             args.optimize_template, args.keyframe, args.paper_grid)
     torch.cuda.synchronize()
     ms, wall = time_steps(prob, args.steps, args.warmup)
     value = 1000.0 / ms
@@ -543,11 +579,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"deforming-ellipsoid sequence, {FRAMES} frames x {NPTS} points, "
                                f"icosphere template {prob.V} verts / {prob.E} edges, grids "
-                               f"{'/'.join(str(r) for r in RES)}^3 x 3 ch per transition",
+                               f"{'/'.join(str(r) for r in prob.res)}^3 x {prob.channels} ch per "
+                               f"transition",
                    "frames": FRAMES, "points_per_frame": NPTS, "template_verts": prob.V,
-                   "template_edges": prob.E, "grid_res": list(RES), "chamfer": args.chamfer,
+                   "template_edges": prob.E, "grid_res": list(prob.res), "chamfer": args.chamfer,
                    "precond": args.precond, "graph_replay": True,
-                   **({"prune_halo": args.prune} if args.prune is not None else {})},
+                   **({"prune_halo": args.prune} if args.prune is not None else {}),
+                   **({"optimize_template": True} if args.optimize_template else {}),
+                   **({"keyframe": args.keyframe} if args.keyframe else {}),
+                   **({"cells": "six-channel, R = 2l - 1, L = 10"} if args.paper_grid else {})},
         "loss_last_step": terms["loss"],
     }
     if stages:
@@ -576,6 +616,7 @@ def main():
         result["pruned"] = time_pruned(args.subdiv, args.chamfer)
         result["template_opt"] = time_template(args.subdiv, args.chamfer, args.precond)
         result["two_way"] = time_two_way(args.subdiv, args.chamfer, args.precond, FRAMES // 2)
+        result["step6"] = time_step6(args.subdiv, args.chamfer, args.precond)
     if args.serve > 0:
         result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
     if not args.no_cpu_baseline:
