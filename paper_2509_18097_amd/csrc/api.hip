@@ -675,9 +675,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
   switch (stage) {
     case PDG_STAGE_WARP:  // P^_t = warp(G_t, P_{t-1}); X_t = warp(G_t, X_{t-1}) (Eq. 1, 8)
       if (g.ch == 6) {   // x' = R(z^) x + t^ (Eq. 5-7), one launch per transition
-        for (long long t = 0; t < T; ++t)
-          PDG_TRY(launch_warp6(g, p.d.params + t * P, p.d.points + t * 3 * N, p.phat + t * 3 * N,
-                               N, st));
+        PDG_TRY(launch_warp6_batch(g, p.d.params, P, p.d.points, 3 * N, p.phat, 3 * N, N, (int)T,
+                                   st));
         if (p.has_tm) {
           PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
           for (long long t = 0; t < T; ++t)
@@ -743,14 +742,14 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
           PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
           for (long long t = T - 1; t >= 0; --t) {
             float *prev = t > 0 ? p.lam + (t - 1) * 3 * V : nullptr;
-            PDG_TRY(launch_adjoint6(g, p.d.params + t * P, p.xhat + t * 3 * V, p.lam + t * 3 * V,
-                                    p.u_t + t * 3 * V, prev, V, st));
-            if (prev) PDG_TRY(launch_add(prev, p.gxhat + (t - 1) * 3 * V, 3 * V, st));
+            PDG_TRY(launch_adjoint6_batch(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0,
+                                          p.lam + t * 3 * V, 0, p.u_t + t * 3 * V, 0, prev,
+                                          prev ? p.gxhat + (t - 1) * 3 * V : nullptr, 0, V, 1,
+                                          st));
           }
         }
-        for (long long t = 0; t < T; ++t)
-          PDG_TRY(launch_adjoint6(g, p.d.params + t * P, p.d.points + t * 3 * N,
-                                  p.gphat + t * 3 * N, p.u_p + t * 3 * N, nullptr, N, st));
+        PDG_TRY(launch_adjoint6_batch(g, p.d.params, P, p.d.points, 3 * N, p.gphat, 3 * N, p.u_p,
+                                      3 * N, nullptr, nullptr, 0, N, (int)T, st));
         return PDG_OK;
       }
       if (p.has_tm)

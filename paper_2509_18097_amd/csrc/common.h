@@ -160,6 +160,15 @@ pdg_status launch_warp6(const GridDev &g, const float *grids, const float *x, fl
 // d<g, out>/dz^ ([3][n]); gx (nullable) receives d<g, out>/dx.
 pdg_status launch_adjoint6(const GridDev &g, const float *grids, const float *x,
                            const float *gout, float *u, float *gx, long long n, hipStream_t st);
+// The same over `batch` grids / sample sets at the given strides (floats);
+// gx = J^T g + gx_add (gx_add nullable, strided like gx).
+pdg_status launch_warp6_batch(const GridDev &g, const float *grids, long long gs, const float *x,
+                              long long xs, float *out, long long os, long long n, int batch,
+                              hipStream_t st);
+pdg_status launch_adjoint6_batch(const GridDev &g, const float *grids, long long gs,
+                                 const float *x, long long xs, const float *gout, long long gos,
+                                 float *u, long long us, float *gx, const float *gx_add,
+                                 long long gxs, long long n, int batch, hipStream_t st);
 pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, const float *x,
                        long long xstride, long long ldx, float *out, long long ostride,
                        long long ldo, long long n, int batch, hipStream_t st,

@@ -149,11 +149,16 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 
 // out = R(z^) p + t^, R in the closed form of the Cayley map (Eq. 5):
 // R p = p + 2 (z x p + z x (z x p)) / (1 + |z|^2).
+// Batch b = blockIdx.y reads grids G + b gs and samples x + b xs (SoA [3][n]).
 __global__ __launch_bounds__(256) void warp6_kernel(GridDev g, const float *__restrict__ G,
-                                                    const float *__restrict__ x,
-                                                    float *__restrict__ out, long long n) {
+                                                    long long gs, const float *__restrict__ x,
+                                                    long long xs, float *__restrict__ out,
+                                                    long long os, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  G += blockIdx.y * gs;
+  x += blockIdx.y * xs;
+  out += blockIdx.y * os;
   const float3 p = make_float3(x[i], x[n + i], x[2 * n + i]);
   float T[6];
   cell_sum(g, G, p.x, p.y, p.z, T);
@@ -207,13 +212,24 @@ __device__ __forceinline__ void level_jt6(const float *__restrict__ L, int R, fl
 //        N = z x p + z x (z x p), d = 1 + |z|^2   (the derivative of R p);
 //   gx = R^T q + level_scale * sum_l sum_c [u; q]_c grad trilerp(G_l,c, p),
 //        R^T q = q + (2/d) (z x (z x q) - z x q).
+// Batch b = blockIdx.y as warp6_kernel; gx (when set) = J^T gout + gx_add
+// (gx_add nullable, laid out like gx).
 __global__ __launch_bounds__(256) void adjoint6_kernel(GridDev g, const float *__restrict__ G,
-                                                       const float *__restrict__ x,
-                                                       const float *__restrict__ gout,
-                                                       float *__restrict__ uo,
-                                                       float *__restrict__ gx, long long n) {
+                                                       long long gs, const float *__restrict__ x,
+                                                       long long xs, const float *__restrict__ gout,
+                                                       long long gos, float *__restrict__ uo,
+                                                       long long us, float *__restrict__ gx,
+                                                       const float *__restrict__ gx_add,
+                                                       long long gxs, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const long long b = blockIdx.y;
+  G += b * gs;
+  x += b * xs;
+  gout += b * gos;
+  if (uo) uo += b * us;
+  if (gx) gx += b * gxs;
+  if (gx_add) gx_add += b * gxs;
   const float3 p = make_float3(x[i], x[n + i], x[2 * n + i]);
   const float3 q = make_float3(gout[i], gout[n + i], gout[2 * n + i]);
   float T[6];
@@ -242,9 +258,17 @@ __global__ __launch_bounds__(256) void adjoint6_kernel(GridDev g, const float *_
       j1 += b;
       j2 += c;
     }
-    gx[i] = (q.x + ca * (zzq.x - zq.x)) + g.scale * j0;
-    gx[n + i] = (q.y + ca * (zzq.y - zq.y)) + g.scale * j1;
-    gx[2 * n + i] = (q.z + ca * (zzq.z - zq.z)) + g.scale * j2;
+    float r0 = (q.x + ca * (zzq.x - zq.x)) + g.scale * j0;
+    float r1 = (q.y + ca * (zzq.y - zq.y)) + g.scale * j1;
+    float r2 = (q.z + ca * (zzq.z - zq.z)) + g.scale * j2;
+    if (gx_add) {
+      r0 += gx_add[i];
+      r1 += gx_add[n + i];
+      r2 += gx_add[2 * n + i];
+    }
+    gx[i] = r0;
+    gx[n + i] = r1;
+    gx[2 * n + i] = r2;
   }
 }
 
@@ -881,18 +905,40 @@ pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, 
   return launched("warp");
 }
 
+// Small launches (a template chain's single transition) take 64-thread
+// workgroups so that the work spreads over every CU.
+static int six_threads(long long n, int batch) {
+  return div_up(n, 256) * (long long)batch < 1024 ? 64 : 256;
+}
+
+pdg_status launch_warp6_batch(const GridDev &g, const float *grids, long long gs, const float *x,
+                              long long xs, float *out, long long os, long long n, int batch,
+                              hipStream_t st) {
+  if (n <= 0 || batch <= 0) return PDG_OK;
+  const int nt = six_threads(n, batch);
+  warp6_kernel<<<dim3(div_up(n, nt), batch), nt, 0, st>>>(g, grids, gs, x, xs, out, os, n);
+  return launched("warp6");
+}
+
 pdg_status launch_warp6(const GridDev &g, const float *grids, const float *x, float *out,
                         long long n, hipStream_t st) {
-  if (n <= 0) return PDG_OK;
-  warp6_kernel<<<div_up(n, 256), 256, 0, st>>>(g, grids, x, out, n);
-  return launched("warp6");
+  return launch_warp6_batch(g, grids, 0, x, 0, out, 0, n, 1, st);
+}
+
+pdg_status launch_adjoint6_batch(const GridDev &g, const float *grids, long long gs,
+                                 const float *x, long long xs, const float *gout, long long gos,
+                                 float *u, long long us, float *gx, const float *gx_add,
+                                 long long gxs, long long n, int batch, hipStream_t st) {
+  if (n <= 0 || batch <= 0 || (!u && !gx)) return PDG_OK;
+  const int nt = six_threads(n, batch);
+  adjoint6_kernel<<<dim3(div_up(n, nt), batch), nt, 0, st>>>(g, grids, gs, x, xs, gout, gos, u, us,
+                                                             gx, gx ? gx_add : nullptr, gxs, n);
+  return launched("adjoint6");
 }
 
 pdg_status launch_adjoint6(const GridDev &g, const float *grids, const float *x,
                            const float *gout, float *u, float *gx, long long n, hipStream_t st) {
-  if (n <= 0 || (!u && !gx)) return PDG_OK;
-  adjoint6_kernel<<<div_up(n, 256), 256, 0, st>>>(g, grids, x, gout, u, gx, n);
-  return launched("adjoint6");
+  return launch_adjoint6_batch(g, grids, 0, x, 0, gout, 0, u, 0, gx, nullptr, 0, n, 1, st);
 }
 
 pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const float *x, long long ldx,
