@@ -679,9 +679,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
                                    st));
         if (p.has_tm) {
           PDG_TRY(launch_copy(p.xhat, p.d.template_verts, 3 * V, st));
-          for (long long t = 0; t < T; ++t)
-            PDG_TRY(launch_warp6(g, p.d.params + t * P, p.xhat + t * 3 * V,
-                                 p.xhat + (t + 1) * 3 * V, V, st));
+          PDG_TRY(launch_chain_warp6(g, p.d.params, P, p.xhat, V, (int)T, st));
         }
       } else {
         // points and vertices in Morton order of P_t and X_0 (cache reuse of grid cells)
@@ -738,16 +736,9 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       if (g.ch == 6) {
         // reverse sweep of Eq. 8 one transition at a time: lam_{t-1} = direct
         // + J_t^T lam_t, with the rotation adjoint u_t of every vertex on the way
-        if (p.has_tm) {
-          PDG_TRY(launch_copy(p.lam + (T - 1) * 3 * V, p.gxhat + (T - 1) * 3 * V, 3 * V, st));
-          for (long long t = T - 1; t >= 0; --t) {
-            float *prev = t > 0 ? p.lam + (t - 1) * 3 * V : nullptr;
-            PDG_TRY(launch_adjoint6_batch(g, p.d.params + t * P, 0, p.xhat + t * 3 * V, 0,
-                                          p.lam + t * 3 * V, 0, p.u_t + t * 3 * V, 0, prev,
-                                          prev ? p.gxhat + (t - 1) * 3 * V : nullptr, 0, V, 1,
-                                          st));
-          }
-        }
+        if (p.has_tm)
+          PDG_TRY(launch_chain_reverse6(g, p.d.params, P, p.xhat, p.gxhat, p.lam, p.u_t, V,
+                                        (int)T, st));
         PDG_TRY(launch_adjoint6_batch(g, p.d.params, P, p.d.points, 3 * N, p.gphat, 3 * N, p.u_p,
                                       3 * N, nullptr, nullptr, 0, N, (int)T, st));
         return PDG_OK;

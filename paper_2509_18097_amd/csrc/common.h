@@ -169,6 +169,14 @@ pdg_status launch_adjoint6_batch(const GridDev &g, const float *grids, long long
                                  const float *x, long long xs, const float *gout, long long gos,
                                  float *u, long long us, float *gx, const float *gx_add,
                                  long long gxs, long long n, int batch, hipStream_t st);
+// The template chain on six-channel cells in one launch each way: xhat
+// [T+1][3][V] with frame 0 = X_0 set; reverse: lam [T][3][V] total adjoints
+// (lam[T-1] = gd[T-1]), u [T][3][V] rotation adjoints of every transition.
+pdg_status launch_chain_warp6(const GridDev &g, const float *params, long long P, float *xhat,
+                              long long V, int T, hipStream_t st);
+pdg_status launch_chain_reverse6(const GridDev &g, const float *params, long long P,
+                                 const float *xhat, const float *gd, float *lam, float *u,
+                                 long long V, int T, hipStream_t st);
 pdg_status launch_warp(const GridDev &g, const float *grids, long long gstride, const float *x,
                        long long xstride, long long ldx, float *out, long long ostride,
                        long long ldo, long long n, int batch, hipStream_t st,

@@ -149,6 +149,19 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 
 // out = R(z^) p + t^, R in the closed form of the Cayley map (Eq. 5):
 // R p = p + 2 (z x p + z x (z x p)) / (1 + |z|^2).
+__device__ __forceinline__ float3 warp6_point(const GridDev &g, const float *__restrict__ G,
+                                              float3 p) {
+  float T[6];
+  cell_sum(g, G, p.x, p.y, p.z, T);
+  const float3 z = make_float3(g.scale * T[0], g.scale * T[1], g.scale * T[2]);
+  const float3 c1 = cross3(z, p), c2 = cross3(z, c1);
+  const float k = 2.0f / (1.0f + dot3(z, z));
+  // t^ added as level_scale * sum, as the translation warp does
+  return make_float3((p.x + k * (c1.x + c2.x)) + g.scale * T[3],
+                     (p.y + k * (c1.y + c2.y)) + g.scale * T[4],
+                     (p.z + k * (c1.z + c2.z)) + g.scale * T[5]);
+}
+
 // Batch b = blockIdx.y reads grids G + b gs and samples x + b xs (SoA [3][n]).
 __global__ __launch_bounds__(256) void warp6_kernel(GridDev g, const float *__restrict__ G,
                                                     long long gs, const float *__restrict__ x,
@@ -159,16 +172,10 @@ __global__ __launch_bounds__(256) void warp6_kernel(GridDev g, const float *__re
   G += blockIdx.y * gs;
   x += blockIdx.y * xs;
   out += blockIdx.y * os;
-  const float3 p = make_float3(x[i], x[n + i], x[2 * n + i]);
-  float T[6];
-  cell_sum(g, G, p.x, p.y, p.z, T);
-  const float3 z = make_float3(g.scale * T[0], g.scale * T[1], g.scale * T[2]);
-  const float3 c1 = cross3(z, p), c2 = cross3(z, c1);
-  const float k = 2.0f / (1.0f + dot3(z, z));
-  // t^ added as level_scale * sum, as the translation warp does
-  out[i] = (p.x + k * (c1.x + c2.x)) + g.scale * T[3];
-  out[n + i] = (p.y + k * (c1.y + c2.y)) + g.scale * T[4];
-  out[2 * n + i] = (p.z + k * (c1.z + c2.z)) + g.scale * T[5];
+  const float3 o = warp6_point(g, G, make_float3(x[i], x[n + i], x[2 * n + i]));
+  out[i] = o.x;
+  out[n + i] = o.y;
+  out[2 * n + i] = o.z;
 }
 
 // sum_c lam_c d/dp trilerp(L_c, p) for one level (zero along clamped axes).
@@ -212,6 +219,37 @@ __device__ __forceinline__ void level_jt6(const float *__restrict__ L, int R, fl
 //        N = z x p + z x (z x p), d = 1 + |z|^2   (the derivative of R p);
 //   gx = R^T q + level_scale * sum_l sum_c [u; q]_c grad trilerp(G_l,c, p),
 //        R^T q = q + (2/d) (z x (z x q) - z x q).
+// u = d<q, R p>/dz^ and (when gx is set) gx = J^T q for one sample.
+__device__ __forceinline__ void adjoint6_point(const GridDev &g, const float *__restrict__ G,
+                                               float3 p, float3 q, float u[3], float3 *gx) {
+  float T[6];
+  cell_sum(g, G, p.x, p.y, p.z, T);
+  const float3 z = make_float3(g.scale * T[0], g.scale * T[1], g.scale * T[2]);
+  const float d = 1.0f + dot3(z, z);
+  const float3 zp = cross3(z, p), zzp = cross3(z, zp);
+  const float3 N = make_float3(zp.x + zzp.x, zp.y + zzp.y, zp.z + zzp.z);
+  const float3 a1 = cross3(p, q), a2 = cross3(zp, q), a3 = cross3(p, cross3(q, z));
+  const float ca = 2.0f / d, cz = 4.0f * dot3(q, N) / (d * d);
+  u[0] = ca * (a1.x + a2.x + a3.x) - cz * z.x;
+  u[1] = ca * (a1.y + a2.y + a3.y) - cz * z.y;
+  u[2] = ca * (a1.z + a2.z + a3.z) - cz * z.z;
+  if (gx) {
+    const float3 zq = cross3(z, q), zzq = cross3(z, zq);
+    const float lam[6] = {u[0], u[1], u[2], q.x, q.y, q.z};
+    float j0 = 0.f, j1 = 0.f, j2 = 0.f;
+    for (int l = 0; l < g.levels; ++l) {
+      float a, b, c;
+      level_jt6(G + g.off[l], g.res[l], p.x, p.y, p.z, lam, a, b, c);
+      j0 += a;
+      j1 += b;
+      j2 += c;
+    }
+    *gx = make_float3((q.x + ca * (zzq.x - zq.x)) + g.scale * j0,
+                      (q.y + ca * (zzq.y - zq.y)) + g.scale * j1,
+                      (q.z + ca * (zzq.z - zq.z)) + g.scale * j2);
+  }
+}
+
 // Batch b = blockIdx.y as warp6_kernel; gx (when set) = J^T gout + gx_add
 // (gx_add nullable, laid out like gx).
 __global__ __launch_bounds__(256) void adjoint6_kernel(GridDev g, const float *__restrict__ G,
@@ -227,48 +265,85 @@ __global__ __launch_bounds__(256) void adjoint6_kernel(GridDev g, const float *_
   G += b * gs;
   x += b * xs;
   gout += b * gos;
-  if (uo) uo += b * us;
-  if (gx) gx += b * gxs;
-  if (gx_add) gx_add += b * gxs;
   const float3 p = make_float3(x[i], x[n + i], x[2 * n + i]);
   const float3 q = make_float3(gout[i], gout[n + i], gout[2 * n + i]);
-  float T[6];
-  cell_sum(g, G, p.x, p.y, p.z, T);
-  const float3 z = make_float3(g.scale * T[0], g.scale * T[1], g.scale * T[2]);
-  const float d = 1.0f + dot3(z, z);
-  const float3 zp = cross3(z, p), zzp = cross3(z, zp);
-  const float3 N = make_float3(zp.x + zzp.x, zp.y + zzp.y, zp.z + zzp.z);
-  const float3 a1 = cross3(p, q), a2 = cross3(zp, q), a3 = cross3(p, cross3(q, z));
-  const float ca = 2.0f / d, cz = 4.0f * dot3(q, N) / (d * d);
-  const float u[3] = {ca * (a1.x + a2.x + a3.x) - cz * z.x, ca * (a1.y + a2.y + a3.y) - cz * z.y,
-                      ca * (a1.z + a2.z + a3.z) - cz * z.z};
+  float u[3];
+  float3 r;
+  adjoint6_point(g, G, p, q, u, gx ? &r : nullptr);
   if (uo) {
+    uo += b * us;
     uo[i] = u[0];
     uo[n + i] = u[1];
     uo[2 * n + i] = u[2];
   }
   if (gx) {
-    const float3 zq = cross3(z, q), zzq = cross3(z, zq);
-    const float lam[6] = {u[0], u[1], u[2], q.x, q.y, q.z};
-    float j0 = 0.f, j1 = 0.f, j2 = 0.f;
-    for (int l = 0; l < g.levels; ++l) {
-      float a, b, c;
-      level_jt6(G + g.off[l], g.res[l], p.x, p.y, p.z, lam, a, b, c);
-      j0 += a;
-      j1 += b;
-      j2 += c;
-    }
-    float r0 = (q.x + ca * (zzq.x - zq.x)) + g.scale * j0;
-    float r1 = (q.y + ca * (zzq.y - zq.y)) + g.scale * j1;
-    float r2 = (q.z + ca * (zzq.z - zq.z)) + g.scale * j2;
+    gx += b * gxs;
     if (gx_add) {
-      r0 += gx_add[i];
-      r1 += gx_add[n + i];
-      r2 += gx_add[2 * n + i];
+      gx_add += b * gxs;
+      r.x += gx_add[i];
+      r.y += gx_add[n + i];
+      r.z += gx_add[2 * n + i];
     }
-    gx[i] = r0;
-    gx[n + i] = r1;
-    gx[2 * n + i] = r2;
+    gx[i] = r.x;
+    gx[n + i] = r.y;
+    gx[2 * n + i] = r.z;
+  }
+}
+
+// The template chain on six-channel cells, one thread per vertex over all T
+// transitions: xhat[t + 1] = R(z^_t) xhat[t] + t^_t (xhat[0] = X_0 is set).
+__global__ __launch_bounds__(64) void chain_warp6_kernel(GridDev g, const float *__restrict__ params,
+                                                         long long P, float *__restrict__ xhat,
+                                                         long long V, int T) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  float3 p = make_float3(xhat[i], xhat[V + i], xhat[2 * V + i]);
+  for (int t = 0; t < T; ++t) {
+    p = warp6_point(g, params + (long long)t * P, p);
+    float *o = xhat + (long long)(t + 1) * 3 * V;
+    o[i] = p.x;
+    o[V + i] = p.y;
+    o[2 * V + i] = p.z;
+  }
+}
+
+// Its reverse sweep: lam[T-1] = gd[T-1]; for t = T-1 .. 0 the rotation
+// adjoint u[t] of transition t at xhat[t], and lam[t-1] = gd[t-1] + J_t^T lam[t].
+__global__ __launch_bounds__(64) void chain_reverse6_kernel(GridDev g,
+                                                            const float *__restrict__ params,
+                                                            long long P,
+                                                            const float *__restrict__ xhat,
+                                                            const float *__restrict__ gd,
+                                                            float *__restrict__ lam,
+                                                            float *__restrict__ uo, long long V,
+                                                            int T) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  const long long s3 = 3 * V;
+  const float *d = gd + (long long)(T - 1) * s3;
+  float3 q = make_float3(d[i], d[V + i], d[2 * V + i]);
+  float *l = lam + (long long)(T - 1) * s3;
+  l[i] = q.x;
+  l[V + i] = q.y;
+  l[2 * V + i] = q.z;
+  for (int t = T - 1; t >= 0; --t) {
+    const float *x = xhat + (long long)t * s3;
+    const float3 p = make_float3(x[i], x[V + i], x[2 * V + i]);
+    float u[3];
+    float3 r;
+    adjoint6_point(g, params + (long long)t * P, p, q, u, t > 0 ? &r : nullptr);
+    float *uu = uo + (long long)t * s3;
+    uu[i] = u[0];
+    uu[V + i] = u[1];
+    uu[2 * V + i] = u[2];
+    if (t > 0) {
+      const float *dd = gd + (long long)(t - 1) * s3;
+      q = make_float3(r.x + dd[i], r.y + dd[V + i], r.z + dd[2 * V + i]);
+      float *ll = lam + (long long)(t - 1) * s3;
+      ll[i] = q.x;
+      ll[V + i] = q.y;
+      ll[2 * V + i] = q.z;
+    }
   }
 }
 
@@ -939,6 +1014,21 @@ pdg_status launch_adjoint6_batch(const GridDev &g, const float *grids, long long
 pdg_status launch_adjoint6(const GridDev &g, const float *grids, const float *x,
                            const float *gout, float *u, float *gx, long long n, hipStream_t st) {
   return launch_adjoint6_batch(g, grids, 0, x, 0, gout, 0, u, 0, gx, nullptr, 0, n, 1, st);
+}
+
+pdg_status launch_chain_warp6(const GridDev &g, const float *params, long long P, float *xhat,
+                              long long V, int T, hipStream_t st) {
+  if (V <= 0 || T <= 0) return PDG_OK;
+  chain_warp6_kernel<<<div_up(V, 64), 64, 0, st>>>(g, params, P, xhat, V, T);
+  return launched("chain_warp6");
+}
+
+pdg_status launch_chain_reverse6(const GridDev &g, const float *params, long long P,
+                                 const float *xhat, const float *gd, float *lam, float *u,
+                                 long long V, int T, hipStream_t st) {
+  if (V <= 0 || T <= 0) return PDG_OK;
+  chain_reverse6_kernel<<<div_up(V, 64), 64, 0, st>>>(g, params, P, xhat, gd, lam, u, V, T);
+  return launched("chain_reverse6");
 }
 
 pdg_status launch_chain_adjoint(const GridDev &g, const float *grids, const float *x, long long ldx,
