@@ -61,8 +61,11 @@ int32_t pdg_version(void);
  *                 Eq. 4-7 with z = 0, where R(0) = I); every call takes it.
  *                 6 -- the full cell vector T = [z0 z1 z2 tx ty tz] of Eq. 4
  *                 (channel order as written there); pdg_grid_size,
- *                 pdg_deform and pdg_deform_backward(+_workspace) take it,
- *                 the other calls return PDG_EUNSUPPORTED.
+ *                 pdg_deform, pdg_deform_backward(+_workspace),
+ *                 pdg_precondition(+_workspace) (the rotation and the
+ *                 translation halves of every level preconditioned alike)
+ *                 pdg_adam and the problem (its full step on these cells)
+ *                 take it; pruning returns PDG_EUNSUPPORTED.
  *   level_scale : factor applied to the sum over levels; 1/L reproduces the
  *                 averaging of Eq. 1. */
 typedef struct {

@@ -282,11 +282,11 @@ def chamfer_backward(a, b, nn_a, nn_b, dir_weight, alpha=5.56):
     return ga
 
 
-def precondition(g, res, lambdas, batch=1, method="cg", iters=0, tol=1e-7):
-    """In place g <- (I + lambda_l L_l)^-2 g per level (Eq. 3)."""
-    d = grid_desc(res, 1.0)
+def precondition(g, res, lambdas, batch=1, method="cg", iters=0, tol=1e-7, channels=3):
+    """In place g <- (I + lambda_l L_l)^-2 g per level and channel (Eq. 3)."""
+    d = grid_desc(res, 1.0, channels)
     _dev(g, torch.float32, "g")
-    if g.numel() != batch * grid_size(res):
+    if g.numel() != batch * grid_size(res, channels):
         raise ValueError("g must hold `batch` packed stacks")
     md = PRECOND_METHODS[method]
     lam = (ctypes.c_float * MAX_LEVELS)(*[float(v) for v in lambdas])
@@ -353,8 +353,8 @@ def precondition_pruned(g, res, lambdas, mask, batch=1, iters=0, tol=1e-7):
     return g
 
 
-def adam(theta, m, v, g, res, lrs, step, batch=1, beta1=0.9, beta2=0.999, eps=1e-8):
-    d = grid_desc(res, 1.0)
+def adam(theta, m, v, g, res, lrs, step, batch=1, beta1=0.9, beta2=0.999, eps=1e-8, channels=3):
+    d = grid_desc(res, 1.0, channels)
     for t, nm in ((theta, "theta"), (m, "m"), (v, "v"), (g, "g")):
         _dev(t, torch.float32, nm)
     lr = (ctypes.c_float * MAX_LEVELS)(*[float(x) for x in lrs])

@@ -1220,7 +1220,7 @@ pdg_status pdg_precondition_pruned(const pdg_grid_desc *d, const float *lambda, 
 pdg_status pdg_adam(const pdg_grid_desc *d, int32_t batch, const float *lr, float beta1,
                     float beta2, float eps, int32_t step, float *theta, float *m, float *v,
                     const float *g, hipStream_t stream) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));   // any channel count: per-level rates over the packed values
   if (!lr || batch < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) ||
       !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f)) {
     set_error("invalid Adam arguments");

@@ -80,6 +80,23 @@ def test_six_channel_graph_replay_equals_eager():
         assert a.terms() == b.terms()
 
 
+def test_six_channel_adam_binding():
+    require_gpu()
+    from oracle import adam as A
+    res = (3, 4)
+    rng = np.random.default_rng(36)
+    th, g = [rng.normal(size=L.grid_size(res, 6)).astype(np.float32) for _ in range(2)]
+    lrs = [5e-3, 5.5e-3]
+    t, m, v = dev(th), torch.zeros(th.size, device="cuda"), torch.zeros(th.size, device="cuda")
+    L.adam(t, m, v, dev(g), res, lrs, 1, channels=6)
+    off = 0
+    for r, lr in zip(res, lrs):
+        sl = slice(off, off + 6 * r ** 3)
+        ref, _, _ = A.update(th[sl], 0.0, 0.0, g[sl], lr, 1)
+        np.testing.assert_allclose(host(t)[sl], ref, rtol=0, atol=1e-6 * lr)
+        off += 6 * r ** 3
+
+
 @pytest.mark.parametrize("method", ["dct", "cg"])
 def test_six_channel_precondition_matches_oracle(method):
     require_gpu()
