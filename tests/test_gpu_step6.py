@@ -93,7 +93,8 @@ def test_six_channel_adam_binding():
     for r, lr in zip(res, lrs):
         sl = slice(off, off + 6 * r ** 3)
         ref, _, _ = A.update(th[sl], 0.0, 0.0, g[sl], lr, 1)
-        np.testing.assert_allclose(host(t)[sl], ref, rtol=0, atol=1e-6 * lr)
+        # the update to 1e-6 of the rate, plus the float32 rounding of the stored value
+        assert np.all(np.abs(host(t)[sl] - ref) <= 1e-6 * lr + 2.0 ** -23 * np.abs(ref))
         off += 6 * r ** 3
 
 
