@@ -540,8 +540,8 @@ def copy_calibration():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
-              "sharding of this path is described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the path would "
+              "shard its transitions across GPUs, which is not run here.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
