@@ -512,7 +512,10 @@ def serve(count, chamfer, precond, slots=32):
     from paper_2509_18097_amd.serve import GpuExecutor, Server, poisson_requests
     stream = synth.request_stream(seed=0, count=256)[:count]
     t = time.perf_counter()
-    reqs = poisson_requests(stream, iterations=20)
+    reqs = []
+    for i in range(0, len(stream), 16):          # inputs drawn up front, progress on stderr
+        reqs += poisson_requests(stream[i:i + 16], iterations=20)
+        print(f"serve: {len(reqs)}/{len(stream)} request inputs drawn", file=sys.stderr, flush=True)
     gen_s = time.perf_counter() - t
     free, _ = torch.cuda.mem_get_info()
     ex = GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4)
