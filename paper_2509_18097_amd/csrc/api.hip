@@ -814,8 +814,8 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
                               p.loss0, p.nn0, p.nn0 + V, p.gx0, st));
       PDG_TRY(launch_mesh_terms(p.terms, user_terms, p.loss0, st));
       // (I + mesh_lambda L)^-2 with the mesh Laplacian, then Adam with mesh_lr
-      PDG_TRY(launch_mesh_precondition(V, p.d.edges, p.E, h.mesh_lambda, p.max_degree,
-                                       p.mesh_iters, p.gx0, p.pgx0, p.meshws, st));
+      PDG_TRY(launch_mesh_solve(V, p.E, h.mesh_lambda, p.max_degree, p.mesh_iters, p.gx0,
+                                p.pgx0, p.meshws, st));   // adjacency built at creation
       AdamLevels al;
       memset(&al, 0, sizeof al);
       al.levels = 1;
@@ -1541,6 +1541,9 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);
   if (s == PDG_OK && p->dctws) s = dct_basis(p->g, p->dctws, stream);
+  // X_0 optimised: the mesh adjacency of its preconditioner (fixed edges)
+  if (s == PDG_OK && p->opt_x0)
+    s = launch_mesh_adjacency(V, pd->edges, p->E, p->meshws, stream);
   // pruned grids: pruned cells hold zero and keep zero moments
   if (pd->prune_mask)
     for (float *buf : {pd->params, pd->adam_m, pd->adam_v})

@@ -410,6 +410,12 @@ int cheb_iterations(double kappa, double tol);
 pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, float lambda,
                                     int max_degree, int iters, const float *g, float *out,
                                     void *ws, hipStream_t st);
+// The two halves of it: the adjacency (sorted directed edges and row table,
+// kept in ws) and the solves on an adjacency built before in the same ws.
+pdg_status launch_mesh_adjacency(long long V, const int *edges, long long E, void *ws,
+                                 hipStream_t st);
+pdg_status launch_mesh_solve(long long V, long long E, float lambda, int max_degree, int iters,
+                             const float *g, float *out, void *ws, hipStream_t st);
 
 // prune.hip: pruned grids.  A stack's mask holds one bit per cell of every
 // level (levels packed in order, mask_words(R) words each; bit c of a level is

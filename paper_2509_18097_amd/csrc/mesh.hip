@@ -137,9 +137,8 @@ int cheb_iterations(double kappa, double tol) {
   return k < 1.0 ? 1 : (int)k;
 }
 
-pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, float lambda,
-                                    int max_degree, int iters, const float *g, float *out,
-                                    void *ws, hipStream_t st) {
+pdg_status launch_mesh_adjacency(long long V, const int *edges, long long E, void *ws,
+                                 hipStream_t st) {
   Carve c(ws);
   MeshWs w = mesh_layout(c, V, E);
   const long long ne = 2 * E;
@@ -151,7 +150,20 @@ pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, 
     PDG_TRY(radix_sort(w.keys, w.vals, ne, bits, w.sort, st));
   }
   mesh_rows_kernel<<<div_up(V + 1, 256), 256, 0, st>>>(w.keys, ne, V, w.off);
-  PDG_TRY(launched("mesh_rows"));
+  return launched("mesh_rows");
+}
+
+pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, float lambda,
+                                    int max_degree, int iters, const float *g, float *out,
+                                    void *ws, hipStream_t st) {
+  PDG_TRY(launch_mesh_adjacency(V, edges, E, ws, st));
+  return launch_mesh_solve(V, E, lambda, max_degree, iters, g, out, ws, st);
+}
+
+pdg_status launch_mesh_solve(long long V, long long E, float lambda, int max_degree, int iters,
+                             const float *g, float *out, void *ws, hipStream_t st) {
+  Carve c(ws);
+  MeshWs w = mesh_layout(c, V, E);
   // Chebyshev coefficients on [lmin, lmax] = [1, 1 + 2 lambda d_max]
   const double lam = lambda, lmin = 1.0, lmax = 1.0 + 2.0 * lam * (double)max_degree;
   const double d = 0.5 * (lmax + lmin), cc = 0.5 * (lmax - lmin);
