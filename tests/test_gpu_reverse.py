@@ -114,3 +114,34 @@ def test_joint_handle_buffers():
     with pytest.raises(L.PdgError, match="per chain"):
         prob.buffer("grad")
     assert prob.branch(0).T == 1 and prob.branch(1).T == 2
+
+
+def test_keyframe_last_frame_optimises_template_with_the_backward_chain():
+    """With X_0 at the last frame only the backward chain exists; X_0 is then
+    optimised with it (L_mesh against P_k), as the oracle's two-way step does."""
+    require_gpu()
+    seq, theta0 = _setup(seed=16, frames=4, n=500, subdiv=1)
+    k = 3
+    prob = _problem(seq, theta0, k, "fp32", precond="dct", optimize_template=True)
+    prob.step(0)
+    prob.stage("precond")
+    torch.cuda.synchronize()
+    ch = prob.branch(0)
+    assert prob.branch(1) is None and ch.T == 3
+    V = seq.template.shape[1]
+    ov = [dict(phat32=host(ch.buffer("phat")), xhat32=host(ch.buffer("xhat")),
+               grad_override=host(ch.buffer("grad")), pgrad_override=host(ch.buffer("pgrad")),
+               gx0_override=host(ch.buffer("gx0")), pgx0_override=host(ch.buffer("pgx0"))), None]
+    z = np.zeros_like(theta0, dtype=np.float64)
+    r = S.step_keyframe(seq.points, seq.template, seq.edges, RES, theta0, z, z, 0, k,
+                        S.Hyper(e_max=10), overrides=ov,
+                        x0_state=(np.zeros((3, V)), np.zeros((3, V))))
+    rb = r.branches[0]
+    nn0 = host(ch.buffer("nn0"))
+    np.testing.assert_array_equal(nn0[:V], rb.nn0[0])
+    np.testing.assert_array_equal(nn0[V:], rb.nn0[1])
+    terms = prob.terms()
+    assert abs(terms["l_mesh"] - rb.l_mesh) <= 1e-10 * rb.l_mesh
+    assert abs(terms["loss"] - r.loss) <= 1e-10 * abs(r.loss)
+    x0 = host(prob.template)
+    assert np.all(np.abs(x0 - rb.x0) <= 1e-5 * S.Hyper().mesh_lr + 2.0 ** -23 * np.abs(rb.x0))
