@@ -425,6 +425,7 @@ struct pdg_problem {
   // six-channel cells [z; t] (Eq. 4-7): rotation adjoints of the point and
   // template samples, and the conjugate-gradient plan of the t half
   float *u_p = nullptr, *u_t = nullptr;
+  int *klist = nullptr;                            // kept CG tiles of pruned grids
   CGPlanDev cg_t;
   // optimisation of X_0 (Eq. 10, Sec. 3.6)
   bool opt_x0 = false;
@@ -610,6 +611,7 @@ void layout(pdg_problem &p, Carve &c) {
     p.dctws = c.take<char>((long long)dct_bytes(p.g));
   else
     p.cgws = c.take<char>((long long)cg_bytes(T * P, p.cg.nsys, p.cg.ntiles));
+  if (p.d.prune_mask) p.klist = c.take<int>(p.cg.ntiles > 0 ? p.cg.ntiles : 1);
 }
 
 void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
@@ -1548,6 +1550,22 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
   if (pd->prune_mask)
     for (float *buf : {pd->params, pd->adam_m, pd->adam_v})
       if (s == PDG_OK) s = launch_mask_apply(p->g, (int)T, pd->prune_mask, buf, stream);
+  // pruned grids: the conjugate-gradient launches cover the kept tiles only
+  // (their list is built on the host from the masks, once)
+  if (s == PDG_OK && pd->prune_mask && p->cg.ntiles > 0) {
+    const long long words = (long long)T * mask_stack_words(p->g);
+    std::vector<uint32_t> hm(words);
+    std::vector<int> kl(p->cg.ntiles);
+    hipError_t he = hipStreamSynchronize(stream);
+    if (he == hipSuccess)
+      he = hipMemcpy(hm.data(), pd->prune_mask, words * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (he == hipSuccess) {
+      const int nk = cg_kept_tiles(p->cg, p->g, hm.data(), kl.data());
+      if (nk > 0) he = hipMemcpy(p->klist, kl.data(), nk * sizeof(int), hipMemcpyHostToDevice);
+      p->cg.klist = p->klist;
+    }
+    if (he != hipSuccess) s = hip_fail(he, "pdg_problem_create kept tiles");
+  }
   if (s == PDG_OK) s = launch_set_int(p->epoch, 0, stream);
   if (s != PDG_OK) {
     delete p;

@@ -347,6 +347,10 @@ struct CGPlanDev {
   int ntiles, nsys;
   const uint32_t *mask;      // pruning masks [batch][mstack] words, or null (box)
   long long mstack;          // mask words per stack
+  // kept tiles of pruned grids (ascending tile ids, level-major), or null:
+  // launches then cover only these, level l's at [kfirst[l], kfirst[l] + kcount[l])
+  const int *klist;
+  int kfirst[PDG_MAX_LEVELS], kcount[PDG_MAX_LEVELS];
   CGLevel lv[PDG_MAX_LEVELS];
 };
 CGPlanDev cg_make_plan(const GridDev &g, int batch, const float *lam, const int *iters,
@@ -432,6 +436,10 @@ pdg_status launch_mask_apply(const GridDev &g, int batch, const uint32_t *mask, 
 // plan fields for masked conjugate gradients (run_cg then solves on the
 // graphs the kept cells induce)
 void cg_set_mask(CGPlanDev &p, const GridDev &g, const uint32_t *mask);
+// The kept-tile list of a masked plan from the masks on the host (hmask:
+// [batch][mstack] words): fills p.kfirst / p.kcount and writes the list to
+// `list` (host, p.ntiles entries at most); returns its length.
+int cg_kept_tiles(CGPlanDev &p, const GridDev &g, const uint32_t *hmask, int *list);
 
 // keyframe.hip: Eq. 19-20 (occupied 128^3 voxels per frame, weighted argmax)
 size_t keyframe_bytes(int frames);

@@ -200,14 +200,16 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
                                                         CGState s, const float *__restrict__ pin,
                                                         float *__restrict__ pout) {
   __shared__ double sh[kThreads / 64];
-  const int tile = tile_of_block(tile_lo, nlaunch);
+  int tile = tile_of_block(tile_lo, nlaunch);
+  if (tile >= tile_lo + nlaunch) return;
+  if (P.klist) tile = P.klist[tile];          // listed tiles hold a kept cell
   Loc o;
-  if (tile >= tile_lo + nlaunch || !locate(P, tile, o)) return;
+  if (!locate(P, tile, o)) return;
   const CGLevel &L = P.lv[o.l];
   if (k >= L.iters) return;
   const int R = L.R;
   const int n = R * R * R;
-  if (MASK && !tile_kept(o.mk, o.lt, n)) {
+  if (MASK && !P.klist && !tile_kept(o.mk, o.lt, n)) {
     if (threadIdx.x == 0) s.pq_part[tile] = 0.0;
     return;
   }
@@ -282,14 +284,16 @@ template <bool MASK>
 __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
                                                         CGState s, const float *__restrict__ pcur) {
   __shared__ double sh[kThreads / 64];
-  const int tile = tile_of_block(tile_lo, nlaunch);
+  int tile = tile_of_block(tile_lo, nlaunch);
+  if (tile >= tile_lo + nlaunch) return;
+  if (P.klist) tile = P.klist[tile];
   Loc o;
-  if (tile >= tile_lo + nlaunch || !locate(P, tile, o)) return;
+  if (!locate(P, tile, o)) return;
   const CGLevel &L = P.lv[o.l];
   if (k >= L.iters) return;
   const int R = L.R;
   const int n = R * R * R;
-  if (MASK && !tile_kept(o.mk, o.lt, n)) {
+  if (MASK && !P.klist && !tile_kept(o.mk, o.lt, n)) {
     if (threadIdx.x == 0) s.rr_part[tile] = 0.0;
     return;
   }
@@ -423,6 +427,16 @@ size_t cg_bytes(long long floats, int nsys, int ntiles) {
   return 4 * a256((size_t)floats * 4) + 2 * a256((size_t)ntiles * 8) + 3 * a256((size_t)nsys * 8);
 }
 
+// The two reductions of an iteration whose span holds no kept tile (the
+// partials stay as they are: alpha and beta follow from them unchanged).
+static pdg_status run_reductions_only(const CGPlanDev &P, int k, int sys_lo, int sys_hi,
+                                      const CGState &t, hipStream_t st) {
+  cg_reduce_kernel<<<sys_hi - sys_lo, kThreads, 0, st>>>(P, k, 1, sys_lo, t);
+  PDG_TRY(launched("cg_reduce"));
+  cg_reduce_kernel<<<sys_hi - sys_lo, kThreads, 0, st>>>(P, k, 2, sys_lo, t);
+  return launched("cg_reduce");
+}
+
 pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipStream_t st) {
   if (P.nsys <= 0 || P.ntiles <= 0) return PDG_OK;
   char *w = (char *)ws;
@@ -447,6 +461,9 @@ pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipS
   int kmax = 0;
   for (int l = 0; l < P.levels; ++l) kmax = P.lv[l].iters > kmax ? P.lv[l].iters : kmax;
   auto padded = [](int n) { return (unsigned)(((n + 7) / 8) * 8); };
+  // listed launches leave the partials of unlisted tiles untouched: the dot
+  // partials start at zero (the residual ones are written by every init)
+  if (P.klist) PDG_TRY(launch_fill((float *)s.pq_part, 2LL * P.ntiles, 0.f, st));
   // solve 1: (I + lam L) y = g, y in s.x ; solve 2: (I + lam L) z = y, z in g
   for (int solve = 0; solve < 2; ++solve) {
     const float *src = solve == 0 ? g : s.x;
@@ -464,12 +481,20 @@ pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipS
           if (lo < 0) lo = l;
           hi = l;
         }
-      const int tile_lo = P.lv[lo].tile0;
-      const int tile_hi = P.lv[hi].tile0 + P.batch * 3 * P.lv[hi].tps;
+      int tile_lo = P.lv[lo].tile0;
+      int tile_hi = P.lv[hi].tile0 + P.batch * 3 * P.lv[hi].tps;
+      if (P.klist) {                       // positions in the kept-tile list
+        tile_lo = P.kfirst[lo];
+        tile_hi = P.kfirst[hi] + P.kcount[hi];
+      }
       const int sys_lo = P.lv[lo].sys0;
       const int sys_hi = P.lv[hi].sys0 + P.batch * 3;
       float *pin = (k & 1) ? t.p1 : t.p0;
       float *pout = (k & 1) ? t.p0 : t.p1;
+      if (tile_hi <= tile_lo) {            // no kept tile in the span: nothing to update
+        PDG_TRY(run_reductions_only(P, k, sys_lo, sys_hi, t, st));
+        continue;
+      }
       if (P.mask)
         cg_a_kernel<true><<<padded(tile_hi - tile_lo), kThreads, 0, st>>>(
             P, k, tile_lo, tile_hi - tile_lo, t, pin, pout);

@@ -9,6 +9,8 @@
 // one per axis, each a bitwise OR over 2 halo + 1 shifted copies.  Rows of
 // R % 32 == 0 levels are whole words, so those passes work on words (shifts
 // along x, word ORs along y and z); other levels go cell by cell.
+#include <algorithm>
+
 #include "common.h"
 
 namespace pdg {
@@ -195,6 +197,30 @@ pdg_status launch_mask_apply(const GridDev &g, int batch, const uint32_t *mask, 
   mask_apply_kernel<<<div_up((long long)batch * g.size, 256), 256, 0, st>>>(g, prune_levels(g),
                                                                            batch, mask, data);
   return launched("mask_apply");
+}
+
+int cg_kept_tiles(CGPlanDev &p, const GridDev &g, const uint32_t *hmask, int *list) {
+  const PruneLevels pl = prune_levels(g);
+  const long long tw = 2048 / 32;              // mask words per 2048-cell CG tile
+  int n = 0;
+  for (int l = 0; l < p.levels; ++l) {
+    const CGLevel &L = p.lv[l];
+    const long long nw = mask_words(L.R);
+    p.kfirst[l] = n;
+    for (int b = 0; b < p.batch; ++b) {
+      const uint32_t *W = hmask + (long long)b * pl.mstack + pl.moff[l];
+      for (int lt = 0; lt < L.tps; ++lt) {
+        bool kept = false;
+        for (long long w = lt * tw; w < (lt + 1) * tw && w < nw && !kept; ++w) kept = W[w] != 0u;
+        if (!kept) continue;
+        for (int c = 0; c < 3; ++c) list[n++] = L.tile0 + (b * 3 + c) * L.tps + lt;
+      }
+    }
+    p.kcount[l] = n - p.kfirst[l];
+  }
+  // ascending: systems are (stack, channel) within a level
+  std::sort(list + 0, list + n);
+  return n;
 }
 
 void cg_set_mask(CGPlanDev &p, const GridDev &g, const uint32_t *mask) {
