@@ -18,9 +18,12 @@ Follows the paper's Sec. 3.3-3.6:
 Readings:
 * Frame 0 is the keyframe; T = F - 1 transitions, grid G_t maps frame t-1 to t.
 * Eq. 14 is read as 1/T sum_t [w_conf(t) CD(X, P) + CD(P^, P)].
-* w_conf is a weight and is not differentiated (only cd_max is marked sg, the
-  bracket is ambiguous); tau runs from 1 to t inclusive; e is the 0-based
-  epoch and e_max the number of epochs.
+* w_conf is differentiated with respect to the template terms
+  CD_R(X_tau, P_tau) it is built from: Eq. 17 puts the stop-gradient on the
+  point terms inside cd_max only, which would be needless if w_conf carried no
+  gradient.  cd_max itself is constant for the gradient.  tau runs from 1 to t
+  inclusive; e is the 0-based epoch and e_max the number of epochs; the
+  derivative of max(0, x) at x = 0 is taken as 0.
 * cd_max is taken from the current iteration's forward pass.
 * Isometry: sign(0) = 0; a zero-length edge contributes no gradient; X_0 is
   fixed.
@@ -105,6 +108,21 @@ def confidence(cd_tm, cd_pt, epoch: int, e_max: int, cd_max: float | None = None
     return np.cumprod(factors), cd_max, float(delta)
 
 
+def template_weight(cd_tm, w_conf, cd_max: float, delta: float) -> np.ndarray:
+    """d/dCD_R(X_tau, P_tau) of sum_t w_conf(t) CD_R(X_t, P_t) (Eq. 14-15),
+    with cd_max held constant (Eq. 17): w_conf(tau) from the term itself, plus,
+    when CD_R(X_tau, P_tau) > cd_max, the change of every later weight through
+    its factor tau,
+        - delta / (1 + CD_R(X_tau, P_tau) - cd_max) * sum_{t >= tau} w_conf(t) CD_R(X_t, P_t).
+    """
+    c = np.asarray(cd_tm, np.float64)
+    w = np.asarray(w_conf, np.float64)
+    later = np.cumsum((w * c)[::-1])[::-1]         # sum over t >= tau
+    active = c - cd_max > 0.0
+    dlog = np.where(active, -delta / (1.0 + np.where(active, c - cd_max, 0.0)), 0.0)
+    return w + dlog * later
+
+
 @dataclass
 class StepResult:
     phat: np.ndarray                  # (T, 3, N) float64 warped input points
@@ -114,6 +132,7 @@ class StepResult:
     cd_tm: np.ndarray = None          # (T, 2)
     cd_max: float = 0.0
     w_conf: np.ndarray = None
+    tm_weight: np.ndarray = None      # (T,) dL_transform/dCD_R(X_t, P_t) times T
     l_iso: float = 0.0
     loss: float = 0.0
     grad: np.ndarray = None           # (T, P) raw packed grid gradient
@@ -231,13 +250,15 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     pt = cd_pt.sum(axis=1)
     tm = cd_tm.sum(axis=1)
     if has_tm:
-        w_conf, cd_max, _ = confidence(tm, pt, epoch, hp.e_max, cd_max)
+        w_conf, cd_max, delta = confidence(tm, pt, epoch, hp.e_max, cd_max)
+        tm_w = template_weight(tm, w_conf, cd_max, delta)
         l_iso, g_iso = isometry(x_nn, edges, hp.w_iso)
         l_iso, g_iso = l_iso * t_count / tn, g_iso * (t_count / tn)
     else:
         w_conf, l_iso, g_iso = np.ones(t_count), 0.0, None
+        tm_w = np.ones(t_count)
         cd_max = float(np.max(pt)) if cd_max is None else float(cd_max)
-    r.w_conf, r.cd_max, r.l_iso = w_conf, cd_max, l_iso
+    r.w_conf, r.cd_max, r.l_iso, r.tm_weight = w_conf, cd_max, l_iso, tm_w
     r.loss = float(np.sum(w_conf * tm + pt) / tn + l_iso) if has_tm else float(np.sum(pt) / tn)
 
     # gradients of the loss with respect to the warped positions
@@ -248,7 +269,7 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
     grad = np.stack([grid_adj(theta[t], points[t], g_phat[t]) for t in range(t_count)])
     if has_tm:
         g_x = np.stack([_ch.gradient(x_nn[t + 1], points[t + 1], r.nn["tm_ab"][t], r.nn["tm_ba"][t],
-                                     hp.alpha, w_conf[t] / tn, w_conf[t] / tn)
+                                     hp.alpha, tm_w[t] / tn, tm_w[t] / tn)
                         for t in range(t_count)]) + g_iso[1:]
         r.g_xhat = g_x
         chain_pos = x_nn

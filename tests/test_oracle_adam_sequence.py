@@ -116,24 +116,33 @@ def test_step_fixed_point_exact():
     assert tmpl.shape == (3, 12) and e.shape[0] == 2
 
 
-def _frozen_loss(seq, res, theta, ref, hp):
+def _live_wconf(ctm, cd_max, epoch, e_max):
+    """Eq. 15-16 on the template terms of the perturbed grids, with cd_max held
+    at the reference forward's value (Eq. 17 detaches it)."""
+    delta = 1.0 - np.sqrt(epoch / e_max)
+    return np.cumprod((1.0 + np.maximum(0.0, np.asarray(ctm) - cd_max)) ** -delta)
+
+
+def _frozen_loss(seq, res, theta, ref, hp, epoch):
     """Loss of the step as a function of the grid values with the neighbour
-    assignment and the confidence weights held at ``ref``'s values."""
+    assignment and cd_max held at ``ref``'s values; the confidence weights
+    follow the template terms (Eq. 15)."""
     pts = seq.points
     t_count = pts.shape[0] - 1
     ls = hp.scale(len(res))
-    tot = 0.0
     xs = [seq.template.astype(np.float64)]
     for t in range(t_count):
         xs.append(W.warp(theta[t], res, xs[t], ls))
+    cpt, ctm = [], []
     for t in range(t_count):
         ph = W.warp(theta[t], res, pts[t], ls)
         tgt = pts[t + 1]
-        cpt = C.direction_loss(ph, tgt, ref.nn["pt_ab"][t], hp.alpha) + \
-            C.direction_loss(tgt, ph, ref.nn["pt_ba"][t], hp.alpha)
-        ctm = C.direction_loss(xs[t + 1], tgt, ref.nn["tm_ab"][t], hp.alpha) + \
-            C.direction_loss(tgt, xs[t + 1], ref.nn["tm_ba"][t], hp.alpha)
-        tot += ref.w_conf[t] * ctm + cpt
+        cpt.append(C.direction_loss(ph, tgt, ref.nn["pt_ab"][t], hp.alpha) +
+                   C.direction_loss(tgt, ph, ref.nn["pt_ba"][t], hp.alpha))
+        ctm.append(C.direction_loss(xs[t + 1], tgt, ref.nn["tm_ab"][t], hp.alpha) +
+                   C.direction_loss(tgt, xs[t + 1], ref.nn["tm_ba"][t], hp.alpha))
+    w = _live_wconf(ctm, ref.cd_max, epoch, hp.e_max)
+    tot = float(np.sum(w * np.array(ctm) + np.array(cpt)))
     return tot / t_count + S.isometry(np.stack(xs), seq.edges, hp.w_iso)[0]
 
 
@@ -157,7 +166,8 @@ def test_step_gradient_finite_difference():
             tp, tm = theta.copy(), theta.copy()
             tp[t, k] += h
             tm[t, k] -= h
-            fd = (_frozen_loss(seq, res, tp, ref, hp) - _frozen_loss(seq, res, tm, ref, hp)) / (2 * h)
+            fd = (_frozen_loss(seq, res, tp, ref, hp, 2) -
+                  _frozen_loss(seq, res, tm, ref, hp, 2)) / (2 * h)
             assert abs(fd - ref.grad[t, k]) <= 2e-4 * max(abs(fd), 1e-3), (t, k, fd, ref.grad[t, k])
 
 
@@ -213,11 +223,12 @@ def test_template_step_pieces():
     np.testing.assert_allclose(step, expect, rtol=1e-9, atol=1e-15)
 
 
-def _frozen_two_way(seq, res, theta, kr, k, hp):
+def _frozen_two_way(seq, res, theta, kr, k, hp, epoch):
     """Loss of a step propagated both ways from keyframe k, as a function of
     the grid values (chain order: backward chain, then forward chain), with
-    the assignments and confidence weights held at ``kr``'s values; 1/T and
-    the isometry normalisation use the total T = F - 1."""
+    the assignments and cd_max held at ``kr``'s values and the confidence
+    weights following each chain's template terms; 1/T and the isometry
+    normalisation use the total T = F - 1."""
     pts = seq.points
     f = pts.shape[0]
     T = f - 1
@@ -231,18 +242,20 @@ def _frozen_two_way(seq, res, theta, kr, k, hp):
         xs = [seq.template.astype(np.float64)]
         for b in range(len(fr) - 1):
             xs.append(W.warp(theta[t0 + b], res, xs[b], ls))
+        cpt, ctm = [], []
         for b in range(len(fr) - 1):
             ph = W.warp(theta[t0 + b], res, pts[fr[b]], ls)
             tgt = pts[fr[b + 1]]
-            cpt = C.direction_loss(ph, tgt, r.nn["pt_ab"][b], hp.alpha) + \
-                C.direction_loss(tgt, ph, r.nn["pt_ba"][b], hp.alpha)
-            ctm = C.direction_loss(xs[b + 1], tgt, r.nn["tm_ab"][b], hp.alpha) + \
-                C.direction_loss(tgt, xs[b + 1], r.nn["tm_ba"][b], hp.alpha)
-            tot += r.w_conf[b] * ctm + cpt
+            cpt.append(C.direction_loss(ph, tgt, r.nn["pt_ab"][b], hp.alpha) +
+                       C.direction_loss(tgt, ph, r.nn["pt_ba"][b], hp.alpha))
+            ctm.append(C.direction_loss(xs[b + 1], tgt, r.nn["tm_ab"][b], hp.alpha) +
+                       C.direction_loss(tgt, xs[b + 1], r.nn["tm_ba"][b], hp.alpha))
             i, j = seq.edges
             l1 = np.linalg.norm(xs[b + 1][:, i] - xs[b + 1][:, j], axis=0)
             l0 = np.linalg.norm(xs[b][:, i] - xs[b][:, j], axis=0)
             iso += np.sum(np.abs(l1 - l0))
+        w = _live_wconf(ctm, kr.cd_max, epoch, hp.e_max)
+        tot += float(np.sum(w * np.array(ctm) + np.array(cpt)))
         t0 += len(fr) - 1
     return tot / T + hp.w_iso * iso / (T * e)
 
@@ -277,8 +290,8 @@ def test_two_way_step_gradient_and_coupling(k):
             tp, tq = theta.copy(), theta.copy()
             tp[t, q] += h
             tq[t, q] -= h
-            fd = (_frozen_two_way(seq, res, tp, kr, k, hp) -
-                  _frozen_two_way(seq, res, tq, kr, k, hp)) / (2 * h)
+            fd = (_frozen_two_way(seq, res, tp, kr, k, hp, 2) -
+                  _frozen_two_way(seq, res, tq, kr, k, hp, 2)) / (2 * h)
             assert abs(fd - grads[t, q]) <= 2e-4 * max(abs(fd), 1e-3), (t, q, fd, grads[t, q])
 
 
@@ -298,24 +311,25 @@ def test_two_way_ends_reduce_to_one_chain():
     np.testing.assert_array_equal(k3.theta, rev.theta)
 
 
-def _frozen_loss6(seq, res, theta, ref, hp):
+def _frozen_loss6(seq, res, theta, ref, hp, epoch):
     """As _frozen_loss for the six-channel cells (x' = R(z^) x + t^)."""
     from oracle import cayley as CY
     pts = seq.points
     t_count = pts.shape[0] - 1
     ls = hp.scale(len(res))
-    tot = 0.0
     xs = [seq.template.astype(np.float64)]
     for t in range(t_count):
         xs.append(CY.warp6(theta[t], res, xs[t], ls))
+    cpt, ctm = [], []
     for t in range(t_count):
         ph = CY.warp6(theta[t], res, pts[t], ls)
         tgt = pts[t + 1]
-        cpt = C.direction_loss(ph, tgt, ref.nn["pt_ab"][t], hp.alpha) + \
-            C.direction_loss(tgt, ph, ref.nn["pt_ba"][t], hp.alpha)
-        ctm = C.direction_loss(xs[t + 1], tgt, ref.nn["tm_ab"][t], hp.alpha) + \
-            C.direction_loss(tgt, xs[t + 1], ref.nn["tm_ba"][t], hp.alpha)
-        tot += ref.w_conf[t] * ctm + cpt
+        cpt.append(C.direction_loss(ph, tgt, ref.nn["pt_ab"][t], hp.alpha) +
+                   C.direction_loss(tgt, ph, ref.nn["pt_ba"][t], hp.alpha))
+        ctm.append(C.direction_loss(xs[t + 1], tgt, ref.nn["tm_ab"][t], hp.alpha) +
+                   C.direction_loss(tgt, xs[t + 1], ref.nn["tm_ba"][t], hp.alpha))
+    w = _live_wconf(ctm, ref.cd_max, epoch, hp.e_max)
+    tot = float(np.sum(w * np.array(ctm) + np.array(cpt)))
     return tot / t_count + S.isometry(np.stack(xs), seq.edges, hp.w_iso)[0]
 
 
@@ -340,7 +354,8 @@ def test_step_six_channel_gradient_finite_difference():
             tp, tm = theta.copy(), theta.copy()
             tp[t, k] += h
             tm[t, k] -= h
-            fd = (_frozen_loss6(seq, res, tp, ref, hp) - _frozen_loss6(seq, res, tm, ref, hp)) / (2 * h)
+            fd = (_frozen_loss6(seq, res, tp, ref, hp, 1) -
+                  _frozen_loss6(seq, res, tm, ref, hp, 1)) / (2 * h)
             assert abs(fd - ref.grad[t, k]) <= 2e-4 * max(abs(fd), 1e-3), (t, k, fd, ref.grad[t, k])
     # the preconditioner acts on each of the six channels of a level as on the three
     lams = hp.schedule(len(res))[1]
@@ -350,3 +365,146 @@ def test_step_six_channel_gradient_finite_difference():
         np.testing.assert_allclose(ref.pgrad[0][off:off + 6 * r ** 3].reshape(6, -1),
                                    PC.apply_dct(blk, r, lam), atol=1e-15)
         off += 6 * r ** 3
+
+
+# ---------------------------------------------------------------------------
+# The assembled loss against values fixed by hand (Eq. 9, 11-18).
+#
+# One level of 2^3 cells holding the affine field D(x) = k x (values k times
+# the cell centres +-0.5) moves every point inside [-0.5, 0.5]^3 to (1 + k) x
+# exactly (trilinear interpolation reproduces affine fields).  The template is
+# two vertices (-+1/8, 0, 0) joined by one edge; frame t holds the chain's
+# vertices shifted by (0, d_t, 0).  All coordinates are dyadic, so float32
+# rounding is exact, and each nearest neighbour is the vertex's own partner.
+# Then every Chamfer term is a closed form:
+#   CD_R(X_t, P_t)  = 2 d_t^2 e^{-alpha d_t^2},
+#   CD_R(P^_t, P_t) = 2 s_t e^{-alpha s_t},  s_t = (d_t - (1 + k_t) d_{t-1})^2,
+# and the edge length of frame t is 2/8 times the product of the (1 + k).
+
+def _affine_level(k):
+    c = np.array([-0.5, 0.5])
+    g = np.zeros((3, 2, 2, 2))
+    g[0] = k * c[None, None, :]           # x fastest
+    g[1] = k * c[None, :, None]
+    g[2] = k * c[:, None, None]
+    return g.reshape(-1)
+
+
+def _two_vertex_frames(scales, offsets):
+    x0 = np.array([[-0.125, 0.125], [0.0, 0.0], [0.0, 0.0]])
+    return [s * x0 + np.array([[0.0], [d], [0.0]]) for s, d in zip(scales, offsets)], x0
+
+
+def _cd(s, alpha=5.56):
+    return 2.0 * s * np.exp(-alpha * s)
+
+
+def test_step_loss_hand_value():
+    """L of one step (Eq. 9, 14-18) on the two-vertex geometry: T = 2,
+    k = (1/4, -1/8), d = (1/4, 1/4, 5/16), epoch 0 of 50 (delta = 1).  Both
+    template terms exceed cd_max, so w_conf < 1; a loss that drops w_conf, the
+    1/T of Eq. 14 or 18, or the weight 250 misses the hand value."""
+    ks, ds = (0.25, -0.125), (0.25, 0.25, 0.3125)
+    sig = [1.0, 1.25, 1.25 * 0.875]
+    frames, x0 = _two_vertex_frames(sig, ds)
+    pts = np.stack(frames).astype(np.float32)
+    theta = np.stack([_affine_level(k) for k in ks])
+    z = np.zeros_like(theta)
+    edges = np.array([[0], [1]], np.int32)
+    r = S.step(pts, x0.astype(np.float32), edges, (2,), theta, z, z, 0, S.Hyper(e_max=50))
+    # the hand values
+    ctm = [_cd(ds[1] ** 2), _cd(ds[2] ** 2)]                      # 2 d^2 e^{-alpha d^2}
+    cpt = [_cd((ds[1] - 1.25 * ds[0]) ** 2), _cd((ds[2] - 0.875 * ds[1]) ** 2)]
+    cd_max = max(cpt)
+    w1 = 1.0 / (1.0 + ctm[0] - cd_max)
+    w2 = w1 / (1.0 + ctm[1] - cd_max)
+    lens = [0.25 * s for s in sig]
+    l_iso = (abs(lens[1] - lens[0]) + abs(lens[2] - lens[1])) / (2 * 1)
+    expect = 0.5 * (w1 * ctm[0] + cpt[0] + w2 * ctm[1] + cpt[1]) + 250.0 * l_iso
+    np.testing.assert_allclose(r.cd_tm.sum(axis=1), ctm, rtol=1e-14)
+    np.testing.assert_allclose(r.cd_pt.sum(axis=1), cpt, rtol=1e-14)
+    assert r.cd_max == pytest.approx(cd_max, rel=1e-14)
+    np.testing.assert_allclose(r.w_conf, [w1, w2], rtol=1e-14)
+    assert w2 < 0.9                                     # the weights matter
+    assert r.l_iso == pytest.approx(250.0 * l_iso, rel=1e-14)
+    assert r.loss == pytest.approx(expect, rel=1e-14)
+    # the template terms' weights in the gradient (Eq. 15 differentiated):
+    # dL_T/dCD_1 = w1 - w1 (w1 c1 + w2 c2) / ... by the product rule, by hand
+    g1 = w1 - (w1 * ctm[0] + w2 * ctm[1]) / (1.0 + ctm[0] - cd_max)
+    g2 = w2 - w2 * ctm[1] / (1.0 + ctm[1] - cd_max)
+    np.testing.assert_allclose(r.tm_weight, [g1, g2], rtol=1e-13)
+
+
+def test_keyframe_loss_hand_value():
+    """The same geometry propagated both ways from keyframe 1 of 3 frames:
+    the backward grid scales X_0 by 5/4 onto frame 0, the forward one by 7/8
+    onto frame 2.  1/T uses the total T = 2, cd_max spans both chains, each
+    chain's confidence product has one factor."""
+    kb, kf = 0.25, -0.125
+    d0, d1, d2 = 0.3125, 0.25, 0.1875
+    frames, x0 = _two_vertex_frames((1.0 + kb, 1.0, 1.0 + kf), (d0, d1, d2))
+    pts = np.stack(frames).astype(np.float32)
+    theta = np.stack([_affine_level(kb), _affine_level(kf)])
+    z = np.zeros_like(theta)
+    edges = np.array([[0], [1]], np.int32)
+    out = S.step_keyframe(pts, x0.astype(np.float32), edges, (2,), theta, z, z, 0, 1,
+                          S.Hyper(e_max=50))
+    ctm_b, ctm_f = _cd(d0 ** 2), _cd(d2 ** 2)
+    cpt_b, cpt_f = _cd((d0 - (1 + kb) * d1) ** 2), _cd((d2 - (1 + kf) * d1) ** 2)
+    cd_max = max(cpt_b, cpt_f)
+    wb = 1.0 / (1.0 + max(0.0, ctm_b - cd_max))
+    wf = 1.0 / (1.0 + max(0.0, ctm_f - cd_max))
+    l_iso = (abs(0.25 * (1 + kb) - 0.25) + abs(0.25 * (1 + kf) - 0.25)) / 2
+    expect = 0.5 * (wb * ctm_b + cpt_b + wf * ctm_f + cpt_f) + 250.0 * l_iso
+    assert out.cd_max == pytest.approx(cd_max, rel=1e-14)
+    assert wb < 0.95 and wf < 0.99
+    assert out.loss == pytest.approx(expect, rel=1e-14)
+
+
+def test_template_weight_by_differences():
+    """template_weight is the derivative of sum_t w_conf(t) c_t (Eq. 15) with
+    cd_max constant: central differences of the confidence product itself,
+    terms above and below cd_max, several epochs."""
+    rng = np.random.default_rng(30)
+    c = rng.uniform(0.01, 0.3, 7)
+    cd_max = 0.12
+    for epoch in (0, 3, 9):
+        w, _, delta = S.confidence(c, [cd_max], epoch, 10)
+        g = S.template_weight(c, w, cd_max, delta)
+        for tau in range(7):
+            if abs(c[tau] - cd_max) < 1e-4:
+                continue
+            h = 1e-6
+            cp, cm = c.copy(), c.copy()
+            cp[tau] += h
+            cm[tau] -= h
+            fp = np.sum(S.confidence(cp, [cd_max], epoch, 10)[0] * cp)
+            fm = np.sum(S.confidence(cm, [cd_max], epoch, 10)[0] * cm)
+            assert g[tau] == pytest.approx((fp - fm) / (2 * h), rel=1e-7, abs=1e-10)
+
+
+def test_step_gradient_finite_difference_confidence_active():
+    """A template far from the points (scaled by 1.4): its Chamfer terms
+    exceed cd_max, the confidence weights fall below 1 and their own
+    derivative (Eq. 15 through later frames) is a material part of the grid
+    gradient; central differences of the loss with live weights."""
+    seq = _tiny_sequence(frames=4, n=40, subdiv=1, seed=5)
+    seq.template[:] = (1.4 * seq.template).astype(np.float32)
+    res = (1, 2, 4)
+    hp = S.Hyper(e_max=10)
+    rng = np.random.default_rng(7)
+    tot = 3 * sum(r ** 3 for r in res)
+    theta = rng.normal(0, 0.02, (3, tot))
+    z = np.zeros_like(theta)
+    ref = S.step(seq.points, seq.template, seq.edges, res, theta, z, z, epoch=1, hp=hp)
+    assert np.all(ref.cd_tm.sum(axis=1) > ref.cd_max) and ref.w_conf[-1] < 0.95
+    assert np.max(np.abs(ref.tm_weight - ref.w_conf)) > 0.1
+    h = 1e-5
+    for t in range(3):
+        for k in rng.choice(tot, 5, replace=False):
+            tp, tm = theta.copy(), theta.copy()
+            tp[t, k] += h
+            tm[t, k] -= h
+            fd = (_frozen_loss(seq, res, tp, ref, hp, 1) -
+                  _frozen_loss(seq, res, tm, ref, hp, 1)) / (2 * h)
+            assert abs(fd - ref.grad[t, k]) <= 2e-4 * max(abs(fd), 1e-3), (t, k, fd, ref.grad[t, k])
