@@ -163,7 +163,7 @@ def time_stages(prob, reps=3):
         for k, name in enumerate(names):
             out[name] += ev[k].elapsed_time(ev[k + 1]) / reps
     if t0 is not None:
-        out["nn_tiles"] = (screen_tiles(prob) - t0) / reps
+        out["nn_mfma"] = (screen_tiles(prob) - t0) / reps
     alone = ("precond", "adam")
     out.update({name: 0.0 for name in alone})
     for _ in range(reps):
@@ -179,7 +179,8 @@ def time_stages(prob, reps=3):
 
 
 def screen_tiles(prob):
-    """Candidate tiles screened so far (bf16 mode), else None."""
+    """Matrix-core products (32 x 32 x 16 bf16 MFMAs) the screen has issued so
+    far (bf16 mode), else None."""
     if prob.chamfer_mode != "bf16":
         return None
     if prob.keyframe > 0:
@@ -233,23 +234,26 @@ def roofline(prob, stages, chamfer, precond):
     nn_ms, pre_ms = stages["nn"], stages["precond"]
     pairs = nn_pairs(prob)
     if chamfer == "bf16":
-        # pairs the matrix cores screened: 256 x 256 per candidate tile that
-        # survived the box cull (padding included); `pairs_per_launch` is the
-        # brute-force pair count the exact result stands for
-        screened = stages["nn_tiles"] * 256 * 256
-        a = screened * PAIR_MFMA_FLOPS / (nn_ms * 1e-3) / 1e12
+        # the matrix-core work actually issued: each wave counts its own
+        # 32 x 32 x 16 products (32,768 flops, 1,024 candidate-query pairs);
+        # `brute_force_pairs_per_launch` is the pair count the exact result
+        # stands for, of which the box cull and the waves' own tests skip most
+        mfma = stages["nn_mfma"]
+        screened = mfma * 1024
+        a = mfma * 1024 * PAIR_MFMA_FLOPS / (nn_ms * 1e-3) / 1e12
         nn = {"bound": "mfma", "achieved": round(a, 2), "peak": BF16_MFMA_PEAK_TFLOPS,
               "unit": "TFLOP/s", "frac": round(a / BF16_MFMA_PEAK_TFLOPS, 4),
               "traffic": pmc_traffic("nn_screen_kernel"),
-              "kernel": "nn_screen_kernel", "pairs_screened_per_launch": int(screened),
-              "pairs_per_launch": pairs, "cull_fraction": round(1 - screened / pairs, 4),
-              "pairs_per_s": round(pairs / (nn_ms * 1e-3), 1), "launch_ms": round(nn_ms, 4)}
+              "kernel": "nn_screen_kernel", "mfma_per_launch": int(mfma),
+              "pairs_screened_per_launch": int(screened),
+              "brute_force_pairs_per_launch": pairs,
+              "screened_fraction": round(screened / pairs, 4), "launch_ms": round(nn_ms, 4)}
     else:
         a = pairs * PAIR_OPS / (nn_ms * 1e-3) / 1e12
         nn = {"bound": "alu", "achieved": round(a, 2), "peak": round(VALU_PEAK_TOPS, 2),
               "unit": "TFLOP/s", "frac": round(a / VALU_PEAK_TOPS, 4), "traffic": None,
               "kernel": "nn_exact_kernel", "pairs_per_launch": pairs,
-              "pairs_per_s": round(pairs / (nn_ms * 1e-3), 1), "launch_ms": round(nn_ms, 4)}
+              "launch_ms": round(nn_ms, 4)}
     if precond == "dct":
         f = dct_flops(prob)
         a = f / (pre_ms * 1e-3) / 1e12
@@ -627,7 +631,7 @@ def main():
         dt = cpu_baseline(seq, workers)
         result["cpu_baseline"] = {
             "value": round(1.0 / (dt * T_), 6), "unit": "iterations/s", "cores": workers,
-            "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "kind": "oracle",
             "sample": f"one of {T_} transitions (all stages at full size: 50k points, "
                       f"{V_}-vertex template, 16..128^3 grids, DCT preconditioner), "
                       f"{dt:.1f} s, scaled x{T_}"}

@@ -17,14 +17,16 @@
  *   Values are cell-centred on the cube [-1,1]^3 (centre of cell i is
  *   -1 + (2i+1)/R) and sampling clamps to the hull of the cell centres.
  * - Every call validates its arguments on the host before enqueuing anything,
- *   enqueues its work on `stream` and returns without waiting (asynchronous).
+ *   enqueues its work on `stream` and returns without waiting (asynchronous),
+ *   except pdg_problem_create, which waits (see there).
  *   Argument errors return PDG_EINVAL and enqueue nothing.  A HIP launch error
  *   returns PDG_EHIP.  A device fault shows up as PDG_EHIP on a later call or
  *   synchronisation.  pdg_last_error() returns a thread-local message for the
- *   most recent failing call.  No call allocates device memory except
- *   pdg_problem_create (a few KB of tables) -- scratch space comes from the
- *   caller through the `*_workspace` size queries; a workspace base must be
- *   256-byte aligned (PDG_EINVAL otherwise).
+ *   most recent failing call.  No call allocates device memory: scratch space
+ *   comes from the caller through the `*_workspace` size queries (a workspace
+ *   base must be 256-byte aligned, PDG_EINVAL otherwise).  pdg_problem_create
+ *   allocates only its host-side handle; its device tables live in the
+ *   caller's workspace.
  * - Calls on one stream are ordered; calls sharing a workspace must not
  *   overlap on different streams.
  */
@@ -328,9 +330,15 @@ typedef struct pdg_problem pdg_problem;
 
 /* [host] Workspace bytes for a problem (all intermediate buffers of a step). */
 pdg_status pdg_problem_workspace(const pdg_problem_desc *pd, size_t *bytes);
-/* Validates pd, lays out the workspace and enqueues the one-time set-up
- * (static scatter tables of the input points, template edge incidence) on
- * `stream`.  *out receives an opaque handle. */
+/* Validates pd, lays out the workspace, writes the problem's job tables into
+ * it and enqueues the one-time set-up (Morton orders, static scatter tables of
+ * the input points, template edge incidence and mesh adjacency, pruned-grid
+ * zeroing) on `stream`.  *out receives an opaque handle (host memory).
+ * SYNCHRONOUS: the tables are written with blocking host-to-device copies;
+ * with a template the edge list is copied to the host to validate it and to
+ * take the maximum vertex degree; with prune_mask the call synchronises
+ * `stream` and copies the mask to the host to list the kept conjugate-
+ * gradient tiles.  Create problems outside graph capture. */
 pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out);
 /* One iteration at 0-based epoch `epoch` (0 <= epoch <= e_max).  loss_terms
  * (device double[9], nullable) receives {L, L_transform, L_iso, cd_max,
@@ -402,9 +410,10 @@ pdg_status pdg_problem_destroy(pdg_problem *p);
  *   PDG_BUF_GXHAT  float [T][3][V]   direct dL/dX_t (Chamfer + isometry), frames 1..T
  *   PDG_BUF_TERMS  double[9]         the loss terms of pdg_step
  *   PDG_BUF_LAM    float [T][3][V]   total dL/dX_t after the reverse sweep of Eq. 8
- *   PDG_BUF_SCREEN_TILES uint64[1]   256 x 256 candidate tiles screened by the
- *                  bf16 screen, summed over every step since creation (0 bytes
- *                  for the float32 mode)
+ *   PDG_BUF_SCREEN_TILES uint64[1]   matrix-core products the bf16 screen
+ *                  issued (each one 32 x 32 x 16 bf16 MFMA: 1,024 candidate-query
+ *                  pairs), summed over every step since creation (0 bytes for
+ *                  the float32 mode)
  * When X_0 is optimised (0 bytes otherwise), from the last TEMPLATE stage:
  *   PDG_BUF_NN0    int32 [V + n]     nn of X_0 in P_0, then nn of P_0 in X_0
  *   PDG_BUF_LOSS0  double[2]         CD directions X_0->P_0, P_0->X_0

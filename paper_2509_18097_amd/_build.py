@@ -58,6 +58,17 @@ def _compile(src: str, hipcc: str) -> str:
     return obj
 
 
+def stale(lib: str = LIB) -> bool:
+    """True when ``lib`` is missing or older than a HIP source, a header or
+    this build script."""
+    if not os.path.exists(lib):
+        return True
+    t = os.path.getmtime(lib)
+    deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + \
+        [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)] + [os.path.abspath(__file__)]
+    return any(os.path.getmtime(d) > t for d in deps if os.path.isfile(d))
+
+
 def build(jobs: int | None = None) -> str:
     """Compile every source and link libpdg.so; returns the library path."""
     hipcc = _hipcc()

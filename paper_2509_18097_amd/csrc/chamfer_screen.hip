@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
   __syncthreads();
   float bmax = fmaxf(fmaxf(wmax[0][0], wmax[0][1]), fmaxf(wmax[0][2], wmax[0][3]));
   int it = 1;                   // parity of the wmax buffer written next
-  unsigned screened = 0;
+  unsigned issued = 0;          // matrix-core products this wave issued (wave-uniform)
   TileRegs regs;
   for (int base = 0; base < ntiles; base += kListMax) {
     const int span = ntiles - base < kListMax ? ntiles - base : kListMax;
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
       i = nxt;
       tmin = nmin;
       tmax = nmax;
-      ++screened;
+      issued += (unsigned)(nsub * kQB);
     }
     __syncthreads();            // the list is rebuilt next
   }
@@ -512,7 +512,9 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
     }
     if (half == 0 && ok[h]) jnn[qorig[h]] = s.idx;
   }
-  if (J.tiles && tid == 0) atomicAdd(glb(J.tiles), (unsigned long long)screened);
+  // one integer atomic per wave: the 32 x 32 x 16 products it issued (tiles
+  // a wave skipped by its own box test count nothing)
+  if (J.tiles && lane == 0 && issued) atomicAdd(glb(J.tiles), (unsigned long long)issued);
 }
 
 }  // namespace

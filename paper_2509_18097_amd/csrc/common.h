@@ -293,7 +293,7 @@ struct ScreenJob {           // one directed search: packed queries over packed 
   const float4 *cc;          // candidate coords, packed order
   const float4 *cboxes;      // candidate tile boxes
   const unsigned *maxnorm;   // of the candidates
-  unsigned long long *tiles; // nullable: += candidate tiles screened
+  unsigned long long *tiles; // nullable: += 32x32x16 bf16 products issued
 };
 inline long long screen_tiles(long long n) { return (n + 255) / 256; }
 // per-set max-norm words sit this many words apart (one 128-byte line each),

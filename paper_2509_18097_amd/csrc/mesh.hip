@@ -45,10 +45,12 @@ __global__ __launch_bounds__(256) void mesh_rows_kernel(const uint32_t *__restri
   off[v] = (int)lo;
 }
 
-// x = 0, r = p = b (b float32 or float64 SoA [3][V]).
+// x = 0, r = p = b (b float32 or float64 SoA [3][V]).  The second solve
+// passes the first solve's result as b and x at once, so b and x may alias
+// (no restrict on either: the compiler keeps the store of x[i] after the
+// load of b[i]).
 template <typename T>
-__global__ __launch_bounds__(256) void cheb_init_kernel(const T *__restrict__ b, long long n,
-                                                        double *__restrict__ x,
+__global__ __launch_bounds__(256) void cheb_init_kernel(const T *b, long long n, double *x,
                                                         double *__restrict__ r,
                                                         double *__restrict__ p) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -223,12 +223,25 @@ __global__ __launch_bounds__(64) void assemble_kernel(AssembleArgs a) {
         for (int j = 0; j < n; ++j) {
           wc *= fac[j];
           a.wconf[t0 + j] = wc;
-          a.w[2 * (T + t0 + j)] = wc / Tn;
-          a.w[2 * (T + t0 + j) + 1] = wc / Tn;
           sum_tm += wc * cc[j];
         }
       }
       __syncthreads();
+    }
+    // Gradient weight of each template term: w_conf(tau) itself plus the
+    // change of every later weight through factor tau (Eq. 15), cd_max held
+    // constant (Eq. 17): when CD_tau > cd_max,
+    //   - delta / (1 + CD_tau - cd_max) * sum_{t >= tau} w_conf(t) CD_t.
+    if (lane == 0) {
+      double later = 0.0;
+      for (int t = T - 1; t >= 0; --t) {
+        const double c = a.losses[2 * (T + t)] + a.losses[2 * (T + t) + 1];
+        const double w = a.wconf[t];
+        later += w * c;
+        const double g = c - cd_max > 0.0 ? w - delta / (1.0 + (c - cd_max)) * later : w;
+        a.w[2 * (T + t)] = g / Tn;
+        a.w[2 * (T + t) + 1] = g / Tn;
+      }
     }
     if (E > 0) {
       double s = 0.0;

@@ -12,10 +12,12 @@ def pytest_configure(config):
 
 
 def _ensure_built():
-    """Build libpdg.so in-tree if it is missing (the build is the product's
-    own hipcc driver; a present library is used as is)."""
+    """Build libpdg.so in-tree if it is missing or older than any of its
+    sources (the build is the product's own hipcc driver), so the tests never
+    run a stale library against newer sources."""
     from paper_2509_18097_amd import _build, _lib
-    if not os.path.exists(_lib.LIB_PATH):
+    if _build.stale(_lib.LIB_PATH):
+        print("conftest: libpdg.so is missing or older than its sources; building", flush=True)
         _build.build()
 
 

@@ -108,6 +108,11 @@ def test_gradients_sampled_transitions(run):
     seq, th, _, _, o = run
     T = 31
     w = o["wconf"]
+    # gradient weight of each template term: w_conf and its own derivative
+    # (Eq. 15), cd_max held constant (Eq. 17); epoch 1 of 50
+    tm = o["losses"][T:].sum(axis=1)
+    cd_max = float(np.max(o["losses"][:T].sum(axis=1)))
+    gw = S.template_weight(tm, w, cd_max, 1.0 - np.sqrt(1 / 50))
     _, g_iso = S.isometry(o["xhat"], seq.edges, 250.0)
     lams = [0.25 * 1.5 ** l for l in range(4)]
     errs = {}
@@ -117,7 +122,7 @@ def test_gradients_sampled_transitions(run):
                         1 / T, 1 / T)
         errs[f"dL/dP^ t={t}"] = _rel(o["gphat"][t], gp)
         gx = C.gradient(o["xhat"][t + 1], tgt, o["nn"]["tm_ab"][t], o["nn"]["tm_ba"][t], 5.56,
-                        w[t] / T, w[t] / T) + g_iso[t + 1]
+                        gw[t] / T, gw[t] / T) + g_iso[t + 1]
         errs[f"dL/dX t={t}"] = _rel(o["gxhat"][t], gx)
         if t < T - 1:
             # one step of the reverse sweep of the chain, from the GPU's later adjoint

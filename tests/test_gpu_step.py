@@ -101,6 +101,23 @@ def test_sequence_step_with_template(epoch, mode, precond):
                mode=mode, precond=precond)
 
 
+@pytest.mark.parametrize("mode", ["fp32", "bf16"])
+def test_sequence_step_confidence_active(mode):
+    """A template far from the points (scaled by 1.4): every template term
+    exceeds cd_max, so the confidence weights fall below 1 and their own
+    derivative (Eq. 15, through the later frames' weights) enters dL/dX and
+    the grid gradient."""
+    require_gpu()
+    seq = synth.deforming_sequence(seed=1, frames=5, n=1500, subdiv=2)
+    tmpl = (1.4 * seq.template).astype(np.float32)
+    res = (4, 8, 16)
+    print(f"confidence-active step mode={mode}", flush=True)
+    _, r = _stagewise(seq.points, tmpl, seq.edges, res, _theta0(4, res, 3), epoch=1, e_max=10,
+                      mode=mode, precond="dct")
+    assert np.all(r.cd_tm.sum(axis=1) > r.cd_max)
+    assert np.max(np.abs(r.tm_weight - r.w_conf)) > 0.05
+
+
 def test_screened_step_equals_exact_step_over_iterations():
     """The served (bf16-screened, warm-started) form and the plain float32 form
     produce bitwise identical iterations."""
