@@ -173,6 +173,22 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
                        int32_t *nn_a, int32_t *nn_b, float *ga,
                        void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* pdg_chamfer for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, with the workspace taken from a fixed 64 MiB device array that the
+ * library holds per GPU from its first use until the process ends.  Calls no
+ * hipMalloc, hipFree or allocating routine.  n and m must satisfy
+ * pdg_chamfer_workspace(n, m, mode) <= 64 MiB (about 4M + 4M points in the
+ * float32 mode, 0.55M + 0.55M with the bf16 screen), else PDG_ENOMEM and
+ * nothing is enqueued.  Every call on one GPU uses that GPU's one array, which
+ * keeps the last call's contents: calls that overlap on one GPU (different
+ * streams, or host threads) race and must be serialised by the caller.  The
+ * first call on a device looks the array's address up (hipGetSymbolAddress)
+ * with that device current. */
+pdg_status pdg_chamfer_noalloc(const float *a, int64_t n, const float *b, int64_t m,
+                               double alpha, int32_t mode, const double *dir_weight, double *loss,
+                               int32_t *nn_a, int32_t *nn_b, float *ga, hipStream_t stream);
+
 /* Adjoint of pdg_chamfer from saved indices (no new search):
  *   ga <- d/da [dir_weight[0]*loss[0] + dir_weight[1]*loss[1]]  (OVERWRITTEN)
  * with nn_a, nn_b as returned by pdg_chamfer for the same a, b.  dir_weight is

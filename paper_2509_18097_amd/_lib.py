@@ -81,6 +81,7 @@ _SIGS = {
     "pdg_keyframe": (_I32, [_P, _I32, _I64, _D, _P, _P, _P, _SZ, _P]),
     "pdg_chamfer_workspace": (_I32, [_I64, _I64, _I32, ctypes.POINTER(_SZ)]),
     "pdg_chamfer": (_I32, [_P, _I64, _P, _I64, _D, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "pdg_chamfer_noalloc": (_I32, [_P, _I64, _P, _I64, _D, _I32, _P, _P, _P, _P, _P, _P]),
     "pdg_chamfer_backward": (_I32, [_P, _I64, _P, _I64, _D, _P, _P, _P, _P, _P, _SZ, _P]),
     "pdg_precondition_workspace": (_I32, [ctypes.POINTER(GridDesc), _I32, _I32, ctypes.POINTER(_SZ)]),
     "pdg_precondition": (_I32, [ctypes.POINTER(GridDesc), ctypes.POINTER(_F), _P, _I32, _I32, _I32,
@@ -261,6 +262,28 @@ def chamfer(a, b, alpha=5.56, mode="fp32", dir_weight=None, need_grad=False):
     check(lib().pdg_chamfer(_ptr(a), n, _ptr(b), m, float(alpha), md, _ptr(dir_weight), _ptr(loss),
                             _ptr(nn_a), _ptr(nn_b), _ptr(ga), _ptr(ws), nb.value, _stream()),
           "pdg_chamfer")
+    return loss, nn_a, nn_b, ga
+
+
+def chamfer_noalloc(a, b, alpha=5.56, mode="fp32", dir_weight=None, need_grad=False,
+                    out=None):
+    """pdg_chamfer on the library's fixed device scratch (no workspace
+    allocated).  ``out`` = (loss, nn_a, nn_b, ga) reuses caller tensors so that
+    nothing is allocated here either.  Returns (loss, nn_a, nn_b, ga or None)."""
+    _dev(a, torch.float32, "a")
+    _dev(b, torch.float32, "b")
+    n, m = a.shape[1], b.shape[1]
+    if out is None:
+        out = (torch.empty(2, dtype=torch.float64, device=a.device),
+               torch.empty(n, dtype=torch.int32, device=a.device),
+               torch.empty(m, dtype=torch.int32, device=a.device),
+               torch.empty_like(a) if need_grad else None)
+    loss, nn_a, nn_b, ga = out
+    if dir_weight is not None:
+        dir_weight = _dev(dir_weight, torch.float64, "dir_weight")
+    check(lib().pdg_chamfer_noalloc(_ptr(a), n, _ptr(b), m, float(alpha), CHAMFER_MODES[mode],
+                                    _ptr(dir_weight), _ptr(loss), _ptr(nn_a), _ptr(nn_b), _ptr(ga),
+                                    _stream()), "pdg_chamfer_noalloc")
     return loss, nn_a, nn_b, ga
 
 

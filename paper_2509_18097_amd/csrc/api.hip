@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -883,6 +884,41 @@ pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
   return PDG_OK;
 }
 
+// ----------------------------------------------- fixed device scratch --
+// Workspace of pdg_chamfer_noalloc: one file-scope device array per GPU, held
+// from module load until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+constexpr size_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];
+
+pdg_status scratch_of_current_device(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) {
+    set_error("device %d: the fixed scratch table holds devices 0..%d", dev, kScratchDevices - 1);
+    return PDG_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || ((uintptr_t)ptr & 255) != 0) {
+      set_error("fixed scratch of device %d is not 256-byte aligned", dev);
+      return PDG_EHIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PDG_OK;
+}
+
 }  // namespace
 }  // namespace pdg
 
@@ -1072,6 +1108,23 @@ pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, dou
   Carve c(ws);
   ChamferWs w = chamfer_layout(c, n, m, mode);
   return enqueue_chamfer(w, a, n, b, m, alpha, mode, dir_weight, loss, nn_a, nn_b, ga, stream);
+}
+
+pdg_status pdg_chamfer_noalloc(const float *a, int64_t n, const float *b, int64_t m,
+                               double alpha, int32_t mode, const double *dir_weight, double *loss,
+                               int32_t *nn_a, int32_t *nn_b, float *ga, hipStream_t stream) {
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_chamfer_workspace(n, m, mode, &need_bytes));
+  if (need_bytes > kScratchBytes) {
+    set_error("pdg_chamfer_noalloc: n = %lld, m = %lld need %zu workspace bytes, above the fixed "
+              "scratch of %zu bytes (use pdg_chamfer with a caller workspace)",
+              (long long)n, (long long)m, need_bytes, kScratchBytes);
+    return PDG_ENOMEM;
+  }
+  void *ws = nullptr;
+  PDG_TRY(scratch_of_current_device(&ws));
+  return pdg_chamfer(a, n, b, m, alpha, mode, dir_weight, loss, nn_a, nn_b, ga, ws, need_bytes,
+                     stream);
 }
 
 pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64_t m,

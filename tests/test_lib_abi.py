@@ -155,3 +155,17 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(L, "LIB_PATH", L.LIB_PATH + ".absent")
     with pytest.raises(RuntimeError, match="no fallback"):
         L.lib()
+
+
+def test_chamfer_noalloc_rejects_sizes_above_its_fixed_scratch():
+    """The no-allocation Chamfer refuses, on the host and before touching any
+    device, a pair whose workspace exceeds its fixed 64 MiB scratch."""
+    lib = L.lib()
+    nb = ctypes.c_size_t()
+    assert lib.pdg_chamfer_workspace(600_000, 600_000, 1, ctypes.byref(nb)) == L.OK
+    assert nb.value > 64 << 20
+    st = lib.pdg_chamfer_noalloc(None, 600_000, None, 600_000, 5.56, 1, None, None, None, None,
+                                 None, None)
+    assert st == L.ENOMEM and "fixed scratch" in L.last_error()
+    assert lib.pdg_chamfer_noalloc(None, 0, None, 10, 5.56, 0, None, None, None, None, None,
+                                   None) == L.EINVAL
