@@ -91,9 +91,15 @@ def parse():
                          "mesh preconditioner, pruned grids)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--serve", type=int, default=24, metavar="R",
+    ap.add_argument("--serve", type=int, default=256, metavar="R",
                     help="also serve the first R requests of the 256-request Poisson stream "
                          "(4 requests/s, 20 iterations each); 0 skips, 256 is the full stream")
+    ap.add_argument("--serve-load", type=float, default=3.0, metavar="X",
+                    help="serve the same requests a second time with arrivals X times as "
+                         "frequent (offered load above 1); 1 skips")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the single-pair, precision (200k x 200k) and differentiation "
+                         "(1M x 1M forward + backward) workloads")
     ap.add_argument("--serve-only", action="store_true", help="skip the sequence benchmark")
     ap.add_argument("--serve-slots", type=int, default=32,
                     help="maximum requests resident and iterating at once")
@@ -468,6 +474,160 @@ def time_keyframe(seq, reps=20):
             "key": int(key.item()), "gb_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def time_pair(chamfer="fp32", precond="dct", iters=50):
+    """Single frame pair: 4,096 points on the unit sphere against their
+    displacement by 0.1 sin(2 pi x) plus N(0, 0.002^2), grids 8/16/32 x 3
+    channels from zero, `iters` Adam iterations of the full step (graph
+    replay), timed from zero parameters."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2509_18097_amd.problem import HyperParams, Problem
+    src, tgt = synth.pair_on_sphere(seed=0, n=4096)
+    pts = torch.from_numpy(np.stack([src, tgt])).cuda()
+    prob = Problem(pts, (8, 16, 32), hp=HyperParams(e_max=iters), chamfer_mode=chamfer,
+                   precond=precond)
+    prob.step(0, use_graph=True)            # captures the graph
+    for t in (prob.params, prob.m, prob.v):
+        t.zero_()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for e in range(iters):
+        prob.step(e, use_graph=True)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    last = prob.terms()["loss"]
+    prob.close()
+    return {"workload": "single frame pair, 4,096 points on the unit sphere, grids 8/16/32^3 "
+                        f"x 3 ch, {iters} Adam iterations from zero grids",
+            "chamfer": chamfer, "precond": precond, "iterations": iters,
+            "ms_total": round(ms, 4), "iterations_per_s": round(iters / (ms * 1e-3), 2),
+            "loss_last": last}
+
+
+def _argmin_f64(q, c, chunk=256):
+    """Nearest index of every column of q among the columns of c, float64
+    difference form, first index on ties (torch, on the device): the float64
+    reference the float32 neighbour contract is measured against."""
+    import torch
+    out = []
+    cd = c.double()
+    for i in range(0, q.shape[1], chunk):
+        d = q[:, i:i + chunk].double().T[:, :, None] - cd[None, :, :]
+        out.append(torch.argmin((d * d).sum(dim=1), dim=1))
+    return torch.cat(out)
+
+
+def time_precision(n=200_000, reps=3, sample=20_000):
+    """200,000 points U[-1,1]^3 against the same jittered by N(0, 0.01^2), both
+    directions (Eq. 11-13): the float32 brute force and the bf16 screen with
+    exact re-rank, timed as one pdg_chamfer call each (the screen's call
+    includes the Morton sorts and packs of both sets, cold, no warm start);
+    their indices compared in full; a sample of queries compared with the
+    float64 argmin (flips) and the relative error of the loss terms against
+    the float64 assignment."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2509_18097_amd import _lib as L
+    p, q = synth.cloud_pair_cube(seed=0, n=n)
+    a, b = torch.from_numpy(p).cuda(), torch.from_numpy(q).cuda()
+    st = torch.cuda.current_stream()
+    out = {"workload": f"{n:,} points U[-1,1]^3 vs the same + N(0, 0.01^2), both directions",
+           "brute_force_pairs": 2 * n * n}
+    res = {}
+    for mode in ("fp32", "bf16"):
+        L.chamfer(a, b, 5.56, mode)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            r = L.chamfer(a, b, 5.56, mode)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[mode] = r
+        pps = 2 * n * n / (ms * 1e-3)
+        ent = {"ms": round(ms, 4), "brute_force_pairs_per_s": round(pps, 1)}
+        if mode == "fp32":
+            a_ = pps * PAIR_OPS / 1e12
+            ent["roofline"] = {"bound": "alu", "achieved": round(a_, 2),
+                               "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                               "frac": round(a_ / VALU_PEAK_TOPS, 4), "kernel": "nn_exact_kernel"}
+        out[mode] = ent
+    out["bf16_speedup"] = round(out["fp32"]["ms"] / out["bf16"]["ms"], 2)
+    out["index_mismatches_bf16_vs_fp32"] = int((res["fp32"][1] != res["bf16"][1]).sum().item() +
+                                               (res["fp32"][2] != res["bf16"][2]).sum().item())
+    out["loss_fp32"] = res["fp32"][0].cpu().tolist()
+    out["loss_bf16"] = res["bf16"][0].cpu().tolist()
+    # float64 reference on a sample of each direction's queries
+    g = torch.Generator(device="cpu")
+    g.manual_seed(0)
+    rep = {"sampled_queries_per_direction": sample}
+    for name, qs, cs, nn in (("a_to_b", a, b, res["fp32"][1]), ("b_to_a", b, a, res["fp32"][2])):
+        idx = torch.randperm(qs.shape[1], generator=g)[:sample].cuda()
+        qq = qs[:, idx]
+        n64 = _argmin_f64(qq, cs)
+        n32 = nn[idx].long()
+        d32 = ((qq.double() - cs[:, n32].double()) ** 2).sum(0)
+        d64 = ((qq.double() - cs[:, n64].double()) ** 2).sum(0)
+        ent = {"flips_fp32_vs_fp64": int((n32 != n64).sum().item())}
+        for alpha in (5.56, 0.0):
+            t32 = (torch.exp(-alpha * d32) * d32).sum().item()
+            t64 = (torch.exp(-alpha * d64) * d64).sum().item()
+            ent[f"loss_rel_err_alpha_{alpha}"] = abs(t32 - t64) / t64
+        rep[name] = ent
+    out["fp64_reference"] = rep
+    return out
+
+
+RES5 = (16, 32, 64, 128, 256)
+
+
+def time_differentiation(reps=3, n=1_000_000):
+    """Forward and backward through the torch.autograd functions with the
+    hand-written adjoints: warp of 1,000,000 points U[-1,1]^3 through a
+    5-level grid stack 16^3..256^3 (N(0, 0.01^2) values), Chamfer (bf16
+    screen, exact re-rank) against 1,000,000 independent points, backward to
+    all 57.5M grid values."""
+    import torch
+    import synth
+    from paper_2509_18097_amd import autograd as AG
+    grids = torch.from_numpy(synth.grid_stack(0, RES5, std=0.01)).cuda().requires_grad_()
+    x = torch.from_numpy(synth.uniform_cube(1, n)).cuda()
+    t = torch.from_numpy(synth.uniform_cube(2, n)).cuda()
+    st = torch.cuda.current_stream()
+
+    def fwd():
+        out = AG.deform(grids, x, RES5)
+        loss, _, _ = AG.chamfer(out, t, mode="bf16")
+        return loss
+
+    loss = fwd()
+    loss.sum().backward()
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for _ in range(reps):
+        grids.grad = None
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(st)
+        loss = fwd()
+        ev[1].record(st)
+        loss.sum().backward()
+        ev[2].record(st)
+        torch.cuda.synchronize()
+        tf += ev[0].elapsed_time(ev[1]) / reps
+        tb += ev[1].elapsed_time(ev[2]) / reps
+    return {"workload": f"5-level grid stack 16..256^3 x 3 ch (57.5M values), {n:,} queries "
+                        f"chained into Chamfer (bf16 screen) against {n:,} targets",
+            "forward_ms": round(tf, 3), "backward_ms": round(tb, 3),
+            "seconds_per_forward_backward": round((tf + tb) * 1e-3, 5),
+            "loss": loss.detach().cpu().tolist()}
+
+
 def cpu_baseline(seq, workers):
     """The oracle on one transition (t = 1) of the same workload, all stages,
     full sizes; scaled to iterations/s of the 31-transition step."""
@@ -507,27 +667,40 @@ def cpu_baseline(seq, workers):
     return dt
 
 
-def serve(count, chamfer, precond, slots=32):
-    """Poisson stream of reconstruction requests (4/s; point counts log-uniform
-    in [2k, 200k]; 8..64 frames; 3-5 levels by point count), 20 iterations
-    each, continuous batching under an HBM budget of 60% of free memory."""
+def serve_requests(count):
+    """The first `count` requests of the 256-request Poisson stream (4/s;
+    point counts log-uniform in [2k, 200k]; 8..64 frames; 3-5 levels by point
+    count; 20 iterations each), their inputs drawn on the GPU up front so they
+    are resident before the stream starts."""
     import torch
     import synth
-    from paper_2509_18097_amd.serve import GpuExecutor, Server, poisson_requests
+    from paper_2509_18097_amd.serve import poisson_requests
     stream = synth.request_stream(seed=0, count=256)[:count]
     t = time.perf_counter()
     reqs = []
-    for i in range(0, len(stream), 16):          # inputs drawn up front, progress on stderr
-        reqs += poisson_requests(stream[i:i + 16], iterations=20)
+    for i in range(0, len(stream), 32):
+        reqs += poisson_requests(stream[i:i + 32], iterations=20, device="cuda")
         print(f"serve: {len(reqs)}/{len(stream)} request inputs drawn", file=sys.stderr, flush=True)
-    gen_s = time.perf_counter() - t
+    torch.cuda.synchronize()
+    return reqs, time.perf_counter() - t
+
+
+def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0):
+    """Serve the requests with continuous batching under an HBM budget of 60%
+    of free memory; arrival times divided by `rate_scale` (1: the stream's
+    4 requests/s)."""
+    import dataclasses
+    import torch
+    from paper_2509_18097_amd.serve import GpuExecutor, Server
+    reqs = [dataclasses.replace(r, arrival=r.arrival / rate_scale) for r in reqs]
     free, _ = torch.cuda.mem_get_info()
     ex = GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4)
     st = Server(ex, budget_bytes=int(0.6 * free), max_slots=slots).run(reqs)
     out = st.summary()
-    out.update({"stream_requests": count, "iterations_per_request": 20,
-                "budget_bytes": int(0.6 * free), "input_generation_s": round(gen_s, 2),
-                "chamfer": chamfer, "precond": precond, "max_slots": slots,
+    out.update({"stream_requests": len(reqs), "iterations_per_request": 20,
+                "arrival_rate_per_s": 4.0 * rate_scale,
+                "budget_bytes": int(0.6 * free), "chamfer": chamfer, "precond": precond,
+                "max_slots": slots,
                 "load": round(st.makespan / st.arrival_span, 3) if st.arrival_span > 0 else None})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
@@ -558,8 +731,10 @@ def main():
         copy_calibration()
         return
     if args.serve_only:
-        print(json.dumps({"metric": METRIC, "serving": serve(args.serve, args.chamfer, args.precond,
-                                                                 args.serve_slots)}))
+        reqs, gen_s = serve_requests(args.serve)
+        out = serve(reqs, args.chamfer, args.precond, args.serve_slots)
+        out["input_generation_s"] = round(gen_s, 2)
+        print(json.dumps({"metric": METRIC, "serving": out}))
         return
     if args.prune is not None and args.precond != "cg":
         sys.exit("--prune needs --precond cg (the DCT solve needs the full box)")
@@ -611,11 +786,25 @@ def main():
         _, vp = make_problem(args.subdiv, ch, pc)
         vms, _ = time_steps(vp, max(3, args.steps // 2), 2)
         variants[v] = {"ms_per_step": round(vms, 4), "iterations_per_s": round(1000.0 / vms, 4)}
+        if not args.no_stages:
+            vst = time_stages(vp, reps=2)
+            nn_r, pre_r = roofline(vp, vst, ch, pc)
+            variants[v]["stages_ms"] = {k: round(x, 4) for k, x in vst.items()}
+            variants[v]["nn_roofline"] = {k: nn_r[k] for k in ("bound", "achieved", "peak", "unit",
+                                                               "frac", "kernel")}
+            variants[v]["precond_roofline"] = {k: pre_r[k] for k in ("bound", "achieved", "peak",
+                                                                     "unit", "frac", "kernel")}
         vp.close()
         del vp
         torch.cuda.empty_cache()
     if variants:
         result["variants"] = variants
+    if not args.no_configs:
+        result["single_pair"] = time_pair("fp32", args.precond)
+        result["single_pair_bf16"] = time_pair("bf16", args.precond)
+        result["precision"] = time_precision()
+        result["differentiation"] = time_differentiation()
+        torch.cuda.empty_cache()
     if not args.no_extras:
         result["cayley6"] = time_cayley6()
         result["keyframe"] = time_keyframe(seq)
@@ -625,7 +814,14 @@ def main():
         result["two_way"] = time_two_way(args.subdiv, args.chamfer, args.precond, FRAMES // 2)
         result["step6"] = time_step6(args.subdiv, args.chamfer, args.precond)
     if args.serve > 0:
-        result["serving"] = serve(args.serve, args.chamfer, args.precond, args.serve_slots)
+        reqs, gen_s = serve_requests(args.serve)
+        result["serving"] = serve(reqs, args.chamfer, args.precond, args.serve_slots)
+        result["serving"]["input_generation_s"] = round(gen_s, 2)
+        if args.serve_load > 1.0:
+            result["serving_overload"] = serve(reqs, args.chamfer, args.precond, args.serve_slots,
+                                               rate_scale=args.serve_load)
+        del reqs
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         workers = min(16, os.cpu_count() or 1)
         dt = cpu_baseline(seq, workers)

@@ -1,53 +1,66 @@
 // Nearest neighbours (paper Eq. 12) with a bf16 matrix-core screen and an
 // exact float32 re-rank: the served form of the Chamfer search.
 //
-// Screen.  For query q and candidate c the matrix cores evaluate
-//     S(q, c) = |c|^2 - 2 q.c           (|q|^2 is constant per query)
+// Screen.  Candidates come in Morton-ordered tiles of 256; every tile has a
+// frame, its box centre C (float32), and is packed relative to it,
+// delta = fl(c - C).  A query q entering the tile is moved into the same frame,
+// x = fl(q - C), and the matrix cores evaluate
+//     S(x, delta) = |delta|^2 - 2 x.delta      (|x|^2 is constant per query)
 // as one K = 16 row of v_mfma_f32_32x32x16_bf16 with float32 accumulation.
-// Each coordinate is split into two bf16 terms, x = x_hi + x_lo, and |c|^2
-// into three, which fills 12 of the 16 K slots:
-//     query row     [q_hi, q_hi, q_lo, 1, 1, 1, 0, 0, 0, 0]
-//     candidate row [-2c_hi, -2c_lo, -2c_hi, n_hi, n_mid, n_lo, 0 x 4]
-// (three coordinates per vector entry), so the only term dropped from q.c is
-// q_lo.c_lo.  With a = |q| and b = max |c| over the candidate set,
-//     |S + |q|^2 - |q - c|^2| <= eps(q) = 3e-5 a b + 2e-6 (a^2 + b^2) + 1e-6,
+// Each coordinate is split into two bf16 terms, x = x_hi + x_lo, and
+// |delta|^2 into three, which fills 12 of the 16 K slots:
+//     query row     [x_hi, x_hi, x_lo, 1, 1, 1, 0, 0, 0, 0]
+//     candidate row [-2d_hi, -2d_lo, -2d_hi, n_hi, n_mid, n_lo, 0 x 4]
+// (three coordinates per vector entry), so the only term dropped from x.delta
+// is x_lo.d_lo.  With a = |x| and b >= |delta| over the tile (its radius),
+//     |S + |x|^2 - |q - c|^2| <= 3e-5 a b + 2e-6 (a^2 + b^2),
 // which covers the bf16 split and dropped term (6.02 * 2^-18 a b), the float32
-// accumulation of 16 terms (16 * 2^-24 (2.01 a b + b^2)), the float32
-// rounding of |c|^2 and |q|^2, and the float32 threshold arithmetic.
+// accumulation of 16 terms (16 * 2^-24 (2.01 a b + 1.01 b^2)), the float32
+// rounding of |delta|^2 and |x|^2 (3.01 * 2^-24 each) and of the two frame
+// shifts (4 * 2^-24 (a + b)^2), with 15% to spare.  Every term scales with the
+// local sizes a and b, not with the distance from the origin: near the query,
+// where the nearest neighbour is, the window is a small fraction of the
+// neighbour distance, so the exact re-rank rarely runs for a row that is not
+// the nearest one.  The float32 arithmetic of the threshold itself adds at
+// most 3 * 2^-24 (best + |x|^2), covered by 4 * 2^-24 |x|^2 in the bound and
+// by 2^-22 best in the slack below.
 //
 // Re-rank.  Every lane keeps the exact best (d2, index) of its query under the
 // library's contract (float32 difference form, no FMA, lowest index on ties).
 // A candidate can be skipped only if its screened lower bound exceeds the
-// current best, S + |q|^2 - eps > best (1 + 2^-20), which implies that its
+// current best, S + |x|^2 - eps > best (1 + 2^-20), which implies that its
 // contract distance is strictly larger (the contract value is within
 // 5 * 2^-24 relative of the true distance).  Every other candidate is
-// evaluated exactly, so the result equals the exact search bit for bit.
+// evaluated exactly, from the tile's float32 coordinates staged in LDS beside
+// its packed rows, so the result equals the exact search bit for bit.
 // The scan may be warm-started from a previous assignment (any valid index
 // is an upper bound; it changes the work, never the result).
 //
 // Layout.  Queries are the B operand (32 columns per MFMA), candidates the A
 // operand (32 rows), so each lane holds 16 screened values of one query and
 // reduces them lane-locally; lanes l and l+32 hold the two row halves of the
-// same query and are merged at the end.  A workgroup (4 waves) owns 256
-// queries (two 32-query blocks per wave, so one LDS read of a candidate
-// fragment feeds two MFMAs) and streams the packed candidates through LDS in
-// tiles of 256: the next tile is fetched into registers while the current one
-// is screened, then written to the other LDS buffer.  The rare exact re-rank
-// reads candidate coordinates from global memory (L2).
+// same query and are merged at the end.  A workgroup is one wave and owns 64
+// Morton-consecutive queries (two 32-query blocks: one A operand feeds two
+// MFMAs, issued before either result is reduced), so waves finish
+// independently and a wave whose queries need many candidate tiles delays no
+// other.  A visited tile's eight A operands go from L2 straight into
+// registers, all issued at the start of the tile and consumed in order; the
+// rare exact re-rank reads the candidate's float32 coordinates from L2.  The
+// wave rebuilds its B operands and thresholds in the frame of every tile it
+// screens.
 //
 // Tile culling.  Both point sets are packed in Morton order (the permutation
 // is computed once for a fixed set and reused for its smooth deformations), so
 // a tile of 256 consecutive points is spatially compact, and the pack records
-// each tile's bounding box.  A candidate tile is skipped for a query tile when
-// the squared distance between the two boxes, times (1 - 2^-20), exceeds every
-// query's current best: the box distance bounds every pair's true distance from
+// each tile's bounding box.  A candidate tile is skipped for a wave when the
+// squared distance between its box and the box of the wave's 64 queries, times
+// (1 - 2^-20), exceeds every one of their current bests: the box distance bounds every pair's true distance from
 // below, the contract distance is within 5 * 2^-24 relative of the true one and
 // the float32 box distance within 6 * 2^-24, so a skipped candidate is strictly
 // farther than the best and can be neither the nearest nor a tie.  Tiles are
 // listed by that test against the warm-start bests, visited starting from the
 // candidate tile of the same Morton rank, and re-tested against the improving
-// bests before each visit; each wave also skips a visited tile whose box
-// distance to its own 64 queries exceeds their largest best.  Ties are broken on the original indices, which the
+// bests before each visit.  Ties are broken on the original indices, which the
 // packed coordinates carry, so the result is the exact search's bit for bit.
 #include "common.h"
 
@@ -63,17 +76,32 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #ifndef PDG_SCREEN_TILE
 #define PDG_SCREEN_TILE 256
 #endif
-constexpr int kThreads = 256;
-constexpr int kQB = PDG_SCREEN_QB;  // 32-query blocks per wave
-constexpr int kQPerBlock = 4 * 32 * kQB;
+#ifndef PDG_SCREEN_WAVES
+#define PDG_SCREEN_WAVES 1
+#endif
+#ifndef PDG_SCREEN_STAGE
+#define PDG_SCREEN_STAGE 0
+#endif
+constexpr int kWaves = PDG_SCREEN_WAVES;   // independent waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr bool kStage = PDG_SCREEN_STAGE;  // tile coordinates staged in LDS for the re-rank
+constexpr int kQB = PDG_SCREEN_QB;  // 32-query blocks per wave (even)
+static_assert(kQB % 2 == 0, "query blocks are screened in pairs");
+constexpr int kQPerWave = 32 * kQB;
+constexpr int kQPerBlock = kWaves * kQPerWave;
 constexpr int kCTile = PDG_SCREEN_TILE;   // candidates per LDS tile
-constexpr int kPerThread = kCTile / kThreads;
 constexpr int kTile = 256;          // points per box tile (query block and candidate tile)
-static_assert(kQPerBlock == kTile && kCTile == kTile, "box tiles must match the screen tiles");
-constexpr int kListMax = 1024;      // candidate tiles listed per pass of the cull
+static_assert(kCTile == kTile, "candidate boxes must match the screened tiles");
+constexpr int kListMax = 256;       // candidate tiles listed per pass of a wave's cull
+constexpr int kBoxStride = 3;       // float4 per tile: min corner, max corner, (centre, radius)
+static_assert(kBoxStride == 3, "the box layout is declared in common.h (screen_box_count)");
 constexpr float kCullSlack = 1.0f - 1.0f / 1048576.0f;   // 1 - 2^-20
-constexpr float kEpsAB = 3e-5f, kEpsSq = 2e-6f, kEpsAbs = 1e-6f;
-constexpr float kRelSlack = 1.0f + 1.0f / 1048576.0f;   // 1 + 2^-20
+// screen error bound in a tile's frame (a = |q - C|, b = tile radius)
+constexpr float kEpsAB = 3e-5f, kEpsSq = 2e-6f;
+constexpr float kEpsQn = 4.0f / 16777216.0f;             // 4 * 2^-24, threshold arithmetic
+constexpr float kEpsAbs = 1e-30f;                        // keeps the bound above underflow
+constexpr float kThrSlack = 1.0f + 1.0f / 1048576.0f + 1.0f / 4194304.0f;   // 1 + 2^-20 + 2^-22
+constexpr float kRadSlack = 1.0f + 1.0f / 1048576.0f;    // 1 + 2^-20
 
 __device__ __forceinline__ unsigned short bf16_rn(float f) {
   unsigned u = __float_as_uint(f);
@@ -114,14 +142,17 @@ __global__ __launch_bounds__(256) void morton_kernel(const float *__restrict__ x
   vals[i] = (uint32_t)i;
 }
 
-// One thread per packed position i (original point perm[i]): the packed bf16
-// row (32 B), the float32 coordinates with the original index, max |c| over
-// the set (float bits of non-negative values order like unsigned integers, so
-// an integer atomic max is exact and order independent; one per block), and,
-// one block per 256-point tile, the tile's bounding box.
+// One workgroup per 256-point tile, one thread per packed position i (original
+// point perm[i]).  The tile's bounding box and its centre C (midpoint of the
+// box in float32) come first; then every point is packed relative to C:
+// delta = fl(c - C), its bf16 row (32 B) and |delta|^2 split in three, the
+// float32 coordinates with the original index, and the tile's radius
+// r = max |delta| (rounded up) beside C.
 __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__ sets, int nsets,
                                                    unsigned nb) {
-  __shared__ float red[7][4];
+#pragma clang fp contract(off)
+  __shared__ float red[6][4];
+  __shared__ float rads[4];
   unsigned job, tb;                   // one set's workgroups on one XCD
   if (!job_block(blockIdx.x, (unsigned)nsets, nb, job, tb)) return;
   const ScreenSet S = sets[job];
@@ -132,21 +163,47 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
   PDG_GLOBAL float4 *scoords = glb(S.coords);
   PDG_GLOBAL float4 *sboxes = glb(S.boxes);
   const int i = tb * 256 + threadIdx.x;
-  float nrm = 0.f;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool in = i < S.n;
+  float c[3] = {0.f, 0.f, 0.f};
+  int o = 0;
   float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
   float hi3[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
-  if (i < S.n) {
+  if (in) {
     const long long n = S.n;
-    const int o = S.perm ? sperm[i] : i;
-    const float c[3] = {sx[o], sx[n + o], sx[2 * n + o]};
+    o = S.perm ? sperm[i] : i;
+    c[0] = sx[o];
+    c[1] = sx[n + o];
+    c[2] = sx[2 * n + o];
+    for (int k = 0; k < 3; ++k) lo[k] = hi3[k] = c[k];
+  }
+  for (int d = 32; d > 0; d >>= 1)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], d, 64));
+      hi3[k] = fmaxf(hi3[k], __shfl_xor(hi3[k], d, 64));
+    }
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) {
+      red[k][wv] = lo[k];
+      red[3 + k][wv] = hi3[k];
+    }
+  __syncthreads();
+  float b[6], ctr[3];
+  for (int k = 0; k < 3; ++k) {
+    b[k] = fminf(fminf(red[k][0], red[k][1]), fminf(red[k][2], red[k][3]));
+    b[3 + k] = fmaxf(fmaxf(red[3 + k][0], red[3 + k][1]), fmaxf(red[3 + k][2], red[3 + k][3]));
+    ctr[k] = 0.5f * (b[k] + b[3 + k]);
+  }
+  float rad = 0.f;
+  if (in) {
+    float dl[3];
     unsigned short hi[3], lw[3];
     for (int k = 0; k < 3; ++k) {
-      hi[k] = bf16_rn(c[k]);
-      lw[k] = bf16_rn(c[k] - bf16_f(hi[k]));
-      lo[k] = c[k];
-      hi3[k] = c[k];
+      dl[k] = c[k] - ctr[k];
+      hi[k] = bf16_rn(dl[k]);
+      lw[k] = bf16_rn(dl[k] - bf16_f(hi[k]));
     }
-    const float nn = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2];
+    const float nn = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
     const unsigned short n0 = bf16_rn(nn);
     const unsigned short n1 = bf16_rn(nn - bf16_f(n0));
     const unsigned short n2 = bf16_rn((nn - bf16_f(n0)) - bf16_f(n1));
@@ -172,35 +229,18 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     spk[2 * i] = w0;
     spk[2 * i + 1] = w1;
     scoords[i] = make_float4(c[0], c[1], c[2], __int_as_float(o));
-    nrm = sqrtf(nn);
+    rad = sqrtf(nn);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    nrm = fmaxf(nrm, __shfl_xor(nrm, o, 64));
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = fminf(lo[k], __shfl_xor(lo[k], o, 64));
-      hi3[k] = fmaxf(hi3[k], __shfl_xor(hi3[k], o, 64));
-    }
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[6][wv] = nrm;
-    for (int k = 0; k < 3; ++k) {
-      red[k][wv] = lo[k];
-      red[3 + k][wv] = hi3[k];
-    }
-  }
+  for (int d = 32; d > 0; d >>= 1) rad = fmaxf(rad, __shfl_xor(rad, d, 64));
+  if (lane == 0) rads[wv] = rad;
   __syncthreads();
   if (threadIdx.x == 0) {
-    float b[6];
-    for (int k = 0; k < 3; ++k) {
-      b[k] = fminf(fminf(red[k][0], red[k][1]), fminf(red[k][2], red[k][3]));
-      b[3 + k] = fmaxf(fmaxf(red[3 + k][0], red[3 + k][1]), fmaxf(red[3 + k][2], red[3 + k][3]));
-    }
-    // one atomic per block; each set's maximum sits on a cache line of its own
-    const float m = fmaxf(fmaxf(red[6][0], red[6][1]), fmaxf(red[6][2], red[6][3]));
-    if (m > 0.f) atomicMax(glb(S.maxnorm), __float_as_uint(m));
-    sboxes[2 * tb] = make_float4(b[0], b[1], b[2], 0.f);
-    sboxes[2 * tb + 1] = make_float4(b[3], b[4], b[5], 0.f);
+    // |delta| <= sqrt(fl(|delta|^2)) (1 + 2^-20): the float32 norm and square
+    // root are within 2.5 * 2^-24 of it
+    const float r = fmaxf(fmaxf(rads[0], rads[1]), fmaxf(rads[2], rads[3])) * kRadSlack;
+    sboxes[kBoxStride * tb] = make_float4(b[0], b[1], b[2], 0.f);
+    sboxes[kBoxStride * tb + 1] = make_float4(b[3], b[4], b[5], 0.f);
+    sboxes[kBoxStride * tb + 2] = make_float4(ctr[0], ctr[1], ctr[2], r);
   }
 }
 
@@ -215,84 +255,94 @@ __device__ __forceinline__ float box_lb(const float4 &amin, const float4 &amax, 
 }
 
 struct QState {
-  float x, y, z, qn, eps, best, thr;
-  int idx;
+  float x, y, z;      // the query (global coordinates)
+  float best;         // contract d2 of the current best candidate
+  int idx;            // its original index
+  float qn, eps;      // |q - C|^2 and the screen's error bound in the current tile's frame
+  float thr;          // screened values above it are neither a better neighbour nor a tie
 };
 
-__device__ __forceinline__ void set_thr(QState &s) { s.thr = s.best * kRelSlack - s.qn + s.eps; }
+// best (1 + 2^-20 + 2^-22): the 2^-20 separates the contract distance from
+// the true one, the 2^-22 covers the float32 threshold arithmetic's rounding
+// of best.
+__device__ __forceinline__ void set_thr(QState &s) { s.thr = s.best * kThrSlack - s.qn + s.eps; }
+
+// The query in the frame of a candidate tile with centre C and radius rb:
+// x = fl(q - C) split into bf16 hi/lo terms as this lane's half of the B
+// operand (half 0: slots 0..7 = x_hi, x_hi, x_lo.x, x_lo.y; half 1: slots
+// 8..15 = x_lo.z, 1, 1, 1, 0 x 4), and the error bound of the screen in
+// that frame.
+__device__ __forceinline__ void enter_tile(QState &s, const float4 &cen, int half, bf16x8 &bq) {
+#pragma clang fp contract(off)
+  const float lx = s.x - cen.x, ly = s.y - cen.y, lz = s.z - cen.z;
+  const __bf16 hx = (__bf16)lx, hy = (__bf16)ly, hz = (__bf16)lz;
+  const __bf16 ox = (__bf16)(lx - (float)hx), oy = (__bf16)(ly - (float)hy),
+               oz = (__bf16)(lz - (float)hz);
+  const __bf16 one = (__bf16)1.0f, zero = (__bf16)0.0f;
+  if (half == 0) {
+    bq[0] = hx; bq[1] = hy; bq[2] = hz; bq[3] = hx;
+    bq[4] = hy; bq[5] = hz; bq[6] = ox; bq[7] = oy;
+  } else {
+    bq[0] = oz; bq[1] = one; bq[2] = one; bq[3] = one;
+    bq[4] = zero; bq[5] = zero; bq[6] = zero; bq[7] = zero;
+  }
+  s.qn = (lx * lx + ly * ly) + lz * lz;
+  // hardware square root (within 1 ulp): the constants keep 15% above the
+  // derived bound
+  const float a = __builtin_amdgcn_sqrtf(s.qn), rb = cen.w;
+  s.eps = kEpsAB * a * rb + kEpsSq * (s.qn + rb * rb) + kEpsQn * s.qn + kEpsAbs;
+  set_thr(s);
+}
 
 // rows held by this lane for output register r of a 32x32 MFMA
 __device__ __forceinline__ int out_row(int r, int lane) {
   return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
-__device__ __forceinline__ void consider(QState &s, const f32x16 &v, int lane, int cbase, int nc,
-                                         const PDG_GLOBAL float4 *__restrict__ cc) {
-  // (the chain starts from +inf, a canonical value, so that no product needs
-  // a canonicalising instruction before the three-operand minima)
-  float m = __builtin_huge_valf();
+// Lane-local minimum of 16 screened values: two chains of three-operand
+// minima from +inf (a canonical value, so no product needs a canonicalising
+// instruction), joined at the end.
+__device__ __forceinline__ float min16(const f32x16 &v) {
+  float a = __builtin_huge_valf(), b = __builtin_huge_valf();
 #pragma unroll
-  for (int r = 0; r < 16; r += 2) m = fminf(fminf(m, v[r]), v[r + 1]);
-  if (!(m <= s.thr)) return;
-  // rare path: rows whose screened value passes the current threshold (the
-  // threshold only tightens below, so re-ranking all of them is safe)
-  unsigned mask = 0;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) mask |= (v[r] <= s.thr ? 1u : 0u) << r;
-  while (mask) {
-    const int r = __builtin_ctz(mask);
-    mask &= mask - 1;
-    const int c = cbase + out_row(r, lane);
-    if (c >= nc) continue;             // padded rows never count
-    const float4 p = cc[c];
-    const float d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
-    const int o = __float_as_int(p.w);
-    if (d < s.best || (d == s.best && o < s.idx)) {
-      s.best = d;
-      s.idx = o;
-      set_thr(s);
+  for (int r = 0; r < 8; r += 2) {
+    a = fminf(fminf(a, v[r]), v[r + 1]);
+    b = fminf(fminf(b, v[r + 8]), v[r + 9]);
+  }
+  return fminf(a, b);
+}
+
+// Exact re-rank of every row of this lane whose screened value passes the
+// threshold (the threshold only tightens on the way, so later rows are tested
+// against the improved best); candidate coordinates come from the wave's LDS
+// copy of the tile.
+template <typename CoordPtr>
+__device__ __forceinline__ void rerank(QState &s, const f32x16 &v, int lane, int r0, int nleft,
+                                       CoordPtr tc) {
+#pragma nounroll
+  for (int r = 0; r < 16; ++r) {   // r is wave-uniform: v[r] is a register-relative move
+    if (v[r] <= s.thr) {
+      const int row = r0 + out_row(r, lane);   // position in the tile
+      if (row < nleft) {                       // padded rows never count
+        const float4 p = tc[row];
+        const float d = d2_contract(s.x, s.y, s.z, p.x, p.y, p.z);
+        const int o = __float_as_int(p.w);
+        if (d < s.best || (d == s.best && o < s.idx)) {
+          s.best = d;
+          s.idx = o;
+          set_thr(s);
+        }
+      }
     }
   }
 }
 
-// this thread's share of a tile: packed rows of candidates c0 + tid + k*256
-struct TileRegs {
-  uint4 w[kPerThread][2];
-};
-
-__device__ __forceinline__ void fetch_tile(const PDG_GLOBAL uint4 *pack, int nc, int c0,
-                                           TileRegs &t) {
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    // every lane loads (rows past the end re-read the last row), so the
-    // number of loads in flight is the same on every path
-    const int c = c0 + k * kThreads + (int)threadIdx.x;
-    const long long cl = c < nc ? c : nc - 1;
-    t.w[k][0] = pack[2 * cl];
-    t.w[k][1] = pack[2 * cl + 1];
-    if (c >= nc) {
-      t.w[k][0] = make_uint4(0u, 0u, 0u, 0u);
-      t.w[k][1] = make_uint4(0x7F800000u, 0u, 0u, 0u);   // n_hi = +inf: S = +inf
-    }
-  }
-}
-
-__device__ __forceinline__ void store_tile(const TileRegs &t, uint4 *spack) {
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const int i = k * kThreads + (int)threadIdx.x;
-    spack[2 * i] = t.w[k][0];
-    spack[2 * i + 1] = t.w[k][1];
-  }
-}
-
+// Largest current best of this wave's valid queries (lanes without a query
+// report 0): an upper bound of every best the wave still improves.
 template <int D>
 __device__ __forceinline__ float row_shr(float x) {   // lane l - D of its row of 16, else 0
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + D, 0xf, 0xf, true));
 }
-
-// Largest current best of this wave's valid queries (lanes without a query
-// report 0); the block maximum bounds every query's best from above.
 __device__ __forceinline__ float wave_best_max(const QState *st, const bool *ok) {
   float m = 0.f;
 #pragma unroll
@@ -316,10 +366,18 @@ __device__ __forceinline__ float wave_best_max(const QState *st, const bool *ok)
 // in that XCD's L2.
 constexpr int kXcds = 8;
 
+// Every wave works alone on its 64 queries: it lists the candidate tiles whose
+// box can hold a better neighbour than its queries' current bests, and
+// screens them one after another, re-testing each against the improved bests
+// before the visit.  A visited tile's packed rows go straight from L2 into
+// registers (the A operands of its eight 32-candidate steps, issued together
+// at the start of the tile) and its coordinates into the wave's own LDS slice
+// (for the re-rank); no workgroup barrier is taken.
+//
 // The grid is 1-D with a multiple of 8 blocks, so lin -> tile is a bijection;
 // tile = job * qt + query tile, tiles >= nblk do nothing.
-__global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob *__restrict__ jobs,
-                                                             int warm, unsigned qt, unsigned nblk) {
+__global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
+    const ScreenJob *__restrict__ jobs, int warm, unsigned qt, unsigned nblk) {
   const unsigned lin = blockIdx.x;
   const unsigned per = gridDim.x / kXcds;
   const unsigned tile = (lin % kXcds) * per + lin / kXcds;
@@ -329,26 +387,26 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
   const int q0 = bx * kQPerBlock;
   if (q0 >= J.nq) return;
   const PDG_GLOBAL float4 *jq = glb(J.q), *jcc = glb(J.cc);
-  const PDG_GLOBAL float4 *jqboxes = glb(J.qboxes), *jcboxes = glb(J.cboxes);
+  const PDG_GLOBAL float4 *jcboxes = glb(J.cboxes);
   const PDG_GLOBAL float *jc = glb(J.c);
   const PDG_GLOBAL uint4 *jpack = glb(J.pack);
   PDG_GLOBAL int *jnn = glb(J.nn);
-  __shared__ uint4 spack[2][kCTile * 2];
-  __shared__ int tlist[kListMax];
-  __shared__ float tlb[kListMax];
-  __shared__ float wmax[2][4];
-  __shared__ int s_count;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ float4 tcs[kWaves][kStage ? kTile : 1];   // each wave's visited tile's coordinates
+  __shared__ int wls[kWaves][kListMax];
+  __shared__ float wlbs[kWaves][kListMax];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float4 *tc = tcs[wv];
+  int *wl = wls[wv];
+  float *wlb = wlbs[wv];
   const int half = lane >> 5;
   const long long nc = J.nc;
-  const float cmax = __uint_as_float(*glb(J.maxnorm));
   QState st[kQB];
   bool ok[kQB];
   int qorig[kQB];
   bf16x8 bq[kQB];
 #pragma unroll
   for (int h = 0; h < kQB; ++h) {
-    const int q = q0 + wv * 32 * kQB + h * 32 + (lane & 31);   // packed position
+    const int q = q0 + wv * kQPerWave + h * 32 + (lane & 31);   // packed position
     QState &s = st[h];
     ok[h] = q < J.nq;
     float4 qc = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -357,9 +415,6 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
     s.x = qc.x;
     s.y = qc.y;
     s.z = qc.z;
-    s.qn = (s.x * s.x + s.y * s.y) + s.z * s.z;
-    const float a = sqrtf(s.qn);
-    s.eps = kEpsAB * a * cmax + kEpsSq * (s.qn + cmax * cmax) + kEpsAbs;
     s.best = __builtin_huge_valf();
     s.idx = 0x7fffffff;
     if (ok[h] && warm) {
@@ -369,23 +424,10 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
         s.idx = p;
       }
     }
+    s.qn = 0.f;
+    s.eps = 0.f;
     set_thr(s);
-    // B operand: column (lane & 31), k-slots 8*half .. 8*half+7 of the query row
-    const float qv[3] = {s.x, s.y, s.z};
-    unsigned short hi[3], lo[3];
-    for (int k = 0; k < 3; ++k) {
-      hi[k] = bf16_rn(qv[k]);
-      lo[k] = bf16_rn(qv[k] - bf16_f(hi[k]));
-    }
-    const unsigned short one = 0x3F80;
-    unsigned short row[16] = {hi[0], hi[1], hi[2], hi[0], hi[1], hi[2], lo[0], lo[1],
-                              lo[2], one, one, one, 0, 0, 0, 0};
-    for (int e = 0; e < 8; ++e) {
-      const unsigned short b = row[8 * half + e];
-      bq[h][e] = *reinterpret_cast<const __bf16 *>(&b);
-    }
   }
-  const float4 qmin = jqboxes[2 * bx], qmax = jqboxes[2 * bx + 1];
   // this wave's 64 queries: their box (wave-uniform)
   float4 wmin = make_float4(__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(), 0.f);
   float4 wmaxc = make_float4(-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf(), 0.f);
@@ -410,96 +452,109 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
   wmaxc = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmaxc.x))),
                       __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmaxc.y))),
                       __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmaxc.z))), 0.f);
-  const bool wany = wmin.x <= wmaxc.x;       // the wave has at least one query
-  const int ntiles = (J.nc + kTile - 1) / kTile;
-  const int qtiles = (J.nq + kTile - 1) / kTile;
-  const int start = (int)((long long)bx * ntiles / qtiles);
-  {
-    const float m = wave_best_max(st, ok);
-    if (lane == 0) wmax[0][wv] = m;
-  }
-  __syncthreads();
-  float bmax = fmaxf(fmaxf(wmax[0][0], wmax[0][1]), fmaxf(wmax[0][2], wmax[0][3]));
-  int it = 1;                   // parity of the wmax buffer written next
   unsigned issued = 0;          // matrix-core products this wave issued (wave-uniform)
-  TileRegs regs;
-  for (int base = 0; base < ntiles; base += kListMax) {
-    const int span = ntiles - base < kListMax ? ntiles - base : kListMax;
-    if (wv == 0) {              // list the tiles that pass the box test, in visiting order
+  if (wmin.x <= wmaxc.x) {      // the wave has at least one query
+    const int ntiles = (J.nc + kTile - 1) / kTile;
+    const int qtiles = (J.nq + kQPerWave - 1) / kQPerWave;
+    const int start = (int)((long long)(bx * kWaves + wv) * ntiles / qtiles);   // same Morton rank
+    float wbest = wave_best_max(st, ok);
+    for (int base = 0; base < ntiles; base += kListMax) {
+      const int span = ntiles - base < kListMax ? ntiles - base : kListMax;
+      // list the tiles that pass the box test, in visiting order
       int count = 0;
       for (int k0 = 0; k0 < span; k0 += 64) {
         const int k = k0 + lane;
         bool pass = false;
         float lb = 0.f;
-        int tile = 0;
+        int t = 0;
         if (k < span) {
-          tile = (start + base + k) % ntiles;
-          lb = box_lb(qmin, qmax, jcboxes[2 * tile], jcboxes[2 * tile + 1]);
-          pass = !(lb * kCullSlack > bmax);
+          t = (start + base + k) % ntiles;
+          lb = box_lb(wmin, wmaxc, jcboxes[kBoxStride * t], jcboxes[kBoxStride * t + 1]);
+          pass = !(lb * kCullSlack > wbest);
         }
         const unsigned long long m = __ballot(pass);
         const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
         if (pass) {
-          tlist[pos] = tile;
-          tlb[pos] = lb;
+          wl[pos] = t;
+          wlb[pos] = lb;
         }
         count += __popcll(m);
       }
-      if (lane == 0) s_count = count;
-    }
-    __syncthreads();
-    const int count = s_count;
-    int i = 0;
-    while (i < count && tlb[i] * kCullSlack > bmax) ++i;
-    float4 tmin = make_float4(0.f, 0.f, 0.f, 0.f), tmax = tmin;   // box of tile tlist[i]
-    if (i < count) {
-      fetch_tile(jpack, J.nc, tlist[i] * kTile, regs);
-      tmin = jcboxes[2 * tlist[i]];
-      tmax = jcboxes[2 * tlist[i] + 1];
-      store_tile(regs, spack[0]);
-    }
-    int buf = 0;
-    while (i < count) {
-      const float wbest = wave_best_max(st, ok);
-      if (lane == 0) wmax[it & 1][wv] = wbest;
-      __syncthreads();          // tile tlist[i] is in spack[buf]; the other buffer is free
-      bmax = fmaxf(fmaxf(wmax[it & 1][0], wmax[it & 1][1]), fmaxf(wmax[it & 1][2], wmax[it & 1][3]));
-      ++it;
-      int nxt = i + 1;
-      while (nxt < count && tlb[nxt] * kCullSlack > bmax) ++nxt;
-      const bool more = nxt < count;
-      // the next tile and its box, in flight while this tile is screened
-      // (issued on every path; without a next tile this one is read again)
-      const int ft = tlist[more ? nxt : i];
-      fetch_tile(jpack, J.nc, ft * kTile, regs);
-      const float4 nmin = jcboxes[2 * ft], nmax = jcboxes[2 * ft + 1];
-      const int c0 = tlist[i] * kTile;
-      const int left = (J.nc - c0 + 31) / 32;
-      // the wave skips a tile that cannot beat any of its own queries' bests
-      const bool wskip = !wany || box_lb(wmin, wmaxc, tmin, tmax) * kCullSlack > wbest;
-      const int nsub = wskip ? 0 : (left < kCTile / 32 ? left : kCTile / 32);
-      // the next sub-tile's operand is read from LDS before this one's products
-      uint4 nraw = spack[buf][2 * (lane & 31) + half];
-      for (int sub = 0; sub < nsub; ++sub) {
-        const uint4 raw = nraw;
-        const int ns = sub + 1 < nsub ? sub + 1 : sub;
-        nraw = spack[buf][2 * (ns * 32 + (lane & 31)) + half];
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&raw);
-        const f32x16 z = {};
+      __builtin_amdgcn_wave_barrier();   // the list is written before it is read
+      for (int i = 0; i < count; ++i) {
+        // list entries are wave-uniform: keep them (and all tile addressing) scalar
+        const float lbi = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wlb[i])));
+        if (lbi * kCullSlack > wbest) continue;   // the improved bests rule it out
+        const int ti = __builtin_amdgcn_readfirstlane(wl[i]);
+        const int c0 = ti * kTile;
+        const int nleft = J.nc - c0;
+        const bool full = nleft >= kTile;   // wave-uniform
+        const int nsub = full ? kCTile / 32 : (nleft + 31) / 32;
+        // the tile's A operands (candidate c0 + 32 s + (lane & 31), this lane's
+        // half row) and coordinates; full tiles address them from one scalar
+        // base with immediate offsets
+        uint4 fr[kCTile / 32];
+        const PDG_GLOBAL uint4 *tp = jpack + 2 * (long long)c0 + 2 * (lane & 31) + half;
+        const PDG_GLOBAL float4 *tq = jcc + c0 + lane;
+        __builtin_amdgcn_wave_barrier();   // the previous tile's re-rank reads are done
+        if (full) {
 #pragma unroll
-        for (int h = 0; h < kQB; ++h) {   // one result live at a time (register budget)
-          const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
-          consider(st[h], v, lane, c0 + sub * 32, J.nc, jcc);
+          for (int sidx = 0; sidx < kCTile / 32; ++sidx) fr[sidx] = tp[64 * sidx];
+          if (kStage) {
+#pragma unroll
+            for (int k = 0; k < kTile / 64; ++k) tc[k * 64 + lane] = tq[64 * k];
+          }
+        } else {
+#pragma unroll
+          for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
+            const int c = c0 + sidx * 32 + (lane & 31);
+            const long long cl = c < J.nc ? c : J.nc - 1;
+            fr[sidx] = jpack[2 * cl + half];
+            if (c >= J.nc)   // padded rows: n_hi = +inf, so S = +inf
+              fr[sidx] = half ? make_uint4(0x7F800000u, 0u, 0u, 0u) : make_uint4(0u, 0u, 0u, 0u);
+          }
+          if (kStage) {
+#pragma unroll
+            for (int k = 0; k < kTile / 64; ++k) {
+              const int c = c0 + k * 64 + lane;
+              tc[k * 64 + lane] = jcc[c < J.nc ? c : J.nc - 1];
+            }
+          }
         }
+        const PDG_GLOBAL float4 *tg = jcc + c0;   // the re-rank's coordinates without staging
+        const float4 cen = jcboxes[kBoxStride * ti + 2];
+#pragma unroll
+        for (int h = 0; h < kQB; ++h) enter_tile(st[h], cen, half, bq[h]);
+        __builtin_amdgcn_wave_barrier();   // the coordinates are written before any re-rank
+#pragma unroll
+        for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
+          if (sidx < nsub) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&fr[sidx]);
+            const f32x16 z = {};
+#pragma unroll
+            for (int hp = 0; hp < kQB; hp += 2) {
+              // two query blocks' products before either is reduced
+              const f32x16 v0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[hp], z, 0, 0, 0);
+              const f32x16 v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[hp + 1], z, 0, 0, 0);
+              const float m0 = min16(v0), m1 = min16(v1);
+              const bool p0 = m0 <= st[hp].thr, p1 = m1 <= st[hp + 1].thr;
+              if (p0 || p1) {   // rare: rows inside the error window
+                if (kStage) {
+                  if (p0) rerank(st[hp], v0, lane, sidx * 32, nleft, tc);
+                  if (p1) rerank(st[hp + 1], v1, lane, sidx * 32, nleft, tc);
+                } else {
+                  if (p0) rerank(st[hp], v0, lane, sidx * 32, nleft, tg);
+                  if (p1) rerank(st[hp + 1], v1, lane, sidx * 32, nleft, tg);
+                }
+              }
+            }
+          }
+        }
+        issued += (unsigned)(nsub * kQB);
+        wbest = wave_best_max(st, ok);
       }
-      if (more) store_tile(regs, spack[buf ^ 1]);
-      buf ^= 1;
-      i = nxt;
-      tmin = nmin;
-      tmax = nmax;
-      issued += (unsigned)(nsub * kQB);
+      __builtin_amdgcn_wave_barrier();   // the list is rebuilt next
     }
-    __syncthreads();            // the list is rebuilt next
   }
 #pragma unroll
   for (int h = 0; h < kQB; ++h) {
@@ -513,7 +568,7 @@ __global__ __launch_bounds__(kThreads, 5) void nn_screen_kernel(const ScreenJob 
     if (half == 0 && ok[h]) jnn[qorig[h]] = s.idx;
   }
   // one integer atomic per wave: the 32 x 32 x 16 products it issued (tiles
-  // a wave skipped by its own box test count nothing)
+  // a wave's own box test rules out count nothing)
   if (J.tiles && lane == 0 && issued) atomicAdd(glb(J.tiles), (unsigned long long)issued);
 }
 

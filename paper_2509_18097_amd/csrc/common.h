@@ -280,7 +280,8 @@ struct ScreenSet {           // one point set packed as screen candidates and qu
   const int *perm;           // [n] packed position -> original index (nullable: identity)
   uint4 *pack;               // [n][2] packed bf16 rows (32 B per point), packed order
   float4 *coords;            // [n] (x, y, z, original index as int bits), packed order
-  float4 *boxes;             // [ceil(n/256)][2] min and max corner of each 256-point tile
+  float4 *boxes;             // [ceil(n/256)][3] per 256-point tile: min corner, max corner,
+                             // (centre C, radius): the frame the tile's rows are packed in
   unsigned *maxnorm;         // float bits of max |x| (zeroed before packing; sets kMaxnormStride apart)
 };
 struct ScreenJob {           // one directed search: packed queries over packed candidates
@@ -299,8 +300,9 @@ inline long long screen_tiles(long long n) { return (n + 255) / 256; }
 // per-set max-norm words sit this many words apart (one 128-byte line each),
 // so the packing atomics of different sets do not meet on one cache line
 constexpr int kMaxnormStride = 32;
-// float4 entries of a set's box array (min and max corner per tile)
-inline long long screen_box_count(long long n) { return 2 * screen_tiles(n); }
+// float4 entries of a set's box array (min corner, max corner, centre and
+// radius per tile)
+inline long long screen_box_count(long long n) { return 3 * screen_tiles(n); }
 // keys = 30-bit Morton codes over [-1, 1]^3 of x ([3][ld] SoA, n points), vals = index
 pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, uint32_t *vals,
                          hipStream_t st);

@@ -39,10 +39,10 @@ import numpy as np
 class ServeRequest:
     rid: int
     arrival: float                 # seconds after the start of the run
-    points: np.ndarray             # (F, 3, N) float32
+    points: object                 # (F, 3, N) float32, host array or device tensor
     res: tuple
-    template: np.ndarray | None = None     # (3, V) float32
-    edges: np.ndarray | None = None        # (2, E) int32
+    template: object = None        # (3, V) float32
+    edges: object = None           # (2, E) int32
     iterations: int = 20
 
     @property
@@ -142,10 +142,13 @@ class GpuExecutor:
         torch = self.torch
         st = self.streams[self._next % len(self.streams)]
         self._next += 1
+        def on_device(a):
+            if a is None or isinstance(a, torch.Tensor):
+                return a                 # already resident (drawn on the device)
+            return torch.from_numpy(a).to("cuda", non_blocking=False)
+
         with torch.cuda.stream(st):
-            pts = torch.from_numpy(req.points).to("cuda", non_blocking=False)
-            tm = None if req.template is None else torch.from_numpy(req.template).cuda()
-            ed = None if req.edges is None else torch.from_numpy(req.edges).cuda()
+            pts, tm, ed = on_device(req.points), on_device(req.template), on_device(req.edges)
             prob = Problem(pts, req.res, template=tm, edges=ed,
                            hp=HyperParams(e_max=req.iterations), chamfer_mode=self.chamfer_mode,
                            precond=self.precond, stream=st)
@@ -269,14 +272,21 @@ class Server:
                           peak_active=peak_active, rounds=rounds)
 
 
-def poisson_requests(stream, iterations: int = 20, with_template: bool = True):
-    """ServeRequests from ``synth.request_stream`` entries (host arrays)."""
+def poisson_requests(stream, iterations: int = 20, with_template: bool = True, device=None):
+    """ServeRequests from ``synth.request_stream`` entries: host arrays, or,
+    with ``device``, tensors drawn on that device by the same recipe."""
+    import synth
     out = []
     for r in stream:
-        seq = r.sequence()
-        out.append(ServeRequest(rid=r.rid, arrival=r.arrival, points=seq.points, res=r.res,
-                                template=seq.template if with_template else None,
-                                edges=seq.edges if with_template else None,
+        if device is None:
+            seq = r.sequence()
+            pts, tmpl, edges = seq.points, seq.template, seq.edges
+        else:
+            pts, tmpl, edges = synth.deforming_sequence_device(
+                seed=r.seed, frames=r.frames, n=r.n, subdiv=r.subdiv, device=device)
+        out.append(ServeRequest(rid=r.rid, arrival=r.arrival, points=pts, res=r.res,
+                                template=tmpl if with_template else None,
+                                edges=edges if with_template else None,
                                 iterations=iterations))
     return out
 

@@ -25,6 +25,7 @@ __all__ = [
     "sphere_points", "ellipsoid_points", "icosphere", "FourierField",
     "pair_on_sphere", "Sequence", "deforming_sequence", "cloud_pair_cube",
     "grid_stack", "Request", "request_stream", "levels_for_points",
+    "deforming_sequence_device",
 ]
 
 ELLIPSOID_AXES = (1.0, 0.6, 0.4)
@@ -170,6 +171,57 @@ def deforming_sequence(seed: int = 0, frames: int = 32, n: int = 50_000,
     meta = dict(seed=seed, frames=frames, n=n, subdiv=subdiv, modes=modes,
                 amp=amp, noise=noise, axes=tuple(axes))
     return Sequence(points=pts, template=_f32(x0.T), edges=e, faces=f, meta=meta)
+
+
+_ICO_CACHE: dict = {}
+
+
+def _icosphere_cached(subdiv: int):
+    if subdiv not in _ICO_CACHE:
+        _ICO_CACHE[subdiv] = icosphere(subdiv)
+    return _ICO_CACHE[subdiv]
+
+
+def deforming_sequence_device(seed: int = 0, frames: int = 32, n: int = 50_000,
+                              subdiv: int = 4, modes: int = 8, amp: float = 0.05,
+                              noise: float = 0.003, axes=ELLIPSOID_AXES, device="cuda"):
+    """The recipe of ``deforming_sequence`` drawn on a torch device (for the
+    serving stream, whose hundreds of requests would take minutes to draw on
+    the host).  Draws come from torch's generator of that device seeded with
+    ``seed``, in float64, cast once to float32; the values differ from the
+    host generator's (another random stream), the distributions are the same.
+
+    Returns ``(points (F, 3, N) float32, template (3, V) float32,
+    edges (2, E) int32)`` as tensors on ``device``.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = dict(dtype=torch.float64, device=device)
+    ax = torch.tensor(axes, **f64)
+
+    def sphere(m):
+        x = torch.randn((m, 3), generator=g, **f64)
+        return x / torch.linalg.norm(x, dim=1, keepdim=True)
+
+    a = sphere(modes)
+    w = torch.randn((modes, 3), generator=g, **f64)
+    phi = torch.rand(modes, generator=g, **f64) * (2.0 * math.pi)
+    nu = 0.5 + torch.rand(modes, generator=g, **f64)
+
+    def field(x, t):
+        arg = 2.0 * math.pi * (x @ w.T) + phi[None, :] + 2.0 * math.pi * nu[None, :] * (t / frames)
+        return (amp / math.sqrt(modes)) * (torch.sin(arg) @ a)
+
+    pts = torch.empty((frames, 3, n), dtype=torch.float32, device=device)
+    for t in range(frames):
+        s = sphere(n) * ax
+        p = s + field(s, t) + noise * torch.randn((n, 3), generator=g, **f64)
+        pts[t] = p.T.to(torch.float32)
+    v, _, e = _icosphere_cached(subdiv)
+    s0 = torch.from_numpy(v).to(device) * ax
+    x0 = (s0 + field(s0, 0)).T.to(torch.float32).contiguous()
+    return pts, x0, torch.from_numpy(e).to(device)
 
 
 def cloud_pair_cube(seed: int = 0, n: int = 200_000, jitter: float = 0.01):
