@@ -685,23 +685,28 @@ def serve_requests(count):
     return reqs, time.perf_counter() - t
 
 
-def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0):
+def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0, executor="batch"):
     """Serve the requests with continuous batching under an HBM budget of 60%
     of free memory; arrival times divided by `rate_scale` (1: the stream's
-    4 requests/s)."""
+    4 requests/s).  executor "batch": every round one batched iteration of all
+    resident requests (one launch of the screen and Chamfer terms over all
+    their jobs); "streams": each request's own graph replayed on 4 streams."""
     import dataclasses
     import torch
-    from paper_2509_18097_amd.serve import GpuExecutor, Server
+    from paper_2509_18097_amd.serve import BatchExecutor, GpuExecutor, Server
     reqs = [dataclasses.replace(r, arrival=r.arrival / rate_scale) for r in reqs]
     free, _ = torch.cuda.mem_get_info()
-    ex = GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4)
+    ex = (BatchExecutor(chamfer_mode=chamfer, precond=precond) if executor == "batch" else
+          GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4))
     st = Server(ex, budget_bytes=int(0.6 * free), max_slots=slots).run(reqs)
     out = st.summary()
-    out.update({"stream_requests": len(reqs), "iterations_per_request": 20,
+    out.update({"executor": executor, "stream_requests": len(reqs), "iterations_per_request": 20,
                 "arrival_rate_per_s": 4.0 * rate_scale,
                 "budget_bytes": int(0.6 * free), "chamfer": chamfer, "precond": precond,
                 "max_slots": slots,
                 "load": round(st.makespan / st.arrival_span, 3) if st.arrival_span > 0 else None})
+    if executor == "batch":
+        out["batches_built"] = ex.batches_built
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 
@@ -820,6 +825,10 @@ def main():
         if args.serve_load > 1.0:
             result["serving_overload"] = serve(reqs, args.chamfer, args.precond, args.serve_slots,
                                                rate_scale=args.serve_load)
+            result["serving_overload_streams"] = serve(reqs, args.chamfer, args.precond,
+                                                       args.serve_slots,
+                                                       rate_scale=args.serve_load,
+                                                       executor="streams")
         del reqs
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

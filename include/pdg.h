@@ -401,14 +401,39 @@ typedef enum {
 } pdg_stage;
 pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream);
 
-/* Several problems' iterations in one call: each problem's step is enqueued
- * on its own stream from `streams` (count entries, [host]); the caller joins
- * them.  epochs: [host] int32[count]; loss_terms: [host] array of device
- * pointers (entries nullable). */
-pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *epochs,
-                          double *const *loss_terms, int32_t use_graph,
-                          const hipStream_t *streams);
 pdg_status pdg_problem_destroy(pdg_problem *p);
+
+/* ------------------------------------------------------------- batches --
+ * Continuous batching of served requests (several independent problems
+ * iterated together; not in the paper).  A batch is a fixed set of problems
+ * whose iterations run as one unit: the screen pack, the nearest-neighbour
+ * search (Eq. 12) and the Chamfer terms (Eq. 11, 13) of every member are one
+ * launch each over a device table of all members' jobs (a job per transition,
+ * term and direction of a member), and every other stage of a member runs as
+ * in pdg_step, the members' kernels overlapping on parallel branches.  A job
+ * writes only its own problem's buffers, so each member's results are bitwise
+ * those of pdg_step on it alone.  A server makes a new batch whenever the set
+ * of resident requests changes (creation copies the members' tables and
+ * captures nothing until the first pdg_batch_step with use_graph).
+ * Members must share the Chamfer mode and alpha, and none may propagate from a
+ * keyframe inside its sequence (PDG_EUNSUPPORTED); a problem may belong to
+ * several batches but the batches' steps must not overlap.
+ * ws: >= pdg_batch_workspace() bytes of device memory, 256-byte aligned, owned
+ * by the caller for the batch's lifetime.  Creation enqueues copies on
+ * `stream`; step the batch on that stream (or synchronise first).  The batch
+ * handle and its branch streams are host resources freed by
+ * pdg_batch_destroy (the members stay). */
+typedef struct pdg_batch pdg_batch;
+pdg_status pdg_batch_workspace(pdg_problem *const *ps /*[host]*/, int32_t count, size_t *bytes);
+pdg_status pdg_batch_create(pdg_problem *const *ps /*[host]*/, int32_t count, void *ws,
+                            size_t ws_bytes, hipStream_t stream, pdg_batch **out);
+/* One iteration of every member: epochs [host] int32[count], in member order
+ * (each in [0, e_max] of its member).  use_graph captures the batch's
+ * iteration once into a HIP graph and replays it.  Loss terms are read per
+ * member (PDG_BUF_TERMS). */
+pdg_status pdg_batch_step(pdg_batch *b, const int32_t *epochs, int32_t use_graph,
+                          hipStream_t stream);
+pdg_status pdg_batch_destroy(pdg_batch *b);
 
 /* Intermediate buffers of the last step, for checking stage by stage.
  *   PDG_BUF_PHAT   float [T][3][n]   warped input points

@@ -98,8 +98,10 @@ _SIGS = {
     "pdg_problem_create": (_I32, [ctypes.POINTER(ProblemDesc), _P, ctypes.POINTER(_P)]),
     "pdg_step": (_I32, [_P, _I32, _P, _I32, _P]),
     "pdg_step_stage": (_I32, [_P, _I32, _P]),
-    "pdg_step_batch": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_I32), ctypes.POINTER(_P),
-                              _I32, ctypes.POINTER(_P)]),
+    "pdg_batch_workspace": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_SZ)]),
+    "pdg_batch_create": (_I32, [ctypes.POINTER(_P), _I32, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "pdg_batch_step": (_I32, [_P, ctypes.POINTER(_I32), _I32, _P]),
+    "pdg_batch_destroy": (_I32, [_P]),
     "pdg_problem_destroy": (_I32, [_P]),
     "pdg_problem_buffer": (_I32, [_P, _I32, ctypes.POINTER(_P), ctypes.POINTER(_SZ)]),
     "pdg_problem_branch": (_I32, [_P, _I32, ctypes.POINTER(_P)]),

@@ -174,7 +174,7 @@ ScatterList scatter_list(const uint32_t *keys, const uint32_t *vals, const int *
 
 // --------------------------------------------------------------- chamfer --
 ScreenSet screen_set(const float *x, long long n, const int *perm, uint4 *pack, float4 *coords,
-                     float4 *boxes, unsigned *maxnorm) {
+                     float4 *boxes) {
   ScreenSet S;
   memset(&S, 0, sizeof S);
   S.x = x;
@@ -183,7 +183,6 @@ ScreenSet screen_set(const float *x, long long n, const int *perm, uint4 *pack, 
   S.pack = pack;
   S.coords = coords;
   S.boxes = boxes;
-  S.maxnorm = maxnorm;
   return S;
 }
 // queries from set Q, candidates from set C
@@ -199,7 +198,6 @@ ScreenJob screen_job(const ScreenSet &Q, const ScreenSet &C, int *nn, unsigned l
   J.pack = C.pack;
   J.cc = C.coords;
   J.cboxes = C.boxes;
-  J.maxnorm = C.maxnorm;
   J.tiles = tiles;
   return J;
 }
@@ -217,7 +215,6 @@ struct ChamferWs {
   uint4 *pack_a, *pack_b;
   float4 *coords_a, *coords_b, *boxes_a, *boxes_b;
   uint32_t *perm_a, *perm_b;
-  unsigned *maxnorm;
 };
 ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
   ChamferWs w;
@@ -233,7 +230,6 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
     w.boxes_b = c.take<float4>(screen_box_count(m));
     w.perm_a = c.take<uint32_t>(n);
     w.perm_b = c.take<uint32_t>(m);
-    w.maxnorm = c.take<unsigned>(2 * kMaxnormStride);
   }
   const long long nk = mode == PDG_CHAMFER_BF16_SCREEN && n > m ? n : m;   // sort entries
   w.jobs = c.take<NNJob>(2);
@@ -277,6 +273,9 @@ pdg_status enqueue_chamfer(const ChamferWs &w, const float *a, long long n, cons
   seg.nn_b = nn_b;
   seg.ga = ga;
   seg.a_base = 0;
+  seg.loss = loss;
+  seg.part = w.partials;
+  seg.w = dir_weight ? dir_weight : w.w_default;
   const unsigned bb = 0;
   const double ones[2] = {1.0, 1.0};
   PDG_TRY(upload_small(w.jobs, jobs, sizeof jobs, stream));
@@ -293,26 +292,23 @@ pdg_status enqueue_chamfer(const ChamferWs &w, const float *a, long long n, cons
     PDG_TRY(radix_sort(w.keys, w.perm_a, n, 30, w.sort, stream));
     PDG_TRY(launch_morton(b, m, (int)m, w.keys, w.perm_b, stream));
     PDG_TRY(radix_sort(w.keys, w.perm_b, m, 30, w.sort, stream));
-    ss[0] = screen_set(a, n, (const int *)w.perm_a, w.pack_a, w.coords_a, w.boxes_a, w.maxnorm);
-    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b,
-                       w.maxnorm + kMaxnormStride);
+    ss[0] = screen_set(a, n, (const int *)w.perm_a, w.pack_a, w.coords_a, w.boxes_a);
+    ss[1] = screen_set(b, m, (const int *)w.perm_b, w.pack_b, w.coords_b, w.boxes_b);
     sj[0] = screen_job(ss[0], ss[1], nn_a, nullptr);
     sj[1] = screen_job(ss[1], ss[0], nn_b, nullptr);
     PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
     PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
-    PDG_TRY(launch_fill((float *)w.maxnorm, 2 * kMaxnormStride, 0.f, stream));
     PDG_TRY(launch_screen_pack(w.ssets, 2, (int)(n > m ? n : m), stream));
     PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
   } else {
     PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
   }
-  PDG_TRY(launch_chamfer_loss(w.segs, 1, alpha, w.partials, loss, stream));
+  PDG_TRY(launch_chamfer_loss(w.segs, 1, alpha, stream));
   if (ga) {
-    const double *dw = dir_weight ? dir_weight : w.w_default;
-    PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dw, stream));
+    PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, stream));
     PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
     PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
-    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha, dw,
+    PDG_TRY(launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha,
                                        w.rpart, stream));
   }
   return PDG_OK;
@@ -410,7 +406,6 @@ struct pdg_problem {
   uint4 *packs = nullptr;
   float4 *coords = nullptr, *boxes = nullptr;
   int *fperm = nullptr, *tperm = nullptr;   // Morton order of every frame / of X_0
-  unsigned *maxnorm = nullptr;
   unsigned long long *tiles = nullptr;     // candidate tiles screened (all steps)
   long long pack_rows = 0, box_tiles = 0;
   ChSeg *segs = nullptr;
@@ -601,7 +596,6 @@ void layout(pdg_problem &p, Carve &c) {
     p.packs = c.take<uint4>(2 * p.pack_rows);
     p.coords = c.take<float4>(p.pack_rows);
     p.boxes = c.take<float4>(p.box_tiles);
-    p.maxnorm = c.take<unsigned>((p.nseg + T) * kMaxnormStride);
     p.tiles = c.take<unsigned long long>(1);
   }
   p.fperm = c.take<int>(F * N);
@@ -667,11 +661,16 @@ IsoArgs iso_args(pdg_problem &p) {
 constexpr int kStageLossTerms = 100;
 constexpr int kStageAssemble = 101;
 
+// Parts of a stage that a batch of problems runs as one launch over its
+// merged job tables (see pdg_batch) and a member therefore skips.
+constexpr unsigned kSkipPack = 1u, kSkipNN = 2u, kSkipChamferLoss = 4u;
+constexpr unsigned kSkipMerged = kSkipPack | kSkipNN | kSkipChamferLoss;
+
 // One stage of the step (the stages in order make one iteration).
 // fuse: part of a full step (the preconditioner may apply Adam itself, see
 // run_dct); false for stages enqueued one at a time.
 pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user_terms,
-                         bool fuse) {
+                         bool fuse, unsigned skip = 0u) {
   const GridDev &g = p.g;
   const long long T = p.T, N = p.N, V = p.V, P = p.P;
   const pdg_hyper &h = p.d.hp;
@@ -692,21 +691,19 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
           PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T,
                                     p.tperm, st));
       }
-      if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
-        // screen packs of the moving sets (P^_t, X_t), which change every step
-        PDG_TRY(launch_fill((float *)p.maxnorm, (long long)p.nseg * kMaxnormStride, 0.f, st));
-        PDG_TRY(launch_screen_pack(p.ssets, p.nseg, p.max_n, st));
-      }
+      if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN && !(skip & kSkipPack))
+        PDG_TRY(launch_screen_pack(p.ssets, p.nseg, p.max_n, st));   // the moving sets P^_t, X_t
       return PDG_OK;
     case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
+      if (skip & kSkipNN) return PDG_OK;
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN)   // warm start: last step's assignment
         return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
       return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
     case PDG_STAGE_LOSS:  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
-      PDG_TRY(enqueue_stage(p, kStageLossTerms, st, user_terms, fuse));
-      return enqueue_stage(p, kStageAssemble, st, user_terms, fuse);
+      PDG_TRY(enqueue_stage(p, kStageLossTerms, st, user_terms, fuse, skip));
+      return enqueue_stage(p, kStageAssemble, st, user_terms, fuse, skip);
     case kStageLossTerms:  // the Chamfer terms and the isometry partials
-      PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, p.partials, p.losses, st));
+      if (!(skip & kSkipChamferLoss)) PDG_TRY(launch_chamfer_loss(p.segs, p.nseg, h.alpha, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_edges(iso_args(p), st));
       return PDG_OK;
     case kStageAssemble: {  // cd_max, w_conf, L
@@ -729,12 +726,12 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
       return launch_assemble(aa, st);
     }
     case PDG_STAGE_GRAD:  // dL/dP^, dL/dX (Chamfer adjoint, isometry), reverse sweep of Eq. 8
-      PDG_TRY(launch_chamfer_grad_fwd(p.segs, p.nseg, p.max_n, (float)h.alpha, p.w, st));
+      PDG_TRY(launch_chamfer_grad_fwd(p.segs, p.nseg, p.max_n, (float)h.alpha, st));
       PDG_TRY(launch_chamfer_rev_keys(p.segs, p.nseg, p.max_m, p.b_base, p.rkeys, p.rvals, st));
       PDG_TRY(radix_sort(p.rkeys, p.rvals, p.nrev,
                          bits_for((unsigned long long)(T * N + T * V)), p.sort, st));
       PDG_TRY(launch_chamfer_rev_scatter(p.segs, p.nseg, p.b_base, p.rkeys, p.rvals, p.nrev,
-                                         (float)h.alpha, p.w, p.rpart, st));
+                                         (float)h.alpha, p.rpart, st));
       if (p.has_tm && p.E > 0) PDG_TRY(launch_iso_vertices(iso_args(p), st));
       if (g.ch == 6) {
         // reverse sweep of Eq. 8 one transition at a time: lam_{t-1} = direct
@@ -882,6 +879,141 @@ pdg_status enqueue_step(pdg_problem &p, hipStream_t st, double *user_terms) {
     PDG_TRY(enqueue_stage(p, s, st, user_terms, true));
   if (p.opt_x0) PDG_TRY(enqueue_stage(p, PDG_STAGE_TEMPLATE, st, user_terms, true));
   return PDG_OK;
+}
+
+// -------------------------------------------------------------- batches --
+// One iteration of several problems (served requests) at once.  The screen
+// pack, the nearest-neighbour search and the Chamfer loss of every member run
+// as one launch each over merged device tables (the members' job tables
+// copied one after another into the batch's workspace); every other stage is
+// the member's own, enqueued on one of kBatchLanes branches of the captured
+// graph so that the members' kernels overlap.  A job writes only its own
+// problem's buffers, so a member's results do not depend on the batch.
+constexpr int kBatchLanes = 4;
+
+}  // namespace
+}  // namespace pdg
+
+struct pdg_batch {
+  std::vector<pdg_problem *> members;
+  int mode = 0;
+  double alpha = 0.0;
+  ScreenSet *ssets = nullptr;      // merged moving sets (screen mode)
+  ScreenJob *sjobs = nullptr;      // merged screen jobs
+  NNJob *jobs = nullptr;           // merged exact jobs
+  ChSeg *segs = nullptr;           // merged Chamfer segments
+  int nsets = 0, njobs = 0, nseg = 0, max_n = 0, max_nq = 0;
+  hipStream_t cap = nullptr, lane[kBatchLanes] = {};
+  hipEvent_t fork[2] = {}, join[2][kBatchLanes] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace pdg {
+namespace {
+
+struct BatchTables {
+  ScreenSet *ssets;
+  ScreenJob *sjobs;
+  NNJob *jobs;
+  ChSeg *segs;
+};
+BatchTables batch_layout(Carve &c, int mode, int nsets, int njobs, int nseg) {
+  BatchTables t;
+  memset(&t, 0, sizeof t);
+  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+    t.ssets = c.take<ScreenSet>(nsets);
+    t.sjobs = c.take<ScreenJob>(njobs);
+  } else {
+    t.jobs = c.take<NNJob>(njobs);
+  }
+  t.segs = c.take<ChSeg>(nseg);
+  return t;
+}
+
+pdg_status check_batch(pdg_problem *const *ps, int32_t count) {
+  if (count < 1 || !ps) {
+    set_error("a batch needs at least one problem");
+    return PDG_EINVAL;
+  }
+  for (int i = 0; i < count; ++i) {
+    if (!ps[i]) {
+      set_error("batch member %d is NULL", i);
+      return PDG_EINVAL;
+    }
+    if (ps[i]->joint) {
+      set_error("batch member %d propagates from a keyframe inside its sequence; step it alone", i);
+      return PDG_EUNSUPPORTED;
+    }
+    if (ps[i]->d.chamfer_mode != ps[0]->d.chamfer_mode || ps[i]->d.hp.alpha != ps[0]->d.hp.alpha) {
+      set_error("batch members need one Chamfer mode and one alpha (member %d differs)", i);
+      return PDG_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ps[j] == ps[i]) {
+        set_error("problem %d appears twice in the batch", i);
+        return PDG_EINVAL;
+      }
+  }
+  return PDG_OK;
+}
+
+// Fork: every lane waits for what `main` has enqueued so far.
+pdg_status batch_fork(pdg_batch &b, hipStream_t main, int k) {
+  PDG_TRY_HIP(hipEventRecord(b.fork[k], main));
+  for (int l = 0; l < kBatchLanes; ++l) PDG_TRY_HIP(hipStreamWaitEvent(b.lane[l], b.fork[k], 0));
+  return PDG_OK;
+}
+// Join: `main` waits for every lane.
+pdg_status batch_join(pdg_batch &b, hipStream_t main, int k) {
+  for (int l = 0; l < kBatchLanes; ++l) {
+    PDG_TRY_HIP(hipEventRecord(b.join[k][l], b.lane[l]));
+    PDG_TRY_HIP(hipStreamWaitEvent(main, b.join[k][l], 0));
+  }
+  return PDG_OK;
+}
+
+// One iteration of every member (the members' epochs set beforehand).
+pdg_status enqueue_batch(pdg_batch &b, hipStream_t main) {
+  const int cnt = (int)b.members.size();
+  PDG_TRY(batch_fork(b, main, 0));
+  for (int i = 0; i < cnt; ++i)   // warps (Eq. 1, 8)
+    PDG_TRY(enqueue_stage(*b.members[i], PDG_STAGE_WARP, b.lane[i % kBatchLanes], nullptr, true,
+                          kSkipMerged));
+  PDG_TRY(batch_join(b, main, 0));
+  // every member's packs, nearest neighbours (Eq. 12) and Chamfer terms (Eq. 11, 13)
+  if (b.mode == PDG_CHAMFER_BF16_SCREEN) {
+    PDG_TRY(launch_screen_pack(b.ssets, b.nsets, b.max_n, main));
+    PDG_TRY(launch_nn_screen(b.sjobs, b.njobs, b.max_nq, 1, main));
+  } else {
+    PDG_TRY(launch_nn_exact(b.jobs, b.njobs, b.max_nq, main));
+  }
+  PDG_TRY(launch_chamfer_loss(b.segs, b.nseg, b.alpha, main));
+  PDG_TRY(batch_fork(b, main, 1));
+  for (int i = 0; i < cnt; ++i) {   // the rest of each member's iteration
+    pdg_problem &p = *b.members[i];
+    const hipStream_t st = b.lane[i % kBatchLanes];
+    PDG_TRY(enqueue_stage(p, PDG_STAGE_LOSS, st, nullptr, true, kSkipMerged));
+    for (int s = PDG_STAGE_GRAD; s <= PDG_STAGE_ADAM; ++s)
+      PDG_TRY(enqueue_stage(p, s, st, nullptr, true, kSkipMerged));
+    if (p.opt_x0) PDG_TRY(enqueue_stage(p, PDG_STAGE_TEMPLATE, st, nullptr, true, kSkipMerged));
+  }
+  return batch_join(b, main, 1);
+}
+
+void release_batch(pdg_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int k = 0; k < 2; ++k) {
+    if (b->fork[k]) (void)hipEventDestroy(b->fork[k]);
+    for (int l = 0; l < kBatchLanes; ++l)
+      if (b->join[k][l]) (void)hipEventDestroy(b->join[k][l]);
+  }
+  for (int l = 0; l < kBatchLanes; ++l)
+    if (b->lane[l]) (void)hipStreamDestroy(b->lane[l]);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
 }
 
 // ----------------------------------------------- fixed device scratch --
@@ -1155,14 +1287,15 @@ pdg_status pdg_chamfer_backward(const float *a, int64_t n, const float *b, int64
   seg.nn_a = const_cast<int32_t *>(nn_a);   // read only on this path
   seg.nn_b = const_cast<int32_t *>(nn_b);
   seg.ga = ga;
+  seg.w = dir_weight;
   const unsigned bb = 0;
   PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
   PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
-  PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, dir_weight, stream));
+  PDG_TRY(launch_chamfer_grad_fwd(w.segs, 1, (int)n, (float)alpha, stream));
   PDG_TRY(launch_chamfer_rev_keys(w.segs, 1, (int)m, w.b_base, w.keys, w.vals, stream));
   PDG_TRY(radix_sort(w.keys, w.vals, m, bits_for((unsigned long long)n), w.sort, stream));
   return launch_chamfer_rev_scatter(w.segs, 1, w.b_base, w.keys, w.vals, m, (float)alpha,
-                                    dir_weight, w.rpart, stream);
+                                    w.rpart, stream);
 }
 
 pdg_status pdg_precondition_workspace(const pdg_grid_desc *d, int32_t batch, int32_t method,
@@ -1468,6 +1601,9 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
     memset(&q, 0, sizeof q);
     q.b = pd->points + (t + 1) * 3 * N;
     q.m = (int)N;
+    q.loss = p->losses + 2 * s;
+    q.part = p->partials + 2 * (long long)s * kLossBlocks;
+    q.w = p->w + 2 * s;
     if (!tm) {
       q.a = p->phat + t * 3 * N;
       q.n = (int)N;
@@ -1508,20 +1644,18 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
   std::vector<ScreenJob> sjobs;
   if (p->packs) {
     long long row = 0, tile = 0;
-    auto add_set = [&](const float *x, long long n, const int *perm, unsigned *mx) {
+    auto add_set = [&](const float *x, long long n, const int *perm) {
       ssets.push_back(screen_set(x, n, perm, p->packs + 2 * row, p->coords + row,
-                                 p->boxes + tile, mx));
+                                 p->boxes + tile));
       row += n;
       tile += screen_box_count(n);
     };
     for (int s = 0; s < p->nseg; ++s) {        // moving sets: P^_t keeps P_t's order, X_t X_0's
       const ChSeg &q = segs[s];
-      add_set(q.a, q.n, s < T ? p->fperm + (long long)s * N : p->tperm,
-              p->maxnorm + (long long)s * kMaxnormStride);
+      add_set(q.a, q.n, s < T ? p->fperm + (long long)s * N : p->tperm);
     }
     for (long long t = 0; t < T; ++t)          // fixed frames P_1..P_T
-      add_set(pd->points + (t + 1) * 3 * N, N, p->fperm + (t + 1) * N,
-              p->maxnorm + (p->nseg + t) * kMaxnormStride);
+      add_set(pd->points + (t + 1) * 3 * N, N, p->fperm + (t + 1) * N);
     for (int s = 0; s < p->nseg; ++s) {
       const ChSeg &q = segs[s];
       const ScreenSet &A = ssets[s], &B = ssets[p->nseg + s % T];
@@ -1579,8 +1713,6 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
   }
   if (p->packs) {
     // the fixed frames' packs (their rows, coordinates and boxes never change)
-    if (s == PDG_OK) s = launch_fill((float *)p->maxnorm + (long long)p->nseg * kMaxnormStride,
-                                     T * kMaxnormStride, 0.f, stream);
     if (s == PDG_OK) s = launch_screen_pack(p->ssets + p->nseg, (int)T, (int)N, stream);
     if (s == PDG_OK) s = launch_fill((float *)p->tiles, 2, 0.f, stream);
   }
@@ -1681,16 +1813,119 @@ pdg_status pdg_step_stage(pdg_problem *p, int32_t stage, hipStream_t stream) {
   return enqueue_stage(*p, stage, stream, nullptr, false);
 }
 
-pdg_status pdg_step_batch(pdg_problem *const *ps, int32_t count, const int32_t *epochs,
-                          double *const *loss_terms, int32_t use_graph,
-                          const hipStream_t *streams) {
-  if (count < 0 || (count > 0 && (!ps || !epochs || !streams))) {
-    set_error("invalid batch arguments");
+pdg_status pdg_batch_workspace(pdg_problem *const *ps, int32_t count, size_t *bytes) {
+  PDG_TRY(check_batch(ps, count));
+  PDG_TRY(need(bytes, "bytes"));
+  int nsets = 0, njobs = 0, nseg = 0;
+  for (int i = 0; i < count; ++i) {
+    nsets += ps[i]->nseg;
+    njobs += ps[i]->njobs;
+    nseg += ps[i]->nseg;
+  }
+  Carve c(nullptr);
+  batch_layout(c, ps[0]->d.chamfer_mode, nsets, njobs, nseg);
+  *bytes = c.off;
+  return PDG_OK;
+}
+
+pdg_status pdg_batch_create(pdg_problem *const *ps, int32_t count, void *ws, size_t ws_bytes,
+                            hipStream_t stream, pdg_batch **out) {
+  size_t need_bytes = 0;
+  PDG_TRY(pdg_batch_workspace(ps, count, &need_bytes));
+  PDG_TRY(need(out, "out"));
+  PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
+  pdg_batch *b = new (std::nothrow) pdg_batch;
+  if (!b) {
+    set_error("host allocation failed");
+    return PDG_ENOMEM;
+  }
+  b->members.assign(ps, ps + count);
+  b->mode = ps[0]->d.chamfer_mode;
+  b->alpha = ps[0]->d.hp.alpha;
+  for (int i = 0; i < count; ++i) {
+    b->nsets += ps[i]->nseg;
+    b->njobs += ps[i]->njobs;
+    b->nseg += ps[i]->nseg;
+    b->max_n = ps[i]->max_n > b->max_n ? ps[i]->max_n : b->max_n;
+    b->max_nq = ps[i]->max_nq > b->max_nq ? ps[i]->max_nq : b->max_nq;
+  }
+  Carve c(ws);
+  const BatchTables t = batch_layout(c, b->mode, b->nsets, b->njobs, b->nseg);
+  b->ssets = t.ssets;
+  b->sjobs = t.sjobs;
+  b->jobs = t.jobs;
+  b->segs = t.segs;
+  // the members' tables, one after another (device to device, on `stream`)
+  hipError_t e = hipSuccess;
+  int os = 0, oj = 0;
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
+    const pdg_problem &p = *ps[i];
+    if (b->mode == PDG_CHAMFER_BF16_SCREEN) {
+      e = hipMemcpyAsync(b->ssets + os, p.ssets, p.nseg * sizeof(ScreenSet),
+                         hipMemcpyDeviceToDevice, stream);   // the moving sets come first
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b->sjobs + oj, p.sjobs, p.njobs * sizeof(ScreenJob),
+                           hipMemcpyDeviceToDevice, stream);
+    } else {
+      e = hipMemcpyAsync(b->jobs + oj, p.jobs, p.njobs * sizeof(NNJob), hipMemcpyDeviceToDevice,
+                         stream);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->segs + os, p.segs, p.nseg * sizeof(ChSeg), hipMemcpyDeviceToDevice,
+                         stream);
+    os += p.nseg;
+    oj += p.njobs;
+  }
+  for (int l = 0; l < kBatchLanes && e == hipSuccess; ++l)
+    e = hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&b->fork[k], hipEventDisableTiming);
+    for (int l = 0; l < kBatchLanes && e == hipSuccess; ++l)
+      e = hipEventCreateWithFlags(&b->join[k][l], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    release_batch(b);
+    return hip_fail(e, "pdg_batch_create");
+  }
+  *out = b;
+  return PDG_OK;
+}
+
+pdg_status pdg_batch_step(pdg_batch *b, const int32_t *epochs, int32_t use_graph,
+                          hipStream_t stream) {
+  if (!b || !epochs) {
+    set_error("batch or epochs is NULL");
     return PDG_EINVAL;
   }
-  for (int i = 0; i < count; ++i)
-    PDG_TRY(pdg_step(ps[i], epochs[i], loss_terms ? loss_terms[i] : nullptr, use_graph,
-                     streams[i]));
+  const int cnt = (int)b->members.size();
+  for (int i = 0; i < cnt; ++i)
+    if (epochs[i] < 0 || epochs[i] > b->members[i]->d.hp.e_max) {
+      set_error("epoch %d of member %d outside [0, e_max = %d]", epochs[i], i,
+                b->members[i]->d.hp.e_max);
+      return PDG_EINVAL;
+    }
+  for (int i = 0; i < cnt; ++i) PDG_TRY(launch_set_int(b->members[i]->epoch, epochs[i], stream));
+  if (!use_graph) return enqueue_batch(*b, stream);
+  if (!b->exec) {
+    if (!b->cap) PDG_TRY_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    PDG_TRY_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    pdg_status s = enqueue_batch(*b, b->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap, &graph);
+    if (s != PDG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture (batch)");
+    b->graph = graph;
+    PDG_TRY_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  PDG_TRY_HIP(hipGraphLaunch(b->exec, stream));
+  return PDG_OK;
+}
+
+pdg_status pdg_batch_destroy(pdg_batch *b) {
+  release_batch(b);
   return PDG_OK;
 }
 

@@ -101,8 +101,7 @@ __device__ __forceinline__ double block_sum_f64(double v, double *sh) {
 // The kLossBlocks workgroups of one (segment, direction) job run on one XCD
 // (job_block), so its L2 holds the job's candidate set once.
 __global__ __launch_bounds__(256) void chamfer_loss_kernel(const ChSeg *__restrict__ segs,
-                                                           int njobs, double alpha,
-                                                           double *__restrict__ partials) {
+                                                           int njobs, double alpha) {
   __shared__ double sh[4];
   unsigned job, blk;
   if (!job_block(blockIdx.x, (unsigned)njobs, kLossBlocks, job, blk)) return;
@@ -124,25 +123,22 @@ __global__ __launch_bounds__(256) void chamfer_loss_kernel(const ChSeg *__restri
     acc += exp(-alpha * s) * s;
   }
   double t = block_sum_f64(acc, sh);
-  if (threadIdx.x == 0)
-    partials[((long long)seg * 2 + dir) * kLossBlocks + blk] = t;
+  if (threadIdx.x == 0) S.part[dir * kLossBlocks + blk] = t;
 }
 
-__global__ void chamfer_loss_final_kernel(const ChSeg *__restrict__ segs, int nseg,
-                                          const double *__restrict__ partials,
-                                          double *__restrict__ losses) {
+__global__ void chamfer_loss_final_kernel(const ChSeg *__restrict__ segs, int nseg) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 2 * nseg) return;
-  double t = 0.0;
-  for (int b = 0; b < kLossBlocks; ++b) t += partials[(long long)k * kLossBlocks + b];
   const ChSeg S = segs[k >> 1];
-  losses[k] = t / (double)((k & 1) ? S.m : S.n);
+  const int dir = k & 1;
+  double t = 0.0;
+  for (int b = 0; b < kLossBlocks; ++b) t += S.part[dir * kLossBlocks + b];
+  S.loss[dir] = t / (double)(dir ? S.m : S.n);
 }
 
 // One segment's nb workgroups on one XCD, as for the loss.
 __global__ __launch_bounds__(256) void chamfer_grad_fwd_kernel(const ChSeg *__restrict__ segs,
-                                                               int nseg, unsigned nb, float alpha,
-                                                               const double *__restrict__ w) {
+                                                               int nseg, unsigned nb, float alpha) {
   unsigned job, blk;
   if (!job_block(blockIdx.x, (unsigned)nseg, nb, job, blk)) return;
   const int seg = (int)job;
@@ -158,7 +154,7 @@ __global__ __launch_bounds__(256) void chamfer_grad_fwd_kernel(const ChSeg *__re
   const float dy = Sa[n + i] - Sb[m + j];
   const float dz = Sa[2 * n + i] - Sb[2 * m + j];
   const float s = dx * dx + dy * dy + dz * dz;
-  const float coef = (float)(w[2 * seg] / (double)S.n) * expf(-alpha * s) * (1.0f - alpha * s) * 2.0f;
+  const float coef = (float)(S.w[0] / (double)S.n) * expf(-alpha * s) * (1.0f - alpha * s) * 2.0f;
   Sga[i] = coef * dx;
   Sga[n + i] = coef * dy;
   Sga[2 * n + i] = coef * dz;
@@ -203,8 +199,7 @@ constexpr int kRevThreads = 256;
 __global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
     const ChSeg *__restrict__ segs, int nseg, const unsigned *__restrict__ b_base,
     const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, long long nent,
-    float alpha, const double *__restrict__ w, float4 *__restrict__ head,
-    float4 *__restrict__ tail) {
+    float alpha, float4 *__restrict__ head, float4 *__restrict__ tail) {
   __shared__ uint32_t skey[kRevThreads + 1];
   __shared__ float wtail[kRevThreads / 64][3];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -226,7 +221,7 @@ __global__ __launch_bounds__(kRevThreads) void chamfer_rev_scatter_kernel(
       const long long n = S.n, m = S.m;
       const int ai = (int)(key - S.a_base);
       const int j = (int)(g0 - b_base[sg]);
-      const float cw = (float)(w[2 * sg + 1] / (double)S.m);
+      const float cw = (float)(S.w[1] / (double)S.m);
       const float dx = Sa[ai] - Sb[j];
       const float dy = Sa[n + ai] - Sb[m + j];
       const float dz = Sa[2 * n + ai] - Sb[2 * m + j];
@@ -330,22 +325,20 @@ pdg_status launch_nn_exact(const NNJob *jobs, int njobs, int max_nq, hipStream_t
   return launched("nn_exact");
 }
 
-pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double *partials,
-                               double *losses, hipStream_t st) {
+pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, hipStream_t st) {
   if (nseg <= 0) return PDG_OK;
   const int njobs = 2 * nseg;
-  chamfer_loss_kernel<<<(unsigned)job_grid(njobs, kLossBlocks), 256, 0, st>>>(segs, njobs, alpha,
-                                                                              partials);
+  chamfer_loss_kernel<<<(unsigned)job_grid(njobs, kLossBlocks), 256, 0, st>>>(segs, njobs, alpha);
   PDG_TRY(launched("chamfer_loss"));
-  chamfer_loss_final_kernel<<<div_up(2 * nseg, 64), 64, 0, st>>>(segs, nseg, partials, losses);
+  chamfer_loss_final_kernel<<<div_up(2 * nseg, 64), 64, 0, st>>>(segs, nseg);
   return launched("chamfer_loss_final");
 }
 
 pdg_status launch_chamfer_grad_fwd(const ChSeg *segs, int nseg, int max_n, float alpha,
-                                   const double *w, hipStream_t st) {
+                                   hipStream_t st) {
   if (nseg <= 0 || max_n <= 0) return PDG_OK;
   const unsigned nb = div_up(max_n, 256);
-  chamfer_grad_fwd_kernel<<<(unsigned)job_grid(nseg, nb), 256, 0, st>>>(segs, nseg, nb, alpha, w);
+  chamfer_grad_fwd_kernel<<<(unsigned)job_grid(nseg, nb), 256, 0, st>>>(segs, nseg, nb, alpha);
   return launched("chamfer_grad_fwd");
 }
 
@@ -361,7 +354,7 @@ long long rev_part_count(long long nent) { return (nent + kRevThreads - 1) / kRe
 
 pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigned *b_base,
                                       const uint32_t *keys, const uint32_t *vals, long long nent,
-                                      float alpha, const double *w, float4 *part, hipStream_t st) {
+                                      float alpha, float4 *part, hipStream_t st) {
   if (nent <= 0) return PDG_OK;
   const long long nb = rev_part_count(nent);
   if (nb >= (1ll << 31)) {
@@ -369,7 +362,7 @@ pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigne
     return PDG_EINVAL;
   }
   chamfer_rev_scatter_kernel<<<xcd_pad(nb), kRevThreads, 0, st>>>(segs, nseg, b_base, keys, vals,
-                                                                  nent, alpha, w, part, part + nb);
+                                                                  nent, alpha, part, part + nb);
   PDG_TRY(launched("chamfer_rev_scatter"));
   rev_join_kernel<<<div_up(nb, 256), 256, 0, st>>>(segs, nseg, b_base, keys, vals, nent, (int)nb,
                                                    part, part + nb);

@@ -262,6 +262,9 @@ struct ChSeg {               // one (moving A, fixed B) Chamfer pair
   float *ga;                 // SoA [3][n] gradient wrt a (nullable)
   unsigned a_base;           // global index of a_0 for the reverse scatter
   int pad;
+  double *loss;              // [2] out: the two directional means
+  double *part;              // [2][kLossBlocks] partial sums of those means
+  const double *w;           // [2] gradient weights of the two directions
 };
 struct NNJob {               // one directed nearest-neighbour search
   const float *q; const float *c;
@@ -282,7 +285,6 @@ struct ScreenSet {           // one point set packed as screen candidates and qu
   float4 *coords;            // [n] (x, y, z, original index as int bits), packed order
   float4 *boxes;             // [ceil(n/256)][3] per 256-point tile: min corner, max corner,
                              // (centre C, radius): the frame the tile's rows are packed in
-  unsigned *maxnorm;         // float bits of max |x| (zeroed before packing; sets kMaxnormStride apart)
 };
 struct ScreenJob {           // one directed search: packed queries over packed candidates
   const float *c;            // candidates SoA [3][nc], original order (warm start)
@@ -293,13 +295,9 @@ struct ScreenJob {           // one directed search: packed queries over packed 
   const uint4 *pack;         // candidate rows, packed order
   const float4 *cc;          // candidate coords, packed order
   const float4 *cboxes;      // candidate tile boxes
-  const unsigned *maxnorm;   // of the candidates
   unsigned long long *tiles; // nullable: += 32x32x16 bf16 products issued
 };
 inline long long screen_tiles(long long n) { return (n + 255) / 256; }
-// per-set max-norm words sit this many words apart (one 128-byte line each),
-// so the packing atomics of different sets do not meet on one cache line
-constexpr int kMaxnormStride = 32;
 // float4 entries of a set's box array (min corner, max corner, centre and
 // radius per tile)
 inline long long screen_box_count(long long n) { return 3 * screen_tiles(n); }
@@ -311,12 +309,13 @@ pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int wa
                             hipStream_t st);
 constexpr int kLossBlocks = 32;  // fixed partial count per (segment, direction)
 constexpr int kIsoBlocks = 1024; // fixed partial count of the isometry loss
-// partials[(seg*2+dir)*kLossBlocks + blk]; then losses[seg*2+dir] = mean.
-pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, double *partials,
-                               double *losses, hipStream_t st);
-// ga <- forward-direction gradient (overwrite), weights w[seg*2 + dir].
+// each segment's part[dir*kLossBlocks + blk]; then its loss[dir] = mean.
+// Segments may belong to different problems: each writes through its own
+// pointers only.
+pdg_status launch_chamfer_loss(const ChSeg *segs, int nseg, double alpha, hipStream_t st);
+// ga <- forward-direction gradient (overwrite), with each segment's weight w[0].
 pdg_status launch_chamfer_grad_fwd(const ChSeg *segs, int nseg, int max_n, float alpha,
-                                   const double *w, hipStream_t st);
+                                   hipStream_t st);
 // Reverse-direction keys: for b_j of segment seg the key is a_base + nn_b[j],
 // value = global b index (seg base + j).  b_base[seg] = first global b index.
 pdg_status launch_chamfer_rev_keys(const ChSeg *segs, int nseg, int max_m,
@@ -327,7 +326,7 @@ pdg_status launch_chamfer_rev_keys(const ChSeg *segs, int nseg, int max_m,
 long long rev_part_count(long long nent);
 pdg_status launch_chamfer_rev_scatter(const ChSeg *segs, int nseg, const unsigned *b_base,
                                       const uint32_t *keys, const uint32_t *vals, long long nent,
-                                      float alpha, const double *w, float4 *part, hipStream_t st);
+                                      float alpha, float4 *part, hipStream_t st);
 
 // precond.hip
 struct CGLevel {             // one level of every stack in a preconditioner call

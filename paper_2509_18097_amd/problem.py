@@ -229,6 +229,46 @@ class Problem:
             pass
 
 
+class Batch:
+    """Several problems iterated together (see pdg_batch): their screen packs,
+    nearest-neighbour searches and Chamfer terms as one launch each over a
+    device table of all their jobs, the rest of each member's iteration on
+    parallel branches of one graph.  The members stay owned by the caller and
+    must outlive the batch."""
+
+    def __init__(self, problems, stream: torch.cuda.Stream | None = None):
+        self.members = list(problems)
+        n = len(self.members)
+        self._ptrs = (ctypes.c_void_p * n)(*[p._h for p in self.members])
+        nb = ctypes.c_size_t()
+        L.check(L.lib().pdg_batch_workspace(self._ptrs, n, ctypes.byref(nb)),
+                "pdg_batch_workspace")
+        self.workspace = L._ws(nb.value, self.members[0].points.device)
+        st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+        h = ctypes.c_void_p()
+        L.check(L.lib().pdg_batch_create(self._ptrs, n, L._ptr(self.workspace), nb.value, st,
+                                         ctypes.byref(h)), "pdg_batch_create")
+        self._h = h
+
+    def step(self, epochs, use_graph: bool = True, stream: torch.cuda.Stream | None = None):
+        """One iteration of every member; epochs in member order."""
+        n = len(self.members)
+        ep = (ctypes.c_int32 * n)(*[int(e) for e in epochs])
+        st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+        L.check(L.lib().pdg_batch_step(self._h, ep, int(bool(use_graph)), st), "pdg_batch_step")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().pdg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Chain:
     """One chain of a problem (its buffers; the frames in chain order)."""
 

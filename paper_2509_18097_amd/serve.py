@@ -11,9 +11,11 @@ iterations.  The server
 * keeps every admitted request's grids, Adam moments, frames and workspace
   resident until it finishes;
 * runs rounds: every round enqueues one iteration of every active request,
-  each a replay of that request's captured HIP graph on one of several HIP
-  streams, so the iterations of different requests overlap on the device; at
-  most two rounds are in flight;
+  either as one batched iteration of all of them (``BatchExecutor``: their
+  nearest-neighbour searches and Chamfer terms as single launches over a
+  device table of all their jobs, the rest overlapping on graph branches) or
+  as replays of each request's own captured graph on several HIP streams
+  (``GpuExecutor``); at most two rounds are in flight;
 * frees a finished request and admits waiting ones between rounds, so a
   request that arrives while others run joins as soon as memory and a slot
   free up (continuous batching, not a queue in front of a single runner);
@@ -72,6 +74,7 @@ class RequestResult:
     bytes: int
     terms: dict = field(default_factory=dict)
     params: np.ndarray | None = None
+    problem: object = None         # the request's Problem, when the executor keeps it
 
     @property
     def latency(self) -> float:
@@ -111,13 +114,14 @@ class GpuExecutor:
     """Runs requests on the current HIP device through ``Problem``."""
 
     def __init__(self, chamfer_mode: str = "bf16", precond: str = "cg", streams: int = 4,
-                 keep_params: bool = False):
+                 keep_params: bool = False, keep_problems: bool = False):
         import torch
         self.torch = torch
         self.chamfer_mode = chamfer_mode
         self.precond = precond
         self.streams = [torch.cuda.Stream() for _ in range(max(1, streams))]
         self.keep_params = keep_params
+        self.keep_problems = keep_problems   # finished requests' state stays for inspection
         self._next = 0
         self.t0 = None
 
@@ -176,8 +180,9 @@ class GpuExecutor:
         h["done"].synchronize()
 
     def finish(self, h):
-        """Returns (completion time in run seconds, terms, params or None) and
-        releases the request's device memory."""
+        """Returns (completion time in run seconds, terms, params or None,
+        the Problem or None) and releases the request's device memory unless
+        problems are kept."""
         ev = h["done"]
         ev.synchronize()
         t_done = self.t0_event.elapsed_time(ev) / 1000.0
@@ -185,9 +190,50 @@ class GpuExecutor:
         with self.torch.cuda.stream(h["stream"]):
             terms = prob.terms()
             params = prob.params.cpu().numpy() if self.keep_params else None
-        prob.close()
+        kept = prob if self.keep_problems else None
+        if kept is None:
+            prob.close()
         h["prob"] = None
-        return t_done, terms, params
+        return t_done, terms, params, kept
+
+
+class BatchExecutor(GpuExecutor):
+    """Runs every round as one batched iteration (``Batch``) of all runnable
+    requests on one stream: their screen packs, nearest-neighbour searches and
+    Chamfer terms are one launch each over a device table of all their jobs,
+    the rest of each request's iteration overlaps on parallel graph branches.
+    The batch (table and graph) is rebuilt only when the set of runnable
+    requests changes; a replaced batch is released once its last round has
+    finished on the device."""
+
+    def __init__(self, chamfer_mode: str = "bf16", precond: str = "dct",
+                 keep_params: bool = False, keep_problems: bool = False):
+        super().__init__(chamfer_mode=chamfer_mode, precond=precond, streams=1,
+                         keep_params=keep_params, keep_problems=keep_problems)
+        self._batch = None
+        self._key = None
+        self._last = None
+        self._retired = deque()      # (batch, event of its last round)
+        self.batches_built = 0
+
+    def step_round(self, handles, epochs):
+        from .problem import Batch
+        key = tuple(id(h["prob"]) for h in handles)
+        st = self.streams[0]
+        if key != self._key:
+            if self._batch is not None:
+                self._retired.append((self._batch, self._last))
+            self._batch = Batch([h["prob"] for h in handles], stream=st)
+            self._key = key
+            self.batches_built += 1
+        self._batch.step(epochs, use_graph=True, stream=st)
+        self._last = self.mark(handles[0])
+        while self._retired and self._retired[0][1].query():
+            self._retired.popleft()[0].close()
+        return [self._last]
+
+    def mark_round_done(self, h):
+        h["done"] = self._last
 
 
 class Server:
@@ -224,12 +270,12 @@ class Server:
             still = []
             for a in active:
                 if a["iter"] >= a["req"].iterations and self.ex.is_done(a["handle"]):
-                    t_done, terms, params = self.ex.finish(a["handle"])
+                    t_done, terms, params, kept = self.ex.finish(a["handle"])
                     used -= a["bytes"]
                     results.append(RequestResult(
                         rid=a["req"].rid, arrival=a["req"].arrival, admitted=a["admitted"],
                         finished=max(t_done, a["admitted"]), iterations=a["req"].iterations,
-                        bytes=a["bytes"], terms=terms, params=params))
+                        bytes=a["bytes"], terms=terms, params=params, problem=kept))
                 else:
                     still.append(a)
             active = still
@@ -253,12 +299,20 @@ class Server:
                 continue
             # one round: one iteration of every runnable request
             marks = []
-            for a in runnable:
-                self.ex.step(a["handle"], a["iter"])
-                a["iter"] += 1
-                if a["iter"] == a["req"].iterations:
-                    self.ex.mark_done(a["handle"])
-                marks.append(self.ex.mark(a["handle"]))
+            if hasattr(self.ex, "step_round"):     # the executor batches the round itself
+                marks += self.ex.step_round([a["handle"] for a in runnable],
+                                            [a["iter"] for a in runnable])
+                for a in runnable:
+                    a["iter"] += 1
+                    if a["iter"] == a["req"].iterations:
+                        self.ex.mark_round_done(a["handle"])
+            else:
+                for a in runnable:
+                    self.ex.step(a["handle"], a["iter"])
+                    a["iter"] += 1
+                    if a["iter"] == a["req"].iterations:
+                        self.ex.mark_done(a["handle"])
+                    marks.append(self.ex.mark(a["handle"]))
             inflight.append(marks)
             rounds += 1
             while len(inflight) >= self.max_inflight:

@@ -57,7 +57,7 @@ class FakeExecutor:
         self.t = max(self.t, h["done"])
 
     def finish(self, h):
-        return h["done"], {"loss": float(h["req"].rid)}, None
+        return h["done"], {"loss": float(h["req"].rid)}, None, None
 
 
 def _req(rid, arrival, n, iters=5):
