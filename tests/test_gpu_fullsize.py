@@ -68,6 +68,21 @@ def test_nearest_neighbours_sampled(run):
             assert np.array_equal(o["nn"][key][t][idx], C.nn_fp32(q[:, idx], c, workers=8)), (t, key)
 
 
+def test_nearest_neighbours_whole_transition(run):
+    """Every index of one whole transition, all four directions (50,000 and
+    40,962 queries against 50,000 or 40,962 candidates), against the oracle's
+    float32-contract brute force: bit for bit."""
+    seq, _, _, _, o = run
+    t = 17
+    tgt = seq.points[t + 1]
+    for q, c, key in ((o["phat"][t], tgt, "pt_ab"), (tgt, o["phat"][t], "pt_ba"),
+                      (o["xhat"][t + 1], tgt, "tm_ab"), (tgt, o["xhat"][t + 1], "tm_ba")):
+        print(f"whole transition {t}: {key} ({q.shape[1]} queries)", flush=True)
+        ref = C.nn_fp32(q, c, chunk=512, workers=16)
+        mism = np.flatnonzero(o["nn"][key][t] != ref)
+        assert mism.size == 0, (key, mism[:10])
+
+
 def test_losses_confidence_and_terms(run):
     seq, _, _, _, o = run
     T = 31

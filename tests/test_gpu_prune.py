@@ -190,3 +190,48 @@ def test_headline_precondition_residual(headline):
             gk = g[sl].astype(np.float64)[keep]
             assert np.linalg.norm(back - gk) <= 1e-4 * np.linalg.norm(gk), f"R={r} c={c}"
         off += 3 * r ** 3
+
+
+def test_step_pruned_with_empty_tiles():
+    """A compact point set in a box of levels up to 64^3, so that most
+    2048-cell conjugate-gradient tiles hold no kept cell: the step's launches
+    cover only the kept tiles (the list built at creation), with the tile skip,
+    the reductions of spans without a kept tile and the partial-sum zeroing
+    all exercised.  The preconditioned gradient against the oracle (Eq. 3 on
+    the kept cells' graph) and bitwise against pdg_precondition_pruned, which
+    launches every tile."""
+    require_gpu()
+    res = (4, 16, 32, 64)
+    seq = synth.deforming_sequence(seed=11, frames=3, n=800, subdiv=1)
+    shift = np.array([0.35, -0.3, 0.2], np.float32)[None, :, None]
+    pts = (0.18 * seq.points + shift).astype(np.float32)
+    tmpl = (0.18 * seq.template + shift[0]).astype(np.float32)
+    T = 2
+    theta0 = np.random.default_rng(12).normal(0, 0.01, (T, L.grid_size(res))).astype(np.float32)
+    prob = Problem(dev(pts), res, template=dev(tmpl), edges=dev(seq.edges),
+                   hp=HyperParams(e_max=10), params=dev(theta0), precond="cg", prune_halo=1)
+    masks = PR.stack_masks(pts, res, halo=1, span=2)
+    keep = np.stack([PR.packed_mask(masks[t], res) for t in range(T)])
+    # most tiles of the 32^3 and 64^3 levels hold no kept cell
+    off = 3 * (4 ** 3 + 16 ** 3)
+    for r in (32, 64):
+        cells = keep[0, off:off + r ** 3]
+        tiles = cells.reshape(-1, 2048).any(axis=1)
+        assert tiles.sum() < 0.5 * tiles.size, (r, tiles.sum(), tiles.size)
+        off += 3 * r ** 3
+    theta_p = np.where(keep, theta0, 0.0).astype(np.float32)
+    prob.step(0)
+    torch.cuda.synchronize()
+    phat, xhat = host(prob.buffer("phat")), host(prob.buffer("xhat"))
+    grad, pgrad = host(prob.buffer("grad")), host(prob.buffer("pgrad"))
+    z = np.zeros_like(theta_p, dtype=np.float64)
+    r = S.step(pts, tmpl, seq.edges, res, theta_p, z, z, 0, S.Hyper(e_max=10),
+               phat32=phat, xhat32=xhat, grad_override=grad, pgrad_override=pgrad, masks=masks)
+    assert_rel(grad, r.grad, 1e-5, "dL/dG")
+    assert_rel(pgrad, r.pgrad, 1e-5, "pruned preconditioned (kept tiles only)")
+    assert np.all(pgrad[~keep] == 0.0)
+    lams = [0.25 * 1.5 ** l for l in range(len(res))]
+    full = host(L.precondition_pruned(dev(grad), res, lams, prob.prune_mask, batch=T))
+    np.testing.assert_array_equal(pgrad, full)
+    theta = host(prob.params)
+    assert np.max(np.abs(theta - r.theta)) <= 1e-5 * max(S.Hyper().schedule(len(res))[0])

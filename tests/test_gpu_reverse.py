@@ -101,9 +101,30 @@ def test_two_way_pruned_masks_in_chain_order():
             off += -(-r ** 3 // 32) * 32
         w = (bits.reshape(-1, 32).astype(np.uint64) << np.arange(32, dtype=np.uint64)).sum(1)
         np.testing.assert_array_equal(got[i].view(np.uint32), w.astype(np.uint32))
+    # each chain's step against the oracle's on the kept cells' graphs
+    order = [2, 1, 0, 3]
+    keep = np.stack([PR.packed_mask(ref[j], RES) for j in order])
+    theta_p = np.where(keep, theta0, 0.0).astype(np.float32)
+    np.testing.assert_array_equal(host(prob.params), theta_p)
     prob.step(0)
     torch.cuda.synchronize()
-    assert np.isfinite(prob.terms()["loss"])
+    chains = [prob.branch(0), prob.branch(1)]
+    ov = [dict(phat32=host(ch.buffer("phat")), xhat32=host(ch.buffer("xhat")),
+               grad_override=host(ch.buffer("grad")), pgrad_override=host(ch.buffer("pgrad")),
+               masks=[ref[j] for j in js])
+          for ch, js in zip(chains, ([2, 1, 0], [3]))]
+    z = np.zeros_like(theta_p, dtype=np.float64)
+    r = S.step_keyframe(seq.points, seq.template, seq.edges, RES, theta_p, z, z, 0, 3,
+                        S.Hyper(e_max=10), overrides=ov, workers=4)
+    for c, ch in enumerate(chains):
+        rb = r.branches[c]
+        assert_rel(host(ch.buffer("grad")), rb.grad, 1e-5, f"chain {c} dL/dG")
+        assert_rel(host(ch.buffer("pgrad")), rb.pgrad, 1e-5, f"chain {c} pruned preconditioned")
+    assert abs(prob.terms()["loss"] - r.loss) <= 1e-10 * abs(r.loss)
+    eta_max = max(S.Hyper().schedule(len(RES))[0])
+    params = host(prob.params)
+    assert np.max(np.abs(params - r.theta)) <= 1e-5 * eta_max
+    assert np.all(params[~keep] == 0.0)
 
 
 def test_joint_handle_buffers():
