@@ -42,12 +42,12 @@ FP32_VALU_PEAK_TFLOPS = 157.3     # vector FP32, an FMA counted as two flops
 PAIR_OPS = 8          # 3 sub + 3 mul + 2 add per pair under the difference-form contract
 PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # HBM bytes per launch from two rocprofv3 PMC runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0,
-# factors from a 1 GiB copy; mean over the 8 timed steps), recorded in
+# factors from a 1 GiB copy; mean over the last 8 of 11 launches), recorded in
 # profiles/nn_screen_c2_bf16_dct.md for the kernel source whose SHA-256 starts
 # with the given prefix; reported only while the source is unchanged.
 PMC_TRAFFIC = {
-    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "d9e5dd1b3e2cb628",
-                         (2 * 260141.0234375 + 104816.5546875) * 1024),
+    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "c35e7c6b30f8c14f",
+                         (2 * 236720.49 + 119336.50) * 1024),
 }
 
 

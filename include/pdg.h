@@ -453,7 +453,8 @@ pdg_status pdg_batch_destroy(pdg_batch *b);
  *   PDG_BUF_LAM    float [T][3][V]   total dL/dX_t after the reverse sweep of Eq. 8
  *   PDG_BUF_SCREEN_TILES uint64[1]   matrix-core products the bf16 screen
  *                  issued (each one 32 x 32 x 16 bf16 MFMA: 1,024 candidate-query
- *                  pairs), summed over every step since creation (0 bytes for
+ *                  pairs; a product recomputed for the exact re-rank counts
+ *                  again), summed over every step since creation (0 bytes for
  *                  the float32 mode)
  * When X_0 is optimised (0 bytes otherwise), from the last TEMPLATE stage:
  *   PDG_BUF_NN0    int32 [V + n]     nn of X_0 in P_0, then nn of P_0 in X_0

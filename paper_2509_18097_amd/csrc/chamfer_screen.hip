@@ -85,8 +85,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kWaves = PDG_SCREEN_WAVES;   // independent waves per workgroup
 constexpr int kThreads = 64 * kWaves;
 constexpr bool kStage = PDG_SCREEN_STAGE;  // tile coordinates staged in LDS for the re-rank
-constexpr int kQB = PDG_SCREEN_QB;  // 32-query blocks per wave (even)
-static_assert(kQB % 2 == 0, "query blocks are screened in pairs");
+constexpr int kQB = PDG_SCREEN_QB;  // 32-query blocks per wave
+static_assert(kQB * 8 <= 32, "one flag bit per (step, query block) of a tile");
 constexpr int kQPerWave = 32 * kQB;
 constexpr int kQPerBlock = kWaves * kQPerWave;
 constexpr int kCTile = PDG_SCREEN_TILE;   // candidates per LDS tile
@@ -526,25 +526,58 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
 #pragma unroll
         for (int h = 0; h < kQB; ++h) enter_tile(st[h], cen, half, bq[h]);
         __builtin_amdgcn_wave_barrier();   // the coordinates are written before any re-rank
+        // The screen proper has no branch: each lane only notes which
+        // (step, query block) products hold a row inside its threshold, and
+        // the steps noted anywhere in the wave are recomputed and re-ranked
+        // after the tile.  Thresholds only tighten, so a product not noted
+        // cannot hold a better neighbour or a tie later, and a noted one is
+        // re-ranked against the tighter threshold.
+        const f32x16 z = {};
+        unsigned flags = 0;   // bit kQB * step + block
+        constexpr int kProducts = kQB * kCTile / 32;
+        if (full) {
+          // software-pipelined: product i + 1 is issued before product i is
+          // reduced, so the matrix core and the vector ALU overlap
+          f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              *reinterpret_cast<const bf16x8 *>(&fr[0]), bq[0], z, 0, 0, 0);
 #pragma unroll
-        for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
-          if (sidx < nsub) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&fr[sidx]);
-            const f32x16 z = {};
+          for (int i = 0; i < kProducts; ++i) {
+            f32x16 vn = z;
+            if (i + 1 < kProducts)
+              vn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  *reinterpret_cast<const bf16x8 *>(&fr[(i + 1) / kQB]), bq[(i + 1) % kQB], z, 0,
+                  0, 0);
+            flags |= (min16(v) <= st[i % kQB].thr ? 1u : 0u) << i;
+            v = vn;
+          }
+        } else {
 #pragma unroll
-            for (int hp = 0; hp < kQB; hp += 2) {
-              // two query blocks' products before either is reduced
-              const f32x16 v0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[hp], z, 0, 0, 0);
-              const f32x16 v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[hp + 1], z, 0, 0, 0);
-              const float m0 = min16(v0), m1 = min16(v1);
-              const bool p0 = m0 <= st[hp].thr, p1 = m1 <= st[hp + 1].thr;
-              if (p0 || p1) {   // rare: rows inside the error window
-                if (kStage) {
-                  if (p0) rerank(st[hp], v0, lane, sidx * 32, nleft, tc);
-                  if (p1) rerank(st[hp + 1], v1, lane, sidx * 32, nleft, tc);
-                } else {
-                  if (p0) rerank(st[hp], v0, lane, sidx * 32, nleft, tg);
-                  if (p1) rerank(st[hp + 1], v1, lane, sidx * 32, nleft, tg);
+          for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
+            if (sidx < nsub) {
+              const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&fr[sidx]);
+#pragma unroll
+              for (int h = 0; h < kQB; ++h) {
+                const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
+                flags |= (min16(v) <= st[h].thr ? 1u : 0u) << (kQB * sidx + h);
+              }
+            }
+          }
+        }
+        if (__ballot(flags != 0u)) {   // rare: rows inside the error window
+#pragma unroll
+          for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
+            const unsigned fs = (flags >> (kQB * sidx)) & ((1u << kQB) - 1u);
+            if (sidx < nsub && __ballot(fs != 0u)) {
+              const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&fr[sidx]);
+#pragma unroll
+              for (int h = 0; h < kQB; ++h) {
+                if (__ballot((fs >> h) & 1u)) {
+                  ++issued;   // the recomputed product is issued work too
+                  const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
+                  if (kStage)
+                    rerank(st[h], v, lane, sidx * 32, nleft, tc);
+                  else
+                    rerank(st[h], v, lane, sidx * 32, nleft, tg);
                 }
               }
             }
