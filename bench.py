@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--subdiv", type=int, default=6, choices=(4, 6),
                     help="template icosphere subdivisions (6: 40,962 vertices, 4: 2,562)")
-    ap.add_argument("--chamfer", default="bf16", choices=("fp32", "bf16"),
+    ap.add_argument("--chamfer", default="bf16", choices=("fp32", "bf16", "fp32cull"),
                     help="bf16: matrix-core screen + exact re-rank (same indices as fp32)")
     ap.add_argument("--precond", default="dct", choices=("cg", "dct"),
                     help="dct: exact spectral solve; cg: conjugate gradients, float64 dots")
@@ -82,7 +82,7 @@ def parse():
                     help="the timed step on the paper's grid: six-channel cells, R = 2l - 1, L = 10")
     ap.add_argument("--keyframe", type=int, default=0,
                     help="X_0 at this frame, propagated both ways (Sec. 3.3); 0: forward only")
-    ap.add_argument("--variants", default="fp32:cg,bf16:cg,fp32:dct",
+    ap.add_argument("--variants", default="fp32:cg,bf16:cg,fp32:dct,fp32cull:dct",
                     help="other chamfer:precond forms to time on the same GPU ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true", help="skip the per-stage timing")
@@ -169,7 +169,8 @@ def time_stages(prob, reps=3):
         for k, name in enumerate(names):
             out[name] += ev[k].elapsed_time(ev[k + 1]) / reps
     if t0 is not None:
-        out["nn_mfma"] = (screen_tiles(prob) - t0) / reps
+        key = "nn_mfma" if prob.chamfer_mode == "bf16" else "nn_pair_units"
+        out[key] = (screen_tiles(prob) - t0) / reps
     alone = ("precond", "adam")
     out.update({name: 0.0 for name in alone})
     for _ in range(reps):
@@ -186,8 +187,9 @@ def time_stages(prob, reps=3):
 
 def screen_tiles(prob):
     """Matrix-core products (32 x 32 x 16 bf16 MFMAs) the screen has issued so
-    far (bf16 mode), else None."""
-    if prob.chamfer_mode != "bf16":
+    far (bf16 mode), or the 1,024-pair units of distances the culled float32
+    search has evaluated (fp32cull mode), else None."""
+    if prob.chamfer_mode not in ("bf16", "fp32cull"):
         return None
     if prob.keyframe > 0:
         return sum(int(ch.buffer("screen_tiles").item())
@@ -254,6 +256,16 @@ def roofline(prob, stages, chamfer, precond):
               "pairs_screened_per_launch": int(screened),
               "brute_force_pairs_per_launch": pairs,
               "screened_fraction": round(screened / pairs, 4), "launch_ms": round(nn_ms, 4)}
+    elif chamfer == "fp32cull":
+        # the distances actually evaluated after the box cull, each at the
+        # exact pair's cost
+        ev = stages["nn_pair_units"] * 1024
+        a = ev * PAIR_OPS / (nn_ms * 1e-3) / 1e12
+        nn = {"bound": "alu", "achieved": round(a, 2), "peak": round(VALU_PEAK_TOPS, 2),
+              "unit": "TFLOP/s", "frac": round(a / VALU_PEAK_TOPS, 4), "traffic": None,
+              "kernel": "nn_cull_kernel", "pairs_evaluated_per_launch": int(ev),
+              "brute_force_pairs_per_launch": pairs,
+              "evaluated_fraction": round(ev / pairs, 4), "launch_ms": round(nn_ms, 4)}
     else:
         a = pairs * PAIR_OPS / (nn_ms * 1e-3) / 1e12
         nn = {"bound": "alu", "achieved": round(a, 2), "peak": round(VALU_PEAK_TOPS, 2),
@@ -539,7 +551,7 @@ def time_precision(n=200_000, reps=3, sample=20_000):
     out = {"workload": f"{n:,} points U[-1,1]^3 vs the same + N(0, 0.01^2), both directions",
            "brute_force_pairs": 2 * n * n}
     res = {}
-    for mode in ("fp32", "bf16"):
+    for mode in ("fp32", "bf16", "fp32cull"):
         L.chamfer(a, b, 5.56, mode)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -559,8 +571,12 @@ def time_precision(n=200_000, reps=3, sample=20_000):
                                "frac": round(a_ / VALU_PEAK_TOPS, 4), "kernel": "nn_exact_kernel"}
         out[mode] = ent
     out["bf16_speedup"] = round(out["fp32"]["ms"] / out["bf16"]["ms"], 2)
-    out["index_mismatches_bf16_vs_fp32"] = int((res["fp32"][1] != res["bf16"][1]).sum().item() +
-                                               (res["fp32"][2] != res["bf16"][2]).sum().item())
+    # the same tile cull without matrix cores: what the cull alone buys
+    out["fp32cull_speedup"] = round(out["fp32"]["ms"] / out["fp32cull"]["ms"], 2)
+    out["bf16_speedup_over_fp32cull"] = round(out["fp32cull"]["ms"] / out["bf16"]["ms"], 2)
+    for mode in ("bf16", "fp32cull"):
+        out[f"index_mismatches_{mode}_vs_fp32"] = int((res["fp32"][1] != res[mode][1]).sum().item() +
+                                                      (res["fp32"][2] != res[mode][2]).sum().item())
     out["loss_fp32"] = res["fp32"][0].cpu().tolist()
     out["loss_bf16"] = res["bf16"][0].cpu().tolist()
     # float64 reference on a sample of each direction's queries

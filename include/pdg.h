@@ -159,13 +159,21 @@ pdg_status pdg_keyframe(const float *points, int32_t frames, int64_t n, double g
  *                                 with float32 accumulation, followed by an
  *                                 exact float32 re-rank of every candidate the
  *                                 screen cannot rule out.
+ *   mode PDG_CHAMFER_FP32_CULL  : exact float32 evaluation of every candidate
+ *                                 in the 256-point Morton tiles that the box
+ *                                 cull of the bf16 screen keeps (no matrix
+ *                                 cores); it isolates what the cull buys.
  * dir_weight (device double[2], nullable = {1,1}) scales the two directions
  * for the gradient.  ga (nullable): OVERWRITTEN with
  *   d/da [dir_weight[0]*loss[0] + dir_weight[1]*loss[1]]
  * with the assignment held fixed and the Gaussian weight differentiated;
  * B receives no gradient.  loss: device double[2].  nn_a: int32[n],
  * nn_b: int32[m].  n, m >= 1 and < 2^31. */
-typedef enum { PDG_CHAMFER_FP32 = 0, PDG_CHAMFER_BF16_SCREEN = 1 } pdg_chamfer_mode;
+typedef enum {
+  PDG_CHAMFER_FP32 = 0,
+  PDG_CHAMFER_BF16_SCREEN = 1,
+  PDG_CHAMFER_FP32_CULL = 2
+} pdg_chamfer_mode;
 
 pdg_status pdg_chamfer_workspace(int64_t n, int64_t m, int32_t mode, size_t *bytes);
 pdg_status pdg_chamfer(const float *a, int64_t n, const float *b, int64_t m, double alpha,
@@ -454,8 +462,9 @@ pdg_status pdg_batch_destroy(pdg_batch *b);
  *   PDG_BUF_SCREEN_TILES uint64[1]   matrix-core products the bf16 screen
  *                  issued (each one 32 x 32 x 16 bf16 MFMA: 1,024 candidate-query
  *                  pairs; a product recomputed for the exact re-rank counts
- *                  again), summed over every step since creation (0 bytes for
- *                  the float32 mode)
+ *                  again), summed over every step since creation; in the
+ *                  culled float32 mode, the 1,024-pair units of candidate-query
+ *                  distances it evaluated (0 bytes for the float32 mode)
  * When X_0 is optimised (0 bytes otherwise), from the last TEMPLATE stage:
  *   PDG_BUF_NN0    int32 [V + n]     nn of X_0 in P_0, then nn of P_0 in X_0
  *   PDG_BUF_LOSS0  double[2]         CD directions X_0->P_0, P_0->X_0

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpdg.so")
 MAX_LEVELS = 16                # PDG_MAX_LEVELS of include/pdg.h
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
-CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1}
+CHAMFER_MODES = {"fp32": 0, "bf16": 1, "bf16_screen": 1, "fp32cull": 2}
 PRECOND_METHODS = {"cg": 0, "dct": 1}
 STAGES = ("warp", "nn", "loss", "grad", "scatter", "precond", "adam")
 # stage ids of pdg_step_stage: the seven stages and "precond_adam" (the last

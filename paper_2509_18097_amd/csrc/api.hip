@@ -219,11 +219,13 @@ struct ChamferWs {
 ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
   ChamferWs w;
   memset(&w, 0, sizeof w);
-  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+  if (uses_packs(mode)) {
     w.ssets = c.take<ScreenSet>(2);
     w.sjobs = c.take<ScreenJob>(2);
-    w.pack_a = c.take<uint4>(2 * n);
-    w.pack_b = c.take<uint4>(2 * m);
+    if (mode == PDG_CHAMFER_BF16_SCREEN) {   // bf16 rows (the exact culled search reads coordinates)
+      w.pack_a = c.take<uint4>(2 * n);
+      w.pack_b = c.take<uint4>(2 * m);
+    }
     w.coords_a = c.take<float4>(n);
     w.coords_b = c.take<float4>(m);
     w.boxes_a = c.take<float4>(screen_box_count(n));
@@ -231,7 +233,7 @@ ChamferWs chamfer_layout(Carve &c, long long n, long long m, int mode) {
     w.perm_a = c.take<uint32_t>(n);
     w.perm_b = c.take<uint32_t>(m);
   }
-  const long long nk = mode == PDG_CHAMFER_BF16_SCREEN && n > m ? n : m;   // sort entries
+  const long long nk = uses_packs(mode) && n > m ? n : m;   // sort entries
   w.jobs = c.take<NNJob>(2);
   w.segs = c.take<ChSeg>(1);
   w.b_base = c.take<unsigned>(1);
@@ -282,7 +284,7 @@ pdg_status enqueue_chamfer(const ChamferWs &w, const float *a, long long n, cons
   PDG_TRY(upload_small(w.segs, &seg, sizeof seg, stream));
   PDG_TRY(upload_small(w.b_base, &bb, sizeof bb, stream));
   PDG_TRY(upload_small(w.w_default, ones, sizeof ones, stream));
-  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+  if (uses_packs(mode)) {
     ScreenSet ss[2];
     ScreenJob sj[2];
     memset(ss, 0, sizeof ss);
@@ -299,7 +301,10 @@ pdg_status enqueue_chamfer(const ChamferWs &w, const float *a, long long n, cons
     PDG_TRY(upload_small(w.ssets, ss, sizeof ss, stream));
     PDG_TRY(upload_small(w.sjobs, sj, sizeof sj, stream));
     PDG_TRY(launch_screen_pack(w.ssets, 2, (int)(n > m ? n : m), stream));
-    PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
+    if (mode == PDG_CHAMFER_BF16_SCREEN)
+      PDG_TRY(launch_nn_screen(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
+    else
+      PDG_TRY(launch_nn_cull(w.sjobs, 2, (int)(n > m ? n : m), 0, stream));
   } else {
     PDG_TRY(launch_nn_exact(w.jobs, 2, (int)(n > m ? n : m), stream));
   }
@@ -484,7 +489,7 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
   PDG_TRY(need(pd->params, "params"));
   PDG_TRY(need(pd->adam_m, "adam_m"));
   PDG_TRY(need(pd->adam_v, "adam_v"));
-  if (pd->chamfer_mode != PDG_CHAMFER_FP32 && pd->chamfer_mode != PDG_CHAMFER_BF16_SCREEN) {
+  if (pd->chamfer_mode != PDG_CHAMFER_FP32 && !uses_packs(pd->chamfer_mode)) {
     set_error("unknown chamfer mode %d", pd->chamfer_mode);
     return PDG_EINVAL;
   }
@@ -586,14 +591,14 @@ void layout(pdg_problem &p, Carve &c) {
   p.nseg = (int)(p.has_tm ? 2 * T : T);
   p.njobs = 2 * p.nseg;
   p.jobs = c.take<NNJob>(p.njobs);
-  if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) {
+  if (uses_packs(p.d.chamfer_mode)) {
     // every segment packs its moving set A and its fixed set B
     // moving sets (P^_t, then X_t) are packed every step, the frames P_1..P_T once
     p.pack_rows = T * N + (p.has_tm ? T * V : 0) + T * N;
     p.box_tiles = T * screen_box_count(N) + (p.has_tm ? T * screen_box_count(V) : 0) + T * screen_box_count(N);
     p.ssets = c.take<ScreenSet>(p.nseg + T);
     p.sjobs = c.take<ScreenJob>(p.njobs);
-    p.packs = c.take<uint4>(2 * p.pack_rows);
+    if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) p.packs = c.take<uint4>(2 * p.pack_rows);
     p.coords = c.take<float4>(p.pack_rows);
     p.boxes = c.take<float4>(p.box_tiles);
     p.tiles = c.take<unsigned long long>(1);
@@ -691,13 +696,15 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
           PDG_TRY(launch_chain_warp(g, p.d.params, P, p.d.template_verts, p.xhat, V, (int)T,
                                     p.tperm, st));
       }
-      if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN && !(skip & kSkipPack))
+      if (uses_packs(p.d.chamfer_mode) && !(skip & kSkipPack))
         PDG_TRY(launch_screen_pack(p.ssets, p.nseg, p.max_n, st));   // the moving sets P^_t, X_t
       return PDG_OK;
     case PDG_STAGE_NN:  // nearest neighbours (Eq. 12)
       if (skip & kSkipNN) return PDG_OK;
       if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN)   // warm start: last step's assignment
         return launch_nn_screen(p.sjobs, p.njobs, p.max_nq, 1, st);
+      if (p.d.chamfer_mode == PDG_CHAMFER_FP32_CULL)
+        return launch_nn_cull(p.sjobs, p.njobs, p.max_nq, 1, st);
       return launch_nn_exact(p.jobs, p.njobs, p.max_nq, st);
     case PDG_STAGE_LOSS:  // CD_R (Eq. 11, 13), L_iso (Eq. 18), w_conf and L (Eq. 9, 14-17)
       PDG_TRY(enqueue_stage(p, kStageLossTerms, st, user_terms, fuse, skip));
@@ -921,7 +928,7 @@ struct BatchTables {
 BatchTables batch_layout(Carve &c, int mode, int nsets, int njobs, int nseg) {
   BatchTables t;
   memset(&t, 0, sizeof t);
-  if (mode == PDG_CHAMFER_BF16_SCREEN) {
+  if (uses_packs(mode)) {
     t.ssets = c.take<ScreenSet>(nsets);
     t.sjobs = c.take<ScreenJob>(njobs);
   } else {
@@ -982,9 +989,12 @@ pdg_status enqueue_batch(pdg_batch &b, hipStream_t main) {
                           kSkipMerged));
   PDG_TRY(batch_join(b, main, 0));
   // every member's packs, nearest neighbours (Eq. 12) and Chamfer terms (Eq. 11, 13)
-  if (b.mode == PDG_CHAMFER_BF16_SCREEN) {
+  if (uses_packs(b.mode)) {
     PDG_TRY(launch_screen_pack(b.ssets, b.nsets, b.max_n, main));
-    PDG_TRY(launch_nn_screen(b.sjobs, b.njobs, b.max_nq, 1, main));
+    if (b.mode == PDG_CHAMFER_BF16_SCREEN)
+      PDG_TRY(launch_nn_screen(b.sjobs, b.njobs, b.max_nq, 1, main));
+    else
+      PDG_TRY(launch_nn_cull(b.sjobs, b.njobs, b.max_nq, 1, main));
   } else {
     PDG_TRY(launch_nn_exact(b.jobs, b.njobs, b.max_nq, main));
   }
@@ -1211,7 +1221,7 @@ pdg_status pdg_chamfer_workspace(int64_t n, int64_t m, int32_t mode, size_t *byt
     set_error("bytes NULL or n, m outside [1, 2^31)");
     return PDG_EINVAL;
   }
-  if (mode != PDG_CHAMFER_FP32 && mode != PDG_CHAMFER_BF16_SCREEN) {
+  if (mode != PDG_CHAMFER_FP32 && !uses_packs(mode)) {
     set_error("unknown chamfer mode %d", mode);
     return PDG_EINVAL;
   }
@@ -1642,10 +1652,10 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
   }
   std::vector<ScreenSet> ssets;
   std::vector<ScreenJob> sjobs;
-  if (p->packs) {
+  if (p->coords) {
     long long row = 0, tile = 0;
     auto add_set = [&](const float *x, long long n, const int *perm) {
-      ssets.push_back(screen_set(x, n, perm, p->packs + 2 * row, p->coords + row,
+      ssets.push_back(screen_set(x, n, perm, p->packs ? p->packs + 2 * row : nullptr, p->coords + row,
                                  p->boxes + tile));
       row += n;
       tile += screen_box_count(n);
@@ -1690,9 +1700,9 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
   if (e == hipSuccess) e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(ChSeg), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->jobs, jobs.data(), jobs.size() * sizeof(NNJob), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->b_base, bb.data(), bb.size() * sizeof(unsigned), hipMemcpyHostToDevice);
-  if (e == hipSuccess && p->packs)
+  if (e == hipSuccess && p->coords)
     e = hipMemcpy(p->ssets, ssets.data(), ssets.size() * sizeof(ScreenSet), hipMemcpyHostToDevice);
-  if (e == hipSuccess && p->packs)
+  if (e == hipSuccess && p->coords)
     e = hipMemcpy(p->sjobs, sjobs.data(), sjobs.size() * sizeof(ScreenJob), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     pdg_status s = hip_fail(e, "pdg_problem_create table upload");
@@ -1711,7 +1721,7 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
     s = launch_morton(pd->template_verts, V, (int)V, p->tkeys, (uint32_t *)p->tperm, stream);
     if (s == PDG_OK) s = radix_sort(p->tkeys, (uint32_t *)p->tperm, V, 30, p->sort, stream);
   }
-  if (p->packs) {
+  if (p->coords) {
     // the fixed frames' packs (their rows, coordinates and boxes never change)
     if (s == PDG_OK) s = launch_screen_pack(p->ssets + p->nseg, (int)T, (int)N, stream);
     if (s == PDG_OK) s = launch_fill((float *)p->tiles, 2, 0.f, stream);
@@ -1860,7 +1870,7 @@ pdg_status pdg_batch_create(pdg_problem *const *ps, int32_t count, void *ws, siz
   int os = 0, oj = 0;
   for (int i = 0; i < count && e == hipSuccess; ++i) {
     const pdg_problem &p = *ps[i];
-    if (b->mode == PDG_CHAMFER_BF16_SCREEN) {
+    if (uses_packs(b->mode)) {
       e = hipMemcpyAsync(b->ssets + os, p.ssets, p.nseg * sizeof(ScreenSet),
                          hipMemcpyDeviceToDevice, stream);   // the moving sets come first
       if (e == hipSuccess)

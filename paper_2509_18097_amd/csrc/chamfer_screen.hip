@@ -195,7 +195,11 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     ctr[k] = 0.5f * (b[k] + b[3 + k]);
   }
   float rad = 0.f;
-  if (in) {
+  if (in && !S.pack) {   // coordinates only (the exact culled search)
+    scoords[i] = make_float4(c[0], c[1], c[2], __int_as_float(o));
+    const float d0 = c[0] - ctr[0], d1 = c[1] - ctr[1], d2 = c[2] - ctr[2];
+    rad = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+  } else if (in) {
     float dl[3];
     unsigned short hi[3], lw[3];
     for (int k = 0; k < 3; ++k) {
@@ -605,6 +609,126 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
   if (J.tiles && lane == 0 && issued) atomicAdd(glb(J.tiles), (unsigned long long)issued);
 }
 
+// Exact float32 search with the same tile cull and no matrix cores (the
+// reference against which the bf16 screen's gain is measured): one wave of 64
+// queries per workgroup, one query per lane; the wave lists and walks its
+// candidate tiles as the screen does, stages each visited tile's coordinates
+// in its LDS slice and every lane evaluates the contract distance to all of
+// them (broadcast LDS reads).  The counter adds one per 1,024 candidate-query
+// pairs evaluated (32 candidates x 32 queries, the unit of the screen's).
+__global__ __launch_bounds__(64) void nn_cull_kernel(const ScreenJob *__restrict__ jobs,
+                                                         int warm, unsigned qt, unsigned nblk) {
+  const unsigned lin = blockIdx.x;
+  const unsigned per = gridDim.x / kXcds;
+  const unsigned tile = (lin % kXcds) * per + lin / kXcds;
+  if (tile >= nblk) return;
+  const unsigned bx = tile % qt, by = tile / qt;
+  const ScreenJob J = jobs[by];
+  const int q0 = bx * 64;
+  if (q0 >= J.nq) return;
+  const PDG_GLOBAL float4 *jq = glb(J.q);
+  const PDG_GLOBAL float4 *jcboxes = glb(J.cboxes);
+  const PDG_GLOBAL float *jc = glb(J.c);
+  PDG_GLOBAL int *jnn = glb(J.nn);
+  __shared__ int wl[kListMax];
+  __shared__ float wlb[kListMax];
+  const int lane = threadIdx.x;
+  const long long nc = J.nc;
+  const int q = q0 + lane;
+  const bool ok = q < J.nq;
+  float4 qc = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (ok) qc = jq[q];
+  const int qorig = __float_as_int(qc.w);
+  float best = __builtin_huge_valf();
+  int idx = 0x7fffffff;
+  if (ok && warm) {
+    const int p = jnn[qorig];
+    if (p >= 0 && p < J.nc) {
+      best = d2_contract(qc.x, qc.y, qc.z, jc[p], jc[nc + p], jc[2 * nc + p]);
+      idx = p;
+    }
+  }
+  float4 wmin = make_float4(ok ? qc.x : __builtin_huge_valf(), ok ? qc.y : __builtin_huge_valf(),
+                            ok ? qc.z : __builtin_huge_valf(), 0.f);
+  float4 wmaxc = make_float4(ok ? qc.x : -__builtin_huge_valf(), ok ? qc.y : -__builtin_huge_valf(),
+                             ok ? qc.z : -__builtin_huge_valf(), 0.f);
+  for (int o = 32; o > 0; o >>= 1) {
+    wmin.x = fminf(wmin.x, __shfl_xor(wmin.x, o, 64));
+    wmin.y = fminf(wmin.y, __shfl_xor(wmin.y, o, 64));
+    wmin.z = fminf(wmin.z, __shfl_xor(wmin.z, o, 64));
+    wmaxc.x = fmaxf(wmaxc.x, __shfl_xor(wmaxc.x, o, 64));
+    wmaxc.y = fmaxf(wmaxc.y, __shfl_xor(wmaxc.y, o, 64));
+    wmaxc.z = fmaxf(wmaxc.z, __shfl_xor(wmaxc.z, o, 64));
+  }
+  auto wave_best = [&]() {
+    float m = ok ? best : 0.f;
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m)));
+  };
+  unsigned pairs = 0;           // 1,024-pair units evaluated (wave-uniform)
+  const int ntiles = (J.nc + kTile - 1) / kTile;
+  const int qtiles = (J.nq + 63) / 64;
+  const int start = (int)((long long)bx * ntiles / qtiles);
+  float wbest = wave_best();
+  for (int base = 0; base < ntiles; base += kListMax) {
+    const int span = ntiles - base < kListMax ? ntiles - base : kListMax;
+    int count = 0;
+    for (int k0 = 0; k0 < span; k0 += 64) {
+      const int k = k0 + lane;
+      bool pass = false;
+      float lb = 0.f;
+      int t = 0;
+      if (k < span) {
+        t = (start + base + k) % ntiles;
+        lb = box_lb(wmin, wmaxc, jcboxes[kBoxStride * t], jcboxes[kBoxStride * t + 1]);
+        pass = !(lb * kCullSlack > wbest);
+      }
+      const unsigned long long m = __ballot(pass);
+      const int pos = count + __popcll(m & ((1ull << lane) - 1ull));
+      if (pass) {
+        wl[pos] = t;
+        wlb[pos] = lb;
+      }
+      count += __popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int i = 0; i < count; ++i) {
+      const float lbi = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wlb[i])));
+      if (lbi * kCullSlack > wbest) continue;
+      const int c0 = __builtin_amdgcn_readfirstlane(wl[i]) * kTile;
+      const int nleft = J.nc - c0 < kTile ? J.nc - c0 : kTile;
+      // the candidate is the same for every lane: read it through the scalar
+      // cache (the coordinates are read-only in this kernel)
+      const PDG_CONST float4 *cp = (const PDG_CONST float4 *)(J.cc + c0);
+      // (distance bits, index) as one 64-bit key: distances are >= 0, so the
+      // unsigned order of the key is the lowest-index-on-ties order
+      unsigned long long key = ((unsigned long long)__float_as_uint(best) << 32) | (unsigned)idx;
+      auto visit = [&](const float4 &p) {
+        const float d = d2_contract(qc.x, qc.y, qc.z, p.x, p.y, p.z);
+        const unsigned long long k =
+            ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)__float_as_int(p.w);
+        key = k < key ? k : key;
+      };
+      int j = 0;
+      for (; j + 8 <= nleft; j += 8) {
+        float4 p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) p[k] = cp[j + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) visit(p[k]);
+      }
+      for (; j < nleft; ++j) visit(cp[j]);
+      best = __uint_as_float((unsigned)(key >> 32));
+      idx = (int)(unsigned)key;
+      pairs += (unsigned)(2 * ((nleft + 31) / 32));
+      wbest = wave_best();
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (ok) jnn[qorig] = idx;
+  if (J.tiles && lane == 0 && pairs) atomicAdd(glb(J.tiles), (unsigned long long)pairs);
+}
+
 }  // namespace
 
 pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, uint32_t *vals,
@@ -633,6 +757,20 @@ pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int wa
   }
   nn_screen_kernel<<<(unsigned)padded, kThreads, 0, st>>>(jobs, warm, qt, (unsigned)nblk);
   return launched("nn_screen");
+}
+
+pdg_status launch_nn_cull(const ScreenJob *jobs, int njobs, int max_nq, int warm,
+                          hipStream_t st) {
+  if (njobs <= 0 || max_nq <= 0) return PDG_OK;
+  const unsigned qt = div_up(max_nq, 64);
+  const unsigned long long nblk = (unsigned long long)qt * njobs;
+  const unsigned long long padded = (nblk + kXcds - 1) / kXcds * kXcds;
+  if (padded >= (1ull << 31)) {
+    set_error("nn cull: %llu workgroups exceed the launch limit", padded);
+    return PDG_EINVAL;
+  }
+  nn_cull_kernel<<<(unsigned)padded, 64, 0, st>>>(jobs, warm, qt, (unsigned)nblk);
+  return launched("nn_cull");
 }
 
 }  // namespace pdg

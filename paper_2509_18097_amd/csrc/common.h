@@ -128,10 +128,14 @@ struct Carve {
 // memory; glb() states that, so global instructions with exact waits are used.
 // (The qualifier means something only to the device pass; the host pass,
 // which parses device code without generating it, sees plain pointers.)
+// PDG_CONST marks memory that no lane writes while the kernel runs (the
+// constant address space): uniform loads from it go through the scalar cache.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define PDG_GLOBAL __attribute__((address_space(1)))
+#define PDG_CONST __attribute__((address_space(4)))
 #else
 #define PDG_GLOBAL
+#define PDG_CONST
 #endif
 template <typename T>
 __device__ __forceinline__ PDG_GLOBAL T *glb(T *p) {
@@ -307,6 +311,10 @@ pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, ui
 pdg_status launch_screen_pack(const ScreenSet *sets, int nsets, int max_n, hipStream_t st);
 pdg_status launch_nn_screen(const ScreenJob *jobs, int njobs, int max_nq, int warm,
                             hipStream_t st);
+// the same jobs searched exactly in float32 (no matrix cores) with the same tile cull
+pdg_status launch_nn_cull(const ScreenJob *jobs, int njobs, int max_nq, int warm, hipStream_t st);
+// Chamfer modes that use the Morton-ordered packs and tile boxes
+inline bool uses_packs(int mode) { return mode == PDG_CHAMFER_BF16_SCREEN || mode == PDG_CHAMFER_FP32_CULL; }
 constexpr int kLossBlocks = 32;  // fixed partial count per (segment, direction)
 constexpr int kIsoBlocks = 1024; // fixed partial count of the isometry loss
 // each segment's part[dir*kLossBlocks + blk]; then its loss[dir] = mean.

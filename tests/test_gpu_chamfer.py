@@ -21,7 +21,7 @@ def _clouds(n, m, seed):
     return a, b
 
 
-MODES = ["fp32", "bf16"]
+MODES = ["fp32", "bf16", "fp32cull"]
 
 
 @pytest.mark.parametrize("n,m", SIZES)
@@ -95,18 +95,20 @@ def test_precision_pair_200k_sampled(mode):
     assert abs(loss[1] - C.direction_loss(q, p, nb)) <= 1e-10 * loss[1]
 
 
-def test_screen_equals_exact_everywhere_200k():
-    """The screened search returns exactly the exact search's indices on every
-    query of the 200k x 200k pair (both directions)."""
+@pytest.mark.parametrize("mode", ["bf16", "fp32cull"])
+def test_screen_equals_exact_everywhere_200k(mode):
+    """The screened and the culled searches return exactly the exact search's
+    indices on every query of the 200k x 200k pair (both directions)."""
     require_gpu()
     p, q = synth.cloud_pair_cube(seed=1, n=200_000)
     l0, a0, b0, _ = L.chamfer(dev(p), dev(q), mode="fp32")
-    l1, a1, b1, _ = L.chamfer(dev(p), dev(q), mode="bf16")
+    l1, a1, b1, _ = L.chamfer(dev(p), dev(q), mode=mode)
     assert torch.equal(a0, a1) and torch.equal(b0, b1)
     assert torch.equal(l0, l1)
 
 
-def test_screen_far_and_clustered_points():
+@pytest.mark.parametrize("mode", ["bf16", "fp32cull"])
+def test_screen_far_and_clustered_points(mode):
     """Coordinates far from the origin (large |x| widens the screen bound) and
     many near-duplicates (narrow gaps) still give the exact indices."""
     require_gpu()
@@ -114,6 +116,6 @@ def test_screen_far_and_clustered_points():
     base = rng.uniform(-1, 1, (3, 64))
     a = (np.repeat(base, 40, axis=1) + rng.normal(0, 1e-4, (3, 2560)) + 3.0).astype(np.float32)
     b = (np.repeat(base, 30, axis=1) + rng.normal(0, 1e-4, (3, 1920)) + 3.0).astype(np.float32)
-    _, na, nb, _ = L.chamfer(dev(a), dev(b), mode="bf16")
+    _, na, nb, _ = L.chamfer(dev(a), dev(b), mode=mode)
     assert np.array_equal(host(na), C.nn_fp32(a, b))
     assert np.array_equal(host(nb), C.nn_fp32(b, a))

@@ -91,7 +91,7 @@ def test_pair_step_ragged():
 
 @pytest.mark.parametrize("epoch,mode,precond", [(0, "fp32", "cg"), (3, "fp32", "cg"),
                                                (10, "fp32", "cg"), (3, "bf16", "cg"),
-                                               (3, "bf16", "dct")])
+                                               (3, "bf16", "dct"), (3, "fp32cull", "dct")])
 def test_sequence_step_with_template(epoch, mode, precond):
     require_gpu()
     seq = synth.deforming_sequence(seed=1, frames=5, n=1500, subdiv=2)
@@ -119,19 +119,20 @@ def test_sequence_step_confidence_active(mode):
 
 
 def test_screened_step_equals_exact_step_over_iterations():
-    """The served (bf16-screened, warm-started) form and the plain float32 form
-    produce bitwise identical iterations."""
+    """The served (bf16-screened, warm-started) form, the culled float32 form
+    and the plain float32 form produce bitwise identical iterations."""
     require_gpu()
     seq = synth.deforming_sequence(seed=4, frames=4, n=3000, subdiv=3)
     res = (4, 8, 16, 32)
     probs = [Problem(dev(seq.points), res, template=dev(seq.template), edges=dev(seq.edges),
-                     chamfer_mode=m) for m in ("fp32", "bf16")]
+                     chamfer_mode=m) for m in ("fp32", "bf16", "fp32cull")]
     for e in range(5):
         for p in probs:
             p.step(e, use_graph=True)
         torch.cuda.synchronize()
-        assert torch.equal(probs[0].buffer("nn"), probs[1].buffer("nn")), e
-        assert torch.equal(probs[0].params, probs[1].params), e
+        for q in probs[1:]:
+            assert torch.equal(probs[0].buffer("nn"), q.buffer("nn")), e
+            assert torch.equal(probs[0].params, q.params), e
 
 
 def test_zero_grids_identical_frames_fixed_point():
