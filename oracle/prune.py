@@ -101,19 +101,20 @@ def apply_masked(g: np.ndarray, r: int, lam: float, mask: np.ndarray) -> np.ndar
     return out.reshape(g.shape)
 
 
-def apply_levels_masked(flat: np.ndarray, res, lams, masks) -> np.ndarray:
+def apply_levels_masked(flat: np.ndarray, res, lams, masks, channels: int = 3) -> np.ndarray:
     """Precondition one transition's packed gradient level by level on its
-    pruned grids (masks: one [r, r, r] per level)."""
+    pruned grids (masks: one [r, r, r] per level); every channel of a level
+    (three, or the six of the cells [z; t] of Eq. 4-7) on the same kept cells."""
     out, off = [], 0
     flat = np.asarray(flat, dtype=np.float64)
     for r, lam, mk in zip(res, lams, masks):
-        n = 3 * r ** 3
-        out.append(apply_masked(flat[off:off + n].reshape(3, r ** 3), r, lam, mk).reshape(-1))
+        n = channels * r ** 3
+        out.append(apply_masked(flat[off:off + n].reshape(channels, r ** 3), r, lam, mk).reshape(-1))
         off += n
     return np.concatenate(out)
 
 
-def packed_mask(masks, res) -> np.ndarray:
-    """Boolean over one transition's packed values (three channels per level)."""
-    return np.concatenate([np.tile(np.asarray(mk, bool).reshape(-1), 3)
+def packed_mask(masks, res, channels: int = 3) -> np.ndarray:
+    """Boolean over one transition's packed values (``channels`` per level)."""
+    return np.concatenate([np.tile(np.asarray(mk, bool).reshape(-1), channels)
                            for mk, _ in zip(masks, res)])

@@ -284,7 +284,7 @@ def step(points, template, edges, res, theta, m, v, epoch: int, hp: Hyper = Hype
         pgrad = np.stack([_pc.apply_levels(g_in[t], res, lams, precond_method, channels)
                           for t in range(t_count)])
     else:
-        pgrad = np.stack([_pr.apply_levels_masked(g_in[t], res, lams, masks[t])
+        pgrad = np.stack([_pr.apply_levels_masked(g_in[t], res, lams, masks[t], channels)
                           for t in range(t_count)])
     r.pgrad = pgrad
     p_in = pgrad if pgrad_override is None else np.asarray(pgrad_override, np.float64)

@@ -8,7 +8,12 @@
   closed form; a cube-shaped mask gives the DCT closed form of the smaller
   cube (the induced graph of a sub-box is a box); two cubes with a gap are
   solved independently; pruned cells come out zero; constants on a connected
-  kept set pass unchanged; the operator is symmetric.
+  kept set pass unchanged; the operator is symmetric;
+* six-channel cells (Eq. 4-7) on pruned grids: every one of the six channels
+  of a level is preconditioned on the same kept cells -- full masks give the
+  box's DCT closed form of all six channels, cube masks the DCT of the
+  sub-cubes, pruned values come out zero, and a full step with full masks
+  equals the unpruned six-channel step.
 """
 import numpy as np
 import pytest
@@ -108,3 +113,61 @@ def test_stack_masks_use_both_frames():
     assert len(ms) == 2
     for b in range(2):
         np.testing.assert_array_equal(ms[b][0], PR.occupied([pts[b], pts[b + 1]], 8))
+
+
+PAPER_RES = (1, 3, 5, 7)               # R = 2l - 1, the first levels of the paper's grid
+
+
+def _lams(res):
+    return [0.25 * 1.5 ** l for l in range(len(res))]
+
+
+def test_six_channel_full_masks_are_dct():
+    res = PAPER_RES
+    g = np.random.default_rng(21).normal(size=6 * sum(r ** 3 for r in res))
+    full = [np.ones((r, r, r), bool) for r in res]
+    got = PR.apply_levels_masked(g, res, _lams(res), full, channels=6)
+    ref = PC.apply_levels(g, res, _lams(res), "dct", channels=6)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_six_channel_cube_masks_and_zeros():
+    res = (4, 9)
+    rng = np.random.default_rng(22)
+    boxes = {4: [(0, 1, 1, 3)], 9: [(1, 2, 0, 4), (5, 5, 5, 3)]}
+    masks = []
+    for r in res:
+        m = np.zeros((r, r, r), bool)
+        for z, y, x, sd in boxes[r]:
+            m[z:z + sd, y:y + sd, x:x + sd] = True
+        masks.append(m)
+    lams = _lams(res)
+    g = rng.normal(size=6 * sum(r ** 3 for r in res))
+    got = PR.apply_levels_masked(g, res, lams, masks, channels=6)
+    keep = PR.packed_mask(masks, res, channels=6)
+    assert keep.size == got.size and np.all(got[~keep] == 0.0)
+    off = 0
+    for r, lam in zip(res, lams):
+        gl = g[off:off + 6 * r ** 3].reshape(6, r, r, r)
+        subs = [PC.apply_dct(gl[:, z:z + sd, y:y + sd, x:x + sd].reshape(6, -1), sd, lam)
+                for z, y, x, sd in boxes[r]]
+        np.testing.assert_allclose(got[off:off + 6 * r ** 3],
+                                   _embed(r, boxes[r], subs).reshape(-1), atol=1e-12)
+        off += 6 * r ** 3
+
+
+def test_six_channel_step_full_masks_equal_unpruned():
+    import synth
+    from oracle import sequence as S
+    res = (1, 3)
+    seq = synth.deforming_sequence(seed=23, frames=3, n=60, subdiv=0)
+    P6 = 6 * sum(r ** 3 for r in res)
+    theta = np.random.default_rng(24).normal(0, 0.05, (2, P6))
+    z = np.zeros_like(theta)
+    full = [[np.ones((r, r, r), bool) for r in res] for _ in range(2)]
+    hp = S.Hyper(e_max=10)
+    a = S.step(seq.points, seq.template, seq.edges, res, theta, z, z, 1, hp, channels=6)
+    b = S.step(seq.points, seq.template, seq.edges, res, theta, z, z, 1, hp, channels=6,
+               masks=full)
+    np.testing.assert_allclose(b.pgrad, a.pgrad, atol=1e-12 * np.abs(a.pgrad).max())
+    np.testing.assert_allclose(b.theta, a.theta, atol=1e-12)
