@@ -66,8 +66,9 @@ int32_t pdg_version(void);
  *                 pdg_deform, pdg_deform_backward(+_workspace),
  *                 pdg_precondition(+_workspace) (the rotation and the
  *                 translation halves of every level preconditioned alike)
- *                 pdg_adam and the problem (its full step on these cells)
- *                 take it; pruning returns PDG_EUNSUPPORTED.
+ *                 pdg_adam and the problem (its full step on these cells,
+ *                 also on pruned grids: all six channels of a level on the
+ *                 same kept cells) take it.
  *   level_scale : factor applied to the sum over levels; 1/L reproduces the
  *                 averaging of Eq. 1. */
 typedef struct {
@@ -238,7 +239,8 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
  * Mask layout (one stack): every level in order, ceil(R^3 / 32) uint32 words
  * each; cell c = (z R + y) R + x of a level is bit (c & 31) of its word
  * c >> 5.  pdg_prune_mask_words gives the words per stack; stacks follow each
- * other at that stride. */
+ * other at that stride.  The masks cover cells, so the three functions below
+ * take a three- or six-channel descriptor alike (same words, same bits). */
 pdg_status pdg_prune_mask_words(const pdg_grid_desc *d, int64_t *words /*[host]*/);
 pdg_status pdg_prune_workspace(const pdg_grid_desc *d, int32_t stacks, size_t *bytes);
 /* Masks of `stacks` grid stacks: stack b is pruned by frames b .. b+span-1 of

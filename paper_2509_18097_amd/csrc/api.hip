@@ -463,10 +463,6 @@ pdg_status check_problem(const pdg_problem_desc *pd) {
     return PDG_EINVAL;
   }
   PDG_TRY(check_grid(&pd->grid, true));
-  if (pd->grid.channels == 6 && pd->prune_mask) {
-    set_error("pruned grids are three-channel only");
-    return PDG_EUNSUPPORTED;
-  }
   if (pd->frames < 2) {
     set_error("frames = %d: need at least 2", pd->frames);
     return PDG_EINVAL;
@@ -641,7 +637,10 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   } else {
     p.cg = cg_plan(p.g, p.T, lam, pd.cg_iters, pd.cg_tol, true);
   }
-  if (pd.prune_mask) cg_set_mask(p.cg, p.g, pd.prune_mask);
+  if (pd.prune_mask) {   // six channels: both halves on the same kept cells
+    cg_set_mask(p.cg, p.g, pd.prune_mask);
+    if (p.g.ch == 6) cg_set_mask(p.cg_t, p.g, pd.prune_mask);
+  }
 }
 
 IsoArgs iso_args(pdg_problem &p) {
@@ -1360,14 +1359,14 @@ pdg_status pdg_precondition(const pdg_grid_desc *d, const float *lambda, float *
 }
 
 pdg_status pdg_prune_mask_words(const pdg_grid_desc *d, int64_t *words) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));   // masks cover cells: the channel count does not matter
   PDG_TRY(need(words, "words"));
   *words = mask_stack_words(make_grid(*d));
   return PDG_OK;
 }
 
 pdg_status pdg_prune_workspace(const pdg_grid_desc *d, int32_t stacks, size_t *bytes) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));
   if (!bytes || stacks < 0) {
     set_error("bytes NULL or stacks < 0");
     return PDG_EINVAL;
@@ -1379,7 +1378,7 @@ pdg_status pdg_prune_workspace(const pdg_grid_desc *d, int32_t stacks, size_t *b
 pdg_status pdg_prune_mask(const pdg_grid_desc *d, int32_t stacks, int32_t span, const float *points,
                           int64_t n, int32_t halo, uint32_t *mask, int64_t *active, void *ws,
                           size_t ws_bytes, hipStream_t stream) {
-  PDG_TRY(check_grid(d));
+  PDG_TRY(check_grid(d, true));
   if (stacks < 0 || span < 1 || n < 0 || n >= (1ll << 31) || halo < 0 || halo > 16) {
     set_error("prune: stacks >= 0, span >= 1, 0 <= n < 2^31 and 0 <= halo <= 16 required");
     return PDG_EINVAL;
@@ -1758,6 +1757,13 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
       const int nk = cg_kept_tiles(p->cg, p->g, hm.data(), kl.data());
       if (nk > 0) he = hipMemcpy(p->klist, kl.data(), nk * sizeof(int), hipMemcpyHostToDevice);
       p->cg.klist = p->klist;
+      if (p->g.ch == 6) {   // the other half's plan numbers its tiles the same way
+        p->cg_t.klist = p->klist;
+        for (int l = 0; l < p->g.levels; ++l) {
+          p->cg_t.kfirst[l] = p->cg.kfirst[l];
+          p->cg_t.kcount[l] = p->cg.kcount[l];
+        }
+      }
     }
     if (he != hipSuccess) s = hip_fail(he, "pdg_problem_create kept tiles");
   }

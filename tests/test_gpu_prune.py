@@ -235,3 +235,54 @@ def test_step_pruned_with_empty_tiles():
     np.testing.assert_array_equal(pgrad, full)
     theta = host(prob.params)
     assert np.max(np.abs(theta - r.theta)) <= 1e-5 * max(S.Hyper().schedule(len(res))[0])
+
+
+PAPER_RES = tuple(2 * l - 1 for l in range(1, 11))    # the paper's grid: L = 10, R = 2l - 1
+
+
+def test_six_channel_step_pruned_paper_grid():
+    """The paper's configuration: six-channel cells [z; t] (Eq. 4-7) on pruned
+    grids (Sec. 3.6) over R = 1, 3, .., 19.  A compact point set with a one-cell
+    halo prunes the outer cells of the finer levels; the pruned values of all
+    six channels start and stay at zero, and the step matches the oracle
+    stage by stage (gradient, the preconditioner of both halves on the kept
+    cells' graph, Adam)."""
+    require_gpu()
+    res = PAPER_RES
+    seq = synth.deforming_sequence(seed=41, frames=4, n=700, subdiv=2)
+    pts = (0.45 * seq.points).astype(np.float32)
+    tmpl = (0.45 * seq.template).astype(np.float32)
+    T = 3
+    P6 = L.grid_size(res, 6)
+    theta0 = np.random.default_rng(42).normal(0, 0.05, (T, P6)).astype(np.float32)
+    print("six-channel pruned step, R = 1..19", flush=True)
+    prob = Problem(dev(pts), res, template=dev(tmpl), edges=dev(seq.edges),
+                   hp=HyperParams(e_max=10), params=dev(theta0), precond="cg", prune_halo=1,
+                   channels=6)
+    masks = PR.stack_masks(pts, res, halo=1, span=2)
+    got = host(prob.prune_mask)
+    for t in range(T):
+        np.testing.assert_array_equal(got[t], _pack(masks[t], res))
+    keep = np.stack([PR.packed_mask(masks[t], res, channels=6) for t in range(T)])
+    assert 0.03 < keep.mean() < 0.9, keep.mean()         # most cells of the finer levels pruned
+    theta_p = np.where(keep, theta0, 0.0).astype(np.float32)
+    np.testing.assert_array_equal(host(prob.params), theta_p)
+    prob.step(1)
+    torch.cuda.synchronize()
+    phat, xhat = host(prob.buffer("phat")), host(prob.buffer("xhat"))
+    grad, pgrad = host(prob.buffer("grad")), host(prob.buffer("pgrad"))
+    z = np.zeros_like(theta_p, dtype=np.float64)
+    r = S.step(pts, tmpl, seq.edges, res, theta_p, z, z, 1, S.Hyper(e_max=10),
+               phat32=phat, xhat32=xhat, grad_override=grad, pgrad_override=pgrad, masks=masks,
+               channels=6, workers=4)
+    assert_rel(grad, r.grad, 1e-5, "dL/dG (six channels)")
+    assert_rel(pgrad, r.pgrad, 1e-5, "pruned preconditioned (six channels)")
+    assert np.all(pgrad[~keep] == 0.0)
+    eta_max = max(S.Hyper().schedule(len(res))[0])
+    assert np.max(np.abs(host(prob.params) - r.theta)) <= 1e-5 * eta_max
+    for e in range(2, 5):
+        prob.step(e, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.all(host(prob.params)[~keep] == 0.0)
+    assert np.all(host(prob.m)[~keep] == 0.0) and np.all(host(prob.v)[~keep] == 0.0)
+    assert np.isfinite(prob.terms()["loss"])

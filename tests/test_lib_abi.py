@@ -95,8 +95,12 @@ def test_prune_validation_on_host():
                                        None) == L.EINVAL
     assert lib.pdg_precondition_pruned(ctypes.byref(d), lam, 256, 1, 0, 1e-7, 256, 256, 8,
                                        None) == L.ENOMEM
+    # masks cover cells: a six-channel descriptor has the same words
     d6 = L.grid_desc((4, 8), channels=6)
-    assert lib.pdg_prune_mask_words(ctypes.byref(d6), ctypes.byref(w)) == L.EUNSUPPORTED
+    w3, w6 = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.pdg_prune_mask_words(ctypes.byref(L.grid_desc((4, 8))), ctypes.byref(w3)) == L.OK
+    assert lib.pdg_prune_mask_words(ctypes.byref(d6), ctypes.byref(w6)) == L.OK
+    assert w6.value == w3.value == 2 + 16
 
 
 def test_problem_validation_on_host():
