@@ -172,22 +172,26 @@ def test_graph_replay_equals_eager_and_is_deterministic():
 def test_fused_precondition_adam_equals_stages():
     """A full step lets the last inverse-DCT pass of the 64^3 and 128^3 levels
     apply Adam (Sec. 3.6) itself; the stages enqueued one at a time run Adam
-    separately.  Both give bitwise the same gradient, parameters and moments,
-    also on a second iteration with non-zero moments."""
+    separately; the full step is also replayed as a captured graph.  All give
+    bitwise the same gradient, parameters and moments, also on a second
+    iteration with non-zero moments."""
     require_gpu()
     seq = synth.deforming_sequence(seed=6, frames=3, n=4000, subdiv=3)
     res = (8, 64, 128)
     th = _theta0(2, res, 7, std=0.001)
     probs = [Problem(dev(seq.points), res, template=dev(seq.template), edges=dev(seq.edges),
-                     params=dev(th), chamfer_mode="bf16", precond="dct") for _ in range(2)]
+                     params=dev(th), chamfer_mode="bf16", precond="dct") for _ in range(3)]
     for it in range(2):
         probs[0].step(0)
         for name in L.STAGES:
             probs[1].stage(name)
+        probs[2].step(0, use_graph=True)
         torch.cuda.synchronize()
-        assert torch.equal(probs[0].buffer("grad"), probs[1].buffer("grad")), it
-        for attr in ("params", "m", "v"):
-            assert torch.equal(getattr(probs[0], attr), getattr(probs[1], attr)), (it, attr)
+        for q in probs[1:]:
+            assert torch.equal(probs[0].buffer("grad"), q.buffer("grad")), it
+            assert torch.equal(probs[0].buffer("xhat"), q.buffer("xhat")), it
+            for attr in ("params", "m", "v"):
+                assert torch.equal(getattr(probs[0], attr), getattr(q, attr)), (it, attr)
     assert torch.count_nonzero(probs[0].m).item() > 0
 
 
