@@ -118,15 +118,47 @@ pdg_status pdg_deform_backward(const pdg_grid_desc *d, const float *grids, const
  * V >= 0 vertices; edges: int32 [2][E] (each undirected edge listed once; an
  * edge listed twice counts twice; edges with an endpoint outside [0, V) are
  * ignored); g, out: SoA [3][V] float32 (out may alias g); lambda >= 0.
- * max_degree: [host] an upper bound on every vertex degree; it fixes the
- * spectrum bound [1, 1 + 2 lambda max_degree] of I + lambda L on which each of
- * the two solves runs a Chebyshev iteration in float64 (a degree above the
- * bound voids the convergence guarantee).  iters: iterations per solve, or 0
- * for the smallest count whose a-priori error bound 2 rho^k is below tol.
- * ws: device workspace of at least pdg_mesh_precondition_workspace() bytes. */
+ * max_degree: [host] an upper bound on every vertex degree (checked: a larger
+ * degree is PDG_EINVAL); it fixes the spectrum bound [1, kappa], kappa =
+ * 1 + 2 lambda max_degree, of I + lambda L.  The operator is evaluated as one
+ * Chebyshev series of t^-2 on [1, kappa] in float64 vectors; terms: series
+ * terms, or 0 for the fewest whose dropped coefficients' magnitudes sum below
+ * tol (a bound on the operator-norm error; 1e-8 gives about 146 terms at
+ * lambda = 16 and degree 6).  lambda = 0 or no edge: out = g exactly.
+ * ws: device workspace of at least pdg_mesh_precondition_workspace() bytes;
+ * it holds the plan's tables and vectors, so it must outlive the plan.
+ *
+ * A plan is built once per edge list (on the host, from a copy of the edges:
+ * pdg_mesh_plan_create synchronises `stream`) and applied any number of
+ * times; pdg_mesh_plan_apply enqueues kernels only (no allocation, no host
+ * synchronisation; capturable in a HIP graph).  Applications of one plan
+ * share its ws: calls that overlap (different streams) race.
+ * pdg_mesh_plan_info: series terms and the number of vertex parts (0: the
+ * graph's neighbourhoods did not fit, one term per launch).
+ * pdg_mesh_precondition = create, apply, destroy (synchronous). */
+typedef struct pdg_mesh_plan pdg_mesh_plan;
 pdg_status pdg_mesh_precondition_workspace(int64_t V, int64_t E, size_t *bytes);
+pdg_status pdg_mesh_plan_create(int64_t V, const int32_t *edges, int64_t E, float lambda,
+                                int32_t max_degree, int32_t terms, double tol, void *ws,
+                                size_t ws_bytes, hipStream_t stream, pdg_mesh_plan **plan);
+pdg_status pdg_mesh_plan_apply(const pdg_mesh_plan *plan, const float *g, float *out,
+                               hipStream_t stream);
+pdg_status pdg_mesh_plan_info(const pdg_mesh_plan *plan, int32_t *terms /*[host]*/,
+                              int32_t *parts /*[host]*/);
+pdg_status pdg_mesh_plan_destroy(pdg_mesh_plan *plan);
+/* [host only, no GPU] The vertex parts a plan of this edge list would use
+ * (edges: HOST int32 [2][E]): sizes[0] = parts (0: one term per launch),
+ * sizes[1] = local vertices over all parts, sizes[2] = recurrence terms per
+ * launch k, sizes[3] = local vertices a part may hold.  With the arrays
+ * non-NULL (sized from a first call): part_off[parts + 1] first local vertex
+ * of each part, part_core[parts] its own vertices (listed first),
+ * local_vertex[] the global index and local_dist[] the edge distance from the
+ * part of every local vertex (every vertex within k edges, by distance). */
+pdg_status pdg_mesh_partition(int64_t V, const int32_t *edges, int64_t E, int32_t *part_off,
+                              int32_t *part_core, int32_t *local_vertex, int32_t *local_dist,
+                              int64_t *sizes);
 pdg_status pdg_mesh_precondition(int64_t V, const int32_t *edges, int64_t E, float lambda,
-                                 int32_t max_degree, int32_t iters, double tol, const float *g,
+                                 int32_t max_degree, int32_t terms, double tol, const float *g,
                                  float *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------- keyframe --
@@ -358,11 +390,12 @@ typedef struct pdg_problem pdg_problem;
 pdg_status pdg_problem_workspace(const pdg_problem_desc *pd, size_t *bytes);
 /* Validates pd, lays out the workspace, writes the problem's job tables into
  * it and enqueues the one-time set-up (Morton orders, static scatter tables of
- * the input points, template edge incidence and mesh adjacency, pruned-grid
- * zeroing) on `stream`.  *out receives an opaque handle (host memory).
+ * the input points, template edge incidence, pruned-grid zeroing) on
+ * `stream`.  *out receives an opaque handle (host memory).
  * SYNCHRONOUS: the tables are written with blocking host-to-device copies;
  * with a template the edge list is copied to the host to validate it and to
- * take the maximum vertex degree; with prune_mask the call synchronises
+ * take the maximum vertex degree (X_0 optimised: also to build the mesh
+ * preconditioner's plan, pdg_mesh_plan_create); with prune_mask the call synchronises
  * `stream` and copies the mask to the host to list the kept conjugate-
  * gradient tiles.  Create problems outside graph capture. */
 pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pdg_problem **out);
@@ -373,8 +406,8 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
  * Optimising X_0 (template_adam_m/v set) adds, after the grids' Adam, the
  * TEMPLATE stage: L_mesh = CD_R(X_0, P_0) (Eq. 10) in the problem's Chamfer
  * mode, its gradient with respect to X_0, (I + mesh_lambda L)^-2 with the
- * mesh Laplacian of the edge list (two Chebyshev solves as in
- * pdg_mesh_precondition, tolerance 1e-7) and Adam with mesh_lr.  X_0 enters
+ * mesh Laplacian of the edge list (the series of pdg_mesh_precondition, tol
+ * 1e-8, its plan built at creation) and Adam with mesh_lr.  X_0 enters
  * the template chain of the next step; the chain's own terms are not
  * differentiated with respect to X_0 (the mesh follows the keyframe's
  * points only).

@@ -77,6 +77,12 @@ _SIGS = {
     "pdg_deform_backward": (_I32, [ctypes.POINTER(GridDesc), _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "pdg_mesh_precondition_workspace": (_I32, [_I64, _I64, ctypes.POINTER(_SZ)]),
     "pdg_mesh_precondition": (_I32, [_I64, _P, _I64, _F, _I32, _I32, _D, _P, _P, _P, _SZ, _P]),
+    "pdg_mesh_plan_create": (_I32, [_I64, _P, _I64, _F, _I32, _I32, _D, _P, _SZ, _P,
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "pdg_mesh_plan_apply": (_I32, [ctypes.c_void_p, _P, _P, _P]),
+    "pdg_mesh_plan_info": (_I32, [ctypes.c_void_p, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "pdg_mesh_plan_destroy": (_I32, [ctypes.c_void_p]),
+    "pdg_mesh_partition": (_I32, [_I64, _P, _I64, _P, _P, _P, _P, _P]),
     "pdg_keyframe_workspace": (_I32, [_I32, ctypes.POINTER(_SZ)]),
     "pdg_keyframe": (_I32, [_P, _I32, _I64, _D, _P, _P, _P, _SZ, _P]),
     "pdg_chamfer_workspace": (_I32, [_I64, _I64, _I32, ctypes.POINTER(_SZ)]),
@@ -210,9 +216,10 @@ def deform_backward(grids, x, gout, res, level_scale=None, need_grids=True, need
 
 
 def mesh_precondition(g: torch.Tensor, edges: torch.Tensor, max_degree: int, lam: float = 16.0,
-                      iters: int = 0, tol: float = 1e-7, out=None) -> torch.Tensor:
+                      terms: int = 0, tol: float = 1e-8, out=None) -> torch.Tensor:
     """(I + lam L)^-2 g for the mesh Laplacian of edges (2, E) int32; g (3, V)
-    float32; max_degree bounds every vertex degree (Sec. 3.2, 3.6)."""
+    float32; max_degree bounds every vertex degree (Sec. 3.2, 3.6).  One call
+    builds a plan (synchronous) and applies it; see MeshPlan to apply many."""
     _dev(g, torch.float32, "g")
     _dev(edges, torch.int32, "edges")
     if g.dim() != 2 or g.shape[0] != 3 or edges.dim() != 2 or edges.shape[0] != 2:
@@ -224,9 +231,81 @@ def mesh_precondition(g: torch.Tensor, edges: torch.Tensor, max_degree: int, lam
           "pdg_mesh_precondition_workspace")
     ws = _ws(nb.value, g.device)
     check(lib().pdg_mesh_precondition(v, _ptr(edges) if e > 0 else None, e, float(lam),
-                                      int(max_degree), int(iters), float(tol), _ptr(g), _ptr(out),
+                                      int(max_degree), int(terms), float(tol), _ptr(g), _ptr(out),
                                       _ptr(ws), nb.value, _stream()), "pdg_mesh_precondition")
     return out
+
+
+def mesh_partition(edges, vertices: int):
+    """The vertex parts a mesh plan of edges ((2, E) host int array) would use
+    (host only): (part_off, part_core, local_vertex, local_dist, k, local_max),
+    the arrays None when the plan runs one term per launch."""
+    import numpy as np
+    e = np.ascontiguousarray(edges, dtype=np.int32)
+    if e.ndim != 2 or e.shape[0] != 2:
+        raise ValueError("edges must be (2, E)")
+    ne = e.shape[1]
+    ep = e.ctypes.data if ne > 0 else None
+    sizes = np.zeros(4, dtype=np.int64)
+    check(lib().pdg_mesh_partition(int(vertices), ep, ne, None, None, None, None,
+                                   sizes.ctypes.data), "pdg_mesh_partition")
+    np_, nl, k, lmax = (int(x) for x in sizes)
+    if np_ == 0:
+        return None, None, None, None, k, lmax
+    po = np.zeros(np_ + 1, np.int32)
+    pc = np.zeros(np_, np.int32)
+    lv = np.zeros(nl, np.int32)
+    ld = np.zeros(nl, np.int32)
+    check(lib().pdg_mesh_partition(int(vertices), ep, ne, po.ctypes.data, pc.ctypes.data,
+                                   lv.ctypes.data, ld.ctypes.data, sizes.ctypes.data),
+          "pdg_mesh_partition")
+    return po, pc, lv, ld, k, lmax
+
+
+class MeshPlan:
+    """A built mesh preconditioner (pdg_mesh_plan_*): the series coefficients
+    and the vertex parts of one edge list, in a device workspace it keeps."""
+
+    def __init__(self, edges: torch.Tensor, vertices: int, max_degree: int, lam: float = 16.0,
+                 terms: int = 0, tol: float = 1e-8):
+        _dev(edges, torch.int32, "edges")
+        if edges.dim() != 2 or edges.shape[0] != 2:
+            raise ValueError("edges must be (2, E)")
+        self.V, e = int(vertices), edges.shape[1]
+        nb = ctypes.c_size_t()
+        check(lib().pdg_mesh_precondition_workspace(self.V, e, ctypes.byref(nb)),
+              "pdg_mesh_precondition_workspace")
+        self._ws = _ws(nb.value, edges.device)
+        h = ctypes.c_void_p()
+        check(lib().pdg_mesh_plan_create(self.V, _ptr(edges) if e > 0 else None, e, float(lam),
+                                         int(max_degree), int(terms), float(tol), _ptr(self._ws),
+                                         nb.value, _stream(), ctypes.byref(h)),
+              "pdg_mesh_plan_create")
+        self._h = h
+        t, p = _I32(), _I32()
+        check(lib().pdg_mesh_plan_info(self._h, ctypes.byref(t), ctypes.byref(p)),
+              "pdg_mesh_plan_info")
+        self.terms, self.parts = t.value, p.value
+
+    def apply(self, g: torch.Tensor, out=None) -> torch.Tensor:
+        _dev(g, torch.float32, "g")
+        if g.dim() != 2 or g.shape != (3, self.V):
+            raise ValueError(f"g must be (3, {self.V})")
+        out = torch.empty_like(g) if out is None else _dev(out, torch.float32, "out")
+        check(lib().pdg_mesh_plan_apply(self._h, _ptr(g), _ptr(out), _stream()),
+              "pdg_mesh_plan_apply")
+        return out
+
+    def close(self):
+        if self._h:
+            lib().pdg_mesh_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def keyframe(points: torch.Tensor, gamma: float = 0.001):

@@ -435,7 +435,8 @@ struct pdg_problem {
   double *loss0 = nullptr;                         // [2]
   ChamferWs cw0;                                   // Chamfer workspace of (X_0, P_0)
   void *meshws = nullptr;
-  int max_degree = 0, mesh_iters = 0;
+  int max_degree = 0;
+  MeshPlan *mesh = nullptr;                        // its preconditioner's plan (in meshws)
   // Eq. 14 and 17 across the two chains of a sequence whose keyframe lies
   // inside it (reverse-time propagation): the 1/T count and the other chain
   long long Tn = 0;
@@ -452,6 +453,7 @@ struct pdg_problem {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  ~pdg_problem() { mesh_plan_free(mesh); }
 };
 
 namespace pdg {
@@ -663,6 +665,8 @@ IsoArgs iso_args(pdg_problem &p) {
 // The loss stage in two halves (a sequence's two chains both compute their
 // terms before either assembles: cd_max spans both).
 constexpr int kStageLossTerms = 100;
+// series tolerance of the mesh preconditioner in a problem's TEMPLATE stage
+constexpr double kMeshTol = 1e-8;
 constexpr int kStageAssemble = 101;
 
 // Parts of a stage that a batch of problems runs as one launch over its
@@ -820,8 +824,7 @@ pdg_status enqueue_stage(pdg_problem &p, int stage, hipStream_t st, double *user
                               p.loss0, p.nn0, p.nn0 + V, p.gx0, st));
       PDG_TRY(launch_mesh_terms(p.terms, user_terms, p.loss0, st));
       // (I + mesh_lambda L)^-2 with the mesh Laplacian, then Adam with mesh_lr
-      PDG_TRY(launch_mesh_solve(V, p.E, h.mesh_lambda, p.max_degree, p.mesh_iters, p.gx0,
-                                p.pgx0, p.meshws, st));   // adjacency built at creation
+      PDG_TRY(mesh_plan_apply(*p.mesh, p.gx0, p.pgx0, st));   // plan built at creation
       AdamLevels al;
       memset(&al, 0, sizeof al);
       al.levels = 1;
@@ -1169,25 +1172,88 @@ pdg_status pdg_mesh_precondition_workspace(int64_t V, int64_t E, size_t *bytes) 
   return PDG_OK;
 }
 
-pdg_status pdg_mesh_precondition(int64_t V, const int32_t *edges, int64_t E, float lambda,
-                                 int32_t max_degree, int32_t iters, double tol, const float *g,
-                                 float *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+struct pdg_mesh_plan {
+  MeshPlan *p = nullptr;
+};
+
+pdg_status pdg_mesh_plan_create(int64_t V, const int32_t *edges, int64_t E, float lambda,
+                                int32_t max_degree, int32_t terms, double tol, void *ws,
+                                size_t ws_bytes, hipStream_t stream, pdg_mesh_plan **plan) {
   size_t need_bytes = 0;
   PDG_TRY(pdg_mesh_precondition_workspace(V, E, &need_bytes));
-  if (!(lambda >= 0.0f) || !isfinite(lambda) || max_degree < 0 || iters < 0 ||
-      (iters == 0 && !(tol > 0.0 && tol < 1.0))) {
-    set_error("lambda must be finite and >= 0, max_degree and iters >= 0, tol in (0, 1)");
+  if (!plan || !(lambda >= 0.0f) || !isfinite(lambda) || max_degree < 0 || terms < 0 ||
+      (terms == 0 && !(tol > 0.0 && tol < 1.0))) {
+    set_error("plan NULL, or lambda not finite and >= 0, max_degree or terms < 0, tol not in (0, 1)");
     return PDG_EINVAL;
   }
-  if (V == 0) return PDG_OK;
-  PDG_TRY(need(g, "g"));
-  PDG_TRY(need(out, "out"));
   if (E > 0) PDG_TRY(need(edges, "edges"));
   PDG_TRY(need_ws(ws, ws_bytes, need_bytes));
-  const int k = iters > 0 ? iters
-                          : cheb_iterations(1.0 + 2.0 * (double)lambda * (double)max_degree, tol);
-  return launch_mesh_precondition(V, (const int *)edges, E, lambda, max_degree, k, g, out, ws,
-                                  stream);
+  pdg_mesh_plan *h = new (std::nothrow) pdg_mesh_plan;
+  if (!h) {
+    set_error("host allocation failed");
+    return PDG_ENOMEM;
+  }
+  pdg_status s = mesh_plan_build(V, (const int *)edges, E, lambda, max_degree, terms, tol, ws,
+                                 stream, &h->p);
+  if (s != PDG_OK) {
+    delete h;
+    return s;
+  }
+  *plan = h;
+  return PDG_OK;
+}
+
+pdg_status pdg_mesh_plan_apply(const pdg_mesh_plan *plan, const float *g, float *out,
+                               hipStream_t stream) {
+  if (!plan) {
+    set_error("plan is NULL");
+    return PDG_EINVAL;
+  }
+  if (mesh_plan_vertices(*plan->p) > 0) {
+    PDG_TRY(need(g, "g"));
+    PDG_TRY(need(out, "out"));
+  }
+  return mesh_plan_apply(*plan->p, g, out, stream);
+}
+
+pdg_status pdg_mesh_plan_info(const pdg_mesh_plan *plan, int32_t *terms, int32_t *parts) {
+  if (!plan) {
+    set_error("plan is NULL");
+    return PDG_EINVAL;
+  }
+  if (terms) *terms = mesh_plan_terms(*plan->p);
+  if (parts) *parts = mesh_plan_parts(*plan->p);
+  return PDG_OK;
+}
+
+pdg_status pdg_mesh_partition(int64_t V, const int32_t *edges, int64_t E, int32_t *part_off,
+                              int32_t *part_core, int32_t *local_vertex, int32_t *local_dist,
+                              int64_t *sizes) {
+  if (!sizes || V < 0 || E < 0 || V >= (1ll << 31) - 1 || E >= (1ll << 30) || (E > 0 && !edges)) {
+    set_error("sizes NULL, edges NULL with E > 0, or V, E outside [0, 2^31 - 1), [0, 2^30)");
+    return PDG_EINVAL;
+  }
+  return mesh_partition_query(V, (const int *)edges, E, (int *)part_off, (int *)part_core,
+                              (int *)local_vertex, (int *)local_dist, (long long *)sizes);
+}
+
+pdg_status pdg_mesh_plan_destroy(pdg_mesh_plan *plan) {
+  if (plan) {
+    mesh_plan_free(plan->p);
+    delete plan;
+  }
+  return PDG_OK;
+}
+
+pdg_status pdg_mesh_precondition(int64_t V, const int32_t *edges, int64_t E, float lambda,
+                                 int32_t max_degree, int32_t terms, double tol, const float *g,
+                                 float *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  pdg_mesh_plan *plan = nullptr;
+  PDG_TRY(pdg_mesh_plan_create(V, edges, E, lambda, max_degree, terms, tol, ws, ws_bytes, stream,
+                               &plan));
+  const pdg_status s = pdg_mesh_plan_apply(plan, g, out, stream);
+  pdg_mesh_plan_destroy(plan);
+  return s;
 }
 
 pdg_status pdg_keyframe_workspace(int32_t frames, size_t *bytes) {
@@ -1694,8 +1760,6 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
       for (long long v = 0; v < V; ++v) p->max_degree = deg[v] > p->max_degree ? deg[v] : p->max_degree;
     }
   }
-  if (p->opt_x0)
-    p->mesh_iters = cheb_iterations(1.0 + 2.0 * (double)pd->hp.mesh_lambda * p->max_degree, 1e-7);
   if (e == hipSuccess) e = hipMemcpy(p->segs, segs.data(), segs.size() * sizeof(ChSeg), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->jobs, jobs.data(), jobs.size() * sizeof(NNJob), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->b_base, bb.data(), bb.size() * sizeof(unsigned), hipMemcpyHostToDevice);
@@ -1737,9 +1801,10 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
     s = launch_incidence(pd->edges, (int)p->E, (int)V, p->ikeys, p->ivals, p->inc_off, p->sort,
                          stream);
   if (s == PDG_OK && p->dctws) s = dct_basis(p->g, p->dctws, stream);
-  // X_0 optimised: the mesh adjacency of its preconditioner (fixed edges)
+  // X_0 optimised: the plan of its preconditioner (fixed edges)
   if (s == PDG_OK && p->opt_x0)
-    s = launch_mesh_adjacency(V, pd->edges, p->E, p->meshws, stream);
+    s = mesh_plan_build(V, pd->edges, p->E, pd->hp.mesh_lambda, p->max_degree, 0, kMeshTol,
+                        p->meshws, stream, &p->mesh);
   // pruned grids: pruned cells hold zero and keep zero moments
   if (pd->prune_mask)
     for (float *buf : {pd->params, pd->adam_m, pd->adam_v})

@@ -417,18 +417,23 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
                    const void *ws, hipStream_t st, const AdamFuse *adam = nullptr,
                    unsigned *fused = nullptr);
 
-// mesh.hip: (I + lambda L)^-2 on a mesh's vertices by two Chebyshev solves
+// mesh.hip: (I + lambda L)^-2 on a mesh's vertices by one Chebyshev series.
+// A plan (host metadata; its device tables and vectors live in the caller's
+// ws of mesh_precond_bytes(V, E)) is built once from the edge list -- which
+// synchronises the stream -- and applied any number of times.
+struct MeshPlan;
 size_t mesh_precond_bytes(long long V, long long E);
-int cheb_iterations(double kappa, double tol);
-pdg_status launch_mesh_precondition(long long V, const int *edges, long long E, float lambda,
-                                    int max_degree, int iters, const float *g, float *out,
-                                    void *ws, hipStream_t st);
-// The two halves of it: the adjacency (sorted directed edges and row table,
-// kept in ws) and the solves on an adjacency built before in the same ws.
-pdg_status launch_mesh_adjacency(long long V, const int *edges, long long E, void *ws,
-                                 hipStream_t st);
-pdg_status launch_mesh_solve(long long V, long long E, float lambda, int max_degree, int iters,
-                             const float *g, float *out, void *ws, hipStream_t st);
+pdg_status mesh_plan_build(long long V, const int *edges, long long E, float lambda,
+                           int max_degree, int terms, double tol, void *ws, hipStream_t st,
+                           MeshPlan **out);
+pdg_status mesh_plan_apply(const MeshPlan &p, const float *g, float *out, hipStream_t st);
+void mesh_plan_free(MeshPlan *p);
+int mesh_plan_terms(const MeshPlan &p);
+long long mesh_plan_vertices(const MeshPlan &p);
+// the parts a plan of this edge list (host copy) would use; arrays nullable
+pdg_status mesh_partition_query(long long V, const int *edges_host, long long E, int *part_off,
+                                int *part_core, int *lglob, int *ldist, long long *sizes);
+int mesh_plan_parts(const MeshPlan &p);
 
 // prune.hip: pruned grids.  A stack's mask holds one bit per cell of every
 // level (levels packed in order, mask_words(R) words each; bit c of a level is

@@ -1,5 +1,7 @@
 """GPU parity of the mesh-vertex preconditioner (I + lambda L)^-2 (Sec. 3.2,
-3.6) against the oracle's sparse solves."""
+3.6) against the oracle's sparse solves: the Chebyshev series on LDS-resident
+vertex parts (meshes) and one term per launch (graphs whose neighbourhoods do
+not fit), plan reuse, in-place application and the degree check."""
 import numpy as np
 import pytest
 import torch
@@ -64,3 +66,67 @@ def test_invalid_edges_ignored_alias_and_empty():
     iso = rng.normal(size=(3, 7)).astype(np.float32)                    # no edges: L = 0
     np.testing.assert_allclose(_run(iso, np.zeros((2, 0), np.int64), 16.0, 0), iso, rtol=0,
                                atol=0)
+
+
+def test_plan_parts_reuse_and_in_place():
+    """The template mesh: the plan splits it into parts (several terms per
+    launch), two applications of one plan are bitwise equal, in place too, and
+    both match the oracle."""
+    require_gpu()
+    verts, _, edges = synth.icosphere(6)
+    v = verts.shape[0]
+    dmax = M.max_degree(v, edges)
+    g = np.random.default_rng(11).normal(size=(3, v)).astype(np.float32)
+    plan = L.MeshPlan(dev(edges.astype(np.int32)), v, dmax, 16.0)
+    assert plan.parts > 1 and 100 < plan.terms < 200, (plan.parts, plan.terms)
+    a = host(plan.apply(dev(g)))
+    gd = dev(g)
+    plan.apply(gd, out=gd)
+    assert np.array_equal(host(gd), a)
+    assert_rel(a, M.precondition(v, edges, 16.0, g), 1e-5, "mesh plan")
+    plan.close()
+
+
+def test_plan_one_term_per_launch_on_an_expander():
+    """A random 8-regular-ish graph of 6000 vertices: every part's 8-edge
+    neighbourhood is about the whole graph, more than the LDS holds, so the
+    plan runs one term per launch; it matches the oracle as well."""
+    require_gpu()
+    rng = np.random.default_rng(12)
+    v = 6000
+    e = np.stack([np.repeat(np.arange(v), 4), rng.integers(0, v, 4 * v)])
+    e = e[:, e[0] != e[1]]
+    dmax = M.max_degree(v, e)
+    g = rng.normal(size=(3, v)).astype(np.float32)
+    lam = 2.0
+    plan = L.MeshPlan(dev(e.astype(np.int32)), v, dmax, lam)
+    assert plan.parts == 0
+    assert_rel(host(plan.apply(dev(g))), M.precondition(v, e, lam, g), 1e-5, "expander")
+    plan.close()
+
+
+def test_plan_degree_above_bound_and_graph_capture():
+    require_gpu()
+    verts, _, edges = synth.icosphere(3)
+    v = verts.shape[0]
+    dmax = M.max_degree(v, edges)
+    ed = dev(edges.astype(np.int32))
+    with pytest.raises(L.PdgError):
+        L.MeshPlan(ed, v, dmax - 1, 16.0)
+    assert "degree" in L.last_error()
+    plan = L.MeshPlan(ed, v, dmax, 16.0)
+    g = dev(np.random.default_rng(13).normal(size=(3, v)).astype(np.float32))
+    ref = host(plan.apply(g))
+    out = torch.empty_like(g)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(gr, stream=s):
+            plan.apply(g, out=out)
+    for _ in range(3):
+        out.zero_()
+        gr.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), ref)
+    plan.close()
