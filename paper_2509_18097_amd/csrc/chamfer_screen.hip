@@ -60,8 +60,14 @@
 // farther than the best and can be neither the nearest nor a tie.  Tiles are
 // listed by that test against the warm-start bests, visited starting from the
 // candidate tile of the same Morton rank, and re-tested against the improving
-// bests before each visit.  Ties are broken on the original indices, which the
-// packed coordinates carry, so the result is the exact search's bit for bit.
+// bests before each visit.  Ties are broken on the original indices, which
+// the packed coordinates carry, so the result is the exact search's bit for
+// bit.  (The pack also records the boxes of each tile's eight 32-point
+// sub-tiles, for the exact culled search below.  Testing them here as well,
+// per 32-query block, leaves about a quarter of a visited tile's products,
+// but the screen's time is set by its per-tile latency, not by its products:
+// the listing of the masks made it 15% slower, so the screen computes whole
+// tiles.)
 #include "common.h"
 
 namespace pdg {
@@ -93,8 +99,11 @@ constexpr int kCTile = PDG_SCREEN_TILE;   // candidates per LDS tile
 constexpr int kTile = 256;          // points per box tile (query block and candidate tile)
 static_assert(kCTile == kTile, "candidate boxes must match the screened tiles");
 constexpr int kListMax = 256;       // candidate tiles listed per pass of a wave's cull
-constexpr int kBoxStride = 3;       // float4 per tile: min corner, max corner, (centre, radius)
-static_assert(kBoxStride == 3, "the box layout is declared in common.h (screen_box_count)");
+// float4 per tile: min corner, max corner, (centre, radius), then the min and
+// max corners of its eight 32-point sub-tiles
+constexpr int kSubBoxes = kTile / 32;
+constexpr int kBoxStride = 3 + 2 * kSubBoxes;
+static_assert(kBoxStride == 19, "the box layout is declared in common.h (screen_box_count)");
 constexpr float kCullSlack = 1.0f - 1.0f / 1048576.0f;   // 1 - 2^-20
 // screen error bound in a tile's frame (a = |q - C|, b = tile radius)
 constexpr float kEpsAB = 3e-5f, kEpsSq = 2e-6f;
@@ -177,11 +186,21 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
     c[2] = sx[2 * n + o];
     for (int k = 0; k < 3; ++k) lo[k] = hi3[k] = c[k];
   }
-  for (int d = 32; d > 0; d >>= 1)
+  // the 32-point sub-tile boxes (each half wave), then the wave's
+  for (int d = 16; d > 0; d >>= 1)
     for (int k = 0; k < 3; ++k) {
       lo[k] = fminf(lo[k], __shfl_xor(lo[k], d, 64));
       hi3[k] = fmaxf(hi3[k], __shfl_xor(hi3[k], d, 64));
     }
+  if ((lane & 31) == 0) {
+    const int sb = (int)(threadIdx.x >> 5);   // sub-tile of the tile
+    sboxes[kBoxStride * tb + 3 + 2 * sb] = make_float4(lo[0], lo[1], lo[2], 0.f);
+    sboxes[kBoxStride * tb + 4 + 2 * sb] = make_float4(hi3[0], hi3[1], hi3[2], 0.f);
+  }
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = fminf(lo[k], __shfl_xor(lo[k], 32, 64));
+    hi3[k] = fmaxf(hi3[k], __shfl_xor(hi3[k], 32, 64));
+  }
   if (lane == 0)
     for (int k = 0; k < 3; ++k) {
       red[k][wv] = lo[k];
@@ -609,13 +628,14 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
   if (J.tiles && lane == 0 && issued) atomicAdd(glb(J.tiles), (unsigned long long)issued);
 }
 
-// Exact float32 search with the same tile cull and no matrix cores (the
-// reference against which the bf16 screen's gain is measured): one wave of 64
-// queries per workgroup, one query per lane; the wave lists and walks its
-// candidate tiles as the screen does, stages each visited tile's coordinates
-// in its LDS slice and every lane evaluates the contract distance to all of
-// them (broadcast LDS reads).  The counter adds one per 1,024 candidate-query
-// pairs evaluated (32 candidates x 32 queries, the unit of the screen's).
+// Exact float32 search with the same tile and sub-tile culls and no matrix
+// cores (the reference against which the bf16 screen's gain is measured): one
+// wave of 64 queries per workgroup, one query per lane; the wave lists and
+// walks its candidate tiles as the screen does, keeps the 32-candidate
+// sub-tiles whose boxes pass its test, and every lane evaluates the contract
+// distance to each of their candidates, read once for the wave through the
+// scalar cache.  The counter adds one per 1,024 candidate-query pairs
+// evaluated (32 candidates x 32 queries, the unit of the screen's).
 __global__ __launch_bounds__(64) void nn_cull_kernel(const ScreenJob *__restrict__ jobs,
                                                          int warm, unsigned qt, unsigned nblk) {
   const unsigned lin = blockIdx.x;
@@ -695,8 +715,19 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const ScreenJob *__restrict
     for (int i = 0; i < count; ++i) {
       const float lbi = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wlb[i])));
       if (lbi * kCullSlack > wbest) continue;
-      const int c0 = __builtin_amdgcn_readfirstlane(wl[i]) * kTile;
+      const int ti = __builtin_amdgcn_readfirstlane(wl[i]);
+      const int c0 = ti * kTile;
       const int nleft = J.nc - c0 < kTile ? J.nc - c0 : kTile;
+      // the 32-candidate sub-tiles whose boxes pass the wave's test (lane s
+      // tests sub-tile s)
+      unsigned sm;
+      {
+        const int sb = lane & (kSubBoxes - 1);
+        const float lbs = box_lb(wmin, wmaxc, jcboxes[kBoxStride * ti + 3 + 2 * sb],
+                                 jcboxes[kBoxStride * ti + 4 + 2 * sb]);
+        sm = (unsigned)__ballot(!(lbs * kCullSlack > wbest) && 32 * sb < nleft) &
+             ((1u << kSubBoxes) - 1u);
+      }
       // the candidate is the same for every lane: read it through the scalar
       // cache (the coordinates are read-only in this kernel)
       const PDG_CONST float4 *cp = (const PDG_CONST float4 *)(J.cc + c0);
@@ -709,18 +740,22 @@ __global__ __launch_bounds__(64) void nn_cull_kernel(const ScreenJob *__restrict
             ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)__float_as_int(p.w);
         key = k < key ? k : key;
       };
-      int j = 0;
-      for (; j + 8 <= nleft; j += 8) {
-        float4 p[8];
+      for (unsigned m = sm; m; m &= m - 1) {
+        const int j0 = 32 * __builtin_ctz(m);
+        const int j1 = nleft - j0 < 32 ? nleft : j0 + 32;
+        int j = j0;
+        for (; j + 8 <= j1; j += 8) {
+          float4 p[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) p[k] = cp[j + k];
+          for (int k = 0; k < 8; ++k) p[k] = cp[j + k];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) visit(p[k]);
+          for (int k = 0; k < 8; ++k) visit(p[k]);
+        }
+        for (; j < j1; ++j) visit(cp[j]);
       }
-      for (; j < nleft; ++j) visit(cp[j]);
       best = __uint_as_float((unsigned)(key >> 32));
       idx = (int)(unsigned)key;
-      pairs += (unsigned)(2 * ((nleft + 31) / 32));
+      pairs += 2u * (unsigned)__popc(sm);
       wbest = wave_best();
     }
     __builtin_amdgcn_wave_barrier();

@@ -302,9 +302,9 @@ struct ScreenJob {           // one directed search: packed queries over packed 
   unsigned long long *tiles; // nullable: += 32x32x16 bf16 products issued
 };
 inline long long screen_tiles(long long n) { return (n + 255) / 256; }
-// float4 entries of a set's box array (min corner, max corner, centre and
-// radius per tile)
-inline long long screen_box_count(long long n) { return 3 * screen_tiles(n); }
+// float4 entries of a set's box array: per tile its min corner, max corner,
+// (centre, radius) and the min and max corners of its eight 32-point sub-tiles
+inline long long screen_box_count(long long n) { return 19 * screen_tiles(n); }
 // keys = 30-bit Morton codes over [-1, 1]^3 of x ([3][ld] SoA, n points), vals = index
 pdg_status launch_morton(const float *x, long long ld, int n, uint32_t *keys, uint32_t *vals,
                          hipStream_t st);
