@@ -716,19 +716,29 @@ def serve_requests(count):
     return reqs, time.perf_counter() - t
 
 
+# size classes of the batched executor: bounds on points x frames (the stream's
+# requests span 16,000 to 12,800,000)
+SERVE_BUCKETS = (2e5, 1.5e6, 5e6)
+
+
 def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0, executor="batch"):
     """Serve the requests with continuous batching under an HBM budget of 60%
     of free memory; arrival times divided by `rate_scale` (1: the stream's
     4 requests/s).  executor "batch": every round one batched iteration of all
     resident requests (one launch of the screen and Chamfer terms over all
-    their jobs); "streams": each request's own graph replayed on 4 streams."""
+    their jobs); "classes": one such batch per size class, each on a stream
+    of its own; "streams": each request's own graph replayed on 4 streams."""
     import dataclasses
     import torch
     from paper_2509_18097_amd.serve import BatchExecutor, GpuExecutor, Server
     reqs = [dataclasses.replace(r, arrival=r.arrival / rate_scale) for r in reqs]
     free, _ = torch.cuda.mem_get_info()
-    ex = (BatchExecutor(chamfer_mode=chamfer, precond=precond) if executor == "batch" else
-          GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4))
+    if executor == "batch":
+        ex = BatchExecutor(chamfer_mode=chamfer, precond=precond)
+    elif executor == "classes":
+        ex = BatchExecutor(chamfer_mode=chamfer, precond=precond, buckets=SERVE_BUCKETS)
+    else:
+        ex = GpuExecutor(chamfer_mode=chamfer, precond=precond, streams=4)
     st = Server(ex, budget_bytes=int(0.6 * free), max_slots=slots).run(reqs)
     out = st.summary()
     out.update({"executor": executor, "stream_requests": len(reqs), "iterations_per_request": 20,
@@ -736,8 +746,9 @@ def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0, executor="batch"):
                 "budget_bytes": int(0.6 * free), "chamfer": chamfer, "precond": precond,
                 "max_slots": slots,
                 "load": round(st.makespan / st.arrival_span, 3) if st.arrival_span > 0 else None})
-    if executor == "batch":
+    if executor.startswith("batch"):
         out["batches_built"] = ex.batches_built
+        out["size_classes"] = len(ex.streams)
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
 
 

@@ -198,42 +198,71 @@ class GpuExecutor:
 
 
 class BatchExecutor(GpuExecutor):
-    """Runs every round as one batched iteration (``Batch``) of all runnable
-    requests on one stream: their screen packs, nearest-neighbour searches and
-    Chamfer terms are one launch each over a device table of all their jobs,
-    the rest of each request's iteration overlaps on parallel graph branches.
-    The batch (table and graph) is rebuilt only when the set of runnable
+    """Runs every round as batched iterations (``Batch``) of the runnable
+    requests: their screen packs, nearest-neighbour searches and Chamfer
+    terms are one launch each over a device table of all their jobs, the rest
+    of each request's iteration overlaps on parallel graph branches.
+    ``buckets`` (ascending bounds on points x frames) splits the requests by
+    size into classes with a batch and a stream each, so that a small
+    request's round does not wait at a batch's joins for the stages of a large
+    one and the classes overlap on the device; no bounds: one batch.  A
+    class's batch (table and graph) is rebuilt only when its set of runnable
     requests changes; a replaced batch is released once its last round has
     finished on the device."""
 
     def __init__(self, chamfer_mode: str = "bf16", precond: str = "dct",
-                 keep_params: bool = False, keep_problems: bool = False):
-        super().__init__(chamfer_mode=chamfer_mode, precond=precond, streams=1,
-                         keep_params=keep_params, keep_problems=keep_problems)
-        self._batch = None
-        self._key = None
-        self._last = None
+                 keep_params: bool = False, keep_problems: bool = False, buckets=()):
+        self.bounds = tuple(sorted(float(b) for b in buckets))
+        super().__init__(chamfer_mode=chamfer_mode, precond=precond,
+                         streams=len(self.bounds) + 1, keep_params=keep_params,
+                         keep_problems=keep_problems)
+        nb = len(self.streams)
+        self._batch = [None] * nb
+        self._key = [None] * nb
         self._retired = deque()      # (batch, event of its last round)
         self.batches_built = 0
 
+    def bucket(self, req: ServeRequest) -> int:
+        work = float(req.n) * float(req.frames)
+        return sum(1 for b in self.bounds if work >= b)
+
+    def start(self, req: ServeRequest):
+        b = self.bucket(req)
+        self._next = b                      # the class's stream
+        h = super().start(req)
+        h["bucket"] = b
+        return h
+
     def step_round(self, handles, epochs):
         from .problem import Batch
-        key = tuple(id(h["prob"]) for h in handles)
-        st = self.streams[0]
-        if key != self._key:
-            if self._batch is not None:
-                self._retired.append((self._batch, self._last))
-            self._batch = Batch([h["prob"] for h in handles], stream=st)
-            self._key = key
-            self.batches_built += 1
-        self._batch.step(epochs, use_graph=True, stream=st)
-        self._last = self.mark(handles[0])
+        groups = {}
+        for h, e in zip(handles, epochs):
+            groups.setdefault(h["bucket"], ([], []))
+            groups[h["bucket"]][0].append(h)
+            groups[h["bucket"]][1].append(e)
+        marks = []
+        for b in sorted(groups):
+            hs, es = groups[b]
+            st = self.streams[b]
+            key = tuple(id(h["prob"]) for h in hs)
+            if key != self._key[b]:
+                if self._batch[b] is not None:
+                    self._retired.append((self._batch[b], self._batch[b].last_event))
+                self._batch[b] = Batch([h["prob"] for h in hs], stream=st)
+                self._key[b] = key
+                self.batches_built += 1
+            self._batch[b].step(es, use_graph=True, stream=st)
+            ev = self.mark(hs[0])
+            self._batch[b].last_event = ev
+            for h in hs:
+                h["last"] = ev
+            marks.append(ev)
         while self._retired and self._retired[0][1].query():
             self._retired.popleft()[0].close()
-        return [self._last]
+        return marks
 
     def mark_round_done(self, h):
-        h["done"] = self._last
+        h["done"] = h["last"]
 
 
 class Server:

@@ -56,16 +56,19 @@ def test_late_arrivals_and_budget():
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
 
 
-@pytest.mark.parametrize("mode", ["bf16", "fp32"])
-def test_batched_server_alone_equals_mix(mode):
-    """The batched executor (one batched iteration of all resident requests per
-    round): every request's result equals its result served alone, and both
-    equal the per-stream executor's."""
+@pytest.mark.parametrize("mode,buckets", [("bf16", ()), ("fp32", ()), ("bf16", (6000, 11000))])
+def test_batched_server_alone_equals_mix(mode, buckets):
+    """The batched executor (one batched iteration of the resident requests per
+    round, in one batch or one per size class on streams of their own): every
+    request's result equals its result served alone, and both equal the
+    per-stream executor's."""
     require_gpu()
     reqs = _requests([0.0, 0.0, 0.0, 0.02, 0.04, 0.06])
     alone = Server(BatchExecutor(chamfer_mode=mode, precond="dct", keep_params=True),
                    budget_bytes=8 << 30, max_slots=1).run(reqs)
-    ex = BatchExecutor(chamfer_mode=mode, precond="dct", keep_params=True)
+    ex = BatchExecutor(chamfer_mode=mode, precond="dct", keep_params=True, buckets=buckets)
+    if buckets:
+        assert len({ex.bucket(r) for r in reqs}) == 3
     mix = Server(ex, budget_bytes=8 << 30, max_slots=6).run(reqs)
     ref = Server(GpuExecutor(chamfer_mode=mode, precond="dct", streams=4, keep_params=True),
                  budget_bytes=8 << 30, max_slots=6).run(reqs)
