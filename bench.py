@@ -103,6 +103,10 @@ def parse():
     ap.add_argument("--serve-only", action="store_true", help="skip the sequence benchmark")
     ap.add_argument("--serve-slots", type=int, default=32,
                     help="maximum requests resident and iterating at once")
+    ap.add_argument("--serve-executor", default="streams", choices=("streams", "batch", "classes"),
+                    help="streams: each request's own graph on 4 streams; batch: one batched "
+                         "iteration of all resident requests per round; classes: one batch "
+                         "and stream per size class")
     return ap.parse_args()
 
 
@@ -721,7 +725,7 @@ def serve_requests(count):
 SERVE_BUCKETS = (2e5, 1.5e6, 5e6)
 
 
-def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0, executor="batch"):
+def serve(reqs, chamfer, precond, slots=32, rate_scale=1.0, executor="streams"):
     """Serve the requests with continuous batching under an HBM budget of 60%
     of free memory; arrival times divided by `rate_scale` (1: the stream's
     4 requests/s).  executor "batch": every round one batched iteration of all
@@ -779,7 +783,8 @@ def main():
         return
     if args.serve_only:
         reqs, gen_s = serve_requests(args.serve)
-        out = serve(reqs, args.chamfer, args.precond, args.serve_slots)
+        out = serve(reqs, args.chamfer, args.precond, args.serve_slots,
+                    executor=args.serve_executor)
         out["input_generation_s"] = round(gen_s, 2)
         print(json.dumps({"metric": METRIC, "serving": out}))
         return
@@ -862,15 +867,13 @@ def main():
         result["step6"] = time_step6(args.subdiv, args.chamfer, args.precond)
     if args.serve > 0:
         reqs, gen_s = serve_requests(args.serve)
-        result["serving"] = serve(reqs, args.chamfer, args.precond, args.serve_slots)
+        result["serving"] = serve(reqs, args.chamfer, args.precond, args.serve_slots,
+                                  executor=args.serve_executor)
         result["serving"]["input_generation_s"] = round(gen_s, 2)
         if args.serve_load > 1.0:
             result["serving_overload"] = serve(reqs, args.chamfer, args.precond, args.serve_slots,
-                                               rate_scale=args.serve_load)
-            result["serving_overload_streams"] = serve(reqs, args.chamfer, args.precond,
-                                                       args.serve_slots,
-                                                       rate_scale=args.serve_load,
-                                                       executor="streams")
+                                               rate_scale=args.serve_load,
+                                               executor=args.serve_executor)
         del reqs
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
