@@ -37,7 +37,6 @@ FRAMES, NPTS, RES = 32, 50_000, (16, 32, 64, 128)
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 BF16_MFMA_PEAK_TFLOPS = 2500.0     # dense
-FP32_MFMA_PEAK_TFLOPS = 157.3
 FP32_VALU_PEAK_TFLOPS = 157.3     # vector FP32, an FMA counted as two flops
 PAIR_OPS = 8          # 3 sub + 3 mul + 2 add per pair under the difference-form contract
 PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
@@ -228,13 +227,14 @@ def cg_bytes(prob):
     return total
 
 
-def dct_flops(prob):
-    """Matrix-core flops of one DCT preconditioner stage: six 1-D transforms
-    (three forward, three inverse) per grid value; a dense length-R transform
-    is 2R flops per value, the even/odd form used for R = 64 and 128 half of
-    that (two length-R/2 products); R = 1 levels are skipped."""
+def dct_stage_bytes(prob):
+    """Algorithmic HBM bytes of one DCT preconditioner stage: three passes per
+    level of R <= 128 (forward plane, pencil, inverse plane), each reading and
+    writing every value once (24 B per grid value), six for R > 128 (48 B);
+    R = 1 levels are skipped.  The R = 64 and 128 levels (nearly all of the
+    values) use fast transforms and are bound by these bytes."""
     T = prob.T
-    return sum(6 * (r if r in (64, 128) else 2 * r) * T * prob.channels * r ** 3
+    return sum((24 if r <= 128 else 48) * T * prob.channels * r ** 3
                for r in prob.res if r > 1)
 
 
@@ -277,12 +277,12 @@ def roofline(prob, stages, chamfer, precond):
               "kernel": "nn_exact_kernel", "pairs_per_launch": pairs,
               "launch_ms": round(nn_ms, 4)}
     if precond == "dct":
-        f = dct_flops(prob)
-        a = f / (pre_ms * 1e-3) / 1e12
-        pre = {"bound": "mfma", "achieved": round(a, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
-               "unit": "TFLOP/s", "frac": round(a / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-               "kernel": "DCT stage: plane, pencil, plane kernels per level (12 launches)",
-               "flops_per_stage": f, "stage_ms": round(pre_ms, 4)}
+        b = dct_stage_bytes(prob)
+        a = b / (pre_ms * 1e-3) / 1e9
+        pre = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
+               "kernel": "DCT stage: plane, pencil, plane kernels per level (fast transforms "
+                         "at R = 64, 128)", "bytes_per_stage": b, "stage_ms": round(pre_ms, 4)}
     else:
         b = cg_bytes(prob)
         a = b / (pre_ms * 1e-3) / 1e9

@@ -6,21 +6,26 @@
 // mu_k = 2 - 2 cos(pi k / R)); the box Laplacian is the Kronecker sum of three
 // path Laplacians, so
 //     (I + lam L)^-2 = (C x C x C)^T diag((1 + lam (mu_i + mu_j + mu_k))^-2) (C x C x C).
-// The step applies C along x, y and z, scales, and applies C^T along z, y, x:
-// six in-place passes, each a dense contraction of every grid line with the
-// R x R basis, run on the matrix cores as v_mfma_f32_32x32x2_f32 (float32 in,
-// float32 accumulate).  The scale is fused into the first inverse pass.
-//
-// For R <= 128 three fused passes do this (x and y on a z-plane held in LDS;
-// forward z, scale and inverse z on 32 z-pencils held in LDS; inverse y and x
-// on a plane), i.e. 3 HBM round trips instead of 6.  Larger R use six axis
-// passes: a wave owns 32 grid lines and all R outputs of each (R/32 output
-// blocks of 32 x 32), reads every input of its lines once, accumulates, then
-// writes its lines, so a pass is in place and touches each value once (8 B per
-// value and pass).  Lines along y and z are taken 32-contiguous in x (coalesced
-// loads and stores); along x the operands are swapped so that the stores stay
-// contiguous.  The basis (and its transpose) is read through the caches.
+// The step applies C along x, y and z, scales, and applies C^T along z, y, x.
+// Three forms:
+//   R = 64, 128 (the finest levels, nearly all of the work): three passes over
+//     HBM (x and y on a z-plane held in LDS; forward z, scale and inverse z on
+//     128 z-pencils held in LDS; inverse y and x on a plane), each line
+//     transformed by fast factorised transforms on one thread's registers, so
+//     that the passes are bound by memory (the "Fast form" section);
+//   other R <= 128: the same three passes as dense contractions of every line
+//     with the R x R basis on the matrix cores (v_mfma_f32_32x32x2_f32, float32
+//     in and accumulate);
+//   R > 128: six axis passes on the matrix cores: a wave owns 32 grid lines and
+//     all R outputs of each (R/32 output blocks of 32 x 32), reads every input
+//     of its lines once, accumulates, then writes its lines, so a pass is in
+//     place and touches each value once (8 B per value and pass).  Lines along
+//     y and z are taken 32-contiguous in x (coalesced loads and stores); along
+//     x the operands are swapped so that the stores stay contiguous.  The basis
+//     (and its transpose) is read through the caches; the scale is fused into
+//     the first inverse pass.
 #include "common.h"
+#include "fastdct_gen.h"
 
 namespace pdg {
 namespace {
@@ -479,184 +484,204 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Even/odd form for R = 64 and 128.  C[k][R-1-x] = (-1)^k C[k][x], so a
-// forward transform needs only the left half of C on folded inputs,
-//   out[2p] = sum_{x<R/2} C[2p][x] (in[x] + in[R-1-x]),
-//   out[2p+1] = sum_{x<R/2} C[2p+1][x] (in[x] - in[R-1-x]),
-// and an inverse one two half products combined,
-//   E[x] = sum_p C[2p][x] s[2p], O[x] = sum_p C[2p+1][x] s[2p+1],
-//   out[x] = E[x] + O[x], out[R-1-x] = E[x] - O[x]   (x < R/2):
-// half the matrix-core work of the dense form.  Between the passes the spectra
-// are kept in the order [even frequencies | odd frequencies] along each axis
-// (index p stands for frequency 2p below R/2 and 2(p - R/2) + 1 above), which
-// the scale and the inverse passes read consistently.  LDS holds the two half
-// bases Ce[p][x] = C[2p][x], Co[p][x] = C[2p+1][x] (x < R/2, pitch R/2 + 1).
-constexpr int kPencilsEO = 128;
-constexpr int kPQ = kPencilsEO + 1;
+// Fast form for R = 64 and 128.  The even/odd split of a line of R values (its
+// folded sums give the even frequencies by a DCT-II of length R/2, its folded
+// differences the odd ones by a DCT-IV of length R/2) is taken one level
+// further: each half is a fast transform of length R/2 on one thread's
+// registers (fastdct_gen.h: split-radix DFTs between twiddle steps, about ten
+// operations per value against R/2 multiply-adds of the dense product), so the
+// passes are bound by memory, not arithmetic.  The transforms are unnormalised
+// (cos(pi k (2x+1) / 2R) without s_k); the squared normalisations s_k^2 of the
+// three axes join the spectral scale in the pencil pass:
+//   C^T D C = Cu^T (S^2 D) Cu,  C = S Cu,  S = diag(s_k).
+// The two threads of a line sit in different waves, so each wave runs one of
+// the two transforms.  Spectra between the passes keep the order
+// [even frequencies | odd frequencies] along each axis: position p < R/2 holds
+// frequency 2p, position p >= R/2 frequency 2 (p - R/2) + 1.
+//
+//   plane fwd   a z-plane in LDS (pitch R + 1): transforms along x (rows, in
+//               LDS), then along y (columns, straight to HBM);
+//   pencil      128 consecutive (qy, qx) pencils of one system in LDS: forward
+//               z, scale by s^2 / (1 + lam mu)^2, inverse z (DCT-III of the
+//               even half, DCT-IV of the odd half), combined through LDS;
+//   plane inv   inverse along x, then along y, combined through LDS into the
+//               natural plane, stored (or, with Adam, driving an Adam step of
+//               the parameters at the same positions, float4 at a time).
+constexpr int kFT = 256;            // threads of a fast-transform block (4 waves)
+constexpr int kFP = 128;            // pencils per block
+constexpr int kFQ = kFP + 1;
 
-__device__ __forceinline__ void load_basis_eo(float *sh, const float *c, int R, int RH, int PH) {
-  for (int i = threadIdx.x; i < R * RH; i += kBig) {
-    const int k = i / RH, x = i % RH;
-    sh[(k & 1) * RH * PH + (k >> 1) * PH + x] = c[k * R + x];
-  }
+template <int H>
+__device__ __forceinline__ void fdct2(float (&v)[H]) {
+  if constexpr (H == 64) fdct::dct2_64(v); else fdct::dct2_32(v);
+}
+template <int H>
+__device__ __forceinline__ void fdct3(float (&v)[H]) {
+  if constexpr (H == 64) fdct::dct3_64(v); else fdct::dct3_32(v);
+}
+template <int H>
+__device__ __forceinline__ void fdct4(float (&v)[H]) {
+  if constexpr (H == 64) fdct::dct4_64(v); else fdct::dct4_32(v);
 }
 
-__device__ __forceinline__ float mu_perm(const float *mu, int p, int RH) {
-  return mu[p < RH ? 2 * p : 2 * (p - RH) + 1];
+// This thread's half (0: even frequencies, 1: odd; uniform per wave) and its
+// line among the block's 128 (plane kernels: plane pl of the block, line ln).
+struct FastLane {
+  int h, gl;
+};
+__device__ __forceinline__ FastLane fast_lane() {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  return {w & 1, (w >> 1) * 64 + (int)(threadIdx.x & 63)};
 }
 
-// acc[p] = sum_k A(k) B_p(k) over k < K (a multiple of 16) with
-//   A(k) = a0[k sa] (+ sga a1[-k sa] with FA),  B_p(k) = b0[p][k sb] (+ sgb b1[p][-k sb] with FB);
-// the NP tiles share A.
-template <int NP, bool FA, bool FB>
-__device__ __forceinline__ void fold_gemm(int K, const float *a0, const float *a1, int sa, float sga,
-                                          const float *const *b0, const float *const *b1, int sb,
-                                          float sgb, f32x16 (&acc)[NP]) {
-  const int h = (threadIdx.x >> 5) & 1;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) acc[p] = (f32x16){};
-#pragma unroll 1
-  for (int k0 = 0; k0 < K; k0 += 2 * kCh) {
-    float av[kCh], bv[NP][kCh];
-#pragma unroll
-    for (int c = 0; c < kCh; ++c) {
-      const int k = k0 + 2 * c + h;
-      av[c] = FA ? a0[k * sa] + sga * a1[-k * sa] : a0[k * sa];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) bv[p][c] = FB ? b0[p][k * sb] + sgb * b1[p][-k * sb] : b0[p][k * sb];
-    }
-#pragma unroll
-    for (int c = 0; c < kCh; ++c)
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-        acc[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[c], bv[p][c], acc[p], 0, 0, 0);
-  }
-}
-
-// e = sum_k ae[k sa] be[k sb], o = sum_k ao[k sa] bo[k sb] over k < K.
-__device__ __forceinline__ void eo_gemm(int K, const float *ae, const float *ao, int sa,
-                                        const float *be, const float *bo, int sb, f32x16 &e,
-                                        f32x16 &o) {
-  const int h = (threadIdx.x >> 5) & 1;
-  e = (f32x16){};
-  o = (f32x16){};
-#pragma unroll 1
-  for (int k0 = 0; k0 < K; k0 += 2 * kCh) {
-    float a[2][kCh], b[2][kCh];
-#pragma unroll
-    for (int c = 0; c < kCh; ++c) {
-      const int k = k0 + 2 * c + h;
-      a[0][c] = ae[k * sa];
-      b[0][c] = be[k * sb];
-      a[1][c] = ao[k * sa];
-      b[1][c] = bo[k * sb];
-    }
-#pragma unroll
-    for (int c = 0; c < kCh; ++c) {
-      e = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][c], b[0][c], e, 0, 0, 0);
-      o = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][c], b[1][c], o, 0, 0, 0);
-    }
-  }
-}
-
-// Forward x and y transforms of z-planes: natural (y, x) in, spectra (q, p) out.
-template <int NT>
-__global__ __launch_bounds__(kBig) void dct_plane_eo_fwd_kernel(FusedArgs a) {
-  constexpr int R = 32 * NT, RH = R / 2, P = R + 1, PH = RH + 1, NH = NT / 2;
-  constexpr int NP = NT == 4 ? 2 : 1;          // tiles per wave (one row band)
-  extern __shared__ float lds[];
-  float *sh = lds;                             // Ce, Co
-  float *sp = lds + 2 * RH * PH;               // plane, R x P
+// Block's planes (kFT / 2R of them) from HBM into LDS (pitch R + 1).
+template <int R>
+__device__ __forceinline__ void fast_load_planes(float *sp, const float *src, long long stack,
+                                                 long long off, long long plane0) {
+  constexpr int PPB = kFT / (2 * R), P = R + 1, G = PPB * R * R / (4 * kFT);
   constexpr long long R2 = (long long)R * R, R3 = R2 * R;
-  load_basis_eo(sh, a.c, R, RH, PH);
-  const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
-  const bool act = NT == 4 || w < 4;
-  const int band = w >> 1, ct0 = NT == 4 ? 2 * (w & 1) : (w & 1);
-  auto plane_base = [&](long long plane) {
+  float4 t[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int idx = 4 * ((int)threadIdx.x + k * kFT);
+    const long long plane = plane0 + idx / (R * R);
     const long long sys = plane / R, z = plane % R;
-    return (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
-  };
-  long long plane = blockIdx.x;
-  if (plane < a.planes) load_rows(sp, P, a.src + plane_base(plane), R, R, R * R);
-  __syncthreads();
-  for (; plane < a.planes; plane += gridDim.x) {
-    const long long base = plane_base(plane);
-    f32x16 acc[NP];
-    if (act) {
-      // along x: t[y][p] = sum_{x<RH} (in[y][x] +- in[y][R-1-x]) C[k(p)][x]
-      const float sg = ct0 < NH ? 1.f : -1.f;
-      const float *a0 = sp + (32 * band + col) * P;
-      const float *b0[NP];
+    const int o = idx % (R * R);
+    t[k] = *reinterpret_cast<const float4 *>(src + (sys / 3) * stack + off + (sys % 3) * R3 +
+                                             z * R2 + o);
+  }
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int pc = 32 * (ct0 + p) + col;
-        b0[p] = sh + (pc < RH ? 0 : RH * PH) + (pc % RH) * PH;     // C[k(pc)][x] along x
-      }
-      fold_gemm<NP, true, false>(RH, a0, a0 + R - 1, 1, sg, b0, b0, 1, 0.f, acc);
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int pc = 32 * (ct0 + p) + col;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) sp[(32 * band + trow(r)) * P + pc] = acc[p][r];
-      }
-    }
-    __syncthreads();
-    constexpr int kPre = R * R / kBig;
-    const long long next = plane + gridDim.x;
-    float pre[kPre];
-    if (next < a.planes) {
-      const float *in = a.src + plane_base(next);
-#pragma unroll
-      for (int e = 0; e < kPre; ++e) pre[e] = in[threadIdx.x + e * kBig];
-    }
-    if (act) {
-      // along y: out[q][p] = sum_{y<RH} C[k(q)][y] (t[y][p] +- t[R-1-y][p])
-      const float sg = band < NH ? 1.f : -1.f;
-      const int qr = 32 * band + col;
-      const float *a0 = sh + (qr < RH ? 0 : RH * PH) + (qr % RH) * PH;   // C[k(q)][y] along y
-      const float *b0[NP], *b1[NP];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int pc = 32 * (ct0 + p) + col;
-        b0[p] = sp + pc;
-        b1[p] = sp + (R - 1) * P + pc;
-      }
-      fold_gemm<NP, false, true>(RH, a0, a0, 1, 0.f, b0, b1, P, sg, acc);
-      float *out = a.dst + base;
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int pc = 32 * (ct0 + p) + col;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) out[(32 * band + trow(r)) * R + pc] = acc[p][r];
-      }
-    }
-    __syncthreads();
-    if (next < a.planes) {
-      float *pb = sp + (threadIdx.x / R) * P + threadIdx.x % R;   // kBig is a multiple of R
-#pragma unroll
-      for (int e = 0; e < kPre; ++e) pb[e * (kBig / R) * P] = pre[e];
-    }
-    __syncthreads();
+  for (int k = 0; k < G; ++k) {
+    const int idx = 4 * ((int)threadIdx.x + k * kFT);
+    const int pl = idx / (R * R), o = idx % (R * R);
+    float *d = sp + pl * R * P + (o / R) * P + o % R;
+    d[0] = t[k].x;
+    d[1] = t[k].y;
+    d[2] = t[k].z;
+    d[3] = t[k].w;
   }
 }
 
-// Inverse y and x transforms: spectra (q, p) in, natural (y, x) out.  With
-// ADAM the outputs are not stored: they drive an Adam step of the
-// parameters at the same positions instead: each thread loads its float4 groups of
-// parameters and first moments when the plane starts and of second moments
-// before the y product, so that the loads overlap the products, and the y
-// products reach the linear epilogue through LDS.
-template <int NT, bool ADAM>
-__global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a, AdamEpi ad) {
-  constexpr int R = 32 * NT, RH = R / 2, P = R + 1, PH = RH + 1, NH = NT / 2;
-  constexpr int kV = R * R / (4 * kBig);        // float4 groups per thread and plane
-  extern __shared__ float lds[];
-  float *sh = lds;
-  float *sp = lds + 2 * RH * PH;
+template <int R>
+__global__ __launch_bounds__(kFT) void fdct_plane_fwd_kernel(FusedArgs a) {
+  constexpr int H = R / 2, P = R + 1, PPB = kFT / (2 * R);
   constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  extern __shared__ float lds[];
+  const long long plane0 = (long long)blockIdx.x * PPB;
+  fast_load_planes<R>(lds, a.src, a.stack, a.off, plane0);
+  __syncthreads();
+  const FastLane fl = fast_lane();
+  const int pl = fl.gl / R, ln = fl.gl % R;
+  float *sp = lds + pl * R * P;
+  float v[H];
+  {   // along x: row ln
+    const float *row = sp + ln * P;
+    if (fl.h == 0) {
+#pragma unroll
+      for (int n = 0; n < H; ++n) v[n] = row[n] + row[R - 1 - n];
+      fdct2<H>(v);
+    } else {
+#pragma unroll
+      for (int n = 0; n < H; ++n) v[n] = row[n] - row[R - 1 - n];
+      fdct4<H>(v);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < H; ++k) sp[ln * P + fl.h * H + k] = v[k];
+  __syncthreads();
+  {   // along y: column ln
+    const float *col = sp + ln;
+    if (fl.h == 0) {
+#pragma unroll
+      for (int n = 0; n < H; ++n) v[n] = col[n * P] + col[(R - 1 - n) * P];
+      fdct2<H>(v);
+    } else {
+#pragma unroll
+      for (int n = 0; n < H; ++n) v[n] = col[n * P] - col[(R - 1 - n) * P];
+      fdct4<H>(v);
+    }
+    const long long plane = plane0 + pl, sys = plane / R, z = plane % R;
+    float *out = a.dst + (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2 + ln;
+#pragma unroll
+    for (int k = 0; k < H; ++k) out[(fl.h * H + k) * R] = v[k];
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kFT) void fdct_pencil_kernel(FusedArgs a) {
+  constexpr int H = R / 2, G = R * kFP / (4 * kFT);
+  constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  constexpr int groups = R * R / kFP;   // pencil groups per system
+  extern __shared__ float sq[];
+  float *smu = sq + R * kFQ;            // mu_f of the z frequencies
+  if (threadIdx.x < R) smu[threadIdx.x] = a.mu[threadIdx.x];
+  const long long sys = blockIdx.x / groups;
+  const int j0 = (blockIdx.x % groups) * kFP;
+  float *base = a.dst + (sys / 3) * a.stack + a.off + (sys % 3) * R3 + j0;
+  {
+    float4 t[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int idx = 4 * ((int)threadIdx.x + k * kFT);
+      t[k] = *reinterpret_cast<const float4 *>(base + (idx / kFP) * R2 + idx % kFP);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int idx = 4 * ((int)threadIdx.x + k * kFT);
+      float *d = sq + (idx / kFP) * kFQ + idx % kFP;
+      d[0] = t[k].x;
+      d[1] = t[k].y;
+      d[2] = t[k].z;
+      d[3] = t[k].w;
+    }
+  }
+  __syncthreads();
+  const FastLane fl = fast_lane();
+  const int j = fl.gl;
+  const float *col = sq + j;
+  float v[H];
+  if (fl.h == 0) {
+#pragma unroll
+    for (int n = 0; n < H; ++n) v[n] = col[n * kFQ] + col[(R - 1 - n) * kFQ];
+    fdct2<H>(v);
+  } else {
+#pragma unroll
+    for (int n = 0; n < H; ++n) v[n] = col[n * kFQ] - col[(R - 1 - n) * kFQ];
+    fdct4<H>(v);
+  }
+  {   // (S^2 D) at (qy, qx, qz): frequency 2p of position p < H, 2 (p - H) + 1 above
+    const int ln = j0 + j, qy = ln / R, qx = ln % R;
+    const int fy = qy < H ? 2 * qy : 2 * (qy - H) + 1, fx = qx < H ? 2 * qx : 2 * (qx - H) + 1;
+    const float s0 = 1.0f / R, s1 = 2.0f / R;
+    const float sxy = (fy ? s1 : s0) * (fx ? s1 : s0);
+    const float mxy = a.mu[fy] + a.mu[fx];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const int fz = 2 * k + fl.h;
+      const float d = 1.0f + a.lam * (mxy + smu[fz]);
+      v[k] *= sxy * (fz ? s1 : s0) / (d * d);
+    }
+  }
+  if (fl.h == 0) fdct3<H>(v); else fdct4<H>(v);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < H; ++k) sq[(fl.h * H + k) * kFQ + j] = v[k];
+  __syncthreads();
+  // out[z] = E[z] + O[z], out[R-1-z] = E[z] - O[z]  (z < H)
+  const float sg = fl.h ? -1.f : 1.f;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const float r = col[k * kFQ] + sg * col[(H + k) * kFQ];
+    base[(fl.h ? R - 1 - k : k) * R2 + j] = r;
+  }
+}
+
+template <int R, bool ADAM>
+__global__ __launch_bounds__(kFT) void fdct_plane_inv_kernel(FusedArgs a, AdamEpi ad) {
+  constexpr int H = R / 2, P = R + 1, PPB = kFT / (2 * R), G = PPB * R * R / (4 * kFT);
+  constexpr long long R2 = (long long)R * R, R3 = R2 * R;
+  extern __shared__ float lds[];
   float bc1 = 1.f, bc2 = 1.f;
   if constexpr (ADAM) {
     __shared__ float sbc[2];
@@ -664,247 +689,131 @@ __global__ __launch_bounds__(kBig) void dct_plane_eo_inv_kernel(FusedArgs a, Ada
     bc1 = sbc[0];
     bc2 = sbc[1];
   }
-  load_basis_eo(sh, a.c, R, RH, PH);
-  const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
-  const bool act = w < NT * NH;                // NT * NH = NH * NT items per phase
-  auto plane_base = [&](long long plane) {
-    const long long sys = plane / R, z = plane % R;
-    return (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
-  };
-  long long plane = blockIdx.x;
-  if (plane < a.planes) load_rows(sp, P, a.src + plane_base(plane), R, R, R * R);
+  const long long plane0 = (long long)blockIdx.x * PPB;
+  fast_load_planes<R>(lds, a.src, a.stack, a.off, plane0);
   __syncthreads();
-  for (; plane < a.planes; plane += gridDim.x) {
-    const long long base = plane_base(plane);
-    float4 th[ADAM ? kV : 1], mo[ADAM ? kV : 1], vo[ADAM ? kV : 1];
-    if constexpr (ADAM) {
+  const FastLane fl = fast_lane();
+  const int pl = fl.gl / R, ln = fl.gl % R;
+  float *sp = lds + pl * R * P;
+  float v[H];
+  {   // along x, spectral row ln: E (even half) or O (odd half) in place
+    float *row = sp + ln * P + fl.h * H;
 #pragma unroll
-      for (int k = 0; k < kV; ++k) {
-        const unsigned i = 4u * (threadIdx.x + k * kBig);
-        th[k] = *reinterpret_cast<const float4 *>(ad.th + base + i);
-        mo[k] = *reinterpret_cast<const float4 *>(ad.m + base + i);
-      }
-    }
-    f32x16 e, o;
-    // along x (item: spectral row band qb, spatial column tile xt < NH):
-    // t[q][x] = E + O, t[q][R-1-x] = E - O
-    const int qb = w / NH, xt = w % NH;
-    if (act) {
-      const float *arow = sp + (32 * qb + col) * P;
-      eo_gemm(RH, arow, arow + RH, 1, sh + 32 * xt + col, sh + RH * PH + 32 * xt + col, PH, e, o);
-    }
-    __syncthreads();
-    if (act) {
-      const int x = 32 * xt + col;
+    for (int k = 0; k < H; ++k) v[k] = row[k];
+    if (fl.h == 0) fdct3<H>(v); else fdct4<H>(v);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int q = 32 * qb + trow(r);
-        sp[q * P + x] = e[r] + o[r];
-        sp[q * P + R - 1 - x] = e[r] - o[r];
-      }
-    }
-    __syncthreads();
-    constexpr int kPre = R * R / kBig;
-    const long long next = plane + gridDim.x;
-    float pre[kPre];
-    auto prefetch = [&]() {
-      if (next < a.planes) {
-        const float *in = a.src + plane_base(next);
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) pre[k] = in[threadIdx.x + k * kBig];
-      }
-    };
-    if constexpr (!ADAM) prefetch();           // (with ADAM after the y product: registers)
-    if constexpr (ADAM) {                      // second moments: one product ahead
-#pragma unroll
-      for (int k = 0; k < kV; ++k)
-        vo[k] = *reinterpret_cast<const float4 *>(ad.v + base + 4u * (threadIdx.x + k * kBig));
-    }
-    // along y (item: spatial row band yb < NH, column tile xc):
-    // out[y][x] = E + O, out[R-1-y][x] = E - O
-    const int yb = w / NT, xc = w % NT;
-    if (act) {
-      const int y = 32 * yb + col;
-      eo_gemm(RH, sh + y, sh + RH * PH + y, PH, sp + 32 * xc + col, sp + RH * P + 32 * xc + col, P,
-              e, o);
-    }
-    if constexpr (ADAM) {
-      prefetch();
-      __syncthreads();                         // every product has read sp
-      if (act) {
-        // rows 32 yb + trow(r) and R - 1 - (32 yb + trow(r)), trow(r) =
-        // 4 (lane / 32) + c_r with c_r = 8 (r / 4) + r % 4 in 0..27: two lane
-        // bases and compile-time offsets
-        const int h4 = 4 * ((threadIdx.x & 63) >> 5);
-        float *top = sp + (32 * yb + h4) * P + 32 * xc + col;
-        float *bot = sp + (R - 1 - 32 * yb - h4 - 27) * P + 32 * xc + col;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int cr = 8 * (r >> 2) + (r & 3);
-          top[cr * P] = e[r] + o[r];
-          bot[(27 - cr) * P] = e[r] - o[r];
-        }
-      }
-      __syncthreads();
-      // thread's group k starts at row (4 t) / R + k (4 kBig / R), column (4 t) % R
-      const float *gb = sp + (4 * threadIdx.x / R) * P + (4 * threadIdx.x) % R;
-#pragma unroll
-      for (int k = 0; k < kV; ++k) {
-        const unsigned i = 4u * (threadIdx.x + k * kBig);
-        const float *gr = gb + k * (4 * kBig / R) * P;
-        const float4 gv = make_float4(gr[0], gr[1], gr[2], gr[3]);
-        th[k].x = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.x, mo[k].x, vo[k].x, th[k].x);
-        th[k].y = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.y, mo[k].y, vo[k].y, th[k].y);
-        th[k].z = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.z, mo[k].z, vo[k].z, th[k].z);
-        th[k].w = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, gv.w, mo[k].w, vo[k].w, th[k].w);
-        *reinterpret_cast<float4 *>(ad.th + base + i) = th[k];
-        *reinterpret_cast<float4 *>(ad.m + base + i) = mo[k];
-        *reinterpret_cast<float4 *>(ad.v + base + i) = vo[k];
-      }
-    } else if (act) {
-      const int x = 32 * xc + col;
-      float *out = a.dst + base;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int yy = 32 * yb + trow(r);
-        out[yy * R + x] = e[r] + o[r];
-        out[(R - 1 - yy) * R + x] = e[r] - o[r];
-      }
-    }
-    __syncthreads();
-    if (next < a.planes) {
-      float *pb = sp + (threadIdx.x / R) * P + threadIdx.x % R;   // kBig is a multiple of R
-#pragma unroll
-      for (int k = 0; k < kPre; ++k) pb[k * (kBig / R) * P] = pre[k];
-    }
-    __syncthreads();
+    for (int k = 0; k < H; ++k) row[k] = v[k];
   }
-}
-
-// Forward z, spectral scale, inverse z for groups of 128 (qy, qx) lines of
-// one system, in place on dst (spectral order in y and x, natural z).
-template <int NT>
-__global__ __launch_bounds__(kBig) void dct_pencil_eo_kernel(FusedArgs a) {
-  constexpr int R = 32 * NT, RH = R / 2, PH = RH + 1, NH = NT / 2, JT = kPencilsEO / 32;
-  constexpr int NP = NT == 4 ? 2 : 1;
-  extern __shared__ float lds[];
-  float *sh = lds;
-  float *sq = lds + 2 * RH * PH;               // R x kPQ
-  constexpr long long R2 = (long long)R * R, R3 = R2 * R;
-  constexpr long long groups = R2 / kPencilsEO;   // per system
-  const long long total = a.planes / R * groups;
-  load_basis_eo(sh, a.c, R, RH, PH);
-  const int w = threadIdx.x >> 6, col = threadIdx.x & 31;
-  // forward tiles: row band fb, column tiles fc0 .. fc0 + NP - 1
-  const int fb = NT == 4 ? (w >> 1) : (w >> 2), fc0 = NT == 4 ? 2 * (w & 1) : (w & 3);
-  // inverse items: spatial row band ib < NH, column tile ic
-  const int ib = w / JT, ic = w % JT;
-  const bool iact = w < NH * JT;
-  auto group_ptr = [&](long long g) {
-    const long long sys = g / groups;
-    return a.dst + (sys / 3) * a.stack + a.off + (sys % 3) * R3 + (g % groups) * kPencilsEO;
+  __syncthreads();
+  {   // along y, natural column ln: t[q][x] = E_q[x] + O_q[x], t[q][R-1-x] = E_q[x] - O_q[x]
+    const int xx = ln < H ? ln : R - 1 - ln;
+    const float sg = ln < H ? 1.f : -1.f;
+    const float *col = sp + fl.h * H * P + xx;
+#pragma unroll
+    for (int k = 0; k < H; ++k) v[k] = col[k * P] + sg * col[k * P + H];
+    if (fl.h == 0) fdct3<H>(v); else fdct4<H>(v);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < H; ++k) sp[(fl.h * H + k) * P + ln] = v[k];
+  __syncthreads();
+  // natural (y, x): E_y[y] + O_y[y] for y < H, E_y[R-1-y] - O_y[R-1-y] above;
+  // float4 group k of this thread starts at 4 (threadIdx.x + k kFT)
+  auto grad4 = [&](int k, long long &at) {
+    const int idx = 4 * ((int)threadIdx.x + k * kFT);
+    const int p = idx / (R * R), o = idx % (R * R), y = o / R, x = o % R;
+    const int yy = y < H ? y : R - 1 - y;
+    const float sg = y < H ? 1.f : -1.f;
+    const float *e = lds + p * R * P + yy * P + x, *od = e + H * P;
+    const long long plane = plane0 + p, sys = plane / R, z = plane % R;
+    at = (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2 + o;
+    return make_float4(e[0] + sg * od[0], e[1] + sg * od[1], e[2] + sg * od[2], e[3] + sg * od[3]);
   };
-  constexpr int kPre = R * kPencilsEO / kBig;
-  float pre[kPre];
-  auto fetch = [&](long long g) {
-    const float *in = group_ptr(g);
+  if constexpr (ADAM) {
+    // batches of groups: every parameter and moment load of a batch in flight
+    // before its first use (the arrays do not overlap)
+    float *__restrict__ pth = ad.th;
+    float *__restrict__ pm = ad.m;
+    float *__restrict__ pv = ad.v;
+    constexpr int GB = G < 8 ? G : 8;
 #pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-      const int i = threadIdx.x + e * kBig;
-      pre[e] = in[(i / kPencilsEO) * R2 + i % kPencilsEO];
-    }
-  };
-  if (blockIdx.x < total) fetch(blockIdx.x);
-  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
-    const long long line0 = (g % groups) * kPencilsEO;
-    float *d0 = group_ptr(g);
-    __syncthreads();               // the previous group's reads of sq are done
+    for (int k0 = 0; k0 < G; k0 += GB) {
+      float4 th[GB], mo[GB], vo[GB];
 #pragma unroll
-    for (int e = 0; e < kPre; ++e) {
-      const int i = threadIdx.x + e * kBig;
-      sq[(i / kPencilsEO) * kPQ + i % kPencilsEO] = pre[e];
-    }
-    __syncthreads();
-    if (g + gridDim.x < total) fetch(g + gridDim.x);   // in flight during this group
-    // forward z: F[qz][j] = sum_{z<RH} C[k(qz)][z] (s[z][j] +- s[R-1-z][j])
-    f32x16 acc[NP];
-    {
-      const float sg = fb < NH ? 1.f : -1.f;
-      const int qr = 32 * fb + col;
-      const float *a0 = sh + (qr < RH ? 0 : RH * PH) + (qr % RH) * PH;
-      const float *b0[NP], *b1[NP];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int j = 32 * (fc0 + p) + col;
-        b0[p] = sq + j;
-        b1[p] = sq + (R - 1) * kPQ + j;
+      for (int k = 0; k < GB; ++k) {
+        const int idx = 4 * ((int)threadIdx.x + (k0 + k) * kFT);
+        const int p = idx / (R * R), o = idx % (R * R);
+        const long long plane = plane0 + p, sys = plane / R, z = plane % R;
+        const long long at = (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2 + o;
+        th[k] = *reinterpret_cast<const float4 *>(pth + at);
+        mo[k] = *reinterpret_cast<const float4 *>(pm + at);
+        vo[k] = *reinterpret_cast<const float4 *>(pv + at);
       }
-      fold_gemm<NP, false, true>(RH, a0, a0, 1, 0.f, b0, b1, kPQ, sg, acc);
-    }
-    __syncthreads();
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const int j = 32 * (fc0 + p) + col;
-      const int ln = (int)line0 + j;                 // qy * R + qx
-      const float sxy = mu_perm(a.mu, ln / R, RH) + mu_perm(a.mu, ln % R, RH);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int qz = 32 * fb + trow(r);
-        const float d = 1.0f + a.lam * (sxy + mu_perm(a.mu, qz, RH));
-        sq[qz * kPQ + j] = acc[p][r] / (d * d);
+      for (int k = 0; k < GB; ++k) {
+        long long at;
+        const float4 g = grad4(k0 + k, at);
+        th[k].x = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.x, mo[k].x, vo[k].x, th[k].x);
+        th[k].y = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.y, mo[k].y, vo[k].y, th[k].y);
+        th[k].z = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.z, mo[k].z, vo[k].z, th[k].z);
+        th[k].w = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.w, mo[k].w, vo[k].w, th[k].w);
+        *reinterpret_cast<float4 *>(pth + at) = th[k];
+        *reinterpret_cast<float4 *>(pm + at) = mo[k];
+        *reinterpret_cast<float4 *>(pv + at) = vo[k];
       }
     }
-    __syncthreads();
-    // inverse z: out[z] = E + O, out[R-1-z] = E - O
-    if (iact) {
-      f32x16 e, o;
-      const int z = 32 * ib + col, j = 32 * ic + col;
-      eo_gemm(RH, sh + z, sh + RH * PH + z, PH, sq + j, sq + RH * kPQ + j, kPQ, e, o);
-      const int r2 = (int)R2;
+  } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int zz = 32 * ib + trow(r);
-        d0[zz * r2 + j] = e[r] + o[r];
-        d0[(R - 1 - zz) * r2 + j] = e[r] - o[r];
-      }
+    for (int k = 0; k < G; ++k) {
+      long long at;
+      const float4 g = grad4(k, at);
+      *reinterpret_cast<float4 *>(a.dst + at) = g;
     }
   }
 }
 
-template <int NT>
-pdg_status eo_level(const FusedArgs &f0, const AdamEpi *ad, hipStream_t st) {
-  constexpr int R = 32 * NT, RH = R / 2;
-  const size_t plane = (size_t)(2 * RH * (RH + 1) + R * (R + 1)) * sizeof(float);
-  const size_t pencil = (size_t)(2 * RH * (RH + 1) + R * kPQ) * sizeof(float);
+template <int R>
+pdg_status fast_level(const FusedArgs &f0, const AdamEpi *ad, hipStream_t st) {
+  constexpr int PPB = kFT / (2 * R);
+  const size_t plane = (size_t)PPB * R * (R + 1) * sizeof(float);
+  const size_t pencil = (size_t)(R * kFQ + R) * sizeof(float);
   static bool attrs = false;
   if (!attrs) {
-    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_fwd_kernel<NT>,
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_plane_fwd_kernel<R>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
-    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_inv_kernel<NT, false>,
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_plane_inv_kernel<R, false>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
-    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_eo_inv_kernel<NT, true>,
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_plane_inv_kernel<R, true>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
-    PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_pencil_eo_kernel<NT>,
+    PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_pencil_kernel<R>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil));
     attrs = true;
   }
   FusedArgs f = f0;
-  const long long groups = f.planes / R * ((long long)R * R / kPencilsEO);
-  const unsigned gp = (unsigned)(f.planes < 2048 ? f.planes : 2048);
-  const unsigned gg = (unsigned)(groups < 2048 ? groups : 2048);
-  dct_plane_eo_fwd_kernel<NT><<<gp, kBig, plane, st>>>(f);
-  PDG_TRY(launched("dct_plane_eo_fwd"));
+  if (f.planes % R != 0 || f.planes % PPB != 0) {   // planes = batch * 3 * R
+    set_error("fast DCT: %lld planes is not a whole number of systems and blocks", f.planes);
+    return PDG_EINVAL;
+  }
+  const long long pblocks = f.planes / PPB;
+  const long long gblocks = f.planes / R * ((long long)R * R / kFP);
+  if (pblocks > 0x7fffffffLL || gblocks > 0x7fffffffLL) {
+    set_error("fast DCT: batch too large (%lld planes)", f.planes);
+    return PDG_EINVAL;
+  }
+  if (pblocks == 0) return PDG_OK;
+  fdct_plane_fwd_kernel<R><<<(unsigned)pblocks, kFT, plane, st>>>(f);
+  PDG_TRY(launched("fdct_plane_fwd"));
   f.src = f.dst;
-  dct_pencil_eo_kernel<NT><<<gg, kBig, pencil, st>>>(f);
-  PDG_TRY(launched("dct_pencil_eo"));
+  fdct_pencil_kernel<R><<<(unsigned)gblocks, kFT, pencil, st>>>(f);
+  PDG_TRY(launched("fdct_pencil"));
   if (ad) {
-    dct_plane_eo_inv_kernel<NT, true><<<gp, kBig, plane, st>>>(f, *ad);
+    fdct_plane_inv_kernel<R, true><<<(unsigned)pblocks, kFT, plane, st>>>(f, *ad);
   } else {
     AdamEpi none;
     memset(&none, 0, sizeof none);
-    dct_plane_eo_inv_kernel<NT, false><<<gp, kBig, plane, st>>>(f, none);
+    fdct_plane_inv_kernel<R, false><<<(unsigned)pblocks, kFT, plane, st>>>(f, none);
   }
-  return launched("dct_plane_eo_inv");
+  return launched("fdct_plane_inv");
 }
 
 int padded(int R) { return 32 * ((R + 31) / 32); }
@@ -1044,7 +953,9 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       f.mu = mu;
       f.R = R;
       f.lam = lam[l];
-      if (R == 128 || R == 64) {
+      // fast form: float4 accesses need the level and transition offsets
+      // to be multiples of 4 floats (else the generic fused passes below)
+      if ((R == 128 || R == 64) && g.size % 4 == 0 && g.off[l] % 4 == 0) {
         AdamEpi ad;
         if (adam) {
           ad.th = adam->th;
@@ -1059,9 +970,9 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
           if (fused) *fused |= 1u << l;
         }
         if (R == 128)
-          PDG_TRY(eo_level<4>(f, adam ? &ad : nullptr, st));
+          PDG_TRY(fast_level<128>(f, adam ? &ad : nullptr, st));
         else
-          PDG_TRY(eo_level<2>(f, adam ? &ad : nullptr, st));
+          PDG_TRY(fast_level<64>(f, adam ? &ad : nullptr, st));
         continue;
       }
       switch ((R + 31) / 32) {
