@@ -242,7 +242,8 @@ def emit(kind, M):
         "dct3": f"v[n] <- sum_k v[k] cos(pi (2n+1) k / {2 * M})",
         "dct4": f"v[k] <- sum_n v[n] cos(pi (2n+1) (2k+1) / {4 * M})",
     }[kind]
-    lines = [f"// {kind.upper().replace('DCT', 'DCT-')} of length {M}, unnormalised: {head}"
+    name = {"dct2": "DCT-II", "dct3": "DCT-III", "dct4": "DCT-IV"}[kind]
+    lines = [f"// {name} of length {M}, unnormalised: {head}"
              f" ({B.ops} operations)",
              f"__device__ __forceinline__ void {kind}_{M}(float (&v)[{M}]) {{"]
     lines += [f"  const float i{n} = v[{n}];" for n in range(M)]
@@ -252,8 +253,7 @@ def emit(kind, M):
     return "\n".join(lines)
 
 
-def main():
-    check()
+def render() -> str:
     body = [
         "// Generated by gen_fastdct.py from its factorisations; do not edit.",
         "// Fast unnormalised DCT-II, DCT-III and DCT-IV of one thread's registers",
@@ -268,8 +268,13 @@ def main():
         for kind in KINDS:
             body += [emit(kind, M), ""]
     body += ["}  // namespace fdct", "}  // namespace pdg", ""]
+    return "\n".join(body)
+
+
+def main():
+    check()
     with open(OUT, "w") as f:
-        f.write("\n".join(body))
+        f.write(render())
     print("wrote", OUT)
 
 
