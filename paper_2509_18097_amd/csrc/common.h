@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "pdg.h"
 
 namespace pdg {
@@ -76,6 +78,18 @@ __device__ __forceinline__ float corner_weight(int k, float fx, float fy, float 
 inline unsigned div_up(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One-time set-up per device (kernel attributes such as the dynamic LDS limit
+// are set per device): done(d) after mark(d); devices beyond the table repeat
+// the set-up on every call.  Instances are function-local statics.
+struct PerDevice {
+  static constexpr int kDevices = 64;
+  std::atomic<bool> f[kDevices];
+  bool done(int d) const { return d >= 0 && d < kDevices && f[d].load(std::memory_order_acquire); }
+  void mark(int d) {
+    if (d >= 0 && d < kDevices) f[d].store(true, std::memory_order_release);
+  }
+};
 
 // Workgroups are dealt to the eight XCDs (each with its own L2) in turn by
 // linear id.  job_block maps workgroup lin of a grid of job_grid(njobs, nb)

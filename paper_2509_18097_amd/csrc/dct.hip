@@ -777,8 +777,10 @@ pdg_status fast_level(const FusedArgs &f0, const AdamEpi *ad, hipStream_t st) {
   constexpr int PPB = kFT / (2 * R);
   const size_t plane = (size_t)PPB * R * (R + 1) * sizeof(float);
   const size_t pencil = (size_t)(R * kFQ + R) * sizeof(float);
-  static bool attrs = false;
-  if (!attrs) {
+  static PerDevice attrs;
+  int dev = 0;
+  PDG_TRY_HIP(hipGetDevice(&dev));
+  if (!attrs.done(dev)) {
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_plane_fwd_kernel<R>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_plane_inv_kernel<R, false>,
@@ -787,7 +789,7 @@ pdg_status fast_level(const FusedArgs &f0, const AdamEpi *ad, hipStream_t st) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)plane));
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)fdct_pencil_kernel<R>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil));
-    attrs = true;
+    attrs.mark(dev);
   }
   FusedArgs f = f0;
   if (f.planes % R != 0 || f.planes % PPB != 0) {   // planes = batch * 3 * R
@@ -822,15 +824,17 @@ size_t pencil_lds(int R) { return (size_t)(padded(R) * (padded(R) + 1) + padded(
 
 template <int NT, bool FULL>
 pdg_status fused_level(const FusedArgs &f0, hipStream_t st) {
-  static bool attrs = false;
-  if (!attrs) {
+  static PerDevice attrs;
+  int dev = 0;
+  PDG_TRY_HIP(hipGetDevice(&dev));
+  if (!attrs.done(dev)) {
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_plane_kernel<NT, FULL>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)plane_lds(32 * NT)));
     PDG_TRY_HIP(hipFuncSetAttribute((const void *)dct_pencil_kernel<NT, FULL>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)pencil_lds(32 * NT)));
-    attrs = true;
+    attrs.mark(dev);
   }
   FusedArgs f = f0;
   const int R = f.R;
@@ -953,9 +957,13 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       f.mu = mu;
       f.R = R;
       f.lam = lam[l];
-      // fast form: float4 accesses need the level and transition offsets
-      // to be multiples of 4 floats (else the generic fused passes below)
-      if ((R == 128 || R == 64) && g.size % 4 == 0 && g.off[l] % 4 == 0) {
+      // fast form: its float4 accesses need 16-byte aligned buffers and level
+      // and transition offsets that are multiples of 4 floats (else the
+      // generic fused passes below, and Adam in its own stage)
+      auto al16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
+      const bool al = g.size % 4 == 0 && g.off[l] % 4 == 0 && al16(src) && al16(data) &&
+                      (!adam || (al16(adam->th) && al16(adam->m) && al16(adam->v)));
+      if ((R == 128 || R == 64) && al) {
         AdamEpi ad;
         if (adam) {
           ad.th = adam->th;

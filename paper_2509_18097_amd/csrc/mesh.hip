@@ -520,12 +520,14 @@ pdg_status mesh_plan_apply(const MeshPlan &p, const float *g, float *out, hipStr
   const int steps = p.terms - 1;              // v_1 .. v_{terms-1}
   if (p.npart > 0) {
     const size_t lds = (size_t)2 * 3 * p.lmax * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
+    static PerDevice attr;
+    int dev = 0;
+    PDG_TRY_HIP(hipGetDevice(&dev));
+    if (!attr.done(dev)) {
       PDG_TRY_HIP(hipFuncSetAttribute((const void *)mesh_block_kernel,
                                       hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)(2 * 3 * kMeshLocalMax * sizeof(double))));
-      attr = true;
+      attr.mark(dev);
     }
     // (cur, prev) in vec[0], vec[1]; the launch writes vec[2], vec[3]; swap
     const double *cur = w.vec[0], *prev = w.vec[1];

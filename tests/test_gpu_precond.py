@@ -90,3 +90,27 @@ def test_invariants_on_gpu(method):
     # lambda = 0 leaves the gradient untouched
     out = host(L.precondition(dev(g), res, [0.0, 0.0], method=method))
     assert np.array_equal(out, g)
+
+
+def test_dct_fast_levels_on_misaligned_and_unaligned_layouts():
+    """The 64^3 and 128^3 levels' fast passes read and write float4; a buffer
+    that is not 16-byte aligned (a view one float into an allocation) or a level
+    offset that is not a multiple of 4 floats (a 3^3 level before it) takes the
+    generic passes, with the same result."""
+    require_gpu()
+    import torch
+    for res in ((64,), (3, 64)):
+        rng = np.random.default_rng(11 + len(res))
+        g = rng.normal(size=L.grid_size(res)).astype(np.float32)
+        lam = _lams(len(res))
+        ref = P.apply_levels(g, res, lam)
+        aligned = host(L.precondition(dev(g), res, lam, method="dct"))
+        buf = torch.zeros(g.size + 1, dtype=torch.float32, device="cuda")
+        buf[1:] = dev(g)
+        shifted = host(L.precondition(buf[1:], res, lam, method="dct"))
+        for out, what in ((aligned, "aligned"), (shifted, "shifted")):
+            off = 0
+            for r in res:
+                sl = slice(off, off + 3 * r ** 3)
+                assert_rel(out[sl], ref[sl], 1e-5, f"{what} res={res} R={r}")
+                off += 3 * r ** 3
