@@ -413,7 +413,8 @@ pdg_status pdg_problem_create(const pdg_problem_desc *pd, hipStream_t stream, pd
  * points only).
  * With use_graph != 0 the step is replayed from a HIP graph captured on the
  * first call for this stream.  With the DCT preconditioner the last inverse
- * pass of each 64^3 and 128^3 level applies Adam to the values it computes
+ * pass of each level of R = 16, 32, 64 or 128 (with the parameter, moment and
+ * gradient buffers 16-byte aligned) applies Adam to the values it computes
  * (same arithmetic as the Adam stage, so the same parameters bit for bit)
  * and does not store them: after pdg_step those levels of PDG_BUF_PGRAD are
  * not the preconditioned gradient (pdg_step_stage(PDG_STAGE_PRECOND) fills

@@ -8,7 +8,7 @@
 //     (I + lam L)^-2 = (C x C x C)^T diag((1 + lam (mu_i + mu_j + mu_k))^-2) (C x C x C).
 // The step applies C along x, y and z, scales, and applies C^T along z, y, x.
 // Three forms:
-//   R = 64, 128 (the finest levels, nearly all of the work): three passes over
+//   R = 16, 32, 64, 128 (the step's levels): three passes over
 //     HBM (x and y on a z-plane held in LDS; forward z, scale and inverse z on
 //     128 z-pencils held in LDS; inverse y and x on a plane), each line
 //     transformed by fast factorised transforms on one thread's registers, so
@@ -484,10 +484,10 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Fast form for R = 64 and 128.  The even/odd split of a line of R values (its
-// folded sums give the even frequencies by a DCT-II of length R/2, its folded
-// differences the odd ones by a DCT-IV of length R/2) is taken one level
-// further: each half is a fast transform of length R/2 on one thread's
+// Fast form for R = 16, 32, 64 and 128.  The even/odd split of a line of R
+// values (its folded sums give the even frequencies by a DCT-II of length R/2,
+// its folded differences the odd ones by a DCT-IV of length R/2) is taken one
+// level further: each half is a fast transform of length R/2 on one thread's
 // registers (fastdct_gen.h: split-radix DFTs between twiddle steps, about ten
 // operations per value against R/2 multiply-adds of the dense product), so the
 // passes are bound by memory, not arithmetic.  The transforms are unnormalised
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
 // three axes join the spectral scale in the pencil pass:
 //   C^T D C = Cu^T (S^2 D) Cu,  C = S Cu,  S = diag(s_k).
 // The two threads of a line sit in different waves, so each wave runs one of
-// the two transforms.  Spectra between the passes keep the order
+// the two transforms; a block holds 256 / 2R z-planes (one for R = 128).  Spectra between the passes keep the order
 // [even frequencies | odd frequencies] along each axis: position p < R/2 holds
 // frequency 2p, position p >= R/2 frequency 2 (p - R/2) + 1.
 //
@@ -513,15 +513,24 @@ constexpr int kFQ = kFP + 1;
 
 template <int H>
 __device__ __forceinline__ void fdct2(float (&v)[H]) {
-  if constexpr (H == 64) fdct::dct2_64(v); else fdct::dct2_32(v);
+  if constexpr (H == 64) fdct::dct2_64(v);
+  else if constexpr (H == 32) fdct::dct2_32(v);
+  else if constexpr (H == 16) fdct::dct2_16(v);
+  else fdct::dct2_8(v);
 }
 template <int H>
 __device__ __forceinline__ void fdct3(float (&v)[H]) {
-  if constexpr (H == 64) fdct::dct3_64(v); else fdct::dct3_32(v);
+  if constexpr (H == 64) fdct::dct3_64(v);
+  else if constexpr (H == 32) fdct::dct3_32(v);
+  else if constexpr (H == 16) fdct::dct3_16(v);
+  else fdct::dct3_8(v);
 }
 template <int H>
 __device__ __forceinline__ void fdct4(float (&v)[H]) {
-  if constexpr (H == 64) fdct::dct4_64(v); else fdct::dct4_32(v);
+  if constexpr (H == 64) fdct::dct4_64(v);
+  else if constexpr (H == 32) fdct::dct4_32(v);
+  else if constexpr (H == 16) fdct::dct4_16(v);
+  else fdct::dct4_8(v);
 }
 
 // This thread's half (0: even frequencies, 1: odd; uniform per wave) and its
@@ -963,7 +972,7 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       auto al16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
       const bool al = g.size % 4 == 0 && g.off[l] % 4 == 0 && al16(src) && al16(data) &&
                       (!adam || (al16(adam->th) && al16(adam->m) && al16(adam->v)));
-      if ((R == 128 || R == 64) && al) {
+      if ((R == 128 || R == 64 || R == 32 || R == 16) && al) {
         AdamEpi ad;
         if (adam) {
           ad.th = adam->th;
@@ -977,10 +986,12 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
           ad.step_host = adam->step_host;
           if (fused) *fused |= 1u << l;
         }
-        if (R == 128)
-          PDG_TRY(fast_level<128>(f, adam ? &ad : nullptr, st));
-        else
-          PDG_TRY(fast_level<64>(f, adam ? &ad : nullptr, st));
+        switch (R) {
+          case 128: PDG_TRY(fast_level<128>(f, adam ? &ad : nullptr, st)); break;
+          case 64: PDG_TRY(fast_level<64>(f, adam ? &ad : nullptr, st)); break;
+          case 32: PDG_TRY(fast_level<32>(f, adam ? &ad : nullptr, st)); break;
+          default: PDG_TRY(fast_level<16>(f, adam ? &ad : nullptr, st)); break;
+        }
         continue;
       }
       switch ((R + 31) / 32) {

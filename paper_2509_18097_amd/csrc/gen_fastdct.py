@@ -1,6 +1,6 @@
 """Writes fastdct_gen.h: straight-line fast DCT-II, DCT-III and DCT-IV of
-lengths 32 and 64 on one thread's registers, for the separable preconditioner
-of Sec. 3.2 (Eq. 3) at R = 64 and 128.
+lengths 8, 16, 32 and 64 on one thread's registers, for the separable
+preconditioner of Sec. 3.2 (Eq. 3) at R = 16, 32, 64 and 128.
 
     python paper_2509_18097_amd/csrc/gen_fastdct.py
 
@@ -30,7 +30,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "fastdct_gen.h")
-SIZES = (32, 64)
+SIZES = (8, 16, 32, 64)
 
 
 class Num:
@@ -257,7 +257,7 @@ def render() -> str:
     body = [
         "// Generated by gen_fastdct.py from its factorisations; do not edit.",
         "// Fast unnormalised DCT-II, DCT-III and DCT-IV of one thread's registers",
-        "// (lengths 32 and 64), each checked against its dense definition.",
+        "// (lengths 8, 16, 32 and 64), each checked against its dense definition.",
         "#pragma once",
         "",
         "namespace pdg {",

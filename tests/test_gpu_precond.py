@@ -93,7 +93,7 @@ def test_invariants_on_gpu(method):
 
 
 def test_dct_fast_levels_on_misaligned_and_unaligned_layouts():
-    """The 64^3 and 128^3 levels' fast passes read and write float4; a buffer
+    """The fast passes (R = 16, 32, 64, 128) read and write float4; a buffer
     that is not 16-byte aligned (a view one float into an allocation) or a level
     offset that is not a multiple of 4 floats (a 3^3 level before it) takes the
     generic passes, with the same result."""

@@ -170,14 +170,14 @@ def test_graph_replay_equals_eager_and_is_deterministic():
 
 
 def test_fused_precondition_adam_equals_stages():
-    """A full step lets the last inverse-DCT pass of the 64^3 and 128^3 levels
-    apply Adam (Sec. 3.6) itself; the stages enqueued one at a time run Adam
+    """A full step lets the last inverse-DCT pass of the 16^3 .. 128^3 levels
+    apply Adam (Sec. 3.6) itself (the 8^3 level runs Adam in its own stage); the stages enqueued one at a time run Adam
     separately; the full step is also replayed as a captured graph.  All give
     bitwise the same gradient, parameters and moments, also on a second
     iteration with non-zero moments."""
     require_gpu()
     seq = synth.deforming_sequence(seed=6, frames=3, n=4000, subdiv=3)
-    res = (8, 64, 128)
+    res = (8, 16, 32, 64, 128)
     th = _theta0(2, res, 7, std=0.001)
     probs = [Problem(dev(seq.points), res, template=dev(seq.template), edges=dev(seq.edges),
                      params=dev(th), chamfer_mode="bf16", precond="dct") for _ in range(3)]
