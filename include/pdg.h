@@ -18,7 +18,8 @@
  *   -1 + (2i+1)/R) and sampling clamps to the hull of the cell centres.
  * - Every call validates its arguments on the host before enqueuing anything,
  *   enqueues its work on `stream` and returns without waiting (asynchronous),
- *   except pdg_problem_create, which waits (see there).
+ *   except pdg_problem_create, pdg_mesh_plan_create and pdg_mesh_precondition,
+ *   which build host-side tables and wait (see there).
  *   Argument errors return PDG_EINVAL and enqueue nothing.  A HIP launch error
  *   returns PDG_EHIP.  A device fault shows up as PDG_EHIP on a later call or
  *   synchronisation.  pdg_last_error() returns a thread-local message for the
