@@ -46,7 +46,7 @@ PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # with the given prefix; reported only while the source is unchanged.
 PMC_TRAFFIC = {
     "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "7180d50d122cc34a",
-                         (2 * 239547.00 + 123711.54) * 1024),
+                         (2 * 237366.80 + 122467.96) * 1024),
 }
 
 
@@ -231,8 +231,8 @@ def dct_stage_bytes(prob):
     """Algorithmic HBM bytes of one DCT preconditioner stage: three passes per
     level of R <= 128 (forward plane, pencil, inverse plane), each reading and
     writing every value once (24 B per grid value), six for R > 128 (48 B);
-    R = 1 levels are skipped.  The R = 64 and 128 levels (nearly all of the
-    values) use fast transforms and are bound by these bytes."""
+    R = 1 levels are skipped.  The R = 16, 32, 64 and 128 levels use fast
+    transforms and are bound by these bytes."""
     T = prob.T
     return sum((24 if r <= 128 else 48) * T * prob.channels * r ** 3
                for r in prob.res if r > 1)
@@ -282,7 +282,7 @@ def roofline(prob, stages, chamfer, precond):
         pre = {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(a / HBM_PEAK_GBS, 4), "traffic": None,
                "kernel": "DCT stage: plane, pencil, plane kernels per level (fast transforms "
-                         "at R = 64, 128)", "bytes_per_stage": b, "stage_ms": round(pre_ms, 4)}
+                         "at R = 16, 32, 64, 128)", "bytes_per_stage": b, "stage_ms": round(pre_ms, 4)}
     else:
         b = cg_bytes(prob)
         a = b / (pre_ms * 1e-3) / 1e9
