@@ -5,11 +5,14 @@
 // order by one thread (no floating-point atomics anywhere).
 //
 // Per 8-bit digit pass:
-//   hist    -- per 2048-entry tile, digit counts (LDS integer atomics: exact);
-//   scan    -- exclusive scan of the digit-major count table (one workgroup);
+//   hist    -- per 2048-entry tile, digit counts (LDS integer atomics: exact;
+//              a wave whose entries share one digit, as on nearly sorted
+//              input, adds its count with one atomic instead of 64);
+//   scan    -- exclusive scan of the digit-major count table;
 //   scatter -- each tile ranks its entries stably (round-major, then wave,
-//              then lane order; lanes with equal digits are matched with eight
-//              wave64 ballots) and writes them to their final slots.
+//              then lane order; the same ballot matching), stages them in LDS
+//              in digit order and writes each digit's run of the tile to its
+//              consecutive final slots (coalesced).
 #include "common.h"
 
 namespace pdg {
@@ -20,6 +23,17 @@ constexpr int kItems = 8;
 constexpr int kTile = kThreads * kItems;
 constexpr int kScanThreads = 1024;
 
+// Lanes of the wave (valid ones) holding the same 8-bit digit d as this lane.
+__device__ __forceinline__ unsigned long long digit_peers(uint32_t d, bool valid) {
+  unsigned long long same = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const unsigned long long m = __ballot((d >> b) & 1u);
+    same &= ((d >> b) & 1u) ? m : ~m;
+  }
+  return same;
+}
+
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__restrict__ keys,
                                                               long long n, int shift,
                                                               uint32_t *__restrict__ hist,
@@ -27,11 +41,26 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t *__
   __shared__ uint32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  long long base = (long long)blockIdx.x * kTile;
+  const long long base = (long long)blockIdx.x * kTile;
+  const int lane = threadIdx.x & 63;
+  uint32_t k[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    long long i = base + r * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    const long long i = base + r * kThreads + threadIdx.x;
+    k[r] = i < n ? keys[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const bool valid = base + r * kThreads + threadIdx.x < n;
+    const uint32_t d = (k[r] >> shift) & 255u;
+    const unsigned long long live = __ballot(valid);
+    if (live == 0ull) continue;
+    const uint32_t d0 = (uint32_t)__shfl(d, __ffsll((long long)live) - 1, 64);
+    if (__ballot(valid && d == d0) == live) {      // one digit in the whole wave
+      if (lane == __ffsll((long long)live) - 1) atomicAdd(&cnt[d0], (uint32_t)__popcll(live));
+    } else if (valid) {
+      atomicAdd(&cnt[d], 1u);
+    }
   }
   __syncthreads();
   hist[(long long)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
@@ -125,43 +154,82 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, long long n, int shift,
     const uint32_t *__restrict__ hist, int nblocks) {
-  __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_cnt[kThreads / 64][256];
+  __shared__ uint32_t s_off[256];                  // global slot of the tile's digit run
+  __shared__ uint32_t s_run[256];                  // tile-local start of each digit run
+  __shared__ uint32_t s_cnt[kThreads / 64][256];   // a round's per-wave digit counts
+  __shared__ uint32_t s_key[kTile], s_val[kTile];  // the tile in (digit, rank) order
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
   s_off[tid] = hist[(long long)tid * nblocks + blockIdx.x];
-  long long base = (long long)blockIdx.x * kTile;
+  s_run[tid] = 0;                                  // running count of digit tid
+  const long long base = (long long)blockIdx.x * kTile;
+  const int tn = n - base < kTile ? (int)(n - base) : kTile;
+  uint32_t key[kItems], val[kItems], rank[kItems];
+  // ranks: stable order (round, wave, lane) among the tile's entries of a digit
+#pragma unroll
   for (int r = 0; r < kItems; ++r) {
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) s_cnt[w][tid] = 0;
-    long long i = base + r * kThreads + tid;
-    bool valid = i < n;
-    uint32_t k = valid ? kin[i] : 0u;
-    uint32_t d = (k >> shift) & 255u;
-    unsigned long long same = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      unsigned long long m = __ballot((d >> b) & 1u);
-      same &= ((d >> b) & 1u) ? m : ~m;
-    }
-    int rank = __popcll(same & lt);
+    const int li = r * kThreads + tid;
+    const bool valid = li < tn;
+    key[r] = valid ? kin[base + li] : 0u;
+    val[r] = valid ? vin[base + li] : 0u;
+    const uint32_t d = (key[r] >> shift) & 255u;
+    const unsigned long long same = digit_peers(d, valid);
+    const int wr = __popcll(same & lt);
     __syncthreads();
-    if (valid && rank == 0) s_cnt[wid][d] = (uint32_t)__popcll(same);
+    if (valid && wr == 0) s_cnt[wid][d] = (uint32_t)__popcll(same);
     __syncthreads();
-    if (valid) {
-      uint32_t pos = s_off[d] + (uint32_t)rank;
-      for (int w = 0; w < wid; ++w) pos += s_cnt[w][d];
-      kout[pos] = k;
-      vout[pos] = vin[i];
-    }
+    uint32_t rk = s_run[d] + (uint32_t)wr;
+    for (int w = 0; w < wid; ++w) rk += s_cnt[w][d];
+    rank[r] = rk;
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) add += s_cnt[w][tid];
-    s_off[tid] += add;
+    s_run[tid] += add;                             // digit tid's count so far
+  }
+  __syncthreads();
+  // tile-local run starts: exclusive scan of the 256 digit counts
+  {
+    const uint32_t c = s_run[tid];
+    uint32_t incl = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += o;
+    }
+    __shared__ uint32_t s_wsum[kThreads / 64];
+    if (lane == 63) s_wsum[wid] = incl;
     __syncthreads();
+    uint32_t off = incl - c;
+    for (int w = 0; w < wid; ++w) off += s_wsum[w];
+    __syncthreads();
+    s_run[tid] = off;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    if (r * kThreads + tid < tn) {
+      const uint32_t p = s_run[(key[r] >> shift) & 255u] + rank[r];
+      s_key[p] = key[r];
+      s_val[p] = val[r];
+    }
+  }
+  __syncthreads();
+  // slot i of the staged tile: digit d, the (i - run start)-th of the tile's
+  // entries of d, so its final slot is s_off[d] + i - s_run[d]
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int i = r * kThreads + tid;
+    if (i < tn) {
+      const uint32_t k = s_key[i], d = (k >> shift) & 255u;
+      const uint32_t pos = s_off[d] + (uint32_t)i - s_run[d];
+      kout[pos] = k;
+      vout[pos] = s_val[i];
+    }
   }
 }
 
