@@ -495,12 +495,13 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
 // three axes join the spectral scale in the pencil pass:
 //   C^T D C = Cu^T (S^2 D) Cu,  C = S Cu,  S = diag(s_k).
 // The two threads of a line sit in different waves, so each wave runs one of
-// the two transforms; a block holds 256 / 2R z-planes (one for R = 128).  Spectra between the passes keep the order
+// the two transforms.  Spectra between the passes keep the order
 // [even frequencies | odd frequencies] along each axis: position p < R/2 holds
 // frequency 2p, position p >= R/2 frequency 2 (p - R/2) + 1.
 //
-//   plane fwd   a z-plane in LDS (pitch R + 1): transforms along x (rows, in
-//               LDS), then along y (columns, straight to HBM);
+//   plane fwd   256 / 2R z-planes in LDS (pitch R + 1; one for R = 128):
+//               transforms along x (rows, in LDS), then along y (columns,
+//               straight to HBM);
 //   pencil      128 consecutive (qy, qx) pencils of one system in LDS: forward
 //               z, scale by s^2 / (1 + lam mu)^2, inverse z (DCT-III of the
 //               even half, DCT-IV of the odd half), combined through LDS;
