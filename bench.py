@@ -46,7 +46,7 @@ PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # with the given prefix; reported only while the source is unchanged.
 PMC_TRAFFIC = {
     "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "7180d50d122cc34a",
-                         (2 * 237324.49 + 122486.25) * 1024),
+                         (2 * 237324.4921875 + 122486.25) * 1024),
 }
 
 
