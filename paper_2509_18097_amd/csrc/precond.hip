@@ -29,8 +29,10 @@
 // on pruned cells and A p' is zero there, so r, p and x stay zero on them; a
 // kept cell sees a pruned neighbour as missing (the neighbour's value is
 // replaced by the cell's own, difference 0, selected and never multiplied, so
-// stale values never enter).  Tiles without a kept cell return at once: their
-// p buffers are never written, and no kept cell reads them.
+// stale values never enter).  Tiles without a kept cell return at once, and
+// inside a kept tile a float4 quad without a kept cell is skipped (it adds
+// exactly zero to both inner products): their p values are never written, and
+// no kept cell uses them, so the traffic follows the kept quads.
 #include "common.h"
 
 namespace pdg {
@@ -224,6 +226,9 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
     for (int u = 0; u < kQuads; ++u) {
       const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
       if (q >= n) continue;
+      // a quad without a kept cell adds exactly zero to <p', A p'>: skip its
+      // loads and stores (its p values are never read unselected)
+      if (MASK && nib4(o.mk, q) == 0u) continue;
       int x0, y, z;
       coords(L, q, x0, y, z);
       auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
@@ -308,6 +313,7 @@ __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int 
     for (int u = 0; u < kQuads; ++u) {
       const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
       if (q >= n) continue;
+      if (MASK && nib4(o.mk, q) == 0u) continue;   // x, r stay zero there
       int x0, y, z;
       coords(L, q, x0, y, z);
       const float4 c = ld4(pp + q);
