@@ -642,6 +642,7 @@ void init_problem(pdg_problem &p, const pdg_problem_desc &pd) {
   if (pd.prune_mask) {   // six channels: both halves on the same kept cells
     cg_set_mask(p.cg, p.g, pd.prune_mask);
     if (p.g.ch == 6) cg_set_mask(p.cg_t, p.g, pd.prune_mask);
+    adam_set_mask(p.adam, p.g, pd.prune_mask);
   }
 }
 

@@ -412,6 +412,14 @@ struct AdamLevels {
   int levels;
   long long off[PDG_MAX_LEVELS + 1];
   float lr[PDG_MAX_LEVELS];
+  // pruned grids (adam_set_mask): the kept-cell bits ([stacks][mstack] words,
+  // level l at moff[l], one bit per cell of its R^3 = r3[l], shared by the
+  // channels); a value whose cell is pruned has zero gradient, parameter and
+  // moments, which Adam leaves as they are, so it may be skipped.  Null: none.
+  const uint32_t *mask = nullptr;
+  long long mstack = 0;
+  long long moff[PDG_MAX_LEVELS] = {};
+  long long r3[PDG_MAX_LEVELS] = {};
 };
 // Adam applied by the last pass of the preconditioner: params, moments and
 // per-level rates laid out like the preconditioned gradient.
@@ -464,6 +472,8 @@ pdg_status launch_mask_apply(const GridDev &g, int batch, const uint32_t *mask, 
 // plan fields for masked conjugate gradients (run_cg then solves on the
 // graphs the kept cells induce)
 void cg_set_mask(CGPlanDev &p, const GridDev &g, const uint32_t *mask);
+// the same for Adam: values of pruned cells are skipped
+void adam_set_mask(AdamLevels &lv, const GridDev &g, const uint32_t *mask);
 // The kept-tile list of a masked plan from the masks on the host (hmask:
 // [batch][mstack] words): fills p.kfirst / p.kcount and writes the list to
 // `list` (host, p.ntiles entries at most); returns its length.

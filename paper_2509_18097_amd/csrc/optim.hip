@@ -11,6 +11,29 @@ __device__ __forceinline__ int level_of(const AdamLevels &lv, long long w) {
   return l;
 }
 
+// Kept bit of value w of stack b (pruned grids; 1 without a mask).
+__device__ __forceinline__ unsigned kept_of(const AdamLevels &lv, long long b, long long w) {
+  if (!lv.mask) return 1u;
+  const int l = level_of(lv, w);
+  const long long cell = (w - lv.off[l]) % lv.r3[l];
+  return (lv.mask[b * lv.mstack + lv.moff[l] + (cell >> 5)] >> (cell & 31)) & 1u;
+}
+
+// Whether any of values w .. w + 3 (w % 4 == 0) is kept: one lookup when the
+// four lie in one level's channel block (its offset and R^3 multiples of 4,
+// so they share a mask word), else one per value.
+__device__ __forceinline__ bool kept_any4(const AdamLevels &lv, long long b, long long w) {
+  if (!lv.mask) return true;
+  const int l = level_of(lv, w);
+  if (w + 3 < lv.off[l + 1] && (lv.off[l] & 3) == 0 && (lv.r3[l] & 3) == 0 &&
+      lv.r3[l] < (1ll << 32)) {
+    const unsigned cell = (unsigned)(w - lv.off[l]) % (unsigned)lv.r3[l];
+    return ((lv.mask[b * lv.mstack + lv.moff[l] + (cell >> 5)] >> (cell & 31)) & 15u) != 0u;
+  }
+  return (kept_of(lv, b, w) | kept_of(lv, b, w + 1) | kept_of(lv, b, w + 2) |
+          kept_of(lv, b, w + 3)) != 0u;
+}
+
 // kAdamGroups groups of four consecutive values of stack blockIdx.y per thread (all
 // loads issued before the arithmetic); stack % 4 == 0 and 16-byte aligned arrays.
 constexpr int kAdamGroups = 1;
@@ -26,10 +49,13 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
   const long long w0 = c0 + (long long)blockIdx.x * blockDim.x * 4 * kAdamGroups + threadIdx.x * 4;
   const long long base = (long long)blockIdx.y * stack;
   float4 gi[kAdamGroups], mi[kAdamGroups], vi[kAdamGroups], ti[kAdamGroups];
+  bool live[kAdamGroups];
 #pragma unroll
   for (int q = 0; q < kAdamGroups; ++q) {
     const long long w = w0 + (long long)q * blockDim.x * 4;
-    if (w < c1) {
+    // a group of four pruned values is left as it is (no loads, no stores)
+    live[q] = w < c1 && kept_any4(lv, blockIdx.y, w);
+    if (live[q]) {
       gi[q] = *reinterpret_cast<const float4 *>(g + base + w);
       mi[q] = *reinterpret_cast<const float4 *>(m + base + w);
       vi[q] = *reinterpret_cast<const float4 *>(v + base + w);
@@ -39,7 +65,7 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
 #pragma unroll
   for (int q = 0; q < kAdamGroups; ++q) {
     const long long w = w0 + (long long)q * blockDim.x * 4;
-    if (w >= c1) continue;
+    if (!live[q]) continue;
     ti[q].x = adam_one(b1, b2, eps, lv.lr[level_of(lv, w)], bc1, bc2, gi[q].x, mi[q].x, vi[q].x, ti[q].x);
     ti[q].y = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 1)], bc1, bc2, gi[q].y, mi[q].y, vi[q].y, ti[q].y);
     ti[q].z = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 2)], bc1, bc2, gi[q].z, mi[q].z, vi[q].z, ti[q].z);
@@ -60,7 +86,7 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamLevels lv, long long stac
   __shared__ float sbc[2];
   adam_bias(b1, b2, step_dev, step_host, sbc);
   const long long w = c0 + (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= c1) return;
+  if (w >= c1 || !kept_of(lv, blockIdx.y, w)) return;   // pruned values stay as they are
   const long long i = (long long)blockIdx.y * stack + w;
   float mi = m[i], vi = v[i];
   th[i] = adam_one(b1, b2, eps, lv.lr[level_of(lv, w)], sbc[0], sbc[1], g[i], mi, vi, th[i]);
@@ -313,13 +339,15 @@ pdg_status adam_cols(const AdamLevels &lv, long long stack, long long c0, long l
   for (int b0 = 0; b0 < batch; b0 += 65535) {      // grid.y limit
     const int nb = batch - b0 < 65535 ? batch - b0 : 65535;
     const long long o = (long long)b0 * stack;
+    AdamLevels lb = lv;                 // this chunk's stacks' mask words
+    if (lb.mask) lb.mask += (long long)b0 * lb.mstack;
     if (vec) {
       dim3 grid(div_up(cols / 4, 256 * kAdamGroups), nb);
-      adam4_kernel<<<grid, 256, 0, st>>>(lv, stack, c0, c1, b1, b2, eps, step_dev, step_host,
+      adam4_kernel<<<grid, 256, 0, st>>>(lb, stack, c0, c1, b1, b2, eps, step_dev, step_host,
                                          theta + o, m + o, v + o, g + o);
     } else {
       dim3 grid(div_up(cols, 256), nb);
-      adam_kernel<<<grid, 256, 0, st>>>(lv, stack, c0, c1, b1, b2, eps, step_dev, step_host,
+      adam_kernel<<<grid, 256, 0, st>>>(lb, stack, c0, c1, b1, b2, eps, step_dev, step_host,
                                         theta + o, m + o, v + o, g + o);
     }
     PDG_TRY(launched("adam"));

@@ -223,6 +223,16 @@ int cg_kept_tiles(CGPlanDev &p, const GridDev &g, const uint32_t *hmask, int *li
   return n;
 }
 
+void adam_set_mask(AdamLevels &lv, const GridDev &g, const uint32_t *mask) {
+  const PruneLevels pl = prune_levels(g);
+  lv.mask = mask;
+  lv.mstack = pl.mstack;
+  for (int l = 0; l < g.levels; ++l) {
+    lv.moff[l] = pl.moff[l];
+    lv.r3[l] = (long long)g.res[l] * g.res[l] * g.res[l];
+  }
+}
+
 void cg_set_mask(CGPlanDev &p, const GridDev &g, const uint32_t *mask) {
   const PruneLevels pl = prune_levels(g);
   p.mask = mask;
