@@ -172,11 +172,15 @@ __device__ __forceinline__ void coords(const CGLevel &L, int c, int &x, int &y, 
   }
 }
 
+// r = src on the kept cells (all cells without a mask), x = 0.  On a pruned
+// cell r is never read unselected and x only matters where it is the solve's
+// output (zero_x_pruned): the other stores are left out there.
 __global__ __launch_bounds__(kThreads) void cg_init_kernel(CGPlanDev P, int ntiles,
                                                            const float *__restrict__ src,
                                                            float *__restrict__ r,
                                                            float *__restrict__ x,
-                                                           double *__restrict__ rr_part) {
+                                                           double *__restrict__ rr_part,
+                                                           int zero_x_pruned) {
   __shared__ double sh[kThreads / 64];
   const int tile = tile_of_block(0, ntiles);
   Loc o;
@@ -187,7 +191,11 @@ __global__ __launch_bounds__(kThreads) void cg_init_kernel(CGPlanDev P, int ntil
   for (int k = 0; k < 4 * kQuads; ++k) {
     const int c = o.lt * kTileCells + k * kThreads + threadIdx.x;
     if (c < n) {
-      const float v = (o.mk && !bit1(o.mk, c)) ? 0.0f : src[o.base + c];
+      if (o.mk && !bit1(o.mk, c)) {
+        if (zero_x_pruned) x[o.base + c] = 0.f;
+        continue;
+      }
+      const float v = src[o.base + c];
       r[o.base + c] = v;
       x[o.base + c] = 0.f;
       acc += (double)v * v;
@@ -337,7 +345,10 @@ __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int 
         ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
       }
       st4(xx + q, axpy4(ld4(xx + q), alpha, c));
-      const float4 rn = axpy4(ld4(rr + q), -alpha, ap);
+      float4 rn = axpy4(ld4(rr + q), -alpha, ap);
+      // the residual of a pruned cell is zero (its stored value is not kept
+      // up to date: the set-up does not write it)
+      if (MASK) rn = keep4(rn, nib4(o.mk, q));
       st4(rr + q, rn);
       acc += dot4(rn, rn);
     }
@@ -475,7 +486,9 @@ pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipS
     const float *src = solve == 0 ? g : s.x;
     CGState t = s;
     t.x = solve == 0 ? s.x : g;
-    cg_init_kernel<<<padded(P.ntiles), kThreads, 0, st>>>(P, P.ntiles, src, t.r, t.x, t.rr_part);
+    // solve 1's x feeds solve 2 through its kept cells only; solve 2's x is the output
+    cg_init_kernel<<<padded(P.ntiles), kThreads, 0, st>>>(P, P.ntiles, src, t.r, t.x, t.rr_part,
+                                                          solve == 1);
     PDG_TRY(launched("cg_init"));
     cg_reduce_kernel<<<P.nsys, kThreads, 0, st>>>(P, 0, 0, 0, t);
     PDG_TRY(launched("cg_reduce"));
