@@ -36,6 +36,10 @@ FLAGS = [
     # kernels consume every MFMA result with VALU instructions
     "-mllvm", "-amdgpu-mfma-vgpr-form=1",
 ]
+# Per-file additions.  The nearest-neighbour screen takes finite coordinates
+# only, so its minima need no NaN-quieting instruction per matrix-core
+# result.
+FILE_FLAGS = {"chamfer_screen.hip": ["-fno-honor-nans"]}
 
 
 def _hipcc() -> str:
@@ -47,7 +51,7 @@ def _hipcc() -> str:
 
 def _compile(src: str, hipcc: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc, *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -335,16 +335,23 @@ __device__ __forceinline__ float min16(const f32x16 &v) {
   return fminf(a, b);
 }
 
-// Exact re-rank of every row of this lane whose screened value passes the
-// threshold (the threshold only tightens on the way, so later rows are tested
-// against the improved best); candidate coordinates come from the wave's LDS
-// copy of the tile.
+// Exact re-rank of every row of this lane whose screened value passes its
+// threshold.  The lane first notes those rows against the threshold it has on
+// entry (thresholds only tighten, so the rows a tighter one would skip are
+// extra work, never a different result: each is strictly farther than the
+// best at that point); then every lane evaluates one of its rows per round,
+// lowest first, so that a round issues all lanes' coordinate loads together
+// and a product costs as many rounds as its busiest lane has rows.
 template <typename CoordPtr>
 __device__ __forceinline__ void rerank(QState &s, const f32x16 &v, int lane, int r0, int nleft,
                                        CoordPtr tc) {
-#pragma nounroll
-  for (int r = 0; r < 16; ++r) {   // r is wave-uniform: v[r] is a register-relative move
-    if (v[r] <= s.thr) {
+  unsigned pm = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) pm |= (v[r] <= s.thr ? 1u : 0u) << r;
+  while (__ballot(pm != 0u)) {
+    if (pm != 0u) {
+      const int r = __builtin_ctz(pm);
+      pm &= pm - 1u;
       const int row = r0 + out_row(r, lane);   // position in the tile
       if (row < nleft) {                       // padded rows never count
         const float4 p = tc[row];
@@ -399,7 +406,9 @@ constexpr int kXcds = 8;
 //
 // The grid is 1-D with a multiple of 8 blocks, so lin -> tile is a bijection;
 // tile = job * qt + query tile, tiles >= nblk do nothing.
-__global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
+// Four waves per SIMD (the second bound counts waves per execution unit):
+// at most 128 VGPRs.
+__global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
     const ScreenJob *__restrict__ jobs, int warm, unsigned qt, unsigned nblk) {
   const unsigned lin = blockIdx.x;
   const unsigned per = gridDim.x / kXcds;
@@ -438,7 +447,9 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
     s.x = qc.x;
     s.y = qc.y;
     s.z = qc.z;
-    s.best = __builtin_huge_valf();
+    // a lane without a query starts at best = -inf, so its threshold never
+    // passes and it flags no product
+    s.best = ok[h] ? __builtin_huge_valf() : -__builtin_huge_valf();
     s.idx = 0x7fffffff;
     if (ok[h] && warm) {
       const int p = jnn[qorig[h]];
@@ -549,14 +560,14 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
 #pragma unroll
         for (int h = 0; h < kQB; ++h) enter_tile(st[h], cen, half, bq[h]);
         __builtin_amdgcn_wave_barrier();   // the coordinates are written before any re-rank
-        // The screen proper has no branch: each lane only notes which
-        // (step, query block) products hold a row inside its threshold, and
-        // the steps noted anywhere in the wave are recomputed and re-ranked
-        // after the tile.  Thresholds only tighten, so a product not noted
+        // The screen proper has no branch: the wave only notes which
+        // (step, query block) products hold a row inside some lane's
+        // threshold (a ballot, kept in scalar registers), and those are
+        // recomputed and re-ranked after the tile.  Thresholds only tighten, so a product not noted
         // cannot hold a better neighbour or a tie later, and a noted one is
         // re-ranked against the tighter threshold.
         const f32x16 z = {};
-        unsigned flags = 0;   // bit kQB * step + block
+        unsigned flags = 0;   // bit kQB * step + block (wave-uniform)
         constexpr int kProducts = kQB * kCTile / 32;
         if (full) {
           // software-pipelined: product i + 1 is issued before product i is
@@ -570,7 +581,7 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
               vn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                   *reinterpret_cast<const bf16x8 *>(&fr[(i + 1) / kQB]), bq[(i + 1) % kQB], z, 0,
                   0, 0);
-            flags |= (min16(v) <= st[i % kQB].thr ? 1u : 0u) << i;
+            flags |= (__ballot(min16(v) <= st[i % kQB].thr) != 0ull ? 1u : 0u) << i;
             v = vn;
           }
         } else {
@@ -581,20 +592,20 @@ __global__ __launch_bounds__(kThreads, 16 / kWaves) void nn_screen_kernel(
 #pragma unroll
               for (int h = 0; h < kQB; ++h) {
                 const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
-                flags |= (min16(v) <= st[h].thr ? 1u : 0u) << (kQB * sidx + h);
+                flags |= (__ballot(min16(v) <= st[h].thr) != 0ull ? 1u : 0u) << (kQB * sidx + h);
               }
             }
           }
         }
-        if (__ballot(flags != 0u)) {   // rare: rows inside the error window
+        if (flags != 0u) {   // rare: rows inside the error window
 #pragma unroll
           for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
             const unsigned fs = (flags >> (kQB * sidx)) & ((1u << kQB) - 1u);
-            if (sidx < nsub && __ballot(fs != 0u)) {
+            if (sidx < nsub && fs != 0u) {
               const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&fr[sidx]);
 #pragma unroll
               for (int h = 0; h < kQB; ++h) {
-                if (__ballot((fs >> h) & 1u)) {
+                if ((fs >> h) & 1u) {
                   ++issued;   // the recomputed product is issued work too
                   const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
                   if (kStage)
