@@ -174,7 +174,7 @@ ScatterList scatter_list(const uint32_t *keys, const uint32_t *vals, const int *
 
 // --------------------------------------------------------------- chamfer --
 ScreenSet screen_set(const float *x, long long n, const int *perm, uint4 *pack, float4 *coords,
-                     float4 *boxes) {
+                     float4 *boxes, int *inv = nullptr) {
   ScreenSet S;
   memset(&S, 0, sizeof S);
   S.x = x;
@@ -183,6 +183,7 @@ ScreenSet screen_set(const float *x, long long n, const int *perm, uint4 *pack, 
   S.pack = pack;
   S.coords = coords;
   S.boxes = boxes;
+  S.inv = inv;
   return S;
 }
 // queries from set Q, candidates from set C
@@ -199,6 +200,7 @@ ScreenJob screen_job(const ScreenSet &Q, const ScreenSet &C, int *nn, unsigned l
   J.cc = C.coords;
   J.cboxes = C.boxes;
   J.tiles = tiles;
+  J.cinv = C.inv;
   return J;
 }
 
@@ -410,6 +412,7 @@ struct pdg_problem {
   ScreenJob *sjobs = nullptr;
   uint4 *packs = nullptr;
   float4 *coords = nullptr, *boxes = nullptr;
+  int *pinv = nullptr;                 // packed sets: original index -> packed position
   int *fperm = nullptr, *tperm = nullptr;   // Morton order of every frame / of X_0
   unsigned long long *tiles = nullptr;     // candidate tiles screened (all steps)
   long long pack_rows = 0, box_tiles = 0;
@@ -598,6 +601,7 @@ void layout(pdg_problem &p, Carve &c) {
     p.sjobs = c.take<ScreenJob>(p.njobs);
     if (p.d.chamfer_mode == PDG_CHAMFER_BF16_SCREEN) p.packs = c.take<uint4>(2 * p.pack_rows);
     p.coords = c.take<float4>(p.pack_rows);
+    p.pinv = c.take<int>(p.pack_rows);
     p.boxes = c.take<float4>(p.box_tiles);
     p.tiles = c.take<unsigned long long>(1);
   }
@@ -1722,7 +1726,7 @@ static pdg_status create_chain(const pdg_problem_desc *pd, hipStream_t stream, p
     long long row = 0, tile = 0;
     auto add_set = [&](const float *x, long long n, const int *perm) {
       ssets.push_back(screen_set(x, n, perm, p->packs ? p->packs + 2 * row : nullptr, p->coords + row,
-                                 p->boxes + tile));
+                                 p->boxes + tile, p->pinv + row));
       row += n;
       tile += screen_box_count(n);
     };

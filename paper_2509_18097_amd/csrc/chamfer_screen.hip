@@ -172,6 +172,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ScreenSet *__restrict__
   PDG_GLOBAL float4 *scoords = glb(S.coords);
   PDG_GLOBAL float4 *sboxes = glb(S.boxes);
   const int i = tb * 256 + threadIdx.x;
+  if (i < S.n && S.inv) glb(S.inv)[S.perm ? sperm[i] : i] = i;   // the inverse order
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool in = i < S.n;
   float c[3] = {0.f, 0.f, 0.f};
@@ -281,6 +282,7 @@ struct QState {
   float x, y, z;      // the query (global coordinates)
   float best;         // contract d2 of the current best candidate
   int idx;            // its original index
+  int pos;            // its packed position (-1: not known)
   float qn, eps;      // |q - C|^2 and the screen's error bound in the current tile's frame
   float thr;          // screened values above it are neither a better neighbour nor a tie
 };
@@ -339,15 +341,21 @@ __device__ __forceinline__ float min16(const f32x16 &v) {
 // threshold.  The lane first notes those rows against the threshold it has on
 // entry (thresholds only tighten, so the rows a tighter one would skip are
 // extra work, never a different result: each is strictly farther than the
-// best at that point); then every lane evaluates one of its rows per round,
-// lowest first, so that a round issues all lanes' coordinate loads together
-// and a product costs as many rounds as its busiest lane has rows.
+// best at that point), leaving out the row of its current best itself (its
+// distance equals the best and its index is the best's, so it changes
+// nothing); then every lane evaluates one of its rows per round, lowest
+// first, so that a round issues all lanes' coordinate loads together and a
+// product costs as many rounds as its busiest lane has rows.
 template <typename CoordPtr>
 __device__ __forceinline__ void rerank(QState &s, const f32x16 &v, int lane, int r0, int nleft,
-                                       CoordPtr tc) {
+                                       CoordPtr tc, int c0) {
   unsigned pm = 0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) pm |= (v[r] <= s.thr ? 1u : 0u) << r;
+  // the current best's row, when this product holds it on this lane's half
+  const int rel = s.pos - (c0 + r0);
+  if (rel >= 0 && rel < 32 && ((rel >> 2) & 1) == (lane >> 5))
+    pm &= ~(1u << (((rel >> 3) << 2) | (rel & 3)));
   while (__ballot(pm != 0u)) {
     if (pm != 0u) {
       const int r = __builtin_ctz(pm);
@@ -360,6 +368,7 @@ __device__ __forceinline__ void rerank(QState &s, const f32x16 &v, int lane, int
         if (d < s.best || (d == s.best && o < s.idx)) {
           s.best = d;
           s.idx = o;
+          s.pos = c0 + row;
           set_thr(s);
         }
       }
@@ -451,11 +460,13 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
     // passes and it flags no product
     s.best = ok[h] ? __builtin_huge_valf() : -__builtin_huge_valf();
     s.idx = 0x7fffffff;
+    s.pos = -1;
     if (ok[h] && warm) {
       const int p = jnn[qorig[h]];
       if (p >= 0 && p < J.nc) {
         s.best = d2_contract(s.x, s.y, s.z, jc[p], jc[nc + p], jc[2 * nc + p]);
         s.idx = p;
+        if (J.cinv) s.pos = glb(J.cinv)[p];
       }
     }
     s.qn = 0.f;
@@ -609,9 +620,9 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
                   ++issued;   // the recomputed product is issued work too
                   const f32x16 v = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bq[h], z, 0, 0, 0);
                   if (kStage)
-                    rerank(st[h], v, lane, sidx * 32, nleft, tc);
+                    rerank(st[h], v, lane, sidx * 32, nleft, tc, c0);
                   else
-                    rerank(st[h], v, lane, sidx * 32, nleft, tg);
+                    rerank(st[h], v, lane, sidx * 32, nleft, tg, c0);
                 }
               }
             }

@@ -303,6 +303,7 @@ struct ScreenSet {           // one point set packed as screen candidates and qu
   float4 *coords;            // [n] (x, y, z, original index as int bits), packed order
   float4 *boxes;             // [ceil(n/256)][3] per 256-point tile: min corner, max corner,
                              // (centre C, radius): the frame the tile's rows are packed in
+  int *inv;                  // nullable: [n] original index -> packed position
 };
 struct ScreenJob {           // one directed search: packed queries over packed candidates
   const float *c;            // candidates SoA [3][nc], original order (warm start)
@@ -314,6 +315,7 @@ struct ScreenJob {           // one directed search: packed queries over packed 
   const float4 *cc;          // candidate coords, packed order
   const float4 *cboxes;      // candidate tile boxes
   unsigned long long *tiles; // nullable: += 32x32x16 bf16 products issued
+  const int *cinv;           // nullable: candidates' original index -> packed position
 };
 inline long long screen_tiles(long long n) { return (n + 255) / 256; }
 // float4 entries of a set's box array: per tile its min corner, max corner,
