@@ -86,7 +86,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #define PDG_SCREEN_WAVES 1
 #endif
 #ifndef PDG_SCREEN_STAGE
-#define PDG_SCREEN_STAGE 0
+#define PDG_SCREEN_STAGE 1
 #endif
 constexpr int kWaves = PDG_SCREEN_WAVES;   // independent waves per workgroup
 constexpr int kThreads = 64 * kWaves;
@@ -319,6 +319,18 @@ __device__ __forceinline__ void enter_tile(QState &s, const float4 &cen, int hal
   set_thr(s);
 }
 
+// Coordinates staged for the re-rank: each lane's 16 bytes go from global
+// memory straight into LDS at base + 16 * lane (no registers, no wait at the
+// issue); stage_wait() waits for every outstanding vector memory load,
+// these included, before LDS is read.
+__device__ __forceinline__ void stage_lds(const PDG_GLOBAL float4 *src, float4 *lds_base) {
+  __builtin_amdgcn_global_load_lds((const PDG_GLOBAL void *)src,
+                                   (__attribute__((address_space(3))) void *)lds_base, 16, 0, 0);
+}
+__device__ __forceinline__ void stage_wait() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt and lgkmcnt not waited for
+}
+
 // rows held by this lane for output register r of a 32x32 MFMA
 __device__ __forceinline__ int out_row(int r, int lane) {
   return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -435,10 +447,12 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
   __shared__ float4 tcs[kWaves][kStage ? kTile : 1];   // each wave's visited tile's coordinates
   __shared__ int wls[kWaves][kListMax];
   __shared__ float wlbs[kWaves][kListMax];
+  __shared__ float4 wcs[kWaves][kListMax];   // the listed tiles' (centre, radius)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float4 *tc = tcs[wv];
   int *wl = wls[wv];
   float *wlb = wlbs[wv];
+  float4 *wc = wcs[wv];
   const int half = lane >> 5;
   const long long nc = J.nc;
   QState st[kQB];
@@ -522,6 +536,7 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
         if (pass) {
           wl[pos] = t;
           wlb[pos] = lb;
+          wc[pos] = jcboxes[kBoxStride * t + 2];
         }
         count += __popcll(m);
       }
@@ -539,15 +554,21 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
         // half row) and coordinates; full tiles address them from one scalar
         // base with immediate offsets
         uint4 fr[kCTile / 32];
+        const float4 cl = wc[i];   // wave-uniform
+        const float4 cen = make_float4(
+            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cl.x))),
+            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cl.y))),
+            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cl.z))),
+            __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cl.w))));
         const PDG_GLOBAL uint4 *tp = jpack + 2 * (long long)c0 + 2 * (lane & 31) + half;
         const PDG_GLOBAL float4 *tq = jcc + c0 + lane;
         __builtin_amdgcn_wave_barrier();   // the previous tile's re-rank reads are done
         if (full) {
 #pragma unroll
           for (int sidx = 0; sidx < kCTile / 32; ++sidx) fr[sidx] = tp[64 * sidx];
-          if (kStage) {
+          if (kStage) {   // straight from memory into LDS, 16 B per lane
 #pragma unroll
-            for (int k = 0; k < kTile / 64; ++k) tc[k * 64 + lane] = tq[64 * k];
+            for (int k = 0; k < kTile / 64; ++k) stage_lds(tq + 64 * k, tc + 64 * k);
           }
         } else {
 #pragma unroll
@@ -562,15 +583,13 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
 #pragma unroll
             for (int k = 0; k < kTile / 64; ++k) {
               const int c = c0 + k * 64 + lane;
-              tc[k * 64 + lane] = jcc[c < J.nc ? c : J.nc - 1];
+              stage_lds(jcc + (c < J.nc ? c : J.nc - 1), tc + 64 * k);
             }
           }
         }
         const PDG_GLOBAL float4 *tg = jcc + c0;   // the re-rank's coordinates without staging
-        const float4 cen = jcboxes[kBoxStride * ti + 2];
 #pragma unroll
         for (int h = 0; h < kQB; ++h) enter_tile(st[h], cen, half, bq[h]);
-        __builtin_amdgcn_wave_barrier();   // the coordinates are written before any re-rank
         // The screen proper has no branch: the wave only notes which
         // (step, query block) products hold a row inside some lane's
         // threshold (a ballot, kept in scalar registers), and those are
@@ -609,6 +628,10 @@ __global__ __launch_bounds__(kThreads, 4) void nn_screen_kernel(
           }
         }
         if (flags != 0u) {   // rare: rows inside the error window
+          if (kStage) {
+            stage_wait();   // the tile's coordinates have reached LDS
+            __builtin_amdgcn_wave_barrier();
+          }
 #pragma unroll
           for (int sidx = 0; sidx < kCTile / 32; ++sidx) {
             const unsigned fs = (flags >> (kQB * sidx)) & ((1u << kQB) - 1u);
