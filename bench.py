@@ -45,8 +45,8 @@ PAIR_MFMA_FLOPS = 32  # one output of a K = 16 bf16 MFMA
 # profiles/nn_screen_c2_bf16_dct.md for the kernel source whose SHA-256 starts
 # with the given prefix; reported only while the source is unchanged.
 PMC_TRAFFIC = {
-    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "7180d50d122cc34a",
-                         (2 * 237324.4921875 + 122486.25) * 1024),
+    "nn_screen_kernel": ("paper_2509_18097_amd/csrc/chamfer_screen.hip", "e4f10a87f7e5f3f5",
+                         (2 * 314499.1171875 + 206854.234375) * 1024),
 }
 
 

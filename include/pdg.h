@@ -185,7 +185,9 @@ pdg_status pdg_keyframe(const float *points, int32_t frames, int64_t n, double g
  *   loss[1] = 1/m sum_j exp(-alpha s_j) s_j,  s_j = |a_nn_b[j] - b_j|^2.
  * Neighbour contract: d2 is evaluated in float32 in difference form without
  * fused multiply-add, dx = a_x - b_x, d2 = (dx*dx + dy*dy) + dz*dz, and ties
- * go to the lowest index; both modes return exactly these indices.
+ * go to the lowest index; every mode returns exactly these indices for finite
+ * coordinates (NaN coordinates give unspecified indices in the screen and
+ * culled modes).
  * Losses are float64 sums of float64 distances (alpha is taken in float64
  * there; the float32 gradient uses alpha rounded to float32).
  *   mode PDG_CHAMFER_FP32       : exact float32 tiles.
