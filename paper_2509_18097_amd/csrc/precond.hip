@@ -32,7 +32,9 @@
 // stale values never enter).  Tiles without a kept cell return at once, and
 // inside a kept tile a float4 quad without a kept cell is skipped (it adds
 // exactly zero to both inner products): their p values are never written, and
-// no kept cell uses them, so the traffic follows the kept quads.
+// no kept cell uses them, so the traffic follows the kept quads.  The kept
+// quads of a tile are listed in LDS (in index order) and dealt to the block's
+// threads in turn, so that lanes do not idle on empty quads.
 #include "common.h"
 
 namespace pdg {
@@ -159,6 +161,38 @@ __device__ __forceinline__ bool tile_kept(const uint32_t *mk, int lt, int n) {
   return __syncthreads_or(v != 0u) != 0;
 }
 
+// The kept quads of a tile, in index order: kq[0 .. count) are the tile's
+// quad numbers u * kThreads + t (cells lt * kTileCells + 4 * (u * kThreads + t))
+// whose four cells hold a kept one; the block's threads then take them in
+// turn, so no lane idles on an empty quad.  gcount: kQuads * kThreads / 64
+// ints of LDS.  Block-uniform count.
+__device__ __forceinline__ int kept_quads(const uint32_t *mk, int lt, int n, unsigned short *kq,
+                                          int *gcount) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int kW = kThreads / 64;
+  unsigned long long m[kQuads];
+#pragma unroll
+  for (int u = 0; u < kQuads; ++u) {
+    const int q = lt * kTileCells + 4 * (u * kThreads + (int)threadIdx.x);
+    m[u] = __ballot(q < n && nib4(mk, q) != 0u);
+    if (lane == 0) gcount[u * kW + w] = __popcll(m[u]);
+  }
+  __syncthreads();
+  int total = 0;
+#pragma unroll
+  for (int g = 0; g < kQuads * kW; ++g) total += gcount[g];
+#pragma unroll
+  for (int u = 0; u < kQuads; ++u) {
+    int off = 0;   // kept quads of the (u, wave) groups before this one
+    for (int g = 0; g < u * kW + w; ++g) off += gcount[g];
+    if ((m[u] >> lane) & 1ull)
+      kq[off + __popcll(m[u] & ((1ull << lane) - 1ull))] =
+          (unsigned short)(u * kThreads + (int)threadIdx.x);
+  }
+  __syncthreads();
+  return total;
+}
+
 // generic cell coordinates (any R)
 __device__ __forceinline__ void coords(const CGLevel &L, int c, int &x, int &y, int &z) {
   if (L.shift >= 0) {
@@ -210,6 +244,8 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
                                                         CGState s, const float *__restrict__ pin,
                                                         float *__restrict__ pout) {
   __shared__ double sh[kThreads / 64];
+  __shared__ unsigned short kq[kQuads * kThreads];   // the tile's kept quads (masked)
+  __shared__ int gcount[kQuads * kThreads / 64];
   int tile = tile_of_block(tile_lo, nlaunch);
   if (tile >= tile_lo + nlaunch) return;
   if (P.klist) tile = P.klist[tile];          // listed tiles hold a kept cell
@@ -231,12 +267,7 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
   double acc = 0.0;
   if (L.vec) {
     const int RR = R * R;
-    for (int u = 0; u < kQuads; ++u) {
-      const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
-      if (q >= n) continue;
-      // a quad without a kept cell adds exactly zero to <p', A p'>: skip its
-      // loads and stores (its p values are never read unselected)
-      if (MASK && nib4(o.mk, q) == 0u) continue;
+    auto quad = [&](int q) {
       int x0, y, z;
       coords(L, q, x0, y, z);
       auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
@@ -264,6 +295,19 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
       }
       st4(po + q, c);
       acc += dot4(c, ap);
+    };
+    if (MASK) {
+      // a quad without a kept cell adds exactly zero to <p', A p'>: only the
+      // kept quads are visited (the others' p values are never read
+      // unselected)
+      const int cnt = kept_quads(o.mk, o.lt, n, kq, gcount);
+#pragma unroll 1
+      for (int j = threadIdx.x; j < cnt; j += kThreads) quad(o.lt * kTileCells + 4 * (int)kq[j]);
+    } else {
+      for (int u = 0; u < kQuads; ++u) {
+        const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
+        if (q < n) quad(q);
+      }
     }
   } else {
     auto pn = [&](int i) { return k == 0 ? rr[i] : rr[i] + beta * pp[i]; };
@@ -294,9 +338,11 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
 }
 
 template <bool MASK>
-__global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
+__global__ __launch_bounds__(kThreads, 8) void cg_b_kernel(CGPlanDev P, int k, int tile_lo, int nlaunch,
                                                         CGState s, const float *__restrict__ pcur) {
   __shared__ double sh[kThreads / 64];
+  __shared__ unsigned short kq[kQuads * kThreads];   // the tile's kept quads (masked)
+  __shared__ int gcount[kQuads * kThreads / 64];
   int tile = tile_of_block(tile_lo, nlaunch);
   if (tile >= tile_lo + nlaunch) return;
   if (P.klist) tile = P.klist[tile];
@@ -318,10 +364,7 @@ __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int 
   double acc = 0.0;
   if (L.vec) {
     const int RR = R * R;
-    for (int u = 0; u < kQuads; ++u) {
-      const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
-      if (q >= n) continue;
-      if (MASK && nib4(o.mk, q) == 0u) continue;   // x, r stay zero there
+    auto quad = [&](int q) {
       int x0, y, z;
       coords(L, q, x0, y, z);
       const float4 c = ld4(pp + q);
@@ -351,6 +394,16 @@ __global__ __launch_bounds__(kThreads) void cg_b_kernel(CGPlanDev P, int k, int 
       if (MASK) rn = keep4(rn, nib4(o.mk, q));
       st4(rr + q, rn);
       acc += dot4(rn, rn);
+    };
+    if (MASK) {   // x and r stay zero on the quads without a kept cell
+      const int cnt = kept_quads(o.mk, o.lt, n, kq, gcount);
+#pragma unroll 1
+      for (int j = threadIdx.x; j < cnt; j += kThreads) quad(o.lt * kTileCells + 4 * (int)kq[j]);
+    } else {
+      for (int u = 0; u < kQuads; ++u) {
+        const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
+        if (q < n) quad(q);
+      }
     }
   } else {
     auto on = [&](int i) { return !MASK || bit1(o.mk, i) != 0u; };
