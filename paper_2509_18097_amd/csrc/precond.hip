@@ -208,20 +208,44 @@ __device__ __forceinline__ void coords(const CGLevel &L, int c, int &x, int &y, 
 
 // r = src on the kept cells (all cells without a mask), x = 0.  On a pruned
 // cell r is never read unselected and x only matters where it is the solve's
-// output (zero_x_pruned): the other stores are left out there.
+// output (zero_x_pruned): the other stores are left out there (a kept quad
+// writes all four cells of r and x; only its kept cells enter <r, r>).
+// list (nullable): the launched tiles are list[0 .. ntiles).
 __global__ __launch_bounds__(kThreads) void cg_init_kernel(CGPlanDev P, int ntiles,
+                                                           const int *__restrict__ list,
                                                            const float *__restrict__ src,
                                                            float *__restrict__ r,
                                                            float *__restrict__ x,
                                                            double *__restrict__ rr_part,
                                                            int zero_x_pruned) {
   __shared__ double sh[kThreads / 64];
-  const int tile = tile_of_block(0, ntiles);
+  int tile = tile_of_block(0, ntiles);
+  if (tile >= ntiles) return;
+  if (list) tile = list[tile];
   Loc o;
-  if (tile >= ntiles || !locate(P, tile, o)) return;
+  if (!locate(P, tile, o)) return;
   const CGLevel &L = P.lv[o.l];
   const int n = L.R * L.R * L.R;
   double acc = 0.0;
+  if (L.vec) {
+    for (int u = 0; u < kQuads; ++u) {
+      const int q = o.lt * kTileCells + u * (4 * kThreads) + 4 * threadIdx.x;
+      if (q >= n) continue;
+      const unsigned own = o.mk ? nib4(o.mk, q) : 15u;
+      if (own == 0u) {
+        if (zero_x_pruned) st4(x + o.base + q, make_float4(0.f, 0.f, 0.f, 0.f));
+        continue;
+      }
+      const float4 v = ld4(src + o.base + q);
+      st4(r + o.base + q, v);
+      st4(x + o.base + q, make_float4(0.f, 0.f, 0.f, 0.f));
+      const float4 kv = keep4(v, own);
+      acc += dot4(kv, kv);
+    }
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) rr_part[tile] = t;
+    return;
+  }
   for (int k = 0; k < 4 * kQuads; ++k) {
     const int c = o.lt * kTileCells + k * kThreads + threadIdx.x;
     if (c < n) {
@@ -531,17 +555,28 @@ pdg_status run_cg(const CGPlanDev &P, float *g, long long floats, void *ws, hipS
   int kmax = 0;
   for (int l = 0; l < P.levels; ++l) kmax = P.lv[l].iters > kmax ? P.lv[l].iters : kmax;
   auto padded = [](int n) { return (unsigned)(((n + 7) / 8) * 8); };
-  // listed launches leave the partials of unlisted tiles untouched: the dot
-  // partials start at zero (the residual ones are written by every init)
-  if (P.klist) PDG_TRY(launch_fill((float *)s.pq_part, 2LL * P.ntiles, 0.f, st));
+  // listed launches leave the partials of unlisted tiles untouched: both dot
+  // partials start at zero
+  int nlisted = 0;
+  if (P.klist) {
+    for (int l = 0; l < P.levels; ++l) nlisted += P.kcount[l];
+    PDG_TRY(launch_fill((float *)s.pq_part, 2LL * P.ntiles, 0.f, st));
+    PDG_TRY(launch_fill((float *)s.rr_part, 2LL * P.ntiles, 0.f, st));
+  }
   // solve 1: (I + lam L) y = g, y in s.x ; solve 2: (I + lam L) z = y, z in g
   for (int solve = 0; solve < 2; ++solve) {
     const float *src = solve == 0 ? g : s.x;
     CGState t = s;
     t.x = solve == 0 ? s.x : g;
-    // solve 1's x feeds solve 2 through its kept cells only; solve 2's x is the output
-    cg_init_kernel<<<padded(P.ntiles), kThreads, 0, st>>>(P, P.ntiles, src, t.r, t.x, t.rr_part,
-                                                          solve == 1);
+    // solve 1's x feeds solve 2 through its kept cells only (its set-up visits
+    // the listed tiles); solve 2's x is the output (every tile, zeros on the
+    // pruned cells)
+    if (P.klist && solve == 0)
+      cg_init_kernel<<<padded(nlisted), kThreads, 0, st>>>(P, nlisted, P.klist, src, t.r, t.x,
+                                                           t.rr_part, 0);
+    else
+      cg_init_kernel<<<padded(P.ntiles), kThreads, 0, st>>>(P, P.ntiles, nullptr, src, t.r, t.x,
+                                                            t.rr_part, solve == 1);
     PDG_TRY(launched("cg_init"));
     cg_reduce_kernel<<<P.nsys, kThreads, 0, st>>>(P, 0, 0, 0, t);
     PDG_TRY(launched("cg_reduce"));
