@@ -172,6 +172,24 @@ struct FusedArgs {
   float lam;
 };
 
+// Several levels of one generic pass in one launch: level i owns workgroups
+// [first[i], first[i + 1]) and strides over its planes or pencil groups with
+// that many workgroups (the levels are independent systems).
+struct FusedBatch {
+  int n;
+  int first[PDG_MAX_LEVELS + 1];
+  FusedArgs lv[PDG_MAX_LEVELS];
+};
+// this workgroup's level, its index among the level's workgroups and their count
+__device__ __forceinline__ const FusedArgs &batch_level(const FusedBatch &b, long long &blk,
+                                                        long long &nblk) {
+  int i = 0;
+  while (i + 1 < b.n && (int)blockIdx.x >= b.first[i + 1]) ++i;
+  blk = (long long)blockIdx.x - b.first[i];
+  nblk = b.first[i + 1] - b.first[i];
+  return b.lv[i];
+}
+
 // Adam epilogue of the last inverse pass of one level.
 struct AdamEpi {
   float *th, *m, *v;
@@ -276,7 +294,9 @@ struct Split {
 // after a barrier; the second's go straight to HBM while the next plane is in
 // flight into registers.
 template <int NT, bool FULL>
-__global__ __launch_bounds__(kBig) void dct_plane_kernel(FusedArgs a, int inverse) {
+__global__ __launch_bounds__(kBig) void dct_plane_kernel(FusedBatch fb, int inverse) {
+  long long blk, nblk;
+  const FusedArgs &a = batch_level(fb, blk, nblk);
   using S = Split<NT, NT>;
   constexpr int RP = 32 * NT, P = RP + 1, NP = S::NP;
   extern __shared__ float lds[];
@@ -293,10 +313,10 @@ __global__ __launch_bounds__(kBig) void dct_plane_kernel(FusedArgs a, int invers
     return (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2;
   };
   __syncthreads();
-  long long plane = blockIdx.x;
+  long long plane = blk;
   if (plane < a.planes) load_rows(sp, P, a.src + plane_base(plane), R, R, R * R);
   __syncthreads();
-  for (; plane < a.planes; plane += gridDim.x) {
+  for (; plane < a.planes; plane += nblk) {
     const long long base = plane_base(plane);
     f32x16 acc[S::kRounds][NP];
 #pragma unroll
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(kBig) void dct_plane_kernel(FusedArgs a, int invers
     __syncthreads();
     // the next plane is fetched into registers while the second transform runs
     constexpr int kPre = RP * RP / kBig;
-    const long long next = plane + gridDim.x;
+    const long long next = plane + nblk;
     float pre[kPre];
     if (next < a.planes) {
       const float *in = a.src + plane_base(next);
@@ -382,7 +402,9 @@ constexpr int kPencils = 64;
 constexpr int kPP = kPencils + 1;      // LDS pitch of a pencil row
 
 template <int NT, bool FULL>
-__global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
+__global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedBatch fb) {
+  long long blk, nblk;
+  const FusedArgs &a = batch_level(fb, blk, nblk);
   using S = Split<NT, kPencils / 32>;
   constexpr int RP = 32 * NT, P = RP + 1, NP = S::NP;
   extern __shared__ float lds[];
@@ -413,8 +435,8 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
       pre[e] = (FULL || (z < R && j < nl)) ? in[z * r2 + j] : 0.f;
     }
   };
-  if (blockIdx.x < total) fetch(blockIdx.x);
-  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+  if (blk < total) fetch(blk);
+  for (long long g = blk; g < total; g += nblk) {
     const long long line0 = (g % groups) * kPencils;
     int nl;
     float *d0 = group_ptr(g, nl);
@@ -425,7 +447,7 @@ __global__ __launch_bounds__(kBig) void dct_pencil_kernel(FusedArgs a) {
       if (FULL || z < R) sq[z * kPP + j] = pre[e];
     }
     __syncthreads();
-    if (g + gridDim.x < total) fetch(g + gridDim.x);   // in flight during this group
+    if (g + nblk < total) fetch(g + nblk);   // in flight during this group
     f32x16 acc[S::kRounds][NP];
 #pragma unroll
     for (int rnd = 0; rnd < S::kRounds; ++rnd) {
@@ -833,7 +855,7 @@ size_t plane_lds(int R) { return (size_t)2 * padded(R) * (padded(R) + 1) * sizeo
 size_t pencil_lds(int R) { return (size_t)(padded(R) * (padded(R) + 1) + padded(R) * kPP) * sizeof(float); }
 
 template <int NT, bool FULL>
-pdg_status fused_level(const FusedArgs &f0, hipStream_t st) {
+pdg_status fused_levels(const FusedArgs *f0, int n, hipStream_t st) {
   static PerDevice attrs;
   int dev = 0;
   PDG_TRY_HIP(hipGetDevice(&dev));
@@ -846,23 +868,34 @@ pdg_status fused_level(const FusedArgs &f0, hipStream_t st) {
                                     (int)pencil_lds(32 * NT)));
     attrs.mark(dev);
   }
-  FusedArgs f = f0;
-  const int R = f.R;
-  const long long groups = f.planes / R * (((long long)R * R + kPencils - 1) / kPencils);
-  const unsigned gp = (unsigned)(f.planes < 2048 ? f.planes : 2048);
-  const unsigned gg = (unsigned)(groups < 2048 ? groups : 2048);
-  dct_plane_kernel<NT, FULL><<<gp, kBig, plane_lds(R), st>>>(f, 0);
+  // the levels' three passes, each one launch for all of them (the levels of
+  // one call share NT, so one LDS size serves them)
+  FusedBatch fwd, pen, inv;   // plane forward, pencil, plane inverse
+  fwd.n = pen.n = inv.n = n;
+  fwd.first[0] = pen.first[0] = inv.first[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    const FusedArgs &f = f0[i];
+    const int R = f.R;
+    const long long groups = f.planes / R * (((long long)R * R + kPencils - 1) / kPencils);
+    const int gp = (int)(f.planes < 2048 ? f.planes : 2048);
+    const int gg = (int)(groups < 2048 ? groups : 2048);
+    fwd.lv[i] = pen.lv[i] = inv.lv[i] = f;
+    pen.lv[i].src = inv.lv[i].src = f.dst;   // the later passes work on dst
+    fwd.first[i + 1] = inv.first[i + 1] = fwd.first[i] + gp;
+    pen.first[i + 1] = pen.first[i] + gg;
+  }
+  const int RP = 32 * NT;
+  dct_plane_kernel<NT, FULL><<<(unsigned)fwd.first[n], kBig, plane_lds(RP), st>>>(fwd, 0);
   PDG_TRY(launched("dct_plane"));
-  f.src = f.dst;
-  dct_pencil_kernel<NT, FULL><<<gg, kBig, pencil_lds(R), st>>>(f);
+  dct_pencil_kernel<NT, FULL><<<(unsigned)pen.first[n], kBig, pencil_lds(RP), st>>>(pen);
   PDG_TRY(launched("dct_pencil"));
-  dct_plane_kernel<NT, FULL><<<gp, kBig, plane_lds(R), st>>>(f, 1);
+  dct_plane_kernel<NT, FULL><<<(unsigned)inv.first[n], kBig, plane_lds(RP), st>>>(inv, 1);
   return launched("dct_plane");
 }
 
 template <int NT>
 pdg_status fused_level(const FusedArgs &f, hipStream_t st) {
-  return f.R == 32 * NT ? fused_level<NT, true>(f, st) : fused_level<NT, false>(f, st);
+  return f.R == 32 * NT ? fused_levels<NT, true>(&f, 1, st) : fused_levels<NT, false>(&f, 1, st);
 }
 
 // basis C[k][x] (row-major), its transpose, and mu_k, in float64 then rounded
@@ -947,6 +980,8 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
     src = data;
   }
   const char *w = (const char *)ws;
+  FusedArgs small[PDG_MAX_LEVELS];   // the generic fused levels with R < 32
+  int nsmall = 0;
   for (int l = 0; l < g.levels; ++l) {
     const int R = g.res[l];
     const float *c = (const float *)w;
@@ -995,6 +1030,10 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
         }
         continue;
       }
+      if (R < 32) {   // every such level's passes go in one launch each, below
+        small[nsmall++] = f;
+        continue;
+      }
       switch ((R + 31) / 32) {
         case 1: PDG_TRY(fused_level<1>(f, st)); break;
         case 2: PDG_TRY(fused_level<2>(f, st)); break;
@@ -1026,6 +1065,7 @@ pdg_status run_dct(const GridDev &g, int batch, const float *lam, const float *s
       PDG_TRY(pass(a, st));
     }
   }
+  if (nsmall > 0) PDG_TRY((fused_levels<1, false>(small, nsmall, st)));
   return PDG_OK;
 }
 
