@@ -567,6 +567,18 @@ __device__ __forceinline__ FastLane fast_lane() {
 }
 
 // Block's planes (kFT / 2R of them) from HBM into LDS (pitch R + 1).
+// Streams read or written once per pass go past the caches (non-temporal
+// loads and stores)
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 nt_load4(const float *p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store4(float *p, float4 x) {
+  const nt_f4 v = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
+
 template <int R>
 __device__ __forceinline__ void fast_load_planes(float *sp, const float *src, long long stack,
                                                  long long off, long long plane0) {
@@ -579,8 +591,7 @@ __device__ __forceinline__ void fast_load_planes(float *sp, const float *src, lo
     const long long plane = plane0 + idx / (R * R);
     const long long sys = plane / R, z = plane % R;
     const int o = idx % (R * R);
-    t[k] = *reinterpret_cast<const float4 *>(src + (sys / 3) * stack + off + (sys % 3) * R3 +
-                                             z * R2 + o);
+    t[k] = nt_load4(src + (sys / 3) * stack + off + (sys % 3) * R3 + z * R2 + o);
   }
 #pragma unroll
   for (int k = 0; k < G; ++k) {
@@ -636,7 +647,7 @@ __global__ __launch_bounds__(kFT) void fdct_plane_fwd_kernel(FusedArgs a) {
     const long long plane = plane0 + pl, sys = plane / R, z = plane % R;
     float *out = a.dst + (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2 + ln;
 #pragma unroll
-    for (int k = 0; k < H; ++k) out[(fl.h * H + k) * R] = v[k];
+    for (int k = 0; k < H; ++k) __builtin_nontemporal_store(v[k], &out[(fl.h * H + k) * R]);
   }
 }
 
@@ -656,7 +667,7 @@ __global__ __launch_bounds__(kFT) void fdct_pencil_kernel(FusedArgs a) {
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int idx = 4 * ((int)threadIdx.x + k * kFT);
-      t[k] = *reinterpret_cast<const float4 *>(base + (idx / kFP) * R2 + idx % kFP);
+      t[k] = nt_load4(base + (idx / kFP) * R2 + idx % kFP);
     }
 #pragma unroll
     for (int k = 0; k < G; ++k) {
@@ -705,7 +716,7 @@ __global__ __launch_bounds__(kFT) void fdct_pencil_kernel(FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < H; ++k) {
     const float r = col[k * kFQ] + sg * col[(H + k) * kFQ];
-    base[(fl.h ? R - 1 - k : k) * R2 + j] = r;
+    __builtin_nontemporal_store(r, &base[(fl.h ? R - 1 - k : k) * R2 + j]);
   }
 }
 
@@ -777,9 +788,9 @@ __global__ __launch_bounds__(kFT) void fdct_plane_inv_kernel(FusedArgs a, AdamEp
         const int p = idx / (R * R), o = idx % (R * R);
         const long long plane = plane0 + p, sys = plane / R, z = plane % R;
         const long long at = (sys / 3) * a.stack + a.off + (sys % 3) * R3 + z * R2 + o;
-        th[k] = *reinterpret_cast<const float4 *>(pth + at);
-        mo[k] = *reinterpret_cast<const float4 *>(pm + at);
-        vo[k] = *reinterpret_cast<const float4 *>(pv + at);
+        th[k] = nt_load4(pth + at);
+        mo[k] = nt_load4(pm + at);
+        vo[k] = nt_load4(pv + at);
       }
 #pragma unroll
       for (int k = 0; k < GB; ++k) {
@@ -789,9 +800,9 @@ __global__ __launch_bounds__(kFT) void fdct_plane_inv_kernel(FusedArgs a, AdamEp
         th[k].y = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.y, mo[k].y, vo[k].y, th[k].y);
         th[k].z = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.z, mo[k].z, vo[k].z, th[k].z);
         th[k].w = adam_one(ad.b1, ad.b2, ad.eps, ad.lr, bc1, bc2, g.w, mo[k].w, vo[k].w, th[k].w);
-        *reinterpret_cast<float4 *>(pth + at) = th[k];
-        *reinterpret_cast<float4 *>(pm + at) = mo[k];
-        *reinterpret_cast<float4 *>(pv + at) = vo[k];
+        nt_store4(pth + at, th[k]);
+        nt_store4(pm + at, mo[k]);
+        nt_store4(pv + at, vo[k]);
       }
     }
   } else {
