@@ -34,6 +34,18 @@ __device__ __forceinline__ bool kept_any4(const AdamLevels &lv, long long b, lon
           kept_of(lv, b, w + 3)) != 0u;
 }
 
+// Adam's streams are read or written once: past the caches (non-temporal
+// accesses)
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 nt_load4(const float *p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store4(float *p, float4 x) {
+  const nt_f4 v = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
+
 // kAdamGroups groups of four consecutive values of stack blockIdx.y per thread (all
 // loads issued before the arithmetic); stack % 4 == 0 and 16-byte aligned arrays.
 constexpr int kAdamGroups = 1;
@@ -56,10 +68,10 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
     // a group of four pruned values is left as it is (no loads, no stores)
     live[q] = w < c1 && kept_any4(lv, blockIdx.y, w);
     if (live[q]) {
-      gi[q] = *reinterpret_cast<const float4 *>(g + base + w);
-      mi[q] = *reinterpret_cast<const float4 *>(m + base + w);
-      vi[q] = *reinterpret_cast<const float4 *>(v + base + w);
-      ti[q] = *reinterpret_cast<const float4 *>(th + base + w);
+      gi[q] = nt_load4(g + base + w);
+      mi[q] = nt_load4(m + base + w);
+      vi[q] = nt_load4(v + base + w);
+      ti[q] = nt_load4(th + base + w);
     }
   }
 #pragma unroll
@@ -70,9 +82,9 @@ __global__ __launch_bounds__(256) void adam4_kernel(AdamLevels lv, long long sta
     ti[q].y = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 1)], bc1, bc2, gi[q].y, mi[q].y, vi[q].y, ti[q].y);
     ti[q].z = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 2)], bc1, bc2, gi[q].z, mi[q].z, vi[q].z, ti[q].z);
     ti[q].w = adam_one(b1, b2, eps, lv.lr[level_of(lv, w + 3)], bc1, bc2, gi[q].w, mi[q].w, vi[q].w, ti[q].w);
-    *reinterpret_cast<float4 *>(m + base + w) = mi[q];
-    *reinterpret_cast<float4 *>(v + base + w) = vi[q];
-    *reinterpret_cast<float4 *>(th + base + w) = ti[q];
+    nt_store4(m + base + w, mi[q]);
+    nt_store4(v + base + w, vi[q]);
+    nt_store4(th + base + w, ti[q]);
   }
 }
 

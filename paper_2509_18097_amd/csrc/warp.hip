@@ -923,9 +923,9 @@ __global__ __launch_bounds__(kGatherThreads, 5) void gather_kernel(GridDev g, Ga
                       : scratch + gp.sof[l] + ((long long)piece * gp.segs + seg) * 3 * R3) +
               (long long)z * R2 + (long long)y0 * R;
   for (int i = t; i < band_n; i += kGatherThreads) {
-    Gd[i] = band[i];
-    Gd[R3 + i] = band[band_n + i];
-    Gd[2 * R3 + i] = band[2 * band_n + i];
+    __builtin_nontemporal_store(band[i], &Gd[i]);   // read once, by the next stage
+    __builtin_nontemporal_store(band[band_n + i], &Gd[R3 + i]);
+    __builtin_nontemporal_store(band[2 * band_n + i], &Gd[2 * R3 + i]);
   }
 }
 
