@@ -96,6 +96,17 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 __device__ __forceinline__ float4 ld4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 __device__ __forceinline__ void st4(float *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+// streams a pass reads or writes once (no stencil neighbour reads them in the
+// same pass): past the caches
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld4nt(const float *p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4nt(float *p, float4 x) {
+  const nt_f4 v = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
 __device__ __forceinline__ float4 axpy4(float4 a, float b, float4 c) {
   return make_float4(a.x + b * c.x, a.y + b * c.y, a.z + b * c.z, a.w + b * c.w);
 }
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void cg_a_kernel(CGPlanDev P, int k, int 
       } else {
         ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
       }
-      st4(po + q, c);
+      st4nt(po + q, c);
       acc += dot4(c, ap);
     };
     if (MASK) {
@@ -411,12 +422,12 @@ __global__ __launch_bounds__(kThreads, 8) void cg_b_kernel(CGPlanDev P, int k, i
       } else {
         ap = axpy4(c, lam, lap4(c, xl, xr, ym, yp, zm, zp));
       }
-      st4(xx + q, axpy4(ld4(xx + q), alpha, c));
-      float4 rn = axpy4(ld4(rr + q), -alpha, ap);
+      st4nt(xx + q, axpy4(ld4nt(xx + q), alpha, c));
+      float4 rn = axpy4(ld4nt(rr + q), -alpha, ap);
       // the residual of a pruned cell is zero (its stored value is not kept
       // up to date: the set-up does not write it)
       if (MASK) rn = keep4(rn, nib4(o.mk, q));
-      st4(rr + q, rn);
+      st4nt(rr + q, rn);
       acc += dot4(rn, rn);
     };
     if (MASK) {   // x and r stay zero on the quads without a kept cell
